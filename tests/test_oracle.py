@@ -1,0 +1,353 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+No GPU.  Each test checks the oracle against something other than itself:
+values the paper prints (tests/golden), closed forms, invariants, special
+cases that reduce to a textbook or library routine, or an independent
+brute-force reference (long-double Taylor series, long-double RK4 on Eq. (1)).
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+import oracle
+from paper_2603_18052_amd import workloads as W
+from conftest import read_golden
+
+
+def rand_c(shape, g):
+    return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+
+# ------------------------------------------------------------- Liouvillian
+def kron_form(H, Lk):
+    """The row-major Kronecker closed form of Eq. (1): vec_r(A X B) = (A x B^T) vec_r(X)."""
+    d = H.shape[0]
+    I = np.eye(d)
+    L = -1j * (np.kron(H, I) - np.kron(I, H.T))
+    for Lj in Lk:
+        M = Lj.conj().T @ Lj
+        L += np.kron(Lj, Lj.conj()) - 0.5 * np.kron(M, I) - 0.5 * np.kron(I, M.T)
+    return L
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_liouvillian_matches_kronecker_closed_form(q):
+    H, Lk = W.transmon_system(q)
+    assert np.abs(oracle.liouvillian(H, Lk) - kron_form(H, Lk)).max() < 1e-15
+
+
+def test_liouvillian_random_operators_and_rhs():
+    g = np.random.default_rng(7)
+    d = 4
+    H = rand_c((d, d), g)
+    H = H + H.conj().T
+    Lk = rand_c((3, d, d), g)
+    L = oracle.liouvillian(H, Lk)
+    assert np.abs(L - kron_form(H, Lk)).max() < 1e-13
+    # a plain restatement of Eq. (1) on a random (non-Hermitian) matrix
+    rho = rand_c((d, d), g)
+    ref = -1j * (H @ rho - rho @ H)
+    for Lj in Lk:
+        M = Lj.conj().T @ Lj
+        ref = ref + Lj @ rho @ Lj.conj().T - 0.5 * (M @ rho + rho @ M)
+    assert np.abs(oracle.lindblad_rhs(H, Lk, rho) - ref).max() < 1e-13
+    assert np.abs(L @ rho.reshape(-1) - ref.reshape(-1)).max() < 1e-13
+
+
+def test_liouvillian_trace_and_hermiticity_preservation():
+    H, Lk = W.transmon_system(2)
+    L = oracle.liouvillian(H, Lk)
+    d = 9
+    vecI = np.eye(d).reshape(-1)
+    assert np.abs(vecI @ L).max() < 1e-15  # d/dt Tr rho = 0
+    g = np.random.default_rng(3)
+    X = rand_c((d, d), g)
+    Y = (L @ X.reshape(-1)).reshape(d, d)
+    Yd = (L @ X.conj().T.reshape(-1)).reshape(d, d)
+    assert np.abs(Yd - Y.conj().T).max() < 1e-15  # L(X^dag) = L(X)^dag
+
+
+def test_liouvillian_decomposed_equals_monolithic():
+    """The paper's unit test of the control-affine split (Eq. (5))."""
+    q = 2
+    H0 = W.drift_hamiltonian(q, static_drive=False)
+    Hc = W.control_hamiltonians(q)
+    Lk = W.collapse_ops(q)
+    u = np.array([0.1, -0.05, 0.02, 0.07])
+    mono = oracle.liouvillian(H0 + np.tensordot(u, Hc, axes=1), Lk)
+    Ldiss = oracle.liouvillian(np.zeros_like(H0), Lk)
+    L0 = oracle.liouvillian(H0, Lk[:0])
+    Lc = [oracle.liouvillian(h, Lk[:0]) for h in Hc]
+    deco = L0 + Ldiss + sum(uc * l for uc, l in zip(u, Lc))
+    assert np.abs(mono - deco).max() < 1e-15
+
+
+# ---------------------------------------------------------------- Alg. 1
+def test_pade13_coefficients_reproduce_exp():
+    """p(x)/p(-x) with p = sum b_k x^k is the [13/13] Pade approximant of
+    exp: at |x| <= theta it equals exp(x) to double precision, and the
+    leading error term is O(x^27), so any wrong coefficient is visible."""
+    b = oracle.pade13_coefficients()
+    assert b[13] == 1.0 and b[12] == 182.0 and b[0] == 64764752532480000.0
+    for x in (0.25, -0.25, 0.25j, 0.1 + 0.2j, 1.0, 2.0):
+        p = sum(bk * x ** k for k, bk in enumerate(b))
+        q = sum(bk * (-x) ** k for k, bk in enumerate(b))
+        tol = 4e-16 if abs(x) <= 0.25 else 1e-13
+        assert abs(p / q - np.exp(x)) <= tol * abs(np.exp(x))
+
+
+def test_scaling_exponent_rule():
+    assert oracle.scaling_exponent(0.0) == 0
+    assert oracle.scaling_exponent(0.25) == 0
+    assert oracle.scaling_exponent(0.2500001) == 1
+    assert oracle.scaling_exponent(1.0) == 2        # exact power: ceil(log2(4)) = 2
+    assert oracle.scaling_exponent(1.0000001) == 3
+    assert oracle.scaling_exponent(float("nan")) == -1
+    assert oracle.scaling_exponent(float("inf")) == -1
+
+
+def test_norm1_is_max_column_modulus_sum():
+    A = np.array([[3 + 4j, 1], [0, -2j]])
+    assert oracle.norm1(A) == 5.0
+    A = np.array([[1, 0], [1j, 1 - 1j]])
+    assert abs(oracle.norm1(A) - (1 + 1)) < 1e-15 or abs(oracle.norm1(A) - (1 + np.sqrt(2))) < 1e-15
+    assert abs(oracle.norm1(A) - max(2.0, np.sqrt(2))) < 1e-15
+
+
+def test_paper_scaling_exponents_golden():
+    for d, s_paper in read_golden("paper_scaling_exponents.txt"):
+        H, Lk, dt = W.paper_grape_model(int(d))
+        if d == 27:
+            L = kron_form(H, Lk)  # cheaper than the column-by-column build here
+        else:
+            L = oracle.liouvillian(H, Lk)
+        assert oracle.scaling_exponent(oracle.norm1(L * dt)) == int(s_paper)
+
+
+def test_config_scaling_exponents():
+    for q, s_expect in ((1, 2), (2, 3), (3, 4)):
+        H, Lk = W.transmon_system(q)
+        L = kron_form(H, Lk)
+        assert oracle.scaling_exponent(oracle.norm1(L * W.DT_NS)) == s_expect
+
+
+def test_lu_solve_against_library_and_pivoting():
+    g = np.random.default_rng(11)
+    A = rand_c((12, 12), g)
+    A[0, 0] = 0.0  # forces a row exchange in the first column
+    B = rand_c((12, 5), g)
+    X = oracle.lu_solve(A, B)
+    assert np.abs(A @ X - B).max() < 1e-12
+    assert np.abs(X - np.linalg.solve(A, B)).max() < 1e-12
+    with pytest.raises(oracle.OracleError):
+        oracle.lu_solve(np.zeros((3, 3), complex), np.eye(3, dtype=complex))
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_expm_matches_long_double_taylor(q):
+    H, Lk = W.transmon_system(q)
+    A = oracle.liouvillian(H, Lk) * W.DT_NS
+    P = oracle.expm(A)
+    assert oracle.rel_fro(P, oracle.expm_taylor_ld(A)) < 1e-14
+    assert oracle.rel_fro(P, sl.expm(A)) < 1e-13  # library cross-check
+
+
+def test_expm_large_norm_random_and_identities():
+    g = np.random.default_rng(5)
+    A = 0.8 * rand_c((10, 10), g)  # ||A||_1 ~ 10: several squarings
+    P, s = oracle.expm(A, return_s=True)
+    assert s >= 4
+    assert oracle.rel_fro(P, oracle.expm_taylor_ld(A)) < 1e-13
+    P2 = oracle.expm(2 * A)
+    assert oracle.rel_fro(P2, P @ P) < 1e-12                      # semigroup
+    assert np.abs(P @ oracle.expm(-A) - np.eye(10)).max() < 1e-11  # inverse
+    D = np.diag(rand_c(6, g))
+    assert np.abs(oracle.expm(D) - np.diag(np.exp(np.diag(D)))).max() < 1e-14
+
+
+def test_expm_nonfinite_and_zero():
+    A = np.zeros((4, 4), complex)
+    P, s = oracle.expm(A, return_s=True)
+    assert s == 0 and np.array_equal(P, np.eye(4))
+    A[1, 2] = np.nan
+    with pytest.raises(oracle.OracleError):
+        oracle.expm(A)
+
+
+def test_propagator_trace_preserving_and_unitary_limit():
+    H, Lk = W.transmon_system(2)
+    P = oracle.propagator(oracle.liouvillian(H, Lk), W.DT_NS)
+    vecI = np.eye(9).reshape(-1)
+    assert np.abs(vecI @ P - vecI).max() < 1e-14
+    ev = np.abs(np.linalg.eigvals(P))
+    assert abs(ev.max() - 1.0) < 1e-13  # unique steady state, contraction
+    # unitary limit: no collapse operators -> P = U x conj(U)
+    Pu = oracle.propagator(oracle.liouvillian(H, Lk[:0]), W.DT_NS)
+    e, V = np.linalg.eigh(H)
+    U = V @ np.diag(np.exp(-1j * e * W.DT_NS)) @ V.conj().T
+    assert np.abs(Pu - np.kron(U, U.conj())).max() < 5e-14
+
+
+# ----------------------------------------------------------------- Alg. 2-3
+def test_matvec_and_propagate_against_library():
+    g = np.random.default_rng(2)
+    P = rand_c((20, 20), g) / 10
+    X = rand_c((7, 20), g)
+    assert np.abs(oracle.matvec(P, X[0]) - P @ X[0]).max() < 1e-14
+    Y = oracle.propagate(P, X, 5, nthreads=3)
+    ref = X.T.copy()
+    for _ in range(5):
+        ref = P @ ref
+    assert np.abs(Y - ref.T).max() < 1e-12
+
+
+def amplitude_damping_P(gamma, dt):
+    a = W.annihilation()
+    L = oracle.liouvillian(np.zeros((3, 3), complex), np.sqrt(gamma) * a[None])
+    return oracle.propagator(L, dt)
+
+
+def test_chain_amplitude_damping_closed_form():
+    gamma, dt, N = 0.01, 0.5, 2000
+    P = amplitude_damping_P(gamma, dt)
+    t = N * dt
+    r1 = np.zeros((3, 3), complex); r1[1, 1] = 1
+    r2 = np.zeros((3, 3), complex); r2[2, 2] = 1
+    out = oracle.propagate(P, np.stack([r1, r2]), N)
+    e1, e2 = np.exp(-gamma * t), np.exp(-2 * gamma * t)
+    assert abs(out[0, 1, 1] - e1) < 1e-12 and abs(out[0, 0, 0] - (1 - e1)) < 1e-12
+    assert abs(out[1, 2, 2] - e2) < 1e-12
+    assert abs(out[1, 1, 1] - 2 * (e1 - e2)) < 1e-12
+
+
+def test_chain_pure_dephasing_closed_form():
+    gphi, dt, N = 0.003, 0.5, 1000
+    E = np.array([0.0, 1.3, 2.9])
+    n = np.diag([0.0, 1.0, 2.0]).astype(complex)
+    L = oracle.liouvillian(np.diag(E).astype(complex), (np.sqrt(gphi) * n)[None])
+    P = oracle.propagator(L, dt)
+    rho0 = W.pure_state(3, np.random.default_rng(1))
+    out = oracle.propagate(P, rho0[None], N)[0]
+    t = N * dt
+    m = np.arange(3)
+    ref = rho0 * np.exp(-1j * np.subtract.outer(E, E) * t - gphi * np.subtract.outer(m, m) ** 2 * t / 2)
+    assert np.abs(out - ref).max() < 1e-12
+
+
+def test_chain_unitary_limit():
+    H, _ = W.transmon_system(1)
+    L = oracle.liouvillian(H, np.zeros((0, 3, 3), complex))
+    P = oracle.propagator(L, 0.5)
+    rho0 = W.pure_state(3, np.random.default_rng(4))
+    out = oracle.propagate(P, rho0[None], 3000)[0]
+    e, V = np.linalg.eigh(H)
+    U = V @ np.diag(np.exp(-1j * e * 1500.0)) @ V.conj().T
+    assert np.abs(out - U @ rho0 @ U.conj().T).max() < 1e-11
+
+
+def test_chain_config1_against_long_double_taylor_stepper():
+    """d = 3, 1e4 steps of 0.5 ns: the propagator chain vs Eq. (1) stepped
+    by its own Taylor series in long double (no superoperator involved)."""
+    c = W.config1()
+    A = oracle.liouvillian(c["H"], c["Lk"]) * c["dt"]
+    ref = oracle.taylor_steps_ld(c["H"], c["Lk"], c["rho0"][0], c["dt"], c["nsteps"])
+    # chain on the exact propagator rounded once to double
+    out_exact_P = oracle.propagate(oracle.expm_taylor_ld(A), c["rho0"], c["nsteps"])[0]
+    assert oracle.trace_distance(out_exact_P, ref) < 1e-12
+    # chain on the Pade build: its ~5e-16 relative FP64 rounding error in P
+    # grows linearly over N = 1e4 steps, so the bound is N * 1e-15
+    out = oracle.propagate(oracle.expm(A), c["rho0"], c["nsteps"])[0]
+    assert oracle.trace_distance(out, ref) < c["nsteps"] * 1e-15
+    rep = oracle.state_report(out[None])
+    assert rep["trace_err"][0] < c["nsteps"] * 1e-15 and rep["antiherm"][0] < c["nsteps"] * 1e-15
+    assert rep["lambda_min"][0] > -c["nsteps"] * 1e-15
+
+
+def test_chain_against_long_double_rk4():
+    """RK4 on Eq. (1) converges at fourth order to the chain: halving the
+    substep divides the gap by ~16 (1000 steps of 0.5 ns at d = 3)."""
+    c = W.config1()
+    P = oracle.propagator(oracle.liouvillian(c["H"], c["Lk"]), c["dt"])
+    out = oracle.propagate(P, c["rho0"], 1000)[0]
+    e16 = oracle.trace_distance(out, oracle.rk4_ld(c["H"], c["Lk"], c["rho0"][0], c["dt"], 1000, sub=16))
+    e32 = oracle.trace_distance(out, oracle.rk4_ld(c["H"], c["Lk"], c["rho0"][0], c["dt"], 1000, sub=32))
+    assert e32 < 1e-6 and 14.0 < e16 / e32 < 18.0
+
+
+def test_trace_distance_metric():
+    a = np.diag([1.0, 0.0]).astype(complex)
+    b = np.diag([0.0, 1.0]).astype(complex)
+    assert abs(oracle.trace_distance(a, b) - 1.0) < 1e-15
+    p = np.array([1, 1]) / np.sqrt(2)
+    c = np.outer(p, p.conj())
+    # pure states: T = sqrt(1 - |<a|c>|^2)
+    assert abs(oracle.trace_distance(a, c) - np.sqrt(0.5)) < 1e-14
+
+
+# ------------------------------------------------------------------- GRAPE
+def test_frechet_against_library_and_identities():
+    g = np.random.default_rng(9)
+    A = 0.3 * rand_c((6, 6), g)
+    E = rand_c((6, 6), g)
+    eA, Lf = oracle.expm_frechet(A, E)
+    eA_ref, Lf_ref = sl.expm_frechet(A, E)
+    assert oracle.rel_fro(Lf, Lf_ref) < 1e-12 and oracle.rel_fro(eA, eA_ref) < 1e-12
+    _, LAA = oracle.expm_frechet(A, A)
+    assert oracle.rel_fro(LAA, A @ oracle.expm(A)) < 1e-12  # L(A, A) = A e^A
+    # commuting direction: L(A, E) = E e^A when AE = EA
+    Ec = 0.7 * A @ A + 0.2 * A
+    _, Lc = oracle.expm_frechet(A, Ec)
+    assert oracle.rel_fro(Lc, Ec @ oracle.expm(A)) < 1e-12
+
+
+def grape_setup(q, M):
+    p = W.grape_problem(q, M=M)
+    L0 = oracle.liouvillian(p["H0"], p["Lk"])
+    Lc = np.stack([oracle.liouvillian(h, p["Lk"][:0]) for h in p["Hc"]])
+    return p, L0, Lc
+
+
+def test_grape_gradient_against_central_differences():
+    p, L0, Lc = grape_setup(1, M=6)
+    x0 = p["rho0"].reshape(-1)
+    w = p["target"].reshape(-1)
+    F, grad = oracle.grape(L0, Lc, p["u"], p["dt"], x0, w)
+    # forward value: the product of the slice propagators
+    x = x0.copy()
+    for m in range(p["M"]):
+        x = oracle.expm(p["dt"] * (L0 + np.tensordot(p["u"][m], Lc, axes=1))) @ x
+    assert abs(F - np.vdot(w, x).real) < 1e-14
+    h = 1e-6
+    for m, c in [(0, 0), (2, 1), (5, 0), (5, 1)]:
+        up, um = p["u"].copy(), p["u"].copy()
+        up[m, c] += h
+        um[m, c] -= h
+        Fp, _ = oracle.grape(L0, Lc, up, p["dt"], x0, w, want_grad=False)
+        Fm, _ = oracle.grape(L0, Lc, um, p["dt"], x0, w, want_grad=False)
+        fd = (Fp - Fm) / (2 * h)
+        assert abs(grad[m, c] - fd) <= 1e-8 + 1e-7 * abs(grad[m, c])
+
+
+def test_grape_commuting_controls_closed_form():
+    """Diagonal drift, number-operator control: the control superoperator
+    commutes with the generator, so dP/du = dt Lc P exactly."""
+    d = 3
+    n_op = np.diag([0.0, 1.0, 2.0]).astype(complex)
+    H0 = np.diag([0.0, 0.7, 1.1]).astype(complex)
+    Lk = (np.sqrt(0.01) * n_op)[None]
+    L0 = oracle.liouvillian(H0, Lk)
+    Lc = oracle.liouvillian(n_op, Lk[:0])[None]
+    assert np.abs(L0 @ Lc[0] - Lc[0] @ L0).max() < 1e-15
+    M, dt = 4, 0.5
+    u = np.array([[0.1], [-0.2], [0.05], [0.3]])
+    rho0 = W.pure_state(d, np.random.default_rng(8))
+    tgt = W.pure_state(d, np.random.default_rng(9))
+    x0, w = rho0.reshape(-1), tgt.reshape(-1)
+    F, grad = oracle.grape(L0, Lc, u, dt, x0, w)
+    # all slices commute: x_M = exp(dt (M L0 + sum u Lc)) x0 and the
+    # gradient is the same for every slice
+    Atot = dt * (M * L0 + u.sum() * Lc[0])
+    xM = sl.expm(Atot) @ x0
+    assert abs(F - np.vdot(w, xM).real) < 1e-13
+    g_ref = np.vdot(w, dt * Lc[0] @ xM).real
+    assert np.abs(grad[:, 0] - g_ref).max() < 1e-13
