@@ -126,7 +126,8 @@ double orc_norm1(int n, const zc *A)
     for (int j = 0; j < n; ++j) {
         double s = 0.0;
         for (int i = 0; i < n; ++i) s += cabs(A[(size_t)i * n + j]);
-        if (!(s <= best)) best = s; /* propagates NaN */
+        if (isnan(s)) return s; /* a NaN column makes the norm undefined */
+        if (s > best) best = s;
     }
     return best;
 }

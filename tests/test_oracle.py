@@ -170,7 +170,12 @@ def test_expm_nonfinite_and_zero():
     P, s = oracle.expm(A, return_s=True)
     assert s == 0 and np.array_equal(P, np.eye(4))
     A[1, 2] = np.nan
-    with pytest.raises(oracle.OracleError):
+    assert np.isnan(oracle.norm1(A))
+    with pytest.raises(oracle.OracleError, match="status -6"):
+        oracle.expm(A)
+    A[1, 2] = np.inf
+    assert oracle.norm1(A) == np.inf
+    with pytest.raises(oracle.OracleError, match="status -6"):
         oracle.expm(A)
 
 
