@@ -1,0 +1,180 @@
+/*
+ * lindblad.h -- C-ABI of liblindblad.so, dense time-independent Lindblad
+ * propagation on one AMD Instinct MI355X (gfx950).
+ *
+ * Paper: "Hardware-Aware Performance Characterization of Small Dense Lindblad
+ * Propagation for Near-Term Quantum Control", arXiv 2603.18052.
+ *
+ * Conventions (every call):
+ *  - Matrices are row-major.  Complex numbers are interleaved {double re, im}
+ *    (numpy/torch complex128).  A d x d density matrix stored row-major IS the
+ *    length-n vector of the vectorised equation (n = d*d); the paper's step
+ *    (Sec. 3, Alg. 2 storage note) uses the same row-major vectorisation.
+ *  - Every array pointer is a DEVICE pointer owned by the caller, unless the
+ *    argument is marked "host".  The library never frees, reallocates or
+ *    keeps caller memory after a call returns.
+ *  - `stream` is the caller's hipStream_t (NULL = the legacy default stream).
+ *    Work is enqueued on it in order.  Calls that document a host
+ *    synchronisation block the host until their own work on `stream` ends.
+ *  - The return value is an lb_status.  Validation errors are detected before
+ *    anything is enqueued and leave every output untouched.  On any non-zero
+ *    status lindblad_last_error() returns a message (thread-local, valid until
+ *    the next call on the same thread).  No C++ exception crosses the ABI.
+ *  - Scratch memory comes from an lb_workspace.  Passing NULL selects the
+ *    library's per-device default workspace (grown on demand, cap 64 GiB).
+ *    Calls that share one workspace must be ordered (same stream, or
+ *    synchronised by the caller): the workspace is not locked.
+ */
+#ifndef LINDBLAD_H
+#define LINDBLAD_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,      /* bad argument value (NULL pointer, negative count, bad enum) */
+    LB_ESHAPE = -2,      /* unsupported size (d, n, B, K, C out of the supported range) */
+    LB_ENOMEM = -3,      /* workspace cap exceeded or device allocation failed */
+    LB_EHIP = -4,        /* a HIP runtime call failed (launch, copy, synchronise) */
+    LB_ESINGULAR = -5,   /* zero pivot in the LU of the Pade denominator V - U */
+    LB_ENONFINITE = -6,  /* NaN or Inf in ||L dt||_1: the scaling exponent is undefined */
+    LB_ENOTSUP = -7      /* valid request this build does not implement */
+} lb_status;
+
+/* Arithmetic of the propagation chain (lindblad_propagate).  The state is
+ * always handed over as complex128; the variants differ in how P and the
+ * in-flight state are represented inside the kernel. */
+typedef enum {
+    LB_C128 = 0,        /* complex FP64: P and states FP64, FP64 MFMA accumulation */
+    LB_C64 = 1,         /* complex FP32: P rounded to FP32 (nearest-even), FP32 MFMA accumulation,
+                           state rounded to FP32 after every step */
+    LB_BF16_HILO = 2,   /* split BF16: P = Phi + Plo and x = xhi + xlo in BF16, products
+                           Phi xhi + Phi xlo + Plo xhi on BF16 MFMA with FP32 accumulation */
+    LB_BF16_SLICED = 3  /* exponent-aligned BF16 integer slices of P (per row) and of each
+                           state (per state): every slice product sums exactly in the FP32
+                           MFMA accumulator; slice pairs are combined in FP64 */
+} lb_precision;
+
+typedef struct lb_workspace lb_workspace;
+
+/* Library-owned device scratch on the current device (the paper's reusable
+ * matrix-exponential workspace, Sec. 2 "Reusable Propagator Construction").
+ * Memory is allocated on first need and grown up to `max_bytes`; a request
+ * beyond the cap fails with LB_ENOMEM.  destroy synchronises the device
+ * before freeing.  Thread-compatible, not thread-safe. */
+int lb_workspace_create(size_t max_bytes, lb_workspace **ws);
+int lb_workspace_destroy(lb_workspace *ws);
+/* Bytes currently allocated by the workspace (host query, no device work). */
+size_t lb_workspace_bytes(const lb_workspace *ws);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *lindblad_last_error(void);
+
+/* Superoperator of the Lindblad master equation, Eq. (1), vectorised row-major
+ * (Eqs. (2)-(3)):
+ *   L = -i (H (x) I - I (x) H^T)
+ *       + sum_k [ Lk (x) conj(Lk) - 1/2 (Lk^dag Lk) (x) I - 1/2 I (x) (Lk^dag Lk)^T ]
+ * so that L vec(rho) = vec(-i[H, rho] + sum_k D[Lk] rho) for every rho.
+ *   d     : Hilbert-space dimension, 1 <= d <= 64 (n = d*d <= 4096)
+ *   H     : d x d complex128 (need not be Hermitian; used as given)
+ *   K     : number of collapse operators, 0 <= K <= 64
+ *   Lk    : K x d x d complex128 (may be NULL when K = 0)
+ *   Lout  : n x n complex128, written completely
+ * Asynchronous; no workspace. */
+int lindblad_liouvillian(int d, const void *H, int K, const void *Lk, void *Lout, hipStream_t stream);
+
+/* Control-affine slice generators (Eq. (5), one generator per segment):
+ *   Lout[m] = L0 + sum_c u[m*C + c] * Lc[c],   m = 0..M-1
+ *   n     : superoperator size, 1 <= n <= 4096
+ *   L0    : n x n complex128 (drift incl. dissipators); Lc: C x n x n complex128
+ *   u     : M x C double (device); Lout: M x n x n complex128
+ *   0 <= C <= 64, M >= 0.  Asynchronous; no workspace. */
+int lindblad_generators(int n, int M, int C, const void *L0, const void *Lc, const double *u,
+                        void *Lout, hipStream_t stream);
+
+/* Propagators P[m] = exp(L[m] dt[m]) by Alg. 1: scaling exponent
+ * s = smallest s >= 0 with ||A||_1 <= theta 2^s (A = L dt, ||.||_1 the largest
+ * column sum of complex moduli), Pade [13/13] numerator V + U and denominator
+ * V - U of A / 2^s (three powers, three products), LU with partial pivoting of
+ * V - U (largest modulus, lowest row on ties) solving for P with the n columns
+ * of V + U as right-hand sides, then s squarings.  FP64 throughout.
+ *   n      : 1 <= n <= 4096;  M >= 1 generators, L is M x n x n complex128
+ *   dt     : HOST array of M step lengths
+ *   theta  : threshold, > 0 (the paper uses 0.25; Higham's is 5.37)
+ *   P      : M x n x n complex128 output (may alias nothing else)
+ *   s_used : HOST array of M ints receiving s, or NULL
+ * Synchronises the host with `stream` twice (the scaling exponents decide the
+ * number of squaring launches; the pivots decide the status).  Returns
+ * LB_ENONFINITE if some ||A||_1 is not finite and LB_ESINGULAR if some
+ * denominator has an exactly zero pivot; P is then unspecified. */
+int lindblad_propagator(int n, int M, const void *L, const double *dt, double theta, void *P,
+                        int *s_used, lb_workspace *ws, hipStream_t stream);
+
+/* The step chain, Alg. 2 applied nsteps times to each of B independent states
+ * (Alg. 3 parallelism): rho_b <- P^nsteps rho_b.
+ *   n      : 1 <= n <= 4096 (n = d*d)
+ *   P      : n x n complex128 (converted once per call to `prec`'s format)
+ *   prec   : lb_precision
+ *   B      : number of states, >= 1
+ *   rho    : B x n complex128, in place (row b = vec of state b)
+ *   nsteps : >= 0
+ * Asynchronous.  LB_C128 has a fused kernel for every n; LB_C64,
+ * LB_BF16_HILO and LB_BF16_SLICED for every n as well (P resident in LDS for
+ * n <= 96, tiled from L2 otherwise). */
+int lindblad_propagate(int n, const void *P, lb_precision prec, int B, void *rho, long long nsteps,
+                       lb_workspace *ws, hipStream_t stream);
+
+/* The plain per-state FP64 matvec chain the fast paths are measured against:
+ * one launch per step, each wavefront reads rows of P from memory (coalesced)
+ * for one state and reduces with cross-lane shuffles.  Same arguments and
+ * result as lindblad_propagate with LB_C128.  Asynchronous. */
+int lindblad_propagate_baseline(int n, const void *P, int B, void *rho, long long nsteps,
+                                lb_workspace *ws, hipStream_t stream);
+
+/* GRAPE fidelity and its gradient for piecewise-constant controls.
+ * (Not in the paper, which runs only the forward landscape point of Eq. (5).)
+ *   L0 : n x n complex128 generator of the drift (coherent + dissipative)
+ *   Lc : C x n x n complex128 control generators (coherent, -i[Hc, .])
+ *   u  : M x C double amplitudes (device); dt: slice length
+ *   x0 : n complex128 initial state; w: n complex128 target (vec of sigma)
+ *   A_m = dt (L0 + sum_c u[m,c] Lc[c]),  P_m = exp(A_m)  (Alg. 1)
+ *   x_m = P_m x_{m-1},  F = Re <w, x_M>
+ *   dF/du[m,c] = Re Tr(dt Lc[c] G_m),  G_m = L(A_m, x_{m-1} lambda_m^dag)
+ *   lambda_M = w, lambda_{m-1} = P_m^dag lambda_m
+ * where L(A, E) is the Frechet derivative of exp at A in direction E,
+ * evaluated with the Pade [13/13] derivative recurrences that share the LU of
+ * V - U, followed by the squaring recurrence L <- R L + L R.
+ *   F    : HOST double;  grad: M x C double (device)
+ *   checkpoint_bytes : if the propagators of all slices (M n^2 16 bytes) do not
+ *          fit in this budget, they are not kept; each backward slice is rebuilt
+ *          (forward states x_m are always kept: (M+1) n 16 bytes).  <= 0: no limit.
+ * Synchronises the host with `stream`.  Returns the propagator's statuses. */
+int grape_gradient(int n, int M, int C, const void *L0, const void *Lc, const double *u, double dt,
+                   double theta, const void *x0, const void *w, double *F, double *grad,
+                   long long checkpoint_bytes, lb_workspace *ws, hipStream_t stream);
+
+/* One entry of a mixed batch: its own generator, step and state. */
+typedef struct lb_problem {
+    int d;                /* 3, 9 or 27 (any d with d*d <= 4096 is accepted) */
+    const void *L;        /* n x n complex128 generator (device) */
+    double dt;            /* step length */
+    long long nsteps;     /* >= 0 */
+    void *rho;            /* n complex128 state, in place (device) */
+} lb_problem;
+
+/* Mixed serving batch: builds every problem's propagator in FP64 (Alg. 1,
+ * problems of one size batched together) and runs every chain in `prec`
+ * (problems of one size advance together; states whose step count is reached
+ * stop being updated).  probs is a HOST array.  Synchronises the host. */
+int lindblad_batch_run(const lb_problem *probs, int nprob, lb_precision prec, double theta,
+                       lb_workspace *ws, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LINDBLAD_H */

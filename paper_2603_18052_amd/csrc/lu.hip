@@ -1,0 +1,338 @@
+// Batched solve D X = N (n x n, n right-hand sides) by LU with partial
+// pivoting -- line 6 of Alg. 1, where D = V - U and N = V + U.
+//
+// Right-looking blocked factorisation with panels of NB = 16 columns.  The
+// right-hand sides ride along as extra columns of the trailing matrix, so the
+// forward substitution L^{-1} Pi N happens inside the factorisation's trailing
+// updates and no row swap is ever applied to the already factored columns
+// (they are not needed again).  Per panel:
+//   1. lu_panel:  one workgroup per matrix (1024 threads), each thread holds
+//      whole rows of the panel in registers; per column a block-wide argmax of
+//      |a|^2 (lowest row on ties), a row exchange through LDS, the multipliers
+//      and the rank-1 update of the rest of the panel;
+//   2. swap_trsm_lower: the panel's row exchanges and the unit-lower triangular
+//      solve of the panel rows, applied column by column to the trailing
+//      columns of D and to all columns of N;
+//   3. two batched MFMA GEMMs: D22 -= L21 U12 and N2 -= L21 N1.
+// Then blocked back substitution with U: per block of NB rows from the bottom,
+// trsm_upper on the block rows of N, then N_above -= U_above,block X_block.
+#include <climits>
+
+#include "lb_internal.hpp"
+
+namespace lb {
+
+constexpr int NB = 16;
+constexpr int PANEL_THREADS = 1024;
+
+template <int R>
+__global__ void __launch_bounds__(PANEL_THREADS) lu_panel_kernel(cd *D, int n, long long sD, int k0, int *ipiv,
+                                                                 int *info) {
+    const int b = blockIdx.x;
+    cd *A = D + (size_t)b * sD;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nrows = n - k0;
+    const int ncols = min(NB, n - k0);
+
+    __shared__ double red_v[PANEL_THREADS / 64];
+    __shared__ int red_i[PANEL_THREADS / 64];
+    __shared__ cd rowbuf[2][NB];
+    __shared__ int s_piv;
+
+    cd a[R][NB];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = tid + PANEL_THREADS * q;
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            a[q][c] = (r < nrows && c < ncols) ? A[(size_t)(k0 + r) * n + k0 + c] : cd{0.0, 0.0};
+    }
+
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j < ncols) {
+        // ---- pivot search: largest |a|^2 in column j among rows >= j
+        double bv = -1.0;
+        int bi = INT_MAX;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = tid + PANEL_THREADS * q;
+            if (r >= j && r < nrows) {
+                const double v = a[q][j].re * a[q][j].re + a[q][j].im * a[q][j].im;
+                if (v > bv) {
+                    bv = v;
+                    bi = r;
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ov = __shfl_xor(bv, off);
+            const int oi = __shfl_xor(bi, off);
+            if (ov > bv || (ov == bv && oi < bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            red_v[wave] = bv;
+            red_i[wave] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double v = red_v[0];
+            int i = red_i[0];
+            for (int w = 1; w < PANEL_THREADS / 64; ++w)
+                if (red_v[w] > v || (red_v[w] == v && red_i[w] < i)) {
+                    v = red_v[w];
+                    i = red_i[w];
+                }
+            if (!(v > 0.0)) {  // zero (or NaN) pivot: flag, keep going on the diagonal
+                info[b] = 1;
+                i = j;
+            }
+            s_piv = i;
+            ipiv[(size_t)b * n + k0 + j] = k0 + i;
+        }
+        __syncthreads();
+        const int p = s_piv;
+        // ---- row exchange j <-> p through LDS; rowbuf[0] ends up holding the pivot row
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = tid + PANEL_THREADS * q;
+            if (r == p) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) rowbuf[0][c] = a[q][c];
+            }
+            if (r == j && p != j) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) rowbuf[1][c] = a[q][c];
+            }
+        }
+        __syncthreads();
+        if (p != j) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int r = tid + PANEL_THREADS * q;
+                if (r == j) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) a[q][c] = rowbuf[0][c];
+                } else if (r == p) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) a[q][c] = rowbuf[1][c];
+                }
+            }
+        }
+        // ---- multipliers and rank-1 update of the remaining panel columns
+        const cd u = rowbuf[0][j];
+        const double den = u.re * u.re + u.im * u.im;
+        const cd inv = {u.re / den, -u.im / den};
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = tid + PANEL_THREADS * q;
+            if (r > j && r < nrows) {
+                const cd l = cmul(a[q][j], inv);
+                a[q][j] = l;
+#pragma unroll
+                for (int c = j + 1; c < NB; ++c) {
+                    const cd uc = rowbuf[0][c];
+                    a[q][c].re = fma(-l.re, uc.re, fma(l.im, uc.im, a[q][c].re));
+                    a[q][c].im = fma(-l.re, uc.im, fma(-l.im, uc.re, a[q][c].im));
+                }
+            }
+        }
+        __syncthreads();  // rowbuf is rewritten by the next column
+        }
+    }
+
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = tid + PANEL_THREADS * q;
+        if (r < nrows) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                if (c < ncols) A[(size_t)(k0 + r) * n + k0 + c] = a[q][c];
+        }
+    }
+}
+
+// Row exchanges of the panel and X1 = L11^{-1} X1 on every column outside the
+// panel: trailing columns of D first, then all n columns of N.
+__global__ void __launch_bounds__(256) swap_trsm_lower_kernel(cd *D, cd *N, int n, long long sD, long long sN,
+                                                              int k0, int nb, const int *ipiv) {
+    const int b = blockIdx.y;
+    cd *Dm = D + (size_t)b * sD;
+    cd *Nm = N + (size_t)b * sN;
+    __shared__ cd L11[NB][NB];
+    __shared__ int piv[NB];
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, j = e % NB;
+        L11[i][j] = (i < nb && j < nb) ? Dm[(size_t)(k0 + i) * n + k0 + j] : cd{0.0, 0.0};
+    }
+    if (threadIdx.x < NB) piv[threadIdx.x] = threadIdx.x < nb ? ipiv[(size_t)b * n + k0 + threadIdx.x] : 0;
+    __syncthreads();
+    const int ntrail = n - k0 - nb;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;  // one column per thread (grid covers all)
+    if (v < ntrail + n) {
+        cd *col = v < ntrail ? Dm + (k0 + nb + v) : Nm + (v - ntrail);
+        for (int jj = 0; jj < nb; ++jj) {
+            const int r = k0 + jj, p = piv[jj];
+            if (p != r) {
+                const cd t = col[(size_t)r * n];
+                col[(size_t)r * n] = col[(size_t)p * n];
+                col[(size_t)p * n] = t;
+            }
+        }
+        cd x[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) x[i] = i < nb ? col[(size_t)(k0 + i) * n] : cd{0.0, 0.0};
+#pragma unroll
+        for (int i = 1; i < NB; ++i) {
+            if (i < nb) {
+                cd acc = x[i];
+#pragma unroll
+                for (int j = 0; j < i; ++j) {
+                    const cd l = L11[i][j];
+                    acc.re = fma(-l.re, x[j].re, fma(l.im, x[j].im, acc.re));
+                    acc.im = fma(-l.re, x[j].im, fma(-l.im, x[j].re, acc.im));
+                }
+                x[i] = acc;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            if (i < nb) col[(size_t)(k0 + i) * n] = x[i];
+    }
+}
+
+__device__ inline cd cdiv(cd a, cd d) {
+    const double den = d.re * d.re + d.im * d.im;
+    return {(a.re * d.re + a.im * d.im) / den, (a.im * d.re - a.re * d.im) / den};
+}
+
+// X_block = U_block^{-1} X_block for the rows [b0, b0 + nb) of every column of N.
+__global__ void __launch_bounds__(256) trsm_upper_kernel(const cd *D, cd *N, int n, long long sD, long long sN, int b0,
+                                                         int nb) {
+    const int b = blockIdx.y;
+    const cd *Dm = D + (size_t)b * sD;
+    cd *Nm = N + (size_t)b * sN;
+    __shared__ cd U[NB][NB];
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, j = e % NB;
+        U[i][j] = (i < nb && j < nb) ? Dm[(size_t)(b0 + i) * n + b0 + j] : cd{1.0, 0.0};
+    }
+    __syncthreads();
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;  // one column per thread (grid covers all)
+    if (c < n) {
+        cd x[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) x[i] = i < nb ? Nm[(size_t)(b0 + i) * n + c] : cd{0.0, 0.0};
+#pragma unroll
+        for (int i = NB - 1; i >= 0; --i) {
+            if (i < nb) {
+                cd acc = x[i];
+#pragma unroll
+                for (int j = i + 1; j < NB; ++j)
+                    if (j < nb) {
+                        const cd u = U[i][j];
+                        acc.re = fma(-u.re, x[j].re, fma(u.im, x[j].im, acc.re));
+                        acc.im = fma(-u.re, x[j].im, fma(-u.im, x[j].re, acc.im));
+                    }
+                x[i] = cdiv(acc, U[i][i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            if (i < nb) Nm[(size_t)(b0 + i) * n + c] = x[i];
+    }
+}
+
+int lu_solve_batched(int n, int batch, cd *D, cd *N, int *ipiv, int *info, hipStream_t s) {
+    const long long sD = (long long)n * n, sN = (long long)n * n;
+    if (batch > 65535) return fail(LB_ESHAPE, "lu_solve: batch > 65535");
+    for (int k0 = 0; k0 < n; k0 += NB) {
+        const int nb = n - k0 < NB ? n - k0 : NB;
+        if (n - k0 <= PANEL_THREADS)
+            lu_panel_kernel<1><<<batch, PANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
+        else if (n - k0 <= 2 * PANEL_THREADS)
+            lu_panel_kernel<2><<<batch, PANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
+        else
+            lu_panel_kernel<4><<<batch, PANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
+        LB_TRY(check_launch("lu_panel"));
+        const int ntrail = n - k0 - nb;
+        {
+            dim3 grid((ntrail + n + 255) / 256, batch);
+            swap_trsm_lower_kernel<<<grid, 256, 0, s>>>(D, N, n, sD, sN, k0, nb, ipiv);
+            LB_TRY(check_launch("swap_trsm_lower"));
+        }
+        if (ntrail > 0) {
+            ZgemmBatch g;
+            g.M = ntrail;
+            g.K = nb;
+            g.batch = batch;
+            g.A = D + (size_t)(k0 + nb) * n + k0;  // L21
+            g.lda = n;
+            g.sA = sD;
+            g.alpha = -1.0;
+            g.beta = 1.0;
+            // D22 -= L21 U12
+            g.N = ntrail;
+            g.B = D + (size_t)k0 * n + k0 + nb;  // U12
+            g.ldb = n;
+            g.sB = sD;
+            g.D = D + (size_t)(k0 + nb) * n + k0 + nb;
+            g.ldd = n;
+            g.sD = sD;
+            g.Cin = g.D;
+            g.ldc = n;
+            g.sC = sD;
+            LB_TRY(zgemm_batched(g, s));
+            // N2 -= L21 N1
+            g.N = n;
+            g.B = N + (size_t)k0 * n;
+            g.ldb = n;
+            g.sB = sN;
+            g.D = N + (size_t)(k0 + nb) * n;
+            g.ldd = n;
+            g.sD = sN;
+            g.Cin = g.D;
+            g.ldc = n;
+            g.sC = sN;
+            LB_TRY(zgemm_batched(g, s));
+        }
+    }
+    // back substitution
+    const int nblk = (n + NB - 1) / NB;
+    for (int blk = nblk - 1; blk >= 0; --blk) {
+        const int b0 = blk * NB;
+        const int nb = n - b0 < NB ? n - b0 : NB;
+        dim3 grid((n + 255) / 256, batch);
+        trsm_upper_kernel<<<grid, 256, 0, s>>>(D, N, n, sD, sN, b0, nb);
+        LB_TRY(check_launch("trsm_upper"));
+        if (b0 > 0) {
+            ZgemmBatch g;
+            g.M = b0;
+            g.N = n;
+            g.K = nb;
+            g.batch = batch;
+            g.A = D + b0;  // U[0:b0, b0:b0+nb]
+            g.lda = n;
+            g.sA = sD;
+            g.B = N + (size_t)b0 * n;
+            g.ldb = n;
+            g.sB = sN;
+            g.D = N;
+            g.ldd = n;
+            g.sD = sN;
+            g.alpha = -1.0;
+            g.beta = 1.0;
+            g.Cin = N;
+            g.ldc = n;
+            g.sC = sN;
+            LB_TRY(zgemm_batched(g, s));
+        }
+    }
+    return LB_OK;
+}
+
+}  // namespace lb

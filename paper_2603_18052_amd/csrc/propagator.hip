@@ -1,0 +1,270 @@
+// Alg. 1: P = exp(L dt) by Pade [13/13] scaling and squaring, batched over M
+// generators, FP64 throughout.
+//   norm1_kernel     ||L dt||_1 per matrix (column sums of moduli, max)
+//   host             s = smallest s >= 0 with ||A||_1 <= theta 2^s (exact)
+//   scale_kernel     A = (L dt) 2^-s
+//   zgemm            A2, A4, A6; V, W' with fused linear-combination epilogues; U
+//   zlincomb         V - U, V + U
+//   lu_solve         (V - U) P = (V + U)
+//   zgemm (masked)   s squarings, ping-pong between two buffers
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "lb_internal.hpp"
+
+namespace lb {
+
+// Pade [13/13] coefficients, b_13 = 1 and b_k = b_{k+1} (26 - k)(k + 1) / (13 - k):
+// the ratio of consecutive terms of (26 - k)! / (k! (13 - k)!).  Exact in 64-bit
+// integers (the largest intermediate is 8.4e17), each converted once to double.
+static void pade13(double b[14]) {
+    unsigned long long c = 1;
+    b[13] = 1.0;
+    for (int k = 12; k >= 0; --k) {
+        c = c * (unsigned long long)(26 - k) * (unsigned long long)(k + 1) / (unsigned long long)(13 - k);
+        b[k] = (double)c;
+    }
+}
+
+// Column sums of |L dt| over all rows, max over the columns of each matrix,
+// merged across workgroups with an integer atomic max on the bit pattern
+// (non-negative doubles order like their bits; NaN wins).
+__global__ void __launch_bounds__(256) norm1_kernel(int n, const cd *__restrict__ L, const double *__restrict__ dt,
+                                                    unsigned long long *__restrict__ normbits) {
+    const int m = blockIdx.y;
+    const cd *Lm = L + (size_t)m * n * n;
+    const double h = dt[m];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (j < n)
+        for (int i = 0; i < n; ++i) {
+            const cd v = Lm[(size_t)i * n + j];
+            s += hypot(v.re * h, v.im * h);
+        }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const double o = red[threadIdx.x + w], c = red[threadIdx.x];
+            if (isnan(o) || (!isnan(c) && o > c)) red[threadIdx.x] = o;  // NaN wins
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(normbits + m, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0ull;
+}
+
+__global__ void fill_i32_kernel(int *p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+// A = (L dt) 2^-s, elementwise (the dt product is rounded first, the power of
+// two is exact).
+__global__ void __launch_bounds__(256) scale_kernel(long long nn, int M, const cd *__restrict__ L,
+                                                    const double *__restrict__ dt, const int *__restrict__ sexp,
+                                                    cd *__restrict__ A) {
+    const long long total = nn * M;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int m = (int)(e / nn);
+        const double h = dt[m];
+        const int s = sexp[m];
+        const cd v = L[e];
+        A[e] = {ldexp(v.re * h, -s), ldexp(v.im * h, -s)};
+    }
+}
+
+// Copy src -> dst for the matrices whose squaring count is odd (their last
+// squaring landed in the scratch buffer).
+__global__ void __launch_bounds__(256) odd_copy_kernel(long long nn, int M, const int *__restrict__ sexp,
+                                                       const cd *__restrict__ src, cd *__restrict__ dst) {
+    const long long total = nn * M;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int m = (int)(e / nn);
+        if (sexp[m] & 1) dst[e] = src[e];
+    }
+}
+
+static int grid_1d(long long work) {
+    long long g = (work + 255) / 256;
+    if (g > 65536) g = 65536;
+    return (int)(g < 1 ? 1 : g);
+}
+
+int scaling_exponent(double norm, double theta) {
+    if (!std::isfinite(norm)) return -1;
+    int s = 0;
+    while (norm > std::ldexp(theta, s)) ++s;
+    return s;
+}
+
+// One chunk of matrices (all buffers sized for `M` matrices).
+static int build_chunk(int n, int M, const cd *L, const double *dt_host, double theta, cd *P, int *s_host,
+                       Workspace *ws, hipStream_t s) {
+    const size_t nn = (size_t)n * n;
+    const size_t mat = nn * sizeof(cd) * M;
+    size_t need = 8 * align256(mat) + 4 * align256(M * sizeof(double)) + align256((size_t)M * n * sizeof(int)) +
+                  2 * align256(M * sizeof(int));
+    LB_TRY(ws_reserve_total(ws, need));
+    cd *A = (cd *)ws_take(ws, mat);
+    cd *A2 = (cd *)ws_take(ws, mat);
+    cd *A4 = (cd *)ws_take(ws, mat);
+    cd *A6 = (cd *)ws_take(ws, mat);
+    cd *T = (cd *)ws_take(ws, mat);
+    cd *V = (cd *)ws_take(ws, mat);
+    cd *Wp = (cd *)ws_take(ws, mat);
+    cd *U = (cd *)ws_take(ws, mat);
+    double *d_dt = (double *)ws_take(ws, M * sizeof(double));
+    unsigned long long *d_norm = (unsigned long long *)ws_take(ws, M * sizeof(double));
+    int *d_s = (int *)ws_take(ws, M * sizeof(int));
+    int *d_info = (int *)ws_take(ws, M * sizeof(int));
+    int *d_ipiv = (int *)ws_take(ws, (size_t)M * n * sizeof(int));
+
+    LB_HIP(hipMemcpyAsync(d_dt, dt_host, M * sizeof(double), hipMemcpyHostToDevice, s));
+    fill_u64_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_norm, M);
+    fill_i32_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_info, M);
+    {
+        dim3 grid((n + 255) / 256, M);
+        norm1_kernel<<<grid, 256, 0, s>>>(n, L, d_dt, d_norm);
+        LB_TRY(check_launch("norm1"));
+    }
+    std::vector<unsigned long long> nb(M);
+    std::vector<int> sv(M);
+    LB_HIP(hipMemcpyAsync(nb.data(), d_norm, M * sizeof(double), hipMemcpyDeviceToHost, s));
+    LB_HIP(hipStreamSynchronize(s));
+    int smax = 0;
+    for (int m = 0; m < M; ++m) {
+        double v;
+        std::memcpy(&v, &nb[m], sizeof v);
+        sv[m] = scaling_exponent(v, theta);
+        if (sv[m] < 0) {
+            if (s_host) s_host[m] = -1;
+            return fail(LB_ENONFINITE, "lindblad_propagator: ||L dt||_1 of generator " + std::to_string(m) +
+                                           " is not finite");
+        }
+        if (sv[m] > smax) smax = sv[m];
+    }
+    if (s_host) std::memcpy(s_host, sv.data(), M * sizeof(int));
+    LB_HIP(hipMemcpyAsync(d_s, sv.data(), M * sizeof(int), hipMemcpyHostToDevice, s));
+    scale_kernel<<<grid_1d((long long)nn * M), 256, 0, s>>>((long long)nn, M, L, d_dt, d_s, A);
+    LB_TRY(check_launch("scale"));
+
+    double b[14];
+    pade13(b);
+    ZgemmBatch g;
+    g.M = g.N = g.K = n;
+    g.batch = M;
+    g.lda = g.ldb = g.ldd = g.ldc = g.ldx = n;
+    g.sA = g.sB = g.sD = g.sC = g.sX = (long long)nn;
+    auto mul = [&](const cd *X, const cd *Y, cd *Z) {
+        ZgemmBatch h = g;
+        h.A = X;
+        h.B = Y;
+        h.D = Z;
+        return zgemm_batched(h, s);
+    };
+    LB_TRY(mul(A, A, A2));
+    LB_TRY(mul(A2, A2, A4));
+    LB_TRY(mul(A4, A2, A6));
+    {  // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
+        const cd *X[3] = {A6, A4, A2};
+        const double c[3] = {b[12], b[10], b[8]};
+        LB_TRY(zlincomb(n, M, 3, X, c, 0.0, T, s));
+        ZgemmBatch h = g;
+        h.A = A6;
+        h.B = T;
+        h.D = V;
+        h.nx = 3;
+        h.X[0] = A6, h.X[1] = A4, h.X[2] = A2;
+        h.coef[0] = b[6], h.coef[1] = b[4], h.coef[2] = b[2];
+        h.gamma = b[0];
+        LB_TRY(zgemm_batched(h, s));
+    }
+    {  // W' = A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I;  U = A W'
+        const cd *X[3] = {A6, A4, A2};
+        const double c[3] = {b[13], b[11], b[9]};
+        LB_TRY(zlincomb(n, M, 3, X, c, 0.0, T, s));
+        ZgemmBatch h = g;
+        h.A = A6;
+        h.B = T;
+        h.D = Wp;
+        h.nx = 3;
+        h.X[0] = A6, h.X[1] = A4, h.X[2] = A2;
+        h.coef[0] = b[7], h.coef[1] = b[5], h.coef[2] = b[3];
+        h.gamma = b[1];
+        LB_TRY(zgemm_batched(h, s));
+        LB_TRY(mul(A, Wp, U));
+    }
+    {  // denominator V - U into A2, numerator V + U into P
+        const cd *X[2] = {V, U};
+        const double cm[2] = {1.0, -1.0}, cp[2] = {1.0, 1.0};
+        LB_TRY(zlincomb(n, M, 2, X, cm, 0.0, A2, s));
+        LB_TRY(zlincomb(n, M, 2, X, cp, 0.0, P, s));
+    }
+    LB_TRY(lu_solve_batched(n, M, A2, P, d_ipiv, d_info, s));
+    // squarings: level k reads buffer (k even ? P : A4) and writes the other;
+    // matrices with s <= k are skipped.
+    for (int k = 0; k < smax; ++k) {
+        ZgemmBatch h = g;
+        const cd *src = (k & 1) ? A4 : P;
+        cd *dst = (k & 1) ? P : A4;
+        h.A = src;
+        h.B = src;
+        h.D = dst;
+        h.active = d_s;
+        h.level = k;
+        LB_TRY(zgemm_batched(h, s));
+    }
+    if (smax > 0) {
+        odd_copy_kernel<<<grid_1d((long long)nn * M), 256, 0, s>>>((long long)nn, M, d_s, A4, P);
+        LB_TRY(check_launch("odd_copy"));
+    }
+    std::vector<int> info(M);
+    LB_HIP(hipMemcpyAsync(info.data(), d_info, M * sizeof(int), hipMemcpyDeviceToHost, s));
+    LB_HIP(hipStreamSynchronize(s));
+    for (int m = 0; m < M; ++m)
+        if (info[m]) return fail(LB_ESINGULAR, "lindblad_propagator: zero pivot in V - U of generator " + std::to_string(m));
+    return LB_OK;
+}
+
+int build_propagators(int n, int M, const cd *L, const double *dt_host, double theta, cd *P, int *s_host,
+                      Workspace *ws, hipStream_t s) {
+    // Chunk the batch so that the eight n x n temporaries per matrix fit in
+    // the workspace cap (and the grid's y dimension).
+    const size_t per = 8 * align256((size_t)n * n * sizeof(cd)) + 1024 + (size_t)n * sizeof(int) * 2;
+    long long chunk = (long long)(ws->cap / (per + 4096));
+    if (chunk > M) chunk = M;
+    if (chunk > 4096) chunk = 4096;
+    if (chunk < 1) return fail(LB_ENOMEM, "lindblad_propagator: workspace cap too small for one n x n build");
+    const size_t nn = (size_t)n * n;
+    for (int m0 = 0; m0 < M; m0 += (int)chunk) {
+        const int mc = (int)((M - m0) < chunk ? (M - m0) : chunk);
+        LB_TRY(build_chunk(n, mc, L + nn * m0, dt_host + m0, theta, P + nn * m0, s_host ? s_host + m0 : nullptr, ws,
+                           s));
+    }
+    return LB_OK;
+}
+
+}  // namespace lb
+
+using namespace lb;
+
+extern "C" int lindblad_propagator(int n, int M, const void *L, const double *dt, double theta, void *P, int *s_used,
+                                   lb_workspace *ws, hipStream_t stream) {
+    if (n < 1 || n > 4096) return fail(LB_ESHAPE, "lindblad_propagator: n must be in [1, 4096]");
+    if (M < 1) return fail(LB_ESHAPE, "lindblad_propagator: M must be >= 1");
+    if (!L || !dt || !P) return fail(LB_EINVAL, "lindblad_propagator: NULL pointer");
+    if (!(theta > 0.0) || !std::isfinite(theta)) return fail(LB_EINVAL, "lindblad_propagator: theta must be > 0");
+    for (int m = 0; m < M; ++m)
+        if (!std::isfinite(dt[m])) return fail(LB_EINVAL, "lindblad_propagator: dt must be finite");
+    return build_propagators(n, M, static_cast<const cd *>(L), dt, theta, static_cast<cd *>(P), s_used,
+                             ws_resolve(ws), stream);
+}

@@ -1,0 +1,238 @@
+"""ctypes binding of liblindblad.so (C-ABI in include/lindblad.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Tensors are torch CUDA (ROCm) tensors; the work is enqueued on
+torch's current stream.  If the library is missing or fails to load, every
+call raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblindblad.so")
+
+OK, EINVAL, ESHAPE, ENOMEM, EHIP, ESINGULAR, ENONFINITE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
+C128, C64, BF16_HILO, BF16_SLICED = 0, 1, 2, 3
+PRECISIONS = {"c128": C128, "c64": C64, "bf16_hilo": BF16_HILO, "bf16_sliced": BF16_SLICED}
+
+SYMBOLS = {
+    # name: (restype, argtypes)
+    "lb_workspace_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]),
+    "lb_workspace_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "lb_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "lindblad_last_error": (ctypes.c_char_p, []),
+    "lindblad_liouvillian": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "lindblad_generators": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lindblad_propagator": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+    "lindblad_propagate": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p, ctypes.c_void_p]),
+    "lindblad_propagate_baseline": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                                   ctypes.c_longlong, ctypes.c_void_p, ctypes.c_void_p]),
+    "grape_gradient": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "lindblad_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+}
+
+
+class LindbladError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    """struct lb_problem of the C-ABI."""
+    _fields_ = [("d", ctypes.c_int), ("L", ctypes.c_void_p), ("dt", ctypes.c_double),
+                ("nsteps", ctypes.c_longlong), ("rho", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_18052_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SYMBOLS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().lindblad_last_error().decode()
+
+
+def _check(rc):
+    if rc != OK:
+        raise LindbladError(rc, last_error())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype=torch.complex128, name="tensor") -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (ROCm) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Workspace:
+    """Library-owned device scratch with a byte cap (lb_workspace)."""
+
+    def __init__(self, max_bytes: int = 64 << 30):
+        h = ctypes.c_void_p()
+        _check(lib().lb_workspace_create(int(max_bytes), ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def nbytes(self) -> int:
+        return lib().lb_workspace_bytes(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            _check(lib().lb_workspace_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ws(ws):
+    return ws.handle if ws is not None else None
+
+
+# ------------------------------------------------------------ entry points
+def liouvillian(H: torch.Tensor, Lk: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Eq. (1) superoperator, row-major vectorisation: (d^2, d^2) complex128."""
+    H = _dev(H, name="H")
+    d = H.shape[0]
+    K = 0 if Lk is None else Lk.shape[0]
+    if K:
+        Lk = _dev(Lk, name="Lk")
+    if out is None:
+        out = torch.empty((d * d, d * d), dtype=torch.complex128, device=H.device)
+    _check(lib().lindblad_liouvillian(d, _ptr(H), K, _ptr(Lk) if K else None, _ptr(out), _stream()))
+    return out
+
+
+def generators(L0: torch.Tensor, Lc: torch.Tensor, u: torch.Tensor, out: torch.Tensor | None = None):
+    """Eq. (5) slice generators: out[m] = L0 + sum_c u[m, c] Lc[c]."""
+    L0 = _dev(L0, name="L0")
+    u = _dev(u, torch.float64, "u")
+    n = L0.shape[0]
+    M, C = u.shape
+    if C:
+        Lc = _dev(Lc, name="Lc")
+    if out is None:
+        out = torch.empty((M, n, n), dtype=torch.complex128, device=L0.device)
+    _check(lib().lindblad_generators(n, M, C, _ptr(L0), _ptr(Lc) if C else None, _ptr(u), _ptr(out), _stream()))
+    return out
+
+
+def propagator(L: torch.Tensor, dt, theta: float = 0.25, ws: Workspace | None = None, return_s: bool = False):
+    """Alg. 1: P = exp(L dt).  L is (n, n) or (M, n, n); dt a float or M floats."""
+    L = _dev(L, name="L")
+    single = L.dim() == 2
+    Lb = L.unsqueeze(0) if single else L
+    M, n = Lb.shape[0], Lb.shape[1]
+    dts = (ctypes.c_double * M)(*([float(dt)] * M if isinstance(dt, (int, float)) else [float(x) for x in dt]))
+    s_used = (ctypes.c_int * M)()
+    P = torch.empty_like(Lb)
+    _check(lib().lindblad_propagator(n, M, _ptr(Lb), dts, float(theta), _ptr(P), s_used, _ws(ws), _stream()))
+    P = P[0] if single else P
+    s = list(s_used)
+    if return_s:
+        return P, (s[0] if single else s)
+    return P
+
+
+def propagate(P: torch.Tensor, rho: torch.Tensor, nsteps: int, precision="c128", ws: Workspace | None = None):
+    """rho (B, n) or (B, d, d) complex128, updated in place: rho <- P^nsteps rho."""
+    P = _dev(P, name="P")
+    rho = _dev(rho, name="rho")
+    n = P.shape[0]
+    B = rho.numel() // n
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().lindblad_propagate(n, _ptr(P), prec, B, _ptr(rho), int(nsteps), _ws(ws), _stream()))
+    return rho
+
+
+def propagate_baseline(P: torch.Tensor, rho: torch.Tensor, nsteps: int, ws: Workspace | None = None):
+    P = _dev(P, name="P")
+    rho = _dev(rho, name="rho")
+    n = P.shape[0]
+    B = rho.numel() // n
+    _check(lib().lindblad_propagate_baseline(n, _ptr(P), B, _ptr(rho), int(nsteps), _ws(ws), _stream()))
+    return rho
+
+
+def grape_gradient(L0, Lc, u, dt, x0, w, theta=0.25, checkpoint_bytes=0, ws: Workspace | None = None):
+    """Returns (F, grad (M, C) float64 on the device)."""
+    L0 = _dev(L0, name="L0")
+    Lc = _dev(Lc, name="Lc")
+    u = _dev(u, torch.float64, "u")
+    x0 = _dev(x0, name="x0")
+    w = _dev(w, name="w")
+    n = L0.shape[0]
+    M, C = u.shape
+    F = ctypes.c_double(0.0)
+    grad = torch.empty((M, C), dtype=torch.float64, device=u.device)
+    _check(lib().grape_gradient(n, M, C, _ptr(L0), _ptr(Lc), _ptr(u), float(dt), float(theta), _ptr(x0), _ptr(w),
+                                ctypes.byref(F), _ptr(grad), int(checkpoint_bytes), _ws(ws), _stream()))
+    return F.value, grad
+
+
+def batch_run(problems, precision="c64", theta: float = 0.25, ws: Workspace | None = None):
+    """problems: list of dicts with d, L (n x n tensor), dt, nsteps, rho (n tensor, updated in place)."""
+    arr = (Problem * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i].d = int(p["d"])
+        arr[i].L = _dev(p["L"], name="L").data_ptr()
+        arr[i].dt = float(p["dt"])
+        arr[i].nsteps = int(p["nsteps"])
+        arr[i].rho = _dev(p["rho"], name="rho").data_ptr()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().lindblad_batch_run(arr, len(problems), prec, float(theta), _ws(ws), _stream()))
+
+
+class GrapeFidelity(torch.autograd.Function):
+    """F(u) = Re <w, x_M> with the hand-written adjoint gradient of grape_gradient."""
+
+    @staticmethod
+    def forward(ctx, u, L0, Lc, dt, x0, w, theta=0.25):
+        F, grad = grape_gradient(L0, Lc, u.detach().contiguous(), dt, x0, w, theta)
+        ctx.save_for_backward(grad)
+        return torch.tensor(F, dtype=torch.float64, device=u.device)
+
+    @staticmethod
+    def backward(ctx, gF):
+        (grad,) = ctx.saved_tensors
+        return gF * grad, None, None, None, None, None, None

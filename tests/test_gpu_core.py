@@ -1,0 +1,244 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C-ABI.
+
+Superoperator (Eq. (1)), propagator (Alg. 1) and the FP64 step chain
+(Alg. 2-3) on the configurations' own operators, at sizes the oracle finishes
+in seconds (several MFMA tiles and a ragged tail), plus sampled checks at the
+full configuration sizes.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_18052_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def N(t):
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def lb():
+    from paper_2603_18052_amd import lindblad
+    lindblad.lib()
+    assert torch.cuda.is_available()
+    return lindblad
+
+
+@pytest.fixture(scope="module")
+def systems():
+    """Oracle superoperators and propagators of the three transmon systems."""
+    out = {}
+    for q in (1, 2, 3):
+        H, Lk = W.transmon_system(q)
+        L = oracle.liouvillian(H, Lk)
+        out[q] = dict(H=H, Lk=Lk, L=L)
+    return out
+
+
+def oracle_P(systems, q):
+    s = systems[q]
+    if "P" not in s:
+        s["P"], s["s"] = oracle.propagator(s["L"], W.DT_NS, return_s=True)
+    return s["P"]
+
+
+# ------------------------------------------------------------ Liouvillian
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_liouvillian_parity(lb, systems, q):
+    s = systems[q]
+    L = N(lb.liouvillian(T(s["H"]), T(s["Lk"])))
+    assert np.abs(L - s["L"]).max() < 1e-15
+
+
+def test_liouvillian_random_and_no_collapse(lb):
+    g = np.random.default_rng(1)
+    for d, K in ((5, 3), (7, 0), (1, 1), (16, 2)):
+        H = g.standard_normal((d, d)) + 1j * g.standard_normal((d, d))
+        Lk = g.standard_normal((K, d, d)) + 1j * g.standard_normal((K, d, d))
+        ref = oracle.liouvillian(H, Lk)
+        got = N(lb.liouvillian(T(H), T(Lk) if K else None))
+        assert np.abs(got - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_generators_parity(lb, systems):
+    q = 2
+    p = W.grape_problem(q, M=7)
+    L0 = oracle.liouvillian(p["H0"], p["Lk"])
+    Lc = np.stack([oracle.liouvillian(h, p["Lk"][:0]) for h in p["Hc"]])
+    got = N(lb.generators(T(L0), T(Lc), T(p["u"])))
+    for m in range(p["M"]):
+        ref = L0.copy()
+        for c in range(Lc.shape[0]):
+            ref = ref + p["u"][m, c] * Lc[c]
+        assert np.abs(got[m] - ref).max() < 1e-15
+    # C > 16 takes the generic kernel
+    g = np.random.default_rng(3)
+    Lc2 = g.standard_normal((20, 9, 9)) + 1j * g.standard_normal((20, 9, 9))
+    u2 = g.standard_normal((3, 20))
+    got2 = N(lb.generators(T(np.eye(9, dtype=complex)), T(Lc2), T(u2)))
+    ref2 = np.eye(9) + np.einsum("mc,cij->mij", u2, Lc2)
+    assert np.abs(got2 - ref2).max() < 1e-13
+
+
+# -------------------------------------------------------------- Alg. 1
+@pytest.mark.parametrize("q", [1, 2])
+def test_propagator_parity_configs(lb, systems, q):
+    Pref = oracle_P(systems, q)
+    P, s = lb.propagator(T(systems[q]["L"]), W.DT_NS, return_s=True)
+    assert s == systems[q]["s"]
+    assert oracle.rel_fro(N(P), Pref) < 1e-13
+
+
+def test_propagator_parity_d27(lb, systems):
+    Pref = oracle_P(systems, 3)
+    P, s = lb.propagator(T(systems[3]["L"]), W.DT_NS, return_s=True)
+    assert s == systems[3]["s"] == 4
+    assert oracle.rel_fro(N(P), Pref) < 1e-12
+
+
+def test_propagator_batched_mixed_s_and_ragged(lb):
+    """M generators with different norms (different s, odd and even) and
+    n = 37 (ragged against the 64 x 64 GEMM tiles and the 16-column panels)."""
+    g = np.random.default_rng(7)
+    n, M = 37, 5
+    Ls = (g.standard_normal((M, n, n)) + 1j * g.standard_normal((M, n, n))) / np.sqrt(n)
+    dts = [0.01, 0.3, 1.0, 2.5, 7.0]
+    P, s = lb.propagator(T(Ls), dts, return_s=True)
+    P = N(P)
+    for m in range(M):
+        Pm, sm = oracle.expm(Ls[m] * dts[m], return_s=True)
+        assert s[m] == sm
+        assert oracle.rel_fro(P[m], Pm) < 1e-12
+    assert len(set(s)) >= 4
+
+
+def test_propagator_pivoting_matters(lb):
+    """A generator whose Pade denominator needs row exchanges."""
+    g = np.random.default_rng(11)
+    n = 20
+    A = g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))
+    A[np.arange(n), np.arange(n)] = -3.0  # large negative diagonal
+    P = N(lb.propagator(T(A), 1.0))
+    assert oracle.rel_fro(P, oracle.expm(A)) < 1e-12
+
+
+def test_propagator_errors(lb):
+    A = np.zeros((4, 4), complex)
+    P, s = lb.propagator(T(A), 1.0, return_s=True)
+    assert s == 0 and np.allclose(N(P), np.eye(4))
+    A[1, 2] = np.nan
+    with pytest.raises(lb.LindbladError) as e:
+        lb.propagator(T(A), 1.0)
+    assert e.value.status == lb.ENONFINITE
+    tiny = lb.Workspace(1024)
+    with pytest.raises(lb.LindbladError) as e:
+        lb.propagator(T(np.eye(9, dtype=complex)), 1.0, ws=tiny)
+    assert e.value.status == lb.ENOMEM
+    tiny.close()
+    # the stream still works afterwards
+    P = N(lb.propagator(T(np.eye(3, dtype=complex)), 0.5))
+    assert np.allclose(P, np.exp(0.5) * np.eye(3))
+
+
+# ----------------------------------------------------------- Alg. 2-3, FP64
+def states(d, B, seed):
+    g = np.random.default_rng(seed)
+    return np.stack([W.wishart_state(d, g) for _ in range(B)]).reshape(B, d * d)
+
+
+@pytest.mark.parametrize("which", ["fused", "baseline"])
+def test_chain_c128_config1(lb, systems, which):
+    """d = 3, one pure state, 1e4 steps from the oracle's P (protocol beta)."""
+    c = W.config1()
+    P = oracle_P(systems, 1)
+    ref = oracle.propagate(P, c["rho0"].reshape(1, 9), c["nsteps"])
+    x = T(c["rho0"].reshape(1, 9).copy())
+    if which == "fused":
+        lb.propagate(T(P), x, c["nsteps"], "c128")
+    else:
+        lb.propagate_baseline(T(P), x, c["nsteps"])
+    got = N(x)
+    assert oracle.rel_fro(got, ref) < 1e-12
+    assert oracle.trace_distance(got.reshape(3, 3), ref.reshape(3, 3)) < 1e-12
+
+
+@pytest.mark.parametrize("B", [1, 15, 33])
+@pytest.mark.parametrize("which", ["fused", "baseline"])
+def test_chain_c128_d9(lb, systems, B, which):
+    P = oracle_P(systems, 2)
+    X = states(9, B, 100 + B)
+    ref = oracle.propagate(P, X, 1000)
+    x = T(X.copy())
+    if which == "fused":
+        lb.propagate(T(P), x, 1000, "c128")
+    else:
+        lb.propagate_baseline(T(P), x, 1000)
+    assert oracle.rel_fro(N(x), ref) < 1e-12
+
+
+@pytest.mark.parametrize("B", [1, 20])
+def test_chain_c128_d27(lb, systems, B):
+    P = oracle_P(systems, 3)
+    X = states(27, B, 200 + B)
+    ref = oracle.propagate(P, X, 20)
+    for fn in (lambda p, x: lb.propagate(p, x, 20, "c128"), lambda p, x: lb.propagate_baseline(p, x, 20)):
+        x = T(X.copy())
+        fn(T(P), x)
+        assert oracle.rel_fro(N(x), ref) < 1e-12
+
+
+def test_chain_zero_steps_and_determinism(lb, systems):
+    P = T(oracle_P(systems, 2))
+    X = states(9, 40, 5)
+    x = T(X.copy())
+    lb.propagate(P, x, 0, "c128")
+    assert np.array_equal(N(x), X)
+    a, b = T(X.copy()), T(X.copy())
+    lb.propagate(P, a, 300, "c128")
+    lb.propagate(P, b, 300, "c128")
+    assert torch.equal(a, b)
+
+
+def test_chain_c128_config2_full_size_sampled(lb, systems):
+    """Config 2 at full size (B = 4096, 1e4 steps) on the GPU; the oracle
+    recomputes a sample of 6 states (states are independent)."""
+    c = W.config2()
+    P = oracle_P(systems, 2)
+    X = c["rho0"].reshape(4096, 81)
+    x = T(X.copy())
+    lb.propagate(T(P), x, c["nsteps"], "c128")
+    idx = [0, 1, 777, 2048, 4000, 4095]
+    ref = oracle.propagate(P, X[idx], c["nsteps"])
+    got = N(x)[idx]
+    assert oracle.rel_fro(got, ref) < 1e-12
+    td = oracle.trace_distance(got.reshape(-1, 9, 9), ref.reshape(-1, 9, 9))
+    assert td.max() < 1e-12
+
+
+# ------------------------------------------------------------ c64 (literal)
+@pytest.mark.parametrize("q", [1, 2])
+def test_chain_c64_error_report(lb, systems, q):
+    """Literal complex FP32: P rounded to FP32, FP32 accumulation.  The
+    expected trace distance after 1e3 steps is ~1e-5 (the P representation
+    error accumulates), so this checks a 1e-4 ceiling and the invariants."""
+    d = 3 ** q
+    P = oracle_P(systems, q)
+    X = states(d, 20, 300 + q)
+    ref = oracle.propagate(P, X, 1000)
+    x = T(X.copy())
+    lb.propagate(T(P), x, 1000, "c64")
+    got = N(x).reshape(-1, d, d)
+    td = oracle.trace_distance(got, ref.reshape(-1, d, d))
+    print(f"c64 d={d} trace distance after 1e3 steps: max {td.max():.3e} median {np.median(td):.3e}")
+    assert td.max() < 1e-4
+    rep = oracle.state_report(got)
+    assert rep["trace_err"].max() < 1e-4 and rep["lambda_min"].min() > -1e-4
