@@ -68,7 +68,19 @@ int chain_baseline(int n, const cd *P, int B, cd *rho, long long nsteps, Workspa
 }
 
 // ------------------------------------------------------ fused small-n chain
-constexpr int NS = 16;  // states per workgroup = one MFMA N tile
+// One workgroup of 8 wavefronts owns NS = 16 states for every step.  The
+// product Y = P X (Mp x Kp times Kp x 16) is cut into units = (16-row tile of
+// P, run of KPU consecutive 4-deep k steps).  Units are dealt round-robin to
+// the wavefronts (at most UPW each); a unit's slice of P lives in registers as
+// MFMA A fragments for the whole chain, so per step a wavefront only reads its
+// X fragments from LDS, runs its MFMAs (all units interleaved for independent
+// accumulator chains), and writes its partial tile to LDS.  After a barrier the
+// partials of each tile are summed in a fixed order (deterministic) into the
+// next X, and a second barrier ends the step.
+constexpr int NS = 16;       // states per workgroup = one MFMA N tile
+constexpr int CW = 8;        // wavefronts per workgroup
+constexpr int MAXUPW = 4;    // units per wavefront, at most
+constexpr int MAXU = CW * MAXUPW;
 
 template <typename T>
 struct Mfma;
@@ -85,95 +97,129 @@ struct Mfma<float> {
     static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T>
-static size_t fused_lds_bytes(int n) {
-    const int Kp = (n + 3) & ~3;
-    return sizeof(T) * (2 * (size_t)Kp * n + 4 * (size_t)Kp * NS);
+struct FusedShape {
+    int Kp, KS, mtiles, kparts, units, kpu;
+};
+
+static FusedShape fused_shape(int n) {
+    FusedShape f;
+    f.Kp = (n + 3) & ~3;
+    f.KS = f.Kp / 4;
+    f.mtiles = (n + 15) / 16;
+    const int cands[] = {1, 2, 3, 4, 6, 8, 11, 16, 32};
+    f.kpu = 32;
+    for (int c : cands) {
+        if (f.mtiles * ((f.KS + c - 1) / c) <= MAXU) {
+            f.kpu = c;
+            break;
+        }
+    }
+    f.kparts = (f.KS + f.kpu - 1) / f.kpu;
+    f.units = f.mtiles * f.kparts;
+    return f;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) fused_chain_kernel(int n, const cd *__restrict__ P, int B, cd *__restrict__ rho,
-                                                          long long nsteps) {
+static size_t fused_lds_bytes(int n) {
+    const FusedShape f = fused_shape(n);
+    return sizeof(T) * (2 * (size_t)f.Kp * NS + 2 * (size_t)f.units * 256);
+}
+
+template <typename T, int KPU, int UPW>
+__global__ void __launch_bounds__(CW * 64) fused_chain_kernel(int n, int kparts, const cd *__restrict__ P, int B,
+                                                              cd *__restrict__ rho, long long nsteps) {
     typedef typename Mfma<T>::acc acc_t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *smem = reinterpret_cast<T *>(smem_raw);
-    const int Kp = (n + 3) & ~3;
-    T *PT_re = smem;                 // [Kp][n]: PT[k][i] = P[i][k]
-    T *PT_im = PT_re + (size_t)Kp * n;
-    T *X_re = PT_im + (size_t)Kp * n;  // [2][Kp][NS]
-    T *X_im = X_re + 2 * (size_t)Kp * NS;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int Kp = (n + 3) & ~3, KS = Kp / 4, mtiles = (n + 15) >> 4, units = mtiles * kparts;
+    T *X_re = reinterpret_cast<T *>(smem_raw);  // [Kp][NS]
+    T *X_im = X_re + (size_t)Kp * NS;
+    T *part_re = X_im + (size_t)Kp * NS;        // [units][256]
+    T *part_im = part_re + (size_t)units * 256;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int b0 = blockIdx.x * NS;
 
-    for (int e = tid; e < Kp * n; e += 256) {
-        const int k = e / n, i = e - (e / n) * n;
-        const cd v = k < n ? P[(size_t)i * n + k] : cd{0.0, 0.0};
-        PT_re[e] = (T)v.re;
-        PT_im[e] = (T)v.im;
+    // This wavefront's A fragments (unit j = wave + CW j).  Missing work --
+    // units past the last one, k steps past KS -- is a zero fragment, so the
+    // step loop below runs without a single branch.
+    T fr[UPW][KPU], fi[UPW][KPU];
+    int xoff[UPW][KPU];  // LDS offset of the X fragment each MFMA reads
+#pragma unroll
+    for (int j = 0; j < UPW; ++j) {
+        const int u = wave + CW * j;
+        const int t = u / kparts, p = u - (u / kparts) * kparts;
+        int row = t * 16 + (lane & 15);
+        row = row < n ? row : n - 1;  // rows past n only feed discarded outputs
+#pragma unroll
+        for (int kk = 0; kk < KPU; ++kk) {
+            const int ks = p * KPU + kk;
+            int k = ks * 4 + (lane >> 4);
+            cd v = {0.0, 0.0};
+            if (u < units && ks < KS && k < n) v = P[(size_t)row * n + k];
+            fr[j][kk] = (T)v.re;
+            fi[j][kk] = (T)v.im;
+            k = k < Kp ? k : Kp - 1;  // a finite X row times a zero fragment
+            xoff[j][kk] = k * NS + (lane & 15);
+        }
     }
-    for (int e = tid; e < 2 * Kp * NS; e += 256) {
-        const int buf = e / (Kp * NS), r = e - buf * (Kp * NS);
-        const int k = r / NS, sidx = r - k * NS;
+    for (int e = tid; e < Kp * NS; e += CW * 64) {
+        const int k = e / NS, sidx = e - k * NS;
         cd v = {0.0, 0.0};
-        if (buf == 0 && k < n && b0 + sidx < B) v = rho[(size_t)(b0 + sidx) * n + k];
+        if (k < n && b0 + sidx < B) v = rho[(size_t)(b0 + sidx) * n + k];
         X_re[e] = (T)v.re;
         X_im[e] = (T)v.im;
     }
     __syncthreads();
 
-    const int mtiles = (n + 15) >> 4;
-    int cur = 0;
     for (long long t = 0; t < nsteps; ++t) {
-        const T *xr = X_re + (size_t)cur * Kp * NS, *xi = X_im + (size_t)cur * Kp * NS;
-        T *yr = X_re + (size_t)(cur ^ 1) * Kp * NS, *yi = X_im + (size_t)(cur ^ 1) * Kp * NS;
-        for (int mt0 = wave; mt0 < mtiles; mt0 += 8) {
-            const int mt1 = mt0 + 4;
-            const bool two = mt1 < mtiles;
-            acc_t a0[4], a1[4];
+        acc_t ar[UPW], ai[UPW];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a0[q] = acc_t{0, 0, 0, 0};
-                a1[q] = acc_t{0, 0, 0, 0};
-            }
-            const int r0 = mt0 * 16 + (lane & 15), r1 = mt1 * 16 + (lane & 15);
-            const bool v0 = r0 < n, v1 = two && r1 < n;
-            for (int k0 = 0; k0 < Kp; k0 += 4) {
-                const int k = k0 + (lane >> 4);
-                const T xbr = xr[k * NS + (lane & 15)], xbi = xi[k * NS + (lane & 15)];
-                const T p0r = v0 ? PT_re[(size_t)k * n + r0] : T(0), p0i = v0 ? PT_im[(size_t)k * n + r0] : T(0);
-                a0[0] = Mfma<T>::mma(p0r, xbr, a0[0]);
-                a0[1] = Mfma<T>::mma(-p0i, xbi, a0[1]);
-                a0[2] = Mfma<T>::mma(p0r, xbi, a0[2]);
-                a0[3] = Mfma<T>::mma(p0i, xbr, a0[3]);
-                if (two) {
-                    const T p1r = v1 ? PT_re[(size_t)k * n + r1] : T(0), p1i = v1 ? PT_im[(size_t)k * n + r1] : T(0);
-                    a1[0] = Mfma<T>::mma(p1r, xbr, a1[0]);
-                    a1[1] = Mfma<T>::mma(-p1i, xbi, a1[1]);
-                    a1[2] = Mfma<T>::mma(p1r, xbi, a1[2]);
-                    a1[3] = Mfma<T>::mma(p1i, xbr, a1[3]);
-                }
-            }
+        for (int j = 0; j < UPW; ++j) {
+            ar[j] = acc_t{0, 0, 0, 0};
+            ai[j] = acc_t{0, 0, 0, 0};
+        }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i0 = mt0 * 16 + Mfma<T>::row(lane, r);
-                if (i0 < n) {
-                    yr[i0 * NS + (lane & 15)] = a0[0][r] + a0[1][r];
-                    yi[i0 * NS + (lane & 15)] = a0[2][r] + a0[3][r];
-                }
-                const int i1 = mt1 * 16 + Mfma<T>::row(lane, r);
-                if (two && i1 < n) {
-                    yr[i1 * NS + (lane & 15)] = a1[0][r] + a1[1][r];
-                    yi[i1 * NS + (lane & 15)] = a1[2][r] + a1[3][r];
+        for (int kk = 0; kk < KPU; ++kk) {
+#pragma unroll
+            for (int j = 0; j < UPW; ++j) {
+                const T xr = X_re[xoff[j][kk]], xi = X_im[xoff[j][kk]];
+                ar[j] = Mfma<T>::mma(fr[j][kk], xr, ar[j]);
+                ai[j] = Mfma<T>::mma(fr[j][kk], xi, ai[j]);
+                ar[j] = Mfma<T>::mma(fi[j][kk], -xi, ar[j]);
+                ai[j] = Mfma<T>::mma(fi[j][kk], xr, ai[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < UPW; ++j) {
+            const int u = wave + CW * j;
+            if (u < units) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int o = Mfma<T>::row(lane, r) * 16 + (lane & 15);
+                    part_re[u * 256 + o] = ar[j][r];
+                    part_im[u * 256 + o] = ai[j][r];
                 }
             }
         }
-        cur ^= 1;
+        __syncthreads();
+        for (int o = tid; o < mtiles * 256; o += CW * 64) {
+            const int tt = o >> 8, lo = o & 255;
+            const int row = tt * 16 + (lo >> 4);
+            if (row < n) {
+                T sr = 0, si = 0;
+                for (int p = 0; p < kparts; ++p) {
+                    sr += part_re[(tt * kparts + p) * 256 + lo];
+                    si += part_im[(tt * kparts + p) * 256 + lo];
+                }
+                X_re[row * NS + (lo & 15)] = sr;
+                X_im[row * NS + (lo & 15)] = si;
+            }
+        }
         __syncthreads();
     }
-    const T *xr = X_re + (size_t)cur * Kp * NS, *xi = X_im + (size_t)cur * Kp * NS;
-    for (int e = tid; e < n * NS; e += 256) {
+    for (int e = tid; e < n * NS; e += CW * 64) {
         const int sidx = e / n, k = e - sidx * n;
-        if (b0 + sidx < B) rho[(size_t)(b0 + sidx) * n + k] = {(double)xr[k * NS + sidx], (double)xi[k * NS + sidx]};
+        if (b0 + sidx < B) rho[(size_t)(b0 + sidx) * n + k] = {(double)X_re[k * NS + sidx], (double)X_im[k * NS + sidx]};
     }
 }
 
@@ -187,19 +233,46 @@ int fused_max_n(lb_precision prec) {
     }
 }
 
+template <typename T, int KPU, int UPW>
+static int launch_fused_k(int n, int kparts, const cd *P, int B, cd *rho, long long nsteps, size_t lds,
+                          hipStream_t s) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        LB_HIP(hipFuncSetAttribute((const void *)fused_chain_kernel<T, KPU, UPW>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+        attr_set = true;
+    }
+    const int blocks = (B + NS - 1) / NS;
+    fused_chain_kernel<T, KPU, UPW><<<blocks, CW * 64, lds, s>>>(n, kparts, P, B, rho, nsteps);
+    return check_launch("fused_chain");
+}
+
+template <typename T, int KPU>
+static int launch_fused_u(int n, const FusedShape &f, const cd *P, int B, cd *rho, long long nsteps, size_t lds,
+                          hipStream_t s) {
+    switch ((f.units + CW - 1) / CW) {
+        case 1: return launch_fused_k<T, KPU, 1>(n, f.kparts, P, B, rho, nsteps, lds, s);
+        case 2: return launch_fused_k<T, KPU, 2>(n, f.kparts, P, B, rho, nsteps, lds, s);
+        case 3: return launch_fused_k<T, KPU, 3>(n, f.kparts, P, B, rho, nsteps, lds, s);
+        case 4: return launch_fused_k<T, KPU, 4>(n, f.kparts, P, B, rho, nsteps, lds, s);
+        default: return fail(LB_ESHAPE, "fused chain: unsupported unit count");
+    }
+}
+
 template <typename T>
 static int launch_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
     const size_t lds = fused_lds_bytes<T>(n);
     if (lds > kLdsLimit) return fail(LB_ESHAPE, "fused chain: n too large for LDS");
-    static bool attr_set = false;
-    if (!attr_set) {
-        LB_HIP(hipFuncSetAttribute((const void *)fused_chain_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)kLdsLimit));
-        attr_set = true;
+    const FusedShape f = fused_shape(n);
+    switch (f.kpu) {
+        case 1: return launch_fused_u<T, 1>(n, f, P, B, rho, nsteps, lds, s);
+        case 2: return launch_fused_u<T, 2>(n, f, P, B, rho, nsteps, lds, s);
+        case 3: return launch_fused_u<T, 3>(n, f, P, B, rho, nsteps, lds, s);
+        case 4: return launch_fused_u<T, 4>(n, f, P, B, rho, nsteps, lds, s);
+        case 6: return launch_fused_u<T, 6>(n, f, P, B, rho, nsteps, lds, s);
+        case 8: return launch_fused_u<T, 8>(n, f, P, B, rho, nsteps, lds, s);
+        default: return fail(LB_ESHAPE, "fused chain: unsupported unit shape");
     }
-    const int blocks = (B + NS - 1) / NS;
-    fused_chain_kernel<T><<<blocks, 256, lds, s>>>(n, P, B, rho, nsteps);
-    return check_launch("fused_chain");
 }
 
 // ------------------------------------------------------------- large n

@@ -242,3 +242,31 @@ def test_chain_c64_error_report(lb, systems, q):
     assert td.max() < 1e-4
     rep = oracle.state_report(got)
     assert rep["trace_err"].max() < 1e-4 and rep["lambda_min"].min() > -1e-4
+
+
+def random_contraction(n, seed):
+    g = np.random.default_rng(seed)
+    A = g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))
+    return A / (1.05 * np.linalg.norm(A, 2))
+
+
+@pytest.mark.parametrize("n", [1, 4, 16, 25, 36, 49, 64, 84])
+def test_chain_c128_fused_shapes(lb, n):
+    """Every (k-run, units-per-wavefront) shape of the fused kernel up to its
+    LDS limit, against the oracle's chain on a random contraction."""
+    P = random_contraction(n, n)
+    X = np.random.default_rng(n + 1).standard_normal((37, n)) + 0j
+    ref = oracle.propagate(P, X, 25)
+    x = T(X.copy())
+    lb.propagate(T(P), x, 25, "c128")
+    assert oracle.rel_fro(N(x), ref) < 1e-13
+
+
+@pytest.mark.parametrize("n", [9, 64, 100, 121])
+def test_chain_c64_fused_shapes(lb, n):
+    P = random_contraction(n, n + 50)
+    X = np.random.default_rng(n + 2).standard_normal((20, n)) + 0j
+    ref = oracle.propagate(P, X, 25)
+    x = T(X.copy())
+    lb.propagate(T(P), x, 25, "c64")
+    assert oracle.rel_fro(N(x), ref) < 2e-5
