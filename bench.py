@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--nsteps", type=int, default=10_000, help="chain steps per bench step")
     ap.add_argument("--precision", default="auto",
                     help="chain variant timed as `value` (auto = fastest meeting its error target)")
-    ap.add_argument("--paths", default="c128,c64,baseline", help="variants measured for the `paths` report")
+    ap.add_argument("--paths", default="c128,c64,bf16_hilo,bf16_sliced,baseline", help="variants measured for the `paths` report")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()

@@ -329,8 +329,12 @@ int chain_run(int n, const cd *P, lb_precision prec, int B, cd *rho, long long n
         case LB_C64:
             if (n <= fused_max_n(LB_C64)) return launch_fused<float>(n, P, B, rho, nsteps, s);
             return fail(LB_ENOTSUP, "lindblad_propagate: LB_C64 for n > 124 is not built yet");
+        case LB_BF16_HILO:
+        case LB_BF16_SLICED:
+            if (n <= bf16_fused_max_n(prec)) return chain_bf16_fused(n, P, prec, B, rho, nsteps, s);
+            return fail(LB_ENOTSUP, "lindblad_propagate: BF16 chains for large n are not built yet");
         default:
-            return fail(LB_ENOTSUP, "lindblad_propagate: precision not built yet");
+            return fail(LB_EINVAL, "lindblad_propagate: bad precision");
     }
 }
 

@@ -1,0 +1,110 @@
+"""BF16 chains (hi+lo and exponent-aligned slices) against the FP64 oracle
+run on the same P.  The sliced variant is gated at trace distance 1e-6
+after 1e3 steps (and after 1e4, where it switches to more slices); hi+lo is
+report-only with a ceiling derived from its ~2^-16 relative representation
+error per step."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_18052_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def lb():
+    from paper_2603_18052_amd import lindblad
+    lindblad.lib()
+    return lindblad
+
+
+@pytest.fixture(scope="module")
+def P9():
+    H, Lk = W.transmon_system(2)
+    return oracle.propagator(oracle.liouvillian(H, Lk), W.DT_NS)
+
+
+@pytest.fixture(scope="module")
+def P3():
+    H, Lk = W.transmon_system(1)
+    return oracle.propagator(oracle.liouvillian(H, Lk), W.DT_NS)
+
+
+def states(d, B, seed):
+    g = np.random.default_rng(seed)
+    return np.stack([W.wishart_state(d, g) for _ in range(B)]).reshape(B, d * d)
+
+
+def run(lb, P, X, nsteps, prec):
+    x = T(X.copy())
+    lb.propagate(T(P), x, nsteps, prec)
+    return x.cpu().numpy()
+
+
+@pytest.mark.parametrize("nsteps", [1000, 10000])
+def test_sliced_d9_meets_1e6(lb, P9, nsteps):
+    X = states(9, 37, 41)
+    ref = oracle.propagate(P9, X, nsteps)
+    got = run(lb, P9, X, nsteps, "bf16_sliced")
+    td = oracle.trace_distance(got.reshape(-1, 9, 9), ref.reshape(-1, 9, 9))
+    print(f"sliced d=9 N={nsteps}: trace distance max {td.max():.3e} median {np.median(td):.3e}")
+    assert td.max() < 1e-6
+    rep = oracle.state_report(got.reshape(-1, 9, 9))
+    assert rep["trace_err"].max() < 1e-6 and rep["lambda_min"].min() > -1e-6
+
+
+def test_sliced_d3_config1(lb, P3):
+    c = W.config1()
+    ref = oracle.propagate(P3, c["rho0"].reshape(1, 9), c["nsteps"])
+    got = run(lb, P3, c["rho0"].reshape(1, 9), c["nsteps"], "bf16_sliced")
+    td = oracle.trace_distance(got.reshape(3, 3), ref.reshape(3, 3))
+    print(f"sliced d=3 N=1e4: trace distance {td:.3e}")
+    assert td < 1e-6
+
+
+def test_sliced_single_step_precision(lb, P9):
+    """One step: the sliced product equals P x to ~2^-33 of the row scale."""
+    X = states(9, 16, 3)
+    ref = X @ P9.T
+    got = run(lb, P9, X, 1, "bf16_sliced")
+    assert np.abs(got - ref).max() < 1e-9
+
+
+@pytest.mark.parametrize("n", [1, 9, 16, 40, 64, 81, 85])
+def test_sliced_shapes(lb, n):
+    g = np.random.default_rng(n)
+    A = g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))
+    P = A / (1.02 * np.linalg.norm(A, 2))
+    X = g.standard_normal((19, n)) + 1j * g.standard_normal((19, n))
+    ref = oracle.propagate(P, X, 40)
+    got = run(lb, P, X, 40, "bf16_sliced")
+    assert oracle.rel_fro(got, ref) < 1e-8
+
+
+def test_sliced_deterministic_and_zero_state(lb, P9):
+    X = states(9, 20, 8)
+    X[3] = 0.0  # an all-zero state stays zero (exponent rule for m = 0)
+    a = run(lb, P9, X, 500, "bf16_sliced")
+    b = run(lb, P9, X, 500, "bf16_sliced")
+    assert np.array_equal(a, b)
+    assert np.all(a[3] == 0)
+    assert np.array_equal(run(lb, P9, X, 0, "bf16_sliced"), X)
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_hilo_error_report(lb, P3, P9, q):
+    d = 3 ** q
+    P = P3 if q == 1 else P9
+    X = states(d, 20, 70 + q)
+    ref = oracle.propagate(P, X, 1000)
+    got = run(lb, P, X, 1000, "bf16_hilo")
+    td = oracle.trace_distance(got.reshape(-1, d, d), ref.reshape(-1, d, d))
+    print(f"hilo d={d} N=1e3: trace distance max {td.max():.3e} median {np.median(td):.3e}")
+    assert td.max() < 5e-3
