@@ -27,9 +27,14 @@ int check_launch(const char *what) {
 }
 
 // ------------------------------------------------------------ workspace
-int ws_reserve_total(Workspace *ws, size_t bytes) {
-    ws->used = 0;
-    if (bytes <= ws->size) return LB_OK;
+void ws_begin(Workspace *ws) { ws->used = 0; }
+
+int ws_ensure(Workspace *ws, size_t bytes) {
+    bytes = align256(bytes);
+    if (ws->used + bytes <= ws->size) return LB_OK;
+    if (ws->used != 0)
+        return fail(LB_ENOMEM, "workspace: nested request of " + std::to_string(bytes) +
+                                   " bytes exceeds the reservation");
     if (bytes > ws->cap)
         return fail(LB_ENOMEM, "workspace: need " + std::to_string(bytes) + " bytes, cap is " +
                                    std::to_string(ws->cap));

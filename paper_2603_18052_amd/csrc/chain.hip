@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) baseline_step_kernel(int n, const cd *__r
 int chain_baseline(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
     if (nsteps == 0 || B == 0) return LB_OK;
     const size_t bytes = (size_t)B * n * sizeof(cd);
-    LB_TRY(ws_reserve_total(ws, align256(bytes)));
+    LB_TRY(ws_ensure(ws, bytes));
     cd *tmp = (cd *)ws_take(ws, bytes);
     const long long rows = (long long)B * n;
     long long blocks = (rows + 3) / 4;
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(256) transpose_kernel(int n, const cd *__restr
 
 static int chain_large_c128(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
     const size_t pbytes = (size_t)n * n * sizeof(cd), xbytes = (size_t)B * n * sizeof(cd);
-    LB_TRY(ws_reserve_total(ws, align256(pbytes) + align256(xbytes)));
+    LB_TRY(ws_ensure(ws, align256(pbytes) + align256(xbytes)));
     cd *PT = (cd *)ws_take(ws, pbytes);
     cd *tmp = (cd *)ws_take(ws, xbytes);
     dim3 tg((n + 31) / 32, (n + 31) / 32);
@@ -354,11 +354,15 @@ extern "C" int lindblad_propagate(int n, const void *P, lb_precision prec, int B
                                   lb_workspace *ws, hipStream_t stream) {
     LB_TRY(validate_chain("lindblad_propagate", n, P, B, rho, nsteps));
     if ((int)prec < LB_C128 || (int)prec > LB_BF16_SLICED) return fail(LB_EINVAL, "lindblad_propagate: bad precision");
-    return chain_run(n, static_cast<const cd *>(P), prec, B, static_cast<cd *>(rho), nsteps, ws_resolve(ws), stream);
+    Workspace *w = ws_resolve(ws);
+    ws_begin(w);
+    return chain_run(n, static_cast<const cd *>(P), prec, B, static_cast<cd *>(rho), nsteps, w, stream);
 }
 
 extern "C" int lindblad_propagate_baseline(int n, const void *P, int B, void *rho, long long nsteps, lb_workspace *ws,
                                            hipStream_t stream) {
     LB_TRY(validate_chain("lindblad_propagate_baseline", n, P, B, rho, nsteps));
-    return chain_baseline(n, static_cast<const cd *>(P), B, static_cast<cd *>(rho), nsteps, ws_resolve(ws), stream);
+    Workspace *w = ws_resolve(ws);
+    ws_begin(w);
+    return chain_baseline(n, static_cast<const cd *>(P), B, static_cast<cd *>(rho), nsteps, w, stream);
 }

@@ -1,14 +1,433 @@
-// GRAPE fidelity gradient (adjoint + Frechet derivative of the propagator).
+// GRAPE fidelity and gradient for piecewise-constant controls (the
+// control-affine segment generator of Eq. (5), propagators by Alg. 1).
+//
+//   A_m = dt (L0 + sum_c u[m,c] Lc[c]),  P_m = exp(A_m)
+//   x_{m+1} = P_m x_m (0-based slices),   F = Re <w, x_M>
+//   lambda_M = w,  lambda_m = P_m^dag lambda_{m+1}
+//   dF/du[m,c] = Re <lambda_{m+1}, L(A_m, dt Lc[c]) x_m> = dt Re Tr(Lc[c] G_m),
+//   G_m = L(A_m, x_m lambda_{m+1}^dag)
+// using Tr(L(A,E) B) = Tr(E L(A,B)) for the Frechet derivative of exp, so one
+// derivative per slice (in a rank-1 direction) serves every control.
+//
+// The derivative is evaluated with the Pade [13/13] derivative recurrences
+// of scaling and squaring (Al-Mohy & Higham, SIAM J. Matrix Anal. Appl. 30,
+// 2009): with X = A/2^s and F = E/2^s, the products and their directional
+// derivatives
+//   A2 = X X,   M2 = X F + F X;   A4 = A2 A2, M4 = A2 M2 + M2 A2;
+//   A6 = A2 A4, M6 = A4 M2 + M4 A2;
+//   W1 = b13 A6 + b11 A4 + b9 A2,  W = A6 W1 + b7 A6 + b5 A4 + b3 A2 + b1 I,  U = X W
+//   Z1 = b12 A6 + b10 A4 + b8 A2,  V = A6 Z1 + b6 A6 + b4 A4 + b2 A2 + b0 I
+//   Lw = A6 (b13 M6 + b11 M4 + b9 M2) + M6 W1 + b7 M6 + b5 M4 + b3 M2
+//   Lu = X Lw + F W
+//   Lv = A6 (b12 M6 + b10 M4 + b8 M2) + M6 Z1 + b6 M6 + b4 M4 + b2 M2
+// one LU of Q = V - U solving Q [X1 | X2 | R] = [Lu + Lv | Lu - Lv | V + U],
+// L = X1 + X2 R (the derivative of Q^{-1}(V + U)), then s times
+//   L <- R L + L R,  R <- R R.
+// All slices of a chunk go through these steps together as batched GEMMs.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "lb_internal.hpp"
+
+namespace lb {
+
+namespace grape {
+
+__global__ void outer_kernel(int n, int Mc, const cd *__restrict__ x, const cd *__restrict__ lam,
+                             const int *__restrict__ sexp, cd *__restrict__ E) {
+    const long long nn = (long long)n * n, total = nn * Mc;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int m = (int)(e / nn);
+        const long long r = e - (long long)m * nn;
+        const int i = (int)(r / n), j = (int)(r - (long long)i * n);
+        const cd a = x[(size_t)m * n + i], b = lam[(size_t)m * n + j];
+        const int s = sexp[m];
+        E[e] = {ldexp(a.re * b.re + a.im * b.im, -s), ldexp(a.im * b.re - a.re * b.im, -s)};  // a conj(b)
+    }
+}
+
+// RHS (n x 3n per slice) = [Lu + Lv | Lu - Lv | V + U]
+__global__ void rhs3_kernel(int n, int Mc, const cd *__restrict__ Lu, const cd *__restrict__ Lv,
+                            const cd *__restrict__ V, const cd *__restrict__ U, cd *__restrict__ R3) {
+    const long long nn = (long long)n * n, total = nn * Mc;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long m = e / nn, r = e - m * nn;
+        const long long i = r / n, j = r - i * n;
+        cd *row = R3 + (size_t)m * 3 * nn + (size_t)i * 3 * n;
+        const cd lu = Lu[e], lv = Lv[e], v = V[e], u = U[e];
+        row[j] = cadd(lu, lv);
+        row[n + j] = csub(lu, lv);
+        row[2 * n + j] = cadd(v, u);
+    }
+}
+
+// dst[m] (n x n, contiguous) = block `blk` (n columns) of src[m] (n x 3n)
+__global__ void take_block_kernel(int n, int Mc, const cd *__restrict__ R3, int blk, cd *__restrict__ dst) {
+    const long long nn = (long long)n * n, total = nn * Mc;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long m = e / nn, r = e - m * nn;
+        const long long i = r / n, j = r - i * n;
+        dst[e] = R3[(size_t)m * 3 * nn + (size_t)i * 3 * n + (size_t)blk * n + j];
+    }
+}
+
+// y = P x (one state), one wavefront per row, lanes over the row
+__global__ void __launch_bounds__(256) matvec_kernel(int n, const cd *__restrict__ P, const cd *__restrict__ x,
+                                                     cd *__restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= n) return;
+    double re = 0.0, im = 0.0;
+    for (int j = lane; j < n; j += 64) {
+        const cd p = P[(size_t)row * n + j], v = x[j];
+        re = fma(p.re, v.re, fma(-p.im, v.im, re));
+        im = fma(p.re, v.im, fma(p.im, v.re, im));
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        re += __shfl_xor(re, off);
+        im += __shfl_xor(im, off);
+    }
+    if (lane == 0) y[row] = {re, im};
+}
+
+// y = P^dag x: thread j sums conj(P[i][j]) x[i] over i (coalesced across j)
+__global__ void __launch_bounds__(256) matvec_h_kernel(int n, const cd *__restrict__ P, const cd *__restrict__ x,
+                                                       cd *__restrict__ y) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double re = 0.0, im = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const cd p = P[(size_t)i * n + j], v = x[i];
+        re = fma(p.re, v.re, fma(p.im, v.im, re));   // conj(p) v
+        im = fma(p.re, v.im, fma(-p.im, v.re, im));
+    }
+    y[j] = {re, im};
+}
+
+// F = Re sum conj(w_i) x_i, one workgroup, fixed reduction order
+__global__ void __launch_bounds__(256) fidelity_kernel(int n, const cd *__restrict__ w, const cd *__restrict__ x,
+                                                       double *__restrict__ F) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += w[i].re * x[i].re + w[i].im * x[i].im;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *F = red[0];
+}
+
+// LcT[c] = Lc[c]^T
+__global__ void transpose_batch_kernel(int n, int C, const cd *__restrict__ Lc, cd *__restrict__ LcT) {
+    const long long nn = (long long)n * n, total = nn * C;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long c = e / nn, r = e - c * nn;
+        const long long i = r / n, j = r - i * n;
+        LcT[c * nn + j * n + i] = Lc[e];
+    }
+}
+
+constexpr int CMAX = 16;
+constexpr int CHUNK = 4096;  // elements per contraction workgroup
+
+// partial[(b * Mc + m) * C + c] = Re sum_{e in chunk b} LcT[c][e] G[m][e]
+__global__ void __launch_bounds__(256) contract_kernel(long long nn, int C, const cd *__restrict__ LcT,
+                                                       const cd *__restrict__ G, int Mc, double *__restrict__ partial) {
+    const int b = blockIdx.x, m = blockIdx.y;
+    double acc[CMAX];
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c) acc[c] = 0.0;
+    const long long e0 = (long long)b * CHUNK;
+    const cd *Gm = G + (size_t)m * nn;
+    for (long long e = e0 + threadIdx.x; e < e0 + CHUNK && e < nn; e += 256) {
+        const cd g = Gm[e];
+#pragma unroll
+        for (int c = 0; c < CMAX; ++c)
+            if (c < C) {
+                const cd l = LcT[(size_t)c * nn + e];
+                acc[c] = fma(l.re, g.re, fma(-l.im, g.im, acc[c]));
+            }
+    }
+    __shared__ double red[256];
+    for (int c = 0; c < C; ++c) {
+        red[threadIdx.x] = acc[c];
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[((size_t)b * Mc + m) * C + c] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void contract_reduce_kernel(int nblk, int Mc, int C, double dt, const double *__restrict__ partial,
+                                       double *__restrict__ grad) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Mc * C) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * Mc * C + t];
+    grad[t] = dt * s;
+}
+
+static int grid1(long long work) {
+    long long g = (work + 255) / 256;
+    if (g > 65536) g = 65536;
+    return (int)(g < 1 ? 1 : g);
+}
+
+constexpr int FRECHET_MATS = 26;  // n x n temporaries per slice (RHS3 counts 3)
+
+static size_t frechet_bytes(int n, int Mc) {
+    const size_t mat = align256((size_t)n * n * sizeof(cd) * Mc);
+    return FRECHET_MATS * mat + 4 * align256(Mc * sizeof(double)) + align256((size_t)Mc * n * sizeof(int)) +
+           2 * align256(Mc * sizeof(int));
+}
+
+// G[m] = L(A_m, x_m lam_m^dag) for a chunk of Mc slices; A_m = dt Lg[m].
+static int frechet_chunk(int n, int Mc, const cd *Lg, const double *dt_host, const cd *x, const cd *lam, double theta,
+                         cd *G, Workspace *ws, hipStream_t s) {
+    const size_t nn = (size_t)n * n, mat = nn * sizeof(cd) * Mc;
+    LB_TRY(ws_ensure(ws, frechet_bytes(n, Mc)));
+    const size_t mark = ws->used;
+    struct Release {
+        Workspace *w;
+        size_t m;
+        ~Release() { w->used = m; }
+    } release{ws, mark};
+    cd *A = (cd *)ws_take(ws, mat), *E = (cd *)ws_take(ws, mat);
+    cd *A2 = (cd *)ws_take(ws, mat), *A4 = (cd *)ws_take(ws, mat), *A6 = (cd *)ws_take(ws, mat);
+    cd *M2 = (cd *)ws_take(ws, mat), *M4 = (cd *)ws_take(ws, mat), *M6 = (cd *)ws_take(ws, mat);
+    cd *W1 = (cd *)ws_take(ws, mat), *Z1 = (cd *)ws_take(ws, mat), *T = (cd *)ws_take(ws, mat);
+    cd *W = (cd *)ws_take(ws, mat), *U = (cd *)ws_take(ws, mat), *V = (cd *)ws_take(ws, mat);
+    cd *Lw = (cd *)ws_take(ws, mat), *Lu = (cd *)ws_take(ws, mat), *Lv = (cd *)ws_take(ws, mat);
+    cd *Q = (cd *)ws_take(ws, mat), *R = (cd *)ws_take(ws, mat), *Rt = (cd *)ws_take(ws, mat);
+    cd *Lt = (cd *)ws_take(ws, mat);
+    cd *R3 = (cd *)ws_take(ws, 3 * mat);
+    double *d_dt = (double *)ws_take(ws, Mc * sizeof(double));
+    unsigned long long *d_norm = (unsigned long long *)ws_take(ws, Mc * sizeof(double));
+    int *d_s = (int *)ws_take(ws, Mc * sizeof(int));
+    int *d_info = (int *)ws_take(ws, Mc * sizeof(int));
+    int *d_ipiv = (int *)ws_take(ws, (size_t)Mc * n * sizeof(int));
+
+    LB_TRY(fill_i32_launch(d_info, Mc, s));
+    std::vector<int> sv(Mc);
+    LB_TRY(scaling_stage(n, Mc, Lg, dt_host, theta, d_dt, d_norm, d_s, sv.data(), s));
+    int smax = 0;
+    for (int m = 0; m < Mc; ++m) smax = sv[m] > smax ? sv[m] : smax;
+    LB_TRY(scale_launch(n, Mc, Lg, d_dt, d_s, A, s));
+    outer_kernel<<<grid1((long long)nn * Mc), 256, 0, s>>>(n, Mc, x, lam, d_s, E);
+    LB_TRY(check_launch("outer"));
+
+    double b[14];
+    pade13_coefficients(b);
+    ZgemmBatch g;
+    g.M = g.N = g.K = n;
+    g.batch = Mc;
+    g.lda = g.ldb = g.ldd = g.ldc = g.ldx = n;
+    g.sA = g.sB = g.sD = g.sC = g.sX = (long long)nn;
+    auto mul = [&](const cd *X, const cd *Y, cd *Z, bool acc) {
+        ZgemmBatch h = g;
+        h.A = X, h.B = Y, h.D = Z;
+        if (acc) h.beta = 1.0, h.Cin = Z;
+        return zgemm_batched(h, s);
+    };
+    auto mul_lc = [&](const cd *X, const cd *Y, cd *Z, const cd *x0, const cd *x1, const cd *x2, double c0,
+                      double c1, double c2, double gamma) {
+        ZgemmBatch h = g;
+        h.A = X, h.B = Y, h.D = Z;
+        h.nx = 3;
+        h.X[0] = x0, h.X[1] = x1, h.X[2] = x2;
+        h.coef[0] = c0, h.coef[1] = c1, h.coef[2] = c2;
+        h.gamma = gamma;
+        return zgemm_batched(h, s);
+    };
+    auto lin3 = [&](const cd *x0, const cd *x1, const cd *x2, double c0, double c1, double c2, cd *D) {
+        const cd *X[3] = {x0, x1, x2};
+        const double c[3] = {c0, c1, c2};
+        return zlincomb(n, Mc, 3, X, c, 0.0, D, s);
+    };
+    LB_TRY(mul(A, A, A2, false));
+    LB_TRY(mul(A, E, M2, false));
+    LB_TRY(mul(E, A, M2, true));
+    LB_TRY(mul(A2, A2, A4, false));
+    LB_TRY(mul(A2, M2, M4, false));
+    LB_TRY(mul(M2, A2, M4, true));
+    LB_TRY(mul(A2, A4, A6, false));
+    LB_TRY(mul(A4, M2, M6, false));
+    LB_TRY(mul(M4, A2, M6, true));
+    LB_TRY(lin3(A6, A4, A2, b[13], b[11], b[9], W1));
+    LB_TRY(mul_lc(A6, W1, W, A6, A4, A2, b[7], b[5], b[3], b[1]));
+    LB_TRY(mul(A, W, U, false));
+    LB_TRY(lin3(A6, A4, A2, b[12], b[10], b[8], Z1));
+    LB_TRY(mul_lc(A6, Z1, V, A6, A4, A2, b[6], b[4], b[2], b[0]));
+    LB_TRY(lin3(M6, M4, M2, b[13], b[11], b[9], T));
+    LB_TRY(mul_lc(A6, T, Lw, M6, M4, M2, b[7], b[5], b[3], 0.0));
+    LB_TRY(mul(M6, W1, Lw, true));
+    LB_TRY(mul(A, Lw, Lu, false));
+    LB_TRY(mul(E, W, Lu, true));
+    LB_TRY(lin3(M6, M4, M2, b[12], b[10], b[8], T));
+    LB_TRY(mul_lc(A6, T, Lv, M6, M4, M2, b[6], b[4], b[2], 0.0));
+    LB_TRY(mul(M6, Z1, Lv, true));
+    {
+        const cd *X[2] = {V, U};
+        const double c[2] = {1.0, -1.0};
+        LB_TRY(zlincomb(n, Mc, 2, X, c, 0.0, Q, s));
+    }
+    rhs3_kernel<<<grid1((long long)nn * Mc), 256, 0, s>>>(n, Mc, Lu, Lv, V, U, R3);
+    LB_TRY(check_launch("rhs3"));
+    LB_TRY(lu_solve_batched(n, 3 * n, Mc, Q, R3, d_ipiv, d_info, s));
+    take_block_kernel<<<grid1((long long)nn * Mc), 256, 0, s>>>(n, Mc, R3, 2, R);
+    LB_TRY(check_launch("take_block"));
+    {  // L = X1 + X2 R  into G
+        ZgemmBatch h = g;
+        h.A = R3 + n;  // X2
+        h.lda = 3 * n;
+        h.sA = 3 * (long long)nn;
+        h.B = R;
+        h.D = G;
+        h.beta = 1.0;
+        h.Cin = R3;  // X1
+        h.ldc = 3 * n;
+        h.sC = 3 * (long long)nn;
+        LB_TRY(zgemm_batched(h, s));
+    }
+    // squarings, masked by each slice's s: level k reads (k even ? G, R : Lt, Rt)
+    for (int k = 0; k < smax; ++k) {
+        const cd *Ls = (k & 1) ? Lt : G, *Rs = (k & 1) ? Rt : R;
+        cd *Ld = (k & 1) ? G : Lt, *Rd = (k & 1) ? R : Rt;
+        ZgemmBatch h = g;
+        h.active = d_s;
+        h.level = k;
+        h.A = Rs, h.B = Ls, h.D = Ld;
+        LB_TRY(zgemm_batched(h, s));
+        h.A = Ls, h.B = Rs, h.beta = 1.0, h.Cin = Ld;
+        LB_TRY(zgemm_batched(h, s));
+        h.A = Rs, h.B = Rs, h.D = Rd, h.beta = 0.0, h.Cin = nullptr;
+        LB_TRY(zgemm_batched(h, s));
+    }
+    if (smax > 0) LB_TRY(odd_copy_launch(n, Mc, d_s, Lt, G, s));
+    std::vector<int> info(Mc);
+    LB_HIP(hipMemcpyAsync(info.data(), d_info, Mc * sizeof(int), hipMemcpyDeviceToHost, s));
+    LB_HIP(hipStreamSynchronize(s));
+    for (int m = 0; m < Mc; ++m)
+        if (info[m]) return fail(LB_ESINGULAR, "grape_gradient: zero pivot in V - U of a slice");
+    return LB_OK;
+}
+
+}  // namespace grape
+
+int generators_launch(int n, int M, int C, const cd *L0, const cd *Lc, const double *u, cd *Lout, hipStream_t s);
+
+static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const double *u, double dt, double theta,
+                     const cd *x0, const cd *w, double *F, double *grad, long long checkpoint_bytes, Workspace *ws,
+                     hipStream_t s) {
+    using namespace grape;
+    const size_t nn = (size_t)n * n;
+    const size_t matb = nn * sizeof(cd);
+    const bool keepP = checkpoint_bytes <= 0 || (double)M * (double)matb <= (double)checkpoint_bytes;
+    const int Mc = M < 16 ? M : 16;  // slices per batched chunk
+    const int nblk = (int)((nn + CHUNK - 1) / CHUNK);
+    // ---- reservation: persistent buffers + the larger of the chunk phases
+    size_t persistent = align256((size_t)(M + 1) * n * sizeof(cd)) * 2 + align256((size_t)C * matb) +
+                        align256(sizeof(double)) + align256((size_t)nblk * Mc * C * sizeof(double)) +
+                        (keepP ? align256((size_t)M * matb) : 0);
+    size_t chunkp = 2 * align256((size_t)Mc * matb);  // generators + propagators of a chunk
+    size_t phase = build_workspace_bytes(n, Mc);
+    const size_t fr = frechet_bytes(n, Mc) + align256((size_t)Mc * matb);
+    if (fr > phase) phase = fr;
+    const size_t total = persistent + chunkp + phase;
+    LB_TRY(ws_ensure(ws, total));
+    cd *xs = (cd *)ws_take(ws, (size_t)(M + 1) * n * sizeof(cd));
+    cd *lams = (cd *)ws_take(ws, (size_t)(M + 1) * n * sizeof(cd));
+    cd *LcT = (cd *)ws_take(ws, (size_t)C * matb);
+    double *d_F = (double *)ws_take(ws, sizeof(double));
+    double *partial = (double *)ws_take(ws, (size_t)nblk * Mc * C * sizeof(double));
+    cd *Pall = keepP ? (cd *)ws_take(ws, (size_t)M * matb) : nullptr;
+    cd *Lg = (cd *)ws_take(ws, (size_t)Mc * matb);
+    cd *Pc = (cd *)ws_take(ws, (size_t)Mc * matb);
+    std::vector<double> dts(Mc, dt);
+
+    if (C > 0) {
+        transpose_batch_kernel<<<grid1((long long)nn * C), 256, 0, s>>>(n, C, Lc, LcT);
+        LB_TRY(check_launch("transpose_batch"));
+    }
+    LB_HIP(hipMemcpyAsync(xs, x0, n * sizeof(cd), hipMemcpyDeviceToDevice, s));
+    auto chunk_props = [&](int m0, int mc, cd *dst) -> int {
+        LB_TRY(generators_launch(n, mc, C, L0, Lc, u + (size_t)m0 * C, Lg, s));
+        return build_propagators(n, mc, Lg, dts.data(), theta, dst, nullptr, ws, s);
+    };
+    // ---- forward: propagators (kept if they fit the budget) and states
+    for (int m0 = 0; m0 < M; m0 += Mc) {
+        const int mc = M - m0 < Mc ? M - m0 : Mc;
+        cd *Pdst = keepP ? Pall + (size_t)m0 * nn : Pc;
+        LB_TRY(chunk_props(m0, mc, Pdst));
+        for (int m = 0; m < mc; ++m) {
+            matvec_kernel<<<(n * 64 + 255) / 256, 256, 0, s>>>(n, Pdst + (size_t)m * nn, xs + (size_t)(m0 + m) * n,
+                                                              xs + (size_t)(m0 + m + 1) * n);
+        }
+        LB_TRY(check_launch("matvec"));
+    }
+    fidelity_kernel<<<1, 256, 0, s>>>(n, w, xs + (size_t)M * n, d_F);
+    LB_TRY(check_launch("fidelity"));
+    LB_HIP(hipMemcpyAsync(F, d_F, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!grad) {
+        LB_HIP(hipStreamSynchronize(s));
+        return LB_OK;
+    }
+    // ---- backward, chunks from the last slice
+    LB_HIP(hipMemcpyAsync(lams + (size_t)M * n, w, n * sizeof(cd), hipMemcpyDeviceToDevice, s));
+    const int nchunks = (M + Mc - 1) / Mc;
+    for (int ci = nchunks - 1; ci >= 0; --ci) {
+        const int m0 = ci * Mc, mc = M - m0 < Mc ? M - m0 : Mc;
+        const cd *Pch = keepP ? Pall + (size_t)m0 * nn : Pc;
+        if (!keepP) LB_TRY(chunk_props(m0, mc, Pc));
+        for (int m = mc - 1; m >= 0; --m)
+            matvec_h_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, Pch + (size_t)m * nn, lams + (size_t)(m0 + m + 1) * n,
+                                                           lams + (size_t)(m0 + m) * n);
+        LB_TRY(check_launch("matvec_h"));
+        // generators of the chunk, then the batched Frechet derivatives
+        LB_TRY(generators_launch(n, mc, C, L0, Lc, u + (size_t)m0 * C, Lg, s));
+        const size_t mark = ws->used;
+        cd *G = (cd *)ws_take(ws, (size_t)mc * matb);
+        LB_TRY(frechet_chunk(n, mc, Lg, dts.data(), xs + (size_t)m0 * n, lams + (size_t)(m0 + 1) * n, theta, G, ws,
+                             s));
+        if (C > 0) {
+            dim3 cg(nblk, mc);
+            contract_kernel<<<cg, 256, 0, s>>>((long long)nn, C, LcT, G, mc, partial);
+            LB_TRY(check_launch("contract"));
+            contract_reduce_kernel<<<(mc * C + 255) / 256, 256, 0, s>>>(nblk, mc, C, dt, partial,
+                                                                        grad + (size_t)m0 * C);
+            LB_TRY(check_launch("contract_reduce"));
+        }
+        ws->used = mark;
+    }
+    LB_HIP(hipStreamSynchronize(s));
+    return LB_OK;
+}
+
+}  // namespace lb
 
 using namespace lb;
 
 extern "C" int grape_gradient(int n, int M, int C, const void *L0, const void *Lc, const double *u, double dt,
                               double theta, const void *x0, const void *w, double *F, double *grad,
                               long long checkpoint_bytes, lb_workspace *ws, hipStream_t stream) {
-    (void)n; (void)M; (void)C; (void)L0; (void)Lc; (void)u; (void)dt; (void)theta; (void)x0; (void)w;
-    (void)F; (void)grad; (void)checkpoint_bytes; (void)ws; (void)stream;
-    return fail(LB_ENOTSUP, "grape_gradient: not built yet");
+    if (n < 1 || n > 4096) return fail(LB_ESHAPE, "grape_gradient: n must be in [1, 4096]");
+    if (M < 1 || C < 0 || C > grape::CMAX) return fail(LB_ESHAPE, "grape_gradient: need M >= 1, 0 <= C <= 16");
+    if (!L0 || !x0 || !w || !F || (C > 0 && (!Lc || !u))) return fail(LB_EINVAL, "grape_gradient: NULL pointer");
+    if (!std::isfinite(dt) || !(theta > 0.0)) return fail(LB_EINVAL, "grape_gradient: bad dt or theta");
+    Workspace *wsp = ws_resolve(ws);
+    ws_begin(wsp);
+    return grape_run(n, M, C, static_cast<const cd *>(L0), static_cast<const cd *>(Lc), u, dt, theta,
+                     static_cast<const cd *>(x0), static_cast<const cd *>(w), F, grad, checkpoint_bytes, wsp, stream);
 }
 
 extern "C" int lindblad_batch_run(const lb_problem *probs, int nprob, lb_precision prec, double theta,

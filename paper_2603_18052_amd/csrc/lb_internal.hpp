@@ -41,11 +41,15 @@ struct Workspace {
     int device = -1;
 };
 
-// Reserve `bytes` (256-byte aligned) from ws for the current call.  Grows the
-// device buffer (synchronising the device) if needed.  Pointers handed out
-// earlier in the same call stay valid only if no growth happens after them,
-// so callers reserve everything they need first with reserve_all().
-int ws_reserve_total(Workspace *ws, size_t bytes);
+// Bump allocation inside one device buffer.  A top-level entry point calls
+// ws_begin(), which resets the bump offset; a routine takes what it needs
+// with ws_ensure() + ws_take() and gives it back by restoring ws->used.
+// ws_ensure grows the buffer (synchronising the device, invalidating earlier
+// pointers) only when nothing is taken yet; a nested request beyond the
+// reservation fails with LB_ENOMEM, so callers that nest reserve the total
+// first.
+void ws_begin(Workspace *ws);
+int ws_ensure(Workspace *ws, size_t bytes);
 void *ws_take(Workspace *ws, size_t bytes);
 Workspace *ws_resolve(lb_workspace *ws);
 
@@ -99,10 +103,27 @@ int zlincomb(int n, int batch, int nx, const cd *const *X, const double *coef, d
 // Uses the workspace; synchronises the stream.
 int build_propagators(int n, int M, const cd *L, const double *dt_host, double theta, cd *P, int *s_host,
                       Workspace *ws, hipStream_t s);
+// Workspace bytes build_propagators needs for a batch of M (chunked inside).
+size_t build_workspace_bytes(int n, int M);
+
+// Scaling stage of Alg. 1 for M generators: s[m] from ||L[m] dt[m]||_1
+// (host sync), uploaded to d_s; d_dt receives dt.  Fails with LB_ENONFINITE.
+int scaling_stage(int n, int M, const cd *L, const double *dt_host, double theta, double *d_dt,
+                  unsigned long long *d_norm, int *d_s, int *s_host, hipStream_t s);
+// A[m] = (L[m] dt[m]) 2^-s[m]
+int scale_launch(int n, int M, const cd *L, const double *d_dt, const int *d_s, cd *A, hipStream_t s);
+// p[0..count) = 0 with a kernel (no memset nodes in captured streams)
+int fill_i32_launch(int *p, int count, hipStream_t s);
+// dst[m] = src[m] for the m with odd s[m]
+int odd_copy_launch(int n, int M, const int *d_s, const cd *src, cd *dst, hipStream_t s);
 
 // Solve D X = N in place (X overwrites N) for `batch` systems of size n with
-// n right-hand sides by LU with partial pivoting.  D is destroyed.  info[b]
-// (device) is set non-zero on a zero pivot.
-int lu_solve_batched(int n, int batch, cd *D, cd *N, int *ipiv, int *info, hipStream_t s);
+// nrhs right-hand sides (N is n x nrhs row-major) by LU with partial
+// pivoting.  D is destroyed.  info[b] (device) is set non-zero on a zero pivot.
+int lu_solve_batched(int n, int nrhs, int batch, cd *D, cd *N, int *ipiv, int *info, hipStream_t s);
+
+// Pade [13/13] coefficients b_0..b_13 (b_13 = 1).
+void pade13_coefficients(double b[14]);
+int scaling_exponent(double norm, double theta);
 
 }  // namespace lb

@@ -158,8 +158,8 @@ __global__ void __launch_bounds__(PANEL_THREADS) lu_panel_kernel(cd *D, int n, l
 
 // Row exchanges of the panel and X1 = L11^{-1} X1 on every column outside the
 // panel: trailing columns of D first, then all n columns of N.
-__global__ void __launch_bounds__(256) swap_trsm_lower_kernel(cd *D, cd *N, int n, long long sD, long long sN,
-                                                              int k0, int nb, const int *ipiv) {
+__global__ void __launch_bounds__(256) swap_trsm_lower_kernel(cd *D, cd *N, int n, int nrhs, long long sD,
+                                                              long long sN, int k0, int nb, const int *ipiv) {
     const int b = blockIdx.y;
     cd *Dm = D + (size_t)b * sD;
     cd *Nm = N + (size_t)b * sN;
@@ -173,19 +173,20 @@ __global__ void __launch_bounds__(256) swap_trsm_lower_kernel(cd *D, cd *N, int 
     __syncthreads();
     const int ntrail = n - k0 - nb;
     const int v = blockIdx.x * blockDim.x + threadIdx.x;  // one column per thread (grid covers all)
-    if (v < ntrail + n) {
+    if (v < ntrail + nrhs) {
         cd *col = v < ntrail ? Dm + (k0 + nb + v) : Nm + (v - ntrail);
+        const size_t ld = v < ntrail ? (size_t)n : (size_t)nrhs;
         for (int jj = 0; jj < nb; ++jj) {
             const int r = k0 + jj, p = piv[jj];
             if (p != r) {
-                const cd t = col[(size_t)r * n];
-                col[(size_t)r * n] = col[(size_t)p * n];
-                col[(size_t)p * n] = t;
+                const cd t = col[(size_t)r * ld];
+                col[(size_t)r * ld] = col[(size_t)p * ld];
+                col[(size_t)p * ld] = t;
             }
         }
         cd x[NB];
 #pragma unroll
-        for (int i = 0; i < NB; ++i) x[i] = i < nb ? col[(size_t)(k0 + i) * n] : cd{0.0, 0.0};
+        for (int i = 0; i < NB; ++i) x[i] = i < nb ? col[(size_t)(k0 + i) * ld] : cd{0.0, 0.0};
 #pragma unroll
         for (int i = 1; i < NB; ++i) {
             if (i < nb) {
@@ -201,7 +202,7 @@ __global__ void __launch_bounds__(256) swap_trsm_lower_kernel(cd *D, cd *N, int 
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i)
-            if (i < nb) col[(size_t)(k0 + i) * n] = x[i];
+            if (i < nb) col[(size_t)(k0 + i) * ld] = x[i];
     }
 }
 
@@ -211,8 +212,8 @@ __device__ inline cd cdiv(cd a, cd d) {
 }
 
 // X_block = U_block^{-1} X_block for the rows [b0, b0 + nb) of every column of N.
-__global__ void __launch_bounds__(256) trsm_upper_kernel(const cd *D, cd *N, int n, long long sD, long long sN, int b0,
-                                                         int nb) {
+__global__ void __launch_bounds__(256) trsm_upper_kernel(const cd *D, cd *N, int n, int nrhs, long long sD, long long sN,
+                                                         int b0, int nb) {
     const int b = blockIdx.y;
     const cd *Dm = D + (size_t)b * sD;
     cd *Nm = N + (size_t)b * sN;
@@ -223,10 +224,10 @@ __global__ void __launch_bounds__(256) trsm_upper_kernel(const cd *D, cd *N, int
     }
     __syncthreads();
     const int c = blockIdx.x * blockDim.x + threadIdx.x;  // one column per thread (grid covers all)
-    if (c < n) {
+    if (c < nrhs) {
         cd x[NB];
 #pragma unroll
-        for (int i = 0; i < NB; ++i) x[i] = i < nb ? Nm[(size_t)(b0 + i) * n + c] : cd{0.0, 0.0};
+        for (int i = 0; i < NB; ++i) x[i] = i < nb ? Nm[(size_t)(b0 + i) * nrhs + c] : cd{0.0, 0.0};
 #pragma unroll
         for (int i = NB - 1; i >= 0; --i) {
             if (i < nb) {
@@ -243,12 +244,12 @@ __global__ void __launch_bounds__(256) trsm_upper_kernel(const cd *D, cd *N, int
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i)
-            if (i < nb) Nm[(size_t)(b0 + i) * n + c] = x[i];
+            if (i < nb) Nm[(size_t)(b0 + i) * nrhs + c] = x[i];
     }
 }
 
-int lu_solve_batched(int n, int batch, cd *D, cd *N, int *ipiv, int *info, hipStream_t s) {
-    const long long sD = (long long)n * n, sN = (long long)n * n;
+int lu_solve_batched(int n, int nrhs, int batch, cd *D, cd *N, int *ipiv, int *info, hipStream_t s) {
+    const long long sD = (long long)n * n, sN = (long long)n * nrhs;
     if (batch > 65535) return fail(LB_ESHAPE, "lu_solve: batch > 65535");
     for (int k0 = 0; k0 < n; k0 += NB) {
         const int nb = n - k0 < NB ? n - k0 : NB;
@@ -261,8 +262,8 @@ int lu_solve_batched(int n, int batch, cd *D, cd *N, int *ipiv, int *info, hipSt
         LB_TRY(check_launch("lu_panel"));
         const int ntrail = n - k0 - nb;
         {
-            dim3 grid((ntrail + n + 255) / 256, batch);
-            swap_trsm_lower_kernel<<<grid, 256, 0, s>>>(D, N, n, sD, sN, k0, nb, ipiv);
+            dim3 grid((ntrail + nrhs + 255) / 256, batch);
+            swap_trsm_lower_kernel<<<grid, 256, 0, s>>>(D, N, n, nrhs, sD, sN, k0, nb, ipiv);
             LB_TRY(check_launch("swap_trsm_lower"));
         }
         if (ntrail > 0) {
@@ -288,15 +289,15 @@ int lu_solve_batched(int n, int batch, cd *D, cd *N, int *ipiv, int *info, hipSt
             g.sC = sD;
             LB_TRY(zgemm_batched(g, s));
             // N2 -= L21 N1
-            g.N = n;
-            g.B = N + (size_t)k0 * n;
-            g.ldb = n;
+            g.N = nrhs;
+            g.B = N + (size_t)k0 * nrhs;
+            g.ldb = nrhs;
             g.sB = sN;
-            g.D = N + (size_t)(k0 + nb) * n;
-            g.ldd = n;
+            g.D = N + (size_t)(k0 + nb) * nrhs;
+            g.ldd = nrhs;
             g.sD = sN;
             g.Cin = g.D;
-            g.ldc = n;
+            g.ldc = nrhs;
             g.sC = sN;
             LB_TRY(zgemm_batched(g, s));
         }
@@ -306,28 +307,28 @@ int lu_solve_batched(int n, int batch, cd *D, cd *N, int *ipiv, int *info, hipSt
     for (int blk = nblk - 1; blk >= 0; --blk) {
         const int b0 = blk * NB;
         const int nb = n - b0 < NB ? n - b0 : NB;
-        dim3 grid((n + 255) / 256, batch);
-        trsm_upper_kernel<<<grid, 256, 0, s>>>(D, N, n, sD, sN, b0, nb);
+        dim3 grid((nrhs + 255) / 256, batch);
+        trsm_upper_kernel<<<grid, 256, 0, s>>>(D, N, n, nrhs, sD, sN, b0, nb);
         LB_TRY(check_launch("trsm_upper"));
         if (b0 > 0) {
             ZgemmBatch g;
             g.M = b0;
-            g.N = n;
+            g.N = nrhs;
             g.K = nb;
             g.batch = batch;
             g.A = D + b0;  // U[0:b0, b0:b0+nb]
             g.lda = n;
             g.sA = sD;
-            g.B = N + (size_t)b0 * n;
-            g.ldb = n;
+            g.B = N + (size_t)b0 * nrhs;
+            g.ldb = nrhs;
             g.sB = sN;
             g.D = N;
-            g.ldd = n;
+            g.ldd = nrhs;
             g.sD = sN;
             g.alpha = -1.0;
             g.beta = 1.0;
             g.Cin = N;
-            g.ldc = n;
+            g.ldc = nrhs;
             g.sC = sN;
             LB_TRY(zgemm_batched(g, s));
         }

@@ -18,7 +18,7 @@ namespace lb {
 // Pade [13/13] coefficients, b_13 = 1 and b_k = b_{k+1} (26 - k)(k + 1) / (13 - k):
 // the ratio of consecutive terms of (26 - k)! / (k! (13 - k)!).  Exact in 64-bit
 // integers (the largest intermediate is 8.4e17), each converted once to double.
-static void pade13(double b[14]) {
+void pade13_coefficients(double b[14]) {
     unsigned long long c = 1;
     b[13] = 1.0;
     for (int k = 12; k >= 0; --k) {
@@ -106,14 +106,64 @@ int scaling_exponent(double norm, double theta) {
     return s;
 }
 
+int scaling_stage(int n, int M, const cd *L, const double *dt_host, double theta, double *d_dt,
+                  unsigned long long *d_norm, int *d_s, int *s_host, hipStream_t s) {
+    LB_HIP(hipMemcpyAsync(d_dt, dt_host, M * sizeof(double), hipMemcpyHostToDevice, s));
+    fill_u64_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_norm, M);
+    {
+        dim3 grid((n + 255) / 256, M);
+        norm1_kernel<<<grid, 256, 0, s>>>(n, L, d_dt, d_norm);
+        LB_TRY(check_launch("norm1"));
+    }
+    std::vector<unsigned long long> nb(M);
+    std::vector<int> sv(M);
+    LB_HIP(hipMemcpyAsync(nb.data(), d_norm, M * sizeof(double), hipMemcpyDeviceToHost, s));
+    LB_HIP(hipStreamSynchronize(s));
+    for (int m = 0; m < M; ++m) {
+        double v;
+        std::memcpy(&v, &nb[m], sizeof v);
+        sv[m] = scaling_exponent(v, theta);
+        if (s_host) s_host[m] = sv[m];
+        if (sv[m] < 0)
+            return fail(LB_ENONFINITE, "lindblad_propagator: ||L dt||_1 of generator " + std::to_string(m) +
+                                           " is not finite");
+    }
+    LB_HIP(hipMemcpyAsync(d_s, sv.data(), M * sizeof(int), hipMemcpyHostToDevice, s));
+    LB_HIP(hipStreamSynchronize(s));  // sv leaves scope
+    return LB_OK;
+}
+
+int fill_i32_launch(int *p, int count, hipStream_t s) {
+    if (count <= 0) return LB_OK;
+    fill_i32_kernel<<<(count + 255) / 256, 256, 0, s>>>(p, count);
+    return check_launch("fill");
+}
+
+int scale_launch(int n, int M, const cd *L, const double *d_dt, const int *d_s, cd *A, hipStream_t s) {
+    const size_t nn = (size_t)n * n;
+    scale_kernel<<<grid_1d((long long)nn * M), 256, 0, s>>>((long long)nn, M, L, d_dt, d_s, A);
+    return check_launch("scale");
+}
+
+int odd_copy_launch(int n, int M, const int *d_s, const cd *src, cd *dst, hipStream_t s) {
+    const size_t nn = (size_t)n * n;
+    odd_copy_kernel<<<grid_1d((long long)nn * M), 256, 0, s>>>((long long)nn, M, d_s, src, dst);
+    return check_launch("odd_copy");
+}
+
+static size_t chunk_bytes(int n, int M) {
+    const size_t mat = (size_t)n * n * sizeof(cd) * M;
+    return 8 * align256(mat) + 4 * align256(M * sizeof(double)) + align256((size_t)M * n * sizeof(int)) +
+           2 * align256(M * sizeof(int));
+}
+
 // One chunk of matrices (all buffers sized for `M` matrices).
 static int build_chunk(int n, int M, const cd *L, const double *dt_host, double theta, cd *P, int *s_host,
                        Workspace *ws, hipStream_t s) {
     const size_t nn = (size_t)n * n;
     const size_t mat = nn * sizeof(cd) * M;
-    size_t need = 8 * align256(mat) + 4 * align256(M * sizeof(double)) + align256((size_t)M * n * sizeof(int)) +
-                  2 * align256(M * sizeof(int));
-    LB_TRY(ws_reserve_total(ws, need));
+    LB_TRY(ws_ensure(ws, chunk_bytes(n, M)));
+    const size_t mark = ws->used;
     cd *A = (cd *)ws_take(ws, mat);
     cd *A2 = (cd *)ws_take(ws, mat);
     cd *A4 = (cd *)ws_take(ws, mat);
@@ -127,38 +177,22 @@ static int build_chunk(int n, int M, const cd *L, const double *dt_host, double 
     int *d_s = (int *)ws_take(ws, M * sizeof(int));
     int *d_info = (int *)ws_take(ws, M * sizeof(int));
     int *d_ipiv = (int *)ws_take(ws, (size_t)M * n * sizeof(int));
+    struct Release {
+        Workspace *w;
+        size_t m;
+        ~Release() { w->used = m; }
+    } release{ws, mark};
 
-    LB_HIP(hipMemcpyAsync(d_dt, dt_host, M * sizeof(double), hipMemcpyHostToDevice, s));
-    fill_u64_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_norm, M);
     fill_i32_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_info, M);
-    {
-        dim3 grid((n + 255) / 256, M);
-        norm1_kernel<<<grid, 256, 0, s>>>(n, L, d_dt, d_norm);
-        LB_TRY(check_launch("norm1"));
-    }
-    std::vector<unsigned long long> nb(M);
     std::vector<int> sv(M);
-    LB_HIP(hipMemcpyAsync(nb.data(), d_norm, M * sizeof(double), hipMemcpyDeviceToHost, s));
-    LB_HIP(hipStreamSynchronize(s));
-    int smax = 0;
-    for (int m = 0; m < M; ++m) {
-        double v;
-        std::memcpy(&v, &nb[m], sizeof v);
-        sv[m] = scaling_exponent(v, theta);
-        if (sv[m] < 0) {
-            if (s_host) s_host[m] = -1;
-            return fail(LB_ENONFINITE, "lindblad_propagator: ||L dt||_1 of generator " + std::to_string(m) +
-                                           " is not finite");
-        }
-        if (sv[m] > smax) smax = sv[m];
-    }
+    LB_TRY(scaling_stage(n, M, L, dt_host, theta, d_dt, d_norm, d_s, sv.data(), s));
     if (s_host) std::memcpy(s_host, sv.data(), M * sizeof(int));
-    LB_HIP(hipMemcpyAsync(d_s, sv.data(), M * sizeof(int), hipMemcpyHostToDevice, s));
-    scale_kernel<<<grid_1d((long long)nn * M), 256, 0, s>>>((long long)nn, M, L, d_dt, d_s, A);
-    LB_TRY(check_launch("scale"));
+    int smax = 0;
+    for (int m = 0; m < M; ++m) smax = sv[m] > smax ? sv[m] : smax;
+    LB_TRY(scale_launch(n, M, L, d_dt, d_s, A, s));
 
     double b[14];
-    pade13(b);
+    pade13_coefficients(b);
     ZgemmBatch g;
     g.M = g.N = g.K = n;
     g.batch = M;
@@ -209,7 +243,7 @@ static int build_chunk(int n, int M, const cd *L, const double *dt_host, double 
         LB_TRY(zlincomb(n, M, 2, X, cm, 0.0, A2, s));
         LB_TRY(zlincomb(n, M, 2, X, cp, 0.0, P, s));
     }
-    LB_TRY(lu_solve_batched(n, M, A2, P, d_ipiv, d_info, s));
+    LB_TRY(lu_solve_batched(n, n, M, A2, P, d_ipiv, d_info, s));
     // squarings: level k reads buffer (k even ? P : A4) and writes the other;
     // matrices with s <= k are skipped.
     for (int k = 0; k < smax; ++k) {
@@ -223,10 +257,7 @@ static int build_chunk(int n, int M, const cd *L, const double *dt_host, double 
         h.level = k;
         LB_TRY(zgemm_batched(h, s));
     }
-    if (smax > 0) {
-        odd_copy_kernel<<<grid_1d((long long)nn * M), 256, 0, s>>>((long long)nn, M, d_s, A4, P);
-        LB_TRY(check_launch("odd_copy"));
-    }
+    if (smax > 0) LB_TRY(odd_copy_launch(n, M, d_s, A4, P, s));
     std::vector<int> info(M);
     LB_HIP(hipMemcpyAsync(info.data(), d_info, M * sizeof(int), hipMemcpyDeviceToHost, s));
     LB_HIP(hipStreamSynchronize(s));
@@ -235,15 +266,23 @@ static int build_chunk(int n, int M, const cd *L, const double *dt_host, double 
     return LB_OK;
 }
 
+static long long build_chunk_size(int n, int M, size_t avail) {
+    long long chunk = M;
+    while (chunk > 1 && chunk_bytes(n, (int)chunk) > avail) chunk = (chunk + 1) / 2;
+    if (chunk > 4096) chunk = 4096;
+    return chunk;
+}
+
+size_t build_workspace_bytes(int n, int M) { return chunk_bytes(n, M); }
+
 int build_propagators(int n, int M, const cd *L, const double *dt_host, double theta, cd *P, int *s_host,
                       Workspace *ws, hipStream_t s) {
     // Chunk the batch so that the eight n x n temporaries per matrix fit in
-    // the workspace cap (and the grid's y dimension).
-    const size_t per = 8 * align256((size_t)n * n * sizeof(cd)) + 1024 + (size_t)n * sizeof(int) * 2;
-    long long chunk = (long long)(ws->cap / (per + 4096));
-    if (chunk > M) chunk = M;
-    if (chunk > 4096) chunk = 4096;
-    if (chunk < 1) return fail(LB_ENOMEM, "lindblad_propagator: workspace cap too small for one n x n build");
+    // what the workspace can still give (its cap when nothing is taken yet).
+    const size_t avail = ws->used == 0 ? ws->cap : (ws->size > ws->used ? ws->size - ws->used : 0);
+    const long long chunk = build_chunk_size(n, M, avail);
+    if (chunk_bytes(n, (int)chunk) > avail)
+        return fail(LB_ENOMEM, "lindblad_propagator: workspace too small for one n x n build");
     const size_t nn = (size_t)n * n;
     for (int m0 = 0; m0 < M; m0 += (int)chunk) {
         const int mc = (int)((M - m0) < chunk ? (M - m0) : chunk);
@@ -265,6 +304,7 @@ extern "C" int lindblad_propagator(int n, int M, const void *L, const double *dt
     if (!(theta > 0.0) || !std::isfinite(theta)) return fail(LB_EINVAL, "lindblad_propagator: theta must be > 0");
     for (int m = 0; m < M; ++m)
         if (!std::isfinite(dt[m])) return fail(LB_EINVAL, "lindblad_propagator: dt must be finite");
-    return build_propagators(n, M, static_cast<const cd *>(L), dt, theta, static_cast<cd *>(P), s_used,
-                             ws_resolve(ws), stream);
+    Workspace *w = ws_resolve(ws);
+    ws_begin(w);
+    return build_propagators(n, M, static_cast<const cd *>(L), dt, theta, static_cast<cd *>(P), s_used, w, stream);
 }

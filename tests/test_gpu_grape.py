@@ -1,0 +1,131 @@
+"""GRAPE gradient through the C-ABI against the oracle's block-triangular
+Frechet gradient, central finite differences, torch.autograd.gradcheck and a
+commuting-control closed form."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_18052_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def lb():
+    from paper_2603_18052_amd import lindblad
+    lindblad.lib()
+    return lindblad
+
+
+def setup(q, M, seed_u=None):
+    p = W.grape_problem(q, M=M)
+    L0 = oracle.liouvillian(p["H0"], p["Lk"])
+    Lc = np.stack([oracle.liouvillian(h, p["Lk"][:0]) for h in p["Hc"]])
+    if seed_u is not None:
+        p["u"] = np.random.default_rng(seed_u).uniform(-W.U_MAX, W.U_MAX, size=p["u"].shape)
+    return p, L0, Lc
+
+
+def gpu_grad(lb, p, L0, Lc, u=None, **kw):
+    u = p["u"] if u is None else u
+    F, g = lb.grape_gradient(T(L0), T(Lc), T(u), p["dt"], T(p["rho0"].reshape(-1)), T(p["target"].reshape(-1)), **kw)
+    return F, g.cpu().numpy()
+
+
+def test_grape_d3_against_oracle(lb):
+    p, L0, Lc = setup(1, M=6)
+    F, g = gpu_grad(lb, p, L0, Lc)
+    Fo, go = oracle.grape(L0, Lc, p["u"], p["dt"], p["rho0"].reshape(-1), p["target"].reshape(-1))
+    assert abs(F - Fo) < 1e-13
+    assert np.abs(g - go).max() <= 1e-10 * np.abs(go).max()
+
+
+def test_grape_d9_config4_sampled_slices(lb):
+    """Config 4 at d = 9: M = 200 slices of 1 ns, 4 controls.  F against the
+    oracle's forward pass; gradient rows of 4 seeded slices against the
+    oracle's block-triangular Frechet gradient (the rest by FD below)."""
+    p, L0, Lc = setup(2, M=200)
+    F, g = gpu_grad(lb, p, L0, Lc)
+    rows = [0, 57, 131, 199]
+    Fo, go = oracle.grape(L0, Lc, p["u"], p["dt"], p["rho0"].reshape(-1), p["target"].reshape(-1), slices=rows)
+    assert abs(F - Fo) < 1e-12
+    scale = np.abs(go[rows]).max()
+    assert np.abs(g[rows] - go[rows]).max() <= 1e-10 * scale
+    assert np.all(np.isfinite(g))
+
+
+def test_grape_d9_central_differences(lb):
+    p, L0, Lc = setup(2, M=200)
+    F, g = gpu_grad(lb, p, L0, Lc)
+    h = 1e-6
+    rng = np.random.default_rng(5)
+    for m, c in [(0, 0), (100, 3), (199, 1)]:
+        up, um = p["u"].copy(), p["u"].copy()
+        up[m, c] += h
+        um[m, c] -= h
+        fd = (gpu_grad(lb, p, L0, Lc, up)[0] - gpu_grad(lb, p, L0, Lc, um)[0]) / (2 * h)
+        assert abs(g[m, c] - fd) <= 1e-8 + 1e-7 * abs(g[m, c])
+    v = rng.standard_normal(p["u"].shape)
+    v /= np.linalg.norm(v)
+    fd = (gpu_grad(lb, p, L0, Lc, p["u"] + h * v)[0] - gpu_grad(lb, p, L0, Lc, p["u"] - h * v)[0]) / (2 * h)
+    dd = float(np.sum(g * v))
+    assert abs(dd - fd) <= 1e-8 + 1e-7 * abs(dd)
+
+
+def test_grape_checkpoint_recompute_matches(lb):
+    p, L0, Lc = setup(2, M=37)
+    F1, g1 = gpu_grad(lb, p, L0, Lc)
+    F2, g2 = gpu_grad(lb, p, L0, Lc, checkpoint_bytes=1)  # nothing kept: rebuild per chunk
+    assert F1 == F2
+    assert np.array_equal(g1, g2)
+
+
+def test_grape_commuting_controls_closed_form(lb):
+    d = 3
+    n_op = np.diag([0.0, 1.0, 2.0]).astype(complex)
+    H0 = np.diag([0.0, 0.7, 1.1]).astype(complex)
+    Lk = (np.sqrt(0.01) * n_op)[None]
+    L0 = oracle.liouvillian(H0, Lk)
+    Lc = oracle.liouvillian(n_op, Lk[:0])[None]
+    M, dt = 4, 0.5
+    u = np.array([[0.1], [-0.2], [0.05], [0.3]])
+    rho0 = W.pure_state(d, np.random.default_rng(8))
+    tgt = W.pure_state(d, np.random.default_rng(9))
+    F, g = lb.grape_gradient(T(L0), T(Lc), T(u), dt, T(rho0.reshape(-1)), T(tgt.reshape(-1)))
+    g = g.cpu().numpy()
+    xM = oracle.expm(dt * (M * L0 + u.sum() * Lc[0])) @ rho0.reshape(-1)
+    assert abs(F - np.vdot(tgt.reshape(-1), xM).real) < 1e-13
+    assert np.abs(g[:, 0] - np.vdot(tgt.reshape(-1), dt * Lc[0] @ xM).real).max() < 1e-13
+
+
+def test_grape_autograd_gradcheck(lb):
+    p, L0, Lc = setup(1, M=3)
+    L0t, Lct = T(L0), T(Lc)
+    x0, w = T(p["rho0"].reshape(-1)), T(p["target"].reshape(-1))
+    u = T(p["u"]).requires_grad_(True)
+
+    def f(uu):
+        return lb.GrapeFidelity.apply(uu, L0t, Lct, p["dt"], x0, w)
+
+    assert torch.autograd.gradcheck(f, (u,), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+def test_grape_d27_directional_fd_and_forward(lb):
+    """d = 27, 6 controls, M = 4 slices: F against the oracle's forward pass;
+    the adjoint against a central difference along a random direction."""
+    p, L0, Lc = setup(3, M=4)
+    F, g = gpu_grad(lb, p, L0, Lc)
+    Fo, _ = oracle.grape(L0, Lc, p["u"], p["dt"], p["rho0"].reshape(-1), p["target"].reshape(-1), want_grad=False)
+    assert abs(F - Fo) < 1e-12
+    h = 1e-6
+    v = np.random.default_rng(3).standard_normal(p["u"].shape)
+    v /= np.linalg.norm(v)
+    fd = (gpu_grad(lb, p, L0, Lc, p["u"] + h * v)[0] - gpu_grad(lb, p, L0, Lc, p["u"] - h * v)[0]) / (2 * h)
+    dd = float(np.sum(g * v))
+    assert abs(dd - fd) <= 1e-8 + 1e-7 * abs(dd)
