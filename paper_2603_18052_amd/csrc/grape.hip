@@ -429,9 +429,3 @@ extern "C" int grape_gradient(int n, int M, int C, const void *L0, const void *L
     return grape_run(n, M, C, static_cast<const cd *>(L0), static_cast<const cd *>(Lc), u, dt, theta,
                      static_cast<const cd *>(x0), static_cast<const cd *>(w), F, grad, checkpoint_bytes, wsp, stream);
 }
-
-extern "C" int lindblad_batch_run(const lb_problem *probs, int nprob, lb_precision prec, double theta,
-                                  lb_workspace *ws, hipStream_t stream) {
-    (void)probs; (void)nprob; (void)prec; (void)theta; (void)ws; (void)stream;
-    return fail(LB_ENOTSUP, "lindblad_batch_run: not built yet");
-}

@@ -1,0 +1,87 @@
+"""Mixed serving batch (lindblad_batch_run) against per-problem oracle runs,
+and each problem's result independent of the rest of the batch (bitwise)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_18052_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def lb():
+    from paper_2603_18052_amd import lindblad
+    lindblad.lib()
+    return lindblad
+
+
+@pytest.fixture(scope="module")
+def problems():
+    probs = W.mixed_batch(nprob=9, nmin=0, nmax=150)
+    probs[4]["nsteps"] = 0
+    for p in probs:
+        p["L"] = oracle.liouvillian(p["H"], p["Lk"]) if p["d"] < 27 else None
+    return probs
+
+
+def kron_L(H, Lk):
+    d = H.shape[0]
+    I = np.eye(d)
+    L = -1j * (np.kron(H, I) - np.kron(I, H.T))
+    for Lj in Lk:
+        M = Lj.conj().T @ Lj
+        L += np.kron(Lj, Lj.conj()) - 0.5 * np.kron(M, I) - 0.5 * np.kron(I, M.T)
+    return L
+
+
+def as_gpu(probs):
+    out = []
+    for p in probs:
+        L = p["L"] if p["L"] is not None else kron_L(p["H"], p["Lk"])
+        out.append(dict(d=p["d"], L=T(L), dt=p["dt"], nsteps=p["nsteps"], rho=T(p["rho0"].reshape(-1).copy())))
+    return out
+
+
+def test_batch_c128_against_oracle(lb, problems):
+    g = as_gpu(problems)
+    lb.batch_run(g, "c128")
+    for p, q in zip(problems, g):
+        L = p["L"] if p["L"] is not None else kron_L(p["H"], p["Lk"])
+        P = oracle.propagator(L, p["dt"])
+        ref = oracle.propagate(P, p["rho0"].reshape(1, -1), p["nsteps"])[0]
+        got = q["rho"].cpu().numpy()
+        if p["nsteps"] == 0:
+            assert np.array_equal(got, p["rho0"].reshape(-1))
+        assert oracle.rel_fro(got, ref) < 1e-12, (p["d"], p["nsteps"])
+
+
+def test_batch_c64_error_and_independence(lb, problems):
+    g = as_gpu(problems)
+    lb.batch_run(g, "c64")
+    for i, (p, q) in enumerate(zip(problems, g)):
+        d = p["d"]
+        L = p["L"] if p["L"] is not None else kron_L(p["H"], p["Lk"])
+        ref = oracle.propagate(oracle.propagator(L, p["dt"]), p["rho0"].reshape(1, -1), p["nsteps"])[0]
+        td = oracle.trace_distance(q["rho"].cpu().numpy().reshape(d, d), ref.reshape(d, d))
+        assert td < 1e-4, (d, p["nsteps"], td)
+        # the same problem alone gives the same bits
+        single = as_gpu([p])
+        lb.batch_run(single, "c64")
+        assert torch.equal(single[0]["rho"], q["rho"]), i
+
+
+def test_batch_validation(lb):
+    with pytest.raises(lb.LindbladError):
+        lb.batch_run([dict(d=3, L=T(np.eye(9, dtype=complex)), dt=0.5, nsteps=-1, rho=T(np.zeros(9, complex)))])
+    with pytest.raises(lb.LindbladError) as e:
+        lb.batch_run([dict(d=3, L=T(np.eye(9, dtype=complex)), dt=0.5, nsteps=1, rho=T(np.zeros(9, complex)))],
+                     "bf16_sliced")
+    assert e.value.status == lb.ENOTSUP
+    lb.batch_run([])
