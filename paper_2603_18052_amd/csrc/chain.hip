@@ -325,14 +325,15 @@ int chain_run(int n, const cd *P, lb_precision prec, int B, cd *rho, long long n
     switch (prec) {
         case LB_C128:
             if (n <= fused_max_n(LB_C128)) return launch_fused<double>(n, P, B, rho, nsteps, s);
+            if (B < 16) return chain_large(n, P, prec, B, rho, nsteps, ws, s);
             return chain_large_c128(n, P, B, rho, nsteps, ws, s);
         case LB_C64:
             if (n <= fused_max_n(LB_C64)) return launch_fused<float>(n, P, B, rho, nsteps, s);
-            return fail(LB_ENOTSUP, "lindblad_propagate: LB_C64 for n > 124 is not built yet");
+            return chain_large(n, P, prec, B, rho, nsteps, ws, s);
         case LB_BF16_HILO:
         case LB_BF16_SLICED:
             if (n <= bf16_fused_max_n(prec)) return chain_bf16_fused(n, P, prec, B, rho, nsteps, s);
-            return fail(LB_ENOTSUP, "lindblad_propagate: BF16 chains for large n are not built yet");
+            return chain_large(n, P, prec, B, rho, nsteps, ws, s);
         default:
             return fail(LB_EINVAL, "lindblad_propagate: bad precision");
     }

@@ -1,0 +1,512 @@
+// Step chains for large n (P too big for one CU's LDS, e.g. d = 27, n = 729):
+// one GEMM launch per step, Y[b][i] = sum_k X[b][k] P[i][k] (states as rows,
+// outputs as columns, both operands read along k, which is contiguous in the
+// row-major state batch and in the rows of P).
+//
+//   LB_C64          P and the states in complex FP32, FP32 matrix cores
+//                   (v_mfma_f32_16x16x4f32); each lane loads four consecutive
+//                   k as one 16-byte load and feeds them to four MFMAs (the k
+//                   order inside a 16-deep block is permuted identically for
+//                   both operands, which leaves the sum unchanged).
+//   LB_BF16_HILO    BF16 planes hi / lo of P (once per call) and of the FP32
+//   LB_BF16_SLICED  state (every step), or exponent-aligned 8-bit integer
+//                   slices exactly as in the fused kernel; BF16 matrix cores.
+//                   For the slices the k range is cut into 64-deep chunks so
+//                   that every level sum stays an exact FP32 integer
+//                   (2 * 64 * max_L sum|q_a||q_b| < 2^24); each chunk's levels
+//                   are flushed into FP64 accumulators.
+// A workgroup owns a 16-state x 32-output tile; its four wavefronts split the
+// k chunks and their FP64 partials are summed through LDS in a fixed order.
+// Fewer than 16 states with FP32/FP64 arithmetic use a GEMV kernel instead:
+// one wavefront per row of P, all states of the batch in registers.
+#include <cmath>
+
+#include "chain.hpp"
+
+namespace lb {
+namespace lg {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+enum Mode { HILO = 0, SLICED = 1 };
+constexpr int KCH = 64;  // k chunk (exact level sums for the slices)
+constexpr int WN = 2;    // 16-output tiles per wavefront
+constexpr int TS = 16;   // states per workgroup tile
+constexpr int TO = 16 * WN;
+
+__device__ inline unsigned short bf16_bits(float f) {
+    unsigned int u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_float(unsigned short b) { return __uint_as_float(((unsigned int)b) << 16); }
+__device__ inline int exp_of(double m) {
+    if (!(m > 0.0)) return 0;
+    int e;
+    (void)frexp(m, &e);
+    return e;
+}
+__device__ inline f4v mma(bf16x8 a, bf16x8 b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+
+template <int MODE, int SP, int SX>
+struct Planes {
+    static constexpr int XD = MODE == SLICED ? SX : 2;  // state digits
+    static constexpr int PD = MODE == SLICED ? SP : 2;  // propagator digits
+};
+
+// P planes [PD][2][n][Kp] (Re, Im) and, for the slices, row exponents eP.
+// One workgroup per row of P.
+template <int MODE, int SP, int SX>
+__global__ void __launch_bounds__(256) prep_p_kernel(int n, int Kp, const cd *__restrict__ P,
+                                                     unsigned short *__restrict__ Pp, int *__restrict__ eP) {
+    constexpr int PD = Planes<MODE, SP, SX>::PD;
+    const int i = blockIdx.x;
+    __shared__ double red[256];
+    __shared__ int se;
+    double m = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) {
+        const cd v = P[(size_t)i * n + k];
+        m = fmax(m, fmax(fabs(v.re), fabs(v.im)));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        se = MODE == SLICED ? exp_of(red[0]) : 0;
+        eP[i] = se;
+    }
+    __syncthreads();
+    const size_t plane = (size_t)n * Kp;
+    for (int k = threadIdx.x; k < Kp; k += 256) {
+        const cd v = k < n ? P[(size_t)i * n + k] : cd{0.0, 0.0};
+        unsigned short *o = Pp + (size_t)i * Kp + k;
+        if (MODE == SLICED) {
+            double vr = ldexp(v.re, -se), vi = ldexp(v.im, -se);
+#pragma unroll
+            for (int a = 0; a < PD; ++a) {
+                const double dr = rint(vr * 256.0), di = rint(vi * 256.0);
+                vr = vr * 256.0 - dr;
+                vi = vi * 256.0 - di;
+                o[(a * 2 + 0) * plane] = bf16_bits((float)dr);
+                o[(a * 2 + 1) * plane] = bf16_bits((float)di);
+            }
+        } else {
+            const float fr = (float)v.re, fi = (float)v.im;
+            const unsigned short hr = bf16_bits(fr), hi = bf16_bits(fi);
+            o[0 * plane] = hr;
+            o[1 * plane] = hi;
+            o[2 * plane] = bf16_bits(fr - bf16_float(hr));
+            o[3 * plane] = bf16_bits(fi - bf16_float(hi));
+        }
+    }
+}
+
+// State planes [XD][3][B][Kp] (Re, Im, -Im) and, for the slices, eX.  One
+// workgroup per state.  HILO: the state is FP32 (Y holds FP32 values).
+template <int MODE, int SP, int SX>
+__global__ void __launch_bounds__(256) slice_x_kernel(int n, int Kp, int B, const cd *__restrict__ Y,
+                                                      unsigned short *__restrict__ Xp, int *__restrict__ eX) {
+    constexpr int XD = Planes<MODE, SP, SX>::XD;
+    const int b = blockIdx.x;
+    __shared__ double red[256];
+    __shared__ int se;
+    double m = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) {
+        const cd v = Y[(size_t)b * n + k];
+        m = fmax(m, fmax(fabs(v.re), fabs(v.im)));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        se = MODE == SLICED ? exp_of(red[0]) : 0;
+        eX[b] = se;
+    }
+    __syncthreads();
+    const size_t plane = (size_t)B * Kp;
+    for (int k = threadIdx.x; k < Kp; k += 256) {
+        const cd v = k < n ? Y[(size_t)b * n + k] : cd{0.0, 0.0};
+        unsigned short *o = Xp + (size_t)b * Kp + k;
+        if (MODE == SLICED) {
+            double vr = ldexp(v.re, -se), vi = ldexp(v.im, -se);
+#pragma unroll
+            for (int a = 0; a < XD; ++a) {
+                const double dr = rint(vr * 256.0), di = rint(vi * 256.0);
+                vr = vr * 256.0 - dr;
+                vi = vi * 256.0 - di;
+                o[(a * 3 + 0) * plane] = bf16_bits((float)dr);
+                o[(a * 3 + 1) * plane] = bf16_bits((float)di);
+                o[(a * 3 + 2) * plane] = bf16_bits((float)-di);
+            }
+        } else {
+            const float fr = (float)v.re, fi = (float)v.im;
+            const unsigned short hr = bf16_bits(fr), hi = bf16_bits(fi);
+            const unsigned short lr = bf16_bits(fr - bf16_float(hr)), li = bf16_bits(fi - bf16_float(hi));
+            o[0 * plane] = hr;
+            o[1 * plane] = hi;
+            o[2 * plane] = hi ^ 0x8000u;
+            o[3 * plane] = lr;
+            o[4 * plane] = li;
+            o[5 * plane] = li ^ 0x8000u;
+        }
+    }
+}
+
+template <int MODE, int SP, int SX, int LMAX>
+__global__ void __launch_bounds__(256) plane_gemm_kernel(int n, int B, int Kp, const unsigned short *__restrict__ Xp,
+                                                         const unsigned short *__restrict__ Pp,
+                                                         const int *__restrict__ eP, const int *__restrict__ eX,
+                                                         cd *__restrict__ Y) {
+    constexpr int XD = Planes<MODE, SP, SX>::XD, PD = Planes<MODE, SP, SX>::PD;
+    constexpr int NL = MODE == SLICED ? LMAX + 1 : 1;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int b0 = blockIdx.y * TS, i0 = blockIdx.x * TO;
+    const int bl = b0 + (lane & 15);
+    const bool bvalid = bl < B;
+    const size_t xplane = (size_t)B * Kp, pplane = (size_t)n * Kp;
+    const unsigned short *xrow = Xp + (size_t)(bvalid ? bl : 0) * Kp + 8 * (lane >> 4);
+    const unsigned short *prow[WN];
+    bool pvalid[WN];
+#pragma unroll
+    for (int t = 0; t < WN; ++t) {
+        const int i = i0 + t * 16 + (lane & 15);
+        pvalid[t] = i < n;
+        prow[t] = Pp + (size_t)(pvalid[t] ? i : 0) * Kp + 8 * (lane >> 4);
+    }
+    double ar[WN][4], ai[WN][4];
+#pragma unroll
+    for (int t = 0; t < WN; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ar[t][r] = ai[t][r] = 0.0;
+    const bf16x8 zero = {};
+    const int nch = Kp / KCH;
+    for (int kc = wave; kc < nch; kc += 4) {
+        f4v lr[WN][NL], li[WN][NL];
+#pragma unroll
+        for (int t = 0; t < WN; ++t)
+#pragma unroll
+            for (int L = 0; L < NL; ++L) lr[t][L] = li[t][L] = f4v{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < KCH / 32; ++ks) {
+            const int k = kc * KCH + ks * 32;
+            bf16x8 xa[XD][3];
+#pragma unroll
+            for (int a = 0; a < XD; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    xa[a][c] = bvalid ? *reinterpret_cast<const bf16x8 *>(xrow + (a * 3 + c) * xplane + k) : zero;
+#pragma unroll
+            for (int t = 0; t < WN; ++t) {
+                bf16x8 pb[PD][2];
+#pragma unroll
+                for (int a = 0; a < PD; ++a)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+                        pb[a][c] = pvalid[t] ? *reinterpret_cast<const bf16x8 *>(prow[t] + (a * 2 + c) * pplane + k)
+                                             : zero;
+#pragma unroll
+                for (int a = 0; a < PD; ++a)
+#pragma unroll
+                    for (int bq = 0; bq < XD; ++bq) {
+                        const int L = a + bq;
+                        if (MODE == SLICED ? (L <= LMAX) : (L <= 1)) {
+                            const int Lq = MODE == SLICED ? L : 0;
+                            lr[t][Lq] = mma(xa[bq][0], pb[a][0], lr[t][Lq]);
+                            lr[t][Lq] = mma(xa[bq][2], pb[a][1], lr[t][Lq]);
+                            li[t][Lq] = mma(xa[bq][1], pb[a][0], li[t][Lq]);
+                            li[t][Lq] = mma(xa[bq][0], pb[a][1], li[t][Lq]);
+                        }
+                    }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < WN; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int L = NL - 1; L >= 0; --L) {
+                    const double w = MODE == SLICED ? ldexp(1.0, -8 * (L + 2)) : 1.0;
+                    ar[t][r] = fma((double)lr[t][L][r], w, ar[t][r]);
+                    ai[t][r] = fma((double)li[t][L][r], w, ai[t][r]);
+                }
+    }
+    // sum the wavefronts' partials (fixed order) and write
+    __shared__ double red[4][WN][4][2][64];
+#pragma unroll
+    for (int t = 0; t < WN; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            red[wave][t][r][0][lane] = ar[t][r];
+            red[wave][t][r][1][lane] = ai[t][r];
+        }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int t = 0; t < WN; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double sr = red[0][t][r][0][lane], si = red[0][t][r][1][lane];
+                for (int w = 1; w < 4; ++w) {
+                    sr += red[w][t][r][0][lane];
+                    si += red[w][t][r][1][lane];
+                }
+                const int b = b0 + 4 * (lane >> 4) + r, i = i0 + t * 16 + (lane & 15);
+                if (b < B && i < n) {
+                    if (MODE == SLICED) {
+                        const int sc = eP[i] + eX[b];
+                        Y[(size_t)b * n + i] = {ldexp(sr, sc), ldexp(si, sc)};
+                    } else {
+                        Y[(size_t)b * n + i] = {(double)(float)sr, (double)(float)si};
+                    }
+                }
+            }
+    }
+}
+
+// ------------------------------------------------------------- FP32 path
+// planar FP32 copies: re[B or n][Kp], im[...] (zero padded in k)
+__global__ void to_planes_f32_kernel(int rows, int n, int Kp, const cd *__restrict__ src, float *__restrict__ re,
+                                     float *__restrict__ im) {
+    const long long total = (long long)rows * Kp;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long r = e / Kp, k = e - r * Kp;
+        const cd v = k < n ? src[r * n + k] : cd{0.0, 0.0};
+        re[e] = (float)v.re;
+        im[e] = (float)v.im;
+    }
+}
+
+typedef float f4s __attribute__((ext_vector_type(4)));
+
+// Y[b][i] (FP32 values, stored as c128) = sum_k X[b][k] P[i][k], FP32 MFMA.
+// Wavefronts split the 16-deep k blocks; per block each lane loads 4
+// consecutive k of its state row and of its P rows.
+__global__ void __launch_bounds__(256) cgemm_step_kernel(int n, int B, int Kp, const float *__restrict__ Xr,
+                                                         const float *__restrict__ Xi, const float *__restrict__ Pr,
+                                                         const float *__restrict__ Pi, float *__restrict__ Yr,
+                                                         float *__restrict__ Yi, cd *__restrict__ Yout) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int b0 = blockIdx.y * TS, i0 = blockIdx.x * TO;
+    const int bl = b0 + (lane & 15);
+    const bool bvalid = bl < B;
+    const size_t xo = (size_t)(bvalid ? bl : 0) * Kp + 4 * (lane >> 4);
+    size_t po[WN];
+    bool pvalid[WN];
+#pragma unroll
+    for (int t = 0; t < WN; ++t) {
+        const int i = i0 + t * 16 + (lane & 15);
+        pvalid[t] = i < n;
+        po[t] = (size_t)(pvalid[t] ? i : 0) * Kp + 4 * (lane >> 4);
+    }
+    f4v cr[WN], ci[WN];
+#pragma unroll
+    for (int t = 0; t < WN; ++t) cr[t] = ci[t] = f4v{0, 0, 0, 0};
+    const f4s z = {0, 0, 0, 0};
+    for (int kb = wave * 16; kb < Kp; kb += 64) {
+        const f4s xr = bvalid ? *reinterpret_cast<const f4s *>(Xr + xo + kb) : z;
+        const f4s xi = bvalid ? *reinterpret_cast<const f4s *>(Xi + xo + kb) : z;
+#pragma unroll
+        for (int t = 0; t < WN; ++t) {
+            const f4s pr = pvalid[t] ? *reinterpret_cast<const f4s *>(Pr + po[t] + kb) : z;
+            const f4s pi = pvalid[t] ? *reinterpret_cast<const f4s *>(Pi + po[t] + kb) : z;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[q], pr[q], cr[t], 0, 0, 0);
+                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-xi[q], pi[q], cr[t], 0, 0, 0);
+                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[q], pr[q], ci[t], 0, 0, 0);
+                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[q], pi[q], ci[t], 0, 0, 0);
+            }
+        }
+    }
+    __shared__ float red[4][WN][4][2][64];
+#pragma unroll
+    for (int t = 0; t < WN; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            red[wave][t][r][0][lane] = cr[t][r];
+            red[wave][t][r][1][lane] = ci[t][r];
+        }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int t = 0; t < WN; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float sr = red[0][t][r][0][lane], si = red[0][t][r][1][lane];
+                for (int w = 1; w < 4; ++w) {
+                    sr += red[w][t][r][0][lane];
+                    si += red[w][t][r][1][lane];
+                }
+                const int b = b0 + 4 * (lane >> 4) + r, i = i0 + t * 16 + (lane & 15);
+                if (b < B && i < n) {
+                    Yr[(size_t)b * Kp + i] = sr;
+                    Yi[(size_t)b * Kp + i] = si;
+                    if (Yout) Yout[(size_t)b * n + i] = {(double)sr, (double)si};
+                }
+            }
+    }
+}
+
+// ------------------------------------------------------------ GEMV (B < 16)
+template <typename T>
+struct Cx {
+    T re, im;
+};
+
+template <typename T, int BM>
+__global__ void __launch_bounds__(256) gemv_step_kernel(int n, int B, const Cx<T> *__restrict__ P,
+                                                        const Cx<T> *__restrict__ X, Cx<T> *__restrict__ Y) {
+    const int lane = threadIdx.x & 63;
+    const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= n) return;
+    T re[BM], im[BM];
+#pragma unroll
+    for (int b = 0; b < BM; ++b) re[b] = im[b] = 0;
+    const Cx<T> *Pr = P + (size_t)row * n;
+    for (int j = lane; j < n; j += 64) {
+        const Cx<T> p = Pr[j];
+#pragma unroll
+        for (int b = 0; b < BM; ++b)
+            if (b < B) {
+                const Cx<T> v = X[(size_t)b * n + j];
+                re[b] = fma(p.re, v.re, fma(-p.im, v.im, re[b]));
+                im[b] = fma(p.re, v.im, fma(p.im, v.re, im[b]));
+            }
+    }
+#pragma unroll
+    for (int b = 0; b < BM; ++b) {
+        if (b < B) {
+            T r = re[b], i = im[b];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                r += __shfl_xor(r, off);
+                i += __shfl_xor(i, off);
+            }
+            if (lane == 0) Y[(size_t)b * n + row] = {r, i};
+        }
+    }
+}
+
+template <typename T>
+__global__ void convert_kernel(long long count, const cd *__restrict__ src, Cx<T> *__restrict__ dst) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (long long)gridDim.x * blockDim.x)
+        dst[e] = {(T)src[e].re, (T)src[e].im};
+}
+
+template <typename T>
+__global__ void back_kernel(long long count, const Cx<T> *__restrict__ src, cd *__restrict__ dst) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (long long)gridDim.x * blockDim.x)
+        dst[e] = {(double)src[e].re, (double)src[e].im};
+}
+
+static int grid1(long long work) {
+    long long g = (work + 255) / 256;
+    if (g > 65536) g = 65536;
+    return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace lg
+
+using namespace lg;
+
+template <typename T>
+static int chain_gemv(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+    const size_t nn = (size_t)n * n;
+    LB_TRY(ws_ensure(ws, align256(nn * sizeof(Cx<T>)) + 2 * align256((size_t)B * n * sizeof(Cx<T>))));
+    Cx<T> *Pc = (Cx<T> *)ws_take(ws, nn * sizeof(Cx<T>));
+    Cx<T> *X0 = (Cx<T> *)ws_take(ws, (size_t)B * n * sizeof(Cx<T>));
+    Cx<T> *X1 = (Cx<T> *)ws_take(ws, (size_t)B * n * sizeof(Cx<T>));
+    convert_kernel<T><<<grid1(nn), 256, 0, s>>>((long long)nn, P, Pc);
+    convert_kernel<T><<<grid1((long long)B * n), 256, 0, s>>>((long long)B * n, rho, X0);
+    const int blocks = (n * 64 + 255) / 256;
+    for (long long t = 0; t < nsteps; ++t) {
+        const Cx<T> *x = (t & 1) ? X1 : X0;
+        Cx<T> *y = (t & 1) ? X0 : X1;
+        gemv_step_kernel<T, 16><<<blocks, 256, 0, s>>>(n, B, Pc, x, y);
+    }
+    LB_TRY(check_launch("gemv_step"));
+    back_kernel<T><<<grid1((long long)B * n), 256, 0, s>>>((long long)B * n, (nsteps & 1) ? X1 : X0, rho);
+    return check_launch("gemv_back");
+}
+
+static int chain_large_c64(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+    const int Kp = (n + 63) / 64 * 64;
+    const size_t pp = (size_t)n * Kp * sizeof(float), xp = (size_t)B * Kp * sizeof(float);
+    LB_TRY(ws_ensure(ws, 2 * align256(pp) + 4 * align256(xp)));
+    float *Pr = (float *)ws_take(ws, pp), *Pi = (float *)ws_take(ws, pp);
+    float *X[2][2];
+    for (int q = 0; q < 2; ++q)
+        for (int c = 0; c < 2; ++c) X[q][c] = (float *)ws_take(ws, xp);
+    to_planes_f32_kernel<<<grid1((long long)n * Kp), 256, 0, s>>>(n, n, Kp, P, Pr, Pi);
+    for (int q = 0; q < 2; ++q)  // zero k padding of both buffers
+        to_planes_f32_kernel<<<grid1((long long)B * Kp), 256, 0, s>>>(B, n, Kp, rho, X[q][0], X[q][1]);
+    LB_TRY(check_launch("to_planes"));
+    dim3 grid((n + TO - 1) / TO, (B + TS - 1) / TS);
+    for (long long t = 0; t < nsteps; ++t) {
+        const int c = (int)(t & 1);
+        cgemm_step_kernel<<<grid, 256, 0, s>>>(n, B, Kp, X[c][0], X[c][1], Pr, Pi, X[c ^ 1][0], X[c ^ 1][1],
+                                               t + 1 == nsteps ? rho : nullptr);
+    }
+    return check_launch("cgemm_step");
+}
+
+template <int MODE, int SP, int SX, int LMAX>
+static int chain_large_planes(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+    constexpr int XD = Planes<MODE, SP, SX>::XD, PD = Planes<MODE, SP, SX>::PD;
+    const int Kp = (n + KCH - 1) / KCH * KCH;
+    const size_t pbytes = (size_t)PD * 2 * n * Kp * 2, xbytes = (size_t)XD * 3 * B * Kp * 2;
+    const size_t ybytes = (size_t)B * n * sizeof(cd);
+    LB_TRY(ws_ensure(ws, align256(pbytes) + align256(xbytes) + align256(ybytes) + align256(n * 4) + align256(B * 4)));
+    unsigned short *Pp = (unsigned short *)ws_take(ws, pbytes);
+    unsigned short *Xp = (unsigned short *)ws_take(ws, xbytes);
+    cd *Yt = (cd *)ws_take(ws, ybytes);
+    int *eP = (int *)ws_take(ws, n * 4);
+    int *eX = (int *)ws_take(ws, B * 4);
+    prep_p_kernel<MODE, SP, SX><<<n, 256, 0, s>>>(n, Kp, P, Pp, eP);
+    LB_TRY(check_launch("prep_p"));
+    dim3 grid((n + TO - 1) / TO, (B + TS - 1) / TS);
+    // the state ping-pongs between rho and Yt; it ends in rho
+    cd *cur = rho, *nxt = Yt;
+    for (long long t = 0; t < nsteps; ++t) {
+        slice_x_kernel<MODE, SP, SX><<<B, 256, 0, s>>>(n, Kp, B, cur, Xp, eX);
+        plane_gemm_kernel<MODE, SP, SX, LMAX><<<grid, 256, 0, s>>>(n, B, Kp, Xp, Pp, eP, eX, nxt);
+        cd *z = cur;
+        cur = nxt;
+        nxt = z;
+    }
+    LB_TRY(check_launch("plane_gemm"));
+    if (cur != rho) LB_HIP(hipMemcpyAsync(rho, cur, ybytes, hipMemcpyDeviceToDevice, s));
+    return LB_OK;
+}
+
+int chain_large(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
+                hipStream_t s) {
+    switch (prec) {
+        case LB_C128:
+            return chain_gemv<double>(n, P, B, rho, nsteps, ws, s);
+        case LB_C64:
+            if (B < 16) return chain_gemv<float>(n, P, B, rho, nsteps, ws, s);
+            return chain_large_c64(n, P, B, rho, nsteps, ws, s);
+        case LB_BF16_HILO:
+            return chain_large_planes<HILO, 2, 2, 1>(n, P, B, rho, nsteps, ws, s);
+        case LB_BF16_SLICED:
+            if (nsteps <= kSlicedShortRun) return chain_large_planes<SLICED, 4, 4, 3>(n, P, B, rho, nsteps, ws, s);
+            return chain_large_planes<SLICED, 5, 4, 4>(n, P, B, rho, nsteps, ws, s);
+        default:
+            return fail(LB_EINVAL, "chain_large: bad precision");
+    }
+}
+
+}  // namespace lb

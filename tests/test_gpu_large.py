@@ -1,0 +1,82 @@
+"""Large-n chains (d = 27, n = 729: per-step GEMM launches) and the n just
+above each fused kernel's limit, against the FP64 oracle on the same P."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_18052_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def lb():
+    from paper_2603_18052_amd import lindblad
+    lindblad.lib()
+    return lindblad
+
+
+@pytest.fixture(scope="module")
+def P27(lb):
+    H, Lk = W.transmon_system(3)
+    L = lb.liouvillian(T(H), T(Lk))
+    return lb.propagator(L, W.DT_NS).cpu().numpy()  # parity of this build is tested elsewhere
+
+
+def states(d, B, seed):
+    g = np.random.default_rng(seed)
+    return np.stack([W.wishart_state(d, g) for _ in range(B)]).reshape(B, d * d)
+
+
+def run(lb, P, X, nsteps, prec):
+    x = T(X.copy())
+    lb.propagate(T(P), x, nsteps, prec)
+    return x.cpu().numpy()
+
+
+def test_d27_sliced_config3_meets_1e6(lb, P27):
+    """Config 3 length (1e3 steps), sliced BF16: trace distance < 1e-6."""
+    X = states(27, 8, 11)
+    ref = oracle.propagate(P27, X, 1000)
+    got = run(lb, P27, X, 1000, "bf16_sliced")
+    td = oracle.trace_distance(got.reshape(-1, 27, 27), ref.reshape(-1, 27, 27))
+    print(f"sliced d=27 N=1e3: trace distance max {td.max():.3e}")
+    assert td.max() < 1e-6
+
+
+@pytest.mark.parametrize("B", [1, 20, 33])
+@pytest.mark.parametrize("prec,tol", [("c64", 5e-5), ("bf16_hilo", 5e-3), ("bf16_sliced", 1e-6), ("c128", 1e-12)])
+def test_d27_paths(lb, P27, B, prec, tol):
+    X = states(27, B, 100 + B)
+    ref = oracle.propagate(P27, X, 60)
+    got = run(lb, P27, X, 60, prec)
+    td = oracle.trace_distance(got.reshape(-1, 27, 27), ref.reshape(-1, 27, 27))
+    print(f"{prec} d=27 B={B} N=60: trace distance max {td.max():.3e}")
+    assert td.max() < tol
+
+
+@pytest.mark.parametrize("n,prec,tol", [(100, "bf16_sliced", 1e-8), (130, "c64", 5e-5), (100, "bf16_hilo", 5e-3),
+                                        (90, "c128", 1e-13)])
+def test_past_fused_limits(lb, n, prec, tol):
+    g = np.random.default_rng(n)
+    A = g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))
+    P = A / (1.02 * np.linalg.norm(A, 2))
+    for B in (3, 37):
+        X = g.standard_normal((B, n)) + 1j * g.standard_normal((B, n))
+        ref = oracle.propagate(P, X, 30)
+        got = run(lb, P, X, 30, prec)
+        assert oracle.rel_fro(got, ref) < tol, (B, oracle.rel_fro(got, ref))
+
+
+def test_d27_deterministic(lb, P27):
+    X = states(27, 17, 5)
+    for prec in ("c64", "bf16_sliced"):
+        a = run(lb, P27, X, 10, prec)
+        b = run(lb, P27, X, 10, prec)
+        assert np.array_equal(a, b)
