@@ -56,7 +56,104 @@ def parse():
     ap.add_argument("--paths", default="c128,c64,bf16_hilo,bf16_sliced,baseline", help="variants measured for the `paths` report")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the d=27, GRAPE and mixed-batch sections")
     return ap.parse_args()
+
+
+def _traffic(kernel):
+    """HBM bytes per launch of `kernel` measured with rocprofv3 counters and
+    stored in profiles/traffic.json, or None if absent or if the kernel's
+    source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(kernel)
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
+                return None
+        return rec["bytes_per_launch"]
+    except (OSError, KeyError, TypeError, ValueError):
+        return None
+
+
+def extra_sections(lb, W, torch, dev, ws, want_cpu):
+    """d = 27 chains (config 3), GRAPE gradients (config 4), mixed batch (config 5)."""
+    out = {}
+    # ---- config 3: d = 27, B in {1, 64, 1024}, 1e3 steps
+    cfg = W.config3(B=1024, nsteps=1000)
+    n, N = 729, cfg["nsteps"]
+    H, Lk = torch.from_numpy(cfg["H"]).to(dev), torch.from_numpy(cfg["Lk"]).to(dev)
+    t0 = time.perf_counter()
+    L = lb.liouvillian(H, Lk)
+    P = lb.propagator(L, cfg["dt"], ws=ws)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    X0 = torch.from_numpy(cfg["rho0"].reshape(-1, n)).to(dev)
+    d27 = {"build_ms": build_ms}
+    samples = {}
+    for B in (1, 64, 1024):
+        row = {}
+        for prec in ("c128", "c64", "bf16_hilo", "bf16_sliced", "baseline"):
+            nst = N if not (prec == "baseline" and B == 1024) else 100
+            x = X0[:B].clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if prec == "baseline":
+                lb.propagate_baseline(P, x, nst, ws=ws)
+            else:
+                lb.propagate(P, x, nst, prec, ws=ws)
+            torch.cuda.synchronize()
+            dtm = time.perf_counter() - t0
+            row[prec] = {"state_steps_per_s": B * nst / dtm, "ms": dtm * 1e3, "nsteps": nst}
+            if nst == N:
+                samples[(B, prec)] = x[:min(B, 2)].cpu().numpy()
+        d27[f"B{B}"] = row
+    if want_cpu:
+        import oracle
+        ref = oracle.propagate(P.cpu().numpy(), cfg["rho0"].reshape(-1, n)[:2], N, nthreads=oracle.max_threads())
+        for (B, prec), fin in samples.items():
+            td = oracle.trace_distance(fin.reshape(-1, 27, 27), ref[:fin.shape[0]].reshape(-1, 27, 27))
+            d27[f"B{B}"][prec]["trace_distance_max"] = float(td.max())
+    out["d27_config3"] = d27
+    # ---- config 4: GRAPE gradients, M = 200 slices of 1 ns
+    grape = {}
+    for q in (2, 3):
+        p = W.grape_problem(q, M=200)
+        Hc = torch.from_numpy(p["Hc"]).to(dev)
+        L0 = lb.liouvillian(torch.from_numpy(p["H0"]).to(dev), torch.from_numpy(p["Lk"]).to(dev))
+        Lc = torch.stack([lb.liouvillian(Hc[c], None) for c in range(Hc.shape[0])])
+        u = torch.from_numpy(p["u"]).to(dev)
+        x0 = torch.from_numpy(p["rho0"].reshape(-1)).to(dev)
+        w = torch.from_numpy(p["target"].reshape(-1)).to(dev)
+        lb.grape_gradient(L0, Lc, u, p["dt"], x0, w, ws=ws)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F, g = lb.grape_gradient(L0, Lc, u, p["dt"], x0, w, ws=ws)
+        torch.cuda.synchronize()
+        grape[f"d{3 ** q}"] = {"ms_per_gradient": (time.perf_counter() - t0) * 1e3, "M": 200,
+                               "controls": int(u.shape[1]), "F": F}
+    out["grape_config4"] = grape
+    # ---- config 5: mixed batch of 256 problems, complex64 chains
+    probs = W.mixed_batch()
+    gp = []
+    for pr in probs:
+        Lp = lb.liouvillian(torch.from_numpy(pr["H"]).to(dev), torch.from_numpy(pr["Lk"]).to(dev))
+        gp.append(dict(d=pr["d"], L=Lp, dt=pr["dt"], nsteps=pr["nsteps"],
+                       rho=torch.from_numpy(pr["rho0"].reshape(-1)).to(dev)))
+    total_ss = sum(pr["nsteps"] for pr in probs)
+    lb.batch_run(gp, "c64", ws=ws)  # warm
+    for q, pr in zip(gp, probs):
+        q["rho"].copy_(torch.from_numpy(pr["rho0"].reshape(-1)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lb.batch_run(gp, "c64", ws=ws)
+    torch.cuda.synchronize()
+    dtm = time.perf_counter() - t0
+    out["mixed_config5"] = {"problems": len(probs), "state_steps": total_ss, "makespan_ms": dtm * 1e3,
+                            "state_steps_per_s": total_ss / dtm, "precision": "c64 chains, FP64 builds"}
+    return out
 
 
 def main():
@@ -173,11 +270,14 @@ def main():
     value = B * N * args.steps / wall
 
     bound, peak_key, dtype = PATH_UNIT.get(prec, ("mfma", "fp64_tflops", "f64"))
+    kernel_name = {"c128": "fused_chain_kernel<double>", "c64": "fused_chain_kernel<float>",
+                   "bf16_hilo": "bf16_chain_kernel<HILO>", "bf16_sliced": "bf16_chain_kernel<SLICED>"}.get(
+                       prec, "baseline_step_kernel")
     flops = 8.0 * n * n * B * N  # algorithmic: 8 n^2 per state-step (paper Eq. (4))
     achieved = flops / chain_s / 1e12
     roofline = {"bound": bound, "achieved": achieved, "peak": PEAKS[peak_key], "unit": "TFLOP/s",
-                "frac": achieved / PEAKS[peak_key], "traffic": None,
-                "kernel": "fused_chain_kernel" if prec != "baseline" else "baseline_step_kernel",
+                "frac": achieved / PEAKS[peak_key], "traffic": _traffic(kernel_name),
+                "kernel": kernel_name,
                 "kernel_ms": chain_s * 1e3}
     out = {
         "metric": "state-steps/s at d=9/27: batched MFMA vs plain FP64 matvec at stated error",
@@ -192,6 +292,8 @@ def main():
         out["speedup_vs_fp64_baseline"] = value / paths["baseline"]["state_steps_per_s"]
     if prec in errors:
         out["trace_distance_max"] = errors[prec]
+    if not args.no_extra:
+        out["extra"] = extra_sections(lb, W, torch, dev, ws, not args.no_cpu)
     print(json.dumps(out))
 
 

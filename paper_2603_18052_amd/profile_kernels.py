@@ -1,0 +1,49 @@
+"""Workload for rocprofv3 counter runs: one plain device copy of a known
+size (calibrates FETCH_SIZE / WRITE_SIZE against bytes actually moved), then
+one launch of a chain kernel on the d = 9 workload (B = 4096 Wishart states,
+1e4 steps) in the requested precision.
+
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR -o run -- \\
+        python -m paper_2603_18052_amd.profile_kernels --precision c128
+"""
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+COPY_BYTES = 512 << 20
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--precision", default="c128")
+    ap.add_argument("--nsteps", type=int, default=10_000)
+    ap.add_argument("--batch", type=int, default=4096)
+    a = ap.parse_args()
+    import torch
+    from paper_2603_18052_amd import lindblad as lb
+    from paper_2603_18052_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)  # the calibration copy: COPY_BYTES read, COPY_BYTES written
+    torch.cuda.synchronize()
+    cfg = W.config2(B=a.batch, nsteps=a.nsteps)
+    H, Lk = torch.from_numpy(cfg["H"]).to(dev), torch.from_numpy(cfg["Lk"]).to(dev)
+    P = lb.propagator(lb.liouvillian(H, Lk), cfg["dt"])
+    X = torch.from_numpy(cfg["rho0"].reshape(a.batch, -1)).to(dev)
+    torch.cuda.synchronize()
+    if a.precision == "baseline":
+        lb.propagate_baseline(P, X, a.nsteps)
+    else:
+        lb.propagate(P, X, a.nsteps, a.precision)
+    torch.cuda.synchronize()
+    print("profile_kernels: done", a.precision, flush=True)
+
+
+if __name__ == "__main__":
+    main()
