@@ -11,8 +11,7 @@
 //    (FP64: v_mfma_f64_16x16x4f64, FP32: v_mfma_f32_16x16x4f32), four real
 //    MFMAs per complex block, one barrier per step.  No HBM traffic between
 //    the first load and the final store.
-//  * large n (P does not fit in one CU's LDS): one GEMM launch per step,
-//    Y = X P^T with P^T prepared once.
+//  * large n (P does not fit in one CU's LDS): see chain_large.hip.
 #include <cstring>
 
 #include "chain.hpp"
@@ -275,58 +274,12 @@ static int launch_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hi
     }
 }
 
-// ------------------------------------------------------------- large n
-__global__ void __launch_bounds__(256) transpose_kernel(int n, const cd *__restrict__ P, cd *__restrict__ PT) {
-    __shared__ cd tile[32][33];
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-    for (int j = ty; j < 32; j += 8) {
-        const int r = by + j, c = bx + tx;
-        if (r < n && c < n) tile[j][tx] = P[(size_t)r * n + c];
-    }
-    __syncthreads();
-    for (int j = ty; j < 32; j += 8) {
-        const int r = bx + j, c = by + tx;
-        if (r < n && c < n) PT[(size_t)r * n + c] = tile[tx][j];
-    }
-}
-
-static int chain_large_c128(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
-    const size_t pbytes = (size_t)n * n * sizeof(cd), xbytes = (size_t)B * n * sizeof(cd);
-    LB_TRY(ws_ensure(ws, align256(pbytes) + align256(xbytes)));
-    cd *PT = (cd *)ws_take(ws, pbytes);
-    cd *tmp = (cd *)ws_take(ws, xbytes);
-    dim3 tg((n + 31) / 32, (n + 31) / 32);
-    transpose_kernel<<<tg, 256, 0, s>>>(n, P, PT);
-    LB_TRY(check_launch("transpose"));
-    ZgemmBatch g;
-    g.M = B;
-    g.N = n;
-    g.K = n;
-    g.lda = n;
-    g.B = PT;
-    g.ldb = n;
-    g.ldd = n;
-    cd *x = rho, *y = tmp;
-    for (long long t = 0; t < nsteps; ++t) {
-        g.A = x;
-        g.D = y;
-        LB_TRY(zgemm_batched(g, s));
-        cd *z = x;
-        x = y;
-        y = z;
-    }
-    if (x != rho) LB_HIP(hipMemcpyAsync(rho, x, xbytes, hipMemcpyDeviceToDevice, s));
-    return LB_OK;
-}
-
 int chain_run(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
     if (nsteps == 0 || B == 0) return LB_OK;
     switch (prec) {
         case LB_C128:
             if (n <= fused_max_n(LB_C128)) return launch_fused<double>(n, P, B, rho, nsteps, s);
-            if (B < 16) return chain_large(n, P, prec, B, rho, nsteps, ws, s);
-            return chain_large_c128(n, P, B, rho, nsteps, ws, s);
+            return chain_large(n, P, prec, B, rho, nsteps, ws, s);
         case LB_C64:
             if (n <= fused_max_n(LB_C64)) return launch_fused<float>(n, P, B, rho, nsteps, s);
             return chain_large(n, P, prec, B, rho, nsteps, ws, s);

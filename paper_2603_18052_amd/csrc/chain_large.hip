@@ -3,11 +3,12 @@
 // outputs as columns, both operands read along k, which is contiguous in the
 // row-major state batch and in the rows of P).
 //
-//   LB_C64          P and the states in complex FP32, FP32 matrix cores
-//                   (v_mfma_f32_16x16x4f32); each lane loads four consecutive
-//                   k as one 16-byte load and feeds them to four MFMAs (the k
-//                   order inside a 16-deep block is permuted identically for
-//                   both operands, which leaves the sum unchanged).
+//   LB_C64, LB_C128 P and the states in complex FP32 / FP64 planes, FP32 or
+//                   FP64 matrix cores (v_mfma_f{32,64}_16x16x4); each lane
+//                   loads four consecutive k at once and feeds them to four
+//                   MFMAs (the k order inside a 16-deep block is permuted
+//                   identically for both operands, which leaves the sum
+//                   unchanged).
 //   LB_BF16_HILO    BF16 planes hi / lo of P (once per call) and of the FP32
 //   LB_BF16_SLICED  state (every step), or exponent-aligned 8-bit integer
 //                   slices exactly as in the fused kernel; BF16 matrix cores.
@@ -17,8 +18,9 @@
 //                   are flushed into FP64 accumulators.
 // A workgroup owns a 16-state x 32-output tile; its four wavefronts split the
 // k chunks and their FP64 partials are summed through LDS in a fixed order.
-// Fewer than 16 states with FP32/FP64 arithmetic use a GEMV kernel instead:
-// one wavefront per row of P, all states of the batch in registers.
+// Fewer than 16 states use matrix-vector kernels instead: FP64 the per-state
+// matvec, FP32 a GEMV with one wavefront per row of P and all states of the
+// batch in registers.
 #include <cmath>
 
 #include "chain.hpp"
@@ -271,29 +273,53 @@ __global__ void __launch_bounds__(256) plane_gemm_kernel(int n, int B, int Kp, c
     }
 }
 
-// ------------------------------------------------------------- FP32 path
-// planar FP32 copies: re[B or n][Kp], im[...] (zero padded in k)
-__global__ void to_planes_f32_kernel(int rows, int n, int Kp, const cd *__restrict__ src, float *__restrict__ re,
-                                     float *__restrict__ im) {
+// --------------------------------------------------------- FP32 / FP64
+// planar copies: re[rows][Kp], im[rows][Kp] (zero padded in k)
+template <typename T>
+__global__ void to_planes_kernel(int rows, int n, int Kp, const cd *__restrict__ src, T *__restrict__ re,
+                                 T *__restrict__ im) {
     const long long total = (long long)rows * Kp;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         const long long r = e / Kp, k = e - r * Kp;
         const cd v = k < n ? src[r * n + k] : cd{0.0, 0.0};
-        re[e] = (float)v.re;
-        im[e] = (float)v.im;
+        re[e] = (T)v.re;
+        im[e] = (T)v.im;
     }
 }
 
 typedef float f4s __attribute__((ext_vector_type(4)));
+typedef double d4s __attribute__((ext_vector_type(4)));
 
-// Y[b][i] (FP32 values, stored as c128) = sum_k X[b][k] P[i][k], FP32 MFMA.
-// Wavefronts split the 16-deep k blocks; per block each lane loads 4
-// consecutive k of its state row and of its P rows.
-__global__ void __launch_bounds__(256) cgemm_step_kernel(int n, int B, int Kp, const float *__restrict__ Xr,
-                                                         const float *__restrict__ Xi, const float *__restrict__ Pr,
-                                                         const float *__restrict__ Pi, float *__restrict__ Yr,
-                                                         float *__restrict__ Yi, cd *__restrict__ Yout) {
+template <typename T>
+struct StepMma;
+template <>
+struct StepMma<float> {
+    typedef f4s v4;
+    typedef f4v acc;
+    static __device__ inline acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <>
+struct StepMma<double> {
+    typedef d4s v4;
+    typedef d4s acc;
+    static __device__ inline acc mma(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+// Y[b][i] = sum_k X[b][k] P[i][k] in T on the matrix cores.  Wavefronts split
+// the 16-deep k blocks; per block each lane loads 4 consecutive k of its state
+// row and of its P rows and feeds them to four MFMAs (four real products per
+// complex block, each in its own accumulator).  Writes the planar next state
+// and, on the last step, the complex128 result.
+template <typename T>
+__global__ void __launch_bounds__(256) gemm_step_kernel(int n, int B, int Kp, const T *__restrict__ Xr,
+                                                        const T *__restrict__ Xi, const T *__restrict__ Pr,
+                                                        const T *__restrict__ Pi, T *__restrict__ Yr,
+                                                        T *__restrict__ Yi, cd *__restrict__ Yout) {
+    typedef typename StepMma<T>::v4 v4;
+    typedef typename StepMma<T>::acc acc_t;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int b0 = blockIdx.y * TS, i0 = blockIdx.x * TO;
@@ -308,33 +334,33 @@ __global__ void __launch_bounds__(256) cgemm_step_kernel(int n, int B, int Kp, c
         pvalid[t] = i < n;
         po[t] = (size_t)(pvalid[t] ? i : 0) * Kp + 4 * (lane >> 4);
     }
-    f4v cr[WN], ci[WN];
+    acc_t rr[WN], ii[WN], ri[WN], ir[WN];
 #pragma unroll
-    for (int t = 0; t < WN; ++t) cr[t] = ci[t] = f4v{0, 0, 0, 0};
-    const f4s z = {0, 0, 0, 0};
+    for (int t = 0; t < WN; ++t) rr[t] = ii[t] = ri[t] = ir[t] = acc_t{0, 0, 0, 0};
+    const v4 z = {0, 0, 0, 0};
     for (int kb = wave * 16; kb < Kp; kb += 64) {
-        const f4s xr = bvalid ? *reinterpret_cast<const f4s *>(Xr + xo + kb) : z;
-        const f4s xi = bvalid ? *reinterpret_cast<const f4s *>(Xi + xo + kb) : z;
+        const v4 xr = bvalid ? *reinterpret_cast<const v4 *>(Xr + xo + kb) : z;
+        const v4 xi = bvalid ? *reinterpret_cast<const v4 *>(Xi + xo + kb) : z;
 #pragma unroll
         for (int t = 0; t < WN; ++t) {
-            const f4s pr = pvalid[t] ? *reinterpret_cast<const f4s *>(Pr + po[t] + kb) : z;
-            const f4s pi = pvalid[t] ? *reinterpret_cast<const f4s *>(Pi + po[t] + kb) : z;
+            const v4 pr = pvalid[t] ? *reinterpret_cast<const v4 *>(Pr + po[t] + kb) : z;
+            const v4 pi = pvalid[t] ? *reinterpret_cast<const v4 *>(Pi + po[t] + kb) : z;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[q], pr[q], cr[t], 0, 0, 0);
-                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-xi[q], pi[q], cr[t], 0, 0, 0);
-                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[q], pr[q], ci[t], 0, 0, 0);
-                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[q], pi[q], ci[t], 0, 0, 0);
+                rr[t] = StepMma<T>::mma(xr[q], pr[q], rr[t]);
+                ii[t] = StepMma<T>::mma(xi[q], pi[q], ii[t]);
+                ri[t] = StepMma<T>::mma(xr[q], pi[q], ri[t]);
+                ir[t] = StepMma<T>::mma(xi[q], pr[q], ir[t]);
             }
         }
     }
-    __shared__ float red[4][WN][4][2][64];
+    __shared__ T red[4][WN][4][2][64];
 #pragma unroll
     for (int t = 0; t < WN; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            red[wave][t][r][0][lane] = cr[t][r];
-            red[wave][t][r][1][lane] = ci[t][r];
+            red[wave][t][r][0][lane] = rr[t][r] - ii[t][r];
+            red[wave][t][r][1][lane] = ri[t][r] + ir[t][r];
         }
     __syncthreads();
     if (wave == 0) {
@@ -342,12 +368,12 @@ __global__ void __launch_bounds__(256) cgemm_step_kernel(int n, int B, int Kp, c
         for (int t = 0; t < WN; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                float sr = red[0][t][r][0][lane], si = red[0][t][r][1][lane];
+                T sr = red[0][t][r][0][lane], si = red[0][t][r][1][lane];
                 for (int w = 1; w < 4; ++w) {
                     sr += red[w][t][r][0][lane];
                     si += red[w][t][r][1][lane];
                 }
-                const int b = b0 + 4 * (lane >> 4) + r, i = i0 + t * 16 + (lane & 15);
+                const int b = b0 + StepMma<T>::row(lane, r), i = i0 + t * 16 + (lane & 15);
                 if (b < B && i < n) {
                     Yr[(size_t)b * Kp + i] = sr;
                     Yi[(size_t)b * Kp + i] = si;
@@ -441,25 +467,26 @@ static int chain_gemv(int n, const cd *P, int B, cd *rho, long long nsteps, Work
     return check_launch("gemv_back");
 }
 
-static int chain_large_c64(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+template <typename T>
+static int chain_large_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
     const int Kp = (n + 63) / 64 * 64;
-    const size_t pp = (size_t)n * Kp * sizeof(float), xp = (size_t)B * Kp * sizeof(float);
+    const size_t pp = (size_t)n * Kp * sizeof(T), xp = (size_t)B * Kp * sizeof(T);
     LB_TRY(ws_ensure(ws, 2 * align256(pp) + 4 * align256(xp)));
-    float *Pr = (float *)ws_take(ws, pp), *Pi = (float *)ws_take(ws, pp);
-    float *X[2][2];
+    T *Pr = (T *)ws_take(ws, pp), *Pi = (T *)ws_take(ws, pp);
+    T *X[2][2];
     for (int q = 0; q < 2; ++q)
-        for (int c = 0; c < 2; ++c) X[q][c] = (float *)ws_take(ws, xp);
-    to_planes_f32_kernel<<<grid1((long long)n * Kp), 256, 0, s>>>(n, n, Kp, P, Pr, Pi);
+        for (int c = 0; c < 2; ++c) X[q][c] = (T *)ws_take(ws, xp);
+    to_planes_kernel<T><<<grid1((long long)n * Kp), 256, 0, s>>>(n, n, Kp, P, Pr, Pi);
     for (int q = 0; q < 2; ++q)  // zero k padding of both buffers
-        to_planes_f32_kernel<<<grid1((long long)B * Kp), 256, 0, s>>>(B, n, Kp, rho, X[q][0], X[q][1]);
+        to_planes_kernel<T><<<grid1((long long)B * Kp), 256, 0, s>>>(B, n, Kp, rho, X[q][0], X[q][1]);
     LB_TRY(check_launch("to_planes"));
     dim3 grid((n + TO - 1) / TO, (B + TS - 1) / TS);
     for (long long t = 0; t < nsteps; ++t) {
         const int c = (int)(t & 1);
-        cgemm_step_kernel<<<grid, 256, 0, s>>>(n, B, Kp, X[c][0], X[c][1], Pr, Pi, X[c ^ 1][0], X[c ^ 1][1],
-                                               t + 1 == nsteps ? rho : nullptr);
+        gemm_step_kernel<T><<<grid, 256, 0, s>>>(n, B, Kp, X[c][0], X[c][1], Pr, Pi, X[c ^ 1][0], X[c ^ 1][1],
+                                                 t + 1 == nsteps ? rho : nullptr);
     }
-    return check_launch("cgemm_step");
+    return check_launch("gemm_step");
 }
 
 template <int MODE, int SP, int SX, int LMAX>
@@ -495,10 +522,11 @@ int chain_large(int n, const cd *P, lb_precision prec, int B, cd *rho, long long
                 hipStream_t s) {
     switch (prec) {
         case LB_C128:
-            return chain_gemv<double>(n, P, B, rho, nsteps, ws, s);
+            if (B < 16) return chain_baseline(n, P, B, rho, nsteps, ws, s);
+            return chain_large_gemm<double>(n, P, B, rho, nsteps, ws, s);
         case LB_C64:
             if (B < 16) return chain_gemv<float>(n, P, B, rho, nsteps, ws, s);
-            return chain_large_c64(n, P, B, rho, nsteps, ws, s);
+            return chain_large_gemm<float>(n, P, B, rho, nsteps, ws, s);
         case LB_BF16_HILO:
             return chain_large_planes<HILO, 2, 2, 1>(n, P, B, rho, nsteps, ws, s);
         case LB_BF16_SLICED:
