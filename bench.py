@@ -10,8 +10,11 @@ bench step), inputs resident in HBM before the timed region starts.
 Printed: ONE JSON line.  Besides the contract's keys it carries
   roofline      the dominant kernel (the chain) against the chip's peak
   cpu_baseline  the CPU oracle timed on this host on a bounded sample
-  paths         every chain variant's rate on the same workload and its
+  paths         every precision's rate on the same workload (its chain
+                kernel chosen by the library's autotuner) and its
                 trace-distance error against the oracle (sampled states)
+  extra         d = 3 single-state latency, d = 27 chains, GRAPE gradients,
+                the mixed batch
 """
 from __future__ import annotations
 
@@ -78,9 +81,56 @@ def _traffic(kernel):
         return None
 
 
+KERNEL_OF_FAMILY = {1: "baseline_step_kernel", 2: "wave_chain_kernel", 3: "fused_chain_kernel",
+                    4: "bf16_chain_kernel", 5: "gemm_step_kernel", 6: "matvec_step_kernel", 7: "plane_gemm_kernel"}
+
+
+def kernel_of(variant, prec):
+    """Name of the chain kernel a variant launches (as rocprofv3 lists it, templates abbreviated)."""
+    fam = variant // 100
+    base = KERNEL_OF_FAMILY.get(fam, "unknown")
+    if fam in (2, 3, 5):
+        return base + ("<double>" if prec == "c128" else "<float>")
+    if fam in (4, 7):
+        return base + ("<HILO>" if prec == "bf16_hilo" else "<SLICED>")
+    return base
+
+
+def config1_section(lb, W, torch, dev, ws, want_cpu):
+    """Config 1: d = 3, one pure state, 1e4 steps -- the latency-bound
+    single-state regime; ns per step of each FP64 variant."""
+    c = W.config1()
+    H, Lk = torch.from_numpy(c["H"]).to(dev), torch.from_numpy(c["Lk"]).to(dev)
+    P = lb.propagator(lb.liouvillian(H, Lk), c["dt"], ws=ws)
+    x0 = torch.from_numpy(c["rho0"].reshape(1, 9)).to(dev)
+    N = c["nsteps"]
+    res = {"default_variant": lb.variant_name(lb.chain_variant(9, "c128", 1))}
+    ref = None
+    if want_cpu:
+        import oracle
+        ref = oracle.propagate(P.cpu().numpy(), c["rho0"].reshape(1, 9), N)
+    for v in lb.chain_variants(9, "c128", 1):
+        x = x0.clone()
+        lb.propagate_variant(P, x, N, v, "c128", ws=ws)  # warm
+        x = x0.clone()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        lb.propagate_variant(P, x, N, v, "c128", ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        row = {"ns_per_step": e0.elapsed_time(e1) * 1e6 / N}
+        if ref is not None:
+            import oracle
+            row["rel_fro"] = float(oracle.rel_fro(x.cpu().numpy(), ref))
+        res[lb.variant_name(v)] = row
+    return res
+
+
 def extra_sections(lb, W, torch, dev, ws, want_cpu):
-    """d = 27 chains (config 3), GRAPE gradients (config 4), mixed batch (config 5)."""
-    out = {}
+    """d = 3 single state (config 1), d = 27 chains (config 3), GRAPE
+    gradients (config 4), mixed batch (config 5)."""
+    out = {"d3_config1": config1_section(lb, W, torch, dev, ws, want_cpu)}
     # ---- config 3: d = 27, B in {1, 64, 1024}, 1e3 steps
     cfg = W.config3(B=1024, nsteps=1000)
     n, N = 729, cfg["nsteps"]
@@ -98,6 +148,10 @@ def extra_sections(lb, W, torch, dev, ws, want_cpu):
         for prec in ("c128", "c64", "bf16_hilo", "bf16_sliced", "baseline"):
             nst = N if not (prec == "baseline" and B == 1024) else 100
             x = X0[:B].clone()
+            variant = None
+            if prec != "baseline":
+                lb.tune(P, x, prec, probe_steps=20, repeats=2, ws=ws)
+                variant = lb.variant_name(lb.chain_variant(n, prec, B))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if prec == "baseline":
@@ -107,6 +161,8 @@ def extra_sections(lb, W, torch, dev, ws, want_cpu):
             torch.cuda.synchronize()
             dtm = time.perf_counter() - t0
             row[prec] = {"state_steps_per_s": B * nst / dtm, "ms": dtm * 1e3, "nsteps": nst}
+            if variant:
+                row[prec]["variant"] = variant
             if nst == N:
                 samples[(B, prec)] = x[:min(B, 2)].cpu().numpy()
         d27[f"B{B}"] = row
@@ -198,6 +254,9 @@ def main():
     finals = {}
     for prec in [p for p in args.paths.split(",") if p]:
         try:
+            if prec != "baseline":  # autotune the chain kernel for this shape
+                Pt = lb.propagator(lb.liouvillian(H, Lk), cfg["dt"], ws=ws)
+                lb.tune(Pt, X0, prec, probe_steps=100, repeats=3, ws=ws)
             one_step(prec)
         except lb.LindbladError as e:
             paths[prec] = {"status": str(e)}
@@ -210,7 +269,8 @@ def main():
         torch.cuda.synchronize()
         dtm = (time.perf_counter() - t0) / reps
         finals[prec] = X[torch.as_tensor(sample_idx, device=dev)].cpu().numpy()
-        paths[prec] = {"state_steps_per_s": B * N / dtm, "ms_per_step": dtm * 1e3}
+        paths[prec] = {"state_steps_per_s": B * N / dtm, "ms_per_step": dtm * 1e3,
+                       "variant": "baseline" if prec == "baseline" else lb.variant_name(lb.chain_variant(n, prec, B))}
     Pn = P.cpu().numpy()
 
     # ---- choose the headline variant
@@ -238,7 +298,9 @@ def main():
         oracle.propagate(Ph, cfg["rho0"].reshape(B, n)[:Bs], Ns, nthreads=nthreads)
         t_probe = time.perf_counter() - t0
         scale = max(1.0, args.cpu_seconds / max(t_probe, 1e-3))
-        Ns = int(min(N, Ns * scale))
+        Ns_want = Ns * scale  # grow the step count first, then the state count
+        Ns = int(min(N, Ns_want))
+        Bs = int(min(B, Bs * max(1.0, Ns_want / Ns)))
         t0 = time.perf_counter()
         Lh = oracle.liouvillian(cfg["H"], cfg["Lk"])
         Ph = oracle.propagator(Lh, cfg["dt"])
@@ -270,9 +332,8 @@ def main():
     value = B * N * args.steps / wall
 
     bound, peak_key, dtype = PATH_UNIT.get(prec, ("mfma", "fp64_tflops", "f64"))
-    kernel_name = {"c128": "fused_chain_kernel<double>", "c64": "fused_chain_kernel<float>",
-                   "bf16_hilo": "bf16_chain_kernel<HILO>", "bf16_sliced": "bf16_chain_kernel<SLICED>"}.get(
-                       prec, "baseline_step_kernel")
+    variant = 100 if prec == "baseline" else lb.chain_variant(n, prec, B)
+    kernel_name = kernel_of(variant, prec)
     flops = 8.0 * n * n * B * N  # algorithmic: 8 n^2 per state-step (paper Eq. (4))
     achieved = flops / chain_s / 1e12
     roofline = {"bound": bound, "achieved": achieved, "peak": PEAKS[peak_key], "unit": "TFLOP/s",
@@ -285,7 +346,8 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
         "config": {"workload": "d=9 two coupled transmons (81x81 P), Wishart states", "global_batch": B,
-                   "nsteps": N, "precision": prec, "parallelism": "single GPU"},
+                   "nsteps": N, "precision": prec, "variant": lb.variant_name(variant),
+                   "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "paths": paths,
     }
     if "baseline" in paths and "state_steps_per_s" in paths["baseline"]:

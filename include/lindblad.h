@@ -123,9 +123,14 @@ int lindblad_propagator(int n, int M, const void *L, const double *dt, double th
  *   B      : number of states, >= 1
  *   rho    : B x n complex128, in place (row b = vec of state b)
  *   nsteps : >= 0
- * Asynchronous.  LB_C128 has a fused kernel for every n; LB_C64,
- * LB_BF16_HILO and LB_BF16_SLICED for every n as well (P resident in LDS for
- * n <= 96, tiled from L2 otherwise). */
+ * Asynchronous.  Every precision runs for every n.  The kernel ("variant")
+ * is the one lindblad_tune recorded for (n, prec, B) on this device, else
+ * the built-in rule: one wavefront per state with P rows in registers for
+ * n <= 16 (LB_C128, LB_C64); the plain per-state matvec for LB_C128 when
+ * B n^2 <= 1.1e6; the whole chain in one launch with P on chip while it fits
+ * one compute unit's LDS (n <= 84 LB_C128, 124 LB_C64, 85 LB_BF16_SLICED,
+ * 96 LB_BF16_HILO); beyond that one MFMA GEMM launch per step (B >= 16) or
+ * a per-state matvec (B < 16). */
 int lindblad_propagate(int n, const void *P, lb_precision prec, int B, void *rho, long long nsteps,
                        lb_workspace *ws, hipStream_t stream);
 
@@ -135,6 +140,46 @@ int lindblad_propagate(int n, const void *P, lb_precision prec, int B, void *rho
  * result as lindblad_propagate with LB_C128.  Asynchronous. */
 int lindblad_propagate_baseline(int n, const void *P, int B, void *rho, long long nsteps,
                                 lb_workspace *ws, hipStream_t stream);
+
+/* Chain variants and their autotuner (Alg. 2 / Alg. 3: the same steps, a
+ * choice of kernel and tile shape).  A variant id is family * 100 + tile
+ * parameter:
+ *   100       plain FP64 per-state matvec (LB_C128 only)
+ *   200       one wavefront per state, P rows in registers (n <= 16)
+ *   300 + k   whole chain in one launch, P as MFMA fragments in registers,
+ *             k = 4-deep k steps per work unit (n within the fused limit)
+ *   400       whole BF16 chain in one launch (BF16 precisions, fused limit)
+ *   500 + w   one MFMA GEMM launch per step, w = 16-output tiles per wavefront
+ *   600       per-state FP32 matvec, one launch per step (LB_C64 only)
+ *   700       one BF16 plane-GEMM launch per step (BF16 precisions)
+ * Variants of one shape differ only in summation order. */
+
+/* Variants that exist for (n, prec, B): up to max_ids ids written to the HOST
+ * array ids, the total number to *count. */
+int lindblad_chain_variants(int n, lb_precision prec, int B, int *ids, int max_ids, int *count);
+
+/* The variant lindblad_propagate runs for (n, prec, B) on the current device
+ * (tuned, else the built-in rule), to the HOST int *variant. */
+int lindblad_chain_variant(int n, lb_precision prec, int B, int *variant);
+
+/* lindblad_propagate with an explicit variant; LB_EINVAL if the variant does
+ * not exist for the shape.  Asynchronous. */
+int lindblad_propagate_variant(int n, const void *P, lb_precision prec, int B, void *rho, long long nsteps,
+                               int variant, lb_workspace *ws, hipStream_t stream);
+
+/* Autotuner: runs every variant of (n, prec, B) for probe_steps steps on a
+ * workspace copy of rho (rho itself is only read), `repeats` times after one
+ * warm-up run, times each with HIP events on `stream`, and records the
+ * fastest for (current device, n, prec, B) for the rest of the process.
+ * *best_variant and *best_ms (its fastest probe run in ms; both HOST, may be
+ * NULL) receive the winner.  Synchronises the host with `stream`.  Thread-safe
+ * table; calls that share a workspace must still be ordered. */
+int lindblad_tune(int n, const void *P, lb_precision prec, int B, const void *rho, long long probe_steps,
+                  int repeats, lb_workspace *ws, hipStream_t stream, int *best_variant, float *best_ms);
+
+/* Record `variant` for (current device, n, prec, B) without timing (e.g. a
+ * choice saved from an earlier tuning run); 0 removes the record. */
+int lindblad_tune_set(int n, lb_precision prec, int B, int variant);
 
 /* GRAPE fidelity and its gradient for piecewise-constant controls.
  * (Not in the paper, which runs only the forward landscape point of Eq. (5).)

@@ -66,6 +66,81 @@ int chain_baseline(int n, const cd *P, int B, cd *rho, long long nsteps, Workspa
     return LB_OK;
 }
 
+// ------------------------------------------------------- one state per wave
+// Small n (d <= 4): one wavefront per state, no LDS and no barrier.  Lane i
+// holds row i of P and element i of the state in registers; each step reads
+// every x_k with v_readlane into scalar registers (a wavefront-wide broadcast)
+// and lane i forms y_i = sum_k P_ik x_k with four independent FMA chains
+// (Re/Im times Re/Im), so one step costs about 4n FMAs + 2n lane reads of
+// latency.  This is the latency-bound single-state regime (B = 1, d = 3).
+__device__ inline double lane_read(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, k);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), k);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ inline float lane_read(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+template <typename T, int NP>
+__global__ void __launch_bounds__(256) wave_chain_kernel(int n, const cd *__restrict__ P, int B, cd *__restrict__ rho,
+                                                         long long nsteps) {
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (b >= B) return;  // uniform per wavefront
+    const bool row = lane < n;
+    T pr[NP], pi[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        cd v = {0.0, 0.0};
+        if (row && k < n) v = P[(size_t)lane * n + k];
+        pr[k] = (T)v.re;
+        pi[k] = (T)v.im;
+    }
+    cd v0 = {0.0, 0.0};
+    if (row) v0 = rho[(size_t)b * n + lane];
+    T xr = (T)v0.re, xi = (T)v0.im;
+    for (long long t = 0; t < nsteps; ++t) {
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const T sr = lane_read(xr, k), si = lane_read(xi, k);
+            a0 = fma(pr[k], sr, a0);
+            a1 = fma(-pi[k], si, a1);
+            a2 = fma(pr[k], si, a2);
+            a3 = fma(pi[k], sr, a3);
+        }
+        xr = a0 + a1;
+        xi = a2 + a3;
+    }
+    if (row) rho[(size_t)b * n + lane] = {(double)xr, (double)xi};
+}
+
+template <typename T>
+static int launch_wave_chain(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
+    const int blocks = (B + 3) / 4;
+    if (n <= 4)
+        wave_chain_kernel<T, 4><<<blocks, 256, 0, s>>>(n, P, B, rho, nsteps);
+    else if (n <= 9)
+        wave_chain_kernel<T, 9><<<blocks, 256, 0, s>>>(n, P, B, rho, nsteps);
+    else if (n <= kWaveChainMaxN)
+        wave_chain_kernel<T, kWaveChainMaxN><<<blocks, 256, 0, s>>>(n, P, B, rho, nsteps);
+    else
+        return fail(LB_ESHAPE, "wave chain: n too large");
+    return check_launch("wave_chain");
+}
+
+int chain_wave(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s) {
+    if (nsteps == 0 || B == 0) return LB_OK;
+    if (n > kWaveChainMaxN) return fail(LB_ESHAPE, "wave chain: n too large");
+    switch (prec) {
+        case LB_C128: return launch_wave_chain<double>(n, P, B, rho, nsteps, s);
+        case LB_C64: return launch_wave_chain<float>(n, P, B, rho, nsteps, s);
+        default: return fail(LB_ENOTSUP, "wave chain: complex128 / complex64 only");
+    }
+}
+
 // ------------------------------------------------------ fused small-n chain
 // One workgroup of 8 wavefronts owns NS = 16 states for every step.  The
 // product Y = P X (Mp x Kp times Kp x 16) is cut into units = (16-row tile of
@@ -100,27 +175,22 @@ struct FusedShape {
     int Kp, KS, mtiles, kparts, units, kpu;
 };
 
-static FusedShape fused_shape(int n) {
+// k steps per unit the fused kernel is instantiated for.
+static const int kFusedKpu[] = {1, 2, 3, 4, 6, 8, 11};
+
+static FusedShape fused_shape(int n, int kpu) {
     FusedShape f;
     f.Kp = (n + 3) & ~3;
     f.KS = f.Kp / 4;
     f.mtiles = (n + 15) / 16;
-    const int cands[] = {1, 2, 3, 4, 6, 8, 11, 16, 32};
-    f.kpu = 32;
-    for (int c : cands) {
-        if (f.mtiles * ((f.KS + c - 1) / c) <= MAXU) {
-            f.kpu = c;
-            break;
-        }
-    }
-    f.kparts = (f.KS + f.kpu - 1) / f.kpu;
+    f.kpu = kpu;
+    f.kparts = (f.KS + kpu - 1) / kpu;
     f.units = f.mtiles * f.kparts;
     return f;
 }
 
 template <typename T>
-static size_t fused_lds_bytes(int n) {
-    const FusedShape f = fused_shape(n);
+static size_t fused_lds_bytes(const FusedShape &f) {
     return sizeof(T) * (2 * (size_t)f.Kp * NS + 2 * (size_t)f.units * 256);
 }
 
@@ -259,36 +329,52 @@ static int launch_fused_u(int n, const FusedShape &f, const cd *P, int B, cd *rh
 }
 
 template <typename T>
-static int launch_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
-    const size_t lds = fused_lds_bytes<T>(n);
-    if (lds > kLdsLimit) return fail(LB_ESHAPE, "fused chain: n too large for LDS");
-    const FusedShape f = fused_shape(n);
-    switch (f.kpu) {
+static int launch_fused(int n, int kpu, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
+    const FusedShape f = fused_shape(n, kpu);
+    const size_t lds = fused_lds_bytes<T>(f);
+    switch (kpu) {
         case 1: return launch_fused_u<T, 1>(n, f, P, B, rho, nsteps, lds, s);
         case 2: return launch_fused_u<T, 2>(n, f, P, B, rho, nsteps, lds, s);
         case 3: return launch_fused_u<T, 3>(n, f, P, B, rho, nsteps, lds, s);
         case 4: return launch_fused_u<T, 4>(n, f, P, B, rho, nsteps, lds, s);
         case 6: return launch_fused_u<T, 6>(n, f, P, B, rho, nsteps, lds, s);
         case 8: return launch_fused_u<T, 8>(n, f, P, B, rho, nsteps, lds, s);
+        case 11: return launch_fused_u<T, 11>(n, f, P, B, rho, nsteps, lds, s);
         default: return fail(LB_ESHAPE, "fused chain: unsupported unit shape");
     }
 }
 
-int chain_run(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+// Valid k-steps-per-unit values for n, ascending; a larger value that gives
+// the same number of k parts would only add zero fragments, so it is skipped.
+int fused_kpus(int n, lb_precision prec, int *kpus, int max) {
+    if (n < 1 || n > fused_max_n(prec) || (prec != LB_C128 && prec != LB_C64)) return 0;
+    int c = 0, last_parts = 0;
+    for (int k : kFusedKpu) {
+        const FusedShape f = fused_shape(n, k);
+        if (f.units > MAXU || f.kparts == last_parts) continue;
+        const size_t lds = prec == LB_C128 ? fused_lds_bytes<double>(f) : fused_lds_bytes<float>(f);
+        if (lds > kLdsLimit) continue;
+        last_parts = f.kparts;
+        if (c < max) kpus[c++] = k;
+    }
+    return c;
+}
+
+bool fused_kpu_ok(int n, lb_precision prec, int kpu) {
+    int k[16];
+    const int c = fused_kpus(n, prec, k, 16);
+    for (int i = 0; i < c; ++i)
+        if (k[i] == kpu) return true;
+    return false;
+}
+
+int chain_fused(int n, const cd *P, lb_precision prec, int kpu, int B, cd *rho, long long nsteps, hipStream_t s) {
     if (nsteps == 0 || B == 0) return LB_OK;
+    if (!fused_kpu_ok(n, prec, kpu)) return fail(LB_ESHAPE, "fused chain: shape not available for this n");
     switch (prec) {
-        case LB_C128:
-            if (n <= fused_max_n(LB_C128)) return launch_fused<double>(n, P, B, rho, nsteps, s);
-            return chain_large(n, P, prec, B, rho, nsteps, ws, s);
-        case LB_C64:
-            if (n <= fused_max_n(LB_C64)) return launch_fused<float>(n, P, B, rho, nsteps, s);
-            return chain_large(n, P, prec, B, rho, nsteps, ws, s);
-        case LB_BF16_HILO:
-        case LB_BF16_SLICED:
-            if (n <= bf16_fused_max_n(prec)) return chain_bf16_fused(n, P, prec, B, rho, nsteps, s);
-            return chain_large(n, P, prec, B, rho, nsteps, ws, s);
-        default:
-            return fail(LB_EINVAL, "lindblad_propagate: bad precision");
+        case LB_C128: return launch_fused<double>(n, kpu, P, B, rho, nsteps, s);
+        case LB_C64: return launch_fused<float>(n, kpu, P, B, rho, nsteps, s);
+        default: return fail(LB_ENOTSUP, "fused chain: complex128 / complex64 only");
     }
 }
 
@@ -296,21 +382,12 @@ int chain_run(int n, const cd *P, lb_precision prec, int B, cd *rho, long long n
 
 using namespace lb;
 
-static int validate_chain(const char *who, int n, const void *P, int B, const void *rho, long long nsteps) {
+int lb::validate_chain(const char *who, int n, const void *P, int B, const void *rho, long long nsteps) {
     if (n < 1 || n > 4096) return fail(LB_ESHAPE, std::string(who) + ": n must be in [1, 4096]");
     if (B < 1) return fail(LB_ESHAPE, std::string(who) + ": B must be >= 1");
     if (nsteps < 0) return fail(LB_EINVAL, std::string(who) + ": nsteps must be >= 0");
     if (!P || !rho) return fail(LB_EINVAL, std::string(who) + ": NULL pointer");
     return LB_OK;
-}
-
-extern "C" int lindblad_propagate(int n, const void *P, lb_precision prec, int B, void *rho, long long nsteps,
-                                  lb_workspace *ws, hipStream_t stream) {
-    LB_TRY(validate_chain("lindblad_propagate", n, P, B, rho, nsteps));
-    if ((int)prec < LB_C128 || (int)prec > LB_BF16_SLICED) return fail(LB_EINVAL, "lindblad_propagate: bad precision");
-    Workspace *w = ws_resolve(ws);
-    ws_begin(w);
-    return chain_run(n, static_cast<const cd *>(P), prec, B, static_cast<cd *>(rho), nsteps, w, stream);
 }
 
 extern "C" int lindblad_propagate_baseline(int n, const void *P, int B, void *rho, long long nsteps, lb_workspace *ws,

@@ -1,13 +1,36 @@
-// Internal launchers of the propagation chain (lindblad_propagate).
+// Internal launchers of the propagation chain (lindblad_propagate) and its
+// variants.  Every variant runs the same N steps x <- P x on each state; they
+// differ in kernel, tiling and summation order only.
 #pragma once
 #include "lb_internal.hpp"
 
 namespace lb {
 
+// Variant ids: family * 100 + tile parameter.
+enum ChainFamily : int {
+    VF_BASELINE = 1,    // plain FP64 per-state matvec, one launch per step
+    VF_WAVE = 2,        // one wavefront per state, P rows in registers (n <= kWaveChainMaxN)
+    VF_FUSED = 3,       // whole chain in one launch, P on chip; param = k steps per unit
+    VF_BF16_FUSED = 4,  // whole BF16 chain in one launch (n <= bf16_fused_max_n)
+    VF_GEMM = 5,        // one MFMA GEMM launch per step; param = 16-output tiles per wavefront
+    VF_MATVEC = 6,      // per-state FP32 matvec, one launch per step (LB_C64)
+    VF_PLANES = 7,      // one BF16 plane-GEMM launch per step
+};
+inline int variant_family(int v) { return v / 100; }
+inline int variant_param(int v) { return v % 100; }
+
+int validate_chain(const char *who, int n, const void *P, int B, const void *rho, long long nsteps);
+
 // Largest n whose fused, LDS-resident chain exists for each precision.
 int fused_max_n(lb_precision prec);
+bool fused_kpu_ok(int n, lb_precision prec, int kpu);
+int fused_kpus(int n, lb_precision prec, int *kpus, int max);  // valid k-steps-per-unit values, ascending
 
 int chain_baseline(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s);
+constexpr int kWaveChainMaxN = 16;
+int chain_wave(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
+int chain_fused(int n, const cd *P, lb_precision prec, int kpu, int B, cd *rho, long long nsteps, hipStream_t s);
+
 // Longest chain that runs with the 4 x 4-digit slice set (10 slice pairs);
 // longer chains use 5 x 4 digits (14 pairs).  Emulated and measured trace
 // distances of the short set grow about linearly with the step count and
@@ -15,8 +38,22 @@ int chain_baseline(int n, const cd *P, int B, cd *rho, long long nsteps, Workspa
 constexpr long long kSlicedShortRun = 600;
 int bf16_fused_max_n(lb_precision prec);
 int chain_bf16_fused(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
-int chain_large(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
-                hipStream_t s);
+
+int chain_gemm(int n, const cd *P, lb_precision prec, int wn, int B, cd *rho, long long nsteps, Workspace *ws,
+               hipStream_t s);
+int chain_matvec(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
+                 hipStream_t s);
+int chain_planes(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
+                 hipStream_t s);
+size_t large_ws_bytes(int family, int n, lb_precision prec, int B);
+
+// Variant selection (tune.hip): the list of variants that exist for a shape,
+// the built-in choice, the tuned choice if any, and the dispatcher.
+int chain_variants(int n, lb_precision prec, int B, int *ids, int max);
+int chain_heuristic(int n, lb_precision prec, int B);
+size_t chain_ws_bytes(int n, lb_precision prec, int B, int variant);
+int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, int variant,
+                      Workspace *ws, hipStream_t s);
 int chain_run(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s);
 
 }  // namespace lb

@@ -18,9 +18,8 @@
 //                   are flushed into FP64 accumulators.
 // A workgroup owns a 16-state x 32-output tile; its four wavefronts split the
 // k chunks and their FP64 partials are summed through LDS in a fixed order.
-// Fewer than 16 states use matrix-vector kernels instead: FP64 the per-state
-// matvec, FP32 a GEMV with one wavefront per row of P and all states of the
-// batch in registers.
+// Complex64 chains can also run as a per-state FP32 matvec (one wavefront per
+// state and row), the counterpart of the FP64 baseline.
 #include <cmath>
 
 #include "chain.hpp"
@@ -308,12 +307,13 @@ struct StepMma<double> {
     static __device__ inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
-// Y[b][i] = sum_k X[b][k] P[i][k] in T on the matrix cores.  Wavefronts split
+// Y[b][i] = sum_k X[b][k] P[i][k] in T on the matrix cores, 16 states x 16 GWN
+// outputs per workgroup.  Wavefronts split
 // the 16-deep k blocks; per block each lane loads 4 consecutive k of its state
 // row and of its P rows and feeds them to four MFMAs (four real products per
 // complex block, each in its own accumulator).  Writes the planar next state
 // and, on the last step, the complex128 result.
-template <typename T>
+template <typename T, int GWN>
 __global__ void __launch_bounds__(256) gemm_step_kernel(int n, int B, int Kp, const T *__restrict__ Xr,
                                                         const T *__restrict__ Xi, const T *__restrict__ Pr,
                                                         const T *__restrict__ Pi, T *__restrict__ Yr,
@@ -322,27 +322,27 @@ __global__ void __launch_bounds__(256) gemm_step_kernel(int n, int B, int Kp, co
     typedef typename StepMma<T>::acc acc_t;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int b0 = blockIdx.y * TS, i0 = blockIdx.x * TO;
+    const int b0 = blockIdx.y * TS, i0 = blockIdx.x * 16 * GWN;
     const int bl = b0 + (lane & 15);
     const bool bvalid = bl < B;
     const size_t xo = (size_t)(bvalid ? bl : 0) * Kp + 4 * (lane >> 4);
-    size_t po[WN];
-    bool pvalid[WN];
+    size_t po[GWN];
+    bool pvalid[GWN];
 #pragma unroll
-    for (int t = 0; t < WN; ++t) {
+    for (int t = 0; t < GWN; ++t) {
         const int i = i0 + t * 16 + (lane & 15);
         pvalid[t] = i < n;
         po[t] = (size_t)(pvalid[t] ? i : 0) * Kp + 4 * (lane >> 4);
     }
-    acc_t rr[WN], ii[WN], ri[WN], ir[WN];
+    acc_t rr[GWN], ii[GWN], ri[GWN], ir[GWN];
 #pragma unroll
-    for (int t = 0; t < WN; ++t) rr[t] = ii[t] = ri[t] = ir[t] = acc_t{0, 0, 0, 0};
+    for (int t = 0; t < GWN; ++t) rr[t] = ii[t] = ri[t] = ir[t] = acc_t{0, 0, 0, 0};
     const v4 z = {0, 0, 0, 0};
     for (int kb = wave * 16; kb < Kp; kb += 64) {
         const v4 xr = bvalid ? *reinterpret_cast<const v4 *>(Xr + xo + kb) : z;
         const v4 xi = bvalid ? *reinterpret_cast<const v4 *>(Xi + xo + kb) : z;
 #pragma unroll
-        for (int t = 0; t < WN; ++t) {
+        for (int t = 0; t < GWN; ++t) {
             const v4 pr = pvalid[t] ? *reinterpret_cast<const v4 *>(Pr + po[t] + kb) : z;
             const v4 pi = pvalid[t] ? *reinterpret_cast<const v4 *>(Pi + po[t] + kb) : z;
 #pragma unroll
@@ -354,9 +354,9 @@ __global__ void __launch_bounds__(256) gemm_step_kernel(int n, int B, int Kp, co
             }
         }
     }
-    __shared__ T red[4][WN][4][2][64];
+    __shared__ T red[4][GWN][4][2][64];
 #pragma unroll
-    for (int t = 0; t < WN; ++t)
+    for (int t = 0; t < GWN; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             red[wave][t][r][0][lane] = rr[t][r] - ii[t][r];
@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(256) gemm_step_kernel(int n, int B, int Kp, co
     __syncthreads();
     if (wave == 0) {
 #pragma unroll
-        for (int t = 0; t < WN; ++t)
+        for (int t = 0; t < GWN; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 T sr = red[0][t][r][0][lane], si = red[0][t][r][1][lane];
@@ -383,43 +383,37 @@ __global__ void __launch_bounds__(256) gemm_step_kernel(int n, int B, int Kp, co
     }
 }
 
-// ------------------------------------------------------------ GEMV (B < 16)
+// ------------------------------------------------- per-state matvec in T
 template <typename T>
 struct Cx {
     T re, im;
 };
 
-template <typename T, int BM>
-__global__ void __launch_bounds__(256) gemv_step_kernel(int n, int B, const Cx<T> *__restrict__ P,
-                                                        const Cx<T> *__restrict__ X, Cx<T> *__restrict__ Y) {
+// One wavefront per (state, row): lanes read the row of P (in T) and the
+// state contiguously and reduce with cross-lane shuffles.
+template <typename T>
+__global__ void __launch_bounds__(256) matvec_step_kernel(int n, const Cx<T> *__restrict__ P,
+                                                          const Cx<T> *__restrict__ X, Cx<T> *__restrict__ Y,
+                                                          long long rows_total) {
     const int lane = threadIdx.x & 63;
-    const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (row >= n) return;
-    T re[BM], im[BM];
-#pragma unroll
-    for (int b = 0; b < BM; ++b) re[b] = im[b] = 0;
-    const Cx<T> *Pr = P + (size_t)row * n;
-    for (int j = lane; j < n; j += 64) {
-        const Cx<T> p = Pr[j];
-#pragma unroll
-        for (int b = 0; b < BM; ++b)
-            if (b < B) {
-                const Cx<T> v = X[(size_t)b * n + j];
-                re[b] = fma(p.re, v.re, fma(-p.im, v.im, re[b]));
-                im[b] = fma(p.re, v.im, fma(p.im, v.re, im[b]));
-            }
-    }
-#pragma unroll
-    for (int b = 0; b < BM; ++b) {
-        if (b < B) {
-            T r = re[b], i = im[b];
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                r += __shfl_xor(r, off);
-                i += __shfl_xor(i, off);
-            }
-            if (lane == 0) Y[(size_t)b * n + row] = {r, i};
+    const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
+    for (long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < rows_total; w += nwaves) {
+        const long long b = w / n;
+        const int i = (int)(w - b * n);
+        const Cx<T> *Pi = P + (size_t)i * n;
+        const Cx<T> *xb = X + (size_t)b * n;
+        T re = 0, im = 0;
+        for (int j = lane; j < n; j += 64) {
+            const Cx<T> p = Pi[j], v = xb[j];
+            re = fma(p.re, v.re, fma(-p.im, v.im, re));
+            im = fma(p.re, v.im, fma(p.im, v.re, im));
         }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            re += __shfl_xor(re, off);
+            im += __shfl_xor(im, off);
+        }
+        if (lane == 0) Y[(size_t)b * n + i] = {re, im};
     }
 }
 
@@ -448,7 +442,7 @@ static int grid1(long long work) {
 using namespace lg;
 
 template <typename T>
-static int chain_gemv(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+static int matvec_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
     const size_t nn = (size_t)n * n;
     LB_TRY(ws_ensure(ws, align256(nn * sizeof(Cx<T>)) + 2 * align256((size_t)B * n * sizeof(Cx<T>))));
     Cx<T> *Pc = (Cx<T> *)ws_take(ws, nn * sizeof(Cx<T>));
@@ -456,19 +450,21 @@ static int chain_gemv(int n, const cd *P, int B, cd *rho, long long nsteps, Work
     Cx<T> *X1 = (Cx<T> *)ws_take(ws, (size_t)B * n * sizeof(Cx<T>));
     convert_kernel<T><<<grid1(nn), 256, 0, s>>>((long long)nn, P, Pc);
     convert_kernel<T><<<grid1((long long)B * n), 256, 0, s>>>((long long)B * n, rho, X0);
-    const int blocks = (n * 64 + 255) / 256;
+    const long long rows = (long long)B * n;
+    long long blocks = (rows + 3) / 4;
+    if (blocks > 16384) blocks = 16384;
     for (long long t = 0; t < nsteps; ++t) {
         const Cx<T> *x = (t & 1) ? X1 : X0;
         Cx<T> *y = (t & 1) ? X0 : X1;
-        gemv_step_kernel<T, 16><<<blocks, 256, 0, s>>>(n, B, Pc, x, y);
+        matvec_step_kernel<T><<<(int)blocks, 256, 0, s>>>(n, Pc, x, y, rows);
     }
-    LB_TRY(check_launch("gemv_step"));
+    LB_TRY(check_launch("matvec_step"));
     back_kernel<T><<<grid1((long long)B * n), 256, 0, s>>>((long long)B * n, (nsteps & 1) ? X1 : X0, rho);
-    return check_launch("gemv_back");
+    return check_launch("matvec_back");
 }
 
-template <typename T>
-static int chain_large_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+template <typename T, int GWN>
+static int gemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
     const int Kp = (n + 63) / 64 * 64;
     const size_t pp = (size_t)n * Kp * sizeof(T), xp = (size_t)B * Kp * sizeof(T);
     LB_TRY(ws_ensure(ws, 2 * align256(pp) + 4 * align256(xp)));
@@ -480,17 +476,17 @@ static int chain_large_gemm(int n, const cd *P, int B, cd *rho, long long nsteps
     for (int q = 0; q < 2; ++q)  // zero k padding of both buffers
         to_planes_kernel<T><<<grid1((long long)B * Kp), 256, 0, s>>>(B, n, Kp, rho, X[q][0], X[q][1]);
     LB_TRY(check_launch("to_planes"));
-    dim3 grid((n + TO - 1) / TO, (B + TS - 1) / TS);
+    dim3 grid((n + 16 * GWN - 1) / (16 * GWN), (B + TS - 1) / TS);
     for (long long t = 0; t < nsteps; ++t) {
         const int c = (int)(t & 1);
-        gemm_step_kernel<T><<<grid, 256, 0, s>>>(n, B, Kp, X[c][0], X[c][1], Pr, Pi, X[c ^ 1][0], X[c ^ 1][1],
-                                                 t + 1 == nsteps ? rho : nullptr);
+        gemm_step_kernel<T, GWN><<<grid, 256, 0, s>>>(n, B, Kp, X[c][0], X[c][1], Pr, Pi, X[c ^ 1][0], X[c ^ 1][1],
+                                                      t + 1 == nsteps ? rho : nullptr);
     }
     return check_launch("gemm_step");
 }
 
 template <int MODE, int SP, int SX, int LMAX>
-static int chain_large_planes(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
     constexpr int XD = Planes<MODE, SP, SX>::XD, PD = Planes<MODE, SP, SX>::PD;
     const int Kp = (n + KCH - 1) / KCH * KCH;
     const size_t pbytes = (size_t)PD * 2 * n * Kp * 2, xbytes = (size_t)XD * 3 * B * Kp * 2;
@@ -518,23 +514,52 @@ static int chain_large_planes(int n, const cd *P, int B, cd *rho, long long nste
     return LB_OK;
 }
 
-int chain_large(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
-                hipStream_t s) {
+int chain_matvec(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
+                 hipStream_t s) {
+    if (nsteps == 0 || B == 0) return LB_OK;
+    if (prec != LB_C64) return fail(LB_ENOTSUP, "matvec chain: complex64 only (complex128 is the baseline)");
+    return matvec_run<float>(n, P, B, rho, nsteps, ws, s);
+}
+
+int chain_gemm(int n, const cd *P, lb_precision prec, int wn, int B, cd *rho, long long nsteps, Workspace *ws,
+               hipStream_t s) {
+    if (nsteps == 0 || B == 0) return LB_OK;
+    if (wn != 1 && wn != 2) return fail(LB_ESHAPE, "gemm chain: 1 or 2 output tiles per wavefront");
     switch (prec) {
         case LB_C128:
-            if (B < 16) return chain_baseline(n, P, B, rho, nsteps, ws, s);
-            return chain_large_gemm<double>(n, P, B, rho, nsteps, ws, s);
+            return wn == 1 ? gemm_run<double, 1>(n, P, B, rho, nsteps, ws, s) : gemm_run<double, 2>(n, P, B, rho, nsteps, ws, s);
         case LB_C64:
-            if (B < 16) return chain_gemv<float>(n, P, B, rho, nsteps, ws, s);
-            return chain_large_gemm<float>(n, P, B, rho, nsteps, ws, s);
-        case LB_BF16_HILO:
-            return chain_large_planes<HILO, 2, 2, 1>(n, P, B, rho, nsteps, ws, s);
-        case LB_BF16_SLICED:
-            if (nsteps <= kSlicedShortRun) return chain_large_planes<SLICED, 4, 4, 3>(n, P, B, rho, nsteps, ws, s);
-            return chain_large_planes<SLICED, 5, 4, 4>(n, P, B, rho, nsteps, ws, s);
-        default:
-            return fail(LB_EINVAL, "chain_large: bad precision");
+            return wn == 1 ? gemm_run<float, 1>(n, P, B, rho, nsteps, ws, s) : gemm_run<float, 2>(n, P, B, rho, nsteps, ws, s);
+        default: return fail(LB_ENOTSUP, "gemm chain: complex128 / complex64 only");
     }
+}
+
+int chain_planes(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
+                 hipStream_t s) {
+    if (nsteps == 0 || B == 0) return LB_OK;
+    switch (prec) {
+        case LB_BF16_HILO: return planes_run<HILO, 2, 2, 1>(n, P, B, rho, nsteps, ws, s);
+        case LB_BF16_SLICED:
+            if (nsteps <= kSlicedShortRun) return planes_run<SLICED, 4, 4, 3>(n, P, B, rho, nsteps, ws, s);
+            return planes_run<SLICED, 5, 4, 4>(n, P, B, rho, nsteps, ws, s);
+        default: return fail(LB_ENOTSUP, "plane chain: BF16 precisions only");
+    }
+}
+
+size_t large_ws_bytes(int family, int n, lb_precision prec, int B) {
+    const size_t tsz = prec == LB_C128 ? 8 : 4;
+    if (family == VF_MATVEC) return align256((size_t)n * n * 2 * tsz) + 2 * align256((size_t)B * n * 2 * tsz);
+    if (family == VF_GEMM) {
+        const size_t Kp = (size_t)(n + 63) / 64 * 64;
+        return 2 * align256(n * Kp * tsz) + 4 * align256(B * Kp * tsz);
+    }
+    if (family == VF_PLANES) {
+        const size_t Kp = (size_t)(n + KCH - 1) / KCH * KCH;
+        const size_t PD = prec == LB_BF16_HILO ? 2 : 5, XD = prec == LB_BF16_HILO ? 2 : 4;
+        return align256(PD * 2 * n * Kp * 2) + align256(XD * 3 * B * Kp * 2) + align256((size_t)B * n * sizeof(cd)) +
+               align256((size_t)n * 4) + align256((size_t)B * 4);
+    }
+    return 0;
 }
 
 }  // namespace lb

@@ -1,0 +1,250 @@
+// Variant selection for the step chain and its autotuner.
+//
+// Several kernels can run the chain of one shape (n, precision, B); which is
+// fastest depends on the shape and the device, so the library lists the
+// variants that exist for a shape, picks one by a built-in rule, and lets a
+// caller time them all once (lindblad_tune) and keep the winner for the rest
+// of the process.  Every variant computes the same N steps; results differ by
+// summation order only (within each precision's documented error).
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "chain.hpp"
+
+namespace lb {
+
+namespace {
+
+typedef std::tuple<int, int, int, int> TuneKey;  // device, n, precision, B
+
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
+
+int current_device() {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return dev;
+}
+
+int tuned_variant(int n, lb_precision prec, int B) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned.find(TuneKey(current_device(), n, (int)prec, B));
+    return it == g_tuned.end() ? 0 : it->second;
+}
+
+void set_tuned(int n, lb_precision prec, int B, int variant) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const TuneKey k(current_device(), n, (int)prec, B);
+    if (variant == 0)
+        g_tuned.erase(k);
+    else
+        g_tuned[k] = variant;
+}
+
+bool is_c(lb_precision p) { return p == LB_C128 || p == LB_C64; }
+
+}  // namespace
+
+int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
+    int c = 0;
+    auto add = [&](int v) {
+        if (c < max) ids[c] = v;
+        ++c;
+    };
+    if (is_c(prec)) {
+        if (prec == LB_C128) add(VF_BASELINE * 100);
+        if (n <= kWaveChainMaxN) add(VF_WAVE * 100);
+        int kpus[8];
+        const int nk = fused_kpus(n, prec, kpus, 8);
+        for (int i = 0; i < nk; ++i) add(VF_FUSED * 100 + kpus[i]);
+        add(VF_GEMM * 100 + 1);
+        add(VF_GEMM * 100 + 2);
+        if (prec == LB_C64) add(VF_MATVEC * 100);
+    } else if (prec == LB_BF16_HILO || prec == LB_BF16_SLICED) {
+        if (n <= bf16_fused_max_n(prec)) add(VF_BF16_FUSED * 100);
+        add(VF_PLANES * 100);
+    }
+    return c;
+}
+
+// Built-in rule, from measurements on MI355X (d = 3 / 9 / 27 transmon
+// chains): the register-resident wave chain for n <= 16 at every batch size;
+// for FP64 with little work per step (B n^2 up to ~1e6) the plain per-state
+// matvec, whose step is shorter than the fused kernel's 8-wavefront MFMA
+// step; the fused on-chip chain while P fits in one CU's LDS; otherwise a
+// GEMM per step with one output tile per wavefront up to 256 states (more
+// workgroups) and two beyond, or a matvec for few states.
+int chain_heuristic(int n, lb_precision prec, int B) {
+    switch (prec) {
+        case LB_C128:
+        case LB_C64: {
+            if (n <= kWaveChainMaxN) return VF_WAVE * 100;
+            if (prec == LB_C128 && (double)B * n * n <= 1.1e6) return VF_BASELINE * 100;
+            int kpu;
+            if (fused_kpus(n, prec, &kpu, 1) == 1) return VF_FUSED * 100 + kpu;
+            if (B >= 16) return VF_GEMM * 100 + (B <= 256 ? 1 : 2);
+            return prec == LB_C128 ? VF_BASELINE * 100 : VF_MATVEC * 100;
+        }
+        case LB_BF16_HILO:
+        case LB_BF16_SLICED:
+            return n <= bf16_fused_max_n(prec) ? VF_BF16_FUSED * 100 : VF_PLANES * 100;
+        default:
+            return 0;
+    }
+}
+
+static bool variant_listed(int n, lb_precision prec, int B, int variant) {
+    int ids[32];
+    const int c = chain_variants(n, prec, B, ids, 32);
+    for (int i = 0; i < c && i < 32; ++i)
+        if (ids[i] == variant) return true;
+    return false;
+}
+
+size_t chain_ws_bytes(int n, lb_precision prec, int B, int variant) {
+    const int fam = variant_family(variant);
+    if (fam == VF_BASELINE) return align256((size_t)B * n * sizeof(cd));
+    return large_ws_bytes(fam, n, prec, B);
+}
+
+int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, int variant,
+                      Workspace *ws, hipStream_t s) {
+    if (!variant_listed(n, prec, B, variant))
+        return fail(LB_EINVAL, "chain variant " + std::to_string(variant) + " does not exist for this shape");
+    if (nsteps == 0) return LB_OK;
+    const int prm = variant_param(variant);
+    switch (variant_family(variant)) {
+        case VF_BASELINE: return chain_baseline(n, P, B, rho, nsteps, ws, s);
+        case VF_WAVE: return chain_wave(n, P, prec, B, rho, nsteps, s);
+        case VF_FUSED: return chain_fused(n, P, prec, prm, B, rho, nsteps, s);
+        case VF_BF16_FUSED: return chain_bf16_fused(n, P, prec, B, rho, nsteps, s);
+        case VF_GEMM: return chain_gemm(n, P, prec, prm, B, rho, nsteps, ws, s);
+        case VF_MATVEC: return chain_matvec(n, P, prec, B, rho, nsteps, ws, s);
+        case VF_PLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s);
+        default: return fail(LB_EINVAL, "unknown chain variant");
+    }
+}
+
+int chain_run(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+    if (nsteps == 0 || B == 0) return LB_OK;
+    int v = tuned_variant(n, prec, B);
+    if (v == 0) v = chain_heuristic(n, prec, B);
+    return chain_run_variant(n, P, prec, B, rho, nsteps, v, ws, s);
+}
+
+}  // namespace lb
+
+using namespace lb;
+
+static int check_prec(const char *who, lb_precision prec) {
+    if ((int)prec < LB_C128 || (int)prec > LB_BF16_SLICED) return fail(LB_EINVAL, std::string(who) + ": bad precision");
+    return LB_OK;
+}
+
+extern "C" int lindblad_propagate(int n, const void *P, lb_precision prec, int B, void *rho, long long nsteps,
+                                  lb_workspace *ws, hipStream_t stream) {
+    LB_TRY(validate_chain("lindblad_propagate", n, P, B, rho, nsteps));
+    LB_TRY(check_prec("lindblad_propagate", prec));
+    Workspace *w = ws_resolve(ws);
+    ws_begin(w);
+    return chain_run(n, static_cast<const cd *>(P), prec, B, static_cast<cd *>(rho), nsteps, w, stream);
+}
+
+extern "C" int lindblad_propagate_variant(int n, const void *P, lb_precision prec, int B, void *rho,
+                                          long long nsteps, int variant, lb_workspace *ws, hipStream_t stream) {
+    LB_TRY(validate_chain("lindblad_propagate_variant", n, P, B, rho, nsteps));
+    LB_TRY(check_prec("lindblad_propagate_variant", prec));
+    Workspace *w = ws_resolve(ws);
+    ws_begin(w);
+    return chain_run_variant(n, static_cast<const cd *>(P), prec, B, static_cast<cd *>(rho), nsteps, variant, w,
+                             stream);
+}
+
+extern "C" int lindblad_chain_variants(int n, lb_precision prec, int B, int *ids, int max_ids, int *count) {
+    if (n < 1 || n > 4096 || B < 1) return fail(LB_ESHAPE, "lindblad_chain_variants: bad n or B");
+    LB_TRY(check_prec("lindblad_chain_variants", prec));
+    if (!count || (max_ids > 0 && !ids) || max_ids < 0) return fail(LB_EINVAL, "lindblad_chain_variants: bad output");
+    *count = chain_variants(n, prec, B, ids, max_ids);
+    return LB_OK;
+}
+
+extern "C" int lindblad_chain_variant(int n, lb_precision prec, int B, int *variant) {
+    if (n < 1 || n > 4096 || B < 1) return fail(LB_ESHAPE, "lindblad_chain_variant: bad n or B");
+    LB_TRY(check_prec("lindblad_chain_variant", prec));
+    if (!variant) return fail(LB_EINVAL, "lindblad_chain_variant: NULL output");
+    const int v = tuned_variant(n, prec, B);
+    *variant = v ? v : chain_heuristic(n, prec, B);
+    return LB_OK;
+}
+
+extern "C" int lindblad_tune_set(int n, lb_precision prec, int B, int variant) {
+    if (n < 1 || n > 4096 || B < 1) return fail(LB_ESHAPE, "lindblad_tune_set: bad n or B");
+    LB_TRY(check_prec("lindblad_tune_set", prec));
+    if (variant != 0 && !variant_listed(n, prec, B, variant))
+        return fail(LB_EINVAL, "lindblad_tune_set: variant " + std::to_string(variant) + " does not exist for this shape");
+    set_tuned(n, prec, B, variant);
+    return LB_OK;
+}
+
+extern "C" int lindblad_tune(int n, const void *P, lb_precision prec, int B, const void *rho, long long probe_steps,
+                             int repeats, lb_workspace *ws, hipStream_t stream, int *best_variant, float *best_ms) {
+    LB_TRY(validate_chain("lindblad_tune", n, P, B, rho, probe_steps));
+    LB_TRY(check_prec("lindblad_tune", prec));
+    if (probe_steps < 1 || repeats < 1) return fail(LB_EINVAL, "lindblad_tune: probe_steps and repeats must be >= 1");
+    int ids[32];
+    const int nv = chain_variants(n, prec, B, ids, 32);
+    if (nv < 1 || nv > 32) return fail(LB_ENOTSUP, "lindblad_tune: no variants for this shape");
+    Workspace *w = ws_resolve(ws);
+    ws_begin(w);
+    const size_t xbytes = (size_t)B * n * sizeof(cd);
+    size_t need = 0;
+    for (int i = 0; i < nv; ++i) need = std::max(need, chain_ws_bytes(n, prec, B, ids[i]));
+    LB_TRY(ws_ensure(w, align256(xbytes) + need));
+    cd *x = (cd *)ws_take(w, xbytes);
+    LB_HIP(hipMemcpyAsync(x, rho, xbytes, hipMemcpyDeviceToDevice, stream));
+    const size_t base = w->used;
+    hipEvent_t e0, e1;
+    LB_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(LB_EHIP, "lindblad_tune: hipEventCreate failed");
+    }
+    int best = 0, st = LB_OK;
+    float best_t = 0.f;
+    const cd *Pc = static_cast<const cd *>(P);
+    for (int i = 0; i < nv && st == LB_OK; ++i) {
+        w->used = base;
+        st = chain_run_variant(n, Pc, prec, B, x, probe_steps, ids[i], w, stream);  // warm-up
+        float tmin = 0.f;
+        for (int r = 0; r < repeats && st == LB_OK; ++r) {  // fastest of the repeats
+            w->used = base;
+            float ms = 0.f;
+            if (hipEventRecord(e0, stream) != hipSuccess) {
+                st = fail(LB_EHIP, "lindblad_tune: hipEventRecord failed");
+                break;
+            }
+            st = chain_run_variant(n, Pc, prec, B, x, probe_steps, ids[i], w, stream);
+            if (st != LB_OK) break;
+            if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = fail(LB_EHIP, "lindblad_tune: timing failed");
+                break;
+            }
+            if (r == 0 || ms < tmin) tmin = ms;
+        }
+        if (st != LB_OK) break;
+        if (best == 0 || tmin < best_t) {
+            best = ids[i];
+            best_t = tmin;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != LB_OK) return st;
+    set_tuned(n, prec, B, best);
+    if (best_variant) *best_variant = best;
+    if (best_ms) *best_ms = best_t;
+    return LB_OK;
+}

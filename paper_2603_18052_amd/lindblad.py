@@ -42,7 +42,30 @@ SYMBOLS = {
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "lindblad_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "lindblad_chain_variants": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                               ctypes.c_int, ctypes.c_void_p]),
+    "lindblad_chain_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "lindblad_propagate_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_void_p, ctypes.c_longlong, ctypes.c_int, ctypes.c_void_p,
+                                                  ctypes.c_void_p]),
+    "lindblad_tune": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_longlong, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "lindblad_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
 }
+
+# Chain variant families (id = family * 100 + tile parameter).
+VARIANT_FAMILIES = {1: "baseline", 2: "wave", 3: "fused", 4: "bf16_fused", 5: "gemm", 6: "matvec32", 7: "planes"}
+
+
+def variant_name(v: int) -> str:
+    fam, prm = divmod(int(v), 100)
+    name = VARIANT_FAMILIES.get(fam, f"family{fam}")
+    if fam == 3:
+        return f"{name}(k{prm})"
+    if fam == 5:
+        return f"{name}(w{prm})"
+    return name
 
 
 class LindbladError(RuntimeError):
@@ -180,9 +203,57 @@ def propagate(P: torch.Tensor, rho: torch.Tensor, nsteps: int, precision="c128",
     rho = _dev(rho, name="rho")
     n = P.shape[0]
     B = rho.numel() // n
-    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    _check(lib().lindblad_propagate(n, _ptr(P), prec, B, _ptr(rho), int(nsteps), _ws(ws), _stream()))
+    _check(lib().lindblad_propagate(n, _ptr(P), _prec(precision), B, _ptr(rho), int(nsteps), _ws(ws), _stream()))
     return rho
+
+
+def _prec(precision) -> int:
+    return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+
+def chain_variants(n: int, precision="c128", B: int = 1) -> list[int]:
+    """Variant ids that exist for (n, precision, B)."""
+    ids = (ctypes.c_int * 32)()
+    cnt = ctypes.c_int()
+    _check(lib().lindblad_chain_variants(int(n), _prec(precision), int(B), ids, 32, ctypes.byref(cnt)))
+    return list(ids[:min(cnt.value, 32)])
+
+
+def chain_variant(n: int, precision="c128", B: int = 1) -> int:
+    """The variant lindblad_propagate runs for (n, precision, B) right now."""
+    v = ctypes.c_int()
+    _check(lib().lindblad_chain_variant(int(n), _prec(precision), int(B), ctypes.byref(v)))
+    return v.value
+
+
+def propagate_variant(P: torch.Tensor, rho: torch.Tensor, nsteps: int, variant: int, precision="c128",
+                      ws: Workspace | None = None):
+    P = _dev(P, name="P")
+    rho = _dev(rho, name="rho")
+    n = P.shape[0]
+    B = rho.numel() // n
+    _check(lib().lindblad_propagate_variant(n, _ptr(P), _prec(precision), B, _ptr(rho), int(nsteps), int(variant),
+                                            _ws(ws), _stream()))
+    return rho
+
+
+def tune(P: torch.Tensor, rho: torch.Tensor, precision="c128", probe_steps: int = 32, repeats: int = 3,
+         ws: Workspace | None = None):
+    """Time every chain variant for this shape on a copy of rho and keep the
+    fastest for the process.  Returns (variant id, ms per probe run)."""
+    P = _dev(P, name="P")
+    rho = _dev(rho, name="rho")
+    n = P.shape[0]
+    B = rho.numel() // n
+    v, ms = ctypes.c_int(), ctypes.c_float()
+    _check(lib().lindblad_tune(n, _ptr(P), _prec(precision), B, _ptr(rho), int(probe_steps), int(repeats), _ws(ws),
+                               _stream(), ctypes.byref(v), ctypes.byref(ms)))
+    return v.value, ms.value
+
+
+def tune_set(n: int, precision, B: int, variant: int):
+    """Record a variant for (n, precision, B) without timing; 0 clears."""
+    _check(lib().lindblad_tune_set(int(n), _prec(precision), int(B), int(variant)))
 
 
 def propagate_baseline(P: torch.Tensor, rho: torch.Tensor, nsteps: int, ws: Workspace | None = None):

@@ -68,3 +68,48 @@ def test_workspace_lifecycle(L):
     assert L.lb_workspace_bytes(h) == 0
     assert L.lb_workspace_destroy(h) == 0
     assert L.lb_workspace_create(1 << 20, None) == -1
+
+
+def test_chain_variant_lists_and_rule(L):
+    """Host-side variant bookkeeping: which kernels exist for a shape, the
+    built-in choice, and the tuning table (no kernel runs)."""
+    from paper_2603_18052_amd import lindblad as lb
+    # d = 3: every FP64 family that handles n = 9
+    v = lb.chain_variants(9, "c128", 1)
+    assert v[:2] == [100, 200]
+    assert [x for x in v if x // 100 == 3] == [301, 302, 303]  # KS = 3 k steps
+    assert {501, 502} <= set(v) and 600 not in v
+    assert 600 in lb.chain_variants(9, "c64", 1000) and 100 not in lb.chain_variants(9, "c64", 1)
+    assert lb.chain_variant(9, "c128", 1) == 200
+    # d = 9 headline: fused with the smallest k split giving at most 32 units
+    v = lb.chain_variants(81, "c128", 4096)
+    assert [x for x in v if x // 100 == 3] == [306, 308, 311]
+    assert 200 not in v
+    assert lb.chain_variant(81, "c128", 4096) == 306
+    assert lb.chain_variant(81, "c128", 64) == 100  # little work per step: plain matvec
+    assert lb.chain_variant(81, "c64", 64) == 306
+    assert lb.chain_variant(16, "c64", 4096) == 200
+    # d = 27: no fused variant; GEMM from 16 states, matvec below
+    assert not [x for x in lb.chain_variants(729, "c128", 64) if x // 100 == 3]
+    assert lb.chain_variant(729, "c128", 64) == 501
+    assert lb.chain_variant(729, "c128", 1024) == 502
+    assert lb.chain_variant(729, "c128", 1) == 100
+    assert lb.chain_variant(729, "c64", 1) == 600
+    assert 100 not in lb.chain_variants(729, "c64", 64)
+    # BF16 precisions
+    assert lb.chain_variants(81, "bf16_sliced", 16) == [400, 700]
+    assert lb.chain_variants(729, "bf16_sliced", 16) == [700]
+    assert lb.chain_variant(729, "bf16_hilo", 16) == 700
+    # tuning table: set, read back, reject a variant the shape lacks, clear
+    lb.tune_set(81, "c128", 4096, 502)
+    assert lb.chain_variant(81, "c128", 4096) == 502
+    with pytest.raises(lb.LindbladError):
+        lb.tune_set(81, "c128", 4096, 200)
+    lb.tune_set(81, "c128", 4096, 0)
+    assert lb.chain_variant(81, "c128", 4096) == 306
+    cnt = ctypes.c_int()
+    assert L.lindblad_chain_variants(0, 0, 1, None, 0, ctypes.byref(cnt)) == lb.ESHAPE
+    assert L.lindblad_chain_variants(9, 7, 1, None, 0, ctypes.byref(cnt)) == lb.EINVAL
+    assert L.lindblad_chain_variants(9, 0, 1, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 7
+    assert L.lindblad_propagate_variant(9, 1, 0, 1, 1, 5, 999, None, None) == lb.EINVAL
+    assert L.lindblad_tune(9, 1, 0, 1, 1, 0, 1, None, None, None, None) == lb.EINVAL

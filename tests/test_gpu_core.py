@@ -155,14 +155,14 @@ def states(d, B, seed):
     return np.stack([W.wishart_state(d, g) for _ in range(B)]).reshape(B, d * d)
 
 
-@pytest.mark.parametrize("which", ["fused", "baseline"])
+@pytest.mark.parametrize("which", ["default", "baseline"])
 def test_chain_c128_config1(lb, systems, which):
     """d = 3, one pure state, 1e4 steps from the oracle's P (protocol beta)."""
     c = W.config1()
     P = oracle_P(systems, 1)
     ref = oracle.propagate(P, c["rho0"].reshape(1, 9), c["nsteps"])
     x = T(c["rho0"].reshape(1, 9).copy())
-    if which == "fused":
+    if which == "default":
         lb.propagate(T(P), x, c["nsteps"], "c128")
     else:
         lb.propagate_baseline(T(P), x, c["nsteps"])
@@ -172,13 +172,13 @@ def test_chain_c128_config1(lb, systems, which):
 
 
 @pytest.mark.parametrize("B", [1, 15, 33])
-@pytest.mark.parametrize("which", ["fused", "baseline"])
+@pytest.mark.parametrize("which", ["default", "baseline"])
 def test_chain_c128_d9(lb, systems, B, which):
     P = oracle_P(systems, 2)
     X = states(9, B, 100 + B)
     ref = oracle.propagate(P, X, 1000)
     x = T(X.copy())
-    if which == "fused":
+    if which == "default":
         lb.propagate(T(P), x, 1000, "c128")
     else:
         lb.propagate_baseline(T(P), x, 1000)
@@ -257,9 +257,12 @@ def test_chain_c128_fused_shapes(lb, n):
     P = random_contraction(n, n)
     X = np.random.default_rng(n + 1).standard_normal((37, n)) + 0j
     ref = oracle.propagate(P, X, 25)
-    x = T(X.copy())
-    lb.propagate(T(P), x, 25, "c128")
-    assert oracle.rel_fro(N(x), ref) < 1e-13
+    fused = [v for v in lb.chain_variants(n, "c128", 37) if v // 100 == 3]
+    assert fused
+    for v in fused:
+        x = T(X.copy())
+        lb.propagate_variant(T(P), x, 25, v, "c128")
+        assert oracle.rel_fro(N(x), ref) < 1e-13, lb.variant_name(v)
 
 
 @pytest.mark.parametrize("n", [9, 64, 100, 121])
@@ -267,6 +270,9 @@ def test_chain_c64_fused_shapes(lb, n):
     P = random_contraction(n, n + 50)
     X = np.random.default_rng(n + 2).standard_normal((20, n)) + 0j
     ref = oracle.propagate(P, X, 25)
-    x = T(X.copy())
-    lb.propagate(T(P), x, 25, "c64")
-    assert oracle.rel_fro(N(x), ref) < 2e-5
+    fused = [v for v in lb.chain_variants(n, "c64", 20) if v // 100 == 3]
+    assert fused
+    for v in fused:
+        x = T(X.copy())
+        lb.propagate_variant(T(P), x, 25, v, "c64")
+        assert oracle.rel_fro(N(x), ref) < 2e-5, lb.variant_name(v)
