@@ -7,10 +7,14 @@
 //  2. n <= 128: one workgroup per problem runs all of that problem's steps
 //     with its P resident in LDS; each row of P x is split over G lanes that
 //     reduce with cross-lane shuffles, one barrier per step.
-//  3. larger n: problems are sorted by step count; step t launches one grid
-//     over the prefix of problems still running, 16 rows of one problem per
-//     workgroup, lanes reading P rows contiguously (coalesced).  P streams
-//     from HBM/MALL every step: this group is bandwidth-bound.
+//  3. larger n: every step reads each running problem's whole P, so this
+//     group is bound by the bandwidth of wherever the P's live.  Problems run
+//     in a sliding window: at most W at a time, longest first, each started as
+//     soon as a slot frees (W chosen so that the window's P's stay resident in
+//     the 256 MB Infinity Cache instead of streaming from HBM).  Step t
+//     launches one grid over the window, 16 rows of one problem per
+//     workgroup; rows of P are padded so every lane reads 16 bytes at a time,
+//     the state sits in registers, and each wavefront interleaves 4 rows.
 // Every problem's result is independent of the others in the batch.
 #include <algorithm>
 #include <cmath>
@@ -56,6 +60,7 @@ __global__ void __launch_bounds__(512) small_chain_kernel(int n, const Cx<T> *__
     const Cx<T> *P = Pall + (size_t)m * n * n;
     cd *rho = rhos[m];
     const long long N = nsteps[m];
+    if (N == 0) return;  // untouched (no round trip through T)
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) Ps[e] = P[e];
     for (int e = threadIdx.x; e < n; e += blockDim.x) xs[e] = {(T)rho[e].re, (T)rho[e].im};
     __syncthreads();
@@ -84,52 +89,122 @@ __global__ void __launch_bounds__(512) small_chain_kernel(int n, const Cx<T> *__
     for (int e = threadIdx.x; e < n; e += blockDim.x) rho[e] = {(double)xs[cur * n + e].re, (double)xs[cur * n + e].im};
 }
 
-// one step for the problems [0, active) of a sorted group: y = P x
+// 16-byte vectors of complex values: 2 complex FP32 or 1 complex FP64
 template <typename T>
-__global__ void __launch_bounds__(256) large_step_kernel(int n, const Cx<T> *__restrict__ Pall,
-                                                         const Cx<T> *__restrict__ X, Cx<T> *__restrict__ Y) {
-    const int m = blockIdx.y;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const Cx<T> *P = Pall + (size_t)m * n * n;
-    const Cx<T> *x = X + (size_t)m * n;
-    for (int r = 0; r < 4; ++r) {
-        const int row = blockIdx.x * 16 + wave * 4 + r;
-        if (row >= n) break;
-        const Cx<T> *Pr = P + (size_t)row * n;
-        T re = 0, im = 0;
-        for (int j = lane; j < n; j += 64) {
-            const Cx<T> p = Pr[j], v = x[j];
-            re = fma(p.re, v.re, fma(-p.im, v.im, re));
-            im = fma(p.re, v.im, fma(p.im, v.re, im));
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            re += __shfl_xor(re, off);
-            im += __shfl_xor(im, off);
-        }
-        if (lane == 0) Y[(size_t)m * n + row] = {re, im};
-    }
-}
+struct Vec;
+template <>
+struct Vec<float> {
+    typedef float v __attribute__((ext_vector_type(4)));
+    static constexpr int C = 2;
+};
+template <>
+struct Vec<double> {
+    typedef double v __attribute__((ext_vector_type(2)));
+    static constexpr int C = 1;
+};
 
+// P rows converted to T and zero padded to Kp columns: PT[m][i][Kp]
 template <typename T>
-__global__ void load_states_kernel(int n, int M, cd *const *__restrict__ rhos, Cx<T> *__restrict__ X) {
-    const long long total = (long long)n * M;
+__global__ void convert_pad_kernel(int n, int Kp, int M, const cd *__restrict__ src, Cx<T> *__restrict__ dst) {
+    const long long total = (long long)M * n * Kp;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
-        const long long m = e / n, i = e - m * n;
-        const cd v = rhos[m][i];
-        X[e] = {(T)v.re, (T)v.im};
+        const long long r = e / Kp;  // m * n + i
+        const int k = (int)(e - r * Kp);
+        const cd v = k < n ? src[r * n + k] : cd{0.0, 0.0};
+        dst[e] = {(T)v.re, (T)v.im};
+    }
+}
+
+// y = P x for the window's problems at global step t.  Problem m started at
+// step start[m]; its local step parity picks the ping-pong buffer.  Lane l
+// holds x[(l + 64 i) VEC .. + VEC - 1] for i < NJ (Kp = 64 VEC NJ, padding
+// zero), each wavefront 4 rows.
+template <typename T, int NJ>
+__global__ void __launch_bounds__(256) window_step_kernel(int n, int Kp, const Cx<T> *__restrict__ PT,
+                                                          const int *__restrict__ list,
+                                                          const long long *__restrict__ start, long long t,
+                                                          Cx<T> *__restrict__ X0, Cx<T> *__restrict__ X1) {
+    typedef typename Vec<T>::v V;
+    constexpr int VC = Vec<T>::C;
+    const int m = list[blockIdx.y];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool odd = ((t - start[m]) & 1) != 0;
+    const Cx<T> *x = (odd ? X1 : X0) + (size_t)m * Kp;
+    Cx<T> *y = (odd ? X0 : X1) + (size_t)m * Kp;
+    const Cx<T> *P = PT + (size_t)m * n * Kp;
+    constexpr int NR = NJ > 0 ? NJ : 1;
+    V xv[NR];
+    if (NJ > 0) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) xv[i] = *reinterpret_cast<const V *>(x + (size_t)(lane + 64 * i) * VC);
+    }
+    const int rb = blockIdx.x * 16 + wave * 4;
+    const Cx<T> *prow[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) prow[q] = P + (size_t)(rb + q < n ? rb + q : n - 1) * Kp + (size_t)lane * VC;
+    T re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
+    auto mac = [&](const V &xq, int i) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const V p = *reinterpret_cast<const V *>(prow[q] + (size_t)64 * VC * i);
+#pragma unroll
+            for (int c = 0; c < VC; ++c) {
+                const T pr = p[2 * c], pi = p[2 * c + 1], xr = xq[2 * c], xi = xq[2 * c + 1];
+                re[q] = fma(pr, xr, fma(-pi, xi, re[q]));
+                im[q] = fma(pr, xi, fma(pi, xr, im[q]));
+            }
+        }
+    };
+    if (NJ > 0) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) mac(xv[i], i);
+    } else {  // wide rows: the state is re-read from cache
+        const int nj = Kp / (64 * VC);
+        for (int i = 0; i < nj; ++i) mac(*reinterpret_cast<const V *>(x + (size_t)(lane + 64 * i) * VC), i);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            re[q] += __shfl_xor(re[q], off);
+            im[q] += __shfl_xor(im[q], off);
+        }
+    }
+    if (lane < 4) {
+        T r = re[0], i = im[0];
+#pragma unroll
+        for (int q = 1; q < 4; ++q)
+            if (lane == q) {
+                r = re[q];
+                i = im[q];
+            }
+        if (rb + lane < n) y[rb + lane] = {r, i};
     }
 }
 
 template <typename T>
-__global__ void store_states_kernel(int n, int M, const Cx<T> *__restrict__ X0, const Cx<T> *__restrict__ X1,
+__global__ void load_states_kernel(int n, int Kp, int M, cd *const *__restrict__ rhos, Cx<T> *__restrict__ X0,
+                                   Cx<T> *__restrict__ X1) {
+    const long long total = (long long)Kp * M;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long m = e / Kp, i = e - m * Kp;
+        const cd v = i < n ? rhos[m][i] : cd{0.0, 0.0};
+        X0[e] = {(T)v.re, (T)v.im};
+        X1[e] = {(T)0, (T)0};
+    }
+}
+
+template <typename T>
+__global__ void store_states_kernel(int n, int Kp, int M, const Cx<T> *__restrict__ X0, const Cx<T> *__restrict__ X1,
                                     const long long *__restrict__ nsteps, cd *const *__restrict__ rhos) {
     const long long total = (long long)n * M;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         const long long m = e / n, i = e - m * n;
-        const Cx<T> v = (nsteps[m] & 1) ? X1[e] : X0[e];
+        if (nsteps[m] == 0) continue;  // untouched (no round trip through T)
+        const Cx<T> v = (nsteps[m] & 1) ? X1[m * Kp + i] : X0[m * Kp + i];
         rhos[m][i] = {(double)v.re, (double)v.im};
     }
 }
@@ -140,11 +215,76 @@ static int grid1(long long work) {
     return (int)(g < 1 ? 1 : g);
 }
 
+// Byte budget of the window's propagators: they should stay resident in the
+// 256 MB Infinity Cache together with the states and the rest of the working set.
+constexpr size_t kWindowBytes = 192ull << 20;
+
+// Supported register tiles of the step kernel (x values per lane, in 16-byte
+// vectors); wider rows use the kernel's cache-read path (NJ = 0).
+static int window_nj(int n, int vc) {
+    const int need = (n + 64 * vc - 1) / (64 * vc);
+    for (int c : {1, 2, 3, 4, 6, 8, 12, 16})
+        if (need <= c) return c;
+    return 0;
+}
+
+template <typename T>
+static int window_launch(int nj, dim3 grid, int n, int Kp, const Cx<T> *PT, const int *list, const long long *start,
+                         long long t, Cx<T> *X0, Cx<T> *X1, hipStream_t s) {
+    switch (nj) {
+        case 1: window_step_kernel<T, 1><<<grid, 256, 0, s>>>(n, Kp, PT, list, start, t, X0, X1); break;
+        case 2: window_step_kernel<T, 2><<<grid, 256, 0, s>>>(n, Kp, PT, list, start, t, X0, X1); break;
+        case 3: window_step_kernel<T, 3><<<grid, 256, 0, s>>>(n, Kp, PT, list, start, t, X0, X1); break;
+        case 4: window_step_kernel<T, 4><<<grid, 256, 0, s>>>(n, Kp, PT, list, start, t, X0, X1); break;
+        case 6: window_step_kernel<T, 6><<<grid, 256, 0, s>>>(n, Kp, PT, list, start, t, X0, X1); break;
+        case 8: window_step_kernel<T, 8><<<grid, 256, 0, s>>>(n, Kp, PT, list, start, t, X0, X1); break;
+        case 12: window_step_kernel<T, 12><<<grid, 256, 0, s>>>(n, Kp, PT, list, start, t, X0, X1); break;
+        case 16: window_step_kernel<T, 16><<<grid, 256, 0, s>>>(n, Kp, PT, list, start, t, X0, X1); break;
+        default: window_step_kernel<T, 0><<<grid, 256, 0, s>>>(n, Kp, PT, list, start, t, X0, X1); break;
+    }
+    return LB_OK;
+}
+
+// Sliding-window schedule: problems (sorted by step count, longest first)
+// take the slot that frees earliest among W.  Returns the start step of each
+// problem and the segments [t_k, t_{k+1}) of constant running set.
+struct Window {
+    std::vector<long long> start, seg_t;   // seg_t: segment boundaries (size segs + 1)
+    std::vector<int> seg_off, list;        // running problems of segment k: list[seg_off[k] .. seg_off[k+1])
+};
+
+static Window window_schedule(const std::vector<long long> &steps, int W) {
+    const int M = (int)steps.size();
+    Window w;
+    w.start.assign(M, 0);
+    std::vector<long long> slot(W, 0);
+    std::vector<long long> ev;
+    for (int i = 0; i < M; ++i) {
+        if (steps[i] == 0) continue;
+        const int k = (int)(std::min_element(slot.begin(), slot.end()) - slot.begin());
+        w.start[i] = slot[k];
+        slot[k] += steps[i];
+        ev.push_back(w.start[i]);
+        ev.push_back(w.start[i] + steps[i]);
+    }
+    std::sort(ev.begin(), ev.end());
+    ev.erase(std::unique(ev.begin(), ev.end()), ev.end());
+    for (size_t k = 0; k + 1 < ev.size(); ++k) {
+        w.seg_t.push_back(ev[k]);
+        w.seg_off.push_back((int)w.list.size());
+        for (int i = 0; i < M; ++i)
+            if (steps[i] > 0 && w.start[i] <= ev[k] && ev[k] < w.start[i] + steps[i]) w.list.push_back(i);
+    }
+    if (!ev.empty()) w.seg_t.push_back(ev.back());
+    w.seg_off.push_back((int)w.list.size());
+    return w;
+}
+
 template <typename T>
 static int run_group(int n, const std::vector<const lb_problem *> &probs, double theta, Workspace *ws, hipStream_t s) {
     const int M = (int)probs.size();
     const size_t nn = (size_t)n * n;
-    // largest step count first: the running problems are always a prefix
+    // longest first (the window schedule takes them in this order)
     std::vector<int> order(M);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a]->nsteps > probs[b]->nsteps; });
@@ -159,29 +299,43 @@ static int run_group(int n, const std::vector<const lb_problem *> &probs, double
         steps[i] = p->nsteps;
         dts[i] = p->dt;
     }
+    const size_t lds = (nn + 2 * (size_t)n) * sizeof(Cx<T>);
+    const bool small = n <= 128 && lds <= 160 * 1024;
+    const int VC = Vec<T>::C;
+    const int nj = window_nj(n, VC);
+    const int Kp = small ? n : (nj > 0 ? nj : (n + 64 * VC - 1) / (64 * VC)) * 64 * VC;
+    const size_t prow = (size_t)Kp * sizeof(Cx<T>);
+    Window win;
+    if (!small) {
+        long long W = (long long)(kWindowBytes / ((size_t)n * prow));
+        W = std::max(1LL, std::min<long long>(W, M));
+        win = window_schedule(steps, (int)W);
+    }
     const size_t mats = align256(nn * sizeof(cd) * M);
-    const size_t need = 2 * mats + align256(nn * sizeof(Cx<T>) * M) + 3 * align256(M * sizeof(void *)) +
-                        2 * align256((size_t)n * M * sizeof(Cx<T>)) + build_workspace_bytes(n, M);
+    const size_t need = 2 * mats + align256((size_t)n * prow * M) + 3 * align256(M * sizeof(void *)) +
+                        align256(M * sizeof(long long)) + align256(win.list.size() * sizeof(int) + 4) +
+                        2 * align256((size_t)Kp * M * sizeof(Cx<T>)) + build_workspace_bytes(n, M);
     LB_TRY(ws_ensure(ws, need));
     const size_t mark = ws->used;
     cd *Lg = (cd *)ws_take(ws, nn * sizeof(cd) * M);
     cd *P = (cd *)ws_take(ws, nn * sizeof(cd) * M);
-    Cx<T> *PT = (Cx<T> *)ws_take(ws, nn * sizeof(Cx<T>) * M);
+    Cx<T> *PT = (Cx<T> *)ws_take(ws, (size_t)n * prow * M);
     const cd **d_srcs = (const cd **)ws_take(ws, M * sizeof(void *));
     cd **d_rhos = (cd **)ws_take(ws, M * sizeof(void *));
     long long *d_steps = (long long *)ws_take(ws, M * sizeof(long long));
-    Cx<T> *X0 = (Cx<T> *)ws_take(ws, (size_t)n * M * sizeof(Cx<T>));
-    Cx<T> *X1 = (Cx<T> *)ws_take(ws, (size_t)n * M * sizeof(Cx<T>));
+    long long *d_start = (long long *)ws_take(ws, M * sizeof(long long));
+    int *d_list = (int *)ws_take(ws, win.list.size() * sizeof(int) + 4);
+    Cx<T> *X0 = (Cx<T> *)ws_take(ws, (size_t)Kp * M * sizeof(Cx<T>));
+    Cx<T> *X1 = (Cx<T> *)ws_take(ws, (size_t)Kp * M * sizeof(Cx<T>));
     LB_HIP(hipMemcpyAsync(d_srcs, srcs.data(), M * sizeof(void *), hipMemcpyHostToDevice, s));
     LB_HIP(hipMemcpyAsync(d_rhos, rhos.data(), M * sizeof(void *), hipMemcpyHostToDevice, s));
     LB_HIP(hipMemcpyAsync(d_steps, steps.data(), M * sizeof(long long), hipMemcpyHostToDevice, s));
     gather_kernel<<<grid1((long long)nn * M), 256, 0, s>>>((long long)nn, d_srcs, Lg, M);
     LB_TRY(check_launch("gather"));
     LB_TRY(build_propagators(n, M, Lg, dts.data(), theta, P, nullptr, ws, s));
-    convert_kernel<T><<<grid1((long long)nn * M), 256, 0, s>>>((long long)nn * M, P, PT);
-    LB_TRY(check_launch("convert"));
-    const size_t lds = (nn + 2 * (size_t)n) * sizeof(Cx<T>);
-    if (n <= 128 && lds <= 160 * 1024) {
+    if (small) {
+        convert_kernel<T><<<grid1((long long)nn * M), 256, 0, s>>>((long long)nn * M, P, PT);
+        LB_TRY(check_launch("convert"));
         static bool attr = false;
         if (!attr) {
             LB_HIP(hipFuncSetAttribute((const void *)small_chain_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -193,19 +347,22 @@ static int run_group(int n, const std::vector<const lb_problem *> &probs, double
         small_chain_kernel<T><<<M, threads, lds, s>>>(n, PT, d_rhos, d_steps);
         LB_TRY(check_launch("small_chain"));
     } else {
-        load_states_kernel<T><<<grid1((long long)n * M), 256, 0, s>>>(n, M, d_rhos, X0);
+        convert_pad_kernel<T><<<grid1((long long)M * n * Kp), 256, 0, s>>>(n, Kp, M, P, PT);
+        LB_TRY(check_launch("convert_pad"));
+        LB_HIP(hipMemcpyAsync(d_start, win.start.data(), M * sizeof(long long), hipMemcpyHostToDevice, s));
+        if (!win.list.empty())
+            LB_HIP(hipMemcpyAsync(d_list, win.list.data(), win.list.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        load_states_kernel<T><<<grid1((long long)Kp * M), 256, 0, s>>>(n, Kp, M, d_rhos, X0, X1);
         LB_TRY(check_launch("load_states"));
         const int rowblocks = (n + 15) / 16;
-        int active = M;
-        for (long long t = 0; t < steps[0]; ++t) {
-            while (active > 0 && steps[active - 1] <= t) --active;
-            dim3 grid(rowblocks, active);
-            const Cx<T> *x = (t & 1) ? X1 : X0;
-            Cx<T> *y = (t & 1) ? X0 : X1;
-            large_step_kernel<T><<<grid, 256, 0, s>>>(n, PT, x, y);
+        for (size_t k = 0; k + 1 < win.seg_t.size(); ++k) {
+            const int cnt = win.seg_off[k + 1] - win.seg_off[k];
+            const dim3 grid(rowblocks, cnt);
+            for (long long t = win.seg_t[k]; t < win.seg_t[k + 1]; ++t)
+                window_launch<T>(nj, grid, n, Kp, PT, d_list + win.seg_off[k], d_start, t, X0, X1, s);
         }
-        LB_TRY(check_launch("large_step"));
-        store_states_kernel<T><<<grid1((long long)n * M), 256, 0, s>>>(n, M, X0, X1, d_steps, d_rhos);
+        LB_TRY(check_launch("window_step"));
+        store_states_kernel<T><<<grid1((long long)n * M), 256, 0, s>>>(n, Kp, M, X0, X1, d_steps, d_rhos);
         LB_TRY(check_launch("store_states"));
     }
     LB_HIP(hipStreamSynchronize(s));  // host arrays above go out of scope

@@ -94,16 +94,43 @@ __global__ void __launch_bounds__(256) matvec_kernel(int n, const cd *__restrict
     if (lane == 0) y[row] = {re, im};
 }
 
-// y = P^dag x: thread j sums conj(P[i][j]) x[i] over i (coalesced across j)
-__global__ void __launch_bounds__(256) matvec_h_kernel(int n, const cd *__restrict__ P, const cd *__restrict__ x,
-                                                       cd *__restrict__ y) {
+// y = P^dag x in two passes with a fixed summation order.  Pass 1: workgroup
+// (jb, r) owns 64 columns j and the r-th of HR row ranges; its four
+// wavefronts take every fourth row of the range, lanes run along j (rows of P
+// are read contiguously), and the four partial sums meet in LDS.  Pass 2 sums
+// the HR partials of each column in order.
+constexpr int HR = 16;  // row ranges of the adjoint matvec
+
+__global__ void __launch_bounds__(256) matvec_h_partial_kernel(int n, const cd *__restrict__ P,
+                                                               const cd *__restrict__ x, cd *__restrict__ part) {
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
+    const int r = blockIdx.y;
+    const int i0 = (int)(((long long)n * r) / HR), i1 = (int)(((long long)n * (r + 1)) / HR);
+    double re = 0.0, im = 0.0;
+    if (j < n) {
+        for (int i = i0 + g; i < i1; i += 4) {
+            const cd p = P[(size_t)i * n + j], v = x[i];
+            re = fma(p.re, v.re, fma(p.im, v.im, re));  // conj(p) v
+            im = fma(p.re, v.im, fma(-p.im, v.re, im));
+        }
+    }
+    __shared__ double sr[4][64], si[4][64];
+    sr[g][c] = re;
+    si[g][c] = im;
+    __syncthreads();
+    if (g == 0 && j < n)
+        part[(size_t)r * n + j] = {((sr[0][c] + sr[1][c]) + sr[2][c]) + sr[3][c],
+                                   ((si[0][c] + si[1][c]) + si[2][c]) + si[3][c]};
+}
+
+__global__ void __launch_bounds__(256) matvec_h_reduce_kernel(int n, const cd *__restrict__ part, cd *__restrict__ y) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     double re = 0.0, im = 0.0;
-    for (int i = 0; i < n; ++i) {
-        const cd p = P[(size_t)i * n + j], v = x[i];
-        re = fma(p.re, v.re, fma(p.im, v.im, re));   // conj(p) v
-        im = fma(p.re, v.im, fma(-p.im, v.re, im));
+    for (int r = 0; r < HR; ++r) {
+        re += part[(size_t)r * n + j].re;
+        im += part[(size_t)r * n + j].im;
     }
     y[j] = {re, im};
 }
@@ -336,7 +363,8 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
     const int Mc = M < 16 ? M : 16;  // slices per batched chunk
     const int nblk = (int)((nn + CHUNK - 1) / CHUNK);
     // ---- reservation: persistent buffers + the larger of the chunk phases
-    size_t persistent = align256((size_t)(M + 1) * n * sizeof(cd)) * 2 + align256((size_t)C * matb) +
+    size_t persistent = align256((size_t)(M + 1) * n * sizeof(cd)) * 2 + align256((size_t)HR * n * sizeof(cd)) +
+                        align256((size_t)C * matb) +
                         align256(sizeof(double)) + align256((size_t)nblk * Mc * C * sizeof(double)) +
                         (keepP ? align256((size_t)M * matb) : 0);
     size_t chunkp = 2 * align256((size_t)Mc * matb);  // generators + propagators of a chunk
@@ -347,6 +375,7 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
     LB_TRY(ws_ensure(ws, total));
     cd *xs = (cd *)ws_take(ws, (size_t)(M + 1) * n * sizeof(cd));
     cd *lams = (cd *)ws_take(ws, (size_t)(M + 1) * n * sizeof(cd));
+    cd *hpart = (cd *)ws_take(ws, (size_t)HR * n * sizeof(cd));
     cd *LcT = (cd *)ws_take(ws, (size_t)C * matb);
     double *d_F = (double *)ws_take(ws, sizeof(double));
     double *partial = (double *)ws_take(ws, (size_t)nblk * Mc * C * sizeof(double));
@@ -389,9 +418,11 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
         const int m0 = ci * Mc, mc = M - m0 < Mc ? M - m0 : Mc;
         const cd *Pch = keepP ? Pall + (size_t)m0 * nn : Pc;
         if (!keepP) LB_TRY(chunk_props(m0, mc, Pc));
-        for (int m = mc - 1; m >= 0; --m)
-            matvec_h_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, Pch + (size_t)m * nn, lams + (size_t)(m0 + m + 1) * n,
-                                                           lams + (size_t)(m0 + m) * n);
+        for (int m = mc - 1; m >= 0; --m) {
+            matvec_h_partial_kernel<<<dim3((n + 63) / 64, HR), 256, 0, s>>>(n, Pch + (size_t)m * nn,
+                                                                            lams + (size_t)(m0 + m + 1) * n, hpart);
+            matvec_h_reduce_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, hpart, lams + (size_t)(m0 + m) * n);
+        }
         LB_TRY(check_launch("matvec_h"));
         // generators of the chunk, then the batched Frechet derivatives
         LB_TRY(generators_launch(n, mc, C, L0, Lc, u + (size_t)m0 * C, Lg, s));
