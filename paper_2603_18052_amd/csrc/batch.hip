@@ -17,6 +17,7 @@
 //     the state sits in registers, and each wavefront interleaves 4 rows.
 // Every problem's result is independent of the others in the batch.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -218,6 +219,7 @@ static int grid1(long long work) {
 // Byte budget of the window's propagators: they should stay resident in the
 // 256 MB Infinity Cache together with the states and the rest of the working set.
 constexpr size_t kWindowBytes = 192ull << 20;
+static std::atomic<size_t> g_window_bytes{kWindowBytes};
 
 // Supported register tiles of the step kernel (x values per lane, in 16-byte
 // vectors); wider rows use the kernel's cache-read path (NJ = 0).
@@ -307,7 +309,7 @@ static int run_group(int n, const std::vector<const lb_problem *> &probs, double
     const size_t prow = (size_t)Kp * sizeof(Cx<T>);
     Window win;
     if (!small) {
-        long long W = (long long)(kWindowBytes / ((size_t)n * prow));
+        long long W = (long long)(g_window_bytes.load() / ((size_t)n * prow));
         W = std::max(1LL, std::min<long long>(W, M));
         win = window_schedule(steps, (int)W);
     }
@@ -408,5 +410,10 @@ extern "C" int lindblad_batch_run(const lb_problem *probs, int nprob, lb_precisi
                                   : mb::run_group<double>(n, part, theta, w, stream));
         }
     }
+    return LB_OK;
+}
+
+extern "C" int lindblad_batch_set_window(size_t bytes) {
+    mb::g_window_bytes.store(bytes ? bytes : mb::kWindowBytes);
     return LB_OK;
 }

@@ -52,6 +52,7 @@ SYMBOLS = {
                                      ctypes.c_longlong, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]),
     "lindblad_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "lindblad_batch_set_window": (ctypes.c_int, [ctypes.c_size_t]),
 }
 
 # Chain variant families (id = family * 100 + tile parameter).
@@ -279,6 +280,11 @@ def grape_gradient(L0, Lc, u, dt, x0, w, theta=0.25, checkpoint_bytes=0, ws: Wor
     _check(lib().grape_gradient(n, M, C, _ptr(L0), _ptr(Lc), _ptr(u), float(dt), float(theta), _ptr(x0), _ptr(w),
                                 ctypes.byref(F), _ptr(grad), int(checkpoint_bytes), _ws(ws), _stream()))
     return F.value, grad
+
+
+def batch_set_window(nbytes: int = 0):
+    """Propagator byte budget of the mixed batch's sliding window (0 = default)."""
+    _check(lib().lindblad_batch_set_window(int(nbytes)))
 
 
 def batch_run(problems, precision="c64", theta: float = 0.25, ws: Workspace | None = None):

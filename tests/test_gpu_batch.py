@@ -26,6 +26,7 @@ def lb():
 def problems():
     probs = W.mixed_batch(nprob=9, nmin=0, nmax=150)
     probs[4]["nsteps"] = 0
+    probs[5]["nsteps"] = 0  # d = 27
     for p in probs:
         p["L"] = oracle.liouvillian(p["H"], p["Lk"]) if p["d"] < 27 else None
     return probs
@@ -69,7 +70,10 @@ def test_batch_c64_error_and_independence(lb, problems):
         d = p["d"]
         L = p["L"] if p["L"] is not None else kron_L(p["H"], p["Lk"])
         ref = oracle.propagate(oracle.propagator(L, p["dt"]), p["rho0"].reshape(1, -1), p["nsteps"])[0]
-        td = oracle.trace_distance(q["rho"].cpu().numpy().reshape(d, d), ref.reshape(d, d))
+        got = q["rho"].cpu().numpy()
+        if p["nsteps"] == 0:
+            assert np.array_equal(got, p["rho0"].reshape(-1))
+        td = oracle.trace_distance(got.reshape(d, d), ref.reshape(d, d))
         assert td < 1e-4, (d, p["nsteps"], td)
         # the same problem alone gives the same bits
         single = as_gpu([p])
@@ -85,3 +89,46 @@ def test_batch_validation(lb):
                      "bf16_sliced")
     assert e.value.status == lb.ENOTSUP
     lb.batch_run([])
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_batch_sliding_window(lb, prec):
+    """Large-n problems (d = 12 and d = 27, past the one-workgroup limit) with a
+    window budget that admits only one or two propagators at a time: every
+    problem starts late except the first, and the results must be bitwise
+    those of the all-at-once schedule and match the oracle."""
+    g = np.random.default_rng(77)
+    probs = []
+    for i, (d, N) in enumerate([(12, 40), (12, 7), (12, 0), (12, 23), (12, 40), (27, 9), (27, 15), (27, 4)]):
+        A = g.standard_normal((d, d)) + 1j * g.standard_normal((d, d))
+        H = 0.05 * (A + A.conj().T)
+        Lk = (0.03 * (g.standard_normal((d, d)) + 1j * g.standard_normal((d, d))))[None]
+        probs.append(dict(d=d, H=H, Lk=Lk, dt=0.5, nsteps=N, rho0=W.wishart_state(d, g)))
+    def run(window):
+        lb.batch_set_window(window)
+        gp = [dict(d=p["d"], L=T(kron_L(p["H"], p["Lk"])), dt=p["dt"], nsteps=p["nsteps"],
+                   rho=T(p["rho0"].reshape(-1).copy())) for p in probs]
+        lb.batch_run(gp, prec)
+        return [q["rho"].cpu().numpy() for q in gp]
+    try:
+        narrow = run(1)          # one problem at a time
+        two = run(9 << 20)       # d = 27 in FP64 / FP32: one or two at a time; d = 12 several
+        wide = run(0)            # default budget: all at once here
+    finally:
+        lb.batch_set_window(0)
+    tol = 1e-12 if prec == "c128" else 1e-4
+    for p, a, b, c in zip(probs, narrow, two, wide):
+        assert np.array_equal(a, c) and np.array_equal(b, c), (p["d"], p["nsteps"])
+        if p["nsteps"] == 0:
+            assert np.array_equal(c, p["rho0"].reshape(-1))
+        L = kron_L(p["H"], p["Lk"])
+        # d = 27: the chain against the oracle's chain on the library's own
+        # build (the build's parity is tested elsewhere; an oracle build at
+        # n = 729 costs tens of seconds)
+        P = oracle.propagator(L, p["dt"]) if p["d"] < 27 else lb.propagator(T(L), p["dt"]).cpu().numpy()
+        ref = oracle.propagate(P, p["rho0"].reshape(1, -1), p["nsteps"])[0]
+        if prec == "c128":
+            assert oracle.rel_fro(c, ref) < tol
+        else:
+            d = p["d"]
+            assert oracle.trace_distance(c.reshape(d, d), ref.reshape(d, d)) < tol
