@@ -129,8 +129,9 @@ int lindblad_propagator(int n, int M, const void *L, const double *dt, double th
  * n <= 16 (LB_C128, LB_C64); the plain per-state matvec for LB_C128 when
  * B n^2 <= 1.1e6; the whole chain in one launch with P on chip while it fits
  * one compute unit's LDS (n <= 84 LB_C128, 124 LB_C64, 85 LB_BF16_SLICED,
- * 96 LB_BF16_HILO); beyond that one MFMA GEMM launch per step (B >= 16) or
- * a per-state matvec (B < 16). */
+ * 96 LB_BF16_HILO; the SIMD-balanced layout for 81 <= n <= 84 / 96); beyond
+ * that one MFMA GEMM launch per step (B >= 16) or a per-state matvec
+ * (B < 16). */
 int lindblad_propagate(int n, const void *P, lb_precision prec, int B, void *rho, long long nsteps,
                        lb_workspace *ws, hipStream_t stream);
 
@@ -152,6 +153,8 @@ int lindblad_propagate_baseline(int n, const void *P, int B, void *rho, long lon
  *   500 + w   one MFMA GEMM launch per step, w = 16-output tiles per wavefront
  *   600       per-state FP32 matvec, one launch per step (LB_C64 only)
  *   700       one BF16 plane-GEMM launch per step (BF16 precisions)
+ *   800       whole chain in one launch, the two wavefronts of every SIMD
+ *             balanced (81 <= n <= 84 LB_C128, <= 96 LB_C64)
  * Variants of one shape differ only in summation order. */
 
 /* Variants that exist for (n, prec, B): up to max_ids ids written to the HOST

@@ -294,6 +294,163 @@ __global__ void __launch_bounds__(CW * 64) fused_chain_kernel(int n, int kparts,
 
 static const size_t kLdsLimit = 160 * 1024;
 
+// ------------------------------------------------ SIMD-balanced fused chain
+// Same on-chip chain for 81 <= n <= 96 (six 16-row tiles, KS = n/4 k steps),
+// with the work laid out so that the two wavefronts sharing a SIMD (w and
+// w + 4) issue the same number of MFMAs and no wavefront runs zero-padded k
+// steps beyond a fraction of one: SIMD s owns tile s plus half of tile
+// 4 + s/2.  Wavefront s takes k steps [0, LA) of tile s; wavefront s + 4 the
+// rest of tile s, [LA, KS), and its half [H (s & 1), H (s & 1) + H) of the
+// extra tile.  Every wavefront holds NF = LA fragments and runs one uniform,
+// branch-free MFMA loop into two accumulator pairs (fragments [0, LB1) and
+// [LB1, NF)); only the partial write differs.
+//
+// Each output tile t ends a step as two partials, slots 2t and 2t + 1, and
+// the next step reads its MFMA B operands straight from them (x = sum of the
+// two slots): no separate reduction pass, one barrier per step.  The slots
+// are double-buffered so that a wavefront writing step t+1's partials never
+// overwrites what a slower one still reads for step t+1.  Rows past n hold
+// finite values that only ever meet zero fragments.
+template <int KS>
+struct Balanced {
+    static constexpr int H = (KS + 1) / 2;         // k steps of a half extra tile
+    static constexpr int LA = (KS + H + 1) / 2;    // wavefront s: tile s, [0, LA)
+    static constexpr int LB1 = KS - LA;            // wavefront s + 4: tile s, [LA, KS)
+    static constexpr int NF = LA;                  // fragments per wavefront
+    static_assert(LB1 >= 1 && LB1 + H <= NF, "layout");
+};
+
+constexpr int kBalSlots = 12;                        // 6 tiles x 2 partials
+constexpr int kBalBuf = kBalSlots * 2 * 256;         // one buffer: [slot][re, im][256]
+
+template <typename T, int KS>
+__global__ void __launch_bounds__(CW * 64) balanced_chain_kernel(int n, const cd *__restrict__ P, int B,
+                                                                 cd *__restrict__ rho, long long nsteps) {
+    typedef typename Mfma<T>::acc acc_t;
+    typedef Balanced<KS> L;
+    constexpr int Kp = 4 * KS;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *part = reinterpret_cast<T *>(smem_raw);  // [2][kBalSlots][2][256]
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int simd = wave & 3;
+    const bool second = wave >= 4;
+    const int b0 = blockIdx.x * NS;
+
+    T fr[L::NF], fi[L::NF];
+    int xoff[L::NF];  // offset of the slot-2t value of the X fragment in a buffer
+#pragma unroll
+    for (int kk = 0; kk < L::NF; ++kk) {
+        int tile, ks, kend;
+        if (!second) {
+            tile = simd, ks = kk, kend = L::LA;
+        } else if (kk < L::LB1) {
+            tile = simd, ks = L::LA + kk, kend = KS;
+        } else {
+            tile = 4 + (simd >> 1), ks = (simd & 1) * L::H + (kk - L::LB1);
+            kend = (simd & 1) * L::H + L::H < KS ? (simd & 1) * L::H + L::H : KS;
+        }
+        int row = tile * 16 + (lane & 15);
+        row = row < n ? row : n - 1;  // rows past n only feed discarded outputs
+        int k = ks * 4 + (lane >> 4);
+        cd v = {0.0, 0.0};
+        if (ks < kend && k < n) v = P[(size_t)row * n + k];
+        fr[kk] = (T)v.re;
+        fi[kk] = (T)v.im;
+        k = k < Kp ? k : Kp - 1;  // a finite X row times a zero fragment
+        xoff[kk] = (2 * (k >> 4)) * 512 + (k & 15) * 16 + (lane & 15);
+    }
+    // initial states: slot 2t holds x, slot 2t + 1 zero (buffer 0)
+    for (int e = tid; e < kBalBuf; e += CW * 64) part[e] = (T)0;
+    __syncthreads();
+    for (int e = tid; e < Kp * NS; e += CW * 64) {
+        const int k = e / NS, sidx = e - k * NS;
+        cd v = {0.0, 0.0};
+        if (k < n && b0 + sidx < B) v = rho[(size_t)(b0 + sidx) * n + k];
+        const int o = (2 * (k >> 4)) * 512 + (k & 15) * 16 + sidx;
+        part[o] = (T)v.re;
+        part[o + 256] = (T)v.im;
+    }
+    __syncthreads();
+
+    for (long long t = 0; t < nsteps; ++t) {
+        const T *cur = part + (t & 1) * kBalBuf;
+        T *nxt = part + ((t & 1) ^ 1) * kBalBuf;
+        acc_t ar[2], ai[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) ar[j] = ai[j] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < L::NF; ++kk) {
+            const int j = kk < L::LB1 ? 0 : 1;
+            const T *c = cur + xoff[kk];
+            const T xr = c[0] + c[512], xi = c[256] + c[768];
+            ar[j] = Mfma<T>::mma(fr[kk], xr, ar[j]);
+            ai[j] = Mfma<T>::mma(fr[kk], xi, ai[j]);
+            ar[j] = Mfma<T>::mma(fi[kk], -xi, ar[j]);
+            ai[j] = Mfma<T>::mma(fi[kk], xr, ai[j]);
+        }
+        if (!second) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = Mfma<T>::row(lane, r) * 16 + (lane & 15);
+                nxt[(2 * simd) * 512 + o] = ar[0][r] + ar[1][r];
+                nxt[(2 * simd) * 512 + 256 + o] = ai[0][r] + ai[1][r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = Mfma<T>::row(lane, r) * 16 + (lane & 15);
+                nxt[(2 * simd + 1) * 512 + o] = ar[0][r];
+                nxt[(2 * simd + 1) * 512 + 256 + o] = ai[0][r];
+                nxt[(8 + simd) * 512 + o] = ar[1][r];
+                nxt[(8 + simd) * 512 + 256 + o] = ai[1][r];
+            }
+        }
+        __syncthreads();
+    }
+    const T *fin = part + (nsteps & 1) * kBalBuf;
+    for (int e = tid; e < n * NS; e += CW * 64) {
+        const int sidx = e / n, k = e - sidx * n;
+        const int o = (2 * (k >> 4)) * 512 + (k & 15) * 16 + sidx;
+        if (b0 + sidx < B) rho[(size_t)(b0 + sidx) * n + k] = {(double)(fin[o] + fin[o + 512]),
+                                                               (double)(fin[o + 256] + fin[o + 768])};
+    }
+}
+
+template <typename T, int KS>
+static int launch_balanced_k(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
+    const size_t lds = sizeof(T) * 2 * (size_t)kBalBuf;
+    static bool attr_set = false;
+    if (!attr_set) {
+        LB_HIP(hipFuncSetAttribute((const void *)balanced_chain_kernel<T, KS>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    balanced_chain_kernel<T, KS><<<(B + NS - 1) / NS, CW * 64, lds, s>>>(n, P, B, rho, nsteps);
+    return check_launch("balanced_chain");
+}
+
+bool balanced_ok(int n, lb_precision prec) {
+    if (prec == LB_C128) return n >= 81 && n <= 84;
+    if (prec == LB_C64) return n >= 81 && n <= 96;
+    return false;
+}
+
+int chain_balanced(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s) {
+    if (nsteps == 0 || B == 0) return LB_OK;
+    if (!balanced_ok(n, prec)) return fail(LB_ESHAPE, "balanced chain: 81 <= n <= 84 (complex128) or 96 (complex64)");
+    const int KS = (n + 3) / 4;
+    if (prec == LB_C128) return launch_balanced_k<double, 21>(n, P, B, rho, nsteps, s);
+    switch (KS) {
+        case 21: return launch_balanced_k<float, 21>(n, P, B, rho, nsteps, s);
+        case 22: return launch_balanced_k<float, 22>(n, P, B, rho, nsteps, s);
+        case 23: return launch_balanced_k<float, 23>(n, P, B, rho, nsteps, s);
+        default: return launch_balanced_k<float, 24>(n, P, B, rho, nsteps, s);
+    }
+}
+
+
+
 int fused_max_n(lb_precision prec) {
     switch (prec) {
         case LB_C128: return 84;

@@ -15,6 +15,7 @@ enum ChainFamily : int {
     VF_GEMM = 5,        // one MFMA GEMM launch per step; param = 16-output tiles per wavefront
     VF_MATVEC = 6,      // per-state FP32 matvec, one launch per step (LB_C64)
     VF_PLANES = 7,      // one BF16 plane-GEMM launch per step
+    VF_BALANCED = 8,    // fused chain with the SIMD-balanced layout (81 <= n <= 84 / 96)
 };
 inline int variant_family(int v) { return v / 100; }
 inline int variant_param(int v) { return v % 100; }
@@ -30,6 +31,8 @@ int chain_baseline(int n, const cd *P, int B, cd *rho, long long nsteps, Workspa
 constexpr int kWaveChainMaxN = 16;
 int chain_wave(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
 int chain_fused(int n, const cd *P, lb_precision prec, int kpu, int B, cd *rho, long long nsteps, hipStream_t s);
+bool balanced_ok(int n, lb_precision prec);
+int chain_balanced(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
 
 // Longest chain that runs with the 4 x 4-digit slice set (10 slice pairs);
 // longer chains use 5 x 4 digits (14 pairs).  Emulated and measured trace

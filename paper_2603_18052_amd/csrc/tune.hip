@@ -59,6 +59,7 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
         int kpus[8];
         const int nk = fused_kpus(n, prec, kpus, 8);
         for (int i = 0; i < nk; ++i) add(VF_FUSED * 100 + kpus[i]);
+        if (balanced_ok(n, prec)) add(VF_BALANCED * 100);
         add(VF_GEMM * 100 + 1);
         add(VF_GEMM * 100 + 2);
         if (prec == LB_C64) add(VF_MATVEC * 100);
@@ -73,7 +74,9 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
 // chains): the register-resident wave chain for n <= 16 at every batch size;
 // for FP64 with little work per step (B n^2 up to ~1e6) the plain per-state
 // matvec, whose step is shorter than the fused kernel's 8-wavefront MFMA
-// step; the fused on-chip chain while P fits in one CU's LDS; otherwise a
+// step; the SIMD-balanced fused chain where its layout exists (81 <= n <= 84
+// / 96, 17-20 % faster than the round-robin units there), the round-robin
+// fused chain elsewhere while P fits in one CU's LDS; otherwise a
 // GEMM per step with one output tile per wavefront up to 256 states (more
 // workgroups) and two beyond, or a matvec for few states.
 int chain_heuristic(int n, lb_precision prec, int B) {
@@ -82,6 +85,7 @@ int chain_heuristic(int n, lb_precision prec, int B) {
         case LB_C64: {
             if (n <= kWaveChainMaxN) return VF_WAVE * 100;
             if (prec == LB_C128 && (double)B * n * n <= 1.1e6) return VF_BASELINE * 100;
+            if (balanced_ok(n, prec)) return VF_BALANCED * 100;
             int kpu;
             if (fused_kpus(n, prec, &kpu, 1) == 1) return VF_FUSED * 100 + kpu;
             if (B >= 16) return VF_GEMM * 100 + (B <= 256 ? 1 : 2);
@@ -123,6 +127,7 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_GEMM: return chain_gemm(n, P, prec, prm, B, rho, nsteps, ws, s);
         case VF_MATVEC: return chain_matvec(n, P, prec, B, rho, nsteps, ws, s);
         case VF_PLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s);
+        case VF_BALANCED: return chain_balanced(n, P, prec, B, rho, nsteps, s);
         default: return fail(LB_EINVAL, "unknown chain variant");
     }
 }

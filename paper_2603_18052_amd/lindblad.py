@@ -56,7 +56,8 @@ SYMBOLS = {
 }
 
 # Chain variant families (id = family * 100 + tile parameter).
-VARIANT_FAMILIES = {1: "baseline", 2: "wave", 3: "fused", 4: "bf16_fused", 5: "gemm", 6: "matvec32", 7: "planes"}
+VARIANT_FAMILIES = {1: "baseline", 2: "wave", 3: "fused", 4: "bf16_fused", 5: "gemm", 6: "matvec32", 7: "planes",
+                    8: "fused_balanced"}
 
 
 def variant_name(v: int) -> str:

@@ -84,10 +84,12 @@ def test_chain_variant_lists_and_rule(L):
     # d = 9 headline: fused with the smallest k split giving at most 32 units
     v = lb.chain_variants(81, "c128", 4096)
     assert [x for x in v if x // 100 == 3] == [306, 308, 311]
+    assert 800 in v and 800 in lb.chain_variants(96, "c64", 16) and 800 not in lb.chain_variants(85, "c128", 16)
     assert 200 not in v
-    assert lb.chain_variant(81, "c128", 4096) == 306
+    assert lb.chain_variant(81, "c128", 4096) == 800  # SIMD-balanced layout
     assert lb.chain_variant(81, "c128", 64) == 100  # little work per step: plain matvec
-    assert lb.chain_variant(81, "c64", 64) == 306
+    assert lb.chain_variant(81, "c64", 64) == 800
+    assert lb.chain_variant(100, "c64", 64) == 308
     assert lb.chain_variant(16, "c64", 4096) == 200
     # d = 27: no fused variant; GEMM from 16 states, matvec below
     assert not [x for x in lb.chain_variants(729, "c128", 64) if x // 100 == 3]
@@ -106,7 +108,7 @@ def test_chain_variant_lists_and_rule(L):
     with pytest.raises(lb.LindbladError):
         lb.tune_set(81, "c128", 4096, 200)
     lb.tune_set(81, "c128", 4096, 0)
-    assert lb.chain_variant(81, "c128", 4096) == 306
+    assert lb.chain_variant(81, "c128", 4096) == 800
     cnt = ctypes.c_int()
     assert L.lindblad_chain_variants(0, 0, 1, None, 0, ctypes.byref(cnt)) == lb.ESHAPE
     assert L.lindblad_chain_variants(9, 7, 1, None, 0, ctypes.byref(cnt)) == lb.EINVAL
