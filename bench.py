@@ -128,10 +128,94 @@ def config1_section(lb, W, torch, dev, ws, want_cpu):
     return res
 
 
+def timing_models_section(lb, W, torch, dev):
+    """The paper's three GPU timing models (kernel-only, resident-P,
+    host-visible; Eqs. (7)-(9)) on MI355X over its (d, batch) grid: one chain
+    step per call on b states, median of 5 trials of 50 calls after 5 warm-up
+    calls, in ns per state-step.  Kernel-only: HIP events around calls on
+    device-resident buffers.  Resident-P: host clock around state upload,
+    step, download and synchronisation (P stays on the device).
+    Host-visible: additionally three device allocations, the upload of P and
+    three frees per call (HIP runtime called directly)."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    H2D, D2H = 1, 2
+    L = lb.lib()
+    out = {}
+    for q in (1, 2, 3):
+        d = 3 ** q
+        n = d * d
+        Hm, Lk = W.transmon_system(q)
+        P = lb.propagator(lb.liouvillian(torch.from_numpy(Hm).to(dev), torch.from_numpy(Lk).to(dev)), W.DT_NS)
+        Ph = np.ascontiguousarray(P.cpu().numpy())
+        row = {}
+        for b in (1, 8, 32, 128):
+            Xh = np.ascontiguousarray(W.wishart_batch(d, b, 6).reshape(b, n))
+            Yh = np.empty_like(Xh)
+            X = torch.from_numpy(Xh).to(dev)
+            variant = lb.variant_name(lb.chain_variant(n, "c128", b))
+
+            # the C-ABI called directly with its arguments prepared once, on
+            # the null stream (the Python binding's checks cost microseconds)
+            call = L.lindblad_propagate
+            args = (n, ctypes.c_void_p(P.data_ptr()), 0, b, ctypes.c_void_p(X.data_ptr()), 1, None, None)
+
+            def kernel_only():
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record(torch.cuda.default_stream())
+                for _ in range(50):
+                    call(*args)
+                e1.record(torch.cuda.default_stream())
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) * 1e6 / 50
+
+            def resident():
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(50):
+                    hip.hipMemcpy(X.data_ptr(), Xh.ctypes.data, Xh.nbytes, H2D)
+                    call(*args)
+                    hip.hipMemcpy(Yh.ctypes.data, X.data_ptr(), Xh.nbytes, D2H)
+                return (time.perf_counter() - t0) * 1e9 / 50
+
+            def host_visible():
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(50):
+                    bufs = [ctypes.c_void_p() for _ in range(3)]
+                    for ptr, size in zip(bufs, (Ph.nbytes, Xh.nbytes, Xh.nbytes)):
+                        if hip.hipMalloc(ctypes.byref(ptr), size) != 0:
+                            raise RuntimeError("hipMalloc failed")
+                    hip.hipMemcpy(bufs[0], Ph.ctypes.data, Ph.nbytes, H2D)
+                    hip.hipMemcpy(bufs[1], Xh.ctypes.data, Xh.nbytes, H2D)
+                    rc = L.lindblad_propagate(n, bufs[0], 0, b, bufs[1], 1, None, None)
+                    if rc != 0:
+                        raise RuntimeError(lb.last_error())
+                    hip.hipMemcpy(Yh.ctypes.data, bufs[1], Xh.nbytes, D2H)
+                    for ptr in bufs:
+                        hip.hipFree(ptr)
+                return (time.perf_counter() - t0) * 1e9 / 50
+
+            res = {"variant": variant}
+            for name, fn in (("kernel_only", kernel_only), ("resident_P", resident), ("host_visible", host_visible)):
+                fn()  # warm-up (50 calls)
+                trials = sorted(fn() for _ in range(5))
+                res[name + "_ns_per_call"] = trials[2]
+                res[name + "_ns_per_state_step"] = trials[2] / b
+            row[f"b{b}"] = res
+        out[f"d{d}"] = row
+    return out
+
+
 def extra_sections(lb, W, torch, dev, ws, want_cpu):
     """d = 3 single state (config 1), d = 27 chains (config 3), GRAPE
     gradients (config 4), mixed batch (config 5)."""
-    out = {"d3_config1": config1_section(lb, W, torch, dev, ws, want_cpu)}
+    out = {"d3_config1": config1_section(lb, W, torch, dev, ws, want_cpu),
+           "timing_models": timing_models_section(lb, W, torch, dev)}
     # ---- config 3: d = 27, B in {1, 64, 1024}, 1e3 steps
     cfg = W.config3(B=1024, nsteps=1000)
     n, N = 729, cfg["nsteps"]

@@ -338,19 +338,35 @@ __global__ void __launch_bounds__(256) gemm_step_kernel(int n, int B, int Kp, co
 #pragma unroll
     for (int t = 0; t < GWN; ++t) rr[t] = ii[t] = ri[t] = ir[t] = acc_t{0, 0, 0, 0};
     const v4 z = {0, 0, 0, 0};
-    for (int kb = wave * 16; kb < Kp; kb += 64) {
-        const v4 xr = bvalid ? *reinterpret_cast<const v4 *>(Xr + xo + kb) : z;
-        const v4 xi = bvalid ? *reinterpret_cast<const v4 *>(Xi + xo + kb) : z;
+    // operands of the next k block are loaded while this one is multiplied
+    v4 xr, xi, pr[GWN], pi[GWN];
+    auto load = [&](int kb) {
+        xr = bvalid ? *reinterpret_cast<const v4 *>(Xr + xo + kb) : z;
+        xi = bvalid ? *reinterpret_cast<const v4 *>(Xi + xo + kb) : z;
 #pragma unroll
         for (int t = 0; t < GWN; ++t) {
-            const v4 pr = pvalid[t] ? *reinterpret_cast<const v4 *>(Pr + po[t] + kb) : z;
-            const v4 pi = pvalid[t] ? *reinterpret_cast<const v4 *>(Pi + po[t] + kb) : z;
+            pr[t] = pvalid[t] ? *reinterpret_cast<const v4 *>(Pr + po[t] + kb) : z;
+            pi[t] = pvalid[t] ? *reinterpret_cast<const v4 *>(Pi + po[t] + kb) : z;
+        }
+    };
+    if (wave * 16 < Kp) load(wave * 16);
+    for (int kb = wave * 16; kb < Kp; kb += 64) {
+        const v4 cxr = xr, cxi = xi;
+        v4 cpr[GWN], cpi[GWN];
+#pragma unroll
+        for (int t = 0; t < GWN; ++t) {
+            cpr[t] = pr[t];
+            cpi[t] = pi[t];
+        }
+        if (kb + 64 < Kp) load(kb + 64);
+#pragma unroll
+        for (int t = 0; t < GWN; ++t) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                rr[t] = StepMma<T>::mma(xr[q], pr[q], rr[t]);
-                ii[t] = StepMma<T>::mma(xi[q], pi[q], ii[t]);
-                ri[t] = StepMma<T>::mma(xr[q], pi[q], ri[t]);
-                ir[t] = StepMma<T>::mma(xi[q], pr[q], ir[t]);
+                rr[t] = StepMma<T>::mma(cxr[q], cpr[t][q], rr[t]);
+                ii[t] = StepMma<T>::mma(cxi[q], cpi[t][q], ii[t]);
+                ri[t] = StepMma<T>::mma(cxr[q], cpi[t][q], ri[t]);
+                ir[t] = StepMma<T>::mma(cxi[q], cpr[t][q], ir[t]);
             }
         }
     }
