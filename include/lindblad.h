@@ -155,7 +155,9 @@ int lindblad_propagate_baseline(int n, const void *P, int B, void *rho, long lon
  *   700       one BF16 plane-GEMM launch per step (BF16 precisions)
  *   800       whole chain in one launch, the two wavefronts of every SIMD
  *             balanced (81 <= n <= 84 LB_C128, <= 96 LB_C64)
- * Variants of one shape differ only in summation order. */
+ * Adding 50 to a per-step family (100, 500 + w, 600, 700) replays its steps
+ * from a HIP graph captured once per call (32 steps, replayed over all but
+ * the last step).  Variants of one shape differ only in summation order. */
 
 /* Variants that exist for (n, prec, B): up to max_ids ids written to the HOST
  * array ids, the total number to *count. */
@@ -172,7 +174,9 @@ int lindblad_propagate_variant(int n, const void *P, lb_precision prec, int B, v
 
 /* Autotuner: runs every variant of (n, prec, B) for probe_steps steps on a
  * workspace copy of rho (rho itself is only read), `repeats` times after one
- * warm-up run, times each with HIP events on `stream`, and records the
+ * warm-up run (graph-replayed twins only when probe_steps > 64, since a
+ * shorter probe replays nothing), times each with HIP events on `stream`, and
+ * records the
  * fastest for (current device, n, prec, B) for the rest of the process.
  * *best_variant and *best_ms (its fastest probe run in ms; both HOST, may be
  * NULL) receive the winner.  Synchronises the host with `stream`.  Thread-safe

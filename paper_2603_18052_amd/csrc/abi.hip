@@ -1,6 +1,7 @@
 // C-ABI entry points of liblindblad.so: validation, workspace, dispatch.
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -65,6 +66,84 @@ void *ws_take(Workspace *ws, size_t bytes) {
     void *p = ws->base + ws->used;
     ws->used += b;
     return p;
+}
+
+// ------------------------------------------------------- graph replay
+// Steps [0, kGraphSteps) are captured once per call on a private stream of the
+// current device (created on first use, default priority) and the executable
+// graph is replayed on the caller's stream.  An executable graph is destroyed
+// only once an event recorded after its last replay has completed (checked on
+// later calls), so nothing in flight is ever freed.
+namespace {
+struct Retired {
+    hipGraphExec_t exec;
+    hipGraph_t graph;
+    hipEvent_t done;
+};
+std::mutex g_graph_mu;
+std::map<int, hipStream_t> g_capture_stream;
+std::vector<Retired> g_retired;
+
+void reap_graphs() {  // caller holds g_graph_mu
+    for (size_t i = 0; i < g_retired.size();) {
+        if (hipEventQuery(g_retired[i].done) == hipSuccess) {
+            (void)hipGraphExecDestroy(g_retired[i].exec);
+            (void)hipGraphDestroy(g_retired[i].graph);
+            (void)hipEventDestroy(g_retired[i].done);
+            g_retired[i] = g_retired.back();
+            g_retired.pop_back();
+        } else {
+            (void)hipGetLastError();  // hipErrorNotReady is not an error here
+            ++i;
+        }
+    }
+}
+}  // namespace
+
+int run_steps(long long nsteps, bool graph, const std::function<int(long long, hipStream_t)> &step, hipStream_t s) {
+    // the last step is always launched directly (it may differ, e.g. write the result)
+    const long long reps = graph && nsteps > 0 ? (nsteps - 1) / kGraphSteps : 0;
+    long long t = 0;
+    if (reps >= 2) {
+        std::lock_guard<std::mutex> lock(g_graph_mu);
+        reap_graphs();
+        int dev = 0;
+        LB_HIP(hipGetDevice(&dev));
+        hipStream_t &cs = g_capture_stream[dev];
+        if (!cs) LB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        LB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        int st = LB_OK;
+        for (long long k = 0; k < kGraphSteps && st == LB_OK; ++k) st = step(k, cs);
+        const hipError_t ce = hipStreamEndCapture(cs, &g);
+        if (st != LB_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (ce != hipSuccess) return fail(LB_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
+        if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(LB_EHIP, "graph instantiation failed");
+        }
+        hipEvent_t done = nullptr;
+        st = hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess ? LB_OK
+                                                                                : fail(LB_EHIP, "hipEventCreate failed");
+        for (long long r = 0; r < reps && st == LB_OK; ++r)
+            if (hipGraphLaunch(ge, s) != hipSuccess) st = fail(LB_EHIP, "hipGraphLaunch failed");
+        if (st == LB_OK && hipEventRecord(done, s) != hipSuccess) st = fail(LB_EHIP, "hipEventRecord failed");
+        if (st != LB_OK) {  // nothing safe to free without waiting
+            (void)hipStreamSynchronize(s);
+            (void)hipGraphExecDestroy(ge);
+            (void)hipGraphDestroy(g);
+            if (done) (void)hipEventDestroy(done);
+            return st;
+        }
+        g_retired.push_back({ge, g, done});
+        t = reps * kGraphSteps;
+    }
+    for (; t < nsteps; ++t) LB_TRY(step(t, s));
+    return LB_OK;
 }
 
 static std::mutex g_ws_mutex;

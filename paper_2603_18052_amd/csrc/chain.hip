@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(256) baseline_step_kernel(int n, const cd *__r
     }
 }
 
-int chain_baseline(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+int chain_baseline(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s, bool graph) {
     if (nsteps == 0 || B == 0) return LB_OK;
     const size_t bytes = (size_t)B * n * sizeof(cd);
     LB_TRY(ws_ensure(ws, bytes));
@@ -54,15 +54,12 @@ int chain_baseline(int n, const cd *P, int B, cd *rho, long long nsteps, Workspa
     const long long rows = (long long)B * n;
     long long blocks = (rows + 3) / 4;
     if (blocks > 16384) blocks = 16384;
-    cd *x = rho, *y = tmp;
-    for (long long t = 0; t < nsteps; ++t) {
-        baseline_step_kernel<<<(int)blocks, 256, 0, s>>>(n, P, x, y, rows);
-        cd *z = x;
-        x = y;
-        y = z;
-    }
+    LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
+        baseline_step_kernel<<<(int)blocks, 256, 0, st>>>(n, P, (t & 1) ? tmp : rho, (t & 1) ? rho : tmp, rows);
+        return LB_OK;
+    }, s));
     LB_TRY(check_launch("baseline_step"));
-    if (x != rho) LB_HIP(hipMemcpyAsync(rho, x, bytes, hipMemcpyDeviceToDevice, s));
+    if (nsteps & 1) LB_HIP(hipMemcpyAsync(rho, tmp, bytes, hipMemcpyDeviceToDevice, s));
     return LB_OK;
 }
 

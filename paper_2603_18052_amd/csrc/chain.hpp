@@ -6,7 +6,10 @@
 
 namespace lb {
 
-// Variant ids: family * 100 + tile parameter.
+// Variant ids: family * 100 + tile parameter; + kGraphVariant for the
+// per-step families (baseline, GEMM, matvec, planes) replays the steps from a
+// captured HIP graph.
+constexpr int kGraphVariant = 50;
 enum ChainFamily : int {
     VF_BASELINE = 1,    // plain FP64 per-state matvec, one launch per step
     VF_WAVE = 2,        // one wavefront per state, P rows in registers (n <= kWaveChainMaxN)
@@ -27,7 +30,8 @@ int fused_max_n(lb_precision prec);
 bool fused_kpu_ok(int n, lb_precision prec, int kpu);
 int fused_kpus(int n, lb_precision prec, int *kpus, int max);  // valid k-steps-per-unit values, ascending
 
-int chain_baseline(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s);
+int chain_baseline(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s,
+                   bool graph = false);
 constexpr int kWaveChainMaxN = 16;
 int chain_wave(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
 int chain_fused(int n, const cd *P, lb_precision prec, int kpu, int B, cd *rho, long long nsteps, hipStream_t s);
@@ -43,11 +47,11 @@ int bf16_fused_max_n(lb_precision prec);
 int chain_bf16_fused(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
 
 int chain_gemm(int n, const cd *P, lb_precision prec, int wn, int B, cd *rho, long long nsteps, Workspace *ws,
-               hipStream_t s);
+               hipStream_t s, bool graph = false);
 int chain_matvec(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
-                 hipStream_t s);
+                 hipStream_t s, bool graph = false);
 int chain_planes(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
-                 hipStream_t s);
+                 hipStream_t s, bool graph = false);
 size_t large_ws_bytes(int family, int n, lb_precision prec, int B);
 
 // Variant selection (tune.hip): the list of variants that exist for a shape,

@@ -458,7 +458,8 @@ static int grid1(long long work) {
 using namespace lg;
 
 template <typename T>
-static int matvec_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+static int matvec_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s,
+                      bool graph) {
     const size_t nn = (size_t)n * n;
     LB_TRY(ws_ensure(ws, align256(nn * sizeof(Cx<T>)) + 2 * align256((size_t)B * n * sizeof(Cx<T>))));
     Cx<T> *Pc = (Cx<T> *)ws_take(ws, nn * sizeof(Cx<T>));
@@ -469,18 +470,18 @@ static int matvec_run(int n, const cd *P, int B, cd *rho, long long nsteps, Work
     const long long rows = (long long)B * n;
     long long blocks = (rows + 3) / 4;
     if (blocks > 16384) blocks = 16384;
-    for (long long t = 0; t < nsteps; ++t) {
-        const Cx<T> *x = (t & 1) ? X1 : X0;
-        Cx<T> *y = (t & 1) ? X0 : X1;
-        matvec_step_kernel<T><<<(int)blocks, 256, 0, s>>>(n, Pc, x, y, rows);
-    }
+    LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
+        matvec_step_kernel<T><<<(int)blocks, 256, 0, st>>>(n, Pc, (t & 1) ? X1 : X0, (t & 1) ? X0 : X1, rows);
+        return LB_OK;
+    }, s));
     LB_TRY(check_launch("matvec_step"));
     back_kernel<T><<<grid1((long long)B * n), 256, 0, s>>>((long long)B * n, (nsteps & 1) ? X1 : X0, rho);
     return check_launch("matvec_back");
 }
 
 template <typename T, int GWN>
-static int gemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+static int gemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s,
+                    bool graph) {
     const int Kp = (n + 63) / 64 * 64;
     const size_t pp = (size_t)n * Kp * sizeof(T), xp = (size_t)B * Kp * sizeof(T);
     LB_TRY(ws_ensure(ws, 2 * align256(pp) + 4 * align256(xp)));
@@ -493,16 +494,18 @@ static int gemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Worksp
         to_planes_kernel<T><<<grid1((long long)B * Kp), 256, 0, s>>>(B, n, Kp, rho, X[q][0], X[q][1]);
     LB_TRY(check_launch("to_planes"));
     dim3 grid((n + 16 * GWN - 1) / (16 * GWN), (B + TS - 1) / TS);
-    for (long long t = 0; t < nsteps; ++t) {
+    LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
         const int c = (int)(t & 1);
-        gemm_step_kernel<T, GWN><<<grid, 256, 0, s>>>(n, B, Kp, X[c][0], X[c][1], Pr, Pi, X[c ^ 1][0], X[c ^ 1][1],
-                                                      t + 1 == nsteps ? rho : nullptr);
-    }
+        gemm_step_kernel<T, GWN><<<grid, 256, 0, st>>>(n, B, Kp, X[c][0], X[c][1], Pr, Pi, X[c ^ 1][0], X[c ^ 1][1],
+                                                       t + 1 == nsteps ? rho : nullptr);
+        return LB_OK;
+    }, s));
     return check_launch("gemm_step");
 }
 
 template <int MODE, int SP, int SX, int LMAX>
-static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s) {
+static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s,
+                      bool graph) {
     constexpr int XD = Planes<MODE, SP, SX>::XD, PD = Planes<MODE, SP, SX>::PD;
     const int Kp = (n + KCH - 1) / KCH * KCH;
     const size_t pbytes = (size_t)PD * 2 * n * Kp * 2, xbytes = (size_t)XD * 3 * B * Kp * 2;
@@ -516,48 +519,48 @@ static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Work
     prep_p_kernel<MODE, SP, SX><<<n, 256, 0, s>>>(n, Kp, P, Pp, eP);
     LB_TRY(check_launch("prep_p"));
     dim3 grid((n + TO - 1) / TO, (B + TS - 1) / TS);
-    // the state ping-pongs between rho and Yt; it ends in rho
-    cd *cur = rho, *nxt = Yt;
-    for (long long t = 0; t < nsteps; ++t) {
-        slice_x_kernel<MODE, SP, SX><<<B, 256, 0, s>>>(n, Kp, B, cur, Xp, eX);
-        plane_gemm_kernel<MODE, SP, SX, LMAX><<<grid, 256, 0, s>>>(n, B, Kp, Xp, Pp, eP, eX, nxt);
-        cd *z = cur;
-        cur = nxt;
-        nxt = z;
-    }
+    // the state ping-pongs between rho and Yt
+    LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
+        cd *cur = (t & 1) ? Yt : rho, *nxt = (t & 1) ? rho : Yt;
+        slice_x_kernel<MODE, SP, SX><<<B, 256, 0, st>>>(n, Kp, B, cur, Xp, eX);
+        plane_gemm_kernel<MODE, SP, SX, LMAX><<<grid, 256, 0, st>>>(n, B, Kp, Xp, Pp, eP, eX, nxt);
+        return LB_OK;
+    }, s));
     LB_TRY(check_launch("plane_gemm"));
-    if (cur != rho) LB_HIP(hipMemcpyAsync(rho, cur, ybytes, hipMemcpyDeviceToDevice, s));
+    if (nsteps & 1) LB_HIP(hipMemcpyAsync(rho, Yt, ybytes, hipMemcpyDeviceToDevice, s));
     return LB_OK;
 }
 
 int chain_matvec(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
-                 hipStream_t s) {
+                 hipStream_t s, bool graph) {
     if (nsteps == 0 || B == 0) return LB_OK;
     if (prec != LB_C64) return fail(LB_ENOTSUP, "matvec chain: complex64 only (complex128 is the baseline)");
-    return matvec_run<float>(n, P, B, rho, nsteps, ws, s);
+    return matvec_run<float>(n, P, B, rho, nsteps, ws, s, graph);
 }
 
 int chain_gemm(int n, const cd *P, lb_precision prec, int wn, int B, cd *rho, long long nsteps, Workspace *ws,
-               hipStream_t s) {
+               hipStream_t s, bool graph) {
     if (nsteps == 0 || B == 0) return LB_OK;
     if (wn != 1 && wn != 2) return fail(LB_ESHAPE, "gemm chain: 1 or 2 output tiles per wavefront");
     switch (prec) {
         case LB_C128:
-            return wn == 1 ? gemm_run<double, 1>(n, P, B, rho, nsteps, ws, s) : gemm_run<double, 2>(n, P, B, rho, nsteps, ws, s);
+            return wn == 1 ? gemm_run<double, 1>(n, P, B, rho, nsteps, ws, s, graph)
+                           : gemm_run<double, 2>(n, P, B, rho, nsteps, ws, s, graph);
         case LB_C64:
-            return wn == 1 ? gemm_run<float, 1>(n, P, B, rho, nsteps, ws, s) : gemm_run<float, 2>(n, P, B, rho, nsteps, ws, s);
+            return wn == 1 ? gemm_run<float, 1>(n, P, B, rho, nsteps, ws, s, graph)
+                           : gemm_run<float, 2>(n, P, B, rho, nsteps, ws, s, graph);
         default: return fail(LB_ENOTSUP, "gemm chain: complex128 / complex64 only");
     }
 }
 
 int chain_planes(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
-                 hipStream_t s) {
+                 hipStream_t s, bool graph) {
     if (nsteps == 0 || B == 0) return LB_OK;
     switch (prec) {
-        case LB_BF16_HILO: return planes_run<HILO, 2, 2, 1>(n, P, B, rho, nsteps, ws, s);
+        case LB_BF16_HILO: return planes_run<HILO, 2, 2, 1>(n, P, B, rho, nsteps, ws, s, graph);
         case LB_BF16_SLICED:
-            if (nsteps <= kSlicedShortRun) return planes_run<SLICED, 4, 4, 3>(n, P, B, rho, nsteps, ws, s);
-            return planes_run<SLICED, 5, 4, 4>(n, P, B, rho, nsteps, ws, s);
+            if (nsteps <= kSlicedShortRun) return planes_run<SLICED, 4, 4, 3>(n, P, B, rho, nsteps, ws, s, graph);
+            return planes_run<SLICED, 5, 4, 4>(n, P, B, rho, nsteps, ws, s, graph);
         default: return fail(LB_ENOTSUP, "plane chain: BF16 precisions only");
     }
 }

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 
 #include "../../include/lindblad.h"
@@ -54,6 +55,14 @@ void *ws_take(Workspace *ws, size_t bytes);
 Workspace *ws_resolve(lb_workspace *ws);
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Enqueues step(t, stream) for t in [0, nsteps) on `s`.  With `graph` (and
+// more than 2 kGraphSteps steps), steps [0, kGraphSteps) are captured once
+// into a HIP graph and replayed over all but the last step, which is always
+// launched directly; `step` must depend on t only through t & 1 except on the
+// last step (kGraphSteps is even) and must not record memset nodes.
+constexpr long long kGraphSteps = 32;
+int run_steps(long long nsteps, bool graph, const std::function<int(long long, hipStream_t)> &step, hipStream_t s);
 
 // ------------------------------------------------------- complex FP64
 struct cd {

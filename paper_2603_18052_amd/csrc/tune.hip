@@ -53,19 +53,23 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
         if (c < max) ids[c] = v;
         ++c;
     };
+    auto add2 = [&](int v) {  // a per-step family: eager and graph-replayed
+        add(v);
+        add(v + kGraphVariant);
+    };
     if (is_c(prec)) {
-        if (prec == LB_C128) add(VF_BASELINE * 100);
+        if (prec == LB_C128) add2(VF_BASELINE * 100);
         if (n <= kWaveChainMaxN) add(VF_WAVE * 100);
         int kpus[8];
         const int nk = fused_kpus(n, prec, kpus, 8);
         for (int i = 0; i < nk; ++i) add(VF_FUSED * 100 + kpus[i]);
         if (balanced_ok(n, prec)) add(VF_BALANCED * 100);
-        add(VF_GEMM * 100 + 1);
-        add(VF_GEMM * 100 + 2);
-        if (prec == LB_C64) add(VF_MATVEC * 100);
+        add2(VF_GEMM * 100 + 1);
+        add2(VF_GEMM * 100 + 2);
+        if (prec == LB_C64) add2(VF_MATVEC * 100);
     } else if (prec == LB_BF16_HILO || prec == LB_BF16_SLICED) {
         if (n <= bf16_fused_max_n(prec)) add(VF_BF16_FUSED * 100);
-        add(VF_PLANES * 100);
+        add2(VF_PLANES * 100);
     }
     return c;
 }
@@ -109,7 +113,7 @@ static bool variant_listed(int n, lb_precision prec, int B, int variant) {
 
 size_t chain_ws_bytes(int n, lb_precision prec, int B, int variant) {
     const int fam = variant_family(variant);
-    if (fam == VF_BASELINE) return align256((size_t)B * n * sizeof(cd));
+    if (fam == VF_BASELINE) return align256((size_t)B * n * sizeof(cd));  // same for the graph twin
     return large_ws_bytes(fam, n, prec, B);
 }
 
@@ -118,15 +122,16 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
     if (!variant_listed(n, prec, B, variant))
         return fail(LB_EINVAL, "chain variant " + std::to_string(variant) + " does not exist for this shape");
     if (nsteps == 0) return LB_OK;
-    const int prm = variant_param(variant);
+    const int prm = variant_param(variant) % kGraphVariant;
+    const bool graph = variant_param(variant) >= kGraphVariant;
     switch (variant_family(variant)) {
-        case VF_BASELINE: return chain_baseline(n, P, B, rho, nsteps, ws, s);
+        case VF_BASELINE: return chain_baseline(n, P, B, rho, nsteps, ws, s, graph);
         case VF_WAVE: return chain_wave(n, P, prec, B, rho, nsteps, s);
         case VF_FUSED: return chain_fused(n, P, prec, prm, B, rho, nsteps, s);
         case VF_BF16_FUSED: return chain_bf16_fused(n, P, prec, B, rho, nsteps, s);
-        case VF_GEMM: return chain_gemm(n, P, prec, prm, B, rho, nsteps, ws, s);
-        case VF_MATVEC: return chain_matvec(n, P, prec, B, rho, nsteps, ws, s);
-        case VF_PLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s);
+        case VF_GEMM: return chain_gemm(n, P, prec, prm, B, rho, nsteps, ws, s, graph);
+        case VF_MATVEC: return chain_matvec(n, P, prec, B, rho, nsteps, ws, s, graph);
+        case VF_PLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s, graph);
         case VF_BALANCED: return chain_balanced(n, P, prec, B, rho, nsteps, s);
         default: return fail(LB_EINVAL, "unknown chain variant");
     }
@@ -220,6 +225,11 @@ extern "C" int lindblad_tune(int n, const void *P, lb_precision prec, int B, con
     float best_t = 0.f;
     const cd *Pc = static_cast<const cd *>(P);
     for (int i = 0; i < nv && st == LB_OK; ++i) {
+        // a probe too short to replay a graph would time the direct twin again
+        if (variant_param(ids[i]) >= kGraphVariant && probe_steps <= 2 * kGraphSteps &&
+            (variant_family(ids[i]) == VF_BASELINE || variant_family(ids[i]) == VF_GEMM ||
+             variant_family(ids[i]) == VF_MATVEC || variant_family(ids[i]) == VF_PLANES))
+            continue;
         w->used = base;
         st = chain_run_variant(n, Pc, prec, B, x, probe_steps, ids[i], w, stream);  // warm-up
         float tmin = 0.f;

@@ -60,14 +60,19 @@ VARIANT_FAMILIES = {1: "baseline", 2: "wave", 3: "fused", 4: "bf16_fused", 5: "g
                     8: "fused_balanced"}
 
 
+GRAPH_VARIANT = 50  # added to a per-step family: steps replayed from a captured HIP graph
+
+
 def variant_name(v: int) -> str:
     fam, prm = divmod(int(v), 100)
     name = VARIANT_FAMILIES.get(fam, f"family{fam}")
+    graph = fam in (1, 5, 6, 7) and prm >= GRAPH_VARIANT
+    prm = prm % GRAPH_VARIANT if fam in (1, 5, 6, 7) else prm
     if fam == 3:
-        return f"{name}(k{prm})"
-    if fam == 5:
-        return f"{name}(w{prm})"
-    return name
+        name = f"{name}(k{prm})"
+    elif fam == 5:
+        name = f"{name}(w{prm})"
+    return name + "+graph" if graph else name
 
 
 class LindbladError(RuntimeError):

@@ -76,9 +76,9 @@ def test_chain_variant_lists_and_rule(L):
     from paper_2603_18052_amd import lindblad as lb
     # d = 3: every FP64 family that handles n = 9
     v = lb.chain_variants(9, "c128", 1)
-    assert v[:2] == [100, 200]
+    assert v[:3] == [100, 150, 200]  # baseline, its graph-replayed twin, wave
     assert [x for x in v if x // 100 == 3] == [301, 302, 303]  # KS = 3 k steps
-    assert {501, 502} <= set(v) and 600 not in v
+    assert {501, 502, 551, 552} <= set(v) and 600 not in v
     assert 600 in lb.chain_variants(9, "c64", 1000) and 100 not in lb.chain_variants(9, "c64", 1)
     assert lb.chain_variant(9, "c128", 1) == 200
     # d = 9 headline: fused with the smallest k split giving at most 32 units
@@ -99,8 +99,10 @@ def test_chain_variant_lists_and_rule(L):
     assert lb.chain_variant(729, "c64", 1) == 600
     assert 100 not in lb.chain_variants(729, "c64", 64)
     # BF16 precisions
-    assert lb.chain_variants(81, "bf16_sliced", 16) == [400, 700]
-    assert lb.chain_variants(729, "bf16_sliced", 16) == [700]
+    assert lb.chain_variants(81, "bf16_sliced", 16) == [400, 700, 750]
+    assert lb.chain_variants(729, "bf16_sliced", 16) == [700, 750]
+    assert [lb.variant_name(x) for x in (150, 552, 306, 800)] == ["baseline+graph", "gemm(w2)+graph", "fused(k6)",
+                                                                   "fused_balanced"]
     assert lb.chain_variant(729, "bf16_hilo", 16) == 700
     # tuning table: set, read back, reject a variant the shape lacks, clear
     lb.tune_set(81, "c128", 4096, 502)
@@ -112,6 +114,6 @@ def test_chain_variant_lists_and_rule(L):
     cnt = ctypes.c_int()
     assert L.lindblad_chain_variants(0, 0, 1, None, 0, ctypes.byref(cnt)) == lb.ESHAPE
     assert L.lindblad_chain_variants(9, 7, 1, None, 0, ctypes.byref(cnt)) == lb.EINVAL
-    assert L.lindblad_chain_variants(9, 0, 1, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 7
+    assert L.lindblad_chain_variants(9, 0, 1, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 10
     assert L.lindblad_propagate_variant(9, 1, 0, 1, 1, 5, 999, None, None) == lb.EINVAL
     assert L.lindblad_tune(9, 1, 0, 1, 1, 0, 1, None, None, None, None) == lb.EINVAL

@@ -47,7 +47,8 @@ def states(d, B, seed):
     return np.stack([W.wishart_state(d, g) for _ in range(B)]).reshape(B, d * d)
 
 
-CASES = [(2, 5, 200), (3, 1, 300), (3, 20, 300), (4, 70, 200), (9, 1, 200), (9, 20, 200), (27, 3, 40), (27, 20, 40)]
+# step counts above 2 x 32 + 1 so that the graph-replayed variants replay
+CASES = [(2, 5, 200), (3, 1, 300), (3, 20, 300), (4, 70, 200), (9, 1, 200), (9, 20, 200), (27, 3, 70), (27, 20, 70)]
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64", "bf16_hilo", "bf16_sliced"])
@@ -117,3 +118,22 @@ def test_tune_records_a_listed_variant(lb, d, B, prec):
         assert oracle.trace_distance(got.reshape(-1, d, d), ref.reshape(-1, d, d)).max() < 1e-4
     lb.tune_set(n, prec, B, 0)
     assert lb.chain_variant(n, prec, B) != 0
+
+
+@pytest.mark.parametrize("d,B,prec", [(9, 20, "c128"), (27, 3, "c64"), (9, 17, "bf16_sliced"), (27, 2, "bf16_hilo")])
+@pytest.mark.parametrize("N", [64, 65, 97, 130])
+def test_graph_replay_matches_direct_launches(lb, d, B, N, prec):
+    """A graph-replayed variant runs exactly the kernels of its direct twin
+    (32 captured steps replayed, the rest and the last step direct): the
+    results must be bitwise equal, for step counts on both sides of the
+    replay boundaries and of both parities."""
+    n = d * d
+    P = T(oracle_P(d))
+    X = states(d, B, 5)
+    graph = [v for v in lb.chain_variants(n, prec, B) if v % 100 >= lb.GRAPH_VARIANT and v // 100 in (1, 5, 6, 7)]
+    assert graph
+    for v in graph:
+        a, b = T(X.copy()), T(X.copy())
+        lb.propagate_variant(P, a, N, v - lb.GRAPH_VARIANT, prec)
+        lb.propagate_variant(P, b, N, v, prec)
+        assert torch.equal(a, b), (lb.variant_name(v), N)
