@@ -229,9 +229,9 @@ int lindblad_batch_run(const lb_problem *probs, int nprob, lb_precision prec, do
 /* Byte budget of the propagators that lindblad_batch_run keeps running at
  * once for sizes past its one-workgroup-per-problem limit (n > 128): problems
  * run longest first in a sliding window of floor(bytes / P_bytes) (at least
- * one) so that the window's propagators stay resident in the Infinity Cache.
- * 0 restores the default (192 MiB).  Process-wide; results do not depend on
- * it (bitwise). */
+ * one), which bounds the propagator bytes streamed per step.  0 restores the
+ * default (192 MiB, the fastest measured budget).  Process-wide; results do
+ * not depend on it (bitwise). */
 int lindblad_batch_set_window(size_t bytes);
 
 #ifdef __cplusplus

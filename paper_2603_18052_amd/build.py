@@ -1,5 +1,6 @@
 """Build liblindblad.so (HIP, gfx950) in-tree: one hipcc -c per source in
-parallel, then one link.  Usage: python -m paper_2603_18052_amd.build"""
+parallel, then one link; also the standalone device probes in probes/bin.
+Usage: python -m paper_2603_18052_amd.build"""
 from __future__ import annotations
 
 import concurrent.futures as cf
@@ -12,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC_DIR = os.path.join(HERE, "csrc")
 OBJ_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblindblad.so")
+PROBE_DIR = os.path.join(HERE, "probes")  # standalone device probes (executables in probes/bin)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
@@ -34,14 +36,27 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _probe(src: str) -> str:
+    exe = os.path.join(PROBE_DIR, "bin", os.path.splitext(os.path.basename(src))[0])
+    if os.path.exists(exe) and os.path.getmtime(exe) >= os.path.getmtime(src):
+        return exe
+    r = subprocess.run([HIPCC, *FLAGS, src, "-o", exe], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    return exe
+
+
 def build(force: bool = False, jobs: int = 8) -> str:
     os.makedirs(OBJ_DIR, exist_ok=True)
+    os.makedirs(os.path.join(PROBE_DIR, "bin"), exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(SRC_DIR, "*.hip")))
+    probes = sorted(glob.glob(os.path.join(PROBE_DIR, "*.hip")))
     if force:
-        for o in glob.glob(os.path.join(OBJ_DIR, "*.o")):
+        for o in glob.glob(os.path.join(OBJ_DIR, "*.o")) + glob.glob(os.path.join(PROBE_DIR, "bin", "*")):
             os.remove(o)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
+        list(ex.map(_probe, probes))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
