@@ -24,6 +24,7 @@
 // L = X1 + X2 R (the derivative of Q^{-1}(V + U)), then s times
 //   L <- R L + L R,  R <- R R.
 // All slices of a chunk go through these steps together as batched GEMMs.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -353,6 +354,10 @@ static int frechet_chunk(int n, int Mc, const cd *Lg, const double *dt_host, con
 
 int generators_launch(int n, int M, int C, const cd *L0, const cd *Lc, const double *u, cd *Lout, hipStream_t s);
 
+// Default cap of the gradient's workspace reservation (slices are processed
+// in chunks that fit it; the library workspace's own cap applies as well).
+constexpr size_t kGrapeChunkBudget = 24ull << 30;
+
 static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const double *u, double dt, double theta,
                      const cd *x0, const cd *w, double *F, double *grad, long long checkpoint_bytes, Workspace *ws,
                      hipStream_t s) {
@@ -360,18 +365,27 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
     const size_t nn = (size_t)n * n;
     const size_t matb = nn * sizeof(cd);
     const bool keepP = checkpoint_bytes <= 0 || (double)M * (double)matb <= (double)checkpoint_bytes;
-    const int Mc = M < 16 ? M : 16;  // slices per batched chunk
     const int nblk = (int)((nn + CHUNK - 1) / CHUNK);
     // ---- reservation: persistent buffers + the larger of the chunk phases
-    size_t persistent = align256((size_t)(M + 1) * n * sizeof(cd)) * 2 + align256((size_t)HR * n * sizeof(cd)) +
-                        align256((size_t)C * matb) +
-                        align256(sizeof(double)) + align256((size_t)nblk * Mc * C * sizeof(double)) +
-                        (keepP ? align256((size_t)M * matb) : 0);
-    size_t chunkp = 2 * align256((size_t)Mc * matb);  // generators + propagators of a chunk
-    size_t phase = build_workspace_bytes(n, Mc);
-    const size_t fr = frechet_bytes(n, Mc) + align256((size_t)Mc * matb);
-    if (fr > phase) phase = fr;
-    const size_t total = persistent + chunkp + phase;
+    auto reservation = [&](int mc) {
+        const size_t persistent = align256((size_t)(M + 1) * n * sizeof(cd)) * 2 +
+                                  align256((size_t)HR * n * sizeof(cd)) + align256((size_t)C * matb) +
+                                  align256(sizeof(double)) + align256((size_t)nblk * mc * C * sizeof(double)) +
+                                  (keepP ? align256((size_t)M * matb) : 0);
+        const size_t chunkp = 2 * align256((size_t)mc * matb);  // generators + propagators of a chunk
+        size_t phase = build_workspace_bytes(n, mc);
+        const size_t fr = frechet_bytes(n, mc) + align256((size_t)mc * matb);
+        if (fr > phase) phase = fr;
+        return persistent + chunkp + phase;
+    };
+    // Slices per batched chunk: the most that fit the budget (larger chunks
+    // fill the device better and run fewer sequential LU panel rounds;
+    // results do not depend on the chunking).
+    const size_t budget = std::min(ws->cap, kGrapeChunkBudget);
+    int Mc = M < 1024 ? M : 1024;
+    while (Mc > 1 && reservation(Mc) > budget) Mc = Mc > 16 ? Mc * 3 / 4 : Mc - 1;
+    Mc = (M + (M + Mc - 1) / Mc - 1) / ((M + Mc - 1) / Mc);  // equal chunks, no short tail
+    const size_t total = reservation(Mc);
     LB_TRY(ws_ensure(ws, total));
     cd *xs = (cd *)ws_take(ws, (size_t)(M + 1) * n * sizeof(cd));
     cd *lams = (cd *)ws_take(ws, (size_t)(M + 1) * n * sizeof(cd));

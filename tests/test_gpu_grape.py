@@ -129,3 +129,19 @@ def test_grape_d27_directional_fd_and_forward(lb):
     fd = (gpu_grad(lb, p, L0, Lc, p["u"] + h * v)[0] - gpu_grad(lb, p, L0, Lc, p["u"] - h * v)[0]) / (2 * h)
     dd = float(np.sum(g * v))
     assert abs(dd - fd) <= 1e-8 + 1e-7 * abs(dd)
+
+
+def test_grape_chunking_does_not_change_bits(lb):
+    """A workspace with a small cap forces the slices into several chunks (the
+    forward builds, the backward rebuilds and the batched Frechet derivatives
+    then cross chunk boundaries); the fidelity and every gradient entry must
+    be bitwise those of the single-chunk run, with and without kept
+    propagators."""
+    p, L0, Lc = setup(2, M=37, seed_u=21)
+    F1, g1 = gpu_grad(lb, p, L0, Lc)
+    small = lb.Workspace(48 << 20)  # a few d = 9 slices per chunk
+    for ckpt in (0, 1):
+        F2, g2 = gpu_grad(lb, p, L0, Lc, ws=small, checkpoint_bytes=ckpt)
+        assert F1 == F2
+        assert np.array_equal(g1, g2)
+    small.close()
