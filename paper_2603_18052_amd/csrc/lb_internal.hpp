@@ -114,6 +114,12 @@ int build_propagators(int n, int M, const cd *L, const double *dt_host, double t
                       Workspace *ws, hipStream_t s);
 // Workspace bytes build_propagators needs for a batch of M (chunked inside).
 size_t build_workspace_bytes(int n, int M);
+// Alg. 1 after its scaling stage for M matrices with d_dt, d_s on the device
+// and smax = max s known on the host; enqueue only (no host synchronisation),
+// zero pivots flagged in d_info (which must start at 0).  Workspace: build_async_bytes.
+int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *d_s, int smax, cd *P, int *d_info,
+                      Workspace *ws, hipStream_t s);
+size_t build_async_bytes(int n, int M);
 
 // Scaling stage of Alg. 1 for M generators: s[m] from ||L[m] dt[m]||_1
 // (host sync), uploaded to d_s; d_dt receives dt.  Fails with LB_ENONFINITE.

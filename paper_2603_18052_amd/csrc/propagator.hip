@@ -157,12 +157,19 @@ static size_t chunk_bytes(int n, int M) {
            2 * align256(M * sizeof(int));
 }
 
-// One chunk of matrices (all buffers sized for `M` matrices).
-static int build_chunk(int n, int M, const cd *L, const double *dt_host, double theta, cd *P, int *s_host,
-                       Workspace *ws, hipStream_t s) {
+size_t build_async_bytes(int n, int M) {
+    const size_t mat = (size_t)n * n * sizeof(cd) * M;
+    return 8 * align256(mat) + align256((size_t)M * n * sizeof(int));
+}
+
+// Alg. 1 after its scaling stage, for M matrices whose d_dt and d_s are on
+// the device (smax = max s on the host): products, LU solve, squarings.
+// Enqueue only, no host synchronisation; zero pivots are flagged in d_info.
+int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *d_s, int smax, cd *P, int *d_info,
+                      Workspace *ws, hipStream_t s) {
     const size_t nn = (size_t)n * n;
     const size_t mat = nn * sizeof(cd) * M;
-    LB_TRY(ws_ensure(ws, chunk_bytes(n, M)));
+    LB_TRY(ws_ensure(ws, build_async_bytes(n, M)));
     const size_t mark = ws->used;
     cd *A = (cd *)ws_take(ws, mat);
     cd *A2 = (cd *)ws_take(ws, mat);
@@ -172,10 +179,6 @@ static int build_chunk(int n, int M, const cd *L, const double *dt_host, double 
     cd *V = (cd *)ws_take(ws, mat);
     cd *Wp = (cd *)ws_take(ws, mat);
     cd *U = (cd *)ws_take(ws, mat);
-    double *d_dt = (double *)ws_take(ws, M * sizeof(double));
-    unsigned long long *d_norm = (unsigned long long *)ws_take(ws, M * sizeof(double));
-    int *d_s = (int *)ws_take(ws, M * sizeof(int));
-    int *d_info = (int *)ws_take(ws, M * sizeof(int));
     int *d_ipiv = (int *)ws_take(ws, (size_t)M * n * sizeof(int));
     struct Release {
         Workspace *w;
@@ -183,14 +186,7 @@ static int build_chunk(int n, int M, const cd *L, const double *dt_host, double 
         ~Release() { w->used = m; }
     } release{ws, mark};
 
-    fill_i32_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_info, M);
-    std::vector<int> sv(M);
-    LB_TRY(scaling_stage(n, M, L, dt_host, theta, d_dt, d_norm, d_s, sv.data(), s));
-    if (s_host) std::memcpy(s_host, sv.data(), M * sizeof(int));
-    int smax = 0;
-    for (int m = 0; m < M; ++m) smax = sv[m] > smax ? sv[m] : smax;
     LB_TRY(scale_launch(n, M, L, d_dt, d_s, A, s));
-
     double b[14];
     pade13_coefficients(b);
     ZgemmBatch g;
@@ -258,6 +254,32 @@ static int build_chunk(int n, int M, const cd *L, const double *dt_host, double 
         LB_TRY(zgemm_batched(h, s));
     }
     if (smax > 0) LB_TRY(odd_copy_launch(n, M, d_s, A4, P, s));
+    return LB_OK;
+}
+
+// One chunk of matrices (all buffers sized for `M` matrices): scaling stage,
+// the asynchronous build, then the pivot check (two host synchronisations).
+static int build_chunk(int n, int M, const cd *L, const double *dt_host, double theta, cd *P, int *s_host,
+                       Workspace *ws, hipStream_t s) {
+    LB_TRY(ws_ensure(ws, chunk_bytes(n, M)));
+    const size_t mark = ws->used;
+    double *d_dt = (double *)ws_take(ws, M * sizeof(double));
+    unsigned long long *d_norm = (unsigned long long *)ws_take(ws, M * sizeof(double));
+    int *d_s = (int *)ws_take(ws, M * sizeof(int));
+    int *d_info = (int *)ws_take(ws, M * sizeof(int));
+    struct Release {
+        Workspace *w;
+        size_t m;
+        ~Release() { w->used = m; }
+    } release{ws, mark};
+
+    fill_i32_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_info, M);
+    std::vector<int> sv(M);
+    LB_TRY(scaling_stage(n, M, L, dt_host, theta, d_dt, d_norm, d_s, sv.data(), s));
+    if (s_host) std::memcpy(s_host, sv.data(), M * sizeof(int));
+    int smax = 0;
+    for (int m = 0; m < M; ++m) smax = sv[m] > smax ? sv[m] : smax;
+    LB_TRY(build_chunk_async(n, M, L, d_dt, d_s, smax, P, d_info, ws, s));
     std::vector<int> info(M);
     LB_HIP(hipMemcpyAsync(info.data(), d_info, M * sizeof(int), hipMemcpyDeviceToHost, s));
     LB_HIP(hipStreamSynchronize(s));
