@@ -117,3 +117,17 @@ def test_chain_variant_lists_and_rule(L):
     assert L.lindblad_chain_variants(9, 0, 1, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 10
     assert L.lindblad_propagate_variant(9, 1, 0, 1, 1, 5, 999, None, None) == lb.EINVAL
     assert L.lindblad_tune(9, 1, 0, 1, 1, 0, 1, None, None, None, None) == lb.EINVAL
+
+
+def test_c_client_compiles_against_the_header(tmp_path):
+    """include/lindblad.h is plain C: the C client in tests/c builds with gcc
+    -std=c99 and links against liblindblad.so (it runs in the GPU tests)."""
+    import subprocess
+    from paper_2603_18052_amd import lindblad
+    lindblad.lib()
+    pkg = os.path.join(ROOT, "paper_2603_18052_amd")
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", "/opt/rocm/include", os.path.join(ROOT, "tests", "c", "abi_client.c"), "-o",
+           str(tmp_path / "abi_client"), "-L", pkg, "-llindblad", "-L", "/opt/rocm/lib", "-lamdhip64"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
