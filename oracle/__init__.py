@@ -64,6 +64,8 @@ def lib():
             "orc_expm_frechet_blocktri": (i, [i, p, p, d, p, p]),
             "orc_grape": (i, [i, i, i, p, p, p, d, d, p, p, p, p, p]),
             "orc_max_threads": (i, []),
+            "orc_quantize_q15": (None, [ll, p, p, p]),
+            "orc_propagate_q15": (None, [i, p, p, i, p, p, ll]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -227,6 +229,33 @@ def grape(L0, Lc, u, dt, x0, w, slices=None, theta=THETA, want_grad=True):
 
 def max_threads():
     return lib().orc_max_threads()
+
+
+# ------------------------------------------------------------ Alg. 5 (Q1.15)
+def quantize_q15(z):
+    """Q1.15 codes (re, im) of complex values: round to nearest, saturate."""
+    z = _c(z)
+    re = np.empty(z.shape, dtype=np.int16)
+    im = np.empty(z.shape, dtype=np.int16)
+    lib().orc_quantize_q15(z.size, _p(z), _p(re), _p(im))
+    return re, im
+
+
+def propagate_q15(P, rho, nsteps):
+    """Alg. 5 fixed-point chain: P and rho (B, n) or (B, d, d) complex are
+    quantised to Q1.15, nsteps exact-integer steps with floor truncation and
+    saturation run, and the codes (re, im) int16 (B, n) are returned."""
+    P = _c(P)
+    n = P.shape[0]
+    x = _c(rho).reshape(-1, n)
+    Pr, Pi = quantize_q15(P)
+    xr, xi = quantize_q15(x)
+    lib().orc_propagate_q15(n, _p(Pr), _p(Pi), x.shape[0], _p(xr), _p(xi), int(nsteps))
+    return xr, xi
+
+
+def from_q15(re, im):
+    return (np.asarray(re, dtype=np.float64) + 1j * np.asarray(im, dtype=np.float64)) / 32768.0
 
 
 # ------------------------------------------------------------ error metrics

@@ -15,12 +15,15 @@
  *            pivoting of the denominator                      -> orc_expm_pade13
  *   Alg. 2   row-major dense complex matvec                   -> orc_matvec
  *   Alg. 3   batch of independent states over threads         -> orc_propagate
+ *   Alg. 5   fixed-point (Q1.15) step: exact integer sums,
+ *            floor truncation and saturation            -> orc_propagate_q15
  * The GRAPE gradient (not in the paper) follows the chain rule with the
  * Frechet derivative of exp taken from the block-triangular identity
  * exp([[A, E], [0, A]]) = [[e^A, L(A,E)], [0, e^A]]   (Van Loan 1978).
  */
 #include <complex.h>
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -507,6 +510,57 @@ int orc_grape(int n, int M, int C, const zc *L0, const zc *Lc, const double *u, 
 done:
     free(P); free(xs); free(A); free(E); free(Lf); free(lam); free(tmp);
     return rc;
+}
+
+/* ------------------------------------------------------------ Alg. 5
+ * Q1.15 fixed point: a value v is the 16-bit integer q with v = q / 2^15.
+ * Quantisation of P and of the initial state rounds to nearest (ties to even)
+ * and saturates to [-2^15, 2^15 - 1] (1.0 itself saturates).  One step forms
+ * acc_i = sum_j P_ij x_j exactly in integers (each real product is Q2.30 and
+ * the sums need 33 + ceil(log2 n) bits, held in 64-bit integers), then
+ * x_i = sat(floor(acc_i / 2^15)) for the real and imaginary parts. */
+static int16_t sat16(long long v) { return (int16_t)(v < -32768 ? -32768 : (v > 32767 ? 32767 : v)); }
+
+void orc_quantize_q15(long long count, const zc *src, int16_t *re, int16_t *im)
+{
+    for (long long e = 0; e < count; ++e) {
+        re[e] = sat16((long long)nearbyint(creal(src[e]) * 32768.0));
+        im[e] = sat16((long long)nearbyint(cimag(src[e]) * 32768.0));
+    }
+}
+
+static long long floor_div_2_15(long long a)
+{
+    long long q = a / 32768;
+    if (a % 32768 != 0 && a < 0) q -= 1; /* C division truncates toward zero */
+    return q;
+}
+
+void orc_propagate_q15(int n, const int16_t *Pr, const int16_t *Pi, int B, int16_t *xr, int16_t *xi,
+                       long long nsteps)
+{
+    long long *ar = malloc((size_t)n * sizeof(long long)), *ai = malloc((size_t)n * sizeof(long long));
+    for (int b = 0; b < B; ++b) {
+        int16_t *vr = xr + (size_t)b * n, *vi = xi + (size_t)b * n;
+        for (long long t = 0; t < nsteps; ++t) {
+            for (int i = 0; i < n; ++i) {
+                long long sr = 0, si = 0;
+                for (int j = 0; j < n; ++j) {
+                    const long long pr = Pr[(size_t)i * n + j], pi = Pi[(size_t)i * n + j];
+                    sr += pr * vr[j] - pi * vi[j];
+                    si += pr * vi[j] + pi * vr[j];
+                }
+                ar[i] = sr;
+                ai[i] = si;
+            }
+            for (int i = 0; i < n; ++i) {
+                vr[i] = sat16(floor_div_2_15(ar[i]));
+                vi[i] = sat16(floor_div_2_15(ai[i]));
+            }
+        }
+    }
+    free(ar);
+    free(ai);
 }
 
 int orc_max_threads(void)

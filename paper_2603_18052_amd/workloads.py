@@ -130,6 +130,24 @@ def paper_grape_model(d: int, drive: float = 0.05):
     return H, Lk, 0.5
 
 
+def paper_fixed_point_model(drive: float = 0.05):
+    """The paper's d = 3 fixed-point drift model (its FPGA section): H0 =
+    diag(0, 1, 2) plus drive * sigma_x on the |0>-|1> pair, amplitude damping
+    with T1 = 50 and dephasing sqrt(1/T2 - 1/(2 T1)) a^dag a with T2 = 30
+    (dimensionless units), dt = 0.5, started from |0><0|.  Returns H, Lk, dt,
+    rho0."""
+    d = 3
+    a = annihilation(d)
+    H = np.diag(np.arange(d, dtype=np.float64)).astype(np.complex128)
+    H[0, 1] += drive
+    H[1, 0] += drive
+    t1, t2 = 50.0, 30.0
+    Lk = np.stack([np.sqrt(1.0 / t1) * a, np.sqrt(1.0 / t2 - 0.5 / t1) * (a.conj().T @ a)])
+    rho0 = np.zeros((d, d), dtype=np.complex128)
+    rho0[0, 0] = 1.0
+    return H, Lk, 0.5, rho0
+
+
 # ------------------------------------------------------------------- states
 def pure_state(d: int, g: np.random.Generator) -> np.ndarray:
     z = g.standard_normal(d) + 1j * g.standard_normal(d)
