@@ -55,9 +55,14 @@ typedef enum {
                            state rounded to FP32 after every step */
     LB_BF16_HILO = 2,   /* split BF16: P = Phi + Plo and x = xhi + xlo in BF16, products
                            Phi xhi + Phi xlo + Plo xhi on BF16 MFMA with FP32 accumulation */
-    LB_BF16_SLICED = 3  /* exponent-aligned BF16 integer slices of P (per row) and of each
+    LB_BF16_SLICED = 3, /* exponent-aligned BF16 integer slices of P (per row) and of each
                            state (per state): every slice product sums exactly in the FP32
                            MFMA accumulator; slice pairs are combined in FP64 */
+    LB_Q15 = 4          /* the paper's fixed-point step (Alg. 5): P and the state quantised to
+                           Q1.15 (16-bit, 15 fractional bits; round to nearest, ties to even,
+                           saturating, so 1.0 becomes 1 - 2^-15), each step's sums exact in
+                           64-bit integers, then floor(acc / 2^15) saturated.  Results are
+                           integers / 2^15, bitwise reproducible and independent of the kernel */
 } lb_precision;
 
 typedef struct lb_workspace lb_workspace;
@@ -155,7 +160,9 @@ int lindblad_propagate_baseline(int n, const void *P, int B, void *rho, long lon
  *   700       one BF16 plane-GEMM launch per step (BF16 precisions)
  *   800       whole chain in one launch, the two wavefronts of every SIMD
  *             balanced (81 <= n <= 84 LB_C128, <= 96 LB_C64)
- * Adding 50 to a per-step family (100, 500 + w, 600, 700) replays its steps
+ *   900       LB_Q15, one wavefront per state (n <= 16)
+ *   901       LB_Q15, one per-row matvec launch per step
+ * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901) replays its steps
  * from a HIP graph captured once per call (32 steps, replayed over all but
  * the last step).  Variants of one shape differ only in summation order. */
 

@@ -524,8 +524,8 @@ static int16_t sat16(long long v) { return (int16_t)(v < -32768 ? -32768 : (v > 
 void orc_quantize_q15(long long count, const zc *src, int16_t *re, int16_t *im)
 {
     for (long long e = 0; e < count; ++e) {
-        re[e] = sat16((long long)nearbyint(creal(src[e]) * 32768.0));
-        im[e] = sat16((long long)nearbyint(cimag(src[e]) * 32768.0));
+        re[e] = (int16_t)fmax(-32768.0, fmin(32767.0, nearbyint(creal(src[e]) * 32768.0)));
+        im[e] = (int16_t)fmax(-32768.0, fmin(32767.0, nearbyint(cimag(src[e]) * 32768.0)));
     }
 }
 

@@ -19,6 +19,7 @@ enum ChainFamily : int {
     VF_MATVEC = 6,      // per-state FP32 matvec, one launch per step (LB_C64)
     VF_PLANES = 7,      // one BF16 plane-GEMM launch per step
     VF_BALANCED = 8,    // fused chain with the SIMD-balanced layout (81 <= n <= 84 / 96)
+    VF_Q15 = 9,         // fixed-point chain (LB_Q15); param 0 one wavefront per state, 1 per-row matvec
 };
 inline int variant_family(int v) { return v / 100; }
 inline int variant_param(int v) { return v % 100; }
@@ -53,6 +54,9 @@ int chain_matvec(int n, const cd *P, lb_precision prec, int B, cd *rho, long lon
 int chain_planes(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
                  hipStream_t s, bool graph = false);
 size_t large_ws_bytes(int family, int n, lb_precision prec, int B);
+int chain_q15(int n, const cd *P, int B, cd *rho, long long nsteps, bool wave, bool graph, Workspace *ws,
+              hipStream_t s);
+size_t q15_ws_bytes(int n, int B, bool wave);
 
 // Variant selection (tune.hip): the list of variants that exist for a shape,
 // the built-in choice, the tuned choice if any, and the dispatcher.

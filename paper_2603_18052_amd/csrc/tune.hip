@@ -70,6 +70,9 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
     } else if (prec == LB_BF16_HILO || prec == LB_BF16_SLICED) {
         if (n <= bf16_fused_max_n(prec)) add(VF_BF16_FUSED * 100);
         add2(VF_PLANES * 100);
+    } else if (prec == LB_Q15) {
+        if (n <= kWaveChainMaxN) add(VF_Q15 * 100);
+        add2(VF_Q15 * 100 + 1);
     }
     return c;
 }
@@ -98,6 +101,8 @@ int chain_heuristic(int n, lb_precision prec, int B) {
         case LB_BF16_HILO:
         case LB_BF16_SLICED:
             return n <= bf16_fused_max_n(prec) ? VF_BF16_FUSED * 100 : VF_PLANES * 100;
+        case LB_Q15:
+            return n <= kWaveChainMaxN ? VF_Q15 * 100 : VF_Q15 * 100 + 1;
         default:
             return 0;
     }
@@ -114,6 +119,7 @@ static bool variant_listed(int n, lb_precision prec, int B, int variant) {
 size_t chain_ws_bytes(int n, lb_precision prec, int B, int variant) {
     const int fam = variant_family(variant);
     if (fam == VF_BASELINE) return align256((size_t)B * n * sizeof(cd));  // same for the graph twin
+    if (fam == VF_Q15) return q15_ws_bytes(n, B, variant_param(variant) == 0);
     return large_ws_bytes(fam, n, prec, B);
 }
 
@@ -133,6 +139,7 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_MATVEC: return chain_matvec(n, P, prec, B, rho, nsteps, ws, s, graph);
         case VF_PLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s, graph);
         case VF_BALANCED: return chain_balanced(n, P, prec, B, rho, nsteps, s);
+        case VF_Q15: return chain_q15(n, P, B, rho, nsteps, prm == 0, graph, ws, s);
         default: return fail(LB_EINVAL, "unknown chain variant");
     }
 }
@@ -149,7 +156,7 @@ int chain_run(int n, const cd *P, lb_precision prec, int B, cd *rho, long long n
 using namespace lb;
 
 static int check_prec(const char *who, lb_precision prec) {
-    if ((int)prec < LB_C128 || (int)prec > LB_BF16_SLICED) return fail(LB_EINVAL, std::string(who) + ": bad precision");
+    if ((int)prec < LB_C128 || (int)prec > LB_Q15) return fail(LB_EINVAL, std::string(who) + ": bad precision");
     return LB_OK;
 }
 
@@ -228,7 +235,8 @@ extern "C" int lindblad_tune(int n, const void *P, lb_precision prec, int B, con
         // a probe too short to replay a graph would time the direct twin again
         if (variant_param(ids[i]) >= kGraphVariant && probe_steps <= 2 * kGraphSteps &&
             (variant_family(ids[i]) == VF_BASELINE || variant_family(ids[i]) == VF_GEMM ||
-             variant_family(ids[i]) == VF_MATVEC || variant_family(ids[i]) == VF_PLANES))
+             variant_family(ids[i]) == VF_MATVEC || variant_family(ids[i]) == VF_PLANES ||
+             variant_family(ids[i]) == VF_Q15))
             continue;
         w->used = base;
         st = chain_run_variant(n, Pc, prec, B, x, probe_steps, ids[i], w, stream);  // warm-up

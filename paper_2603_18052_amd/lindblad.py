@@ -16,8 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblindblad.so")
 
 OK, EINVAL, ESHAPE, ENOMEM, EHIP, ESINGULAR, ENONFINITE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
-C128, C64, BF16_HILO, BF16_SLICED = 0, 1, 2, 3
-PRECISIONS = {"c128": C128, "c64": C64, "bf16_hilo": BF16_HILO, "bf16_sliced": BF16_SLICED}
+C128, C64, BF16_HILO, BF16_SLICED, Q15 = 0, 1, 2, 3, 4
+PRECISIONS = {"c128": C128, "c64": C64, "bf16_hilo": BF16_HILO, "bf16_sliced": BF16_SLICED, "q15": Q15}
 
 SYMBOLS = {
     # name: (restype, argtypes)
@@ -57,7 +57,7 @@ SYMBOLS = {
 
 # Chain variant families (id = family * 100 + tile parameter).
 VARIANT_FAMILIES = {1: "baseline", 2: "wave", 3: "fused", 4: "bf16_fused", 5: "gemm", 6: "matvec32", 7: "planes",
-                    8: "fused_balanced"}
+                    8: "fused_balanced", 9: "q15"}
 
 
 GRAPH_VARIANT = 50  # added to a per-step family: steps replayed from a captured HIP graph
@@ -66,12 +66,14 @@ GRAPH_VARIANT = 50  # added to a per-step family: steps replayed from a captured
 def variant_name(v: int) -> str:
     fam, prm = divmod(int(v), 100)
     name = VARIANT_FAMILIES.get(fam, f"family{fam}")
-    graph = fam in (1, 5, 6, 7) and prm >= GRAPH_VARIANT
-    prm = prm % GRAPH_VARIANT if fam in (1, 5, 6, 7) else prm
+    graph = fam in (1, 5, 6, 7, 9) and prm >= GRAPH_VARIANT
+    prm = prm % GRAPH_VARIANT if fam in (1, 5, 6, 7, 9) else prm
     if fam == 3:
         name = f"{name}(k{prm})"
     elif fam == 5:
         name = f"{name}(w{prm})"
+    elif fam == 9:
+        name = f"{name}_{'wave' if prm == 0 else 'matvec'}"
     return name + "+graph" if graph else name
 
 

@@ -58,6 +58,7 @@ def test_validation_errors_without_gpu(L):
     assert L.lindblad_propagate(9, 1, 0, 0, 1, 1, None, None) == lb.ESHAPE
     assert L.lindblad_propagate(9, 1, 0, 1, 1, -1, None, None) == lb.EINVAL
     assert L.lindblad_propagate(9, 1, 9, 1, 1, 1, None, None) == lb.EINVAL
+    assert L.lindblad_propagate(9, 1, 5, 1, 1, 1, None, None) == lb.EINVAL  # past the last precision
     assert L.lindblad_propagate(9, None, 0, 1, 1, 1, None, None) == lb.EINVAL
     assert L.lindblad_propagate_baseline(5000, 1, 1, 1, 1, None, None) == lb.ESHAPE
 
@@ -104,6 +105,10 @@ def test_chain_variant_lists_and_rule(L):
     assert [lb.variant_name(x) for x in (150, 552, 306, 800)] == ["baseline+graph", "gemm(w2)+graph", "fused(k6)",
                                                                    "fused_balanced"]
     assert lb.chain_variant(729, "bf16_hilo", 16) == 700
+    # fixed point: one wavefront per state for n <= 16, else the per-row matvec (and its graph twin)
+    assert lb.chain_variants(9, "q15", 1) == [900, 901, 951]
+    assert lb.chain_variants(729, "q15", 3) == [901, 951]
+    assert lb.chain_variant(81, "q15", 16) == 901
     # tuning table: set, read back, reject a variant the shape lacks, clear
     lb.tune_set(81, "c128", 4096, 502)
     assert lb.chain_variant(81, "c128", 4096) == 502
