@@ -121,13 +121,16 @@ def _traffic(kernel):
 
 KERNEL_OF_FAMILY = {1: "baseline_step_kernel", 2: "wave_chain_kernel", 3: "fused_chain_kernel",
                     4: "bf16_chain_kernel", 5: "gemm_step_kernel", 6: "matvec_step_kernel", 7: "plane_gemm_kernel",
-                    8: "balanced_chain_kernel"}
+                    8: "balanced_chain_kernel", 10: "tail_chain_kernel"}
 
 
 def kernel_of(variant, prec):
     """Name of the chain kernel a variant launches (as rocprofv3 lists it, templates abbreviated)."""
     fam = variant // 100
     base = KERNEL_OF_FAMILY.get(fam, "unknown")
+    if fam == 10:
+        base = "tiles_chain_kernel" if variant % 100 == 2 else "tail_chain_kernel"
+        return base + ("<double" if prec == "c128" else "<float") + (">" if variant % 100 == 2 else ", 1, ...>")
     if fam in (2, 3, 5, 8):
         return base + ("<double>" if prec == "c128" else "<float>")
     if fam in (4, 7):

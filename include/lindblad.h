@@ -134,7 +134,9 @@ int lindblad_propagator(int n, int M, const void *L, const double *dt, double th
  * n <= 16 (LB_C128, LB_C64); the plain per-state matvec for LB_C128 when
  * B n^2 <= 1.1e6; the whole chain in one launch with P on chip while it fits
  * one compute unit's LDS (n <= 84 LB_C128, 124 LB_C64, 85 LB_BF16_SLICED,
- * 96 LB_BF16_HILO; the SIMD-balanced layout for 81 <= n <= 84 / 96); beyond
+ * 96 LB_BF16_HILO; for n = 81 rows and columns 0..79 on MFMA and row and
+ * column 80 on the vector ALUs, else the SIMD-balanced layout for
+ * 81 <= n <= 84 / 96); beyond
  * that one MFMA GEMM launch per step (B >= 16) or a per-state matvec
  * (B < 16). */
 int lindblad_propagate(int n, const void *P, lb_precision prec, int B, void *rho, long long nsteps,
@@ -162,6 +164,12 @@ int lindblad_propagate_baseline(int n, const void *P, int B, void *rho, long lon
  *             balanced (81 <= n <= 84 LB_C128, <= 96 LB_C64)
  *   900       LB_Q15, one wavefront per state (n <= 16)
  *   901       LB_Q15, one per-row matvec launch per step
+ *   1000      whole chain in one launch, rows 0..79 on MFMA in three k parts
+ *             per tile, row 80 on the vector ALUs (n = 81, LB_C128 / LB_C64)
+ *   1001      the same with 16 wavefronts per workgroup, one part each
+ *   1002      whole chain in one launch, rows and columns 0..79 on MFMA with
+ *             one whole 16-row tile per wavefront, row and column 80 on the
+ *             vector ALUs (n = 81, LB_C128 / LB_C64)
  * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901) replays its steps
  * from a HIP graph captured once per call (32 steps, replayed over all but
  * the last step).  Variants of one shape differ only in summation order. */

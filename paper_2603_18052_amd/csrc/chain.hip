@@ -160,12 +160,19 @@ struct Mfma<double> {
     typedef d4 acc;
     static __device__ inline acc mma(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
     static __device__ inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+    // -a b + c through the instruction's negate-A modifier (the last operand
+    // of the FP64 MFMA builtin selects neg:[a, b, c]); `na` (= -a) is unused
+    static __device__ inline acc mma_neg_a(double a, double na, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 1);
+    }
 };
 template <>
 struct Mfma<float> {
     typedef f4 acc;
     static __device__ inline acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+    // -a b + c with the negated fragment `na` held in registers
+    static __device__ inline acc mma_neg_a(float a, float na, float b, acc c) { return mma(na, b, c); }
 };
 
 struct FusedShape {
@@ -444,6 +451,392 @@ int chain_balanced(int n, const cd *P, lb_precision prec, int B, cd *rho, long l
         case 23: return launch_balanced_k<float, 23>(n, P, B, rho, nsteps, s);
         default: return launch_balanced_k<float, 24>(n, P, B, rho, nsteps, s);
     }
+}
+
+// ------------------------------------------------ MFMA rows + VALU tail chain
+// For n = 81 (d = 9) the sixth 16-row MFMA tile of the layouts above carries
+// one useful row in sixteen.  This layout runs rows 0..79 on MFMA and the
+// NV = n - 80 rows past them on the vector ALUs.  Tiles 0..4 are cut into
+// three parts of 7 k steps (KS = 21): part p = 3 tile + q covers k steps
+// [7q, 7q + 7) and writes partial slot p.  With WPB wavefronts a workgroup
+// (8 or 16, wavefront w on SIMD w % 4), wavefront w owns the NPW = 16 / WPB
+// parts NPW w .. NPW w + NPW - 1 below 15, so SIMDs 0..2 issue four parts a
+// step (112 MFMAs against 128 in the balanced layout) and SIMD 3 three parts,
+// one of each q: (6, 7, 14) with 8 wavefronts, (3, 7, 11) with 16.  The
+// SIMD-3 wavefronts holding parts also multiply the x values they load for
+// their MFMAs by the tail rows of P (registers), reduce over the four
+// k lanes of each state and write partial slot 15 + q (q of their first part)
+// of k-tile 5 (a slot no wavefront writes stays zero).  Every x operand is the
+// sum of its k-tile's three slots, double-buffered, one barrier per step.
+// Slots hold (re, im) pairs so one LDS instruction reads one complex value.
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+    T re, im;
+};
+
+constexpr int kTailKS = 21;      // k steps (n <= 84)
+constexpr int kTailPartKs = 7;   // k steps per part
+constexpr int kTailParts = 15;   // 5 tiles x 3 parts
+constexpr int kTailSlots = 18;   // 6 k-tiles x 3 partials
+constexpr int kTailBuf = kTailSlots * 256;
+
+template <typename T, int NV, bool TAIL>
+__device__ inline void tail_part(const Pair<T> *__restrict__ cur, const T (&fr)[kTailPartKs],
+                                 const T (&fi)[kTailPartKs], const T (&tr)[kTailPartKs][NV],
+                                 const T (&ti)[kTailPartKs][NV], const int (&xoff)[kTailPartKs],
+                                 typename Mfma<T>::acc &ar, typename Mfma<T>::acc &ai, T (&sr)[NV], T (&si)[NV]) {
+#pragma unroll
+    for (int f = 0; f < kTailPartKs; ++f) {
+        const Pair<T> *c = cur + xoff[f];
+        const Pair<T> x0 = c[0], x1 = c[256], x2 = c[512];
+        const T xr = x0.re + x1.re + x2.re, xi = x0.im + x1.im + x2.im;
+        ar = Mfma<T>::mma(fr[f], xr, ar);
+        ai = Mfma<T>::mma(fr[f], xi, ai);
+        ar = Mfma<T>::mma(fi[f], -xi, ar);
+        ai = Mfma<T>::mma(fi[f], xr, ai);
+        if (TAIL) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                sr[v] += tr[f][v] * xr - ti[f][v] * xi;
+                si[v] += tr[f][v] * xi + ti[f][v] * xr;
+            }
+        }
+    }
+}
+
+template <typename T, int NV, int WPB>
+__global__ void __launch_bounds__(WPB * 64) tail_chain_kernel(int n, const cd *__restrict__ P, int B,
+                                                              cd *__restrict__ rho, long long nsteps) {
+    typedef typename Mfma<T>::acc acc_t;
+    constexpr int NPW = 16 / WPB;
+    constexpr int Kp = 4 * kTailKS;
+    static_assert(WPB == 8 || WPB == 16, "8 or 16 wavefronts");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Pair<T> *slots = reinterpret_cast<Pair<T> *>(smem_raw);  // [2][kTailSlots][256]
+    const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, j = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int p0 = NPW * wave;                            // first part of this wavefront
+    const bool tail = (wave & 3) == 3 && p0 < kTailParts;  // SIMD 3, holding parts
+    const int tail_slot = 15 + p0 % 3;
+    const int b0 = blockIdx.x * NS;
+
+    T fr[NPW][kTailPartKs], fi[NPW][kTailPartKs];
+    T tr[NPW][kTailPartKs][NV], ti[NPW][kTailPartKs][NV];
+    int xoff[NPW][kTailPartKs];  // entry of slot 0 of the lane's k-tile in a buffer
+#pragma unroll
+    for (int a = 0; a < NPW; ++a) {
+        const int p = p0 + a;
+        const bool live = p < kTailParts;
+        const int tile = live ? p / 3 : 0, q = live ? p % 3 : 0;
+#pragma unroll
+        for (int f = 0; f < kTailPartKs; ++f) {
+            const int k = 4 * (kTailPartKs * q + f) + g;  // < Kp
+            cd v = {0.0, 0.0};
+            if (live && k < n) v = P[(size_t)(tile * 16 + j) * n + k];
+            fr[a][f] = (T)v.re;
+            fi[a][f] = (T)v.im;
+#pragma unroll
+            for (int r = 0; r < NV; ++r) {
+                cd u = {0.0, 0.0};
+                if (live && tail && k < n) u = P[(size_t)(80 + r) * n + k];
+                tr[a][f][r] = (T)u.re;
+                ti[a][f][r] = (T)u.im;
+            }
+            xoff[a][f] = 3 * (k >> 4) * 256 + (k & 15) * 16 + j;
+        }
+    }
+    // initial states: slot 3 (k >> 4) holds x, the other two zero (buffer 0)
+    for (int e = tid; e < 2 * kTailBuf; e += WPB * 64) slots[e] = Pair<T>{(T)0, (T)0};
+    __syncthreads();
+    for (int e = tid; e < Kp * NS; e += WPB * 64) {
+        const int k = e / NS, sidx = e - k * NS;
+        cd v = {0.0, 0.0};
+        if (k < n && b0 + sidx < B) v = rho[(size_t)(b0 + sidx) * n + k];
+        slots[3 * (k >> 4) * 256 + (k & 15) * 16 + sidx] = Pair<T>{(T)v.re, (T)v.im};
+    }
+    __syncthreads();
+
+    for (long long t = 0; t < nsteps; ++t) {
+        const Pair<T> *cur = slots + (t & 1) * kTailBuf;
+        Pair<T> *nxt = slots + ((t & 1) ^ 1) * kTailBuf;
+        T sr[NV], si[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sr[v] = si[v] = (T)0;
+#pragma unroll
+        for (int a = 0; a < NPW; ++a) {
+            if (p0 + a >= kTailParts) break;  // uniform per wavefront
+            acc_t ar = acc_t{0, 0, 0, 0}, ai = acc_t{0, 0, 0, 0};
+            if (tail)
+                tail_part<T, NV, true>(cur, fr[a], fi[a], tr[a], ti[a], xoff[a], ar, ai, sr, si);
+            else
+                tail_part<T, NV, false>(cur, fr[a], fi[a], tr[a], ti[a], xoff[a], ar, ai, sr, si);
+            Pair<T> *dst = nxt + (p0 + a) * 256;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dst[Mfma<T>::row(lane, r) * 16 + j] = Pair<T>{ar[r], ai[r]};
+        }
+        if (tail) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                sr[v] += __shfl_xor(sr[v], 16);
+                si[v] += __shfl_xor(si[v], 16);
+                sr[v] += __shfl_xor(sr[v], 32);
+                si[v] += __shfl_xor(si[v], 32);
+            }
+            T wr = sr[0], wi = si[0];
+#pragma unroll
+            for (int v = 1; v < NV; ++v)
+                if (g == v) wr = sr[v], wi = si[v];
+            if (g < NV) nxt[tail_slot * 256 + g * 16 + j] = Pair<T>{wr, wi};
+        }
+        __syncthreads();
+    }
+    const Pair<T> *fin = slots + (nsteps & 1) * kTailBuf;
+    for (int e = tid; e < n * NS; e += WPB * 64) {
+        const int sidx = e / n, k = e - sidx * n;
+        const Pair<T> *c = fin + 3 * (k >> 4) * 256 + (k & 15) * 16 + sidx;
+        if (b0 + sidx < B)
+            rho[(size_t)(b0 + sidx) * n + k] = {(double)(c[0].re + c[256].re + c[512].re),
+                                                (double)(c[0].im + c[256].im + c[512].im)};
+    }
+}
+
+template <typename T, int NV, int WPB>
+static int launch_tail_k(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
+    const size_t lds = sizeof(Pair<T>) * 2 * (size_t)kTailBuf;
+    static bool attr_set = false;
+    if (!attr_set) {
+        LB_HIP(hipFuncSetAttribute((const void *)tail_chain_kernel<T, NV, WPB>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    tail_chain_kernel<T, NV, WPB><<<(B + NS - 1) / NS, WPB * 64, lds, s>>>(n, P, B, rho, nsteps);
+    return check_launch("tail_chain");
+}
+
+// Whole-tile layout for n = 81 (variant param 2).  The MFMAs cover rows
+// 0..79 and columns 0..79 of P (20 k steps, no padding); row 80 and column 80
+// run on the VALU.  Wavefront s = 0..3 (SIMD s) owns output tile s over all
+// 20 k steps, so rows 16 s .. 16 s + 15 end each step complete in its
+// registers: slot s of the next buffer holds x of k-tile s.  Its two
+// accumulators start the step at P[rows, 80] x_80 (column 80 as a rank-1
+// term).  Wavefront 4 + s (SIMD s) owns k steps [5 s, 5 s + 5) of tile 4 and
+// writes partial slot 4 + s (the last one starting from P[64..79, 80] x_80),
+// and runs row 80 over the same columns (the last one also P[80, 80] x_80)
+// on the VALU into partial slot 8 + s (entries of row 80 only).  x of k-tiles 0..3 is one LDS read per fragment that goes
+// straight into the MFMA; x of k-tile 4 and x_80 sum four slots.  Each SIMD
+// issues 80 + 20 = 100 MFMAs a step.  The product with -fi is the FP64
+// MFMA's negate modifier, or a negated copy in registers for FP32, so the
+// long wavefront's MFMA operands come from LDS or registers with no vector
+// op in between.
+constexpr int kTilesKS = 20;     // MFMA k steps: columns 0..79
+constexpr int kTilesSlots = 12;
+constexpr int kTilesBuf = kTilesSlots * 256;
+constexpr int kTilesShort = 5;   // k steps of a short wavefront
+
+template <typename T>
+__device__ inline void tiles_store(Pair<T> *__restrict__ dst, int lane, const typename Mfma<T>::acc &ar,
+                                   const typename Mfma<T>::acc &ai) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst[Mfma<T>::row(lane, r) * 16 + (lane & 15)] = Pair<T>{ar[r], ai[r]};
+}
+
+// x of k step ks for this lane: one slot (k-tiles 0..3) or the sum of the
+// four partial slots of k-tile 4
+template <typename T, bool SUM4>
+__device__ inline void tiles_x(const Pair<T> *__restrict__ cur, int ks, int lane, T &xr, T &xi) {
+    const int e = lane + 64 * (ks & 3);
+    if (!SUM4) {
+        const Pair<T> v = cur[(ks >> 2) * 256 + e];
+        xr = v.re, xi = v.im;
+    } else {
+        const Pair<T> *c = cur + 4 * 256 + e;
+        const Pair<T> a = c[0], b = c[256], d = c[512], f = c[768];
+        xr = (a.re + b.re) + (d.re + f.re);
+        xi = (a.im + b.im) + (d.im + f.im);
+    }
+}
+
+// x_80 of state j: the four partial slots of row 80
+template <typename T>
+__device__ inline void tiles_x80(const Pair<T> *__restrict__ cur, int j, T &xr, T &xi) {
+    const Pair<T> *c = cur + 8 * 256 + j;
+    const Pair<T> a = c[0], b = c[256], d = c[512], f = c[768];
+    xr = (a.re + b.re) + (d.re + f.re);
+    xi = (a.im + b.im) + (d.im + f.im);
+}
+
+// short wavefront s = 0..3: k steps [5 s, 5 s + 5) of tile 4 and of row 80;
+// LAST (s = 3): k steps 15..19, the last four in k-tile 4, plus column 80
+// (P[64..79, 80] x_80 as the accumulators' starting value, P[80, 80] x_80)
+template <typename T, bool LAST>
+__device__ inline void tiles_short(int n, const cd *__restrict__ P, Pair<T> *__restrict__ slots, int s, int lane,
+                                   long long nsteps) {
+    typedef typename Mfma<T>::acc acc_t;
+    const int g = lane >> 4, j = lane & 15, kb = kTilesShort * s;
+    T fr[kTilesShort], fi[kTilesShort], fn[kTilesShort], tr[kTilesShort], ti[kTilesShort];
+#pragma unroll
+    for (int f = 0; f < kTilesShort; ++f) {
+        const int k = 4 * (kb + f) + g;  // < 80 <= n
+        const cd v = P[(size_t)(64 + j) * n + k], u = P[(size_t)80 * n + k];
+        fr[f] = (T)v.re, fi[f] = (T)v.im, fn[f] = -(T)v.im;
+        tr[f] = (T)u.re, ti[f] = (T)u.im;
+    }
+    // LAST: column 80 of tile 4 (accumulator layout) and P[80, 80]
+    T cr[4], ci[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        cd v = {0.0, 0.0};
+        if (LAST) v = P[(size_t)(64 + Mfma<T>::row(lane, r)) * n + 80];
+        cr[r] = (T)v.re, ci[r] = (T)v.im;
+    }
+    cd p80 = {0.0, 0.0};
+    if (LAST && g == 0) p80 = P[(size_t)80 * n + 80];
+    const T qr = (T)p80.re, qi = (T)p80.im;
+    for (long long t = 0; t < nsteps; ++t) {
+        const Pair<T> *cur = slots + (t & 1) * kTilesBuf;
+        Pair<T> *nxt = slots + ((t & 1) ^ 1) * kTilesBuf;
+        acc_t a0 = acc_t{0, 0, 0, 0}, a1 = a0;
+        T sr = 0, si = 0;
+        if (LAST) {
+            T xr, xi;
+            tiles_x80<T>(cur, j, xr, xi);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                a0[r] = cr[r] * xr - ci[r] * xi;
+                a1[r] = cr[r] * xi + ci[r] * xr;
+            }
+            sr = qr * xr - qi * xi;
+            si = qr * xi + qi * xr;
+        }
+#pragma unroll
+        for (int f = 0; f < kTilesShort; ++f) {
+            T xr, xi;
+            if (LAST && f > 0)
+                tiles_x<T, true>(cur, kb + f, lane, xr, xi);
+            else
+                tiles_x<T, false>(cur, kb + f, lane, xr, xi);
+            a0 = Mfma<T>::mma(fr[f], xr, a0);
+            a1 = Mfma<T>::mma(fr[f], xi, a1);
+            a0 = Mfma<T>::mma_neg_a(fi[f], fn[f], xi, a0);
+            a1 = Mfma<T>::mma(fi[f], xr, a1);
+            sr += tr[f] * xr - ti[f] * xi;
+            si += tr[f] * xi + ti[f] * xr;
+        }
+        tiles_store<T>(nxt + (4 + s) * 256, lane, a0, a1);
+        sr += __shfl_xor(sr, 16);
+        si += __shfl_xor(si, 16);
+        sr += __shfl_xor(sr, 32);
+        si += __shfl_xor(si, 32);
+        if (g == 0) nxt[(8 + s) * 256 + j] = Pair<T>{sr, si};
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(CW * 64) tiles_chain_kernel(int n, const cd *__restrict__ P, int B,
+                                                              cd *__restrict__ rho, long long nsteps) {
+    typedef typename Mfma<T>::acc acc_t;
+    constexpr int KS = kTilesKS, Kp = 4 * KS + 16;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Pair<T> *slots = reinterpret_cast<Pair<T> *>(smem_raw);  // [2][kTilesSlots][256]
+    const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, j = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int b0 = blockIdx.x * NS;
+
+    for (int e = tid; e < 2 * kTilesBuf; e += CW * 64) slots[e] = Pair<T>{(T)0, (T)0};
+    __syncthreads();
+    for (int e = tid; e < Kp * NS; e += CW * 64) {
+        const int k = e / NS, sidx = e - k * NS, kt = k >> 4;
+        cd v = {0.0, 0.0};
+        if (k < n && b0 + sidx < B) v = rho[(size_t)(b0 + sidx) * n + k];
+        slots[(kt < 4 ? kt : (kt == 4 ? 4 : 8)) * 256 + (k & 15) * 16 + sidx] = Pair<T>{(T)v.re, (T)v.im};
+    }
+    __syncthreads();
+
+    if (wave < 4) {
+        // long wavefront: tile `wave`, columns 0..79 on MFMA, column 80 as the
+        // accumulators' starting value
+        T fr[KS], fi[KS], fn[KS], cr[4], ci[4];
+#pragma unroll
+        for (int f = 0; f < KS; ++f) {
+            const cd v = P[(size_t)(wave * 16 + j) * n + 4 * f + g];
+            fr[f] = (T)v.re, fi[f] = (T)v.im, fn[f] = -(T)v.im;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const cd v = P[(size_t)(wave * 16 + Mfma<T>::row(lane, r)) * n + 80];
+            cr[r] = (T)v.re, ci[r] = (T)v.im;
+        }
+        for (long long t = 0; t < nsteps; ++t) {
+            const Pair<T> *cur = slots + (t & 1) * kTilesBuf;
+            Pair<T> *nxt = slots + ((t & 1) ^ 1) * kTilesBuf;
+            T x80r, x80i;
+            tiles_x80<T>(cur, j, x80r, x80i);
+            acc_t a0, a1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                a0[r] = cr[r] * x80r - ci[r] * x80i;
+                a1[r] = cr[r] * x80i + ci[r] * x80r;
+            }
+#pragma unroll
+            for (int f = 0; f < KS; ++f) {
+                T xr, xi;
+                if (f < 16)
+                    tiles_x<T, false>(cur, f, lane, xr, xi);
+                else
+                    tiles_x<T, true>(cur, f, lane, xr, xi);
+                a0 = Mfma<T>::mma(fr[f], xr, a0);
+                a1 = Mfma<T>::mma(fr[f], xi, a1);
+                a0 = Mfma<T>::mma_neg_a(fi[f], fn[f], xi, a0);
+                a1 = Mfma<T>::mma(fi[f], xr, a1);
+            }
+            tiles_store<T>(nxt + wave * 256, lane, a0, a1);
+            __syncthreads();
+        }
+    } else if (wave < 7) {
+        tiles_short<T, false>(n, P, slots, wave - 4, lane, nsteps);
+    } else {
+        tiles_short<T, true>(n, P, slots, 3, lane, nsteps);
+    }
+    const Pair<T> *fin = slots + (nsteps & 1) * kTilesBuf;
+    for (int e = tid; e < n * NS; e += CW * 64) {
+        const int sidx = e / n, k = e - sidx * n, kt = k >> 4;
+        const Pair<T> *c = fin + (kt < 4 ? kt : (kt == 4 ? 4 : 8)) * 256 + (k & 15) * 16 + sidx;
+        Pair<T> v = c[0];
+        if (kt >= 4) {
+            v.re = (c[0].re + c[256].re) + (c[512].re + c[768].re);
+            v.im = (c[0].im + c[256].im) + (c[512].im + c[768].im);
+        }
+        if (b0 + sidx < B) rho[(size_t)(b0 + sidx) * n + k] = {(double)v.re, (double)v.im};
+    }
+}
+
+template <typename T>
+static int launch_tiles_k(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
+    const size_t lds = sizeof(Pair<T>) * 2 * (size_t)kTilesBuf;
+    static bool attr_set = false;
+    if (!attr_set) {
+        LB_HIP(hipFuncSetAttribute((const void *)tiles_chain_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+        attr_set = true;
+    }
+    tiles_chain_kernel<T><<<(B + NS - 1) / NS, CW * 64, lds, s>>>(n, P, B, rho, nsteps);
+    return check_launch("tiles_chain");
+}
+
+bool tail_ok(int n, lb_precision prec) { return (prec == LB_C128 || prec == LB_C64) && n == 81; }
+
+int chain_tail(int n, const cd *P, lb_precision prec, int wide, int B, cd *rho, long long nsteps, hipStream_t s) {
+    if (nsteps == 0 || B == 0) return LB_OK;
+    if (!tail_ok(n, prec)) return fail(LB_ESHAPE, "MFMA + tail chain: n = 81");
+    if (prec == LB_C128) {
+        if (wide == 2) return launch_tiles_k<double>(n, P, B, rho, nsteps, s);
+        return wide ? launch_tail_k<double, 1, 16>(n, P, B, rho, nsteps, s)
+                    : launch_tail_k<double, 1, 8>(n, P, B, rho, nsteps, s);
+    }
+    if (wide == 2) return launch_tiles_k<float>(n, P, B, rho, nsteps, s);
+    return wide ? launch_tail_k<float, 1, 16>(n, P, B, rho, nsteps, s)
+                : launch_tail_k<float, 1, 8>(n, P, B, rho, nsteps, s);
 }
 
 

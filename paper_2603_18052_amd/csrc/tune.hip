@@ -64,6 +64,11 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
         const int nk = fused_kpus(n, prec, kpus, 8);
         for (int i = 0; i < nk; ++i) add(VF_FUSED * 100 + kpus[i]);
         if (balanced_ok(n, prec)) add(VF_BALANCED * 100);
+        if (tail_ok(n, prec)) {
+            add(VF_TAIL * 100);
+            add(VF_TAIL * 100 + 1);
+            add(VF_TAIL * 100 + 2);
+        }
         add2(VF_GEMM * 100 + 1);
         add2(VF_GEMM * 100 + 2);
         if (prec == LB_C64) add2(VF_MATVEC * 100);
@@ -81,8 +86,11 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
 // chains): the register-resident wave chain for n <= 16 at every batch size;
 // for FP64 with little work per step (B n^2 up to ~1e6) the plain per-state
 // matvec, whose step is shorter than the fused kernel's 8-wavefront MFMA
-// step; the SIMD-balanced fused chain where its layout exists (81 <= n <= 84
-// / 96, 17-20 % faster than the round-robin units there), the round-robin
+// step; for n = 81 the fused chain with rows and columns 0..79 on MFMA, one
+// whole 16-row tile per long wavefront, and row / column 80 on the VALU
+// (21-26 % faster than the SIMD-balanced layout), else the SIMD-balanced
+// fused chain where its layout exists (81 <= n <= 84 / 96, 17-20 % faster
+// than the round-robin units there), the round-robin
 // fused chain elsewhere while P fits in one CU's LDS; otherwise a
 // GEMM per step with one output tile per wavefront up to 256 states (more
 // workgroups) and two beyond, or a matvec for few states.
@@ -92,6 +100,7 @@ int chain_heuristic(int n, lb_precision prec, int B) {
         case LB_C64: {
             if (n <= kWaveChainMaxN) return VF_WAVE * 100;
             if (prec == LB_C128 && (double)B * n * n <= 1.1e6) return VF_BASELINE * 100;
+            if (tail_ok(n, prec)) return VF_TAIL * 100 + 2;
             if (balanced_ok(n, prec)) return VF_BALANCED * 100;
             int kpu;
             if (fused_kpus(n, prec, &kpu, 1) == 1) return VF_FUSED * 100 + kpu;
@@ -140,6 +149,7 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_PLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s, graph);
         case VF_BALANCED: return chain_balanced(n, P, prec, B, rho, nsteps, s);
         case VF_Q15: return chain_q15(n, P, B, rho, nsteps, prm == 0, graph, ws, s);
+        case VF_TAIL: return chain_tail(n, P, prec, prm, B, rho, nsteps, s);
         default: return fail(LB_EINVAL, "unknown chain variant");
     }
 }

@@ -57,7 +57,7 @@ SYMBOLS = {
 
 # Chain variant families (id = family * 100 + tile parameter).
 VARIANT_FAMILIES = {1: "baseline", 2: "wave", 3: "fused", 4: "bf16_fused", 5: "gemm", 6: "matvec32", 7: "planes",
-                    8: "fused_balanced", 9: "q15"}
+                    8: "fused_balanced", 9: "q15", 10: "fused_tail"}
 
 
 GRAPH_VARIANT = 50  # added to a per-step family: steps replayed from a captured HIP graph
@@ -74,6 +74,8 @@ def variant_name(v: int) -> str:
         name = f"{name}(w{prm})"
     elif fam == 9:
         name = f"{name}_{'wave' if prm == 0 else 'matvec'}"
+    elif fam == 10 and prm in (1, 2):
+        name = f"{name}({'w16' if prm == 1 else 'tiles'})"
     return name + "+graph" if graph else name
 
 
