@@ -129,8 +129,10 @@ def kernel_of(variant, prec):
     fam = variant // 100
     base = KERNEL_OF_FAMILY.get(fam, "unknown")
     if fam == 10:
-        base = "tiles_chain_kernel" if variant % 100 == 2 else "tail_chain_kernel"
-        return base + ("<double" if prec == "c128" else "<float") + (">" if variant % 100 == 2 else ", 1, ...>")
+        t = "double" if prec == "c128" else "float"
+        if variant % 100 >= 2:
+            return f"tiles_chain_kernel<{t}, {'true' if variant % 100 == 3 else 'false'}>"
+        return f"tail_chain_kernel<{t}, 1, {16 if variant % 100 == 1 else 8}>"
     if fam in (2, 3, 5, 8):
         return base + ("<double>" if prec == "c128" else "<float>")
     if fam in (4, 7):

@@ -170,6 +170,8 @@ int lindblad_propagate_baseline(int n, const void *P, int B, void *rho, long lon
  *   1002      whole chain in one launch, rows and columns 0..79 on MFMA with
  *             one whole 16-row tile per wavefront, row and column 80 on the
  *             vector ALUs (n = 81, LB_C128 / LB_C64)
+ *   1003      the same with the partial sums of rows 64..80 formed once a
+ *             step by the last wavefront to finish them
  * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901) replays its steps
  * from a HIP graph captured once per call (32 steps, replayed over all but
  * the last step).  Variants of one shape differ only in summation order. */

@@ -613,21 +613,26 @@ static int launch_tail_k(int n, const cd *P, int B, cd *rho, long long nsteps, h
     return check_launch("tail_chain");
 }
 
-// Whole-tile layout for n = 81 (variant param 2).  The MFMAs cover rows
-// 0..79 and columns 0..79 of P (20 k steps, no padding); row 80 and column 80
-// run on the VALU.  Wavefront s = 0..3 (SIMD s) owns output tile s over all
-// 20 k steps, so rows 16 s .. 16 s + 15 end each step complete in its
+// Whole-tile layout for n = 81 (variant params 2 and 3).  The MFMAs cover
+// rows 0..79 and columns 0..79 of P (20 k steps, no padding); row 80 and
+// column 80 run on the VALU.  Wavefront s = 0..3 (SIMD s) owns output tile s
+// over all 20 k steps, so rows 16 s .. 16 s + 15 end each step complete in its
 // registers: slot s of the next buffer holds x of k-tile s.  Its two
 // accumulators start the step at P[rows, 80] x_80 (column 80 as a rank-1
 // term).  Wavefront 4 + s (SIMD s) owns k steps [5 s, 5 s + 5) of tile 4 and
 // writes partial slot 4 + s (the last one starting from P[64..79, 80] x_80),
-// and runs row 80 over the same columns (the last one also P[80, 80] x_80)
-// on the VALU into partial slot 8 + s (entries of row 80 only).  x of k-tiles 0..3 is one LDS read per fragment that goes
-// straight into the MFMA; x of k-tile 4 and x_80 sum four slots.  Each SIMD
-// issues 80 + 20 = 100 MFMAs a step.  The product with -fi is the FP64
-// MFMA's negate modifier, or a negated copy in registers for FP32, so the
-// long wavefront's MFMA operands come from LDS or registers with no vector
-// op in between.
+// and runs row 80 over the same columns (the last one also P[80, 80] x_80) on
+// the VALU into partial slot 8 + s (entries of row 80 only).  These short
+// wavefronts issue at a raised priority so that their MFMAs and VALU work
+// interleave early with the long wavefront's.  x of k-tiles 0..3 is one LDS
+// read per fragment that goes straight into the MFMA.  For k-tile 4 and x_80:
+//  * PRESUM = false (param 2): every reader sums the four partial slots;
+//  * PRESUM = true (param 3): each short wavefront bumps a workgroup counter
+//    in LDS (release / acquire) after writing its partials and the last of
+//    the four sums them in place into slots 4 and 8, so every read is one
+//    LDS read.
+// Each SIMD issues 80 + 20 = 100 MFMAs a step.  The product with -fi is the
+// FP64 MFMA's negate modifier, or a negated copy in registers for FP32.
 constexpr int kTilesKS = 20;     // MFMA k steps: columns 0..79
 constexpr int kTilesSlots = 12;
 constexpr int kTilesBuf = kTilesSlots * 256;
@@ -640,39 +645,37 @@ __device__ inline void tiles_store(Pair<T> *__restrict__ dst, int lane, const ty
     for (int r = 0; r < 4; ++r) dst[Mfma<T>::row(lane, r) * 16 + (lane & 15)] = Pair<T>{ar[r], ai[r]};
 }
 
-// x of k step ks for this lane: one slot (k-tiles 0..3) or the sum of the
-// four partial slots of k-tile 4
-template <typename T, bool SUM4>
-__device__ inline void tiles_x(const Pair<T> *__restrict__ cur, int ks, int lane, T &xr, T &xi) {
-    const int e = lane + 64 * (ks & 3);
-    if (!SUM4) {
-        const Pair<T> v = cur[(ks >> 2) * 256 + e];
-        xr = v.re, xi = v.im;
-    } else {
-        const Pair<T> *c = cur + 4 * 256 + e;
-        const Pair<T> a = c[0], b = c[256], d = c[512], f = c[768];
-        xr = (a.re + b.re) + (d.re + f.re);
-        xi = (a.im + b.im) + (d.im + f.im);
-    }
+template <typename T>
+__device__ inline Pair<T> sum4(const Pair<T> *__restrict__ c) {
+    const Pair<T> a = c[0], b = c[256], d = c[512], f = c[768];
+    return Pair<T>{(a.re + b.re) + (d.re + f.re), (a.im + b.im) + (d.im + f.im)};
 }
 
-// x_80 of state j: the four partial slots of row 80
-template <typename T>
-__device__ inline void tiles_x80(const Pair<T> *__restrict__ cur, int j, T &xr, T &xi) {
-    const Pair<T> *c = cur + 8 * 256 + j;
-    const Pair<T> a = c[0], b = c[256], d = c[512], f = c[768];
-    xr = (a.re + b.re) + (d.re + f.re);
-    xi = (a.im + b.im) + (d.im + f.im);
+// x of k step ks (< 20) for this lane: slot ks / 4, entry (4 (ks % 4) + g) 16 + j;
+// SUM4: k-tile 4 as the sum of its four partial slots
+template <typename T, bool SUM4>
+__device__ inline Pair<T> tiles_x(const Pair<T> *__restrict__ cur, int ks, int lane) {
+    const Pair<T> *c = cur + (ks >> 2) * 256 + lane + 64 * (ks & 3);
+    if (SUM4) return sum4<T>(c);
+    return c[0];
+}
+
+// x_80 of state j (entry j of slot 8, or the sum of slots 8..11)
+template <typename T, bool SUM4>
+__device__ inline Pair<T> tiles_x80(const Pair<T> *__restrict__ cur, int j) {
+    if (SUM4) return sum4<T>(cur + 8 * 256 + j);
+    return cur[8 * 256 + j];
 }
 
 // short wavefront s = 0..3: k steps [5 s, 5 s + 5) of tile 4 and of row 80;
-// LAST (s = 3): k steps 15..19, the last four in k-tile 4, plus column 80
-// (P[64..79, 80] x_80 as the accumulators' starting value, P[80, 80] x_80)
-template <typename T, bool LAST>
-__device__ inline void tiles_short(int n, const cd *__restrict__ P, Pair<T> *__restrict__ slots, int s, int lane,
-                                   long long nsteps) {
+// LAST (s = 3) also column 80 (P[64..79, 80] x_80 as the accumulators'
+// starting value, P[80, 80] x_80)
+template <typename T, bool PRESUM, bool LAST>
+__device__ inline void tiles_short(int n, const cd *__restrict__ P, Pair<T> *__restrict__ slots, unsigned *ctr,
+                                   int s, int lane, long long nsteps) {
     typedef typename Mfma<T>::acc acc_t;
     const int g = lane >> 4, j = lane & 15, kb = kTilesShort * s;
+    __builtin_amdgcn_s_setprio(2);  // issue ahead of the long wavefront sharing the SIMD
     T fr[kTilesShort], fi[kTilesShort], fn[kTilesShort], tr[kTilesShort], ti[kTilesShort];
 #pragma unroll
     for (int f = 0; f < kTilesShort; ++f) {
@@ -681,7 +684,6 @@ __device__ inline void tiles_short(int n, const cd *__restrict__ P, Pair<T> *__r
         fr[f] = (T)v.re, fi[f] = (T)v.im, fn[f] = -(T)v.im;
         tr[f] = (T)u.re, ti[f] = (T)u.im;
     }
-    // LAST: column 80 of tile 4 (accumulator layout) and P[80, 80]
     T cr[4], ci[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -698,29 +700,26 @@ __device__ inline void tiles_short(int n, const cd *__restrict__ P, Pair<T> *__r
         acc_t a0 = acc_t{0, 0, 0, 0}, a1 = a0;
         T sr = 0, si = 0;
         if (LAST) {
-            T xr, xi;
-            tiles_x80<T>(cur, j, xr, xi);
+            const Pair<T> x80 = tiles_x80<T, !PRESUM>(cur, j);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                a0[r] = cr[r] * xr - ci[r] * xi;
-                a1[r] = cr[r] * xi + ci[r] * xr;
+                a0[r] = cr[r] * x80.re - ci[r] * x80.im;
+                a1[r] = cr[r] * x80.im + ci[r] * x80.re;
             }
-            sr = qr * xr - qi * xi;
-            si = qr * xi + qi * xr;
+            sr = qr * x80.re - qi * x80.im;
+            si = qr * x80.im + qi * x80.re;
         }
 #pragma unroll
         for (int f = 0; f < kTilesShort; ++f) {
-            T xr, xi;
-            if (LAST && f > 0)
-                tiles_x<T, true>(cur, kb + f, lane, xr, xi);
-            else
-                tiles_x<T, false>(cur, kb + f, lane, xr, xi);
-            a0 = Mfma<T>::mma(fr[f], xr, a0);
-            a1 = Mfma<T>::mma(fr[f], xi, a1);
-            a0 = Mfma<T>::mma_neg_a(fi[f], fn[f], xi, a0);
-            a1 = Mfma<T>::mma(fi[f], xr, a1);
-            sr += tr[f] * xr - ti[f] * xi;
-            si += tr[f] * xi + ti[f] * xr;
+            // only the last range reaches k-tile 4 (k steps 16..19)
+            const Pair<T> x = (LAST && !PRESUM && f > 0) ? tiles_x<T, true>(cur, kb + f, lane)
+                                                        : tiles_x<T, false>(cur, kb + f, lane);
+            a0 = Mfma<T>::mma(fr[f], x.re, a0);
+            a1 = Mfma<T>::mma(fr[f], x.im, a1);
+            a0 = Mfma<T>::mma_neg_a(fi[f], fn[f], x.im, a0);
+            a1 = Mfma<T>::mma(fi[f], x.re, a1);
+            sr += tr[f] * x.re - ti[f] * x.im;
+            si += tr[f] * x.im + ti[f] * x.re;
         }
         tiles_store<T>(nxt + (4 + s) * 256, lane, a0, a1);
         sr += __shfl_xor(sr, 16);
@@ -728,28 +727,45 @@ __device__ inline void tiles_short(int n, const cd *__restrict__ P, Pair<T> *__r
         sr += __shfl_xor(sr, 32);
         si += __shfl_xor(si, 32);
         if (g == 0) nxt[(8 + s) * 256 + j] = Pair<T>{sr, si};
+        if (PRESUM) {
+            // the last short wavefront of the step to get here sums the partials
+            unsigned prev = 0;
+            if (lane == 0) prev = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            prev = __builtin_amdgcn_readfirstlane(prev);
+            if ((prev & 3) == 3) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    nxt[4 * 256 + lane + 64 * q] = sum4<T>(nxt + 4 * 256 + lane + 64 * q);
+                if (lane < 16) nxt[8 * 256 + lane] = sum4<T>(nxt + 8 * 256 + lane);
+            }
+        }
         __syncthreads();
     }
 }
 
-template <typename T>
+template <typename T, bool PRESUM>
 __global__ void __launch_bounds__(CW * 64) tiles_chain_kernel(int n, const cd *__restrict__ P, int B,
                                                               cd *__restrict__ rho, long long nsteps) {
     typedef typename Mfma<T>::acc acc_t;
     constexpr int KS = kTilesKS, Kp = 4 * KS + 16;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ unsigned ctr;
     Pair<T> *slots = reinterpret_cast<Pair<T> *>(smem_raw);  // [2][kTilesSlots][256]
     const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, j = lane & 15;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int b0 = blockIdx.x * NS;
 
+    if (tid == 0) ctr = 0;
     for (int e = tid; e < 2 * kTilesBuf; e += CW * 64) slots[e] = Pair<T>{(T)0, (T)0};
     __syncthreads();
+    // x of k-tile kt < 5 in slot kt, x_80 in entry 0..15 of slot 8 (the other
+    // partial slots zero)
     for (int e = tid; e < Kp * NS; e += CW * 64) {
         const int k = e / NS, sidx = e - k * NS, kt = k >> 4;
         cd v = {0.0, 0.0};
         if (k < n && b0 + sidx < B) v = rho[(size_t)(b0 + sidx) * n + k];
-        slots[(kt < 4 ? kt : (kt == 4 ? 4 : 8)) * 256 + (k & 15) * 16 + sidx] = Pair<T>{(T)v.re, (T)v.im};
+        slots[(kt < 5 ? kt : 8) * 256 + (k & 15) * 16 + sidx] = Pair<T>{(T)v.re, (T)v.im};
     }
     __syncthreads();
 
@@ -770,73 +786,70 @@ __global__ void __launch_bounds__(CW * 64) tiles_chain_kernel(int n, const cd *_
         for (long long t = 0; t < nsteps; ++t) {
             const Pair<T> *cur = slots + (t & 1) * kTilesBuf;
             Pair<T> *nxt = slots + ((t & 1) ^ 1) * kTilesBuf;
-            T x80r, x80i;
-            tiles_x80<T>(cur, j, x80r, x80i);
+            const Pair<T> x80 = tiles_x80<T, !PRESUM>(cur, j);
             acc_t a0, a1;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                a0[r] = cr[r] * x80r - ci[r] * x80i;
-                a1[r] = cr[r] * x80i + ci[r] * x80r;
+                a0[r] = cr[r] * x80.re - ci[r] * x80.im;
+                a1[r] = cr[r] * x80.im + ci[r] * x80.re;
             }
 #pragma unroll
             for (int f = 0; f < KS; ++f) {
-                T xr, xi;
-                if (f < 16)
-                    tiles_x<T, false>(cur, f, lane, xr, xi);
-                else
-                    tiles_x<T, true>(cur, f, lane, xr, xi);
-                a0 = Mfma<T>::mma(fr[f], xr, a0);
-                a1 = Mfma<T>::mma(fr[f], xi, a1);
-                a0 = Mfma<T>::mma_neg_a(fi[f], fn[f], xi, a0);
-                a1 = Mfma<T>::mma(fi[f], xr, a1);
+                const Pair<T> x = (!PRESUM && f >= 16) ? tiles_x<T, true>(cur, f, lane) : tiles_x<T, false>(cur, f, lane);
+                a0 = Mfma<T>::mma(fr[f], x.re, a0);
+                a1 = Mfma<T>::mma(fr[f], x.im, a1);
+                a0 = Mfma<T>::mma_neg_a(fi[f], fn[f], x.im, a0);
+                a1 = Mfma<T>::mma(fi[f], x.re, a1);
             }
             tiles_store<T>(nxt + wave * 256, lane, a0, a1);
             __syncthreads();
         }
     } else if (wave < 7) {
-        tiles_short<T, false>(n, P, slots, wave - 4, lane, nsteps);
+        tiles_short<T, PRESUM, false>(n, P, slots, &ctr, wave - 4, lane, nsteps);
     } else {
-        tiles_short<T, true>(n, P, slots, 3, lane, nsteps);
+        tiles_short<T, PRESUM, true>(n, P, slots, &ctr, 3, lane, nsteps);
     }
     const Pair<T> *fin = slots + (nsteps & 1) * kTilesBuf;
     for (int e = tid; e < n * NS; e += CW * 64) {
         const int sidx = e / n, k = e - sidx * n, kt = k >> 4;
-        const Pair<T> *c = fin + (kt < 4 ? kt : (kt == 4 ? 4 : 8)) * 256 + (k & 15) * 16 + sidx;
-        Pair<T> v = c[0];
-        if (kt >= 4) {
-            v.re = (c[0].re + c[256].re) + (c[512].re + c[768].re);
-            v.im = (c[0].im + c[256].im) + (c[512].im + c[768].im);
-        }
+        const Pair<T> *c = fin + (kt < 5 ? kt : 8) * 256 + (k & 15) * 16 + sidx;
+        const Pair<T> v = (!PRESUM && kt >= 4) ? sum4<T>(c) : c[0];
         if (b0 + sidx < B) rho[(size_t)(b0 + sidx) * n + k] = {(double)v.re, (double)v.im};
     }
 }
 
-template <typename T>
+template <typename T, bool PRESUM>
 static int launch_tiles_k(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
     const size_t lds = sizeof(Pair<T>) * 2 * (size_t)kTilesBuf;
     static bool attr_set = false;
     if (!attr_set) {
-        LB_HIP(hipFuncSetAttribute((const void *)tiles_chain_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
+        LB_HIP(hipFuncSetAttribute((const void *)tiles_chain_kernel<T, PRESUM>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
-    tiles_chain_kernel<T><<<(B + NS - 1) / NS, CW * 64, lds, s>>>(n, P, B, rho, nsteps);
+    tiles_chain_kernel<T, PRESUM><<<(B + NS - 1) / NS, CW * 64, lds, s>>>(n, P, B, rho, nsteps);
     return check_launch("tiles_chain");
 }
 
 bool tail_ok(int n, lb_precision prec) { return (prec == LB_C128 || prec == LB_C64) && n == 81; }
 
-int chain_tail(int n, const cd *P, lb_precision prec, int wide, int B, cd *rho, long long nsteps, hipStream_t s) {
+int chain_tail(int n, const cd *P, lb_precision prec, int layout, int B, cd *rho, long long nsteps, hipStream_t s) {
     if (nsteps == 0 || B == 0) return LB_OK;
     if (!tail_ok(n, prec)) return fail(LB_ESHAPE, "MFMA + tail chain: n = 81");
     if (prec == LB_C128) {
-        if (wide == 2) return launch_tiles_k<double>(n, P, B, rho, nsteps, s);
-        return wide ? launch_tail_k<double, 1, 16>(n, P, B, rho, nsteps, s)
-                    : launch_tail_k<double, 1, 8>(n, P, B, rho, nsteps, s);
+        switch (layout) {
+            case 0: return launch_tail_k<double, 1, 8>(n, P, B, rho, nsteps, s);
+            case 1: return launch_tail_k<double, 1, 16>(n, P, B, rho, nsteps, s);
+            case 2: return launch_tiles_k<double, false>(n, P, B, rho, nsteps, s);
+            default: return launch_tiles_k<double, true>(n, P, B, rho, nsteps, s);
+        }
     }
-    if (wide == 2) return launch_tiles_k<float>(n, P, B, rho, nsteps, s);
-    return wide ? launch_tail_k<float, 1, 16>(n, P, B, rho, nsteps, s)
-                : launch_tail_k<float, 1, 8>(n, P, B, rho, nsteps, s);
+    switch (layout) {
+        case 0: return launch_tail_k<float, 1, 8>(n, P, B, rho, nsteps, s);
+        case 1: return launch_tail_k<float, 1, 16>(n, P, B, rho, nsteps, s);
+        case 2: return launch_tiles_k<float, false>(n, P, B, rho, nsteps, s);
+        default: return launch_tiles_k<float, true>(n, P, B, rho, nsteps, s);
+    }
 }
 
 

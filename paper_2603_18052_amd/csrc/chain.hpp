@@ -20,7 +20,7 @@ enum ChainFamily : int {
     VF_PLANES = 7,      // one BF16 plane-GEMM launch per step
     VF_BALANCED = 8,    // fused chain with the SIMD-balanced layout (81 <= n <= 84 / 96)
     VF_Q15 = 9,         // fixed-point chain (LB_Q15); param 0 one wavefront per state, 1 per-row matvec
-    VF_TAIL = 10,       // fused chain, rows 0..79 on MFMA, the rows past them on the VALU (n = 81); param 1: 16 wavefronts
+    VF_TAIL = 10,       // fused chain, rows 0..79 on MFMA, the rest on the VALU (n = 81); param = layout 0..3
 };
 inline int variant_family(int v) { return v / 100; }
 inline int variant_param(int v) { return v % 100; }
@@ -40,7 +40,7 @@ int chain_fused(int n, const cd *P, lb_precision prec, int kpu, int B, cd *rho, 
 bool balanced_ok(int n, lb_precision prec);
 int chain_balanced(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
 bool tail_ok(int n, lb_precision prec);
-int chain_tail(int n, const cd *P, lb_precision prec, int wide, int B, cd *rho, long long nsteps, hipStream_t s);
+int chain_tail(int n, const cd *P, lb_precision prec, int layout, int B, cd *rho, long long nsteps, hipStream_t s);
 
 // Longest chain that runs with the 4 x 4-digit slice set (10 slice pairs);
 // longer chains use 5 x 4 digits (14 pairs).  Emulated and measured trace

@@ -68,6 +68,7 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
             add(VF_TAIL * 100);
             add(VF_TAIL * 100 + 1);
             add(VF_TAIL * 100 + 2);
+            add(VF_TAIL * 100 + 3);
         }
         add2(VF_GEMM * 100 + 1);
         add2(VF_GEMM * 100 + 2);
@@ -100,7 +101,7 @@ int chain_heuristic(int n, lb_precision prec, int B) {
         case LB_C64: {
             if (n <= kWaveChainMaxN) return VF_WAVE * 100;
             if (prec == LB_C128 && (double)B * n * n <= 1.1e6) return VF_BASELINE * 100;
-            if (tail_ok(n, prec)) return VF_TAIL * 100 + 2;
+            if (tail_ok(n, prec)) return VF_TAIL * 100 + (prec == LB_C128 ? 2 : 3);
             if (balanced_ok(n, prec)) return VF_BALANCED * 100;
             int kpu;
             if (fused_kpus(n, prec, &kpu, 1) == 1) return VF_FUSED * 100 + kpu;

@@ -86,13 +86,13 @@ def test_chain_variant_lists_and_rule(L):
     v = lb.chain_variants(81, "c128", 4096)
     assert [x for x in v if x // 100 == 3] == [306, 308, 311]
     assert 800 in v and 800 in lb.chain_variants(96, "c64", 16) and 800 not in lb.chain_variants(85, "c128", 16)
-    assert {1000, 1001, 1002} <= set(v) and 1002 in lb.chain_variants(81, "c64", 16)
+    assert {1000, 1001, 1002, 1003} <= set(v) and 1003 in lb.chain_variants(81, "c64", 16)
     assert 1002 not in lb.chain_variants(82, "c128", 16)
     assert 200 not in v
     assert lb.chain_variant(81, "c128", 4096) == 1002  # rows/columns 0..79 on MFMA, 80 on the VALU
     assert lb.chain_variant(84, "c128", 4096) == 800  # SIMD-balanced layout
     assert lb.chain_variant(81, "c128", 64) == 100  # little work per step: plain matvec
-    assert lb.chain_variant(81, "c64", 64) == 1002
+    assert lb.chain_variant(81, "c64", 64) == 1003
     assert lb.chain_variant(100, "c64", 64) == 308
     assert lb.chain_variant(16, "c64", 4096) == 200
     # d = 27: no fused variant; GEMM from 16 states, matvec below
@@ -105,9 +105,9 @@ def test_chain_variant_lists_and_rule(L):
     # BF16 precisions
     assert lb.chain_variants(81, "bf16_sliced", 16) == [400, 700, 750]
     assert lb.chain_variants(729, "bf16_sliced", 16) == [700, 750]
-    assert [lb.variant_name(x) for x in (150, 552, 306, 800, 1000, 1001, 1002)] == [
+    assert [lb.variant_name(x) for x in (150, 552, 306, 800, 1000, 1001, 1002, 1003)] == [
         "baseline+graph", "gemm(w2)+graph", "fused(k6)", "fused_balanced", "fused_tail", "fused_tail(w16)",
-        "fused_tail(tiles)"]
+        "fused_tail(tiles)", "fused_tail(tiles+presum)"]
     assert lb.chain_variant(729, "bf16_hilo", 16) == 700
     # fixed point: one wavefront per state for n <= 16, else the per-row matvec (and its graph twin)
     assert lb.chain_variants(9, "q15", 1) == [900, 901, 951]
