@@ -137,8 +137,8 @@ int lindblad_propagator(int n, int M, const void *L, const double *dt, double th
  * 96 LB_BF16_HILO; for n = 81 rows and columns 0..79 on MFMA and row and
  * column 80 on the vector ALUs, else the SIMD-balanced layout for
  * 81 <= n <= 84 / 96); beyond
- * that one MFMA GEMM launch per step (B >= 16) or a per-state matvec
- * (B < 16). */
+ * that one MFMA GEMM launch per step (B >= 16; the LDS-tiled one once
+ * ceil(B / 64) ceil(n / 48) >= 240) or a per-state matvec (B < 16). */
 int lindblad_propagate(int n, const void *P, lb_precision prec, int B, void *rho, long long nsteps,
                        lb_workspace *ws, hipStream_t stream);
 
@@ -172,7 +172,9 @@ int lindblad_propagate_baseline(int n, const void *P, int B, void *rho, long lon
  *             vector ALUs (n = 81, LB_C128 / LB_C64)
  *   1003      the same with the partial sums of rows 64..80 formed once a
  *             step by the last wavefront to finish them
- * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901) replays its steps
+ *   1100 + w  one LDS-tiled MFMA GEMM launch per step, 64 states x 48 outputs
+ *             per workgroup, w = 4 or 8 wavefronts (LB_C128 / LB_C64)
+ * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901, 1100 + w) replays its steps
  * from a HIP graph captured once per call (32 steps, replayed over all but
  * the last step).  Variants of one shape differ only in summation order. */
 

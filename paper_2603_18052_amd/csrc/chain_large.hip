@@ -399,6 +399,207 @@ __global__ void __launch_bounds__(256) gemm_step_kernel(int n, int B, int Kp, co
     }
 }
 
+// ------------------------------------------ LDS-tiled FP32 / FP64 GEMM step
+// The same step, Y[b][i] = sum_k X[b][k] P[i][k], with a 64-state x 48-output
+// tile per workgroup (B = 1024, n = 729: 16 x 16 = 256 workgroups, one per
+// CU) so that each operand byte fetched feeds 48 or 64 products instead of
+// 16 or 32.  Wavefront w % 4 owns states 16 (w % 4) .. + 15 of the tile
+// against all 48 outputs (three MFMA blocks).  k advances KC = 32 at a time
+// through two LDS buffers (row-major planes, rows padded so that the 16 rows
+// one MFMA operand fetch touches fall in distinct banks); the next chunk is
+// loaded into registers while the current one is multiplied.  With WPB = 8
+// the two wavefronts of a SIMD take alternate 16-deep halves of every chunk
+// and the second adds its partial sums through LDS once at the end.  Each
+// lane reads four consecutive k of a row at once and feeds them to four MFMAs
+// (the same k permutation on both operands leaves the sum unchanged).
+// -Im X Im P uses the FP64 MFMA's negate-A modifier, and a negated Im X plane
+// in LDS for FP32.  Workgroups are numbered so that each XCD (workgroup id
+// mod 8) runs a contiguous range of tiles: whole rows of state tiles, which
+// then stream P through that XCD's own L2.
+constexpr int TGB = 64, TGI = 48, TGK = 32;
+
+template <typename T, int WPB>
+struct TgShape {
+    static constexpr int PAD = 16 / sizeof(T);  // keeps 16-byte row alignment, spreads banks
+    static constexpr int LD = TGK + PAD;
+    static constexpr int XPL = sizeof(T) == 8 ? 2 : 3;  // X planes in LDS: re, im (, -im)
+    static constexpr int XS = TGB * LD, PS = TGI * LD;  // plane sizes in T
+    static constexpr int BUF = XPL * XS + 2 * PS;
+    static constexpr int VPT = 16 / sizeof(T);          // T per 16-byte load
+    static constexpr int NT = 64 * WPB;                 // threads
+    // 16-byte loads per chunk (X: 2 planes, P: 2 planes) and per thread
+    static constexpr int XN = 2 * TGB * TGK / VPT, PN = 2 * TGI * TGK / VPT;
+    static constexpr int XL = (XN + NT - 1) / NT, PL = (PN + NT - 1) / NT;
+};
+
+template <typename T>
+struct TgMma;
+template <>
+struct TgMma<double> {
+    typedef d4s acc;
+    static __device__ inline acc mma(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    // -a b + c (negate-A modifier)
+    static __device__ inline acc mma_na(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 1);
+    }
+    static __device__ inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct TgMma<float> {
+    typedef f4v acc;
+    static __device__ inline acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename T, int WPB>
+__global__ void __launch_bounds__(64 * WPB) tgemm_step_kernel(int n, int B, int Kp, int nbt, int nit,
+                                                              const T *__restrict__ Xr, const T *__restrict__ Xi,
+                                                              const T *__restrict__ Pr, const T *__restrict__ Pi,
+                                                              T *__restrict__ Yr, T *__restrict__ Yi,
+                                                              cd *__restrict__ Yout) {
+    typedef TgShape<T, WPB> S;
+    typedef typename TgMma<T>::acc acc_t;
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    typedef T vl __attribute__((ext_vector_type(S::VPT)));  // one 16-byte load
+    constexpr int KSPLIT = WPB / 4;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);  // [2][BUF]
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wq = wave & 3, kh = wave >> 2;  // state rows; k half (WPB = 8)
+    // XCD-contiguous tile numbering (bijective on [0, nbt * nit))
+    const int total = nbt * nit, per = total / 8, rem = total % 8;
+    const int xcd = blockIdx.x % 8, jx = blockIdx.x / 8;
+    const int L = xcd * per + (xcd < rem ? xcd : rem) + jx;
+    const int bt = L / nit, it = L - bt * nit;
+    const int b0 = bt * TGB, i0 = it * TGI;
+
+    // global -> register staging: load e covers 16 bytes of one row of one plane
+    constexpr int RX = TGK / S::VPT;  // loads per row
+    vl rx[S::XL], rp[S::PL];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < S::XL; ++q) {
+            const int e = tid + S::NT * q;
+            const int pl = e / (TGB * RX), rem2 = e - pl * TGB * RX, r = rem2 / RX, c = rem2 - r * RX;
+            const int b = b0 + r;
+            const bool ok = (S::XN % S::NT == 0 || e < S::XN) && b < B;
+            const T *src = (pl == 0 ? Xr : Xi) + (size_t)(ok ? b : 0) * Kp + k0 + c * S::VPT;
+            rx[q] = ok ? *reinterpret_cast<const vl *>(src) : vl{};
+        }
+#pragma unroll
+        for (int q = 0; q < S::PL; ++q) {
+            const int e = tid + S::NT * q;
+            const int pl = e / (TGI * RX), rem2 = e - pl * TGI * RX, r = rem2 / RX, c = rem2 - r * RX;
+            const int i = i0 + r;
+            const bool ok = (S::PN % S::NT == 0 || e < S::PN) && i < n;
+            const T *src = (pl == 0 ? Pr : Pi) + (size_t)(ok ? i : 0) * Kp + k0 + c * S::VPT;
+            rp[q] = ok ? *reinterpret_cast<const vl *>(src) : vl{};
+        }
+    };
+    auto lstore = [&](T *buf) {
+#pragma unroll
+        for (int q = 0; q < S::XL; ++q) {
+            const int e = tid + S::NT * q;
+            if (S::XN % S::NT != 0 && e >= S::XN) break;
+            const int pl = e / (TGB * RX), rem2 = e - pl * TGB * RX, r = rem2 / RX, c = rem2 - r * RX;
+            *reinterpret_cast<vl *>(buf + pl * S::XS + r * S::LD + c * S::VPT) = rx[q];
+            if (S::XPL == 3 && pl == 1) *reinterpret_cast<vl *>(buf + 2 * S::XS + r * S::LD + c * S::VPT) = -rx[q];
+        }
+#pragma unroll
+        for (int q = 0; q < S::PL; ++q) {
+            const int e = tid + S::NT * q;
+            if (S::PN % S::NT != 0 && e >= S::PN) break;
+            const int pl = e / (TGI * RX), rem2 = e - pl * TGI * RX, r = rem2 / RX, c = rem2 - r * RX;
+            *reinterpret_cast<vl *>(buf + S::XPL * S::XS + pl * S::PS + r * S::LD + c * S::VPT) = rp[q];
+        }
+    };
+
+    acc_t re[3], im[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) re[t] = im[t] = acc_t{0, 0, 0, 0};
+    const int nch = Kp / TGK;
+    gload(0);
+    lstore(lds);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const T *buf = lds + (c & 1) * S::BUF;
+        if (c + 1 < nch) gload((c + 1) * TGK);
+        const T *xr = buf + (16 * wq + (lane & 15)) * S::LD + 4 * (lane >> 4);
+        const T *xi = xr + S::XS;
+        const T *xn = xr + 2 * S::XS;  // FP32 only
+        const T *pr = buf + S::XPL * S::XS + (lane & 15) * S::LD + 4 * (lane >> 4);
+        const T *pi = pr + S::PS;
+#pragma unroll
+        for (int kq = 0; kq < TGK / 16 / KSPLIT; ++kq) {
+            const int kb = 16 * (kq * KSPLIT + kh);
+            const v4 ar = *reinterpret_cast<const v4 *>(xr + kb), ai = *reinterpret_cast<const v4 *>(xi + kb);
+            v4 an;
+            if (S::XPL == 3) an = *reinterpret_cast<const v4 *>(xn + kb);
+            v4 br[3], bi[3];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                br[t] = *reinterpret_cast<const v4 *>(pr + 16 * t * S::LD + kb);
+                bi[t] = *reinterpret_cast<const v4 *>(pi + 16 * t * S::LD + kb);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    re[t] = TgMma<T>::mma(ar[q], br[t][q], re[t]);
+                    im[t] = TgMma<T>::mma(ar[q], bi[t][q], im[t]);
+                }
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    if constexpr (sizeof(T) == 8)
+                        re[t] = TgMma<T>::mma_na(ai[q], bi[t][q], re[t]);
+                    else
+                        re[t] = TgMma<T>::mma(an[q], bi[t][q], re[t]);
+                    im[t] = TgMma<T>::mma(ai[q], br[t][q], im[t]);
+                }
+            }
+        }
+        if (c + 1 < nch) {
+            lstore(lds + ((c + 1) & 1) * S::BUF);
+            __syncthreads();
+        }
+    }
+    if (KSPLIT == 2) {
+        // the second k half adds its partial sums (fixed order: first + second)
+        __syncthreads();  // every wavefront is done with the LDS operands
+        T *red = lds;     // [4 wq][3 t][4 r][2][64]
+        if (kh == 1) {
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    red[(((wq * 3 + t) * 4 + r) * 2 + 0) * 64 + lane] = re[t][r];
+                    red[(((wq * 3 + t) * 4 + r) * 2 + 1) * 64 + lane] = im[t][r];
+                }
+        }
+        __syncthreads();
+        if (kh == 1) return;  // uniform per wavefront; no barrier follows
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                re[t][r] += red[(((wq * 3 + t) * 4 + r) * 2 + 0) * 64 + lane];
+                im[t][r] += red[(((wq * 3 + t) * 4 + r) * 2 + 1) * 64 + lane];
+            }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int b = b0 + 16 * wq + TgMma<T>::row(lane, r), i = i0 + 16 * t + (lane & 15);
+            if (b < B && i < n) {
+                Yr[(size_t)b * Kp + i] = re[t][r];
+                Yi[(size_t)b * Kp + i] = im[t][r];
+                if (Yout) Yout[(size_t)b * n + i] = {(double)re[t][r], (double)im[t][r]};
+            }
+        }
+}
+
 // ------------------------------------------------- per-state matvec in T
 template <typename T>
 struct Cx {
@@ -503,6 +704,39 @@ static int gemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Worksp
     return check_launch("gemm_step");
 }
 
+template <typename T, int WPB>
+static int tgemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s,
+                     bool graph) {
+    typedef TgShape<T, WPB> S;
+    const int Kp = (n + 63) / 64 * 64;
+    const size_t pp = (size_t)n * Kp * sizeof(T), xp = (size_t)B * Kp * sizeof(T);
+    LB_TRY(ws_ensure(ws, 2 * align256(pp) + 4 * align256(xp)));
+    T *Pr = (T *)ws_take(ws, pp), *Pi = (T *)ws_take(ws, pp);
+    T *X[2][2];
+    for (int q = 0; q < 2; ++q)
+        for (int c = 0; c < 2; ++c) X[q][c] = (T *)ws_take(ws, xp);
+    to_planes_kernel<T><<<grid1((long long)n * Kp), 256, 0, s>>>(n, n, Kp, P, Pr, Pi);
+    for (int q = 0; q < 2; ++q)  // zero k padding of both buffers
+        to_planes_kernel<T><<<grid1((long long)B * Kp), 256, 0, s>>>(B, n, Kp, rho, X[q][0], X[q][1]);
+    LB_TRY(check_launch("to_planes"));
+    const size_t lds = 2 * (size_t)S::BUF * sizeof(T);
+    static bool attr_set = false;
+    if (!attr_set) {
+        LB_HIP(hipFuncSetAttribute((const void *)tgemm_step_kernel<T, WPB>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    const int nbt = (B + TGB - 1) / TGB, nit = (n + TGI - 1) / TGI;
+    LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
+        const int c = (int)(t & 1);
+        tgemm_step_kernel<T, WPB><<<nbt * nit, 64 * WPB, lds, st>>>(n, B, Kp, nbt, nit, X[c][0], X[c][1], Pr, Pi,
+                                                                    X[c ^ 1][0], X[c ^ 1][1],
+                                                                    t + 1 == nsteps ? rho : nullptr);
+        return LB_OK;
+    }, s));
+    return check_launch("tgemm_step");
+}
+
 template <int MODE, int SP, int SX, int LMAX>
 static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s,
                       bool graph) {
@@ -553,6 +787,21 @@ int chain_gemm(int n, const cd *P, lb_precision prec, int wn, int B, cd *rho, lo
     }
 }
 
+int chain_tgemm(int n, const cd *P, lb_precision prec, int waves, int B, cd *rho, long long nsteps, Workspace *ws,
+                hipStream_t s, bool graph) {
+    if (nsteps == 0 || B == 0) return LB_OK;
+    if (waves != 4 && waves != 8) return fail(LB_ESHAPE, "tiled gemm chain: 4 or 8 wavefronts");
+    switch (prec) {
+        case LB_C128:
+            return waves == 4 ? tgemm_run<double, 4>(n, P, B, rho, nsteps, ws, s, graph)
+                              : tgemm_run<double, 8>(n, P, B, rho, nsteps, ws, s, graph);
+        case LB_C64:
+            return waves == 4 ? tgemm_run<float, 4>(n, P, B, rho, nsteps, ws, s, graph)
+                              : tgemm_run<float, 8>(n, P, B, rho, nsteps, ws, s, graph);
+        default: return fail(LB_ENOTSUP, "tiled gemm chain: complex128 / complex64 only");
+    }
+}
+
 int chain_planes(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
                  hipStream_t s, bool graph) {
     if (nsteps == 0 || B == 0) return LB_OK;
@@ -568,7 +817,7 @@ int chain_planes(int n, const cd *P, lb_precision prec, int B, cd *rho, long lon
 size_t large_ws_bytes(int family, int n, lb_precision prec, int B) {
     const size_t tsz = prec == LB_C128 ? 8 : 4;
     if (family == VF_MATVEC) return align256((size_t)n * n * 2 * tsz) + 2 * align256((size_t)B * n * 2 * tsz);
-    if (family == VF_GEMM) {
+    if (family == VF_GEMM || family == VF_TGEMM) {
         const size_t Kp = (size_t)(n + 63) / 64 * 64;
         return 2 * align256(n * Kp * tsz) + 4 * align256(B * Kp * tsz);
     }

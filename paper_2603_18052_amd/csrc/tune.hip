@@ -72,6 +72,8 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
         }
         add2(VF_GEMM * 100 + 1);
         add2(VF_GEMM * 100 + 2);
+        add2(VF_TGEMM * 100 + 4);
+        add2(VF_TGEMM * 100 + 8);
         if (prec == LB_C64) add2(VF_MATVEC * 100);
     } else if (prec == LB_BF16_HILO || prec == LB_BF16_SLICED) {
         if (n <= bf16_fused_max_n(prec)) add(VF_BF16_FUSED * 100);
@@ -93,8 +95,10 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
 // fused chain where its layout exists (81 <= n <= 84 / 96, 17-20 % faster
 // than the round-robin units there), the round-robin
 // fused chain elsewhere while P fits in one CU's LDS; otherwise a
-// GEMM per step with one output tile per wavefront up to 256 states (more
-// workgroups) and two beyond, or a matvec for few states.
+// GEMM per step: the LDS-tiled one (64 states x 48 outputs per workgroup,
+// eight wavefronts) once its tiles fill the chip (>= 240), else one output
+// tile per wavefront up to 256 states (more workgroups) and two beyond, or a
+// matvec for few states.
 int chain_heuristic(int n, lb_precision prec, int B) {
     switch (prec) {
         case LB_C128:
@@ -105,7 +109,11 @@ int chain_heuristic(int n, lb_precision prec, int B) {
             if (balanced_ok(n, prec)) return VF_BALANCED * 100;
             int kpu;
             if (fused_kpus(n, prec, &kpu, 1) == 1) return VF_FUSED * 100 + kpu;
-            if (B >= 16) return VF_GEMM * 100 + (B <= 256 ? 1 : 2);
+            if (B >= 16) {
+                const long long tiles = (long long)((B + 63) / 64) * ((n + 47) / 48);
+                if (tiles >= 240) return VF_TGEMM * 100 + 8;  // about one tile per CU or more
+                return VF_GEMM * 100 + (B <= 256 ? 1 : 2);
+            }
             return prec == LB_C128 ? VF_BASELINE * 100 : VF_MATVEC * 100;
         }
         case LB_BF16_HILO:
@@ -151,6 +159,7 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_BALANCED: return chain_balanced(n, P, prec, B, rho, nsteps, s);
         case VF_Q15: return chain_q15(n, P, B, rho, nsteps, prm == 0, graph, ws, s);
         case VF_TAIL: return chain_tail(n, P, prec, prm, B, rho, nsteps, s);
+        case VF_TGEMM: return chain_tgemm(n, P, prec, prm, B, rho, nsteps, ws, s, graph);
         default: return fail(LB_EINVAL, "unknown chain variant");
     }
 }
@@ -247,7 +256,7 @@ extern "C" int lindblad_tune(int n, const void *P, lb_precision prec, int B, con
         if (variant_param(ids[i]) >= kGraphVariant && probe_steps <= 2 * kGraphSteps &&
             (variant_family(ids[i]) == VF_BASELINE || variant_family(ids[i]) == VF_GEMM ||
              variant_family(ids[i]) == VF_MATVEC || variant_family(ids[i]) == VF_PLANES ||
-             variant_family(ids[i]) == VF_Q15))
+             variant_family(ids[i]) == VF_Q15 || variant_family(ids[i]) == VF_TGEMM))
             continue;
         w->used = base;
         st = chain_run_variant(n, Pc, prec, B, x, probe_steps, ids[i], w, stream);  // warm-up

@@ -57,7 +57,7 @@ SYMBOLS = {
 
 # Chain variant families (id = family * 100 + tile parameter).
 VARIANT_FAMILIES = {1: "baseline", 2: "wave", 3: "fused", 4: "bf16_fused", 5: "gemm", 6: "matvec32", 7: "planes",
-                    8: "fused_balanced", 9: "q15", 10: "fused_tail"}
+                    8: "fused_balanced", 9: "q15", 10: "fused_tail", 11: "gemm_tiled"}
 
 
 GRAPH_VARIANT = 50  # added to a per-step family: steps replayed from a captured HIP graph
@@ -66,14 +66,16 @@ GRAPH_VARIANT = 50  # added to a per-step family: steps replayed from a captured
 def variant_name(v: int) -> str:
     fam, prm = divmod(int(v), 100)
     name = VARIANT_FAMILIES.get(fam, f"family{fam}")
-    graph = fam in (1, 5, 6, 7, 9) and prm >= GRAPH_VARIANT
-    prm = prm % GRAPH_VARIANT if fam in (1, 5, 6, 7, 9) else prm
+    graph = fam in (1, 5, 6, 7, 9, 11) and prm >= GRAPH_VARIANT
+    prm = prm % GRAPH_VARIANT if fam in (1, 5, 6, 7, 9, 11) else prm
     if fam == 3:
         name = f"{name}(k{prm})"
     elif fam == 5:
         name = f"{name}(w{prm})"
     elif fam == 9:
         name = f"{name}_{'wave' if prm == 0 else 'matvec'}"
+    elif fam == 11:
+        name = f"{name}(w{prm})"
     elif fam == 10 and prm in (1, 2, 3):
         name = f"{name}({('w16', 'tiles', 'tiles+presum')[prm - 1]})"
     return name + "+graph" if graph else name

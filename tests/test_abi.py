@@ -79,7 +79,7 @@ def test_chain_variant_lists_and_rule(L):
     v = lb.chain_variants(9, "c128", 1)
     assert v[:3] == [100, 150, 200]  # baseline, its graph-replayed twin, wave
     assert [x for x in v if x // 100 == 3] == [301, 302, 303]  # KS = 3 k steps
-    assert {501, 502, 551, 552} <= set(v) and 600 not in v
+    assert {501, 502, 551, 552, 1104, 1154, 1108, 1158} <= set(v) and 600 not in v
     assert 600 in lb.chain_variants(9, "c64", 1000) and 100 not in lb.chain_variants(9, "c64", 1)
     assert lb.chain_variant(9, "c128", 1) == 200
     # d = 9 headline: fused with the smallest k split giving at most 32 units
@@ -98,16 +98,18 @@ def test_chain_variant_lists_and_rule(L):
     # d = 27: no fused variant; GEMM from 16 states, matvec below
     assert not [x for x in lb.chain_variants(729, "c128", 64) if x // 100 == 3]
     assert lb.chain_variant(729, "c128", 64) == 501
-    assert lb.chain_variant(729, "c128", 1024) == 502
+    assert lb.chain_variant(729, "c128", 1024) == 1108  # LDS-tiled GEMM: 16 x 16 tiles fill the chip
+    assert lb.chain_variant(729, "c64", 1024) == 1108
+    assert lb.chain_variant(729, "c128", 512) == 502  # 128 tiles: the small-tile GEMM
     assert lb.chain_variant(729, "c128", 1) == 100
     assert lb.chain_variant(729, "c64", 1) == 600
     assert 100 not in lb.chain_variants(729, "c64", 64)
     # BF16 precisions
     assert lb.chain_variants(81, "bf16_sliced", 16) == [400, 700, 750]
     assert lb.chain_variants(729, "bf16_sliced", 16) == [700, 750]
-    assert [lb.variant_name(x) for x in (150, 552, 306, 800, 1000, 1001, 1002, 1003)] == [
+    assert [lb.variant_name(x) for x in (150, 552, 306, 800, 1000, 1001, 1002, 1003, 1104, 1158)] == [
         "baseline+graph", "gemm(w2)+graph", "fused(k6)", "fused_balanced", "fused_tail", "fused_tail(w16)",
-        "fused_tail(tiles)", "fused_tail(tiles+presum)"]
+        "fused_tail(tiles)", "fused_tail(tiles+presum)", "gemm_tiled(w4)", "gemm_tiled(w8)+graph"]
     assert lb.chain_variant(729, "bf16_hilo", 16) == 700
     # fixed point: one wavefront per state for n <= 16, else the per-row matvec (and its graph twin)
     assert lb.chain_variants(9, "q15", 1) == [900, 901, 951]
@@ -123,7 +125,7 @@ def test_chain_variant_lists_and_rule(L):
     cnt = ctypes.c_int()
     assert L.lindblad_chain_variants(0, 0, 1, None, 0, ctypes.byref(cnt)) == lb.ESHAPE
     assert L.lindblad_chain_variants(9, 7, 1, None, 0, ctypes.byref(cnt)) == lb.EINVAL
-    assert L.lindblad_chain_variants(9, 0, 1, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 10
+    assert L.lindblad_chain_variants(9, 0, 1, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 14
     assert L.lindblad_propagate_variant(9, 1, 0, 1, 1, 5, 999, None, None) == lb.EINVAL
     assert L.lindblad_tune(9, 1, 0, 1, 1, 0, 1, None, None, None, None) == lb.EINVAL
 
