@@ -174,7 +174,9 @@ int lindblad_propagate_baseline(int n, const void *P, int B, void *rho, long lon
  *             step by the last wavefront to finish them
  *   1100 + w  one LDS-tiled MFMA GEMM launch per step, 64 states x 48 outputs
  *             per workgroup, w = 4 or 8 wavefronts (LB_C128 / LB_C64)
- * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901, 1100 + w) replays its steps
+ *   1200      one LDS-tiled BF16 plane-GEMM launch per step, 64 states x 48
+ *             outputs per workgroup, direct global-to-LDS loads (BF16 precisions)
+ * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901, 1100 + w, 1200) replays its steps
  * from a HIP graph captured once per call (32 steps, replayed over all but
  * the last step).  Variants of one shape differ only in summation order. */
 

@@ -272,6 +272,182 @@ __global__ void __launch_bounds__(256) plane_gemm_kernel(int n, int B, int Kp, c
     }
 }
 
+// LDS-tiled BF16 plane GEMM: the step of plane_gemm_kernel with a 64-state x
+// 48-output tile per workgroup (B = 1024, n = 729: 256 workgroups), so that
+// each digit-plane byte fetched from L2 feeds 48 or 64 products instead of 16
+// or 32.  Wavefront w owns states 16 w .. 16 w + 15 of the tile against all
+// 48 outputs (three MFMA blocks) over every k.  k advances TPK = 32 (one
+// v_mfma_f32_16x16x32_bf16 deep) at a time through two LDS buffers, filled
+// by direct global-to-LDS loads (global_load_lds_dwordx4: lane l's 16 bytes
+// land at the wavefront's LDS base + 16 l) issued for the next chunk before
+// the current one is multiplied, so no staging registers are needed.  Each
+// plane row is 64 bytes = four 16-byte chunks, stored at chunk position
+// c ^ ((row >> 2) & 3) so that the 16 rows one MFMA operand fetch touches
+// fall in distinct banks without padding; each lane loads the chunk that
+// belongs in its slot.  Rows past B or n load a valid row instead (they only
+// feed outputs that are not written).  Level sums are flushed into FP64
+// every KCH = 64 k, exactly as in the untiled kernel, so the results agree
+// with it to the FP64 rounding of the flushes.
+constexpr int TPB = 64, TPI = 48, TPK = 32;
+
+template <int MODE, int SP, int SX>
+struct TpShape {
+    static constexpr int XD = Planes<MODE, SP, SX>::XD, PD = Planes<MODE, SP, SX>::PD;
+    static constexpr int XPL = 3 * XD, PPL = 2 * PD;            // planes
+    static constexpr int ROWB = TPK * 2;                        // bytes per plane row (64)
+    static constexpr int XPB = TPB * ROWB, PPB = TPI * ROWB;    // bytes per plane tile
+    static constexpr int BUF = XPL * XPB + PPL * PPB;           // bytes per buffer
+    static constexpr int XI = XPB / 1024, PI = PPB / 1024;      // 1 KB loads per plane tile (4, 3)
+    static constexpr int NI = XPL * XI + PPL * PI;              // 1 KB loads per chunk
+};
+
+__device__ inline int tp_swz(int row, int c) { return c ^ ((row >> 2) & 3); }
+
+template <int MODE, int SP, int SX, int LMAX>
+__global__ void __launch_bounds__(256) tplane_gemm_kernel(int n, int B, int Kp, int nbt, int nit,
+                                                          const unsigned short *__restrict__ Xp,
+                                                          const unsigned short *__restrict__ Pp,
+                                                          const int *__restrict__ eP, const int *__restrict__ eX,
+                                                          cd *__restrict__ Y) {
+    typedef TpShape<MODE, SP, SX> S;
+    constexpr int XD = S::XD, PD = S::PD;
+    constexpr int NLV = MODE == SLICED ? LMAX + 1 : 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int total = nbt * nit, per = total / 8, rem = total % 8;
+    const int xcd = blockIdx.x % 8, jx = blockIdx.x / 8;
+    const int L0 = xcd * per + (xcd < rem ? xcd : rem) + jx;
+    const int bt = L0 / nit, it = L0 - bt * nit;
+    const int b0 = bt * TPB, i0 = it * TPI;
+    const size_t xplane = (size_t)B * Kp, pplane = (size_t)n * Kp;
+
+    // this lane's slot in a 1 KB load: row 16 j + lane / 4 of the plane tile,
+    // chunk position lane % 4, which holds chunk tp_swz(row, lane % 4).  The
+    // wavefront's loads are j = wave, wave + 4, ...; their source offsets (in
+    // elements, k0 = 0) and LDS destinations are fixed for the whole step.
+    constexpr int NJ = (S::NI + 3) / 4;
+    const unsigned short *srcp[NJ];
+    int dsto[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        const int j = wave + 4 * q;
+        srcp[q] = Xp;
+        dsto[q] = 0;
+        if (j < S::XPL * S::XI) {
+            const int pl = j / S::XI, jj = j - pl * S::XI, row = 16 * jj + (lane >> 2);
+            int b = b0 + row;
+            b = b < B ? b : B - 1;
+            srcp[q] = Xp + pl * xplane + (size_t)b * Kp + 8 * tp_swz(row, lane & 3);
+            dsto[q] = pl * S::XPB + 1024 * jj;
+        } else if (j < S::NI) {
+            const int jp = j - S::XPL * S::XI, pl = jp / S::PI, jj = jp - pl * S::PI, row = 16 * jj + (lane >> 2);
+            int i = i0 + row;
+            i = i < n ? i : n - 1;
+            srcp[q] = Pp + pl * pplane + (size_t)i * Kp + 8 * tp_swz(row, lane & 3);
+            dsto[q] = S::XPL * S::XPB + pl * S::PPB + 1024 * jj;
+        }
+    }
+    auto issue = [&](int k0, unsigned char *buf) {
+#pragma unroll
+        for (int q = 0; q < NJ; ++q)
+            if (wave + 4 * q < S::NI)  // uniform per wavefront
+                __builtin_amdgcn_global_load_lds((const void *)(srcp[q] + k0),
+                                                 (__attribute__((address_space(3))) void *)(buf + dsto[q]), 16, 0, 0);
+    };
+
+    double ar[3][4], ai[3][4];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ar[t][r] = ai[t][r] = 0.0;
+    // this lane's operand rows and chunk (k = 8 (lane / 16) .. + 7 of the chunk)
+    const int xrow = 16 * wave + (lane & 15), prow = lane & 15, cq = lane >> 4;
+    const int xoff = xrow * S::ROWB + 16 * tp_swz(xrow, cq);
+    int poff[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) poff[t] = (16 * t + prow) * S::ROWB + 16 * tp_swz(16 * t + prow, cq);
+
+    // chunk c (32 k) from buffer c & 1; two chunks (KCH = 64 k) per iteration,
+    // the level sums start from zero and are flushed into FP64 at its end
+    auto chunk = [&](const unsigned char *buf, f4v (&lr)[3][NLV], f4v (&li)[3][NLV]) {
+        bf16x8 xa[XD][3];
+#pragma unroll
+        for (int a = 0; a < XD; ++a)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                xa[a][q] = *reinterpret_cast<const bf16x8 *>(buf + (a * 3 + q) * S::XPB + xoff);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            bf16x8 pb[PD][2];
+#pragma unroll
+            for (int a = 0; a < PD; ++a)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    pb[a][q] = *reinterpret_cast<const bf16x8 *>(buf + S::XPL * S::XPB + (a * 2 + q) * S::PPB + poff[t]);
+#pragma unroll
+            for (int a = 0; a < PD; ++a)
+#pragma unroll
+                for (int bq = 0; bq < XD; ++bq) {
+                    const int L = a + bq;
+                    if (MODE == SLICED ? (L <= LMAX) : (L <= 1)) {
+                        const int Lq = MODE == SLICED ? L : 0;
+                        lr[t][Lq] = mma(xa[bq][0], pb[a][0], lr[t][Lq]);
+                        lr[t][Lq] = mma(xa[bq][2], pb[a][1], lr[t][Lq]);
+                        li[t][Lq] = mma(xa[bq][1], pb[a][0], li[t][Lq]);
+                        li[t][Lq] = mma(xa[bq][0], pb[a][1], li[t][Lq]);
+                    }
+                }
+        }
+    };
+    const int nch = Kp / TPK;  // even: Kp is a multiple of KCH = 64
+    issue(0, smem_raw);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int c = 0; c < nch; c += 2) {
+        f4v lr[3][NLV], li[3][NLV];
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int L = 0; L < NLV; ++L) lr[t][L] = li[t][L] = f4v{0, 0, 0, 0};
+        issue((c + 1) * TPK, smem_raw + S::BUF);
+        chunk(smem_raw, lr, li);
+        __builtin_amdgcn_s_waitcnt(0);  // this wavefront's loads into buffer 1 have landed
+        __syncthreads();
+        if (c + 2 < nch) issue((c + 2) * TPK, smem_raw);
+        chunk(smem_raw + S::BUF, lr, li);
+        // KCH = 64 k done: flush the exact level sums into FP64
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int L = NLV - 1; L >= 0; --L) {
+                    const double w = MODE == SLICED ? ldexp(1.0, -8 * (L + 2)) : 1.0;
+                    ar[t][r] = fma((double)lr[t][L][r], w, ar[t][r]);
+                    ai[t][r] = fma((double)li[t][L][r], w, ai[t][r]);
+                }
+        if (c + 2 < nch) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int b = b0 + 16 * wave + 4 * (lane >> 4) + r, i = i0 + 16 * t + (lane & 15);
+            if (b < B && i < n) {
+                if (MODE == SLICED) {
+                    const int sc = eP[i] + eX[b];
+                    Y[(size_t)b * n + i] = {ldexp(ar[t][r], sc), ldexp(ai[t][r], sc)};
+                } else {
+                    Y[(size_t)b * n + i] = {(double)(float)ar[t][r], (double)(float)ai[t][r]};
+                }
+            }
+        }
+}
+
 // --------------------------------------------------------- FP32 / FP64
 // planar copies: re[rows][Kp], im[rows][Kp] (zero padded in k)
 template <typename T>
@@ -739,7 +915,7 @@ static int tgemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Works
 
 template <int MODE, int SP, int SX, int LMAX>
 static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s,
-                      bool graph) {
+                      bool graph, bool tiled) {
     constexpr int XD = Planes<MODE, SP, SX>::XD, PD = Planes<MODE, SP, SX>::PD;
     const int Kp = (n + KCH - 1) / KCH * KCH;
     const size_t pbytes = (size_t)PD * 2 * n * Kp * 2, xbytes = (size_t)XD * 3 * B * Kp * 2;
@@ -753,11 +929,25 @@ static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Work
     prep_p_kernel<MODE, SP, SX><<<n, 256, 0, s>>>(n, Kp, P, Pp, eP);
     LB_TRY(check_launch("prep_p"));
     dim3 grid((n + TO - 1) / TO, (B + TS - 1) / TS);
+    const int nbt = (B + TPB - 1) / TPB, nit = (n + TPI - 1) / TPI;
+    const size_t lds = 2 * (size_t)TpShape<MODE, SP, SX>::BUF;
+    if (tiled) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            LB_HIP(hipFuncSetAttribute((const void *)tplane_gemm_kernel<MODE, SP, SX, LMAX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            attr_set = true;
+        }
+    }
     // the state ping-pongs between rho and Yt
     LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
         cd *cur = (t & 1) ? Yt : rho, *nxt = (t & 1) ? rho : Yt;
         slice_x_kernel<MODE, SP, SX><<<B, 256, 0, st>>>(n, Kp, B, cur, Xp, eX);
-        plane_gemm_kernel<MODE, SP, SX, LMAX><<<grid, 256, 0, st>>>(n, B, Kp, Xp, Pp, eP, eX, nxt);
+        if (tiled)
+            tplane_gemm_kernel<MODE, SP, SX, LMAX><<<nbt * nit, 256, lds, st>>>(n, B, Kp, nbt, nit, Xp, Pp, eP, eX,
+                                                                                nxt);
+        else
+            plane_gemm_kernel<MODE, SP, SX, LMAX><<<grid, 256, 0, st>>>(n, B, Kp, Xp, Pp, eP, eX, nxt);
         return LB_OK;
     }, s));
     LB_TRY(check_launch("plane_gemm"));
@@ -803,13 +993,14 @@ int chain_tgemm(int n, const cd *P, lb_precision prec, int waves, int B, cd *rho
 }
 
 int chain_planes(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
-                 hipStream_t s, bool graph) {
+                 hipStream_t s, bool graph, bool tiled) {
     if (nsteps == 0 || B == 0) return LB_OK;
     switch (prec) {
-        case LB_BF16_HILO: return planes_run<HILO, 2, 2, 1>(n, P, B, rho, nsteps, ws, s, graph);
+        case LB_BF16_HILO: return planes_run<HILO, 2, 2, 1>(n, P, B, rho, nsteps, ws, s, graph, tiled);
         case LB_BF16_SLICED:
-            if (nsteps <= kSlicedShortRun) return planes_run<SLICED, 4, 4, 3>(n, P, B, rho, nsteps, ws, s, graph);
-            return planes_run<SLICED, 5, 4, 4>(n, P, B, rho, nsteps, ws, s, graph);
+            if (nsteps <= kSlicedShortRun)
+                return planes_run<SLICED, 4, 4, 3>(n, P, B, rho, nsteps, ws, s, graph, tiled);
+            return planes_run<SLICED, 5, 4, 4>(n, P, B, rho, nsteps, ws, s, graph, tiled);
         default: return fail(LB_ENOTSUP, "plane chain: BF16 precisions only");
     }
 }
@@ -821,7 +1012,7 @@ size_t large_ws_bytes(int family, int n, lb_precision prec, int B) {
         const size_t Kp = (size_t)(n + 63) / 64 * 64;
         return 2 * align256(n * Kp * tsz) + 4 * align256(B * Kp * tsz);
     }
-    if (family == VF_PLANES) {
+    if (family == VF_PLANES || family == VF_TPLANES) {
         const size_t Kp = (size_t)(n + KCH - 1) / KCH * KCH;
         const size_t PD = prec == LB_BF16_HILO ? 2 : 5, XD = prec == LB_BF16_HILO ? 2 : 4;
         return align256(PD * 2 * n * Kp * 2) + align256(XD * 3 * B * Kp * 2) + align256((size_t)B * n * sizeof(cd)) +

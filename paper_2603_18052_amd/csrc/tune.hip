@@ -78,6 +78,7 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
     } else if (prec == LB_BF16_HILO || prec == LB_BF16_SLICED) {
         if (n <= bf16_fused_max_n(prec)) add(VF_BF16_FUSED * 100);
         add2(VF_PLANES * 100);
+        add2(VF_TPLANES * 100);
     } else if (prec == LB_Q15) {
         if (n <= kWaveChainMaxN) add(VF_Q15 * 100);
         add2(VF_Q15 * 100 + 1);
@@ -98,7 +99,8 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
 // GEMM per step: the LDS-tiled one (64 states x 48 outputs per workgroup,
 // eight wavefronts) once its tiles fill the chip (>= 240), else one output
 // tile per wavefront up to 256 states (more workgroups) and two beyond, or a
-// matvec for few states.
+// matvec for few states.  BF16: the fused chain while P fits on chip, else
+// the BF16 plane GEMM per step, LDS-tiled once its tiles fill the chip.
 int chain_heuristic(int n, lb_precision prec, int B) {
     switch (prec) {
         case LB_C128:
@@ -117,8 +119,11 @@ int chain_heuristic(int n, lb_precision prec, int B) {
             return prec == LB_C128 ? VF_BASELINE * 100 : VF_MATVEC * 100;
         }
         case LB_BF16_HILO:
-        case LB_BF16_SLICED:
-            return n <= bf16_fused_max_n(prec) ? VF_BF16_FUSED * 100 : VF_PLANES * 100;
+        case LB_BF16_SLICED: {
+            if (n <= bf16_fused_max_n(prec)) return VF_BF16_FUSED * 100;
+            const long long tiles = (long long)((B + 63) / 64) * ((n + 47) / 48);
+            return tiles >= 240 ? VF_TPLANES * 100 : VF_PLANES * 100;
+        }
         case LB_Q15:
             return n <= kWaveChainMaxN ? VF_Q15 * 100 : VF_Q15 * 100 + 1;
         default:
@@ -160,6 +165,7 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_Q15: return chain_q15(n, P, B, rho, nsteps, prm == 0, graph, ws, s);
         case VF_TAIL: return chain_tail(n, P, prec, prm, B, rho, nsteps, s);
         case VF_TGEMM: return chain_tgemm(n, P, prec, prm, B, rho, nsteps, ws, s, graph);
+        case VF_TPLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s, graph, true);
         default: return fail(LB_EINVAL, "unknown chain variant");
     }
 }
@@ -256,7 +262,8 @@ extern "C" int lindblad_tune(int n, const void *P, lb_precision prec, int B, con
         if (variant_param(ids[i]) >= kGraphVariant && probe_steps <= 2 * kGraphSteps &&
             (variant_family(ids[i]) == VF_BASELINE || variant_family(ids[i]) == VF_GEMM ||
              variant_family(ids[i]) == VF_MATVEC || variant_family(ids[i]) == VF_PLANES ||
-             variant_family(ids[i]) == VF_Q15 || variant_family(ids[i]) == VF_TGEMM))
+             variant_family(ids[i]) == VF_Q15 || variant_family(ids[i]) == VF_TGEMM ||
+             variant_family(ids[i]) == VF_TPLANES))
             continue;
         w->used = base;
         st = chain_run_variant(n, Pc, prec, B, x, probe_steps, ids[i], w, stream);  // warm-up

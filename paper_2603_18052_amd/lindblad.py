@@ -57,7 +57,7 @@ SYMBOLS = {
 
 # Chain variant families (id = family * 100 + tile parameter).
 VARIANT_FAMILIES = {1: "baseline", 2: "wave", 3: "fused", 4: "bf16_fused", 5: "gemm", 6: "matvec32", 7: "planes",
-                    8: "fused_balanced", 9: "q15", 10: "fused_tail", 11: "gemm_tiled"}
+                    8: "fused_balanced", 9: "q15", 10: "fused_tail", 11: "gemm_tiled", 12: "planes_tiled"}
 
 
 GRAPH_VARIANT = 50  # added to a per-step family: steps replayed from a captured HIP graph
@@ -66,8 +66,8 @@ GRAPH_VARIANT = 50  # added to a per-step family: steps replayed from a captured
 def variant_name(v: int) -> str:
     fam, prm = divmod(int(v), 100)
     name = VARIANT_FAMILIES.get(fam, f"family{fam}")
-    graph = fam in (1, 5, 6, 7, 9, 11) and prm >= GRAPH_VARIANT
-    prm = prm % GRAPH_VARIANT if fam in (1, 5, 6, 7, 9, 11) else prm
+    graph = fam in (1, 5, 6, 7, 9, 11, 12) and prm >= GRAPH_VARIANT
+    prm = prm % GRAPH_VARIANT if fam in (1, 5, 6, 7, 9, 11, 12) else prm
     if fam == 3:
         name = f"{name}(k{prm})"
     elif fam == 5:

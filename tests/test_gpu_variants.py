@@ -130,7 +130,7 @@ def test_graph_replay_matches_direct_launches(lb, d, B, N, prec):
     n = d * d
     P = T(oracle_P(d))
     X = states(d, B, 5)
-    graph = [v for v in lb.chain_variants(n, prec, B) if v % 100 >= lb.GRAPH_VARIANT and v // 100 in (1, 5, 6, 7, 11)]
+    graph = [v for v in lb.chain_variants(n, prec, B) if v % 100 >= lb.GRAPH_VARIANT and v // 100 in (1, 5, 6, 7, 11, 12)]
     assert graph
     for v in graph:
         a, b = T(X.copy()), T(X.copy())
