@@ -1,7 +1,7 @@
 """Workload for rocprofv3 counter runs: one plain device copy of a known
 size (calibrates FETCH_SIZE / WRITE_SIZE against bytes actually moved), then
-one launch of a chain kernel on the d = 9 workload (B = 4096 Wishart states,
-1e4 steps) in the requested precision.
+one chain on the d = 9 workload (B = 4096 Wishart states, 1e4 steps) or the
+d = 27 workload (--d 27: B = 1024, a few steps) in the requested precision.
 
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR -o run -- \\
         python -m paper_2603_18052_amd.profile_kernels --precision c128
@@ -20,9 +20,14 @@ COPY_BYTES = 512 << 20
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--precision", default="c128")
-    ap.add_argument("--nsteps", type=int, default=10_000)
-    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--d", type=int, default=9, choices=(9, 27))
+    ap.add_argument("--nsteps", type=int, default=None, help="default 10^4 (d = 9), 40 (d = 27)")
+    ap.add_argument("--batch", type=int, default=None, help="default 4096 (d = 9), 1024 (d = 27)")
     a = ap.parse_args()
+    if a.nsteps is None:
+        a.nsteps = 10_000 if a.d == 9 else 40
+    if a.batch is None:
+        a.batch = 4096 if a.d == 9 else 1024
     import torch
     from paper_2603_18052_amd import lindblad as lb
     from paper_2603_18052_amd import workloads as W
@@ -32,7 +37,7 @@ def main():
     dst = torch.empty_like(src)
     dst.copy_(src)  # the calibration copy: COPY_BYTES read, COPY_BYTES written
     torch.cuda.synchronize()
-    cfg = W.config2(B=a.batch, nsteps=a.nsteps)
+    cfg = (W.config2 if a.d == 9 else W.config3)(B=a.batch, nsteps=a.nsteps)
     H, Lk = torch.from_numpy(cfg["H"]).to(dev), torch.from_numpy(cfg["Lk"]).to(dev)
     P = lb.propagator(lb.liouvillian(H, Lk), cfg["dt"])
     X = torch.from_numpy(cfg["rho0"].reshape(a.batch, -1)).to(dev)
