@@ -224,6 +224,21 @@ def test_chain_c128_config2_full_size_sampled(lb, systems):
     assert td.max() < 1e-12
 
 
+def test_chain_c64_config2_full_size_sampled(lb, systems):
+    """Complex64 at config-2 size (B = 4096) in the bench's launch
+    configuration, 1e3 steps; the oracle recomputes a sample of states."""
+    c = W.config2()
+    P = oracle_P(systems, 2)
+    X = c["rho0"].reshape(4096, 81)
+    x = T(X.copy())
+    lb.propagate(T(P), x, 1000, "c64")
+    idx = [0, 5, 2047, 4095]
+    ref = oracle.propagate(P, X[idx], 1000)
+    td = oracle.trace_distance(N(x)[idx].reshape(-1, 9, 9), ref.reshape(-1, 9, 9))
+    print(f"c64 d=9 B=4096 N=1e3: trace distance max {td.max():.3e}")
+    assert td.max() < 1e-4
+
+
 # ------------------------------------------------------------ c64 (literal)
 @pytest.mark.parametrize("q", [1, 2])
 def test_chain_c64_error_report(lb, systems, q):

@@ -80,3 +80,23 @@ def test_d27_deterministic(lb, P27):
         a = run(lb, P27, X, 10, prec)
         b = run(lb, P27, X, 10, prec)
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec,nsteps,tol,variant", [("c128", 200, 1e-12, 1108), ("c64", 200, 5e-5, 1108),
+                                                     ("bf16_sliced", 1000, 1e-6, 1200)])
+def test_d27_config3_full_batch_sampled(lb, P27, prec, nsteps, tol, variant):
+    """Config 3 at its full batch (B = 1024) in the launch configuration the
+    bench times (the LDS-tiled step kernels, 256 workgroups); the oracle
+    recomputes a sample of states (states are independent)."""
+    c = W.config3()
+    X = c["rho0"].reshape(1024, 729)
+    assert lb.chain_variant(729, prec, 1024) == variant
+    got = run(lb, P27, X, nsteps, prec)
+    idx = [0, 1, 513, 1023]
+    ref = oracle.propagate(P27, X[idx], nsteps)
+    g = got[idx]
+    if prec == "c128":
+        assert oracle.rel_fro(g, ref) < tol
+    td = oracle.trace_distance(g.reshape(-1, 27, 27), ref.reshape(-1, 27, 27))
+    print(f"{prec} d=27 B=1024 N={nsteps}: trace distance max {td.max():.3e}")
+    assert td.max() < (tol if prec != "c128" else 1e-12)
