@@ -291,13 +291,66 @@ def fixed_point_section(lb, W, torch, dev, ws):
     return out
 
 
+def expmv_section(lb, W, torch, dev, ws):
+    """Action of the exponential (no propagator, no LU): per-step cost at
+    d = 27 beside the dense chain and the build, and a one-shot use -- one
+    state through the M = 200 slice generators of the GRAPE workload -- by
+    expmv against batched builds plus one matvec per slice."""
+    out = {}
+    cfg = W.config3(B=1024, nsteps=20)
+    n = 729
+    H, Lk = torch.from_numpy(cfg["H"]).to(dev), torch.from_numpy(cfg["Lk"]).to(dev)
+    L = lb.liouvillian(H, Lk)
+    X0 = torch.from_numpy(cfg["rho0"].reshape(-1, n)).to(dev)
+    for B, N in ((1, 50), (64, 20), (1024, 10)):
+        x = X0[:B].clone()
+        lb.expmv(L, x, cfg["dt"], 1, ws=ws)  # warm-up
+        x = X0[:B].clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prods = lb.expmv(L, x, cfg["dt"], N, ws=ws)
+        torch.cuda.synchronize()
+        dtm = time.perf_counter() - t0
+        out[f"d27_B{B}"] = {"ms_per_step": dtm * 1e3 / N, "state_steps_per_s": B * N / dtm,
+                            "products_per_step": prods, "nsteps": N}
+    # one-shot: x_{m+1} = exp(dt L_m) x_m over the GRAPE slices (d = 27)
+    p = W.grape_problem(3, M=200)
+    Hs = torch.from_numpy(p["H0"]).to(dev) + torch.einsum(
+        "mc,cij->mij", torch.from_numpy(p["u"]).to(dev).to(torch.complex128), torch.from_numpy(p["Hc"]).to(dev))
+    Lk27 = torch.from_numpy(p["Lk"]).to(dev)
+    Ls = torch.stack([lb.liouvillian(Hs[m].contiguous(), Lk27) for m in range(p["M"])])
+    x0 = torch.from_numpy(p["rho0"].reshape(1, -1)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Ps = lb.propagator(Ls, p["dt"], ws=ws)
+    xa = x0.clone()
+    for m in range(p["M"]):
+        lb.propagate(Ps[m], xa, 1, "c128", ws=ws)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    del Ps
+    xb = x0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prods = 0
+    for m in range(p["M"]):
+        prods += lb.expmv(Ls[m], xb, p["dt"], 1, ws=ws)
+    torch.cuda.synchronize()
+    t_expmv = time.perf_counter() - t0
+    rel = float(torch.linalg.norm(xb - xa) / torch.linalg.norm(xa))
+    out["grape_forward_d27_M200"] = {"builds_plus_matvecs_ms": t_build * 1e3, "expmv_ms": t_expmv * 1e3,
+                                     "expmv_products": prods, "rel_diff": rel}
+    return out
+
+
 def extra_sections(lb, W, torch, dev, ws):
     """d = 3 single state (config 1), the timing models, the fixed-point
     chain, d = 27 chains (config 3), GRAPE gradients (config 4), mixed batch
     (config 5)."""
     out = {"d3_config1": config1_section(lb, W, torch, dev, ws),
            "timing_models": timing_models_section(lb, W, torch, dev),
-           "fixed_point_q15": fixed_point_section(lb, W, torch, dev, ws)}
+           "fixed_point_q15": fixed_point_section(lb, W, torch, dev, ws),
+           "expmv_report": expmv_section(lb, W, torch, dev, ws)}
     # ---- config 3: d = 27, B in {1, 64, 1024}, 1e3 steps
     cfg = W.config3(B=1024, nsteps=1000)
     n, N = 729, cfg["nsteps"]

@@ -149,6 +149,31 @@ int lindblad_propagate(int n, const void *P, lb_precision prec, int B, void *rho
 int lindblad_propagate_baseline(int n, const void *P, int B, void *rho, long long nsteps,
                                 lb_workspace *ws, hipStream_t stream);
 
+/* Action of the exponential without forming the propagator -- the
+ * alternative the paper's GRAPE section names for removing the dense LU
+ * solve; it leaves the fixed-propagator regime (every step re-applies a
+ * series in L):  rho_b <- (e^{tL})^nsteps rho_b  for b < B.
+ *   n      : 1 <= n <= 4096
+ *   L      : n x n complex128 generator (row-major), DEVICE memory
+ *   t      : finite step length
+ *   B, rho : B x n complex128 states, DEVICE memory, in place
+ *   nsteps : >= 0
+ *   products (optional HOST int*): receives s m, the number of products
+ *            L V per step
+ * FP64 throughout: mu = tr(L) / n, X = t (L - mu I); s sub-steps of the
+ * m-term Taylor series of X / s, each times e^{t mu / s}; (s, m) from
+ * lindblad_expmv_params(||X||_1).  Synchronises the stream once (the series
+ * length depends on ||X||_1), then enqueues the steps.  LB_EINVAL if
+ * ||X||_1 is not finite or too large for the series. */
+int lindblad_expmv(int n, const void *L, double t, int B, void *rho, long long nsteps, int *products,
+                   lb_workspace *ws, hipStream_t stream);
+
+/* Host only: the sub-steps s and terms m lindblad_expmv uses for
+ * ||t (L - mu I)||_1 = a >= 0: the smallest product count s m over theta in
+ * {0.5, 1, ..., 4} with a / s <= theta and
+ * e^{2 theta} theta^{m+1} / (m+1)! <= 2^-53 (a = 0: s = m = 1). */
+int lindblad_expmv_params(double a, int *s, int *m);
+
 /* Chain variants and their autotuner (Alg. 2 / Alg. 3: the same steps, a
  * choice of kernel and tile shape).  A variant id is family * 100 + tile
  * parameter:

@@ -61,6 +61,10 @@ int chain_planes(int n, const cd *P, lb_precision prec, int B, cd *rho, long lon
 int chain_tgemm(int n, const cd *P, lb_precision prec, int waves, int B, cd *rho, long long nsteps, Workspace *ws,
                 hipStream_t s, bool graph = false);
 size_t large_ws_bytes(int family, int n, lb_precision prec, int B);
+// e^{tL} applied by s sub-steps of an m-term Taylor series of t (L - mu I) / s
+int expmv_run(int n, const cd *L, double t, double mur, double mui, int s, int m, int B, cd *rho, long long nsteps,
+              Workspace *ws, hipStream_t st);
+int expmv_params(double a, int *s, int *m);
 int chain_q15(int n, const cd *P, int B, cd *rho, long long nsteps, bool wave, bool graph, Workspace *ws,
               hipStream_t s);
 size_t q15_ws_bytes(int n, int B, bool wave);

@@ -21,6 +21,7 @@
 // Complex64 chains can also run as a per-state FP32 matvec (one wavefront per
 // state and row), the counterpart of the FP64 baseline.
 #include <cmath>
+#include <complex>
 
 #include "chain.hpp"
 
@@ -953,6 +954,178 @@ static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Work
     LB_TRY(check_launch("plane_gemm"));
     if (nsteps & 1) LB_HIP(hipMemcpyAsync(rho, Yt, ybytes, hipMemcpyDeviceToDevice, s));
     return LB_OK;
+}
+
+// ------------------------------------------------ action of the exponential
+// One Taylor term of e^{tL} v with shift mu: V <- alpha (Y - mu V) (Y = L V
+// from the step GEMM), F <- F + V.  Planes [B][Kp]; padding columns stay zero.
+__global__ void __launch_bounds__(256) expmv_term_kernel(int n, int B, int Kp, const double *__restrict__ Yr,
+                                                         const double *__restrict__ Yi, double *__restrict__ Vr,
+                                                         double *__restrict__ Vi, double *__restrict__ Fr,
+                                                         double *__restrict__ Fi, double alpha, double mur,
+                                                         double mui) {
+    const long long total = (long long)B * n;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long b = e / n, i = e - b * n, o = b * Kp + i;
+        const double vr = Vr[o], vi = Vi[o];
+        const double tr = alpha * (Yr[o] - (mur * vr - mui * vi));
+        const double ti = alpha * (Yi[o] - (mur * vi + mui * vr));
+        Vr[o] = tr;
+        Vi[o] = ti;
+        Fr[o] += tr;
+        Fi[o] += ti;
+    }
+}
+
+// End of a sub-step: F <- eta F; V <- F (the next sub-step starts from it);
+// on the last sub-step of the last step F goes to rho (complex128).
+__global__ void __launch_bounds__(256) expmv_rescale_kernel(int n, int B, int Kp, double *__restrict__ Fr,
+                                                            double *__restrict__ Fi, double *__restrict__ Vr,
+                                                            double *__restrict__ Vi, double er, double ei,
+                                                            cd *__restrict__ out) {
+    const long long total = (long long)B * n;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long b = e / n, i = e - b * n, o = b * Kp + i;
+        const double fr = Fr[o], fi = Fi[o];
+        const double gr = er * fr - ei * fi, gi = er * fi + ei * fr;
+        Fr[o] = gr;
+        Fi[o] = gi;
+        Vr[o] = gr;
+        Vi[o] = gi;
+        if (out) out[e] = {gr, gi};
+    }
+}
+
+// Small batches: one wavefront per (state, row) forms (L v)_i with lanes
+// along the row (coalesced reads of L, fixed-order shuffle reduction) and
+// applies the term update in its epilogue: one launch per product.
+__global__ void __launch_bounds__(256) expmv_matvec_kernel(int n, const cd *__restrict__ L, const cd *__restrict__ V,
+                                                           cd *__restrict__ Vn, cd *__restrict__ F,
+                                                           long long rows_total, double alpha, double mur,
+                                                           double mui) {
+    const int lane = threadIdx.x & 63;
+    const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
+    for (long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < rows_total; w += nwaves) {
+        const long long b = w / n;
+        const int i = (int)(w - b * n);
+        const cd *Li = L + (size_t)i * n;
+        const cd *vb = V + (size_t)b * n;
+        double re = 0.0, im = 0.0;
+        for (int k = lane; k < n; k += 64) {
+            const cd a = Li[k], v = vb[k];
+            re = fma(a.re, v.re, fma(-a.im, v.im, re));
+            im = fma(a.re, v.im, fma(a.im, v.re, im));
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            re += __shfl_xor(re, off);
+            im += __shfl_xor(im, off);
+        }
+        if (lane == 0) {
+            const size_t o = (size_t)b * n + i;
+            const cd v = vb[i];
+            const double tr = alpha * (re - (mur * v.re - mui * v.im));
+            const double ti = alpha * (im - (mur * v.im + mui * v.re));
+            Vn[o] = {tr, ti};
+            F[o] = {F[o].re + tr, F[o].im + ti};
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) expmv_rescale_c_kernel(long long count, cd *__restrict__ F, cd *__restrict__ V,
+                                                              double er, double ei, cd *__restrict__ out) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (long long)gridDim.x * blockDim.x) {
+        const cd f = F[e];
+        const cd g = {er * f.re - ei * f.im, er * f.im + ei * f.re};
+        F[e] = g;
+        V[e] = g;
+        if (out) out[e] = g;
+    }
+}
+
+constexpr int kExpmvSmallB = 8;  // up to this many states: the per-row matvec path
+
+// rho_b <- (e^{tL})^nsteps rho_b by s sub-steps of the m-term Taylor series
+// of t (L - mu I) / s, each sub-step scaled by eta = e^{t mu / s}.  The
+// products L V are the FP64 step GEMMs of the chain (the LDS-tiled one when
+// its tiles fill the chip).
+int expmv_run(int n, const cd *L, double t, double mur, double mui, int s, int m, int B, cd *rho, long long nsteps,
+              Workspace *ws, hipStream_t st) {
+    if (nsteps == 0 || B == 0) return LB_OK;
+    const std::complex<double> eta = std::exp(std::complex<double>(t * mur / s, t * mui / s));
+    if (B <= kExpmvSmallB) {
+        const size_t xb = (size_t)B * n * sizeof(cd);
+        LB_TRY(ws_ensure(ws, 3 * align256(xb)));
+        cd *F = (cd *)ws_take(ws, xb), *V[2] = {(cd *)ws_take(ws, xb), (cd *)ws_take(ws, xb)};
+        LB_HIP(hipMemcpyAsync(F, rho, xb, hipMemcpyDeviceToDevice, st));
+        LB_HIP(hipMemcpyAsync(V[0], rho, xb, hipMemcpyDeviceToDevice, st));
+        const long long rows = (long long)B * n;
+        const int blocks = (int)((rows + 3) / 4);
+        for (long long step = 0; step < nsteps; ++step) {
+            for (int q = 0; q < s; ++q) {
+                for (int j = 1; j <= m; ++j)
+                    expmv_matvec_kernel<<<blocks, 256, 0, st>>>(n, L, V[(j - 1) & 1], V[j & 1], F, rows,
+                                                                t / ((double)s * j), mur, mui);
+                const bool last = step + 1 == nsteps && q + 1 == s;
+                expmv_rescale_c_kernel<<<grid1(rows), 256, 0, st>>>(rows, F, V[0], eta.real(), eta.imag(),
+                                                                    last ? rho : nullptr);
+            }
+            LB_TRY(check_launch("expmv_step"));
+        }
+        return LB_OK;
+    }
+    const int Kp = (n + 63) / 64 * 64;
+    const size_t pp = (size_t)n * Kp * sizeof(double), xp = (size_t)B * Kp * sizeof(double);
+    LB_TRY(ws_ensure(ws, 2 * align256(pp) + 6 * align256(xp)));
+    double *Lr = (double *)ws_take(ws, pp), *Li = (double *)ws_take(ws, pp);
+    double *Vr = (double *)ws_take(ws, xp), *Vi = (double *)ws_take(ws, xp);
+    double *Yr = (double *)ws_take(ws, xp), *Yi = (double *)ws_take(ws, xp);
+    double *Fr = (double *)ws_take(ws, xp), *Fi = (double *)ws_take(ws, xp);
+    to_planes_kernel<double><<<grid1((long long)n * Kp), 256, 0, st>>>(n, n, Kp, L, Lr, Li);
+    to_planes_kernel<double><<<grid1((long long)B * Kp), 256, 0, st>>>(B, n, Kp, rho, Vr, Vi);
+    to_planes_kernel<double><<<grid1((long long)B * Kp), 256, 0, st>>>(B, n, Kp, rho, Fr, Fi);
+    // Y: zero padding columns (its other entries are written by every product)
+    to_planes_kernel<double><<<grid1((long long)B * Kp), 256, 0, st>>>(B, n, Kp, rho, Yr, Yi);
+    LB_TRY(check_launch("expmv_planes"));
+    typedef TgShape<double, 8> S;
+    const bool tiled = (long long)((B + TGB - 1) / TGB) * ((n + TGI - 1) / TGI) >= 240;
+    const size_t lds = 2 * (size_t)S::BUF * sizeof(double);
+    if (tiled) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            LB_HIP(hipFuncSetAttribute((const void *)tgemm_step_kernel<double, 8>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            attr_set = true;
+        }
+    }
+    const int nbt = (B + TGB - 1) / TGB, nit = (n + TGI - 1) / TGI;
+    dim3 grid((n + 15) / 16, (B + TS - 1) / TS);
+    const int eg = grid1((long long)B * n);
+    for (long long step = 0; step < nsteps; ++step) {
+        for (int q = 0; q < s; ++q) {
+            for (int j = 1; j <= m; ++j) {
+                if (tiled)
+                    tgemm_step_kernel<double, 8><<<nbt * nit, 512, lds, st>>>(n, B, Kp, nbt, nit, Vr, Vi, Lr, Li, Yr,
+                                                                            Yi, nullptr);
+                else
+                    gemm_step_kernel<double, 1><<<grid, 256, 0, st>>>(n, B, Kp, Vr, Vi, Lr, Li, Yr, Yi, nullptr);
+                expmv_term_kernel<<<eg, 256, 0, st>>>(n, B, Kp, Yr, Yi, Vr, Vi, Fr, Fi, t / ((double)s * j), mur, mui);
+            }
+            const bool last = step + 1 == nsteps && q + 1 == s;
+            expmv_rescale_kernel<<<eg, 256, 0, st>>>(n, B, Kp, Fr, Fi, Vr, Vi, eta.real(), eta.imag(),
+                                                     last ? rho : nullptr);
+        }
+        LB_TRY(check_launch("expmv_step"));
+    }
+    return LB_OK;
+}
+
+size_t expmv_ws_bytes(int n, int B) {
+    const size_t Kp = (size_t)(n + 63) / 64 * 64;
+    return 2 * align256(n * Kp * sizeof(double)) + 6 * align256((size_t)B * Kp * sizeof(double));
 }
 
 int chain_matvec(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,

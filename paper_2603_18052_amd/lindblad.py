@@ -53,6 +53,11 @@ SYMBOLS = {
                                      ctypes.c_void_p, ctypes.c_void_p]),
     "lindblad_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "lindblad_batch_set_window": (ctypes.c_int, [ctypes.c_size_t]),
+    "lindblad_expmv": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_longlong, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "lindblad_expmv_params": (ctypes.c_int, [ctypes.c_double, ctypes.POINTER(ctypes.c_int),
+                                             ctypes.POINTER(ctypes.c_int)]),
 }
 
 # Chain variant families (id = family * 100 + tile parameter).
@@ -276,6 +281,26 @@ def propagate_baseline(P: torch.Tensor, rho: torch.Tensor, nsteps: int, ws: Work
     B = rho.numel() // n
     _check(lib().lindblad_propagate_baseline(n, _ptr(P), B, _ptr(rho), int(nsteps), _ws(ws), _stream()))
     return rho
+
+
+def expmv(L: torch.Tensor, rho: torch.Tensor, t: float, nsteps: int = 1, ws: Workspace | None = None) -> int:
+    """rho <- (e^{tL})^nsteps rho without forming the propagator (in place);
+    returns the number of products L V per step."""
+    L = _dev(L, name="L")
+    rho = _dev(rho, name="rho")
+    n = L.shape[0]
+    B = rho.numel() // n
+    prods = ctypes.c_int(0)
+    _check(lib().lindblad_expmv(n, _ptr(L), float(t), B, _ptr(rho), int(nsteps), ctypes.byref(prods), _ws(ws),
+                                _stream()))
+    return prods.value
+
+
+def expmv_params(a: float):
+    """(s, m) of lindblad_expmv for ||t (L - mu I)||_1 = a (host only)."""
+    s, m = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib().lindblad_expmv_params(float(a), ctypes.byref(s), ctypes.byref(m)))
+    return s.value, m.value
 
 
 def grape_gradient(L0, Lc, u, dt, x0, w, theta=0.25, checkpoint_bytes=0, ws: Workspace | None = None):

@@ -143,3 +143,21 @@ def test_c_client_compiles_against_the_header(tmp_path):
            str(tmp_path / "abi_client"), "-L", pkg, "-llindblad", "-L", "/opt/rocm/lib", "-lamdhip64"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_expmv_params_meet_the_remainder_bound():
+    """lindblad_expmv_params (host only): every sub-step satisfies
+    e^{2r} r^{m+1} / (m+1)! <= 2^-53 with r = a / s <= 4, and bad norms fail."""
+    import math
+    from paper_2603_18052_amd import lindblad as lb
+    assert lb.expmv_params(0.0) == (1, 1)
+    for a in (1e-6, 0.3, 1.0, 4.0, 13.0, 26.5, 100.0, 1e4):
+        s, m = lb.expmv_params(a)
+        r = a / s
+        assert s >= 1 and 1 <= m <= 80 and r <= 4.0 + 1e-12
+        assert 2 * r + (m + 1) * math.log(r) - math.lgamma(m + 2) <= -53 * math.log(2) + 1e-9, (a, s, m)
+    s1, m1 = lb.expmv_params(13.0)
+    assert s1 * m1 <= 13 * 18  # never worse than theta = 1 (18 terms, 13 sub-steps)
+    for bad in (-1.0, float("inf"), float("nan"), 1e12):
+        with pytest.raises(lb.LindbladError):
+            lb.expmv_params(bad)
