@@ -216,7 +216,7 @@ constexpr int FRECHET_MATS = 26;  // n x n temporaries per slice (RHS3 counts 3)
 static size_t frechet_bytes(int n, int Mc) {
     const size_t mat = align256((size_t)n * n * sizeof(cd) * Mc);
     return FRECHET_MATS * mat + 4 * align256(Mc * sizeof(double)) + align256((size_t)Mc * n * sizeof(int)) +
-           2 * align256(Mc * sizeof(int));
+           2 * align256(Mc * sizeof(int)) + 2 * align256((size_t)zgemm_mask_bytes(n, n) * Mc);
 }
 
 // G[m] = L(A_m, x_m lam_m^dag) for a chunk of Mc slices; A_m = dt Lg[m].
@@ -244,6 +244,9 @@ static int frechet_chunk(int n, int Mc, const cd *Lg, const double *dt_host, con
     int *d_s = (int *)ws_take(ws, Mc * sizeof(int));
     int *d_info = (int *)ws_take(ws, Mc * sizeof(int));
     int *d_ipiv = (int *)ws_take(ws, (size_t)Mc * n * sizeof(int));
+    const long long mb = zgemm_mask_bytes(n, n);
+    unsigned char *mA = (unsigned char *)ws_take(ws, (size_t)mb * Mc);
+    unsigned char *mA2 = (unsigned char *)ws_take(ws, (size_t)mb * Mc);
 
     LB_TRY(fill_i32_launch(d_info, Mc, s));
     std::vector<int> sv(Mc);
@@ -261,10 +264,13 @@ static int frechet_chunk(int n, int Mc, const cd *Lg, const double *dt_host, con
     g.batch = Mc;
     g.lda = g.ldb = g.ldd = g.ldc = g.ldx = n;
     g.sA = g.sB = g.sD = g.sC = g.sX = (long long)nn;
-    auto mul = [&](const cd *X, const cd *Y, cd *Z, bool acc) {
+    // zero 64 x 16 tiles of the sparse left factors A and A2 are skipped
+    auto mul = [&](const cd *X, const cd *Y, cd *Z, bool acc, const unsigned char *mask = nullptr) {
         ZgemmBatch h = g;
         h.A = X, h.B = Y, h.D = Z;
         if (acc) h.beta = 1.0, h.Cin = Z;
+        h.amask = mask;
+        h.sMask = mb;
         return zgemm_batched(h, s);
     };
     auto mul_lc = [&](const cd *X, const cd *Y, cd *Z, const cd *x0, const cd *x1, const cd *x2, double c0,
@@ -282,24 +288,26 @@ static int frechet_chunk(int n, int Mc, const cd *Lg, const double *dt_host, con
         const double c[3] = {c0, c1, c2};
         return zlincomb(n, Mc, 3, X, c, 0.0, D, s);
     };
-    LB_TRY(mul(A, A, A2, false));
-    LB_TRY(mul(A, E, M2, false));
+    LB_TRY(zgemm_tile_mask(n, n, Mc, A, n, (long long)nn, mA, s));
+    LB_TRY(mul(A, A, A2, false, mA));
+    LB_TRY(zgemm_tile_mask(n, n, Mc, A2, n, (long long)nn, mA2, s));
+    LB_TRY(mul(A, E, M2, false, mA));
     LB_TRY(mul(E, A, M2, true));
-    LB_TRY(mul(A2, A2, A4, false));
-    LB_TRY(mul(A2, M2, M4, false));
+    LB_TRY(mul(A2, A2, A4, false, mA2));
+    LB_TRY(mul(A2, M2, M4, false, mA2));
     LB_TRY(mul(M2, A2, M4, true));
-    LB_TRY(mul(A2, A4, A6, false));
+    LB_TRY(mul(A2, A4, A6, false, mA2));
     LB_TRY(mul(A4, M2, M6, false));
     LB_TRY(mul(M4, A2, M6, true));
     LB_TRY(lin3(A6, A4, A2, b[13], b[11], b[9], W1));
     LB_TRY(mul_lc(A6, W1, W, A6, A4, A2, b[7], b[5], b[3], b[1]));
-    LB_TRY(mul(A, W, U, false));
+    LB_TRY(mul(A, W, U, false, mA));
     LB_TRY(lin3(A6, A4, A2, b[12], b[10], b[8], Z1));
     LB_TRY(mul_lc(A6, Z1, V, A6, A4, A2, b[6], b[4], b[2], b[0]));
     LB_TRY(lin3(M6, M4, M2, b[13], b[11], b[9], T));
     LB_TRY(mul_lc(A6, T, Lw, M6, M4, M2, b[7], b[5], b[3], 0.0));
     LB_TRY(mul(M6, W1, Lw, true));
-    LB_TRY(mul(A, Lw, Lu, false));
+    LB_TRY(mul(A, Lw, Lu, false, mA));
     LB_TRY(mul(E, W, Lu, true));
     LB_TRY(lin3(M6, M4, M2, b[12], b[10], b[8], T));
     LB_TRY(mul_lc(A6, T, Lv, M6, M4, M2, b[6], b[4], b[2], 0.0));

@@ -100,8 +100,18 @@ struct ZgemmBatch {
     double gamma = 0.0;          // added on the diagonal (square D only)
     const int *active = nullptr;
     int level = 0;
+    // optional: amask[b * sMask + tm * nkc + kc] == 0 marks an all-zero tile
+    // of A (rows [64 tm, 64 tm + 64), columns [16 kc, 16 kc + 16)); such
+    // k chunks are skipped (their products are exact zeros)
+    const unsigned char *amask = nullptr;
+    long long sMask = 0;
 };
 int zgemm_batched(const ZgemmBatch &g, hipStream_t s);
+// Zero-tile mask of `batch` M x K matrices A (leading dimension lda, stride
+// sA) in the layout ZgemmBatch::amask reads; mask_bytes(M, K) per matrix.
+long long zgemm_mask_bytes(int M, int K);
+int zgemm_tile_mask(int M, int K, int batch, const cd *A, long long lda, long long sA, unsigned char *mask,
+                    hipStream_t s);
 
 // Elementwise: D[b] = sum_t coef[t] X_t[b] + gamma I  (n x n, contiguous batches)
 int zlincomb(int n, int batch, int nx, const cd *const *X, const double *coef, double gamma, cd *D,

@@ -151,15 +151,17 @@ int odd_copy_launch(int n, int M, const int *d_s, const cd *src, cd *dst, hipStr
     return check_launch("odd_copy");
 }
 
+static size_t mask_bytes(int n, int M) { return align256((size_t)zgemm_mask_bytes(n, n) * M); }
+
 static size_t chunk_bytes(int n, int M) {
     const size_t mat = (size_t)n * n * sizeof(cd) * M;
     return 8 * align256(mat) + 4 * align256(M * sizeof(double)) + align256((size_t)M * n * sizeof(int)) +
-           2 * align256(M * sizeof(int));
+           2 * align256(M * sizeof(int)) + 2 * mask_bytes(n, M);
 }
 
 size_t build_async_bytes(int n, int M) {
     const size_t mat = (size_t)n * n * sizeof(cd) * M;
-    return 8 * align256(mat) + align256((size_t)M * n * sizeof(int));
+    return 8 * align256(mat) + align256((size_t)M * n * sizeof(int)) + 2 * mask_bytes(n, M);
 }
 
 // Alg. 1 after its scaling stage, for M matrices whose d_dt and d_s are on
@@ -180,6 +182,9 @@ int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *
     cd *Wp = (cd *)ws_take(ws, mat);
     cd *U = (cd *)ws_take(ws, mat);
     int *d_ipiv = (int *)ws_take(ws, (size_t)M * n * sizeof(int));
+    const long long mb = zgemm_mask_bytes(n, n);
+    unsigned char *mA = (unsigned char *)ws_take(ws, (size_t)mb * M);
+    unsigned char *mA2 = (unsigned char *)ws_take(ws, (size_t)mb * M);
     struct Release {
         Workspace *w;
         size_t m;
@@ -187,6 +192,8 @@ int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *
     } release{ws, mark};
 
     LB_TRY(scale_launch(n, M, L, d_dt, d_s, A, s));
+    // zero 64 x 16 tiles of the sparse left factors A and A2 are skipped
+    LB_TRY(zgemm_tile_mask(n, n, M, A, n, (long long)nn, mA, s));
     double b[14];
     pade13_coefficients(b);
     ZgemmBatch g;
@@ -194,15 +201,18 @@ int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *
     g.batch = M;
     g.lda = g.ldb = g.ldd = g.ldc = g.ldx = n;
     g.sA = g.sB = g.sD = g.sC = g.sX = (long long)nn;
-    auto mul = [&](const cd *X, const cd *Y, cd *Z) {
+    auto mul = [&](const cd *X, const cd *Y, cd *Z, const unsigned char *mask = nullptr) {
         ZgemmBatch h = g;
         h.A = X;
         h.B = Y;
         h.D = Z;
+        h.amask = mask;
+        h.sMask = mb;
         return zgemm_batched(h, s);
     };
-    LB_TRY(mul(A, A, A2));
-    LB_TRY(mul(A2, A2, A4));
+    LB_TRY(mul(A, A, A2, mA));
+    LB_TRY(zgemm_tile_mask(n, n, M, A2, n, (long long)nn, mA2, s));
+    LB_TRY(mul(A2, A2, A4, mA2));
     LB_TRY(mul(A4, A2, A6));
     {  // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
         const cd *X[3] = {A6, A4, A2};
@@ -231,7 +241,7 @@ int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *
         h.coef[0] = b[7], h.coef[1] = b[5], h.coef[2] = b[3];
         h.gamma = b[1];
         LB_TRY(zgemm_batched(h, s));
-        LB_TRY(mul(A, Wp, U));
+        LB_TRY(mul(A, Wp, U, mA));
     }
     {  // denominator V - U into A2, numerator V + U into P
         const cd *X[2] = {V, U};

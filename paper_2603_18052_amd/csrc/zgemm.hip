@@ -58,8 +58,18 @@ __global__ void __launch_bounds__(256) zgemm_kernel(ZgemmBatch g, int tiles_n) {
             rb[q] = (gk2 < g.K && gc < g.N) ? B[(size_t)gk2 * g.ldb + gc] : cd{0.0, 0.0};
         }
     };
-    load_tiles(0);
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
+    // k chunks in order, skipping all-zero tiles of A when a mask is given
+    // (uniform per workgroup: scalar reads of the mask)
+    const int nkc = (g.K + TK - 1) / TK;
+    const unsigned char *mrow = g.amask ? g.amask + (size_t)b * g.sMask + (size_t)tm * nkc : nullptr;
+    auto next_chunk = [&](int kc) {
+        if (mrow)
+            while (kc < nkc && !mrow[kc]) ++kc;
+        return kc;
+    };
+    int kc = next_chunk(0);
+    if (kc < nkc) load_tiles(kc * TK);
+    while (kc < nkc) {
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -72,7 +82,9 @@ __global__ void __launch_bounds__(256) zgemm_kernel(ZgemmBatch g, int tiles_n) {
             Bs_im[bk][bc] = rb[q].im;
         }
         __syncthreads();
-        if (k0 + TK < g.K) load_tiles(k0 + TK);
+        const int kn = next_chunk(kc + 1);
+        if (kn < nkc) load_tiles(kn * TK);
+        kc = kn;
 #pragma unroll
         for (int ks = 0; ks < TK / 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
@@ -124,6 +136,42 @@ __global__ void __launch_bounds__(256) zgemm_kernel(ZgemmBatch g, int tiles_n) {
                     D[(size_t)gi * g.ldd + gj] = v;
                 }
             }
+}
+
+// One wavefront per 64 x 16 tile: any nonzero entry sets its mask byte.
+__global__ void __launch_bounds__(256) tile_mask_kernel(int M, int K, int batch, const cd *__restrict__ A,
+                                                        long long lda, long long sA, unsigned char *__restrict__ mask,
+                                                        long long tiles_per) {
+    const int lane = threadIdx.x & 63;
+    const long long total = tiles_per * batch;
+    const int nkc = (K + TK - 1) / TK;
+    for (long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < total;
+         w += (long long)gridDim.x * (blockDim.x >> 6)) {
+        const long long b = w / tiles_per, t = w - b * tiles_per;
+        const int tm = (int)(t / nkc), kc = (int)(t - (long long)tm * nkc);
+        const cd *Ab = A + (size_t)b * sA;
+        bool nz = false;
+        for (int e = lane; e < TM * TK; e += 64) {
+            const int r = tm * TM + e / TK, k = kc * TK + e % TK;
+            if (r < M && k < K) {
+                const cd v = Ab[(size_t)r * lda + k];
+                nz = nz || v.re != 0.0 || v.im != 0.0;
+            }
+        }
+        const bool any = __any(nz);
+        if (lane == 0) mask[w] = any ? 1 : 0;
+    }
+}
+
+long long zgemm_mask_bytes(int M, int K) { return (long long)((M + TM - 1) / TM) * ((K + TK - 1) / TK); }
+
+int zgemm_tile_mask(int M, int K, int batch, const cd *A, long long lda, long long sA, unsigned char *mask,
+                    hipStream_t s) {
+    const long long per = zgemm_mask_bytes(M, K), total = per * batch;
+    long long blocks = (total + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    tile_mask_kernel<<<(int)blocks, 256, 0, s>>>(M, K, batch, A, lda, sA, mask, per);
+    return check_launch("tile_mask");
 }
 
 int zgemm_batched(const ZgemmBatch &g, hipStream_t s) {
