@@ -1,19 +1,27 @@
-// Batched solve D X = N (n x n, n right-hand sides) by LU with partial
+// Batched solve D X = N (n x n, nrhs right-hand sides) by LU with partial
 // pivoting -- line 6 of Alg. 1, where D = V - U and N = V + U.
 //
-// Right-looking blocked factorisation with panels of NB = 16 columns.  The
+// Right-looking factorisation blocked on two levels: outer blocks J of
+// NBO = 64 columns (batches of 8 or more matrices; single panels below, where
+// launch latency rules), each factored as four panels of NB = 16 columns.  The
 // right-hand sides ride along as extra columns of the trailing matrix, so the
-// forward substitution L^{-1} Pi N happens inside the factorisation's trailing
-// updates and no row swap is ever applied to the already factored columns
-// (they are not needed again).  Per panel:
-//   1. lu_panel:  one workgroup per matrix (1024 threads), each thread holds
-//      whole rows of the panel in registers; per column a block-wide argmax of
-//      |a|^2 (lowest row on ties), a row exchange through LDS, the multipliers
-//      and the rank-1 update of the rest of the panel;
-//   2. swap_trsm_lower: the panel's row exchanges and the unit-lower triangular
-//      solve of the panel rows, applied column by column to the trailing
-//      columns of D and to all columns of N;
-//   3. two batched MFMA GEMMs: D22 -= L21 U12 and N2 -= L21 N1.
+// forward substitution L^{-1} Pi N happens inside the factorisation's
+// updates.  Per outer block J:
+//   per panel, with updates confined to J's columns (all rows):
+//     1. lu_panel: one workgroup per matrix (1024 threads), each thread holds
+//        whole rows of the panel in registers; per column a block-wide argmax
+//        of |a|^2 (lowest row on ties), a row exchange through LDS, the
+//        multipliers and the rank-1 update of the rest of the panel;
+//     2. the panel's row exchanges on the earlier panels' L columns of J (so
+//        that J's L ends in the final row order), and exchanges plus the
+//        unit-lower solve of the panel rows on J's later columns;
+//     3. a batched MFMA GEMM A22 -= L21 U12 on J's later columns;
+//   then on every column right of J (D's trailing columns and all of N): all
+//   of J's exchanges in order, the unit-lower solve of J's rows (per panel,
+//   a 16-row solve and a GEMM on J's rows below it), and one rank-64 GEMM
+//   update of the rows below J -- a quarter of the trailing-matrix traffic of
+//   one rank-16 update per panel.  Factored columns left of J are not
+//   exchanged (they are not needed again).
 // Then blocked back substitution with U: per block of NB rows from the bottom,
 // trsm_upper on the block rows of N, then N_above -= U_above,block X_block.
 #include <climits>
@@ -23,6 +31,8 @@
 namespace lb {
 
 constexpr int NB = 16;
+constexpr int NBO = 64;  // outer block: 4 panels, one rank-64 trailing update
+constexpr int kOuterMinBatch = 8;  // below this many matrices: NB-wide blocks
 constexpr int PANEL_THREADS = 1024;
 
 template <int R>
@@ -156,53 +166,58 @@ __global__ void __launch_bounds__(PANEL_THREADS) lu_panel_kernel(cd *D, int n, l
     }
 }
 
-// Row exchanges of the panel and X1 = L11^{-1} X1 on every column outside the
-// panel: trailing columns of D first, then all n columns of N.
+// Row exchanges of the panel k0 (rows k0 .. k0 + nb) and X1 = L11^{-1} X1
+// (its unit-lower block) on D columns [dc0, dc0 + dcount) and the first
+// ncount columns of N, one column per thread; either step can be skipped.
 __global__ void __launch_bounds__(256) swap_trsm_lower_kernel(cd *D, cd *N, int n, int nrhs, long long sD,
-                                                              long long sN, int k0, int nb, const int *ipiv) {
+                                                              long long sN, int k0, int nb, const int *ipiv, int dc0,
+                                                              int dcount, int ncount, int do_swap, int do_solve) {
     const int b = blockIdx.y;
     cd *Dm = D + (size_t)b * sD;
-    cd *Nm = N + (size_t)b * sN;
+    cd *Nm = N ? N + (size_t)b * sN : nullptr;
     __shared__ cd L11[NB][NB];
     __shared__ int piv[NB];
     for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
         const int i = e / NB, j = e % NB;
-        L11[i][j] = (i < nb && j < nb) ? Dm[(size_t)(k0 + i) * n + k0 + j] : cd{0.0, 0.0};
+        L11[i][j] = (do_solve && i < nb && j < nb) ? Dm[(size_t)(k0 + i) * n + k0 + j] : cd{0.0, 0.0};
     }
     if (threadIdx.x < NB) piv[threadIdx.x] = threadIdx.x < nb ? ipiv[(size_t)b * n + k0 + threadIdx.x] : 0;
     __syncthreads();
-    const int ntrail = n - k0 - nb;
     const int v = blockIdx.x * blockDim.x + threadIdx.x;  // one column per thread (grid covers all)
-    if (v < ntrail + nrhs) {
-        cd *col = v < ntrail ? Dm + (k0 + nb + v) : Nm + (v - ntrail);
-        const size_t ld = v < ntrail ? (size_t)n : (size_t)nrhs;
-        for (int jj = 0; jj < nb; ++jj) {
-            const int r = k0 + jj, p = piv[jj];
-            if (p != r) {
-                const cd t = col[(size_t)r * ld];
-                col[(size_t)r * ld] = col[(size_t)p * ld];
-                col[(size_t)p * ld] = t;
-            }
-        }
-        cd x[NB];
-#pragma unroll
-        for (int i = 0; i < NB; ++i) x[i] = i < nb ? col[(size_t)(k0 + i) * ld] : cd{0.0, 0.0};
-#pragma unroll
-        for (int i = 1; i < NB; ++i) {
-            if (i < nb) {
-                cd acc = x[i];
-#pragma unroll
-                for (int j = 0; j < i; ++j) {
-                    const cd l = L11[i][j];
-                    acc.re = fma(-l.re, x[j].re, fma(l.im, x[j].im, acc.re));
-                    acc.im = fma(-l.re, x[j].im, fma(-l.im, x[j].re, acc.im));
+    if (v < dcount + ncount) {
+        cd *col = v < dcount ? Dm + (dc0 + v) : Nm + (v - dcount);
+        const size_t ld = v < dcount ? (size_t)n : (size_t)nrhs;
+        if (do_swap) {
+            for (int jj = 0; jj < nb; ++jj) {
+                const int r = k0 + jj, p = piv[jj];
+                if (p != r) {
+                    const cd t = col[(size_t)r * ld];
+                    col[(size_t)r * ld] = col[(size_t)p * ld];
+                    col[(size_t)p * ld] = t;
                 }
-                x[i] = acc;
             }
         }
+        if (do_solve) {
+            cd x[NB];
 #pragma unroll
-        for (int i = 0; i < NB; ++i)
-            if (i < nb) col[(size_t)(k0 + i) * ld] = x[i];
+            for (int i = 0; i < NB; ++i) x[i] = i < nb ? col[(size_t)(k0 + i) * ld] : cd{0.0, 0.0};
+#pragma unroll
+            for (int i = 1; i < NB; ++i) {
+                if (i < nb) {
+                    cd acc = x[i];
+#pragma unroll
+                    for (int j = 0; j < i; ++j) {
+                        const cd l = L11[i][j];
+                        acc.re = fma(-l.re, x[j].re, fma(l.im, x[j].im, acc.re));
+                        acc.im = fma(-l.re, x[j].im, fma(-l.im, x[j].re, acc.im));
+                    }
+                    x[i] = acc;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (i < nb) col[(size_t)(k0 + i) * ld] = x[i];
+        }
     }
 }
 
@@ -248,59 +263,75 @@ __global__ void __launch_bounds__(256) trsm_upper_kernel(const cd *D, cd *N, int
     }
 }
 
+static int swap_trsm(cd *D, cd *N, int n, int nrhs, int batch, int k0, int nb, const int *ipiv, int dc0, int dcount,
+                     int ncount, bool do_swap, bool do_solve, hipStream_t s) {
+    if (dcount + ncount <= 0) return LB_OK;
+    const long long sD = (long long)n * n, sN = (long long)n * nrhs;
+    dim3 grid((dcount + ncount + 255) / 256, batch);
+    swap_trsm_lower_kernel<<<grid, 256, 0, s>>>(D, N, n, nrhs, sD, sN, k0, nb, ipiv, dc0, dcount, ncount,
+                                                do_swap ? 1 : 0, do_solve ? 1 : 0);
+    return check_launch("swap_trsm_lower");
+}
+
+// C[b] -= A[b] B[b] on sub-blocks (row-major, leading dimensions la, lb, lc)
+static int gemm_sub(int M, int N, int K, int batch, const cd *A, long long la, long long sA, const cd *B, long long lb,
+                    long long sB, cd *C, long long lc, long long sC, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return LB_OK;
+    ZgemmBatch g;
+    g.M = M, g.N = N, g.K = K, g.batch = batch;
+    g.A = A, g.lda = la, g.sA = sA;
+    g.B = B, g.ldb = lb, g.sB = sB;
+    g.D = C, g.ldd = lc, g.sD = sC;
+    g.Cin = C, g.ldc = lc, g.sC = sC;
+    g.alpha = -1.0, g.beta = 1.0;
+    return zgemm_batched(g, s);
+}
+
 int lu_solve_batched(int n, int nrhs, int batch, cd *D, cd *N, int *ipiv, int *info, hipStream_t s) {
     const long long sD = (long long)n * n, sN = (long long)n * nrhs;
     if (batch > 65535) return fail(LB_ESHAPE, "lu_solve: batch > 65535");
-    for (int k0 = 0; k0 < n; k0 += NB) {
-        const int nb = n - k0 < NB ? n - k0 : NB;
-        if (n - k0 <= PANEL_THREADS)
-            lu_panel_kernel<1><<<batch, PANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
-        else if (n - k0 <= 2 * PANEL_THREADS)
-            lu_panel_kernel<2><<<batch, PANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
-        else
-            lu_panel_kernel<4><<<batch, PANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
-        LB_TRY(check_launch("lu_panel"));
-        const int ntrail = n - k0 - nb;
-        {
-            dim3 grid((ntrail + nrhs + 255) / 256, batch);
-            swap_trsm_lower_kernel<<<grid, 256, 0, s>>>(D, N, n, nrhs, sD, sN, k0, nb, ipiv);
-            LB_TRY(check_launch("swap_trsm_lower"));
+    // small batches are bound by launch latency: one panel per block there
+    const int nbo = batch >= kOuterMinBatch ? NBO : NB;
+    for (int K0 = 0; K0 < n; K0 += nbo) {
+        const int W = n - K0 < nbo ? n - K0 : nbo, KE = K0 + W;
+        // ---- the outer block J = [K0, KE): 16-column panels, updates kept to J
+        for (int k0 = K0; k0 < KE; k0 += NB) {
+            const int nb = KE - k0 < NB ? KE - k0 : NB;
+            if (n - k0 <= PANEL_THREADS)
+                lu_panel_kernel<1><<<batch, PANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
+            else if (n - k0 <= 2 * PANEL_THREADS)
+                lu_panel_kernel<2><<<batch, PANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
+            else
+                lu_panel_kernel<4><<<batch, PANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
+            LB_TRY(check_launch("lu_panel"));
+            // the panel's exchanges also reach the earlier panels' L columns of J
+            LB_TRY(swap_trsm(D, nullptr, n, nrhs, batch, k0, nb, ipiv, K0, k0 - K0, 0, true, false, s));
+            // and the rest of J: exchanges, U12 = L11^{-1} A12, A22 -= L21 U12
+            LB_TRY(swap_trsm(D, nullptr, n, nrhs, batch, k0, nb, ipiv, k0 + nb, KE - k0 - nb, 0, true, true, s));
+            LB_TRY(gemm_sub(n - k0 - nb, KE - k0 - nb, nb, batch, D + (size_t)(k0 + nb) * n + k0, n, sD,
+                            D + (size_t)k0 * n + k0 + nb, n, sD, D + (size_t)(k0 + nb) * n + k0 + nb, n, sD, s));
         }
-        if (ntrail > 0) {
-            ZgemmBatch g;
-            g.M = ntrail;
-            g.K = nb;
-            g.batch = batch;
-            g.A = D + (size_t)(k0 + nb) * n + k0;  // L21
-            g.lda = n;
-            g.sA = sD;
-            g.alpha = -1.0;
-            g.beta = 1.0;
-            // D22 -= L21 U12
-            g.N = ntrail;
-            g.B = D + (size_t)k0 * n + k0 + nb;  // U12
-            g.ldb = n;
-            g.sB = sD;
-            g.D = D + (size_t)(k0 + nb) * n + k0 + nb;
-            g.ldd = n;
-            g.sD = sD;
-            g.Cin = g.D;
-            g.ldc = n;
-            g.sC = sD;
-            LB_TRY(zgemm_batched(g, s));
-            // N2 -= L21 N1
-            g.N = nrhs;
-            g.B = N + (size_t)k0 * nrhs;
-            g.ldb = nrhs;
-            g.sB = sN;
-            g.D = N + (size_t)(k0 + nb) * nrhs;
-            g.ldd = nrhs;
-            g.sD = sN;
-            g.Cin = g.D;
-            g.ldc = nrhs;
-            g.sC = sN;
-            LB_TRY(zgemm_batched(g, s));
+        // ---- the columns right of J (of D and all of N): all of J's exchanges,
+        // the unit-lower solve of J's rows, then one update of the rows below
+        const int dtr = n - KE;
+        const bool one = W <= NB;  // a single panel: exchanges and solve in one pass
+        for (int k0 = K0; k0 < KE && !one; k0 += NB) {
+            const int nb = KE - k0 < NB ? KE - k0 : NB;
+            LB_TRY(swap_trsm(D, N, n, nrhs, batch, k0, nb, ipiv, KE, dtr, nrhs, true, false, s));
         }
+        for (int k0 = K0; k0 < KE; k0 += NB) {
+            const int nb = KE - k0 < NB ? KE - k0 : NB;
+            LB_TRY(swap_trsm(D, N, n, nrhs, batch, k0, nb, ipiv, KE, dtr, nrhs, one, true, s));
+            const int mrows = KE - k0 - nb;  // rows of J below the panel
+            LB_TRY(gemm_sub(mrows, dtr, nb, batch, D + (size_t)(k0 + nb) * n + k0, n, sD, D + (size_t)k0 * n + KE, n,
+                            sD, D + (size_t)(k0 + nb) * n + KE, n, sD, s));
+            LB_TRY(gemm_sub(mrows, nrhs, nb, batch, D + (size_t)(k0 + nb) * n + k0, n, sD, N + (size_t)k0 * nrhs, nrhs,
+                            sN, N + (size_t)(k0 + nb) * nrhs, nrhs, sN, s));
+        }
+        LB_TRY(gemm_sub(n - KE, dtr, W, batch, D + (size_t)KE * n + K0, n, sD, D + (size_t)K0 * n + KE, n, sD,
+                        D + (size_t)KE * n + KE, n, sD, s));
+        LB_TRY(gemm_sub(n - KE, nrhs, W, batch, D + (size_t)KE * n + K0, n, sD, N + (size_t)K0 * nrhs, nrhs, sN,
+                        N + (size_t)KE * nrhs, nrhs, sN, s));
     }
     // back substitution
     const int nblk = (n + NB - 1) / NB;
