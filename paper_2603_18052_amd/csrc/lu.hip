@@ -22,8 +22,9 @@
 //   update of the rows below J -- a quarter of the trailing-matrix traffic of
 //   one rank-16 update per panel.  Factored columns left of J are not
 //   exchanged (they are not needed again).
-// Then blocked back substitution with U: per block of NB rows from the bottom,
-// trsm_upper on the block rows of N, then N_above -= U_above,block X_block.
+// Then back substitution with U, blocked the same way: per outer block of
+// rows from the bottom, NB-row solves (trsm_upper) with their updates kept to
+// the outer block's rows, then one rank-NBO update N_above -= U_above,J X_J.
 #include <climits>
 
 #include "lb_internal.hpp"
@@ -333,36 +334,25 @@ int lu_solve_batched(int n, int nrhs, int batch, cd *D, cd *N, int *ipiv, int *i
         LB_TRY(gemm_sub(n - KE, nrhs, W, batch, D + (size_t)KE * n + K0, n, sD, N + (size_t)K0 * nrhs, nrhs, sN,
                         N + (size_t)KE * nrhs, nrhs, sN, s));
     }
-    // back substitution
+    // back substitution, blocked the same way: per outer block of rows from
+    // the bottom, NB-row solves with updates kept to the block, then one
+    // update of every row above it
     const int nblk = (n + NB - 1) / NB;
-    for (int blk = nblk - 1; blk >= 0; --blk) {
-        const int b0 = blk * NB;
-        const int nb = n - b0 < NB ? n - b0 : NB;
-        dim3 grid((nrhs + 255) / 256, batch);
-        trsm_upper_kernel<<<grid, 256, 0, s>>>(D, N, n, nrhs, sD, sN, b0, nb);
-        LB_TRY(check_launch("trsm_upper"));
-        if (b0 > 0) {
-            ZgemmBatch g;
-            g.M = b0;
-            g.N = nrhs;
-            g.K = nb;
-            g.batch = batch;
-            g.A = D + b0;  // U[0:b0, b0:b0+nb]
-            g.lda = n;
-            g.sA = sD;
-            g.B = N + (size_t)b0 * nrhs;
-            g.ldb = nrhs;
-            g.sB = sN;
-            g.D = N;
-            g.ldd = nrhs;
-            g.sD = sN;
-            g.alpha = -1.0;
-            g.beta = 1.0;
-            g.Cin = N;
-            g.ldc = nrhs;
-            g.sC = sN;
-            LB_TRY(zgemm_batched(g, s));
+    const int per_outer = nbo / NB;
+    for (int ob = (nblk - 1) / per_outer; ob >= 0; --ob) {
+        const int B0 = ob * nbo, BE = n < B0 + nbo ? n : B0 + nbo;
+        for (int blk = (BE - 1) / NB; blk >= B0 / NB; --blk) {
+            const int b0 = blk * NB;
+            const int nb = n - b0 < NB ? n - b0 : NB;
+            dim3 grid((nrhs + 255) / 256, batch);
+            trsm_upper_kernel<<<grid, 256, 0, s>>>(D, N, n, nrhs, sD, sN, b0, nb);
+            LB_TRY(check_launch("trsm_upper"));
+            // rows [B0, b0) -= U[B0:b0, b0:b0+nb] X[b0:b0+nb]
+            LB_TRY(gemm_sub(b0 - B0, nrhs, nb, batch, D + (size_t)B0 * n + b0, n, sD, N + (size_t)b0 * nrhs, nrhs, sN,
+                            N + (size_t)B0 * nrhs, nrhs, sN, s));
         }
+        // rows [0, B0) -= U[0:B0, B0:BE] X[B0:BE]
+        LB_TRY(gemm_sub(B0, nrhs, BE - B0, batch, D + B0, n, sD, N + (size_t)B0 * nrhs, nrhs, sN, N, nrhs, sN, s));
     }
     return LB_OK;
 }
