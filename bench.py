@@ -137,6 +137,10 @@ def kernel_of(variant, prec):
         return base + ("<double>" if prec == "c128" else "<float>")
     if fam in (4, 7):
         return base + ("<HILO>" if prec == "bf16_hilo" else "<SLICED>")
+    if fam == 11:
+        return f"tgemm_step_kernel<{'double' if prec == 'c128' else 'float'}, {variant % 50}>"
+    if fam == 12:
+        return "tqplane_gemm_kernel" if variant % 50 == 1 else "tplane_gemm_kernel"
     return base
 
 

@@ -22,7 +22,7 @@ enum ChainFamily : int {
     VF_Q15 = 9,         // fixed-point chain (LB_Q15); param 0 one wavefront per state, 1 per-row matvec
     VF_TAIL = 10,       // fused chain, rows 0..79 on MFMA, the rest on the VALU (n = 81); param = layout 0..3
     VF_TGEMM = 11,      // one LDS-tiled MFMA GEMM launch per step (64 states x 48 outputs); param = wavefronts 4 / 8
-    VF_TPLANES = 12,    // one LDS-tiled BF16 plane-GEMM launch per step (64 states x 48 outputs)
+    VF_TPLANES = 12,    // one LDS-tiled BF16 plane-GEMM launch per step (64 states x 48 outputs); param 1: state planes in registers
 };
 inline int variant_family(int v) { return v / 100; }
 inline int variant_param(int v) { return v % 100; }
@@ -57,7 +57,7 @@ int chain_gemm(int n, const cd *P, lb_precision prec, int wn, int B, cd *rho, lo
 int chain_matvec(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
                  hipStream_t s, bool graph = false);
 int chain_planes(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
-                 hipStream_t s, bool graph = false, bool tiled = false);
+                 hipStream_t s, bool graph = false, int tiled = 0);
 int chain_tgemm(int n, const cd *P, lb_precision prec, int waves, int B, cd *rho, long long nsteps, Workspace *ws,
                 hipStream_t s, bool graph = false);
 size_t large_ws_bytes(int family, int n, lb_precision prec, int B);

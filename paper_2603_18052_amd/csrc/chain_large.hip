@@ -108,8 +108,9 @@ __global__ void __launch_bounds__(256) prep_p_kernel(int n, int Kp, const cd *__
 }
 
 // State planes [XD][3][B][Kp] (Re, Im, -Im) and, for the slices, eX.  One
-// workgroup per state.  HILO: the state is FP32 (Y holds FP32 values).
-template <int MODE, int SP, int SX>
+// workgroup per state.  HILO: the state is FP32 (Y holds FP32 values).  NEG:
+// also write the -Im planes (the ring kernel negates in registers instead).
+template <int MODE, int SP, int SX, bool NEG>
 __global__ void __launch_bounds__(256) slice_x_kernel(int n, int Kp, int B, const cd *__restrict__ Y,
                                                       unsigned short *__restrict__ Xp, int *__restrict__ eX) {
     constexpr int XD = Planes<MODE, SP, SX>::XD;
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(256) slice_x_kernel(int n, int Kp, int B, cons
                 vi = vi * 256.0 - di;
                 o[(a * 3 + 0) * plane] = bf16_bits((float)dr);
                 o[(a * 3 + 1) * plane] = bf16_bits((float)di);
-                o[(a * 3 + 2) * plane] = bf16_bits((float)-di);
+                if (NEG) o[(a * 3 + 2) * plane] = bf16_bits((float)-di);
             }
         } else {
             const float fr = (float)v.re, fi = (float)v.im;
@@ -153,10 +154,10 @@ __global__ void __launch_bounds__(256) slice_x_kernel(int n, int Kp, int B, cons
             const unsigned short lr = bf16_bits(fr - bf16_float(hr)), li = bf16_bits(fi - bf16_float(hi));
             o[0 * plane] = hr;
             o[1 * plane] = hi;
-            o[2 * plane] = hi ^ 0x8000u;
+            if (NEG) o[2 * plane] = hi ^ 0x8000u;
             o[3 * plane] = lr;
             o[4 * plane] = li;
-            o[5 * plane] = li ^ 0x8000u;
+            if (NEG) o[5 * plane] = li ^ 0x8000u;
         }
     }
 }
@@ -433,6 +434,238 @@ __global__ void __launch_bounds__(256) tplane_gemm_kernel(int n, int B, int Kp, 
             __syncthreads();
         }
     }
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int b = b0 + 16 * wave + 4 * (lane >> 4) + r, i = i0 + 16 * t + (lane & 15);
+            if (b < B && i < n) {
+                if (MODE == SLICED) {
+                    const int sc = eP[i] + eX[b];
+                    Y[(size_t)b * n + i] = {ldexp(ar[t][r], sc), ldexp(ai[t][r], sc)};
+                } else {
+                    Y[(size_t)b * n + i] = {(double)(float)ar[t][r], (double)(float)ai[t][r]};
+                }
+            }
+        }
+}
+
+// The same tile with a deeper pipeline.  The state digit planes lose the -Im
+// copy (a sign flip in registers instead), and each wavefront stages only its
+// own 16 state rows, two chunks deep in a private LDS area: chunk s's planes
+// are read into registers at its start, then chunk s + 2's are loaded into
+// their place.  The propagator digit planes, shared by all four wavefronts,
+// go through a ring of R chunk slots refilled R - 1 chunks ahead.  Every load
+// is a direct global-to-LDS load, so one in-order counter covers them all: at
+// each chunk's barrier a wavefront waits only for its own loads that the
+// chunk needs and leaves the later ones in flight (__syncthreads() would wait
+// for all of them).  A chunk's loads are spread between its MFMA groups, so
+// that their issue overlaps the matrix work.  Past the last chunk the loads
+// repeat valid addresses into slots no later chunk reads, so every chunk
+// issues the same loads and the wait count is a constant.  k runs in whole
+// 128-deep blocks (Kp a multiple of 128).
+constexpr int TQK = 128;  // k granularity of the ring kernel
+constexpr int kLdsBytes = 160 * 1024;
+
+template <int MODE, int SP, int SX>
+struct TqShape {
+    static constexpr int XD = Planes<MODE, SP, SX>::XD, PD = Planes<MODE, SP, SX>::PD;
+    static constexpr int PPL = 2 * PD;        // propagator planes (Re, Im per digit)
+    static constexpr int ROWB = TPK * 2;      // bytes per plane row of a chunk (64)
+    static constexpr int PPB = TPI * ROWB;    // bytes per plane tile (3 KB)
+    static constexpr int BUF = PPL * PPB;     // bytes per ring slot
+    static constexpr int PI = PPB / 1024;     // 1 KB loads per plane tile (3)
+    static constexpr int NI = PPL * PI;       // 1 KB loads per chunk
+    static constexpr int NJ = (NI + 3) / 4;   // per wavefront (the last few repeat others)
+    static constexpr int XL = 2 * XD;         // state loads per wavefront and chunk: (digit, Re/Im), 1 KB each
+    static constexpr int NDMA = NJ + XL;      // loads per wavefront and chunk
+    static constexpr int XST = 4 * 2 * XL * 1024;  // state staging: four wavefronts, two chunks
+    static constexpr int R = (kLdsBytes - XST) / BUF >= 4 ? 4 : 3;  // ring slots
+    static constexpr int LDS = R * BUF + XST;
+    // Chunk t issues chunk t + R - 1's propagator loads, then chunk t + 2's
+    // state loads.  Chunk s needs its state planes (issued by chunk s - 2)
+    // and its ring slot (issued before them): at its barrier only the NDMA
+    // loads of chunk s - 1 may still be in flight.
+    static constexpr int WAIT = NDMA;
+    static_assert(LDS <= kLdsBytes && WAIT <= 63, "ring kernel shape");
+};
+
+// Workgroup barrier for the ring: wait until at most N of this wavefront's
+// vector loads are outstanding and all its LDS reads are done (s_waitcnt,
+// gfx9 encoding: vmcnt N, expcnt 7 = no wait, lgkmcnt 0), then s_barrier.
+// The empty asm statements keep the compiler from moving memory accesses
+// across it.
+#define TQ_SYNC(N)                                                                  \
+    do {                                                                            \
+        asm volatile("" ::: "memory");                                              \
+        __builtin_amdgcn_s_waitcnt(((N) & 15) | (7 << 4) | (((N) >> 4) << 14));    \
+        __builtin_amdgcn_s_barrier();                                               \
+        asm volatile("" ::: "memory");                                              \
+    } while (0)
+
+__device__ inline bf16x8 bf16_neg(bf16x8 v) {
+    typedef unsigned u4v __attribute__((ext_vector_type(4)));
+    u4v u = __builtin_bit_cast(u4v, v);
+    u ^= 0x80008000u;
+    return __builtin_bit_cast(bf16x8, u);
+}
+
+template <int MODE, int SP, int SX, int LMAX>
+__global__ void __launch_bounds__(256) tqplane_gemm_kernel(int n, int B, int Kp, int nbt, int nit,
+                                                           const unsigned short *__restrict__ Xp,
+                                                           const unsigned short *__restrict__ Pp,
+                                                           const int *__restrict__ eP, const int *__restrict__ eX,
+                                                           cd *__restrict__ Y) {
+    typedef TqShape<MODE, SP, SX> S;
+    constexpr int XD = S::XD, PD = S::PD, R = S::R, NJ = S::NJ;
+    constexpr int NLV = MODE == SLICED ? LMAX + 1 : 1;
+    // MFMA groups (4 MFMAs: one digit pair, one 16-output tile) per chunk
+    constexpr int NPAIR = [] {
+        int c = 0;
+        for (int a = 0; a < PD; ++a)
+            for (int b = 0; b < XD; ++b) c += (MODE == SLICED ? (a + b <= LMAX) : (a + b <= 1));
+        return c;
+    }();
+    constexpr int NG = 3 * NPAIR;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int total = nbt * nit, per = total / 8, rem = total % 8;
+    const int xcd = blockIdx.x % 8, jx = blockIdx.x / 8;
+    const int L0 = xcd * per + (xcd < rem ? xcd : rem) + jx;
+    const int bt = L0 / nit, it = L0 - bt * nit;
+    const int b0 = bt * TPB, i0 = it * TPI;
+    const size_t xplane = (size_t)B * Kp, pplane = (size_t)n * Kp;
+    const int nch = Kp / TPK;  // a multiple of 4
+    unsigned char *xst = smem_raw + R * S::BUF + wave * (2 * S::XL * 1024);  // this wavefront's staging
+
+    // a 1 KB load puts lane l's 16 bytes at row l / 4, chunk position l % 4
+    // of a 16-row plane tile; that position holds the row's 16-byte piece
+    // tp_swz(row, l % 4).  Propagator: load j = wave + 4 q of a chunk (past
+    // NI it repeats load j - (4 NJ - NI): same data to the same place)
+    const int lrow = lane >> 2, lpiece = 8 * tp_swz(lane >> 2, lane & 3);
+    const unsigned short *srcp[NJ];
+    int dsto[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        int j = wave + 4 * q;
+        j = j < S::NI ? j : j - (4 * NJ - S::NI);
+        const int pl = j / S::PI, jj = j - pl * S::PI;
+        int i = i0 + 16 * jj + lrow;
+        i = i < n ? i : n - 1;
+        srcp[q] = Pp + pl * pplane + (size_t)i * Kp + lpiece;
+        dsto[q] = pl * S::PPB + 1024 * jj;
+    }
+    int xr = b0 + 16 * wave + lrow;
+    xr = xr < B ? xr : B - 1;
+    const unsigned short *xsrc = Xp + (size_t)xr * Kp + lpiece;
+    // load k of chunk t's set: propagator load k of chunk t + R - 1 into slot
+    // (t + R - 1) % R, then state tile (digit, Re/Im) k - NJ of chunk t + 2
+    // into staging slot t % 2 (past the last chunk: the last chunk again)
+    auto dma = [&](int t, int k) {
+        if (k < NJ) {
+            const int c = t + R - 1;
+            const int k0 = (c < nch ? c : nch - 1) * TPK;
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(srcp[k] + k0),
+                (__attribute__((address_space(3))) void *)(smem_raw + (c % R) * S::BUF + dsto[k]), 16, 0, 0);
+        } else {
+            const int c = t + 2, tile = k - NJ, a = tile >> 1, q = tile & 1;
+            const int k0 = (c < nch ? c : nch - 1) * TPK;
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(xsrc + (a * 3 + q) * xplane + k0),
+                (__attribute__((address_space(3))) void *)(xst + ((t & 1) * S::XL + tile) * 1024), 16, 0, 0);
+        }
+    };
+    // MFMA operands: row lane % 16 of a 16-row tile, k = 8 (lane / 16) .. + 7
+    const int orow = lane & 15, ooff = orow * S::ROWB + 16 * tp_swz(orow, lane >> 4);
+
+    double ar[3][4], ai[3][4];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ar[t][r] = ai[t][r] = 0.0;
+
+    // chunk s: barrier, its state planes into registers, then the MFMA groups
+    // with chunk s's loads issued between them
+    auto chunk = [&](int s, f4v(&lr)[3][NLV], f4v(&li)[3][NLV]) {
+        TQ_SYNC(S::WAIT);
+        const unsigned char *buf = smem_raw + (s % R) * S::BUF;
+        const unsigned char *xs = xst + (s & 1) * S::XL * 1024 + ooff;
+        bf16x8 x[XD][2], xm[XD];
+#pragma unroll
+        for (int a = 0; a < XD; ++a)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) x[a][q] = *reinterpret_cast<const bf16x8 *>(xs + (a * 2 + q) * 1024);
+#pragma unroll
+        for (int a = 0; a < XD; ++a) xm[a] = bf16_neg(x[a][1]);
+        int g = 0;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            bf16x8 pb[PD][2];
+#pragma unroll
+            for (int a = 0; a < PD; ++a)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    pb[a][q] = *reinterpret_cast<const bf16x8 *>(buf + (a * 2 + q) * S::PPB + 16 * t * S::ROWB + ooff);
+#pragma unroll
+            for (int a = 0; a < PD; ++a)
+#pragma unroll
+                for (int bq = 0; bq < XD; ++bq) {
+                    const int L = a + bq;
+                    if (MODE == SLICED ? (L <= LMAX) : (L <= 1)) {
+                        // this group's share of the chunk's loads; the state
+                        // staging slot is rewritten only after its reads returned
+#pragma unroll
+                        for (int k = 0; k < S::NDMA; ++k)
+                            if (k * NG >= g * S::NDMA && k * NG < (g + 1) * S::NDMA) {
+                                if (k == NJ) {
+                                    asm volatile("" ::: "memory");
+                                    __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (3 << 14));  // lgkmcnt 0 only
+                                    asm volatile("" ::: "memory");
+                                }
+                                dma(s, k);
+                            }
+                        const int Lq = MODE == SLICED ? L : 0;
+                        lr[t][Lq] = mma(x[bq][0], pb[a][0], lr[t][Lq]);
+                        lr[t][Lq] = mma(xm[bq], pb[a][1], lr[t][Lq]);
+                        li[t][Lq] = mma(x[bq][1], pb[a][0], li[t][Lq]);
+                        li[t][Lq] = mma(x[bq][0], pb[a][1], li[t][Lq]);
+                        ++g;
+                    }
+                }
+        }
+    };
+
+    // prologue: the loads of chunks -R + 1 .. -1 in the same order (chunk t's
+    // state loads only where t + 2 >= 0)
+#pragma unroll
+    for (int t = -R + 1; t < 0; ++t) {
+#pragma unroll
+        for (int k = 0; k < S::NDMA; ++k)
+            if (k < NJ || t + 2 >= 0) dma(t, k);
+    }
+    for (int c = 0; c < nch; c += 2) {
+        f4v lr[3][NLV], li[3][NLV];
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int L = 0; L < NLV; ++L) lr[t][L] = li[t][L] = f4v{0, 0, 0, 0};
+        chunk(c, lr, li);
+        chunk(c + 1, lr, li);
+        // KCH = 64 k done: flush the exact level sums into FP64
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int L = NLV - 1; L >= 0; --L) {
+                    const double w = MODE == SLICED ? ldexp(1.0, -8 * (L + 2)) : 1.0;
+                    ar[t][r] = fma((double)lr[t][L][r], w, ar[t][r]);
+                    ai[t][r] = fma((double)li[t][L][r], w, ai[t][r]);
+                }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // the loads past the last chunk land before the workgroup ends
 #pragma unroll
     for (int t = 0; t < 3; ++t)
 #pragma unroll
@@ -915,10 +1148,13 @@ static int tgemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Works
 }
 
 template <int MODE, int SP, int SX, int LMAX>
+// tiled: 0 = untiled plane GEMM, 1 = LDS-tiled (state and propagator planes in
+// LDS), 2 = LDS-tiled with the state planes in registers (propagator ring)
 static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s,
-                      bool graph, bool tiled) {
+                      bool graph, int tiled) {
     constexpr int XD = Planes<MODE, SP, SX>::XD, PD = Planes<MODE, SP, SX>::PD;
-    const int Kp = (n + KCH - 1) / KCH * KCH;
+    const int kq = tiled == 2 ? TQK : KCH;
+    const int Kp = (n + kq - 1) / kq * kq;
     const size_t pbytes = (size_t)PD * 2 * n * Kp * 2, xbytes = (size_t)XD * 3 * B * Kp * 2;
     const size_t ybytes = (size_t)B * n * sizeof(cd);
     LB_TRY(ws_ensure(ws, align256(pbytes) + align256(xbytes) + align256(ybytes) + align256(n * 4) + align256(B * 4)));
@@ -931,11 +1167,18 @@ static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Work
     LB_TRY(check_launch("prep_p"));
     dim3 grid((n + TO - 1) / TO, (B + TS - 1) / TS);
     const int nbt = (B + TPB - 1) / TPB, nit = (n + TPI - 1) / TPI;
-    const size_t lds = 2 * (size_t)TpShape<MODE, SP, SX>::BUF;
-    if (tiled) {
+    const size_t lds = tiled == 2 ? (size_t)TqShape<MODE, SP, SX>::LDS : 2 * (size_t)TpShape<MODE, SP, SX>::BUF;
+    if (tiled == 1) {
         static bool attr_set = false;
         if (!attr_set) {
             LB_HIP(hipFuncSetAttribute((const void *)tplane_gemm_kernel<MODE, SP, SX, LMAX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            attr_set = true;
+        }
+    } else if (tiled == 2) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            LB_HIP(hipFuncSetAttribute((const void *)tqplane_gemm_kernel<MODE, SP, SX, LMAX>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
             attr_set = true;
         }
@@ -943,10 +1186,16 @@ static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Work
     // the state ping-pongs between rho and Yt
     LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
         cd *cur = (t & 1) ? Yt : rho, *nxt = (t & 1) ? rho : Yt;
-        slice_x_kernel<MODE, SP, SX><<<B, 256, 0, st>>>(n, Kp, B, cur, Xp, eX);
-        if (tiled)
+        if (tiled == 2)
+            slice_x_kernel<MODE, SP, SX, false><<<B, 256, 0, st>>>(n, Kp, B, cur, Xp, eX);
+        else
+            slice_x_kernel<MODE, SP, SX, true><<<B, 256, 0, st>>>(n, Kp, B, cur, Xp, eX);
+        if (tiled == 1)
             tplane_gemm_kernel<MODE, SP, SX, LMAX><<<nbt * nit, 256, lds, st>>>(n, B, Kp, nbt, nit, Xp, Pp, eP, eX,
                                                                                 nxt);
+        else if (tiled == 2)
+            tqplane_gemm_kernel<MODE, SP, SX, LMAX><<<nbt * nit, 256, lds, st>>>(n, B, Kp, nbt, nit, Xp, Pp, eP, eX,
+                                                                                 nxt);
         else
             plane_gemm_kernel<MODE, SP, SX, LMAX><<<grid, 256, 0, st>>>(n, B, Kp, Xp, Pp, eP, eX, nxt);
         return LB_OK;
@@ -1166,7 +1415,7 @@ int chain_tgemm(int n, const cd *P, lb_precision prec, int waves, int B, cd *rho
 }
 
 int chain_planes(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, Workspace *ws,
-                 hipStream_t s, bool graph, bool tiled) {
+                 hipStream_t s, bool graph, int tiled) {
     if (nsteps == 0 || B == 0) return LB_OK;
     switch (prec) {
         case LB_BF16_HILO: return planes_run<HILO, 2, 2, 1>(n, P, B, rho, nsteps, ws, s, graph, tiled);
@@ -1186,7 +1435,8 @@ size_t large_ws_bytes(int family, int n, lb_precision prec, int B) {
         return 2 * align256(n * Kp * tsz) + 4 * align256(B * Kp * tsz);
     }
     if (family == VF_PLANES || family == VF_TPLANES) {
-        const size_t Kp = (size_t)(n + KCH - 1) / KCH * KCH;
+        const size_t kq = family == VF_TPLANES ? TQK : KCH;  // the ring kernel's k granularity bounds both
+        const size_t Kp = (size_t)(n + kq - 1) / kq * kq;
         const size_t PD = prec == LB_BF16_HILO ? 2 : 5, XD = prec == LB_BF16_HILO ? 2 : 4;
         return align256(PD * 2 * n * Kp * 2) + align256(XD * 3 * B * Kp * 2) + align256((size_t)B * n * sizeof(cd)) +
                align256((size_t)n * 4) + align256((size_t)B * 4);

@@ -83,7 +83,7 @@ def test_d27_deterministic(lb, P27):
 
 
 @pytest.mark.parametrize("prec,nsteps,tol,variant", [("c128", 200, 1e-12, 1108), ("c64", 200, 5e-5, 1108),
-                                                     ("bf16_sliced", 1000, 1e-6, 1200)])
+                                                     ("bf16_sliced", 1000, 1e-6, 1201)])
 def test_d27_config3_full_batch_sampled(lb, P27, prec, nsteps, tol, variant):
     """Config 3 at its full batch (B = 1024) in the launch configuration the
     bench times (the LDS-tiled step kernels, 256 workgroups); the oracle
@@ -100,3 +100,19 @@ def test_d27_config3_full_batch_sampled(lb, P27, prec, nsteps, tol, variant):
     td = oracle.trace_distance(g.reshape(-1, 27, 27), ref.reshape(-1, 27, 27))
     print(f"{prec} d=27 B=1024 N={nsteps}: trace distance max {td.max():.3e}")
     assert td.max() < (tol if prec != "c128" else 1e-12)
+
+
+@pytest.mark.parametrize("prec,nsteps", [("bf16_sliced", 3), ("bf16_sliced", 601), ("bf16_hilo", 3)])
+@pytest.mark.parametrize("B", [1024, 100])
+def test_ring_plane_kernel_matches_tiled(lb, P27, prec, nsteps, B):
+    """The ring-pipelined plane GEMM (1201) does the tiled kernel's (1200)
+    arithmetic in the same order with other data movement: results are
+    bitwise equal, on the full batch and on a ragged one (B = 100: a partial
+    state tile), for the short (<= 600 steps) and the long digit sets."""
+    X = states(27, B, 11 + B)
+    out = {}
+    for v in (1200, 1201):
+        x = T(X.copy())
+        lb.propagate_variant(T(P27), x, nsteps, v, prec)
+        out[v] = x.cpu().numpy()
+    assert np.array_equal(out[1200], out[1201])
