@@ -14,7 +14,7 @@
 // 2009): with X = A/2^s and F = E/2^s, the products and their directional
 // derivatives
 //   A2 = X X,   M2 = X F + F X;   A4 = A2 A2, M4 = A2 M2 + M2 A2;
-//   A6 = A2 A4, M6 = A4 M2 + M4 A2;
+//   A6 = A4 A2, M6 = A4 M2 + M4 A2;
 //   W1 = b13 A6 + b11 A4 + b9 A2,  W = A6 W1 + b7 A6 + b5 A4 + b3 A2 + b1 I,  U = X W
 //   Z1 = b12 A6 + b10 A4 + b8 A2,  V = A6 Z1 + b6 A6 + b4 A4 + b2 A2 + b0 I
 //   Lw = A6 (b13 M6 + b11 M4 + b9 M2) + M6 W1 + b7 M6 + b5 M4 + b3 M2
@@ -213,6 +213,25 @@ static int grid1(long long work) {
 
 constexpr int FRECHET_MATS = 26;  // n x n temporaries per slice (RHS3 counts 3)
 
+// Products of the forward build kept per slice for the derivative: the
+// E-independent half of the recurrences (A2, A4, A6, W1, Z1, W, U, V) and the
+// first KEEP_SQ squaring levels R_0 = r13(X), R_{k+1} = R_k R_k.  Matrix kind j
+// of slice m sits at cache + (j M + m) n^2, so each kind is one batched operand.
+constexpr int KEEP_SQ = 6;
+constexpr int KEEP_MATS = 8 + KEEP_SQ;
+struct Keep {
+    cd *A2, *A4, *A6, *W1, *Z1, *W, *U, *V;
+    cd *R[KEEP_SQ];
+};
+static Keep keep_view(cd *cache, int M, int m0, size_t nn) {
+    auto kind = [&](int j) { return cache + ((size_t)j * M + m0) * nn; };
+    Keep k;
+    k.A2 = kind(0), k.A4 = kind(1), k.A6 = kind(2), k.W1 = kind(3);
+    k.Z1 = kind(4), k.W = kind(5), k.U = kind(6), k.V = kind(7);
+    for (int l = 0; l < KEEP_SQ; ++l) k.R[l] = kind(8 + l);
+    return k;
+}
+
 static size_t frechet_bytes(int n, int Mc) {
     const size_t mat = align256((size_t)n * n * sizeof(cd) * Mc);
     return FRECHET_MATS * mat + 4 * align256(Mc * sizeof(double)) + align256((size_t)Mc * n * sizeof(int)) +
@@ -220,8 +239,11 @@ static size_t frechet_bytes(int n, int Mc) {
 }
 
 // G[m] = L(A_m, x_m lam_m^dag) for a chunk of Mc slices; A_m = dt Lg[m].
+// With keep, the E-independent products and the kept squaring levels come
+// from the forward build instead of being recomputed (same operations, same
+// operands, so the same values).
 static int frechet_chunk(int n, int Mc, const cd *Lg, const double *dt_host, const cd *x, const cd *lam, double theta,
-                         cd *G, Workspace *ws, hipStream_t s) {
+                         cd *G, Workspace *ws, hipStream_t s, const Keep *keep = nullptr) {
     const size_t nn = (size_t)n * n, mat = nn * sizeof(cd) * Mc;
     LB_TRY(ws_ensure(ws, frechet_bytes(n, Mc)));
     const size_t mark = ws->used;
@@ -288,22 +310,28 @@ static int frechet_chunk(int n, int Mc, const cd *Lg, const double *dt_host, con
         const double c[3] = {c0, c1, c2};
         return zlincomb(n, Mc, 3, X, c, 0.0, D, s);
     };
+    if (keep) {
+        A2 = keep->A2, A4 = keep->A4, A6 = keep->A6, W1 = keep->W1;
+        Z1 = keep->Z1, W = keep->W, U = keep->U, V = keep->V;
+    }
     LB_TRY(zgemm_tile_mask(n, n, Mc, A, n, (long long)nn, mA, s));
-    LB_TRY(mul(A, A, A2, false, mA));
+    if (!keep) LB_TRY(mul(A, A, A2, false, mA));
     LB_TRY(zgemm_tile_mask(n, n, Mc, A2, n, (long long)nn, mA2, s));
     LB_TRY(mul(A, E, M2, false, mA));
     LB_TRY(mul(E, A, M2, true));
-    LB_TRY(mul(A2, A2, A4, false, mA2));
+    if (!keep) LB_TRY(mul(A2, A2, A4, false, mA2));
     LB_TRY(mul(A2, M2, M4, false, mA2));
     LB_TRY(mul(M2, A2, M4, true));
-    LB_TRY(mul(A2, A4, A6, false, mA2));
+    if (!keep) LB_TRY(mul(A4, A2, A6, false));  // the operand order of the propagator build
     LB_TRY(mul(A4, M2, M6, false));
     LB_TRY(mul(M4, A2, M6, true));
-    LB_TRY(lin3(A6, A4, A2, b[13], b[11], b[9], W1));
-    LB_TRY(mul_lc(A6, W1, W, A6, A4, A2, b[7], b[5], b[3], b[1]));
-    LB_TRY(mul(A, W, U, false, mA));
-    LB_TRY(lin3(A6, A4, A2, b[12], b[10], b[8], Z1));
-    LB_TRY(mul_lc(A6, Z1, V, A6, A4, A2, b[6], b[4], b[2], b[0]));
+    if (!keep) {
+        LB_TRY(lin3(A6, A4, A2, b[13], b[11], b[9], W1));
+        LB_TRY(mul_lc(A6, W1, W, A6, A4, A2, b[7], b[5], b[3], b[1]));
+        LB_TRY(mul(A, W, U, false, mA));
+        LB_TRY(lin3(A6, A4, A2, b[12], b[10], b[8], Z1));
+        LB_TRY(mul_lc(A6, Z1, V, A6, A4, A2, b[6], b[4], b[2], b[0]));
+    }
     LB_TRY(lin3(M6, M4, M2, b[13], b[11], b[9], T));
     LB_TRY(mul_lc(A6, T, Lw, M6, M4, M2, b[7], b[5], b[3], 0.0));
     LB_TRY(mul(M6, W1, Lw, true));
@@ -335,10 +363,15 @@ static int frechet_chunk(int n, int Mc, const cd *Lg, const double *dt_host, con
         h.sC = 3 * (long long)nn;
         LB_TRY(zgemm_batched(h, s));
     }
-    // squarings, masked by each slice's s: level k reads (k even ? G, R : Lt, Rt)
+    // squarings, masked by each slice's s: level k reads (k even ? G : Lt) and
+    // R_k, which is kept (k < KEEP_SQ with keep) or else in (k even ? R : Rt)
     for (int k = 0; k < smax; ++k) {
-        const cd *Ls = (k & 1) ? Lt : G, *Rs = (k & 1) ? Rt : R;
-        cd *Ld = (k & 1) ? G : Lt, *Rd = (k & 1) ? R : Rt;
+        const cd *Ls = (k & 1) ? Lt : G;
+        cd *Ld = (k & 1) ? G : Lt;
+        const bool kept = keep && k < KEEP_SQ;
+        const int q = keep ? k - KEEP_SQ : k;  // parity of the ping-pong position
+        const cd *Rs = kept ? keep->R[k] : ((q & 1) ? Rt : R);
+        cd *Rd = ((q + 1) & 1) ? Rt : R;
         ZgemmBatch h = g;
         h.active = d_s;
         h.level = k;
@@ -346,10 +379,116 @@ static int frechet_chunk(int n, int Mc, const cd *Lg, const double *dt_host, con
         LB_TRY(zgemm_batched(h, s));
         h.A = Ls, h.B = Rs, h.beta = 1.0, h.Cin = Ld;
         LB_TRY(zgemm_batched(h, s));
-        h.A = Rs, h.B = Rs, h.D = Rd, h.beta = 0.0, h.Cin = nullptr;
-        LB_TRY(zgemm_batched(h, s));
+        if (k + 1 < smax && !(keep && k + 1 < KEEP_SQ)) {  // R_{k+1}, needed and not kept
+            h.A = Rs, h.B = Rs, h.D = Rd, h.beta = 0.0, h.Cin = nullptr;
+            LB_TRY(zgemm_batched(h, s));
+        }
     }
     if (smax > 0) LB_TRY(odd_copy_launch(n, Mc, d_s, Lt, G, s));
+    std::vector<int> info(Mc);
+    LB_HIP(hipMemcpyAsync(info.data(), d_info, Mc * sizeof(int), hipMemcpyDeviceToHost, s));
+    LB_HIP(hipStreamSynchronize(s));
+    for (int m = 0; m < Mc; ++m)
+        if (info[m]) return fail(LB_ESINGULAR, "grape_gradient: zero pivot in V - U of a slice");
+    return LB_OK;
+}
+
+// Forward build of a chunk for the kept path: the same products as the
+// derivative's E-independent half (written into the cache), one LU solve of
+// (V - U) R_0 = V + U, the squarings R_{k+1} = R_k R_k (kept levels into the
+// cache, later ones ping-ponging in the workspace) and P_m = R_{s_m}.
+static size_t forward_keep_bytes(int n, int Mc) {
+    const size_t mat = align256((size_t)n * n * sizeof(cd) * Mc);
+    return 4 * mat + 4 * align256(Mc * sizeof(double)) + align256((size_t)Mc * n * sizeof(int)) +
+           2 * align256(Mc * sizeof(int)) + 2 * align256((size_t)zgemm_mask_bytes(n, n) * Mc);
+}
+
+static int forward_keep_chunk(int n, int Mc, const cd *Lg, const double *dt_host, double theta, const Keep &k,
+                              cd *P, Workspace *ws, hipStream_t s) {
+    const size_t nn = (size_t)n * n, mat = nn * sizeof(cd) * Mc;
+    LB_TRY(ws_ensure(ws, forward_keep_bytes(n, Mc)));
+    const size_t mark = ws->used;
+    struct Release {
+        Workspace *w;
+        size_t m;
+        ~Release() { w->used = m; }
+    } release{ws, mark};
+    cd *A = (cd *)ws_take(ws, mat), *Q = (cd *)ws_take(ws, mat);
+    cd *Rp[2] = {(cd *)ws_take(ws, mat), (cd *)ws_take(ws, mat)};
+    double *d_dt = (double *)ws_take(ws, Mc * sizeof(double));
+    unsigned long long *d_norm = (unsigned long long *)ws_take(ws, Mc * sizeof(double));
+    int *d_s = (int *)ws_take(ws, Mc * sizeof(int));
+    int *d_info = (int *)ws_take(ws, Mc * sizeof(int));
+    int *d_ipiv = (int *)ws_take(ws, (size_t)Mc * n * sizeof(int));
+    const long long mb = zgemm_mask_bytes(n, n);
+    unsigned char *mA = (unsigned char *)ws_take(ws, (size_t)mb * Mc);
+    unsigned char *mA2 = (unsigned char *)ws_take(ws, (size_t)mb * Mc);
+
+    LB_TRY(fill_i32_launch(d_info, Mc, s));
+    std::vector<int> sv(Mc);
+    LB_TRY(scaling_stage(n, Mc, Lg, dt_host, theta, d_dt, d_norm, d_s, sv.data(), s));
+    int smax = 0;
+    for (int m = 0; m < Mc; ++m) smax = sv[m] > smax ? sv[m] : smax;
+    LB_TRY(scale_launch(n, Mc, Lg, d_dt, d_s, A, s));
+
+    double b[14];
+    pade13_coefficients(b);
+    ZgemmBatch g;
+    g.M = g.N = g.K = n;
+    g.batch = Mc;
+    g.lda = g.ldb = g.ldd = g.ldc = g.ldx = n;
+    g.sA = g.sB = g.sD = g.sC = g.sX = (long long)nn;
+    auto mul = [&](const cd *X, const cd *Y, cd *Z, const unsigned char *mask) {
+        ZgemmBatch h = g;
+        h.A = X, h.B = Y, h.D = Z;
+        h.amask = mask;
+        h.sMask = mb;
+        return zgemm_batched(h, s);
+    };
+    auto mul_lc = [&](const cd *X, const cd *Y, cd *Z, double c0, double c1, double c2, double gamma) {
+        ZgemmBatch h = g;
+        h.A = X, h.B = Y, h.D = Z;
+        h.nx = 3;
+        h.X[0] = k.A6, h.X[1] = k.A4, h.X[2] = k.A2;
+        h.coef[0] = c0, h.coef[1] = c1, h.coef[2] = c2;
+        h.gamma = gamma;
+        return zgemm_batched(h, s);
+    };
+    auto lin3 = [&](double c0, double c1, double c2, cd *D) {
+        const cd *X[3] = {k.A6, k.A4, k.A2};
+        const double c[3] = {c0, c1, c2};
+        return zlincomb(n, Mc, 3, X, c, 0.0, D, s);
+    };
+    // the operations and operand order of frechet_chunk and of the propagator
+    // build, so that P_m and every kept product are those of the other paths
+    LB_TRY(zgemm_tile_mask(n, n, Mc, A, n, (long long)nn, mA, s));
+    LB_TRY(mul(A, A, k.A2, mA));
+    LB_TRY(zgemm_tile_mask(n, n, Mc, k.A2, n, (long long)nn, mA2, s));
+    LB_TRY(mul(k.A2, k.A2, k.A4, mA2));
+    LB_TRY(mul(k.A4, k.A2, k.A6, nullptr));
+    LB_TRY(lin3(b[13], b[11], b[9], k.W1));
+    LB_TRY(mul_lc(k.A6, k.W1, k.W, b[7], b[5], b[3], b[1]));
+    LB_TRY(mul(A, k.W, k.U, mA));
+    LB_TRY(lin3(b[12], b[10], b[8], k.Z1));
+    LB_TRY(mul_lc(k.A6, k.Z1, k.V, b[6], b[4], b[2], b[0]));
+    {
+        const cd *X[2] = {k.V, k.U};
+        const double cm[2] = {1.0, -1.0}, cp[2] = {1.0, 1.0};
+        LB_TRY(zlincomb(n, Mc, 2, X, cm, 0.0, Q, s));
+        LB_TRY(zlincomb(n, Mc, 2, X, cp, 0.0, k.R[0], s));
+    }
+    LB_TRY(lu_solve_batched(n, n, Mc, Q, k.R[0], d_ipiv, d_info, s));
+    auto level = [&](int l) -> cd * { return l < KEEP_SQ ? k.R[l] : Rp[(l - KEEP_SQ) & 1]; };
+    for (int l = 0; l < smax; ++l) {
+        ZgemmBatch h = g;
+        h.active = d_s;
+        h.level = l;
+        h.A = level(l), h.B = level(l), h.D = level(l + 1);
+        LB_TRY(zgemm_batched(h, s));
+    }
+    for (int m = 0; m < Mc; ++m)  // P_m = R_{s_m}
+        LB_HIP(hipMemcpyAsync(P + (size_t)m * nn, level(sv[m]) + (size_t)m * nn, nn * sizeof(cd),
+                              hipMemcpyDeviceToDevice, s));
     std::vector<int> info(Mc);
     LB_HIP(hipMemcpyAsync(info.data(), d_info, Mc * sizeof(int), hipMemcpyDeviceToHost, s));
     LB_HIP(hipStreamSynchronize(s));
@@ -365,6 +504,9 @@ int generators_launch(int n, int M, int C, const cd *L0, const cd *Lc, const dou
 // Default cap of the gradient's workspace reservation (slices are processed
 // in chunks that fit it; the library workspace's own cap applies as well).
 constexpr size_t kGrapeChunkBudget = 24ull << 30;
+// Reservation cap when the forward build's products are kept for the
+// derivative (about 14 n x n matrices per slice on top of the above).
+constexpr size_t kGrapeKeepBudget = 60ull << 30;
 
 static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const double *u, double dt, double theta,
                      const cd *x0, const cd *w, double *F, double *grad, long long checkpoint_bytes, Workspace *ws,
@@ -372,14 +514,25 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
     using namespace grape;
     const size_t nn = (size_t)n * n;
     const size_t matb = nn * sizeof(cd);
-    const bool keepP = checkpoint_bytes <= 0 || (double)M * (double)matb <= (double)checkpoint_bytes;
+    bool keepP = checkpoint_bytes <= 0 || (double)M * (double)matb <= (double)checkpoint_bytes;
     const int nblk = (int)((nn + CHUNK - 1) / CHUNK);
+    // Kept path: the propagators and the build's E-independent products of
+    // every slice stay resident for the derivative, when the checkpoint
+    // budget (if any) and the reservation cap allow it.
+    const size_t cache_bytes = align256((size_t)KEEP_MATS * M * matb);
+    bool keep = checkpoint_bytes <= 0 || (double)(KEEP_MATS + 1) * M * (double)matb <= (double)checkpoint_bytes;
     // ---- reservation: persistent buffers + the larger of the chunk phases
     auto reservation = [&](int mc) {
         const size_t persistent = align256((size_t)(M + 1) * n * sizeof(cd)) * 2 +
                                   align256((size_t)HR * n * sizeof(cd)) + align256((size_t)C * matb) +
                                   align256(sizeof(double)) + align256((size_t)nblk * mc * C * sizeof(double)) +
                                   (keepP ? align256((size_t)M * matb) : 0);
+        if (keep) {  // + the cache, the generators of a chunk and the larger phase
+            size_t phase = forward_keep_bytes(n, mc);
+            const size_t fr = frechet_bytes(n, mc) + align256((size_t)mc * matb);
+            if (fr > phase) phase = fr;
+            return persistent + cache_bytes + align256((size_t)mc * matb) + phase;
+        }
         const size_t chunkp = 2 * align256((size_t)mc * matb);  // generators + propagators of a chunk
         size_t phase = build_workspace_bytes(n, mc);
         const size_t fr = frechet_bytes(n, mc) + align256((size_t)mc * matb);
@@ -387,9 +540,16 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
         return persistent + chunkp + phase;
     };
     // Slices per batched chunk: the most that fit the budget (larger chunks
-    // fill the device better and run fewer sequential LU panel rounds;
-    // results do not depend on the chunking).
-    const size_t budget = std::min(ws->cap, kGrapeChunkBudget);
+    // fill the device better and run fewer sequential LU panel rounds).
+    // Results do not depend on the chunking as long as every chunk holds 8
+    // or more slices, or every one fewer (the batched LU blocks differently
+    // below 8 matrices); chunks are equal in size.
+    if (keep) {
+        keepP = true;
+        if (reservation(1) > std::min(ws->cap, kGrapeKeepBudget)) keep = false;
+        keepP = keep || checkpoint_bytes <= 0 || (double)M * (double)matb <= (double)checkpoint_bytes;
+    }
+    const size_t budget = std::min(ws->cap, keep ? kGrapeKeepBudget : kGrapeChunkBudget);
     int Mc = M < 1024 ? M : 1024;
     while (Mc > 1 && reservation(Mc) > budget) Mc = Mc > 16 ? Mc * 3 / 4 : Mc - 1;
     Mc = (M + (M + Mc - 1) / Mc - 1) / ((M + Mc - 1) / Mc);  // equal chunks, no short tail
@@ -402,8 +562,9 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
     double *d_F = (double *)ws_take(ws, sizeof(double));
     double *partial = (double *)ws_take(ws, (size_t)nblk * Mc * C * sizeof(double));
     cd *Pall = keepP ? (cd *)ws_take(ws, (size_t)M * matb) : nullptr;
+    cd *cache = keep ? (cd *)ws_take(ws, cache_bytes) : nullptr;
     cd *Lg = (cd *)ws_take(ws, (size_t)Mc * matb);
-    cd *Pc = (cd *)ws_take(ws, (size_t)Mc * matb);
+    cd *Pc = keep ? nullptr : (cd *)ws_take(ws, (size_t)Mc * matb);
     std::vector<double> dts(Mc, dt);
 
     if (C > 0) {
@@ -419,7 +580,12 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
     for (int m0 = 0; m0 < M; m0 += Mc) {
         const int mc = M - m0 < Mc ? M - m0 : Mc;
         cd *Pdst = keepP ? Pall + (size_t)m0 * nn : Pc;
-        LB_TRY(chunk_props(m0, mc, Pdst));
+        if (keep) {
+            LB_TRY(generators_launch(n, mc, C, L0, Lc, u + (size_t)m0 * C, Lg, s));
+            LB_TRY(forward_keep_chunk(n, mc, Lg, dts.data(), theta, keep_view(cache, M, m0, nn), Pdst, ws, s));
+        } else {
+            LB_TRY(chunk_props(m0, mc, Pdst));
+        }
         for (int m = 0; m < mc; ++m) {
             matvec_kernel<<<(n * 64 + 255) / 256, 256, 0, s>>>(n, Pdst + (size_t)m * nn, xs + (size_t)(m0 + m) * n,
                                                               xs + (size_t)(m0 + m + 1) * n);
@@ -450,8 +616,9 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
         LB_TRY(generators_launch(n, mc, C, L0, Lc, u + (size_t)m0 * C, Lg, s));
         const size_t mark = ws->used;
         cd *G = (cd *)ws_take(ws, (size_t)mc * matb);
+        const Keep kv = keep ? keep_view(cache, M, m0, nn) : Keep{};
         LB_TRY(frechet_chunk(n, mc, Lg, dts.data(), xs + (size_t)m0 * n, lams + (size_t)(m0 + 1) * n, theta, G, ws,
-                             s));
+                             s, keep ? &kv : nullptr));
         if (C > 0) {
             dim3 cg(nblk, mc);
             contract_kernel<<<cg, 256, 0, s>>>((long long)nn, C, LcT, G, mc, partial);

@@ -136,12 +136,13 @@ def test_grape_chunking_does_not_change_bits(lb):
     forward builds, the backward rebuilds and the batched Frechet derivatives
     then cross chunk boundaries); the fidelity and every gradient entry must
     be bitwise those of the single-chunk run, with and without kept
-    propagators."""
+    propagators, and with the build's products kept for the derivative (the
+    100 MB cap holds them for all 37 slices, in chunks of 13)."""
     p, L0, Lc = setup(2, M=37, seed_u=21)
     F1, g1 = gpu_grad(lb, p, L0, Lc)
-    small = lb.Workspace(48 << 20)  # a few d = 9 slices per chunk
-    for ckpt in (0, 1):
+    for cap, ckpt in ((48 << 20, 0), (48 << 20, 1), (100 << 20, 0)):
+        small = lb.Workspace(cap)
         F2, g2 = gpu_grad(lb, p, L0, Lc, ws=small, checkpoint_bytes=ckpt)
+        small.close()
         assert F1 == F2
         assert np.array_equal(g1, g2)
-    small.close()
