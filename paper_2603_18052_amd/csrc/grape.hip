@@ -393,6 +393,252 @@ static int frechet_chunk(int n, int Mc, const cd *Lg, const double *dt_host, con
     return LB_OK;
 }
 
+// ---- low-rank derivative (kept path, n >= kLowRankMinN)
+// The direction F = u0 v0^H (u0 = x 2^-s, v0 = lambda) has rank one, so every
+// derivative matrix of the Pade half is a short sum of rank-one terms, kept
+// as a factor pair U Vh (U: n x r, Vh: r x n, both row-major):
+//   P0 = [X u0 | u0], P1 = A2 P0, P2 = A4 P0;  Q0 = [v0^H ; v0^H X],
+//   Q1 = Q0 A2, Q2 = Q1 A2;  M2 = P0 Q0, M4 = P0 Q1 + P1 Q0,
+//   M6 = P0 Q2 + P1 Q1 + P2 Q0 = [P0 P1 P2] [Q2; Q1; Q0],
+//   c6 M6 + c4 M4 + c2 M2 = [P0 P1 P2] Vc(c),
+//   Vc(c) = [c6 Q2 + c4 Q1 + c2 Q0 ; c6 Q1 + c4 Q0 ; c6 Q0]
+// so with U6 = [P0 P1 P2], Uw = [A6 U6 | U6]:
+//   Lw = Uw [Vc(b13, b11, b9) ; Vc(b7, b5, b3) + Vh6 W1]
+//   Lv = Uw [Vc(b12, b10, b8) ; Vc(b6, b4, b2) + Vh6 Z1]
+//   Lu = X Lw + F W = [X Uw | u0] [Vh_Lw ; v0^H W]
+//   Lu +- Lv = [X Uw | u0 | +-Uw] Vh_all,  Vh_all = [Vh_Lw ; v0^H W ; Vh_Lv]  (25 rows).
+// One LU solve with 25 right-hand sides gives Y = (V - U)^{-1} [X Uw | u0 | Uw];
+// L = X1 + X2 R_0 = [Y | Ya, -Yc] [Vh_all ; Vh_all R_0] (rank 50), and each
+// squaring level L <- R_k L + L R_k = [U | R_k U] [Vh R_k ; Vh] doubles the
+// rank; while every slice is still active and the rank stays <= n / 2 the
+// levels run on the factors, then L = U Vh is formed and the remaining
+// levels run dense as in frechet_chunk.  Same mathematics as frechet_chunk,
+// other rounding.
+constexpr int kLowRankMinN = 128;
+constexpr int LR_NV = 25;  // columns of the solve
+constexpr int LR_R0 = 50;  // rank of L before the squarings
+
+// dst[m][i][j] = sign * src[m][i][j] for i < rows, j < w (row-major blocks)
+__global__ void copy2d_kernel(int rows, int w, int Mc, const cd *__restrict__ src, long long lds, long long sS,
+                              cd *__restrict__ dst, long long ldd, long long sD, double sign) {
+    const long long per = (long long)rows * w, total = per * Mc;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long m = e / per, r = e - m * per;
+        const long long i = r / w, j = r - i * w;
+        const cd v = src[m * sS + i * lds + j];
+        dst[m * sD + i * ldd + j] = {sign * v.re, sign * v.im};
+    }
+}
+
+// P column 1 = u0 = x 2^-s (P: n x 6 per slice), Qv row 4 = v0^H = conj(lambda)
+__global__ void lr_init_kernel(int n, int Mc, const cd *__restrict__ x, const cd *__restrict__ lam,
+                               const int *__restrict__ sexp, cd *__restrict__ P, cd *__restrict__ Qv) {
+    const long long total = (long long)n * Mc;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long m = e / n, i = e - m * n;
+        const cd a = x[e], b = lam[e];
+        const int s = sexp[m];
+        P[m * 6 * n + i * 6 + 1] = {ldexp(a.re, -s), ldexp(a.im, -s)};
+        Qv[m * 6 * n + 4 * n + i] = {b.re, -b.im};
+    }
+}
+
+// dst (6 x n block, row stride n) = Vc(c6, c4, c2) of Qv = [Q2; Q1; Q0] (2 rows each)
+__global__ void vcomb_kernel(int n, int Mc, const cd *__restrict__ Qv, double c6, double c4, double c2,
+                             cd *__restrict__ dst, long long sD) {
+    const long long per = 6LL * n, total = per * Mc;
+    const double c[3] = {c6, c4, c2};
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long m = e / per, r = e - m * per;
+        const int row = (int)(r / n), blk = row >> 1, k = row & 1;
+        const long long col = r - (long long)row * n;
+        double re = 0.0, im = 0.0;
+        for (int t = 0; blk + t < 3; ++t) {
+            const cd q = Qv[m * per + (long long)(2 * (blk + t) + k) * n + col];
+            re = fma(c[t], q.re, re);
+            im = fma(c[t], q.im, im);
+        }
+        dst[m * sD + (long long)row * n + col] = {re, im};
+    }
+}
+
+// slices whose level count past k0 is odd hold their result in src
+__global__ void parity_copy_kernel(long long nn, int Mc, const int *__restrict__ sexp, int k0,
+                                   const cd *__restrict__ src, cd *__restrict__ dst) {
+    const long long total = nn * Mc;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int m = (int)(e / nn);
+        if ((sexp[m] - k0) & 1) dst[e] = src[e];
+    }
+}
+
+// low-rank levels for a chunk whose smallest s is smin: while the rank r
+// allows 2 r <= n, every slice is active and R_k is kept
+static int lowrank_levels(int n, int smin) {
+    int k = 0, r = LR_R0;
+    while (k < smin && k < KEEP_SQ - 1 && 2 * r <= n) ++k, r *= 2;
+    return k;
+}
+
+static size_t frechet_lowrank_bytes(int n, int Mc, int rmax) {
+    const size_t mat = align256((size_t)n * n * sizeof(cd) * Mc);
+    auto tb = [&](size_t cols) { return align256((size_t)n * cols * sizeof(cd) * Mc); };
+    return 4 * mat + tb(6) + tb(6) + tb(12) + tb(LR_NV) + 2 * tb(rmax) + 4 * align256(Mc * sizeof(double)) +
+           align256((size_t)Mc * n * sizeof(int)) + 2 * align256(Mc * sizeof(int)) +
+           2 * align256((size_t)zgemm_mask_bytes(n, n) * Mc);
+}
+static int lowrank_rmax(int n) {
+    int r = LR_R0;
+    for (int k = 0; k < KEEP_SQ - 1 && 2 * r <= n; ++k) r *= 2;
+    return r;
+}
+
+static int frechet_lowrank_chunk(int n, int Mc, const cd *Lg, const double *dt_host, const cd *x, const cd *lam,
+                                 double theta, cd *G, Workspace *ws, hipStream_t s, const Keep &k) {
+    const size_t nn = (size_t)n * n, mat = nn * sizeof(cd) * Mc;
+    const int rmax = lowrank_rmax(n);
+    LB_TRY(ws_ensure(ws, frechet_lowrank_bytes(n, Mc, rmax)));
+    const size_t mark = ws->used;
+    struct Release {
+        Workspace *w;
+        size_t m;
+        ~Release() { w->used = m; }
+    } release{ws, mark};
+    auto thin = [&](size_t cols) { return (cd *)ws_take(ws, (size_t)n * cols * sizeof(cd) * Mc); };
+    cd *A = (cd *)ws_take(ws, mat), *Q = (cd *)ws_take(ws, mat);
+    cd *Lt = (cd *)ws_take(ws, mat), *Rx[2] = {(cd *)ws_take(ws, mat), nullptr};
+    cd *P = thin(6), *Qv = thin(6), *Uw = thin(12), *Y = thin(LR_NV);
+    cd *Ub = thin(rmax), *Vb = thin(rmax);
+    Rx[1] = Q;  // Q is free once the LU solve has run
+    double *d_dt = (double *)ws_take(ws, Mc * sizeof(double));
+    unsigned long long *d_norm = (unsigned long long *)ws_take(ws, Mc * sizeof(double));
+    int *d_s = (int *)ws_take(ws, Mc * sizeof(int));
+    int *d_info = (int *)ws_take(ws, Mc * sizeof(int));
+    int *d_ipiv = (int *)ws_take(ws, (size_t)Mc * n * sizeof(int));
+    const long long mb = zgemm_mask_bytes(n, n);
+    unsigned char *mA = (unsigned char *)ws_take(ws, (size_t)mb * Mc);
+    unsigned char *mA2 = (unsigned char *)ws_take(ws, (size_t)mb * Mc);
+
+    LB_TRY(fill_i32_launch(d_info, Mc, s));
+    std::vector<int> sv(Mc);
+    LB_TRY(scaling_stage(n, Mc, Lg, dt_host, theta, d_dt, d_norm, d_s, sv.data(), s));
+    int smax = 0, smin = 1 << 30;
+    for (int m = 0; m < Mc; ++m) smax = std::max(smax, sv[m]), smin = std::min(smin, sv[m]);
+    LB_TRY(scale_launch(n, Mc, Lg, d_dt, d_s, A, s));
+    LB_TRY(zgemm_tile_mask(n, n, Mc, A, n, (long long)nn, mA, s));
+    LB_TRY(zgemm_tile_mask(n, n, Mc, k.A2, n, (long long)nn, mA2, s));
+
+    double b[14];
+    pade13_coefficients(b);
+    const long long sT6 = 6LL * n, sT12 = 12LL * n, sTY = (long long)LR_NV * n, sTR = (long long)rmax * n;
+    // D (M x N, ldd, stride sD) = A (M x K) B (K x N) [+ D]
+    auto gemm = [&](int M, int N, int K, const cd *Am, long long lda, long long sA, const unsigned char *mask,
+                    const cd *Bm, long long ldb, long long sB, cd *D, long long ldd, long long sD, bool acc) {
+        ZgemmBatch h;
+        h.M = M, h.N = N, h.K = K, h.batch = Mc;
+        h.A = Am, h.lda = lda, h.sA = sA;
+        h.B = Bm, h.ldb = ldb, h.sB = sB;
+        h.D = D, h.ldd = ldd, h.sD = sD;
+        if (acc) h.beta = 1.0, h.Cin = D, h.ldc = ldd, h.sC = sD;
+        h.amask = mask;
+        h.sMask = mb;
+        return zgemm_batched(h, s);
+    };
+    auto copy2d = [&](int rows, int w, const cd *src, long long lds, long long sS, cd *dst, long long ldd,
+                      long long sD, double sign) {
+        copy2d_kernel<<<grid1((long long)rows * w * Mc), 256, 0, s>>>(rows, w, Mc, src, lds, sS, dst, ldd, sD, sign);
+        return check_launch("copy2d");
+    };
+    const long long NN = (long long)nn;
+    lr_init_kernel<<<grid1((long long)n * Mc), 256, 0, s>>>(n, Mc, x, lam, d_s, P, Qv);
+    LB_TRY(check_launch("lr_init"));
+    // P0 = [X u0 | u0], Q0 = [v0^H ; v0^H X]
+    LB_TRY(gemm(n, 1, n, A, n, NN, mA, P + 1, 6, sT6, P, 6, sT6, false));
+    LB_TRY(gemm(1, n, n, Qv + 4 * n, n, sT6, nullptr, A, n, NN, Qv + 5 * n, n, sT6, false));
+    // P1 = A2 P0, P2 = A4 P0, Q1 = Q0 A2, Q2 = Q1 A2
+    LB_TRY(gemm(n, 2, n, k.A2, n, NN, mA2, P, 6, sT6, P + 2, 6, sT6, false));
+    LB_TRY(gemm(n, 2, n, k.A4, n, NN, nullptr, P, 6, sT6, P + 4, 6, sT6, false));
+    LB_TRY(gemm(2, n, n, Qv + 4 * n, n, sT6, nullptr, k.A2, n, NN, Qv + 2 * n, n, sT6, false));
+    LB_TRY(gemm(2, n, n, Qv + 2 * n, n, sT6, nullptr, k.A2, n, NN, Qv, n, sT6, false));
+    // Uw = [A6 U6 | U6]
+    LB_TRY(gemm(n, 6, n, k.A6, n, NN, nullptr, P, 6, sT6, Uw, 12, sT12, false));
+    LB_TRY(copy2d(n, 6, P, 6, sT6, Uw + 6, 12, sT12, 1.0));
+    // Vh_all, built in rows 0 .. 24 of Vb: [Vc(b13..) ; Vc(b7..) + Vh6 W1 ; v0^H W ; Vc(b12..) ; Vc(b6..) + Vh6 Z1]
+    auto vcomb = [&](double c6, double c4, double c2, cd *dst) {
+        vcomb_kernel<<<grid1(6LL * n * Mc), 256, 0, s>>>(n, Mc, Qv, c6, c4, c2, dst, sTR);
+        return check_launch("vcomb");
+    };
+    LB_TRY(vcomb(b[13], b[11], b[9], Vb));
+    LB_TRY(vcomb(b[7], b[5], b[3], Vb + 6 * n));
+    LB_TRY(gemm(6, n, n, Qv, n, sT6, nullptr, k.W1, n, NN, Vb + 6 * n, n, sTR, true));
+    LB_TRY(gemm(1, n, n, Qv + 4 * n, n, sT6, nullptr, k.W, n, NN, Vb + 12 * n, n, sTR, false));
+    LB_TRY(vcomb(b[12], b[10], b[8], Vb + 13 * n));
+    LB_TRY(vcomb(b[6], b[4], b[2], Vb + 19 * n));
+    LB_TRY(gemm(6, n, n, Qv, n, sT6, nullptr, k.Z1, n, NN, Vb + 19 * n, n, sTR, true));
+    // Y = (V - U)^{-1} [X Uw | u0 | Uw]
+    LB_TRY(gemm(n, 12, n, A, n, NN, mA, Uw, 12, sT12, Y, LR_NV, sTY, false));
+    LB_TRY(copy2d(n, 1, P + 1, 6, sT6, Y + 12, LR_NV, sTY, 1.0));
+    LB_TRY(copy2d(n, 12, Uw, 12, sT12, Y + 13, LR_NV, sTY, 1.0));
+    {
+        const cd *X[2] = {k.V, k.U};
+        const double c[2] = {1.0, -1.0};
+        LB_TRY(zlincomb(n, Mc, 2, X, c, 0.0, Q, s));
+    }
+    LB_TRY(lu_solve_batched(n, LR_NV, Mc, Q, Y, d_ipiv, d_info, s));
+    // L = [Y | Ya, -Yc] [Vh_all ; Vh_all R_0]
+    LB_TRY(copy2d(n, LR_NV, Y, LR_NV, sTY, Ub, rmax, sTR, 1.0));
+    LB_TRY(copy2d(n, 13, Y, LR_NV, sTY, Ub + LR_NV, rmax, sTR, 1.0));
+    LB_TRY(copy2d(n, 12, Y + 13, LR_NV, sTY, Ub + LR_NV + 13, rmax, sTR, -1.0));
+    LB_TRY(gemm(LR_NV, n, n, Vb, n, sTR, nullptr, k.R[0], n, NN, Vb + (long long)LR_NV * n, n, sTR, false));
+    // low-rank squaring levels: L <- [U | R_k U] [Vh R_k ; Vh]
+    const int klr = lowrank_levels(n, smin);
+    int r = LR_R0;
+    for (int l = 0; l < klr; ++l, r *= 2) {
+        LB_TRY(copy2d(r, n, Vb, n, sTR, Vb + (long long)r * n, n, sTR, 1.0));
+        LB_TRY(gemm(r, n, n, Vb + (long long)r * n, n, sTR, nullptr, k.R[l], n, NN, Vb, n, sTR, false));
+        LB_TRY(gemm(n, r, n, k.R[l], n, NN, nullptr, Ub, rmax, sTR, Ub + r, rmax, sTR, false));
+    }
+    // L = U Vh, then the remaining levels dense (level l reads ((l - klr) even ? G : Lt))
+    LB_TRY(gemm(n, n, r, Ub, rmax, sTR, nullptr, Vb, n, sTR, G, n, NN, false));
+    ZgemmBatch g;
+    g.M = g.N = g.K = n;
+    g.batch = Mc;
+    g.lda = g.ldb = g.ldd = g.ldc = n;
+    g.sA = g.sB = g.sD = g.sC = NN;
+    for (int l = klr; l < smax; ++l) {
+        const int q = l - klr;
+        const cd *Ls = (q & 1) ? Lt : G;
+        cd *Ld = (q & 1) ? G : Lt;
+        const int qr = l - KEEP_SQ;  // R_l past the kept levels ping-pongs in Rx
+        const cd *Rs = l < KEEP_SQ ? k.R[l] : Rx[qr & 1];
+        ZgemmBatch h = g;
+        h.active = d_s;
+        h.level = l;
+        h.A = Rs, h.B = Ls, h.D = Ld;
+        LB_TRY(zgemm_batched(h, s));
+        h.A = Ls, h.B = Rs, h.beta = 1.0, h.Cin = Ld;
+        LB_TRY(zgemm_batched(h, s));
+        if (l + 1 < smax && l + 1 >= KEEP_SQ) {  // R_{l+1}
+            h.A = Rs, h.B = Rs, h.D = Rx[(qr + 1) & 1], h.beta = 0.0, h.Cin = nullptr;
+            LB_TRY(zgemm_batched(h, s));
+        }
+    }
+    if (smax > klr) {
+        parity_copy_kernel<<<grid1((long long)nn * Mc), 256, 0, s>>>((long long)nn, Mc, d_s, klr, Lt, G);
+        LB_TRY(check_launch("parity_copy"));
+    }
+    std::vector<int> info(Mc);
+    LB_HIP(hipMemcpyAsync(info.data(), d_info, Mc * sizeof(int), hipMemcpyDeviceToHost, s));
+    LB_HIP(hipStreamSynchronize(s));
+    for (int m = 0; m < Mc; ++m)
+        if (info[m]) return fail(LB_ESINGULAR, "grape_gradient: zero pivot in V - U of a slice");
+    return LB_OK;
+}
+
 // Forward build of a chunk for the kept path: the same products as the
 // derivative's E-independent half (written into the cache), one LU solve of
 // (V - U) R_0 = V + U, the squarings R_{k+1} = R_k R_k (kept levels into the
@@ -529,7 +775,8 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
                                   (keepP ? align256((size_t)M * matb) : 0);
         if (keep) {  // + the cache, the generators of a chunk and the larger phase
             size_t phase = forward_keep_bytes(n, mc);
-            const size_t fr = frechet_bytes(n, mc) + align256((size_t)mc * matb);
+            const size_t fr = (n >= kLowRankMinN ? frechet_lowrank_bytes(n, mc, lowrank_rmax(n)) : frechet_bytes(n, mc)) +
+                              align256((size_t)mc * matb);
             if (fr > phase) phase = fr;
             return persistent + cache_bytes + align256((size_t)mc * matb) + phase;
         }
@@ -617,8 +864,12 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
         const size_t mark = ws->used;
         cd *G = (cd *)ws_take(ws, (size_t)mc * matb);
         const Keep kv = keep ? keep_view(cache, M, m0, nn) : Keep{};
-        LB_TRY(frechet_chunk(n, mc, Lg, dts.data(), xs + (size_t)m0 * n, lams + (size_t)(m0 + 1) * n, theta, G, ws,
-                             s, keep ? &kv : nullptr));
+        if (keep && n >= kLowRankMinN)
+            LB_TRY(frechet_lowrank_chunk(n, mc, Lg, dts.data(), xs + (size_t)m0 * n, lams + (size_t)(m0 + 1) * n,
+                                         theta, G, ws, s, kv));
+        else
+            LB_TRY(frechet_chunk(n, mc, Lg, dts.data(), xs + (size_t)m0 * n, lams + (size_t)(m0 + 1) * n, theta, G,
+                                 ws, s, keep ? &kv : nullptr));
         if (C > 0) {
             dim3 cg(nblk, mc);
             contract_kernel<<<cg, 256, 0, s>>>((long long)nn, C, LcT, G, mc, partial);

@@ -131,6 +131,19 @@ def test_grape_d27_directional_fd_and_forward(lb):
     assert abs(dd - fd) <= 1e-8 + 1e-7 * abs(dd)
 
 
+def test_grape_d27_lowrank_derivative_matches_dense(lb):
+    """d = 27 with the build's products kept runs the Frechet derivative on
+    low-rank factors (the direction x lambda^dag has rank one); with nothing
+    kept (checkpoint budget 1 byte) it runs the dense recurrences.  The
+    forward pass is the same build, so F is bitwise equal; the gradients
+    differ only by rounding."""
+    p, L0, Lc = setup(3, M=6, seed_u=5)
+    F1, g1 = gpu_grad(lb, p, L0, Lc)
+    F2, g2 = gpu_grad(lb, p, L0, Lc, checkpoint_bytes=1)
+    assert F1 == F2
+    assert np.abs(g1 - g2).max() <= 1e-11 * np.abs(g2).max()
+
+
 def test_grape_chunking_does_not_change_bits(lb):
     """A workspace with a small cap forces the slices into several chunks (the
     forward builds, the backward rebuilds and the batched Frechet derivatives
