@@ -393,7 +393,7 @@ static int frechet_chunk(int n, int Mc, const cd *Lg, const double *dt_host, con
     return LB_OK;
 }
 
-// ---- low-rank derivative (kept path, n >= kLowRankMinN)
+// ---- low-rank derivative (kept path, n >= kLowRankMinN = 64)
 // The direction F = u0 v0^H (u0 = x 2^-s, v0 = lambda) has rank one, so every
 // derivative matrix of the Pade half is a short sum of rank-one terms, kept
 // as a factor pair U Vh (U: n x r, Vh: r x n, both row-major):
@@ -414,7 +414,7 @@ static int frechet_chunk(int n, int Mc, const cd *Lg, const double *dt_host, con
 // levels run on the factors, then L = U Vh is formed and the remaining
 // levels run dense as in frechet_chunk.  Same mathematics as frechet_chunk,
 // other rounding.
-constexpr int kLowRankMinN = 128;
+constexpr int kLowRankMinN = 64;
 constexpr int LR_NV = 25;  // columns of the solve
 constexpr int LR_R0 = 50;  // rank of L before the squarings
 
