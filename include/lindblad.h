@@ -200,11 +200,13 @@ int lindblad_expmv_params(double a, int *s, int *m);
  *             step by the last wavefront to finish them
  *   1100 + w  one LDS-tiled MFMA GEMM launch per step, 64 states x 48 outputs
  *             per workgroup, w = 4 or 8 wavefronts (LB_C128 / LB_C64)
+ *   1101      the same tile with k chunks loaded straight into an LDS ring a few
+ *             chunks ahead (four wavefronts)
  *   1200      one LDS-tiled BF16 plane-GEMM launch per step, 64 states x 48
  *             outputs per workgroup, direct global-to-LDS loads (BF16 precisions)
  *   1201      the same tile with each wavefront's state planes staged per 64-k
  *             pair and a ring of propagator chunks loaded 2-3 chunks ahead
- * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901, 1100 + w, 1200, 1201) replays its steps
+ * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901, 1100 + w, 1101, 1200, 1201) replays its steps
  * from a HIP graph captured once per call (32 steps, replayed over all but
  * the last step).  Variants of one shape differ only in summation order. */
 

@@ -1114,6 +1114,190 @@ static int gemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Worksp
     return check_launch("gemm_step");
 }
 
+// Ring-pipelined FP32 / FP64 GEMM step: the tile of tgemm_step_kernel (64
+// states x 48 outputs; wavefront w owns states 16 w .. + 15 against all 48
+// outputs over every k) with k in 16-deep chunks that reach LDS by direct
+// global-to-LDS loads into a ring of R slots, R - 1 chunks ahead, instead of
+// through registers: no staging registers, no store phase, and at each
+// chunk's barrier a wavefront waits only for its own loads of that chunk
+// (the count of later loads is a constant: every chunk issues the same loads,
+// past the last one repeating valid addresses into slots no later chunk
+// reads).  Plane rows (16 k = 64 or 128 bytes) keep their 16-byte pieces at
+// XOR-swizzled positions so that the 16 rows of an MFMA operand fetch fall
+// in distinct banks without padding.  -Im X Im P uses the FP64 negate-A
+// modifier, a sign flip in registers for FP32.
+constexpr int TRK = 16;  // k per ring chunk
+
+template <typename T>
+struct TrShape {
+    static constexpr int RB = TRK * (int)sizeof(T);  // bytes per plane row of a chunk
+    static constexpr int NPC = RB / 16;              // 16-byte pieces per row
+    static constexpr int RPL = 1024 / RB;            // rows per 1 KB load
+    static constexpr int XPB = TGB * RB, PPB = TGI * RB;
+    static constexpr int BUF = 2 * XPB + 2 * PPB;    // slot: Re X, Im X, Re P, Im P
+    static constexpr int XI = XPB / 1024, PI = PPB / 1024;
+    static constexpr int NI = BUF / 1024;            // 1 KB loads per chunk
+    static constexpr int NJ = (NI + 3) / 4;          // per wavefront (the last few repeat others)
+    static constexpr int R = kLdsBytes / BUF > 6 ? 6 : kLdsBytes / BUF;
+    static constexpr int LDS = R * BUF;
+    static constexpr int WAIT = (R - 2) * NJ;        // loads of chunks c + 1 .. c + R - 2 stay in flight
+    static_assert(BUF % 1024 == 0 && R >= 3 && WAIT <= 63, "ring GEMM shape");
+};
+// position of a row's 16-byte piece: piece ^ f(row), f spreading 16 rows over all banks
+template <typename T>
+__device__ inline int tr_swz(int row, int piece) {
+    return sizeof(T) == 8 ? piece ^ ((row >> 1) & 7) : piece ^ ((row >> 2) & 3);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) trgemm_step_kernel(int n, int B, int Kp, int nbt, int nit,
+                                                          const T *__restrict__ Xr, const T *__restrict__ Xi,
+                                                          const T *__restrict__ Pr, const T *__restrict__ Pi,
+                                                          T *__restrict__ Yr, T *__restrict__ Yi,
+                                                          cd *__restrict__ Yout) {
+    typedef TrShape<T> S;
+    typedef typename TgMma<T>::acc acc_t;
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    typedef T vh __attribute__((ext_vector_type(16 / sizeof(T))));  // one 16-byte piece
+    constexpr int R = S::R, NJ = S::NJ, VP = 16 / (int)sizeof(T);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int total = nbt * nit, per = total / 8, rem = total % 8;
+    const int xcd = blockIdx.x % 8, jx = blockIdx.x / 8;
+    const int L0 = xcd * per + (xcd < rem ? xcd : rem) + jx;
+    const int bt = L0 / nit, it = L0 - bt * nit;
+    const int b0 = bt * TGB, i0 = it * TGI;
+    const int nch = Kp / TRK;
+
+    // load j = wave + 4 q of a chunk: plane tile (Re X, Im X, Re P, Im P),
+    // its 1 KB part jj; lane l fills row RPL jj + l / NPC, position l % NPC,
+    // which holds the row's piece tr_swz(row, position)
+    const T *srcp[NJ];
+    int dsto[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        int j = wave + 4 * q;
+        j = j < S::NI ? j : j - (4 * NJ - S::NI);
+        int pl, jj;
+        if (j < 2 * S::XI) pl = j / S::XI, jj = j - pl * S::XI;
+        else pl = 2 + (j - 2 * S::XI) / S::PI, jj = (j - 2 * S::XI) - (pl - 2) * S::PI;
+        const int row = S::RPL * jj + lane / S::NPC, pos = lane % S::NPC;
+        const int piece = tr_swz<T>(row, pos);
+        if (pl < 2) {
+            int b = b0 + row;
+            b = b < B ? b : B - 1;
+            srcp[q] = (pl == 0 ? Xr : Xi) + (size_t)b * Kp + piece * VP;
+            dsto[q] = pl * S::XPB + 1024 * jj;
+        } else {
+            int i = i0 + row;
+            i = i < n ? i : n - 1;
+            srcp[q] = (pl == 2 ? Pr : Pi) + (size_t)i * Kp + piece * VP;
+            dsto[q] = 2 * S::XPB + (pl - 2) * S::PPB + 1024 * jj;
+        }
+    }
+    auto dma = [&](int c, int q) {  // load q of chunk c into slot c % R (past the end: the last chunk)
+        const int k0 = (c < nch ? c : nch - 1) * TRK;
+        __builtin_amdgcn_global_load_lds((const void *)(srcp[q] + k0),
+                                         (__attribute__((address_space(3))) void *)(smem_raw + (c % R) * S::BUF +
+                                                                                    dsto[q]),
+                                         16, 0, 0);
+    };
+    // MFMA operands: row lane % 16 of a 16-row block, k = 4 (lane / 16) .. + 3
+    const int orow = lane & 15, g = lane >> 4;
+    auto opnd = [&](const unsigned char *plane, int row) -> v4 {
+        const unsigned char *rp = plane + row * S::RB;
+        if constexpr (sizeof(T) == 8) {
+            const vh lo = *reinterpret_cast<const vh *>(rp + 16 * tr_swz<T>(row, 2 * g));
+            const vh hi = *reinterpret_cast<const vh *>(rp + 16 * tr_swz<T>(row, 2 * g + 1));
+            return v4{lo[0], lo[1], hi[0], hi[1]};
+        } else {
+            return *reinterpret_cast<const v4 *>(rp + 16 * tr_swz<T>(row, g));
+        }
+    };
+
+    acc_t re[3], im[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) re[t] = im[t] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < R - 1; ++c)
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) dma(c, q);
+    for (int c = 0; c < nch; ++c) {
+        TQ_SYNC(S::WAIT);
+        const unsigned char *buf = smem_raw + (c % R) * S::BUF;
+        const v4 ar = opnd(buf, 16 * wave + orow), ai = opnd(buf + S::XPB, 16 * wave + orow);
+        v4 br[3], bi[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            br[t] = opnd(buf + 2 * S::XPB, 16 * t + orow);
+            bi[t] = opnd(buf + 2 * S::XPB + S::PPB, 16 * t + orow);
+        }
+        v4 an;
+        if constexpr (sizeof(T) == 4) an = -ai;
+        int grp = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int t = 0; t < 3; ++t, ++grp) {
+                // this group's share of chunk c + R - 1's loads (into the slot chunk c - 1 used)
+#pragma unroll
+                for (int k = 0; k < NJ; ++k)
+                    if (k * 12 >= grp * NJ && k * 12 < (grp + 1) * NJ) dma(c + R - 1, k);
+                re[t] = TgMma<T>::mma(ar[q], br[t][q], re[t]);
+                im[t] = TgMma<T>::mma(ar[q], bi[t][q], im[t]);
+                if constexpr (sizeof(T) == 8)
+                    re[t] = TgMma<T>::mma_na(ai[q], bi[t][q], re[t]);
+                else
+                    re[t] = TgMma<T>::mma(an[q], bi[t][q], re[t]);
+                im[t] = TgMma<T>::mma(ai[q], br[t][q], im[t]);
+            }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // the loads past the last chunk land before the workgroup ends
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int b = b0 + 16 * wave + TgMma<T>::row(lane, r), i = i0 + 16 * t + (lane & 15);
+            if (b < B && i < n) {
+                Yr[(size_t)b * Kp + i] = re[t][r];
+                Yi[(size_t)b * Kp + i] = im[t][r];
+                if (Yout) Yout[(size_t)b * n + i] = {(double)re[t][r], (double)im[t][r]};
+            }
+        }
+}
+
+template <typename T>
+static int trgemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s,
+                      bool graph) {
+    typedef TrShape<T> S;
+    const int Kp = (n + 63) / 64 * 64;
+    const size_t pp = (size_t)n * Kp * sizeof(T), xp = (size_t)B * Kp * sizeof(T);
+    LB_TRY(ws_ensure(ws, 2 * align256(pp) + 4 * align256(xp)));
+    T *Pr = (T *)ws_take(ws, pp), *Pi = (T *)ws_take(ws, pp);
+    T *X[2][2];
+    for (int q = 0; q < 2; ++q)
+        for (int c = 0; c < 2; ++c) X[q][c] = (T *)ws_take(ws, xp);
+    to_planes_kernel<T><<<grid1((long long)n * Kp), 256, 0, s>>>(n, n, Kp, P, Pr, Pi);
+    for (int q = 0; q < 2; ++q)  // zero k padding of both buffers
+        to_planes_kernel<T><<<grid1((long long)B * Kp), 256, 0, s>>>(B, n, Kp, rho, X[q][0], X[q][1]);
+    LB_TRY(check_launch("to_planes"));
+    static bool attr_set = false;
+    if (!attr_set) {
+        LB_HIP(hipFuncSetAttribute((const void *)trgemm_step_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   S::LDS));
+        attr_set = true;
+    }
+    const int nbt = (B + TGB - 1) / TGB, nit = (n + TGI - 1) / TGI;
+    LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
+        const int c = (int)(t & 1);
+        trgemm_step_kernel<T><<<nbt * nit, 256, S::LDS, st>>>(n, B, Kp, nbt, nit, X[c][0], X[c][1], Pr, Pi,
+                                                              X[c ^ 1][0], X[c ^ 1][1], t + 1 == nsteps ? rho : nullptr);
+        return LB_OK;
+    }, s));
+    return check_launch("trgemm_step");
+}
+
 template <typename T, int WPB>
 static int tgemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s,
                      bool graph) {
@@ -1402,12 +1586,14 @@ int chain_gemm(int n, const cd *P, lb_precision prec, int wn, int B, cd *rho, lo
 int chain_tgemm(int n, const cd *P, lb_precision prec, int waves, int B, cd *rho, long long nsteps, Workspace *ws,
                 hipStream_t s, bool graph) {
     if (nsteps == 0 || B == 0) return LB_OK;
-    if (waves != 4 && waves != 8) return fail(LB_ESHAPE, "tiled gemm chain: 4 or 8 wavefronts");
+    if (waves != 1 && waves != 4 && waves != 8) return fail(LB_ESHAPE, "tiled gemm chain: 4 or 8 wavefronts, or 1 (ring)");
     switch (prec) {
         case LB_C128:
+            if (waves == 1) return trgemm_run<double>(n, P, B, rho, nsteps, ws, s, graph);
             return waves == 4 ? tgemm_run<double, 4>(n, P, B, rho, nsteps, ws, s, graph)
                               : tgemm_run<double, 8>(n, P, B, rho, nsteps, ws, s, graph);
         case LB_C64:
+            if (waves == 1) return trgemm_run<float>(n, P, B, rho, nsteps, ws, s, graph);
             return waves == 4 ? tgemm_run<float, 4>(n, P, B, rho, nsteps, ws, s, graph)
                               : tgemm_run<float, 8>(n, P, B, rho, nsteps, ws, s, graph);
         default: return fail(LB_ENOTSUP, "tiled gemm chain: complex128 / complex64 only");
