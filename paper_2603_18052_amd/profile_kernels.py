@@ -1,7 +1,8 @@
 """Workload for rocprofv3 counter runs: one plain device copy of a known
 size (calibrates FETCH_SIZE / WRITE_SIZE against bytes actually moved), then
 one chain on the d = 9 workload (B = 4096 Wishart states, 1e4 steps) or the
-d = 27 workload (--d 27: B = 1024, a few steps) in the requested precision.
+d = 27 workload (--d 27: B = 1024, a few steps) in the requested precision,
+or (--grape) one GRAPE gradient of the M = 200 slice workload at that d.
 
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR -o run -- \\
         python -m paper_2603_18052_amd.profile_kernels --precision c128
@@ -23,6 +24,7 @@ def main():
     ap.add_argument("--d", type=int, default=9, choices=(9, 27))
     ap.add_argument("--nsteps", type=int, default=None, help="default 10^4 (d = 9), 40 (d = 27)")
     ap.add_argument("--batch", type=int, default=None, help="default 4096 (d = 9), 1024 (d = 27)")
+    ap.add_argument("--grape", action="store_true", help="one GRAPE gradient (M = 200) instead of a chain")
     a = ap.parse_args()
     if a.nsteps is None:
         a.nsteps = 10_000 if a.d == 9 else 40
@@ -37,6 +39,17 @@ def main():
     dst = torch.empty_like(src)
     dst.copy_(src)  # the calibration copy: COPY_BYTES read, COPY_BYTES written
     torch.cuda.synchronize()
+    if a.grape:
+        p = W.grape_problem(2 if a.d == 9 else 3, M=200)
+        Hc = torch.from_numpy(p["Hc"]).to(dev)
+        L0 = lb.liouvillian(torch.from_numpy(p["H0"]).to(dev), torch.from_numpy(p["Lk"]).to(dev))
+        Lc = torch.stack([lb.liouvillian(Hc[c], None) for c in range(Hc.shape[0])])
+        x0 = torch.from_numpy(p["rho0"].reshape(-1)).to(dev)
+        w = torch.from_numpy(p["target"].reshape(-1)).to(dev)
+        F, g = lb.grape_gradient(L0, Lc, torch.from_numpy(p["u"]).to(dev), p["dt"], x0, w)
+        torch.cuda.synchronize()
+        print("profile_kernels: done grape", a.d, F, flush=True)
+        return
     cfg = (W.config2 if a.d == 9 else W.config3)(B=a.batch, nsteps=a.nsteps)
     H, Lk = torch.from_numpy(cfg["H"]).to(dev), torch.from_numpy(cfg["Lk"]).to(dev)
     P = lb.propagator(lb.liouvillian(H, Lk), cfg["dt"])
