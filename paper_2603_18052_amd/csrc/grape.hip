@@ -497,8 +497,9 @@ static int lowrank_rmax(int n) {
     return r;
 }
 
+// k.U holds the kept factorization of V - U (exchanges in ipiv).
 static int frechet_lowrank_chunk(int n, int Mc, const cd *Lg, const double *dt_host, const cd *x, const cd *lam,
-                                 double theta, cd *G, Workspace *ws, hipStream_t s, const Keep &k) {
+                                 double theta, cd *G, Workspace *ws, hipStream_t s, const Keep &k, const int *ipiv) {
     const size_t nn = (size_t)n * n, mat = nn * sizeof(cd) * Mc;
     const int rmax = lowrank_rmax(n);
     LB_TRY(ws_ensure(ws, frechet_lowrank_bytes(n, Mc, rmax)));
@@ -513,7 +514,7 @@ static int frechet_lowrank_chunk(int n, int Mc, const cd *Lg, const double *dt_h
     cd *Lt = (cd *)ws_take(ws, mat), *Rx[2] = {(cd *)ws_take(ws, mat), nullptr};
     cd *P = thin(6), *Qv = thin(6), *Uw = thin(12), *Y = thin(LR_NV);
     cd *Ub = thin(rmax), *Vb = thin(rmax);
-    Rx[1] = Q;  // Q is free once the LU solve has run
+    Rx[1] = Q;  // spare n x n per slice for the squaring levels past the kept ones
     double *d_dt = (double *)ws_take(ws, Mc * sizeof(double));
     unsigned long long *d_norm = (unsigned long long *)ws_take(ws, Mc * sizeof(double));
     int *d_s = (int *)ws_take(ws, Mc * sizeof(int));
@@ -583,12 +584,7 @@ static int frechet_lowrank_chunk(int n, int Mc, const cd *Lg, const double *dt_h
     LB_TRY(gemm(n, 12, n, A, n, NN, mA, Uw, 12, sT12, Y, LR_NV, sTY, false));
     LB_TRY(copy2d(n, 1, P + 1, 6, sT6, Y + 12, LR_NV, sTY, 1.0));
     LB_TRY(copy2d(n, 12, Uw, 12, sT12, Y + 13, LR_NV, sTY, 1.0));
-    {
-        const cd *X[2] = {k.V, k.U};
-        const double c[2] = {1.0, -1.0};
-        LB_TRY(zlincomb(n, Mc, 2, X, c, 0.0, Q, s));
-    }
-    LB_TRY(lu_solve_batched(n, LR_NV, Mc, Q, Y, d_ipiv, d_info, s));
+    LB_TRY(lu_resolve_batched(n, LR_NV, Mc, k.U, Y, ipiv, s));  // the forward build's factorization
     // L = [Y | Ya, -Yc] [Vh_all ; Vh_all R_0]
     LB_TRY(copy2d(n, LR_NV, Y, LR_NV, sTY, Ub, rmax, sTR, 1.0));
     LB_TRY(copy2d(n, 13, Y, LR_NV, sTY, Ub + LR_NV, rmax, sTR, 1.0));
@@ -649,8 +645,10 @@ static size_t forward_keep_bytes(int n, int Mc) {
            2 * align256(Mc * sizeof(int)) + 2 * align256((size_t)zgemm_mask_bytes(n, n) * Mc);
 }
 
+// With ipiv_keep (the low-rank derivative's path) V - U is factored in the
+// slot of U and the factorization kept, with its exchanges in ipiv_keep.
 static int forward_keep_chunk(int n, int Mc, const cd *Lg, const double *dt_host, double theta, const Keep &k,
-                              cd *P, Workspace *ws, hipStream_t s) {
+                              cd *P, Workspace *ws, hipStream_t s, int *ipiv_keep = nullptr) {
     const size_t nn = (size_t)n * n, mat = nn * sizeof(cd) * Mc;
     LB_TRY(ws_ensure(ws, forward_keep_bytes(n, Mc)));
     const size_t mark = ws->used;
@@ -720,10 +718,11 @@ static int forward_keep_chunk(int n, int Mc, const cd *Lg, const double *dt_host
     {
         const cd *X[2] = {k.V, k.U};
         const double cm[2] = {1.0, -1.0}, cp[2] = {1.0, 1.0};
-        LB_TRY(zlincomb(n, Mc, 2, X, cm, 0.0, Q, s));
         LB_TRY(zlincomb(n, Mc, 2, X, cp, 0.0, k.R[0], s));
+        cd *Qd = ipiv_keep ? k.U : Q;  // elementwise, so V - U may overwrite U
+        LB_TRY(zlincomb(n, Mc, 2, X, cm, 0.0, Qd, s));
+        LB_TRY(lu_solve_batched(n, n, Mc, Qd, k.R[0], ipiv_keep ? ipiv_keep : d_ipiv, d_info, s));
     }
-    LB_TRY(lu_solve_batched(n, n, Mc, Q, k.R[0], d_ipiv, d_info, s));
     auto level = [&](int l) -> cd * { return l < KEEP_SQ ? k.R[l] : Rp[(l - KEEP_SQ) & 1]; };
     for (int l = 0; l < smax; ++l) {
         ZgemmBatch h = g;
@@ -765,7 +764,9 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
     // Kept path: the propagators and the build's E-independent products of
     // every slice stay resident for the derivative, when the checkpoint
     // budget (if any) and the reservation cap allow it.
-    const size_t cache_bytes = align256((size_t)KEEP_MATS * M * matb);
+    const bool lowrank = n >= kLowRankMinN;  // (with keep) the derivative on low-rank factors
+    const size_t cache_bytes = align256((size_t)KEEP_MATS * M * matb) +
+                               (lowrank ? align256((size_t)M * n * sizeof(int)) : 0);  // + the LU exchanges
     bool keep = checkpoint_bytes <= 0 || (double)(KEEP_MATS + 1) * M * (double)matb <= (double)checkpoint_bytes;
     // ---- reservation: persistent buffers + the larger of the chunk phases
     auto reservation = [&](int mc) {
@@ -775,7 +776,7 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
                                   (keepP ? align256((size_t)M * matb) : 0);
         if (keep) {  // + the cache, the generators of a chunk and the larger phase
             size_t phase = forward_keep_bytes(n, mc);
-            const size_t fr = (n >= kLowRankMinN ? frechet_lowrank_bytes(n, mc, lowrank_rmax(n)) : frechet_bytes(n, mc)) +
+            const size_t fr = (lowrank ? frechet_lowrank_bytes(n, mc, lowrank_rmax(n)) : frechet_bytes(n, mc)) +
                               align256((size_t)mc * matb);
             if (fr > phase) phase = fr;
             return persistent + cache_bytes + align256((size_t)mc * matb) + phase;
@@ -809,7 +810,8 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
     double *d_F = (double *)ws_take(ws, sizeof(double));
     double *partial = (double *)ws_take(ws, (size_t)nblk * Mc * C * sizeof(double));
     cd *Pall = keepP ? (cd *)ws_take(ws, (size_t)M * matb) : nullptr;
-    cd *cache = keep ? (cd *)ws_take(ws, cache_bytes) : nullptr;
+    cd *cache = keep ? (cd *)ws_take(ws, (size_t)KEEP_MATS * M * matb) : nullptr;
+    int *ipiv_keep = keep && lowrank ? (int *)ws_take(ws, (size_t)M * n * sizeof(int)) : nullptr;
     cd *Lg = (cd *)ws_take(ws, (size_t)Mc * matb);
     cd *Pc = keep ? nullptr : (cd *)ws_take(ws, (size_t)Mc * matb);
     std::vector<double> dts(Mc, dt);
@@ -829,7 +831,8 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
         cd *Pdst = keepP ? Pall + (size_t)m0 * nn : Pc;
         if (keep) {
             LB_TRY(generators_launch(n, mc, C, L0, Lc, u + (size_t)m0 * C, Lg, s));
-            LB_TRY(forward_keep_chunk(n, mc, Lg, dts.data(), theta, keep_view(cache, M, m0, nn), Pdst, ws, s));
+            LB_TRY(forward_keep_chunk(n, mc, Lg, dts.data(), theta, keep_view(cache, M, m0, nn), Pdst, ws, s,
+                                      ipiv_keep ? ipiv_keep + (size_t)m0 * n : nullptr));
         } else {
             LB_TRY(chunk_props(m0, mc, Pdst));
         }
@@ -864,9 +867,9 @@ static int grape_run(int n, int M, int C, const cd *L0, const cd *Lc, const doub
         const size_t mark = ws->used;
         cd *G = (cd *)ws_take(ws, (size_t)mc * matb);
         const Keep kv = keep ? keep_view(cache, M, m0, nn) : Keep{};
-        if (keep && n >= kLowRankMinN)
+        if (keep && lowrank)
             LB_TRY(frechet_lowrank_chunk(n, mc, Lg, dts.data(), xs + (size_t)m0 * n, lams + (size_t)(m0 + 1) * n,
-                                         theta, G, ws, s, kv));
+                                         theta, G, ws, s, kv, ipiv_keep + (size_t)m0 * n));
         else
             LB_TRY(frechet_chunk(n, mc, Lg, dts.data(), xs + (size_t)m0 * n, lams + (size_t)(m0 + 1) * n, theta, G,
                                  ws, s, keep ? &kv : nullptr));

@@ -146,6 +146,9 @@ int odd_copy_launch(int n, int M, const int *d_s, const cd *src, cd *dst, hipStr
 // nrhs right-hand sides (N is n x nrhs row-major) by LU with partial
 // pivoting.  D is destroyed.  info[b] (device) is set non-zero on a zero pivot.
 int lu_solve_batched(int n, int nrhs, int batch, cd *D, cd *N, int *ipiv, int *info, hipStream_t s);
+// Solve D X = N again with the factorization lu_solve_batched left in D and
+// ipiv (same batch size class), N overwritten by X.
+int lu_resolve_batched(int n, int nrhs, int batch, const cd *D, cd *N, const int *ipiv, hipStream_t s);
 
 // Pade [13/13] coefficients b_0..b_13 (b_13 = 1).
 void pade13_coefficients(double b[14]);

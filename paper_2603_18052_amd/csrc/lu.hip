@@ -288,6 +288,36 @@ static int gemm_sub(int M, int N, int K, int batch, const cd *A, long long la, l
     return zgemm_batched(g, s);
 }
 
+static int back_subst(int n, int nrhs, int batch, const cd *D, cd *N, int nbo, hipStream_t s);
+
+// The right-hand-side steps of outer block J = [K0, KE) after its panels are
+// factored: all of J's exchanges, the unit-lower solve of J's rows (per
+// panel, a 16-row solve and a GEMM on J's rows below it), one update of the
+// rows below J.  D's trailing columns (dtr of them, right of J) ride along.
+static int rhs_block(int n, int nrhs, int batch, cd *D, cd *N, const int *ipiv, int K0, int KE, int dtr,
+                     hipStream_t s) {
+    const long long sD = (long long)n * n, sN = (long long)n * nrhs;
+    const int W = KE - K0;
+    const bool one = W <= NB;  // a single panel: exchanges and solve in one pass
+    for (int k0 = K0; k0 < KE && !one; k0 += NB) {
+        const int nb = KE - k0 < NB ? KE - k0 : NB;
+        LB_TRY(swap_trsm(D, N, n, nrhs, batch, k0, nb, ipiv, KE, dtr, nrhs, true, false, s));
+    }
+    for (int k0 = K0; k0 < KE; k0 += NB) {
+        const int nb = KE - k0 < NB ? KE - k0 : NB;
+        LB_TRY(swap_trsm(D, N, n, nrhs, batch, k0, nb, ipiv, KE, dtr, nrhs, one, true, s));
+        const int mrows = KE - k0 - nb;  // rows of J below the panel
+        LB_TRY(gemm_sub(mrows, dtr, nb, batch, D + (size_t)(k0 + nb) * n + k0, n, sD, D + (size_t)k0 * n + KE, n, sD,
+                        D + (size_t)(k0 + nb) * n + KE, n, sD, s));
+        LB_TRY(gemm_sub(mrows, nrhs, nb, batch, D + (size_t)(k0 + nb) * n + k0, n, sD, N + (size_t)k0 * nrhs, nrhs,
+                        sN, N + (size_t)(k0 + nb) * nrhs, nrhs, sN, s));
+    }
+    LB_TRY(gemm_sub(n - KE, dtr, W, batch, D + (size_t)KE * n + K0, n, sD, D + (size_t)K0 * n + KE, n, sD,
+                    D + (size_t)KE * n + KE, n, sD, s));
+    return gemm_sub(n - KE, nrhs, W, batch, D + (size_t)KE * n + K0, n, sD, N + (size_t)K0 * nrhs, nrhs, sN,
+                    N + (size_t)KE * nrhs, nrhs, sN, s);
+}
+
 int lu_solve_batched(int n, int nrhs, int batch, cd *D, cd *N, int *ipiv, int *info, hipStream_t s) {
     const long long sD = (long long)n * n, sN = (long long)n * nrhs;
     if (batch > 65535) return fail(LB_ESHAPE, "lu_solve: batch > 65535");
@@ -314,29 +344,16 @@ int lu_solve_batched(int n, int nrhs, int batch, cd *D, cd *N, int *ipiv, int *i
         }
         // ---- the columns right of J (of D and all of N): all of J's exchanges,
         // the unit-lower solve of J's rows, then one update of the rows below
-        const int dtr = n - KE;
-        const bool one = W <= NB;  // a single panel: exchanges and solve in one pass
-        for (int k0 = K0; k0 < KE && !one; k0 += NB) {
-            const int nb = KE - k0 < NB ? KE - k0 : NB;
-            LB_TRY(swap_trsm(D, N, n, nrhs, batch, k0, nb, ipiv, KE, dtr, nrhs, true, false, s));
-        }
-        for (int k0 = K0; k0 < KE; k0 += NB) {
-            const int nb = KE - k0 < NB ? KE - k0 : NB;
-            LB_TRY(swap_trsm(D, N, n, nrhs, batch, k0, nb, ipiv, KE, dtr, nrhs, one, true, s));
-            const int mrows = KE - k0 - nb;  // rows of J below the panel
-            LB_TRY(gemm_sub(mrows, dtr, nb, batch, D + (size_t)(k0 + nb) * n + k0, n, sD, D + (size_t)k0 * n + KE, n,
-                            sD, D + (size_t)(k0 + nb) * n + KE, n, sD, s));
-            LB_TRY(gemm_sub(mrows, nrhs, nb, batch, D + (size_t)(k0 + nb) * n + k0, n, sD, N + (size_t)k0 * nrhs, nrhs,
-                            sN, N + (size_t)(k0 + nb) * nrhs, nrhs, sN, s));
-        }
-        LB_TRY(gemm_sub(n - KE, dtr, W, batch, D + (size_t)KE * n + K0, n, sD, D + (size_t)K0 * n + KE, n, sD,
-                        D + (size_t)KE * n + KE, n, sD, s));
-        LB_TRY(gemm_sub(n - KE, nrhs, W, batch, D + (size_t)KE * n + K0, n, sD, N + (size_t)K0 * nrhs, nrhs, sN,
-                        N + (size_t)KE * nrhs, nrhs, sN, s));
+        LB_TRY(rhs_block(n, nrhs, batch, D, N, ipiv, K0, KE, n - KE, s));
     }
-    // back substitution, blocked the same way: per outer block of rows from
-    // the bottom, NB-row solves with updates kept to the block, then one
-    // update of every row above it
+    return back_subst(n, nrhs, batch, D, N, nbo, s);
+}
+
+// Back substitution with U (above the diagonal of the factored D), blocked
+// like the factorization: per outer block of rows from the bottom, NB-row
+// solves with updates kept to the block, then one update of every row above.
+static int back_subst(int n, int nrhs, int batch, const cd *D, cd *N, int nbo, hipStream_t s) {
+    const long long sD = (long long)n * n, sN = (long long)n * nrhs;
     const int nblk = (n + NB - 1) / NB;
     const int per_outer = nbo / NB;
     for (int ob = (nblk - 1) / per_outer; ob >= 0; --ob) {
@@ -355,6 +372,22 @@ int lu_solve_batched(int n, int nrhs, int batch, cd *D, cd *N, int *ipiv, int *i
         LB_TRY(gemm_sub(B0, nrhs, BE - B0, batch, D + B0, n, sD, N + (size_t)B0 * nrhs, nrhs, sN, N, nrhs, sN, s));
     }
     return LB_OK;
+}
+
+// Solve with a factorization lu_solve_batched left in D (and ipiv): the
+// right-hand-side steps of every outer block in the factorization's order,
+// then the back substitution.  The same operations on the right-hand sides
+// as solving them during the factorization (each column is independent), so
+// the same results, provided batch is on the same side of kOuterMinBatch.
+int lu_resolve_batched(int n, int nrhs, int batch, const cd *D, cd *N, const int *ipiv, hipStream_t s) {
+    if (batch > 65535) return fail(LB_ESHAPE, "lu_resolve: batch > 65535");
+    const int nbo = batch >= kOuterMinBatch ? NBO : NB;
+    cd *Dm = const_cast<cd *>(D);  // only read: no trailing D columns are passed
+    for (int K0 = 0; K0 < n; K0 += nbo) {
+        const int KE = n - K0 < nbo ? n : K0 + nbo;
+        LB_TRY(rhs_block(n, nrhs, batch, Dm, N, ipiv, K0, KE, 0, s));
+    }
+    return back_subst(n, nrhs, batch, D, N, nbo, s);
 }
 
 }  // namespace lb
