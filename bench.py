@@ -75,6 +75,18 @@ def cpu_baseline_leg(cfg, Pn, B, n, N, sample_idx, cpu_seconds):
     cpu = {"value": Bs * Ns / t_cpu, "unit": "state-steps/s", "cores": nthreads, "kind": "oracle",
            "sample": f"d=9 assembly + FP64 Pade-13 build + {Bs} states x {Ns} steps (of {B} x {N}), "
                      f"OpenMP over states, {t_cpu:.1f} s"}
+    # the same chain on one thread (states x steps sized to about a quarter
+    # of the budget; the build is not repeated): the single-core rate
+    B1, N1 = 8, 50
+    t0 = time.perf_counter()
+    oracle.propagate(Ph, X[:B1], N1, nthreads=1)
+    t1 = time.perf_counter() - t0
+    N1 = int(min(N, max(N1, N1 * 0.25 * cpu_seconds / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.propagate(Ph, X[:B1], N1, nthreads=1)
+    t1 = time.perf_counter() - t0
+    cpu["value_1_thread"] = B1 * N1 / t1
+    cpu["sample_1_thread"] = f"{B1} states x {N1} steps on one thread, {t1:.1f} s"
     return cpu, ref
 
 
