@@ -138,8 +138,9 @@ int lindblad_propagator(int n, int M, const void *L, const double *dt, double th
  * column 80 on the vector ALUs, else the SIMD-balanced layout for
  * 81 <= n <= 84 / 96); beyond
  * that one MFMA GEMM launch per step (B >= 16; the LDS-tiled one once
- * ceil(B / 64) ceil(n / 48) >= 240, for the BF16 precisions the ring-pipelined
- * one once it is >= 64) or a per-state matvec (B < 16). */
+ * ceil(B / 64) ceil(n / 48) >= 240) or a per-state matvec (B < 16); for the
+ * BF16 precisions the ring-pipelined plane GEMM, its k range split over
+ * workgroups when the batch has fewer than 256 tiles. */
 int lindblad_propagate(int n, const void *P, lb_precision prec, int B, void *rho, long long nsteps,
                        lb_workspace *ws, hipStream_t stream);
 
@@ -206,7 +207,9 @@ int lindblad_expmv_params(double a, int *s, int *m);
  *             outputs per workgroup, direct global-to-LDS loads (BF16 precisions)
  *   1201      the same tile with each wavefront's state planes staged per 64-k
  *             pair and a ring of propagator chunks loaded 2-3 chunks ahead
- * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901, 1100 + w, 1101, 1200, 1201) replays its steps
+ *   1202      1201 with the k range split over workgroups when the batch has
+ *             fewer than 256 tiles (partial sums added in a fixed order)
+ * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901, 1100 + w, 1101, 1200 .. 1202) replays its steps
  * from a HIP graph captured once per call (32 steps, replayed over all but
  * the last step).  Variants of one shape differ only in summation order. */
 

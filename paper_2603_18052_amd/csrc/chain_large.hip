@@ -510,12 +510,16 @@ __device__ inline bf16x8 bf16_neg(bf16x8 v) {
     return __builtin_bit_cast(bf16x8, u);
 }
 
+// Split k (ksplit > 1, for batches too small to fill the chip): workgroup
+// L = ks * tiles + tile takes chunks [ks cper, (ks + 1) cper) and writes its
+// scaled FP64 partial sums to Ypart[ks]; split_sum_kernel adds them in order.
 template <int MODE, int SP, int SX, int LMAX>
 __global__ void __launch_bounds__(256) tqplane_gemm_kernel(int n, int B, int Kp, int nbt, int nit,
                                                            const unsigned short *__restrict__ Xp,
                                                            const unsigned short *__restrict__ Pp,
                                                            const int *__restrict__ eP, const int *__restrict__ eX,
-                                                           cd *__restrict__ Y) {
+                                                           cd *__restrict__ Y, int ksplit, int cper,
+                                                           cd *__restrict__ Ypart) {
     typedef TqShape<MODE, SP, SX> S;
     constexpr int XD = S::XD, PD = S::PD, R = S::R, NJ = S::NJ;
     constexpr int NLV = MODE == SLICED ? LMAX + 1 : 1;
@@ -530,13 +534,16 @@ __global__ void __launch_bounds__(256) tqplane_gemm_kernel(int n, int B, int Kp,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int total = nbt * nit, per = total / 8, rem = total % 8;
+    const int tiles = nbt * nit, total = tiles * ksplit, per = total / 8, rem = total % 8;
     const int xcd = blockIdx.x % 8, jx = blockIdx.x / 8;
-    const int L0 = xcd * per + (xcd < rem ? xcd : rem) + jx;
+    const int L = xcd * per + (xcd < rem ? xcd : rem) + jx;
+    const int ks = L / tiles, L0 = L - ks * tiles;
     const int bt = L0 / nit, it = L0 - bt * nit;
     const int b0 = bt * TPB, i0 = it * TPI;
     const size_t xplane = (size_t)B * Kp, pplane = (size_t)n * Kp;
-    const int nch = Kp / TPK;  // a multiple of 4
+    // this workgroup's chunks: kc0 .. kc0 + nch - 1 (an even count)
+    const int kc0 = ks * cper, nall = Kp / TPK;
+    const int nch = nall - kc0 < cper ? nall - kc0 : cper;
     unsigned char *xst = smem_raw + R * S::BUF + wave * (2 * S::XL * 1024);  // this wavefront's staging
 
     // a 1 KB load puts lane l's 16 bytes at row l / 4, chunk position l % 4
@@ -562,16 +569,16 @@ __global__ void __launch_bounds__(256) tqplane_gemm_kernel(int n, int B, int Kp,
     // load k of chunk t's set: propagator load k of chunk t + R - 1 into slot
     // (t + R - 1) % R, then state tile (digit, Re/Im) k - NJ of chunk t + 2
     // into staging slot t % 2 (past the last chunk: the last chunk again)
-    auto dma = [&](int t, int k) {
+    auto dma = [&](int t, int k) {  // t, c: chunks counted from kc0
         if (k < NJ) {
             const int c = t + R - 1;
-            const int k0 = (c < nch ? c : nch - 1) * TPK;
+            const int k0 = (kc0 + (c < nch ? c : nch - 1)) * TPK;
             __builtin_amdgcn_global_load_lds(
                 (const void *)(srcp[k] + k0),
                 (__attribute__((address_space(3))) void *)(smem_raw + (c % R) * S::BUF + dsto[k]), 16, 0, 0);
         } else {
             const int c = t + 2, tile = k - NJ, a = tile >> 1, q = tile & 1;
-            const int k0 = (c < nch ? c : nch - 1) * TPK;
+            const int k0 = (kc0 + (c < nch ? c : nch - 1)) * TPK;
             __builtin_amdgcn_global_load_lds(
                 (const void *)(xsrc + (a * 3 + q) * xplane + k0),
                 (__attribute__((address_space(3))) void *)(xst + ((t & 1) * S::XL + tile) * 1024), 16, 0, 0);
@@ -666,6 +673,7 @@ __global__ void __launch_bounds__(256) tqplane_gemm_kernel(int n, int B, int Kp,
                 }
     }
     __builtin_amdgcn_s_waitcnt(0);  // the loads past the last chunk land before the workgroup ends
+    cd *out = ksplit > 1 ? Ypart + (size_t)ks * B * n : Y;
 #pragma unroll
     for (int t = 0; t < 3; ++t)
 #pragma unroll
@@ -674,12 +682,41 @@ __global__ void __launch_bounds__(256) tqplane_gemm_kernel(int n, int B, int Kp,
             if (b < B && i < n) {
                 if (MODE == SLICED) {
                     const int sc = eP[i] + eX[b];
-                    Y[(size_t)b * n + i] = {ldexp(ar[t][r], sc), ldexp(ai[t][r], sc)};
+                    out[(size_t)b * n + i] = {ldexp(ar[t][r], sc), ldexp(ai[t][r], sc)};
+                } else if (ksplit > 1) {  // rounded to FP32 after the sum
+                    out[(size_t)b * n + i] = {ar[t][r], ai[t][r]};
                 } else {
-                    Y[(size_t)b * n + i] = {(double)(float)ar[t][r], (double)(float)ai[t][r]};
+                    out[(size_t)b * n + i] = {(double)(float)ar[t][r], (double)(float)ai[t][r]};
                 }
             }
         }
+}
+
+// Y[e] = sum over ks = 0, 1, ... of Ypart[ks][e] (in that order); HILO rounds
+// the sum to FP32 as the unsplit kernel does
+template <int MODE>
+__global__ void split_sum_kernel(long long total, int ksplit, const cd *__restrict__ Ypart, cd *__restrict__ Y) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k < ksplit; ++k) {
+            const cd v = Ypart[(size_t)k * total + e];
+            re += v.re;
+            im += v.im;
+        }
+        Y[e] = MODE == SLICED ? cd{re, im} : cd{(double)(float)re, (double)(float)im};
+    }
+}
+
+// split of the k range for the ring kernel: enough workgroups for the chip
+// (about 256) in whole 64-k pairs; returns ksplit, sets the chunks per split
+static int tq_split(int tiles, int Kp, int *cper) {
+    const int npairs = Kp / KCH;
+    int ks = tiles >= 256 ? 1 : (256 + tiles - 1) / tiles;
+    ks = ks < npairs ? ks : npairs;
+    const int pp = (npairs + ks - 1) / ks;
+    *cper = 2 * pp;
+    return (npairs + pp - 1) / pp;
 }
 
 // --------------------------------------------------------- FP32 / FP64
@@ -1333,25 +1370,31 @@ static int tgemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Works
 
 template <int MODE, int SP, int SX, int LMAX>
 // tiled: 0 = untiled plane GEMM, 1 = LDS-tiled (state and propagator planes in
-// LDS), 2 = LDS-tiled with the state planes in registers (propagator ring)
+// LDS), 2 = ring-pipelined (per-wavefront state staging, propagator ring),
+// 3 = ring-pipelined with the k range split over workgroups (small batches)
 static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s,
                       bool graph, int tiled) {
     constexpr int XD = Planes<MODE, SP, SX>::XD, PD = Planes<MODE, SP, SX>::PD;
-    const int kq = tiled == 2 ? TQK : KCH;
+    const int kq = tiled >= 2 ? TQK : KCH;
     const int Kp = (n + kq - 1) / kq * kq;
     const size_t pbytes = (size_t)PD * 2 * n * Kp * 2, xbytes = (size_t)XD * 3 * B * Kp * 2;
     const size_t ybytes = (size_t)B * n * sizeof(cd);
-    LB_TRY(ws_ensure(ws, align256(pbytes) + align256(xbytes) + align256(ybytes) + align256(n * 4) + align256(B * 4)));
+    const int nbt = (B + TPB - 1) / TPB, nit = (n + TPI - 1) / TPI;
+    int cper = Kp / TPK;
+    const int ksplit = tiled == 3 ? tq_split(nbt * nit, Kp, &cper) : 1;
+    const size_t pbytes_part = ksplit > 1 ? (size_t)ksplit * ybytes : 0;
+    LB_TRY(ws_ensure(ws, align256(pbytes) + align256(xbytes) + align256(ybytes) + align256(n * 4) + align256(B * 4) +
+                             align256(pbytes_part)));
     unsigned short *Pp = (unsigned short *)ws_take(ws, pbytes);
     unsigned short *Xp = (unsigned short *)ws_take(ws, xbytes);
     cd *Yt = (cd *)ws_take(ws, ybytes);
     int *eP = (int *)ws_take(ws, n * 4);
     int *eX = (int *)ws_take(ws, B * 4);
+    cd *Ypart = ksplit > 1 ? (cd *)ws_take(ws, pbytes_part) : nullptr;
     prep_p_kernel<MODE, SP, SX><<<n, 256, 0, s>>>(n, Kp, P, Pp, eP);
     LB_TRY(check_launch("prep_p"));
     dim3 grid((n + TO - 1) / TO, (B + TS - 1) / TS);
-    const int nbt = (B + TPB - 1) / TPB, nit = (n + TPI - 1) / TPI;
-    const size_t lds = tiled == 2 ? (size_t)TqShape<MODE, SP, SX>::LDS : 2 * (size_t)TpShape<MODE, SP, SX>::BUF;
+    const size_t lds = tiled >= 2 ? (size_t)TqShape<MODE, SP, SX>::LDS : 2 * (size_t)TpShape<MODE, SP, SX>::BUF;
     if (tiled == 1) {
         static bool attr_set = false;
         if (!attr_set) {
@@ -1359,7 +1402,7 @@ static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Work
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
             attr_set = true;
         }
-    } else if (tiled == 2) {
+    } else if (tiled >= 2) {
         static bool attr_set = false;
         if (!attr_set) {
             LB_HIP(hipFuncSetAttribute((const void *)tqplane_gemm_kernel<MODE, SP, SX, LMAX>,
@@ -1370,17 +1413,20 @@ static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Work
     // the state ping-pongs between rho and Yt
     LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
         cd *cur = (t & 1) ? Yt : rho, *nxt = (t & 1) ? rho : Yt;
-        if (tiled == 2)
+        if (tiled >= 2)
             slice_x_kernel<MODE, SP, SX, false><<<B, 256, 0, st>>>(n, Kp, B, cur, Xp, eX);
         else
             slice_x_kernel<MODE, SP, SX, true><<<B, 256, 0, st>>>(n, Kp, B, cur, Xp, eX);
         if (tiled == 1)
             tplane_gemm_kernel<MODE, SP, SX, LMAX><<<nbt * nit, 256, lds, st>>>(n, B, Kp, nbt, nit, Xp, Pp, eP, eX,
                                                                                 nxt);
-        else if (tiled == 2)
-            tqplane_gemm_kernel<MODE, SP, SX, LMAX><<<nbt * nit, 256, lds, st>>>(n, B, Kp, nbt, nit, Xp, Pp, eP, eX,
-                                                                                 nxt);
-        else
+        else if (tiled >= 2) {
+            // with the k range split, the partial sums are added in order into nxt
+            tqplane_gemm_kernel<MODE, SP, SX, LMAX><<<nbt * nit * ksplit, 256, lds, st>>>(
+                n, B, Kp, nbt, nit, Xp, Pp, eP, eX, nxt, ksplit, cper, Ypart);
+            if (ksplit > 1)
+                split_sum_kernel<MODE><<<grid1((long long)B * n), 256, 0, st>>>((long long)B * n, ksplit, Ypart, nxt);
+        } else
             plane_gemm_kernel<MODE, SP, SX, LMAX><<<grid, 256, 0, st>>>(n, B, Kp, Xp, Pp, eP, eX, nxt);
         return LB_OK;
     }, s));
@@ -1624,8 +1670,11 @@ size_t large_ws_bytes(int family, int n, lb_precision prec, int B) {
         const size_t kq = family == VF_TPLANES ? TQK : KCH;  // the ring kernel's k granularity bounds both
         const size_t Kp = (size_t)(n + kq - 1) / kq * kq;
         const size_t PD = prec == LB_BF16_HILO ? 2 : 5, XD = prec == LB_BF16_HILO ? 2 : 4;
+        int cper = 0;
+        const size_t ks = family == VF_TPLANES ? (size_t)tq_split(((B + TPB - 1) / TPB) * ((n + TPI - 1) / TPI), (int)Kp, &cper) : 1;
         return align256(PD * 2 * n * Kp * 2) + align256(XD * 3 * B * Kp * 2) + align256((size_t)B * n * sizeof(cd)) +
-               align256((size_t)n * 4) + align256((size_t)B * 4);
+               align256((size_t)n * 4) + align256((size_t)B * 4) +
+               (ks > 1 ? align256(ks * (size_t)B * n * sizeof(cd)) : 0);  // split-k partials (param 2)
     }
     return 0;
 }

@@ -81,6 +81,7 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
         add2(VF_PLANES * 100);
         add2(VF_TPLANES * 100);
         add2(VF_TPLANES * 100 + 1);
+        add2(VF_TPLANES * 100 + 2);
     } else if (prec == LB_Q15) {
         if (n <= kWaveChainMaxN) add(VF_Q15 * 100);
         add2(VF_Q15 * 100 + 1);
@@ -123,8 +124,7 @@ int chain_heuristic(int n, lb_precision prec, int B) {
         case LB_BF16_HILO:
         case LB_BF16_SLICED: {
             if (n <= bf16_fused_max_n(prec)) return VF_BF16_FUSED * 100;
-            const long long tiles = (long long)((B + 63) / 64) * ((n + 47) / 48);
-            return tiles >= 64 ? VF_TPLANES * 100 + 1 : VF_PLANES * 100;  // measured crossover at n = 729: B = 128 .. 256
+            return VF_TPLANES * 100 + 2;  // the ring kernel, k split over workgroups below 256 tiles
         }
         case LB_Q15:
             return n <= kWaveChainMaxN ? VF_Q15 * 100 : VF_Q15 * 100 + 1;
@@ -167,7 +167,7 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_Q15: return chain_q15(n, P, B, rho, nsteps, prm == 0, graph, ws, s);
         case VF_TAIL: return chain_tail(n, P, prec, prm, B, rho, nsteps, s);
         case VF_TGEMM: return chain_tgemm(n, P, prec, prm, B, rho, nsteps, ws, s, graph);
-        case VF_TPLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s, graph, prm == 1 ? 2 : 1);
+        case VF_TPLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s, graph, prm == 0 ? 1 : prm + 1);
         default: return fail(LB_EINVAL, "unknown chain variant");
     }
 }

@@ -81,8 +81,8 @@ def variant_name(v: int) -> str:
         name = f"{name}_{'wave' if prm == 0 else 'matvec'}"
     elif fam == 11:
         name = f"{name}(ring)" if prm == 1 else f"{name}(w{prm})"
-    elif fam == 12 and prm == 1:
-        name = f"{name}(ring)"
+    elif fam == 12 and prm in (1, 2):
+        name = f"{name}({'ring' if prm == 1 else 'ring+splitk'})"
     elif fam == 10 and prm in (1, 2, 3):
         name = f"{name}({('w16', 'tiles', 'tiles+presum')[prm - 1]})"
     return name + "+graph" if graph else name

@@ -105,15 +105,15 @@ def test_chain_variant_lists_and_rule(L):
     assert lb.chain_variant(729, "c64", 1) == 600
     assert 100 not in lb.chain_variants(729, "c64", 64)
     # BF16 precisions
-    assert lb.chain_variants(81, "bf16_sliced", 16) == [400, 700, 750, 1200, 1250, 1201, 1251]
-    assert lb.chain_variants(729, "bf16_sliced", 16) == [700, 750, 1200, 1250, 1201, 1251]
+    assert lb.chain_variants(81, "bf16_sliced", 16) == [400, 700, 750, 1200, 1250, 1201, 1251, 1202, 1252]
+    assert lb.chain_variants(729, "bf16_sliced", 16) == [700, 750, 1200, 1250, 1201, 1251, 1202, 1252]
     assert [lb.variant_name(x) for x in (150, 552, 306, 800, 1000, 1001, 1002, 1003, 1104, 1158)] == [
         "baseline+graph", "gemm(w2)+graph", "fused(k6)", "fused_balanced", "fused_tail", "fused_tail(w16)",
         "fused_tail(tiles)", "fused_tail(tiles+presum)", "gemm_tiled(w4)", "gemm_tiled(w8)+graph"]
     assert [lb.variant_name(x) for x in (1200, 1201, 1251)] == [
         "planes_tiled", "planes_tiled(ring)", "planes_tiled(ring)+graph"]
-    assert lb.chain_variant(729, "bf16_hilo", 16) == 700
-    assert lb.chain_variant(729, "bf16_sliced", 1024) == 1201  # LDS-tiled ring plane GEMM fills the chip
+    assert lb.chain_variant(729, "bf16_hilo", 16) == 1202
+    assert lb.chain_variant(729, "bf16_sliced", 1024) == 1202  # ring plane GEMM (256 tiles: no k split)
     # fixed point: one wavefront per state for n <= 16, else the per-row matvec (and its graph twin)
     assert lb.chain_variants(9, "q15", 1) == [900, 901, 951]
     assert lb.chain_variants(729, "q15", 3) == [901, 951]

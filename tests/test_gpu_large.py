@@ -83,7 +83,7 @@ def test_d27_deterministic(lb, P27):
 
 
 @pytest.mark.parametrize("prec,nsteps,tol,variant", [("c128", 200, 1e-12, 1108), ("c64", 200, 5e-5, 1108),
-                                                     ("bf16_sliced", 1000, 1e-6, 1201)])
+                                                     ("bf16_sliced", 1000, 1e-6, 1202)])
 def test_d27_config3_full_batch_sampled(lb, P27, prec, nsteps, tol, variant):
     """Config 3 at its full batch (B = 1024) in the launch configuration the
     bench times (the LDS-tiled step kernels, 256 workgroups); the oracle
@@ -116,3 +116,26 @@ def test_ring_plane_kernel_matches_tiled(lb, P27, prec, nsteps, B):
         lb.propagate_variant(T(P27), x, nsteps, v, prec)
         out[v] = x.cpu().numpy()
     assert np.array_equal(out[1200], out[1201])
+
+
+@pytest.mark.parametrize("prec", ["bf16_sliced", "bf16_hilo"])
+@pytest.mark.parametrize("B,nsteps", [(1024, 3), (100, 3), (64, 601), (1, 20)])
+def test_splitk_plane_kernel_matches_ring(lb, P27, prec, B, nsteps):
+    """The ring kernel with the k range split over workgroups (1202) against
+    the unsplit one (1201): bitwise at 256 tiles (B = 1024: no split).  Else
+    the FP64 partial sums of the k ranges are added in order; the state then
+    differs by FP64 rounding, which can move the last digit of the next
+    step's slicing (2^-32 of the state for the 4-digit state slices) or the
+    FP32 rounding of the hi+lo state (2^-24), so the bound is that."""
+    X = states(27, B, 21 + B)
+    out = {}
+    for v in (1201, 1202):
+        x = T(X.copy())
+        lb.propagate_variant(T(P27), x, nsteps, v, prec)
+        out[v] = x.cpu().numpy()
+    if B == 1024:
+        assert np.array_equal(out[1201], out[1202])
+    else:
+        scale = np.abs(out[1201]).max()
+        tol = 1e-8 if prec == "bf16_sliced" else 1e-5
+        assert np.abs(out[1201] - out[1202]).max() <= tol * scale
