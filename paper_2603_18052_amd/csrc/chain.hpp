@@ -21,7 +21,7 @@ enum ChainFamily : int {
     VF_BALANCED = 8,    // fused chain with the SIMD-balanced layout (81 <= n <= 84 / 96)
     VF_Q15 = 9,         // fixed-point chain (LB_Q15); param 0 one wavefront per state, 1 per-row matvec
     VF_TAIL = 10,       // fused chain, rows 0..79 on MFMA, the rest on the VALU (n = 81); param = layout 0..3
-    VF_TGEMM = 11,      // one LDS-tiled MFMA GEMM launch per step (64 states x 48 outputs); param = wavefronts 4 / 8, 1 = ring
+    VF_TGEMM = 11,      // one LDS-tiled MFMA GEMM launch per step (64 states x 48 outputs); param = wavefronts 4 / 8, 1 = ring, 2 = ring + split k
     VF_TPLANES = 12,    // one LDS-tiled BF16 plane-GEMM launch per step (64 states x 48 outputs); param 1: ring-pipelined, 2: ring + split k
 };
 inline int variant_family(int v) { return v / 100; }

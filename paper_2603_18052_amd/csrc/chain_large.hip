@@ -1186,12 +1186,16 @@ __device__ inline int tr_swz(int row, int piece) {
     return sizeof(T) == 8 ? piece ^ ((row >> 1) & 7) : piece ^ ((row >> 2) & 3);
 }
 
+// Split k (ksplit > 1): workgroup L = ks * tiles + tile takes chunks
+// [ks cper, (ks + 1) cper) and writes its partial sums (FP64) to Ypart[ks];
+// tr_split_sum_kernel adds them in order and writes the next state.
 template <typename T>
 __global__ void __launch_bounds__(256) trgemm_step_kernel(int n, int B, int Kp, int nbt, int nit,
                                                           const T *__restrict__ Xr, const T *__restrict__ Xi,
                                                           const T *__restrict__ Pr, const T *__restrict__ Pi,
                                                           T *__restrict__ Yr, T *__restrict__ Yi,
-                                                          cd *__restrict__ Yout) {
+                                                          cd *__restrict__ Yout, int ksplit, int cper,
+                                                          cd *__restrict__ Ypart) {
     typedef TrShape<T> S;
     typedef typename TgMma<T>::acc acc_t;
     typedef T v4 __attribute__((ext_vector_type(4)));
@@ -1200,12 +1204,15 @@ __global__ void __launch_bounds__(256) trgemm_step_kernel(int n, int B, int Kp, 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int total = nbt * nit, per = total / 8, rem = total % 8;
+    const int tiles = nbt * nit, total = tiles * ksplit, per = total / 8, rem = total % 8;
     const int xcd = blockIdx.x % 8, jx = blockIdx.x / 8;
-    const int L0 = xcd * per + (xcd < rem ? xcd : rem) + jx;
+    const int L = xcd * per + (xcd < rem ? xcd : rem) + jx;
+    const int ks = L / tiles, L0 = L - ks * tiles;
     const int bt = L0 / nit, it = L0 - bt * nit;
     const int b0 = bt * TGB, i0 = it * TGI;
-    const int nch = Kp / TRK;
+    // this workgroup's chunks: kc0 .. kc0 + nch - 1
+    const int kc0 = ks * cper, nall = Kp / TRK;
+    const int nch = nall - kc0 < cper ? nall - kc0 : cper;
 
     // load j = wave + 4 q of a chunk: plane tile (Re X, Im X, Re P, Im P),
     // its 1 KB part jj; lane l fills row RPL jj + l / NPC, position l % NPC,
@@ -1233,8 +1240,8 @@ __global__ void __launch_bounds__(256) trgemm_step_kernel(int n, int B, int Kp, 
             dsto[q] = 2 * S::XPB + (pl - 2) * S::PPB + 1024 * jj;
         }
     }
-    auto dma = [&](int c, int q) {  // load q of chunk c into slot c % R (past the end: the last chunk)
-        const int k0 = (c < nch ? c : nch - 1) * TRK;
+    auto dma = [&](int c, int q) {  // load q of chunk c (from kc0) into slot c % R (past the end: the last chunk)
+        const int k0 = (kc0 + (c < nch ? c : nch - 1)) * TRK;
         __builtin_amdgcn_global_load_lds((const void *)(srcp[q] + k0),
                                          (__attribute__((address_space(3))) void *)(smem_raw + (c % R) * S::BUF +
                                                                                     dsto[q]),
@@ -1297,24 +1304,66 @@ __global__ void __launch_bounds__(256) trgemm_step_kernel(int n, int B, int Kp, 
         for (int r = 0; r < 4; ++r) {
             const int b = b0 + 16 * wave + TgMma<T>::row(lane, r), i = i0 + 16 * t + (lane & 15);
             if (b < B && i < n) {
-                Yr[(size_t)b * Kp + i] = re[t][r];
-                Yi[(size_t)b * Kp + i] = im[t][r];
-                if (Yout) Yout[(size_t)b * n + i] = {(double)re[t][r], (double)im[t][r]};
+                if (ksplit > 1) {
+                    Ypart[((size_t)ks * B + b) * n + i] = {(double)re[t][r], (double)im[t][r]};
+                } else {
+                    Yr[(size_t)b * Kp + i] = re[t][r];
+                    Yi[(size_t)b * Kp + i] = im[t][r];
+                    if (Yout) Yout[(size_t)b * n + i] = {(double)re[t][r], (double)im[t][r]};
+                }
             }
         }
 }
 
+// the next state from the split-k partials: sum over ks in order (FP64),
+// rounded to T into the planes, and on the last step the complex128 result
+template <typename T>
+__global__ void tr_split_sum_kernel(int n, int B, int Kp, int ksplit, const cd *__restrict__ Ypart,
+                                    T *__restrict__ Yr, T *__restrict__ Yi, cd *__restrict__ Yout) {
+    const long long total = (long long)B * n;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k < ksplit; ++k) {
+            const cd v = Ypart[(size_t)k * total + e];
+            re += v.re;
+            im += v.im;
+        }
+        const long long b = e / n, i = e - b * n;
+        const T tr = (T)re, ti = (T)im;
+        Yr[b * Kp + i] = tr;
+        Yi[b * Kp + i] = ti;
+        if (Yout) Yout[e] = {(double)tr, (double)ti};
+    }
+}
+
+// split of the k range (16-deep chunks) for the ring GEMM: about 256
+// workgroups; returns ksplit, sets the chunks per split
+static int tr_split(int tiles, int Kp, int *cper) {
+    const int nch = Kp / TRK;
+    int ks = tiles >= 256 ? 1 : (256 + tiles - 1) / tiles;
+    ks = ks < nch ? ks : nch;
+    const int cp = (nch + ks - 1) / ks;
+    *cper = cp;
+    return (nch + cp - 1) / cp;
+}
+
 template <typename T>
 static int trgemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s,
-                      bool graph) {
+                      bool graph, bool split) {
     typedef TrShape<T> S;
     const int Kp = (n + 63) / 64 * 64;
+    const int nbt = (B + TGB - 1) / TGB, nit = (n + TGI - 1) / TGI;
+    int cper = Kp / TRK;
+    const int ksplit = split ? tr_split(nbt * nit, Kp, &cper) : 1;
     const size_t pp = (size_t)n * Kp * sizeof(T), xp = (size_t)B * Kp * sizeof(T);
-    LB_TRY(ws_ensure(ws, 2 * align256(pp) + 4 * align256(xp)));
+    const size_t partb = ksplit > 1 ? (size_t)ksplit * B * n * sizeof(cd) : 0;
+    LB_TRY(ws_ensure(ws, 2 * align256(pp) + 4 * align256(xp) + align256(partb)));
     T *Pr = (T *)ws_take(ws, pp), *Pi = (T *)ws_take(ws, pp);
     T *X[2][2];
     for (int q = 0; q < 2; ++q)
         for (int c = 0; c < 2; ++c) X[q][c] = (T *)ws_take(ws, xp);
+    cd *Ypart = ksplit > 1 ? (cd *)ws_take(ws, partb) : nullptr;
     to_planes_kernel<T><<<grid1((long long)n * Kp), 256, 0, s>>>(n, n, Kp, P, Pr, Pi);
     for (int q = 0; q < 2; ++q)  // zero k padding of both buffers
         to_planes_kernel<T><<<grid1((long long)B * Kp), 256, 0, s>>>(B, n, Kp, rho, X[q][0], X[q][1]);
@@ -1325,11 +1374,15 @@ static int trgemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Work
                                    S::LDS));
         attr_set = true;
     }
-    const int nbt = (B + TGB - 1) / TGB, nit = (n + TGI - 1) / TGI;
     LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
         const int c = (int)(t & 1);
-        trgemm_step_kernel<T><<<nbt * nit, 256, S::LDS, st>>>(n, B, Kp, nbt, nit, X[c][0], X[c][1], Pr, Pi,
-                                                              X[c ^ 1][0], X[c ^ 1][1], t + 1 == nsteps ? rho : nullptr);
+        cd *out = t + 1 == nsteps ? rho : nullptr;
+        trgemm_step_kernel<T><<<nbt * nit * ksplit, 256, S::LDS, st>>>(n, B, Kp, nbt, nit, X[c][0], X[c][1], Pr, Pi,
+                                                                       X[c ^ 1][0], X[c ^ 1][1], out, ksplit, cper,
+                                                                       Ypart);
+        if (ksplit > 1)
+            tr_split_sum_kernel<T><<<grid1((long long)B * n), 256, 0, st>>>(n, B, Kp, ksplit, Ypart, X[c ^ 1][0],
+                                                                            X[c ^ 1][1], out);
         return LB_OK;
     }, s));
     return check_launch("trgemm_step");
@@ -1632,14 +1685,15 @@ int chain_gemm(int n, const cd *P, lb_precision prec, int wn, int B, cd *rho, lo
 int chain_tgemm(int n, const cd *P, lb_precision prec, int waves, int B, cd *rho, long long nsteps, Workspace *ws,
                 hipStream_t s, bool graph) {
     if (nsteps == 0 || B == 0) return LB_OK;
-    if (waves != 1 && waves != 4 && waves != 8) return fail(LB_ESHAPE, "tiled gemm chain: 4 or 8 wavefronts, or 1 (ring)");
+    if (waves < 1 || (waves > 2 && waves != 4 && waves != 8))
+        return fail(LB_ESHAPE, "tiled gemm chain: 4 or 8 wavefronts, 1 (ring) or 2 (ring, split k)");
     switch (prec) {
         case LB_C128:
-            if (waves == 1) return trgemm_run<double>(n, P, B, rho, nsteps, ws, s, graph);
+            if (waves <= 2) return trgemm_run<double>(n, P, B, rho, nsteps, ws, s, graph, waves == 2);
             return waves == 4 ? tgemm_run<double, 4>(n, P, B, rho, nsteps, ws, s, graph)
                               : tgemm_run<double, 8>(n, P, B, rho, nsteps, ws, s, graph);
         case LB_C64:
-            if (waves == 1) return trgemm_run<float>(n, P, B, rho, nsteps, ws, s, graph);
+            if (waves <= 2) return trgemm_run<float>(n, P, B, rho, nsteps, ws, s, graph, waves == 2);
             return waves == 4 ? tgemm_run<float, 4>(n, P, B, rho, nsteps, ws, s, graph)
                               : tgemm_run<float, 8>(n, P, B, rho, nsteps, ws, s, graph);
         default: return fail(LB_ENOTSUP, "tiled gemm chain: complex128 / complex64 only");
@@ -1664,7 +1718,10 @@ size_t large_ws_bytes(int family, int n, lb_precision prec, int B) {
     if (family == VF_MATVEC) return align256((size_t)n * n * 2 * tsz) + 2 * align256((size_t)B * n * 2 * tsz);
     if (family == VF_GEMM || family == VF_TGEMM) {
         const size_t Kp = (size_t)(n + 63) / 64 * 64;
-        return 2 * align256(n * Kp * tsz) + 4 * align256(B * Kp * tsz);
+        int cper = 0;
+        const size_t ks = family == VF_TGEMM ? (size_t)tr_split(((B + TGB - 1) / TGB) * ((n + TGI - 1) / TGI), (int)Kp, &cper) : 1;
+        return 2 * align256(n * Kp * tsz) + 4 * align256(B * Kp * tsz) +
+               (ks > 1 ? align256(ks * (size_t)B * n * sizeof(cd)) : 0);  // split-k partials (param 2)
     }
     if (family == VF_PLANES || family == VF_TPLANES) {
         const size_t kq = family == VF_TPLANES ? TQK : KCH;  // the ring kernel's k granularity bounds both

@@ -75,6 +75,7 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
         add2(VF_TGEMM * 100 + 4);
         add2(VF_TGEMM * 100 + 8);
         add2(VF_TGEMM * 100 + 1);
+        add2(VF_TGEMM * 100 + 2);
         if (prec == LB_C64) add2(VF_MATVEC * 100);
     } else if (prec == LB_BF16_HILO || prec == LB_BF16_SLICED) {
         if (n <= bf16_fused_max_n(prec)) add(VF_BF16_FUSED * 100);

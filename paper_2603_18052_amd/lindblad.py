@@ -80,7 +80,7 @@ def variant_name(v: int) -> str:
     elif fam == 9:
         name = f"{name}_{'wave' if prm == 0 else 'matvec'}"
     elif fam == 11:
-        name = f"{name}(ring)" if prm == 1 else f"{name}(w{prm})"
+        name = {1: f"{name}(ring)", 2: f"{name}(ring+splitk)"}.get(prm, f"{name}(w{prm})")
     elif fam == 12 and prm in (1, 2):
         name = f"{name}({'ring' if prm == 1 else 'ring+splitk'})"
     elif fam == 10 and prm in (1, 2, 3):

@@ -79,7 +79,7 @@ def test_chain_variant_lists_and_rule(L):
     v = lb.chain_variants(9, "c128", 1)
     assert v[:3] == [100, 150, 200]  # baseline, its graph-replayed twin, wave
     assert [x for x in v if x // 100 == 3] == [301, 302, 303]  # KS = 3 k steps
-    assert {501, 502, 551, 552, 1104, 1154, 1108, 1158, 1101, 1151} <= set(v) and 600 not in v
+    assert {501, 502, 551, 552, 1104, 1154, 1108, 1158, 1101, 1151, 1102, 1152} <= set(v) and 600 not in v
     assert 600 in lb.chain_variants(9, "c64", 1000) and 100 not in lb.chain_variants(9, "c64", 1)
     assert lb.chain_variant(9, "c128", 1) == 200
     # d = 9 headline: fused with the smallest k split giving at most 32 units
@@ -128,7 +128,7 @@ def test_chain_variant_lists_and_rule(L):
     cnt = ctypes.c_int()
     assert L.lindblad_chain_variants(0, 0, 1, None, 0, ctypes.byref(cnt)) == lb.ESHAPE
     assert L.lindblad_chain_variants(9, 7, 1, None, 0, ctypes.byref(cnt)) == lb.EINVAL
-    assert L.lindblad_chain_variants(9, 0, 1, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 16
+    assert L.lindblad_chain_variants(9, 0, 1, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 18
     assert L.lindblad_propagate_variant(9, 1, 0, 1, 1, 5, 999, None, None) == lb.EINVAL
     assert L.lindblad_tune(9, 1, 0, 1, 1, 0, 1, None, None, None, None) == lb.EINVAL
 
