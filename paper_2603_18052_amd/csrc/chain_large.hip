@@ -1177,8 +1177,11 @@ struct TrShape {
     static constexpr int NJ = (NI + 3) / 4;          // per wavefront (the last few repeat others)
     static constexpr int R = kLdsBytes / BUF > 6 ? 6 : kLdsBytes / BUF;
     static constexpr int LDS = R * BUF;
-    static constexpr int WAIT = (R - 2) * NJ;        // loads of chunks c + 1 .. c + R - 2 stay in flight
-    static_assert(BUF % 1024 == 0 && R >= 3 && WAIT <= 63, "ring GEMM shape");
+    // at the wait for chunk c + 1 the loads of chunks c + 2 .. c + R - 1 stay
+    // in flight (chunk c + R is issued after it); before the first chunk
+    // those of chunks 1 .. R - 1
+    static constexpr int WAIT = (R - 2) * NJ, WAIT0 = (R - 1) * NJ;
+    static_assert(BUF % 1024 == 0 && R >= 3 && WAIT0 <= 63, "ring GEMM shape");
 };
 // position of a row's 16-byte piece: piece ^ f(row), f spreading 16 rows over all banks
 template <typename T>
@@ -1263,39 +1266,71 @@ __global__ void __launch_bounds__(256) trgemm_step_kernel(int n, int B, int Kp, 
     acc_t re[3], im[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) re[t] = im[t] = acc_t{0, 0, 0, 0};
-#pragma unroll
-    for (int c = 0; c < R - 1; ++c)
-#pragma unroll
-        for (int q = 0; q < NJ; ++q) dma(c, q);
-    for (int c = 0; c < nch; ++c) {
-        TQ_SYNC(S::WAIT);
+    // The operands of chunk c + 1 are read into registers before chunk c's
+    // MFMAs are issued, so the LDS latency hides behind them; the barrier
+    // before those reads also tells every wavefront that chunk c's slot,
+    // already in registers everywhere, may take chunk c + R.
+    struct Ops {
+        v4 ar, ai, br[3], bi[3];
+    };
+    auto readops = [&](int c, Ops &o) {
         const unsigned char *buf = smem_raw + (c % R) * S::BUF;
-        const v4 ar = opnd(buf, 16 * wave + orow), ai = opnd(buf + S::XPB, 16 * wave + orow);
-        v4 br[3], bi[3];
+        o.ar = opnd(buf, 16 * wave + orow);
+        o.ai = opnd(buf + S::XPB, 16 * wave + orow);
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
-            br[t] = opnd(buf + 2 * S::XPB, 16 * t + orow);
-            bi[t] = opnd(buf + 2 * S::XPB + S::PPB, 16 * t + orow);
+            o.br[t] = opnd(buf + 2 * S::XPB, 16 * t + orow);
+            o.bi[t] = opnd(buf + 2 * S::XPB + S::PPB, 16 * t + orow);
         }
+    };
+    // the chunk's MFMAs, with chunk cd's loads spread between them (cd < 0: none)
+    auto mmas = [&](const Ops &o, int cd) {
         v4 an;
-        if constexpr (sizeof(T) == 4) an = -ai;
+        if constexpr (sizeof(T) == 4) an = -o.ai;
         int grp = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int t = 0; t < 3; ++t, ++grp) {
-                // this group's share of chunk c + R - 1's loads (into the slot chunk c - 1 used)
 #pragma unroll
                 for (int k = 0; k < NJ; ++k)
-                    if (k * 12 >= grp * NJ && k * 12 < (grp + 1) * NJ) dma(c + R - 1, k);
-                re[t] = TgMma<T>::mma(ar[q], br[t][q], re[t]);
-                im[t] = TgMma<T>::mma(ar[q], bi[t][q], im[t]);
+                    if (cd >= 0 && k * 12 >= grp * NJ && k * 12 < (grp + 1) * NJ) dma(cd, k);
+                re[t] = TgMma<T>::mma(o.ar[q], o.br[t][q], re[t]);
+                im[t] = TgMma<T>::mma(o.ar[q], o.bi[t][q], im[t]);
                 if constexpr (sizeof(T) == 8)
-                    re[t] = TgMma<T>::mma_na(ai[q], bi[t][q], re[t]);
+                    re[t] = TgMma<T>::mma_na(o.ai[q], o.bi[t][q], re[t]);
                 else
-                    re[t] = TgMma<T>::mma(an[q], bi[t][q], re[t]);
-                im[t] = TgMma<T>::mma(ai[q], br[t][q], im[t]);
+                    re[t] = TgMma<T>::mma(an[q], o.bi[t][q], re[t]);
+                im[t] = TgMma<T>::mma(o.ai[q], o.br[t][q], im[t]);
             }
+    };
+    // prologue: chunks 0 .. R - 1, one per slot
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) dma(c, q);
+    TQ_SYNC(S::WAIT0);
+    Ops oa, ob;
+    readops(0, oa);
+    // step(c, cur, nxt): chunk c + 1 has landed and chunk c is in every
+    // wavefront's registers: read chunk c + 1, then chunk c's MFMAs with
+    // chunk c + R's loads into chunk c's slot.  Two steps per iteration so
+    // that the operand sets alternate without copies.
+    auto step = [&](int c, const Ops &cur, Ops &nxt) {
+        TQ_SYNC(S::WAIT);
+        readops(c + 1, nxt);
+        mmas(cur, c + R);
+    };
+    int c = 0;
+    for (; c + 2 < nch; c += 2) {
+        step(c, oa, ob);
+        step(c + 1, ob, oa);
+    }
+    if (c + 1 < nch) {  // two chunks left: c in oa
+        step(c, oa, ob);
+        mmas(ob, -1);
+    } else {  // one chunk left
+        mmas(oa, -1);
     }
     __builtin_amdgcn_s_waitcnt(0);  // the loads past the last chunk land before the workgroup ends
 #pragma unroll

@@ -117,7 +117,8 @@ int chain_heuristic(int n, lb_precision prec, int B) {
             if (fused_kpus(n, prec, &kpu, 1) == 1) return VF_FUSED * 100 + kpu;
             if (B >= 16) {
                 const long long tiles = (long long)((B + 63) / 64) * ((n + 47) / 48);
-                if (tiles >= 240) return VF_TGEMM * 100 + 8;  // about one tile per CU or more
+                if (tiles >= 240)  // about one tile per CU or more; FP32: the ring-pipelined form
+                    return VF_TGEMM * 100 + (prec == LB_C64 ? 1 : 8);
                 return VF_GEMM * 100 + (B <= 256 ? 1 : 2);
             }
             return prec == LB_C128 ? VF_BASELINE * 100 : VF_MATVEC * 100;
