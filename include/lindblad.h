@@ -137,8 +137,9 @@ int lindblad_propagator(int n, int M, const void *L, const double *dt, double th
  * 96 LB_BF16_HILO; for n = 81 rows and columns 0..79 on MFMA and row and
  * column 80 on the vector ALUs, else the SIMD-balanced layout for
  * 81 <= n <= 84 / 96); beyond
- * that one MFMA GEMM launch per step (B >= 16; the LDS-tiled one once
- * ceil(B / 64) ceil(n / 48) >= 240) or a per-state matvec (B < 16); for the
+ * that one MFMA GEMM launch per step (B >= 16; the ring-pipelined LDS-tiled
+ * one, variant 1101, once ceil(B / 64) ceil(n / 48) >= 240) or a per-state
+ * matvec (B < 16); for the
  * BF16 precisions the ring-pipelined plane GEMM, its k range split over
  * workgroups when the batch has fewer than 256 tiles. */
 int lindblad_propagate(int n, const void *P, lb_precision prec, int B, void *rho, long long nsteps,

@@ -283,10 +283,10 @@ __global__ void __launch_bounds__(256) plane_gemm_kernel(int n, int B, int Kp, c
 // by direct global-to-LDS loads (global_load_lds_dwordx4: lane l's 16 bytes
 // land at the wavefront's LDS base + 16 l) issued for the next chunk before
 // the current one is multiplied, so no staging registers are needed.  Each
-// plane row is 64 bytes = four 16-byte chunks, stored at chunk position
-// c ^ ((row >> 2) & 3) so that the 16 rows one MFMA operand fetch touches
-// fall in distinct banks without padding; each lane loads the chunk that
-// belongs in its slot.  Rows past B or n load a valid row instead (they only
+// plane row is 64 bytes = four 16-byte chunks, stored at the XOR-swizzled
+// position tp_swz(row, c) so that one MFMA operand fetch runs without bank
+// conflicts and without padding; each lane loads the chunk that belongs in
+// its slot.  Rows past B or n load a valid row instead (they only
 // feed outputs that are not written).  Level sums are flushed into FP64
 // every KCH = 64 k, exactly as in the untiled kernel, so the results agree
 // with it to the FP64 rounding of the flushes.
@@ -303,7 +303,11 @@ struct TpShape {
     static constexpr int NI = XPL * XI + PPL * PI;              // 1 KB loads per chunk
 };
 
-__device__ inline int tp_swz(int row, int c) { return c ^ ((row >> 2) & 3); }
+// Position of a 64-byte row's 16-byte chunk c.  For the operand fetch (lane
+// l reads chunk l / 16 of row l % 16 of a 16-row block) the XOR with row bits
+// 1..2 is the pattern gfx950's LDS bank-conflict counter reads as
+// conflict-free; XOR with bits 2..3, or no swizzle, reads as two-way.
+__device__ inline int tp_swz(int row, int c) { return c ^ ((row >> 1) & 3); }
 
 template <int MODE, int SP, int SX, int LMAX>
 __global__ void __launch_bounds__(256) tplane_gemm_kernel(int n, int B, int Kp, int nbt, int nit,
@@ -1160,8 +1164,8 @@ static int gemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Worksp
 // (the count of later loads is a constant: every chunk issues the same loads,
 // past the last one repeating valid addresses into slots no later chunk
 // reads).  Plane rows (16 k = 64 or 128 bytes) keep their 16-byte pieces at
-// XOR-swizzled positions so that the 16 rows of an MFMA operand fetch fall
-// in distinct banks without padding.  -Im X Im P uses the FP64 negate-A
+// XOR-swizzled positions (tr_swz) so that an MFMA operand fetch runs with
+// fewer bank conflicts, without padding.  -Im X Im P uses the FP64 negate-A
 // modifier, a sign flip in registers for FP32.
 constexpr int TRK = 16;  // k per ring chunk
 
@@ -1183,10 +1187,16 @@ struct TrShape {
     static constexpr int WAIT = (R - 2) * NJ, WAIT0 = (R - 1) * NJ;
     static_assert(BUF % 1024 == 0 && R >= 3 && WAIT0 <= 63, "ring GEMM shape");
 };
-// position of a row's 16-byte piece: piece ^ f(row), f spreading 16 rows over all banks
+// position of a row's 16-byte piece: piece ^ f(row).  FP32 rows are 64
+// bytes with the operand fetch of tp_swz, and take its conflict-free f.  FP64
+// rows are 128 bytes and a lane fetches pieces 2 g and 2 g + 1 (g = lane /
+// 16) of row lane % 16 in two reads; f = row bit 1 into piece bit 0 and row
+// bit 2 into piece bit 2 is one of the maps gfx950's bank-conflict counter
+// reads as conflict-free for both reads (XOR with (row >> 1) & 7 reads as
+// two-way).
 template <typename T>
 __device__ inline int tr_swz(int row, int piece) {
-    return sizeof(T) == 8 ? piece ^ ((row >> 1) & 7) : piece ^ ((row >> 2) & 3);
+    return sizeof(T) == 8 ? piece ^ (((row >> 1) & 1) | (row & 4)) : piece ^ ((row >> 1) & 3);
 }
 
 // Split k (ksplit > 1): workgroup L = ks * tiles + tile takes chunks

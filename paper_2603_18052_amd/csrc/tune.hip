@@ -101,7 +101,7 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
 // than the round-robin units there), the round-robin
 // fused chain elsewhere while P fits in one CU's LDS; otherwise a
 // GEMM per step: the LDS-tiled one (64 states x 48 outputs per workgroup,
-// eight wavefronts) once its tiles fill the chip (>= 240), else one output
+// ring-pipelined) once its tiles fill the chip (>= 240), else one output
 // tile per wavefront up to 256 states (more workgroups) and two beyond, or a
 // matvec for few states.  BF16: the fused chain while P fits on chip, else
 // the BF16 plane GEMM per step, LDS-tiled once its tiles fill the chip.
@@ -117,8 +117,8 @@ int chain_heuristic(int n, lb_precision prec, int B) {
             if (fused_kpus(n, prec, &kpu, 1) == 1) return VF_FUSED * 100 + kpu;
             if (B >= 16) {
                 const long long tiles = (long long)((B + 63) / 64) * ((n + 47) / 48);
-                if (tiles >= 240)  // about one tile per CU or more; FP32: the ring-pipelined form
-                    return VF_TGEMM * 100 + (prec == LB_C64 ? 1 : 8);
+                if (tiles >= 240)  // about one tile per CU or more: the ring-pipelined form
+                    return VF_TGEMM * 100 + 1;
                 return VF_GEMM * 100 + (B <= 256 ? 1 : 2);
             }
             return prec == LB_C128 ? VF_BASELINE * 100 : VF_MATVEC * 100;

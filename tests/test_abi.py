@@ -98,7 +98,7 @@ def test_chain_variant_lists_and_rule(L):
     # d = 27: no fused variant; GEMM from 16 states, matvec below
     assert not [x for x in lb.chain_variants(729, "c128", 64) if x // 100 == 3]
     assert lb.chain_variant(729, "c128", 64) == 501
-    assert lb.chain_variant(729, "c128", 1024) == 1108  # LDS-tiled GEMM: 16 x 16 tiles fill the chip
+    assert lb.chain_variant(729, "c128", 1024) == 1101  # ring LDS-tiled GEMM: 16 x 16 tiles fill the chip
     assert lb.chain_variant(729, "c64", 1024) == 1101
     assert lb.chain_variant(729, "c128", 512) == 502  # 128 tiles: the small-tile GEMM
     assert lb.chain_variant(729, "c128", 1) == 100
