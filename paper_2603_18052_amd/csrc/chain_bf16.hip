@@ -75,7 +75,11 @@ __host__ __device__ inline Shape shape(int n) {
     s.KS = s.Kp / KSTEP;
     s.mtiles = (n + 15) / 16;
     s.units = s.mtiles * s.KS;
-    s.stride = s.Kp + 8;  // 16 B pad: conflict-free 16-lane row reads
+    // 32-byte pad: rows 32 bytes off a multiple of 64 bytes, the stride at
+    // which gfx950's bank-conflict counter reads the operand fetch (16 B of
+    // row l % 16 at piece l / 16) as conflict-free; a 16-byte pad reads as
+    // two-way
+    s.stride = s.Kp + 16;
     return s;
 }
 
