@@ -167,42 +167,59 @@ __global__ void __launch_bounds__(WAVES * 64) bf16_chain_kernel(int n, const cd 
         }
     }
 
-    // ---- elements owned by this thread in the combine / slice phases
-    constexpr int EPT = (MAXN_HILO * NS + WAVES * 64 - 1) / (WAVES * 64);  // 8
+    // ---- elements owned by this thread in the combine / slice phases: pairs
+    // of consecutive k of one state, so that the slicing phase writes each
+    // digit plane as one 4-byte word (two BF16) per lane.  Register i holds
+    // pair q = tid + (i / 2) * 256 (state q % 16, k = 2 (q / 16) + i % 2);
+    // every pair of a thread belongs to the same state tid % 16.
+    constexpr int EPT = 2 * ((MAXN_HILO / 2 * NS + WAVES * 64 - 1) / (WAVES * 64));  // 6
     double yr[EPT], yi[EPT];
-    const int nel = n * NS;
+    const int npair = (n + 1) / 2 * NS;
+    const int es = tid % NS;  // this thread's state
+    auto elem_k = [&](int i) { return 2 * ((tid + (i >> 1) * WAVES * 64) / NS) + (i & 1); };
+    auto elem_ok = [&](int i) { return tid + (i >> 1) * WAVES * 64 < npair && elem_k(i) < n; };
 
     // slice y (registers) into the state digit planes, given exponents
     auto slice_out = [&]() {
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = tid + i * WAVES * 64;
-            if (e < nel) {
-                const int k = e / NS, s = e - (e / NS) * NS;
-                unsigned short *base = xdig + (size_t)s * sh.stride + k;
+        for (int i = 0; i < EPT; i += 2) {
+            if (tid + (i >> 1) * WAVES * 64 < npair) {
+                const int k = elem_k(i);  // even
+                const bool hi_ok = k + 1 < n;
+                unsigned *base = reinterpret_cast<unsigned *>(xdig + (size_t)es * sh.stride + k);
+                // the two BF16 of a word: element k in the low half, k + 1 in the high half
+                auto put = [&](int pl, unsigned short lo, unsigned short hi) {
+                    base[(size_t)pl * plane / 2] = (unsigned)lo | ((unsigned)(hi_ok ? hi : 0) << 16);
+                };
                 if (MODE == SLICED) {
-                    const int ex = sexp[s];
-                    double vr = ldexp(yr[i], -ex), vi = ldexp(yi[i], -ex);
+                    const int ex = sexp[es];
+                    double vr0 = ldexp(yr[i], -ex), vi0 = ldexp(yi[i], -ex);
+                    double vr1 = ldexp(yr[i + 1], -ex), vi1 = ldexp(yi[i + 1], -ex);
 #pragma unroll
                     for (int b = 0; b < XD; ++b) {
-                        const double dr = rint(vr * 256.0), di = rint(vi * 256.0);
-                        vr = vr * 256.0 - dr;
-                        vi = vi * 256.0 - di;
-                        base[(b * 3 + 0) * plane] = bf16_bits((float)dr);
-                        base[(b * 3 + 1) * plane] = bf16_bits((float)di);
-                        base[(b * 3 + 2) * plane] = bf16_bits((float)-di);
+                        const double dr0 = rint(vr0 * 256.0), di0 = rint(vi0 * 256.0);
+                        const double dr1 = rint(vr1 * 256.0), di1 = rint(vi1 * 256.0);
+                        vr0 = vr0 * 256.0 - dr0;
+                        vi0 = vi0 * 256.0 - di0;
+                        vr1 = vr1 * 256.0 - dr1;
+                        vi1 = vi1 * 256.0 - di1;
+                        put(b * 3 + 0, bf16_bits((float)dr0), bf16_bits((float)dr1));
+                        put(b * 3 + 1, bf16_bits((float)di0), bf16_bits((float)di1));
+                        put(b * 3 + 2, bf16_bits((float)-di0), bf16_bits((float)-di1));
                     }
                 } else {
-                    const float fr = (float)yr[i], fi = (float)yi[i];
-                    const unsigned short hr = bf16_bits(fr), hi = bf16_bits(fi);
-                    const float lr = fr - bf16_float(hr), li = fi - bf16_float(hi);
-                    base[0 * plane] = hr;
-                    base[1 * plane] = hi;
-                    base[2 * plane] = hi ^ 0x8000u;
-                    const unsigned short blr = bf16_bits(lr), bli = bf16_bits(li);
-                    base[3 * plane] = blr;
-                    base[4 * plane] = bli;
-                    base[5 * plane] = bli ^ 0x8000u;
+                    unsigned short h[2][6];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const float fr = (float)yr[i + q], fi = (float)yi[i + q];
+                        const unsigned short hr = bf16_bits(fr), hi = bf16_bits(fi);
+                        const float lr = fr - bf16_float(hr), li = fi - bf16_float(hi);
+                        const unsigned short blr = bf16_bits(lr), bli = bf16_bits(li);
+                        h[q][0] = hr, h[q][1] = hi, h[q][2] = hi ^ 0x8000u;
+                        h[q][3] = blr, h[q][4] = bli, h[q][5] = bli ^ 0x8000u;
+                    }
+#pragma unroll
+                    for (int pl = 0; pl < 6; ++pl) put(pl, h[0][pl], h[1][pl]);
                 }
             }
         }
@@ -210,15 +227,11 @@ __global__ void __launch_bounds__(WAVES * 64) bf16_chain_kernel(int n, const cd 
     // per-state max of |Re|, |Im| over this thread's elements -> LDS max
     auto state_max = [&]() {
         if (MODE == SLICED) {
+            double m = 0.0;
 #pragma unroll
-            for (int i = 0; i < EPT; ++i) {
-                const int e = tid + i * WAVES * 64;
-                if (e < nel) {
-                    const int s = e - (e / NS) * NS;
-                    const double m = fmax(fabs(yr[i]), fabs(yi[i]));
-                    atomicMax(smax + s, (unsigned long long)__double_as_longlong(m));
-                }
-            }
+            for (int i = 0; i < EPT; ++i)
+                if (elem_ok(i)) m = fmax(m, fmax(fabs(yr[i]), fabs(yi[i])));
+            if (tid < npair) atomicMax(smax + es, (unsigned long long)__double_as_longlong(m));
         }
     };
 
@@ -228,10 +241,9 @@ __global__ void __launch_bounds__(WAVES * 64) bf16_chain_kernel(int n, const cd 
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-        const int e = tid + i * WAVES * 64;
         yr[i] = yi[i] = 0.0;
-        if (e < nel) {
-            const int k = e / NS, s = e - (e / NS) * NS;
+        if (elem_ok(i)) {
+            const int k = elem_k(i), s = es;
             if (b0 + s < B) {
                 const cd v = rho[(size_t)(b0 + s) * n + k];
                 yr[i] = MODE == SLICED ? v.re : (double)(float)v.re;
@@ -301,9 +313,8 @@ __global__ void __launch_bounds__(WAVES * 64) bf16_chain_kernel(int n, const cd 
         // ---- combine the k-step slots of every tile (fixed order)
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
-            const int e = tid + i * WAVES * 64;
-            if (e < nel) {
-                const int k = e / NS, s = e - (e / NS) * NS;
+            if (elem_ok(i)) {
+                const int k = elem_k(i), s = es;
                 const int tt = k >> 4, o = (k & 15) * 16 + s;
                 double vr = 0.0, vi = 0.0;
                 for (int q = 0; q < sh.KS; ++q) {
@@ -332,9 +343,8 @@ __global__ void __launch_bounds__(WAVES * 64) bf16_chain_kernel(int n, const cd 
     if (nsteps == 0) return;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-        const int e = tid + i * WAVES * 64;
-        if (e < nel) {
-            const int k = e / NS, s = e - (e / NS) * NS;
+        if (elem_ok(i)) {
+            const int k = elem_k(i), s = es;
             if (b0 + s < B) rho[(size_t)(b0 + s) * n + k] = {yr[i], yi[i]};
         }
     }
