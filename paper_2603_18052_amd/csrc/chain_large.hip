@@ -856,8 +856,9 @@ __global__ void __launch_bounds__(256) gemm_step_kernel(int n, int B, int Kp, co
 // CU) so that each operand byte fetched feeds 48 or 64 products instead of
 // 16 or 32.  Wavefront w % 4 owns states 16 (w % 4) .. + 15 of the tile
 // against all 48 outputs (three MFMA blocks).  k advances KC = 32 at a time
-// through two LDS buffers (row-major planes, rows padded so that the 16 rows
-// one MFMA operand fetch touches fall in distinct banks); the next chunk is
+// through two LDS buffers (row-major planes, rows padded by 16 bytes; the
+// bank-conflict counter still reads this kernel's LDS traffic as partly
+// conflicted, about 2.7 stall cycles per LDS instruction); the next chunk is
 // loaded into registers while the current one is multiplied.  With WPB = 8
 // the two wavefronts of a SIMD take alternate 16-deep halves of every chunk
 // and the second adds its partial sums through LDS once at the end.  Each
@@ -871,7 +872,7 @@ constexpr int TGB = 64, TGI = 48, TGK = 32;
 
 template <typename T, int WPB>
 struct TgShape {
-    static constexpr int PAD = 16 / sizeof(T);  // keeps 16-byte row alignment, spreads banks
+    static constexpr int PAD = 16 / sizeof(T);  // keeps 16-byte row alignment
     static constexpr int LD = TGK + PAD;
     static constexpr int XPL = sizeof(T) == 8 ? 2 : 3;  // X planes in LDS: re, im (, -im)
     static constexpr int XS = TGB * LD, PS = TGI * LD;  // plane sizes in T
@@ -1164,8 +1165,8 @@ static int gemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Worksp
 // (the count of later loads is a constant: every chunk issues the same loads,
 // past the last one repeating valid addresses into slots no later chunk
 // reads).  Plane rows (16 k = 64 or 128 bytes) keep their 16-byte pieces at
-// XOR-swizzled positions (tr_swz) so that an MFMA operand fetch runs with
-// fewer bank conflicts, without padding.  -Im X Im P uses the FP64 negate-A
+// XOR-swizzled positions (tr_swz) so that an MFMA operand fetch runs without
+// bank conflicts and without padding.  -Im X Im P uses the FP64 negate-A
 // modifier, a sign flip in registers for FP32.
 constexpr int TRK = 16;  // k per ring chunk
 
