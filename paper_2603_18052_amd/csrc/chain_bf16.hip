@@ -34,6 +34,7 @@ namespace lb {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
 
 namespace bfc {
 
@@ -106,7 +107,7 @@ __global__ void __launch_bounds__(WAVES * 64) bf16_chain_kernel(int n, const cd 
     extern __shared__ __align__(16) unsigned char smem[];
     const Shape sh = shape(n);
     unsigned short *xdig = reinterpret_cast<unsigned short *>(smem);  // [XD][3][NS][stride]
-    double *slots = reinterpret_cast<double *>(smem + (size_t)XD * 3 * NS * sh.stride * 2);  // [units][2][256]
+    double *slots = reinterpret_cast<double *>(smem + (size_t)XD * 3 * NS * sh.stride * 2);  // [units][4][64] x {Re, Im}
     unsigned long long *smax = reinterpret_cast<unsigned long long *>(slots + (size_t)sh.units * 512);  // [NS]
     int *sexp = reinterpret_cast<int *>(smax + NS);        // [NS]
     int *pexp = sexp + NS + 48;                            // [mtiles*16]
@@ -293,7 +294,10 @@ __global__ void __launch_bounds__(WAVES * 64) bf16_chain_kernel(int n, const cd 
                             ai[Lq] = mma(pf[j][a][1], xf[b][0], ai[Lq]);
                         }
                     }
-                double *slot = slots + (size_t)u * 512;
+                // the unit's partial tile, lane-major: register r of lane l (row
+                // 4 (l / 16) + r, state l % 16) at pair r * 64 + l, {Re, Im}
+                // together, so that each register is one contiguous 1 KB write
+                d2v *slot = reinterpret_cast<d2v *>(slots) + (size_t)u * 256;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     double vr = 0.0, vi = 0.0;
@@ -303,9 +307,7 @@ __global__ void __launch_bounds__(WAVES * 64) bf16_chain_kernel(int n, const cd 
                         vr = fma((double)ar[L][r], w, vr);
                         vi = fma((double)ai[L][r], w, vi);
                     }
-                    const int o = (4 * (lane >> 4) + r) * 16 + (lane & 15);
-                    slot[o] = vr;
-                    slot[256 + o] = vi;
+                    slot[r * 64 + lane] = d2v{vr, vi};
                 }
             }
         }
@@ -315,12 +317,13 @@ __global__ void __launch_bounds__(WAVES * 64) bf16_chain_kernel(int n, const cd 
         for (int i = 0; i < EPT; ++i) {
             if (elem_ok(i)) {
                 const int k = elem_k(i), s = es;
-                const int tt = k >> 4, o = (k & 15) * 16 + s;
+                // row k % 16 of the tile = register (k % 16) % 4 of lane 16 ((k % 16) / 4) + s
+                const int tt = k >> 4, o = ((k & 15) & 3) * 64 + 16 * ((k & 15) >> 2) + s;
                 double vr = 0.0, vi = 0.0;
                 for (int q = 0; q < sh.KS; ++q) {
-                    const double *slot = slots + (size_t)(tt * sh.KS + q) * 512;
-                    vr += slot[o];
-                    vi += slot[256 + o];
+                    const d2v v = reinterpret_cast<const d2v *>(slots)[(size_t)(tt * sh.KS + q) * 256 + o];
+                    vr += v[0];
+                    vi += v[1];
                 }
                 if (MODE == SLICED) {
                     const int sc = pexp[k] + sexp[s];
