@@ -49,44 +49,79 @@ PATH_UNIT = {  # arithmetic unit and peak of each chain variant
 TARGET_TD = {"c128": 1e-12, "c64": 1e-6, "bf16_hilo": 1e-6, "bf16_sliced": 1e-6}
 
 
+def paper_step_cost(d):
+    """The paper's per-step cost model, Eq. (4), for one state at Hilbert
+    dimension d (n = d^2): 8 d^4 flops (a complex multiply-add counted as
+    eight real operations) and 16 (d^4 + 2 d^2) bytes (P plus the input and
+    output state in complex FP64).  Returns (flops, bytes)."""
+    n = d * d
+    return 8.0 * n * n, 16.0 * (n * n + 2 * n)
+
+
+def cpu_model():
+    """The host CPU's model name (first "model name" of /proc/cpuinfo, as
+    lscpu reports it) and the number of logical CPUs."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
 def cpu_baseline_leg(cfg, Pn, B, n, N, sample_idx, cpu_seconds):
     """The CPU oracle on this host's cores: (a) its throughput on a bounded
     sample of the headline workload (assembly, FP64 Pade-13 build and Bs
-    states x Ns steps, sized to about cpu_seconds), reported as cpu_baseline;
-    (b) its chain from the GPU's P on the sampled states, which gives the FP64
-    path's error.  The only place the benchmark runs the oracle."""
+    states x Ns steps, one trial sized to about cpu_seconds / 5; the median
+    of 5 trials after one warm-up), reported as cpu_baseline; (b) its chain
+    from the GPU's P on the sampled states, which gives the FP64 path's
+    error.  The only place the benchmark runs the oracle."""
     import oracle
     nthreads = oracle.max_threads()
     X = cfg["rho0"].reshape(B, n)
     ref = oracle.propagate(Pn, X[sample_idx], N, nthreads=nthreads)
+    trials = 5
     t0 = time.perf_counter()
     Ph = oracle.propagator(oracle.liouvillian(cfg["H"], cfg["Lk"]), cfg["dt"])
-    Bs, Ns = 256, 50
-    oracle.propagate(Ph, X[:Bs], Ns, nthreads=nthreads)
+    Bs, Ns = 256, 20
+    oracle.propagate(Ph, X[:Bs], Ns, nthreads=nthreads)  # also the warm-up
     t_probe = time.perf_counter() - t0
-    scale = max(1.0, cpu_seconds / max(t_probe, 1e-3))
+    scale = max(1.0, cpu_seconds / trials / max(t_probe, 1e-3))
     Ns_want = Ns * scale  # grow the step count first, then the state count
     Ns = int(min(N, Ns_want))
     Bs = int(min(B, Bs * max(1.0, Ns_want / Ns)))
-    t0 = time.perf_counter()
-    Ph = oracle.propagator(oracle.liouvillian(cfg["H"], cfg["Lk"]), cfg["dt"])
-    oracle.propagate(Ph, X[:Bs], Ns, nthreads=nthreads)
-    t_cpu = time.perf_counter() - t0
+    times = []
+    for _ in range(trials):
+        t0 = time.perf_counter()
+        Ph = oracle.propagator(oracle.liouvillian(cfg["H"], cfg["Lk"]), cfg["dt"])
+        oracle.propagate(Ph, X[:Bs], Ns, nthreads=nthreads)
+        times.append(time.perf_counter() - t0)
+    t_cpu = sorted(times)[trials // 2]
+    model, ncpu = cpu_model()
     cpu = {"value": Bs * Ns / t_cpu, "unit": "state-steps/s", "cores": nthreads, "kind": "oracle",
+           "cpu_model": model, "logical_cpus": ncpu,
            "sample": f"d=9 assembly + FP64 Pade-13 build + {Bs} states x {Ns} steps (of {B} x {N}), "
-                     f"OpenMP over states, {t_cpu:.1f} s"}
+                     f"OpenMP over states on {nthreads} threads; median of {trials} trials "
+                     f"({min(times):.2f}-{max(times):.2f} s each)"}
     # the same chain on one thread (states x steps sized to about a quarter
     # of the budget; the build is not repeated): the single-core rate
     B1, N1 = 8, 50
     t0 = time.perf_counter()
     oracle.propagate(Ph, X[:B1], N1, nthreads=1)
     t1 = time.perf_counter() - t0
-    N1 = int(min(N, max(N1, N1 * 0.25 * cpu_seconds / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.propagate(Ph, X[:B1], N1, nthreads=1)
-    t1 = time.perf_counter() - t0
+    N1 = int(min(N, max(N1, N1 * 0.25 * cpu_seconds / trials / max(t1, 1e-3))))
+    times = []
+    for _ in range(trials):
+        t0 = time.perf_counter()
+        oracle.propagate(Ph, X[:B1], N1, nthreads=1)
+        times.append(time.perf_counter() - t0)
+    t1 = sorted(times)[trials // 2]
     cpu["value_1_thread"] = B1 * N1 / t1
-    cpu["sample_1_thread"] = f"{B1} states x {N1} steps on one thread, {t1:.1f} s"
+    cpu["sample_1_thread"] = f"{B1} states x {N1} steps on one thread, median of {trials} trials, {t1:.2f} s"
     return cpu, ref
 
 
@@ -270,8 +305,10 @@ def timing_models_section(lb, W, torch, dev):
 
 def fixed_point_section(lb, W, torch, dev, ws):
     """Alg. 5 on the GPU (LB_Q15): the paper's d = 3 fixed-point drift model
-    from |0><0|, trace distance / trace loss / |delta p1| against the FP64
-    chain after 1 ... 1e4 steps, and the fixed-point chain's rate."""
+    from |0><0|, trace distance / trace loss |Re Tr rho - 1| / |delta p1|
+    against the FP64 chain after 1 ... 1e4 steps (the columns of the paper's
+    board-drift table; Im Tr rho reported beside them), and the fixed-point
+    chain's rate."""
     out = {}
     for name, drive in (("undriven", 0.0), ("driven", 0.05)):
         H, Lk, dt, rho0 = W.paper_fixed_point_model(drive)
@@ -284,7 +321,8 @@ def fixed_point_section(lb, W, torch, dev, ws):
             lb.propagate(P, xd, N, "c128", ws=ws)
             q, r = xq.cpu().numpy().reshape(3, 3), xd.cpu().numpy().reshape(3, 3)
             rows[f"N{N}"] = {"trace_distance": float(trace_distance(q[None], r[None])[0]),
-                             "trace_loss": float(abs(np.trace(q) - 1.0)),
+                             "trace_loss": float(abs(np.trace(q).real - 1.0)),
+                             "im_trace": float(np.trace(q).imag),
                              "abs_delta_p1": float(abs(q[1, 1].real - r[1, 1].real))}
         out[name] = rows
     # rates: one state at d = 3 (one wavefront), 4096 states at d = 9 (per-row matvec)
@@ -556,7 +594,7 @@ def main():
     bound, peak_key, dtype = PATH_UNIT.get(prec, ("mfma", "fp64_tflops", "f64"))
     variant = 100 if prec == "baseline" else lb.chain_variant(n, prec, B)
     kernel_name = kernel_of(variant, prec)
-    flops = 8.0 * n * n * B * N  # algorithmic: 8 n^2 per state-step (paper Eq. (4))
+    flops = paper_step_cost(d)[0] * B * N  # algorithmic: 8 n^2 per state-step (paper Eq. (4))
     achieved = flops / chain_s / 1e12
     roofline = {"bound": bound, "achieved": achieved, "peak": PEAKS[peak_key], "unit": "TFLOP/s",
                 "frac": achieved / PEAKS[peak_key], "traffic": _traffic(kernel_name),

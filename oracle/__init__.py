@@ -66,6 +66,8 @@ def lib():
             "orc_max_threads": (i, []),
             "orc_quantize_q15": (None, [ll, p, p, p]),
             "orc_propagate_q15": (None, [i, p, p, i, p, p, ll]),
+            "orc_quantize_q31": (None, [ll, p, p, p]),
+            "orc_propagate_q31": (None, [i, p, p, i, p, p, ll]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -256,6 +258,33 @@ def propagate_q15(P, rho, nsteps):
 
 def from_q15(re, im):
     return (np.asarray(re, dtype=np.float64) + 1j * np.asarray(im, dtype=np.float64)) / 32768.0
+
+
+# ------------------------------------------------------------ Alg. 5 (Q1.31)
+def quantize_q31(z):
+    """Q1.31 codes (re, im) int32 of complex values: round to nearest, saturate."""
+    z = _c(z)
+    re = np.empty(z.shape, dtype=np.int32)
+    im = np.empty(z.shape, dtype=np.int32)
+    lib().orc_quantize_q31(z.size, _p(z), _p(re), _p(im))
+    return re, im
+
+
+def propagate_q31(P, rho, nsteps):
+    """The fixed-point chain at 31 fractional bits: P and rho (B, n) or
+    (B, d, d) quantised to Q1.31, nsteps exact-integer steps (128-bit sums)
+    with floor truncation and saturation; returns the codes (re, im) int32."""
+    P = _c(P)
+    n = P.shape[0]
+    x = _c(rho).reshape(-1, n)
+    Pr, Pi = quantize_q31(P)
+    xr, xi = quantize_q31(x)
+    lib().orc_propagate_q31(n, _p(Pr), _p(Pi), x.shape[0], _p(xr), _p(xi), int(nsteps))
+    return xr, xi
+
+
+def from_q31(re, im):
+    return (np.asarray(re, dtype=np.float64) + 1j * np.asarray(im, dtype=np.float64)) / 2147483648.0
 
 
 # ------------------------------------------------------------ error metrics

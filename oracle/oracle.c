@@ -11,12 +11,14 @@
  * Propagation for Near-Term Quantum Control" (arXiv 2603.18052).
  *   Eq. (1)  Lindblad master equation                       -> orc_lindblad_rhs
  *   Eqs. (2)-(3)  vec rho(t+dt) = P vec rho(t), P = e^{L dt} -> orc_liouvillian
- *   Alg. 1   Pade [13/13] scaling and squaring, theta = 0.25, LU with partial
- *            pivoting of the denominator                      -> orc_expm_pade13
+ *   Alg. 1   scaling and squaring of the [13/13] Pade approximant,
+ *            theta = 0.25, LU with partial pivoting of the
+ *            denominator                                      -> orc_expm_pade13
  *   Alg. 2   row-major dense complex matvec                   -> orc_matvec
  *   Alg. 3   batch of independent states over threads         -> orc_propagate
- *   Alg. 5   fixed-point (Q1.15) step: exact integer sums,
- *            floor truncation and saturation            -> orc_propagate_q15
+ *   Alg. 5   fixed-point step (Q1.15, and Q1.31 as in the paper's drift
+ *            figure): exact integer sums, floor truncation and
+ *            saturation                   -> orc_propagate_q15, orc_propagate_q31
  * The GRAPE gradient (not in the paper) follows the chain rule with the
  * Frechet derivative of exp taken from the block-triangular identity
  * exp([[A, E], [0, A]]) = [[e^A, L(A,E)], [0, e^A]]   (Van Loan 1978).
@@ -208,15 +210,16 @@ int orc_lu_solve(int n, zc *A, zc *B, int nrhs)
     return ORC_OK;
 }
 
-/* Alg. 1: P = exp(A) by Pade [13/13] with scaling and squaring.  A is the
- * already-scaled generator (L dt).  Lines in order:
- *   s from the 1-norm rule; A <- A / 2^s;
- *   A2 = A A, A4 = A2 A2, A6 = A4 A2;
- *   V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I;
- *   W = A6 (b13 A6 + b11 A4 + b9 A2);
- *   U = A (W + b7 A6 + b5 A4 + b3 A2 + b1 I);
- *   solve (V - U) P = (V + U) by LU with partial pivoting;
- *   s squarings P <- P P.
+/* P = exp(A) for an already scaled generator A = L dt, by the scaling and
+ * squaring method of Alg. 1 around the diagonal [13/13] Pade approximant of
+ * exp (Higham 2005).  With p(X) = sum_k b_k X^k (coefficients above) the
+ * approximant is r(X) = p(-X)^{-1} p(X).  Written as its even part
+ * E(X) = sum_j b_{2j} X^{2j} and odd part O(X) = X sum_j b_{2j+1} X^{2j},
+ * p(X) = E + O and p(-X) = E - O, so one set of even powers of X serves both
+ * polynomials; here they are formed one after another (X^2, X^4, ..., X^12)
+ * and summed term by term, the plain definition of the polynomial.  Then
+ * X = A / 2^s with s the scaling exponent, P = r(X) solved from
+ * (E - O) P = (E + O) by the pivoted LU above, and P squared s times.
  * Returns 0, ORC_ESINGULAR, ORC_ENONFINITE or ORC_ENOMEM; *s_out = s. */
 int orc_expm_pade13(int n, const zc *A0, double theta, zc *P, int *s_out)
 {
@@ -226,36 +229,39 @@ int orc_expm_pade13(int n, const zc *A0, double theta, zc *P, int *s_out)
     int s = orc_scaling_exponent(orc_norm1(n, A0), theta);
     if (s_out) *s_out = s;
     if (s < 0) return ORC_ENONFINITE;
-    zc *A = malloc(nn * sizeof(zc)), *A2 = malloc(nn * sizeof(zc)), *A4 = malloc(nn * sizeof(zc));
-    zc *A6 = malloc(nn * sizeof(zc)), *T = malloc(nn * sizeof(zc)), *V = malloc(nn * sizeof(zc));
-    zc *W = malloc(nn * sizeof(zc)), *U = malloc(nn * sizeof(zc));
-    if (!A || !A2 || !A4 || !A6 || !T || !V || !W || !U) {
-        free(A); free(A2); free(A4); free(A6); free(T); free(V); free(W); free(U);
+    zc *X = malloc(nn * sizeof(zc)), *X2 = malloc(nn * sizeof(zc)), *Pw = malloc(nn * sizeof(zc));
+    zc *T = malloc(nn * sizeof(zc)), *Ev = calloc(nn, sizeof(zc)), *Od = calloc(nn, sizeof(zc));
+    zc *Den = malloc(nn * sizeof(zc));
+    if (!X || !X2 || !Pw || !T || !Ev || !Od || !Den) {
+        free(X); free(X2); free(Pw); free(T); free(Ev); free(Od); free(Den);
         return ORC_ENOMEM;
     }
-    for (size_t e = 0; e < nn; ++e) A[e] = ldexp(creal(A0[e]), -s) + I * ldexp(cimag(A0[e]), -s);
-    mm(n, A, A, A2);
-    mm(n, A2, A2, A4);
-    mm(n, A4, A2, A6);
-    for (size_t e = 0; e < nn; ++e) T[e] = b[12] * A6[e] + b[10] * A4[e] + b[8] * A2[e];
-    mm(n, A6, T, V);
-    for (size_t e = 0; e < nn; ++e) V[e] += b[6] * A6[e] + b[4] * A4[e] + b[2] * A2[e];
-    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] += b[0];
-    for (size_t e = 0; e < nn; ++e) T[e] = b[13] * A6[e] + b[11] * A4[e] + b[9] * A2[e];
-    mm(n, A6, T, W);
-    for (size_t e = 0; e < nn; ++e) T[e] = W[e] + b[7] * A6[e] + b[5] * A4[e] + b[3] * A2[e];
-    for (int i = 0; i < n; ++i) T[(size_t)i * n + i] += b[1];
-    mm(n, A, T, U);
-    /* denominator V - U into A2, numerator V + U into P */
-    for (size_t e = 0; e < nn; ++e) { A2[e] = V[e] - U[e]; P[e] = V[e] + U[e]; }
-    int rc = orc_lu_solve(n, A2, P, n);
+    for (size_t e = 0; e < nn; ++e) X[e] = ldexp(creal(A0[e]), -s) + I * ldexp(cimag(A0[e]), -s);
+    mm(n, X, X, X2);
+    /* Pw runs through X^0, X^2, ..., X^12; Ev collects b_{2j} X^{2j} and Od
+     * (before the final product with X) b_{2j+1} X^{2j}. */
+    memset(Pw, 0, nn * sizeof(zc));
+    for (int i = 0; i < n; ++i) Pw[(size_t)i * n + i] = 1.0;
+    for (int j = 0; j <= 6; ++j) {
+        if (j > 0) {
+            mm(n, Pw, X2, T);
+            memcpy(Pw, T, nn * sizeof(zc));
+        }
+        for (size_t e = 0; e < nn; ++e) {
+            Ev[e] += b[2 * j] * Pw[e];
+            Od[e] += b[2 * j + 1] * Pw[e];
+        }
+    }
+    mm(n, X, Od, T); /* T = O(X) */
+    for (size_t e = 0; e < nn; ++e) { Den[e] = Ev[e] - T[e]; P[e] = Ev[e] + T[e]; }
+    int rc = orc_lu_solve(n, Den, P, n);
     if (rc == ORC_OK) {
         for (int k = 0; k < s; ++k) {
             mm(n, P, P, T);
             memcpy(P, T, nn * sizeof(zc));
         }
     }
-    free(A); free(A2); free(A4); free(A6); free(T); free(V); free(W); free(U);
+    free(X); free(X2); free(Pw); free(T); free(Ev); free(Od); free(Den);
     return rc;
 }
 
@@ -556,6 +562,62 @@ void orc_propagate_q15(int n, const int16_t *Pr, const int16_t *Pi, int B, int16
             for (int i = 0; i < n; ++i) {
                 vr[i] = sat16(floor_div_2_15(ar[i]));
                 vi[i] = sat16(floor_div_2_15(ai[i]));
+            }
+        }
+    }
+    free(ar);
+    free(ai);
+}
+
+/* ------------------------------------------------------------ Alg. 5, Q1.31
+ * The same step at 31 fractional bits (the paper's Q1.31 drift curve): a
+ * value is the 32-bit integer q with v = q / 2^31; quantisation rounds to
+ * nearest (ties to even) and saturates to [-2^31, 2^31 - 1].  A real
+ * product is Q2.62 and a row's sum needs 66 + ceil(log2 n) bits, so the
+ * sums are held in 128-bit integers; then x_i = sat(floor(acc_i / 2^31)). */
+static int32_t sat32(__int128 v)
+{
+    const __int128 lo = -((__int128)1 << 31), hi = ((__int128)1 << 31) - 1;
+    return (int32_t)(v < lo ? lo : (v > hi ? hi : v));
+}
+
+void orc_quantize_q31(long long count, const zc *src, int32_t *re, int32_t *im)
+{
+    const double lo = -2147483648.0, hi = 2147483647.0;
+    for (long long e = 0; e < count; ++e) {
+        re[e] = (int32_t)fmax(lo, fmin(hi, nearbyint(creal(src[e]) * 2147483648.0)));
+        im[e] = (int32_t)fmax(lo, fmin(hi, nearbyint(cimag(src[e]) * 2147483648.0)));
+    }
+}
+
+static __int128 floor_div_2_31(__int128 a)
+{
+    const __int128 d = (__int128)1 << 31;
+    __int128 q = a / d;
+    if (a % d != 0 && a < 0) q -= 1; /* C division truncates toward zero */
+    return q;
+}
+
+void orc_propagate_q31(int n, const int32_t *Pr, const int32_t *Pi, int B, int32_t *xr, int32_t *xi,
+                       long long nsteps)
+{
+    __int128 *ar = malloc((size_t)n * sizeof(__int128)), *ai = malloc((size_t)n * sizeof(__int128));
+    for (int b = 0; b < B; ++b) {
+        int32_t *vr = xr + (size_t)b * n, *vi = xi + (size_t)b * n;
+        for (long long t = 0; t < nsteps; ++t) {
+            for (int i = 0; i < n; ++i) {
+                __int128 sr = 0, si = 0;
+                for (int j = 0; j < n; ++j) {
+                    const __int128 pr = Pr[(size_t)i * n + j], pi = Pi[(size_t)i * n + j];
+                    sr += pr * vr[j] - pi * vi[j];
+                    si += pr * vi[j] + pi * vr[j];
+                }
+                ar[i] = sr;
+                ai[i] = si;
+            }
+            for (int i = 0; i < n; ++i) {
+                vr[i] = sat32(floor_div_2_31(ar[i]));
+                vi[i] = sat32(floor_div_2_31(ai[i]));
             }
         }
     }
