@@ -22,8 +22,11 @@
  *    the next call on the same thread).  No C++ exception crosses the ABI.
  *  - Scratch memory comes from an lb_workspace.  Passing NULL selects the
  *    library's per-device default workspace (grown on demand, cap 64 GiB).
- *    Calls that share one workspace must be ordered (same stream, or
- *    synchronised by the caller): the workspace is not locked.
+ *    Growth is stream-ordered on the call's stream (the old buffer goes back
+ *    with hipFreeAsync after the work already enqueued there, the new one
+ *    comes from hipMallocAsync) and does not block the host.  Calls that
+ *    share one workspace must be ordered (same stream, or synchronised by the
+ *    caller): the workspace is not locked.
  */
 #ifndef LINDBLAD_H
 #define LINDBLAD_H
@@ -69,9 +72,10 @@ typedef struct lb_workspace lb_workspace;
 
 /* Library-owned device scratch on the current device (the paper's reusable
  * matrix-exponential workspace, Sec. 2 "Reusable Propagator Construction").
- * Memory is allocated on first need and grown up to `max_bytes`; a request
- * beyond the cap fails with LB_ENOMEM.  destroy synchronises the device
- * before freeing.  Thread-compatible, not thread-safe. */
+ * Memory is allocated on first need and grown up to `max_bytes` (stream-
+ * ordered, see above); a request beyond the cap fails with LB_ENOMEM.
+ * destroy synchronises the device before freeing.  Thread-compatible, not
+ * thread-safe. */
 int lb_workspace_create(size_t max_bytes, lb_workspace **ws);
 int lb_workspace_destroy(lb_workspace *ws);
 /* Bytes currently allocated by the workspace (host query, no device work). */
@@ -109,16 +113,24 @@ int lindblad_generators(int n, int M, int C, const void *L0, const void *Lc, con
  * V - U (largest modulus, lowest row on ties) solving for P with the n columns
  * of V + U as right-hand sides, then s squarings.  FP64 throughout.
  *   n      : 1 <= n <= 4096;  M >= 1 generators, L is M x n x n complex128
- *   dt     : HOST array of M step lengths
+ *   dt     : HOST array of M finite step lengths (read before the call
+ *            returns; the values travel to the device as kernel arguments)
  *   theta  : threshold, > 0 (the paper uses 0.25; Higham's is 5.37)
  *   P      : M x n x n complex128 output (may alias nothing else)
- *   s_used : HOST array of M ints receiving s, or NULL
- * Synchronises the host with `stream` twice (the scaling exponents decide the
- * number of squaring launches; the pivots decide the status).  Returns
- * LB_ENONFINITE if some ||A||_1 is not finite and LB_ESINGULAR if some
- * denominator has an exactly zero pivot; P is then unspecified. */
+ *   s_used : DEVICE array of M ints receiving s, or NULL
+ *   status : DEVICE int, or NULL.  The caller sets it to LB_OK (0) before the
+ *            call; the build lowers it (atomic min, so the smallest code
+ *            wins) to LB_ENOTSUP if some s exceeds 24 (||A||_1 > 2^22: the
+ *            squarings are enqueued up to that cap), LB_ENONFINITE if some
+ *            ||A||_1 is not finite, LB_ESINGULAR if some denominator has an
+ *            exactly zero pivot.  P of such a generator is unspecified.
+ * Stream-ordered and asynchronous: nothing blocks the host.  s and the
+ * status stay on the device; the squarings run as masked launches up to the
+ * cap, each skipping on the device the matrices whose s it exceeds.  The
+ * return value covers argument checks, workspace limits and launch errors
+ * only. */
 int lindblad_propagator(int n, int M, const void *L, const double *dt, double theta, void *P,
-                        int *s_used, lb_workspace *ws, hipStream_t stream);
+                        int *s_used, int *status, lb_workspace *ws, hipStream_t stream);
 
 /* The step chain, Alg. 2 applied nsteps times to each of B independent states
  * (Alg. 3 parallelism): rho_b <- P^nsteps rho_b.

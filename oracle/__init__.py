@@ -303,6 +303,19 @@ def rel_fro(X, Xref):
     return np.linalg.norm((X - Xref).ravel()) / np.linalg.norm(Xref.ravel())
 
 
+def rel_per_state(X, Xref):
+    """Largest relative 2-norm error over the states of a batch: the rows of
+    (B, n) arrays ((B, d, d) batches and single (n,) states are accepted), so
+    one bad state cannot hide among good ones as it can in one Frobenius
+    norm over the batch.  A zero reference state counts its absolute error."""
+    X, Xref = np.asarray(X), np.asarray(Xref)
+    B = 1 if X.ndim == 1 else X.shape[0]
+    D = (X - Xref).reshape(B, -1)
+    den = np.linalg.norm(Xref.reshape(B, -1), axis=1)
+    den = np.where(den > 0, den, 1.0)
+    return float((np.linalg.norm(D, axis=1) / den).max())
+
+
 def state_report(rho):
     """Drift metrics of a batch of density matrices (B, d, d)."""
     rho = np.asarray(rho)

@@ -41,14 +41,23 @@ typedef long double complex lzc;
 #define ORC_ENONFINITE (-6)
 
 /* ------------------------------------------------------------------ basics */
-static void mm(int n, const zc *A, const zc *B, zc *C) /* C = A B, n x n */
+/* C = A B, n x n.  Every entry is the plain sum over k in ascending order;
+ * the loops run k outside j so that rows of B are read contiguously, and
+ * rows of C are independent, so they are shared over threads. */
+static void mm(int n, const zc *A, const zc *B, zc *C)
 {
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
-            zc acc = 0;
-            for (int k = 0; k < n; ++k) acc += A[(size_t)i * n + k] * B[(size_t)k * n + j];
-            C[(size_t)i * n + j] = acc;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (n >= 128)
+#endif
+    for (int i = 0; i < n; ++i) {
+        zc *c = C + (size_t)i * n;
+        for (int j = 0; j < n; ++j) c[j] = 0;
+        for (int k = 0; k < n; ++k) {
+            const zc a = A[(size_t)i * n + k];
+            const zc *b = B + (size_t)k * n;
+            for (int j = 0; j < n; ++j) c[j] += a * b[j];
         }
+    }
 }
 
 /* Eq. (1) applied to one d x d matrix rho, by plain matrix arithmetic:
@@ -186,26 +195,27 @@ int orc_lu_solve(int n, zc *A, zc *B, int nrhs)
             }
         }
         zc piv = A[(size_t)k * n + k];
-        for (int i = k + 1; i < n; ++i) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (n - k >= 256)
+#endif
+        for (int i = k + 1; i < n; ++i) { /* rows are independent */
             zc l = A[(size_t)i * n + k] / piv;
             A[(size_t)i * n + k] = l;
             for (int j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= l * A[(size_t)k * n + j];
         }
     }
-    /* forward substitution with the unit lower factor */
-    for (int i = 0; i < n; ++i)
-        for (int k = 0; k < i; ++k) {
-            zc l = A[(size_t)i * n + k];
-            for (int j = 0; j < nrhs; ++j) B[(size_t)i * nrhs + j] -= l * B[(size_t)k * nrhs + j];
+    /* forward substitution with the unit lower factor, then back substitution
+     * with U; the right-hand-side columns are independent */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (nrhs >= 128)
+#endif
+    for (int j = 0; j < nrhs; ++j) {
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < i; ++k) B[(size_t)i * nrhs + j] -= A[(size_t)i * n + k] * B[(size_t)k * nrhs + j];
+        for (int i = n - 1; i >= 0; --i) {
+            for (int k = i + 1; k < n; ++k) B[(size_t)i * nrhs + j] -= A[(size_t)i * n + k] * B[(size_t)k * nrhs + j];
+            B[(size_t)i * nrhs + j] /= A[(size_t)i * n + i];
         }
-    /* back substitution with U */
-    for (int i = n - 1; i >= 0; --i) {
-        for (int k = i + 1; k < n; ++k) {
-            zc u = A[(size_t)i * n + k];
-            for (int j = 0; j < nrhs; ++j) B[(size_t)i * nrhs + j] -= u * B[(size_t)k * nrhs + j];
-        }
-        zc d = A[(size_t)i * n + i];
-        for (int j = 0; j < nrhs; ++j) B[(size_t)i * nrhs + j] /= d;
     }
     return ORC_OK;
 }

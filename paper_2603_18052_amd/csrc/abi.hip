@@ -28,36 +28,44 @@ int check_launch(const char *what) {
 }
 
 // ------------------------------------------------------------ workspace
-void ws_begin(Workspace *ws) { ws->used = 0; }
+void ws_begin(Workspace *ws, hipStream_t s) {
+    ws->used = 0;
+    ws->stream = s;
+}
 
 int ws_ensure(Workspace *ws, size_t bytes) {
     bytes = align256(bytes);
     if (ws->used + bytes <= ws->size) return LB_OK;
+    if (ws->fixed)
+        return fail(LB_ENOMEM, "workspace: need " + std::to_string(ws->used + bytes) +
+                                   " bytes of the fixed scratch of " + std::to_string(ws->size));
     if (ws->used != 0)
         return fail(LB_ENOMEM, "workspace: nested request of " + std::to_string(bytes) +
                                    " bytes exceeds the reservation");
     if (bytes > ws->cap)
         return fail(LB_ENOMEM, "workspace: need " + std::to_string(bytes) + " bytes, cap is " +
                                    std::to_string(ws->cap));
+    // stream-ordered: the old buffer is released after the work already
+    // enqueued on this call's stream, the new one is valid from here on it
     if (ws->base) {
-        LB_HIP(hipDeviceSynchronize());
-        LB_HIP(hipFree(ws->base));
+        LB_HIP(hipFreeAsync(ws->base, ws->stream));
         ws->base = nullptr;
         ws->size = 0;
     }
     size_t grow = bytes + bytes / 4;
     if (grow > ws->cap) grow = ws->cap;
     void *p = nullptr;
-    if (hipMalloc(&p, grow) != hipSuccess) {
+    if (hipMallocAsync(&p, grow, ws->stream) != hipSuccess) {
         (void)hipGetLastError();
-        if (hipMalloc(&p, bytes) != hipSuccess) {
+        if (hipMallocAsync(&p, bytes, ws->stream) != hipSuccess) {
             (void)hipGetLastError();
-            return fail(LB_ENOMEM, "workspace: hipMalloc of " + std::to_string(bytes) + " bytes failed");
+            return fail(LB_ENOMEM, "workspace: hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
         }
         grow = bytes;
     }
     ws->base = static_cast<char *>(p);
     ws->size = grow;
+    ws->alloc_stream = ws->stream;
     return LB_OK;
 }
 
@@ -185,7 +193,8 @@ int lb_workspace_destroy(lb_workspace *ws) {
     Workspace *w = reinterpret_cast<Workspace *>(ws);
     if (w->base) {
         LB_HIP(hipDeviceSynchronize());
-        LB_HIP(hipFree(w->base));
+        LB_HIP(hipFreeAsync(w->base, w->alloc_stream));
+        LB_HIP(hipDeviceSynchronize());
     }
     delete w;
     return LB_OK;

@@ -397,7 +397,7 @@ extern "C" int lindblad_batch_run(const lb_problem *probs, int nprob, lb_precisi
         if (std::find(sizes.begin(), sizes.end(), p.d) == sizes.end()) sizes.push_back(p.d);
     }
     Workspace *w = ws_resolve(ws);
-    ws_begin(w);
+    ws_begin(w, stream);
     std::sort(sizes.begin(), sizes.end());
     for (int d : sizes) {
         std::vector<const lb_problem *> group;

@@ -954,6 +954,6 @@ extern "C" int lindblad_propagate_baseline(int n, const void *P, int B, void *rh
                                            hipStream_t stream) {
     LB_TRY(validate_chain("lindblad_propagate_baseline", n, P, B, rho, nsteps));
     Workspace *w = ws_resolve(ws);
-    ws_begin(w);
+    ws_begin(w, stream);
     return chain_baseline(n, static_cast<const cd *>(P), B, static_cast<cd *>(rho), nsteps, w, stream);
 }

@@ -97,7 +97,7 @@ extern "C" int lindblad_expmv(int n, const void *L, double t, int B, void *rho, 
     LB_TRY(validate_chain("lindblad_expmv", n, L, B, rho, nsteps));
     if (!std::isfinite(t)) return fail(LB_EINVAL, "lindblad_expmv: t must be finite");
     Workspace *w = ws_resolve(ws);
-    ws_begin(w);
+    ws_begin(w, stream);
     const cd *Lc = static_cast<const cd *>(L);
     // shift and norm (host synchronisation: the series length depends on them)
     LB_TRY(ws_ensure(w, align256((size_t)n * sizeof(cd)) + align256((size_t)n * sizeof(double))));

@@ -899,7 +899,7 @@ extern "C" int grape_gradient(int n, int M, int C, const void *L0, const void *L
     if (!L0 || !x0 || !w || !F || (C > 0 && (!Lc || !u))) return fail(LB_EINVAL, "grape_gradient: NULL pointer");
     if (!std::isfinite(dt) || !(theta > 0.0)) return fail(LB_EINVAL, "grape_gradient: bad dt or theta");
     Workspace *wsp = ws_resolve(ws);
-    ws_begin(wsp);
+    ws_begin(wsp, stream);
     return grape_run(n, M, C, static_cast<const cd *>(L0), static_cast<const cd *>(Lc), u, dt, theta,
                      static_cast<const cd *>(x0), static_cast<const cd *>(w), F, grad, checkpoint_bytes, wsp, stream);
 }

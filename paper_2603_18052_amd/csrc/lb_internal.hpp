@@ -40,16 +40,22 @@ struct Workspace {
     size_t used = 0;     // bump offset within the current call
     char *base = nullptr;
     int device = -1;
+    hipStream_t stream = nullptr;        // stream of the current call (growth is ordered on it)
+    hipStream_t alloc_stream = nullptr;  // stream the buffer was allocated on
+    bool fixed = false;            // a view of caller-provided memory: never grown or freed
 };
 
 // Bump allocation inside one device buffer.  A top-level entry point calls
-// ws_begin(), which resets the bump offset; a routine takes what it needs
-// with ws_ensure() + ws_take() and gives it back by restoring ws->used.
-// ws_ensure grows the buffer (synchronising the device, invalidating earlier
-// pointers) only when nothing is taken yet; a nested request beyond the
-// reservation fails with LB_ENOMEM, so callers that nest reserve the total
-// first.
-void ws_begin(Workspace *ws);
+// ws_begin(), which resets the bump offset and records the call's stream; a
+// routine takes what it needs with ws_ensure() + ws_take() and gives it back
+// by restoring ws->used.  ws_ensure grows the buffer only when nothing is
+// taken yet, stream-ordered on the call's stream (the old buffer is released
+// with hipFreeAsync after the work already enqueued there, the new one comes
+// from hipMallocAsync), so growth never blocks the host; a nested request
+// beyond the reservation fails with LB_ENOMEM, so callers that nest reserve
+// the total first.  A fixed workspace (a view of caller-provided memory)
+// never grows: requests beyond its size fail with LB_ENOMEM.
+void ws_begin(Workspace *ws, hipStream_t s);
 int ws_ensure(Workspace *ws, size_t bytes);
 void *ws_take(Workspace *ws, size_t bytes);
 Workspace *ws_resolve(lb_workspace *ws);
@@ -130,6 +136,22 @@ size_t build_workspace_bytes(int n, int M);
 int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *d_s, int smax, cd *P, int *d_info,
                       Workspace *ws, hipStream_t s);
 size_t build_async_bytes(int n, int M);
+
+// Alg. 1 for M generators without any host synchronisation: dt goes to the
+// device through kernel arguments, s is computed on the device (d_s_out, M
+// ints, or NULL), the squarings run as masked launches up to kMaxSquarings,
+// and data-dependent failures are reported in the device status word
+// d_status (or dropped if NULL): LB_ENONFINITE for a non-finite ||L dt||_1,
+// LB_ESINGULAR for a zero pivot, LB_ENOTSUP for s > kMaxSquarings (the
+// smallest code wins).  Chunks of the batch are enqueued one after another
+// so that each fits what the workspace can give.
+constexpr int kMaxSquarings = 24;
+int build_propagators_async(int n, int M, const cd *L, const double *dt_host, double theta, cd *P, int *d_s_out,
+                            int *d_status, Workspace *ws, hipStream_t s);
+// Workspace bytes build_propagators_async needs for one chunk of M matrices.
+size_t build_async_chunk_bytes(int n, int M);
+// Argument checks of the propagator entry points (who names the caller).
+int propagator_args(const char *who, int n, int M, const void *L, const double *dt, double theta, const void *P);
 
 // Scaling stage of Alg. 1 for M generators: s[m] from ||L[m] dt[m]||_1
 // (host sync), uploaded to d_s; d_dt receives dt.  Fails with LB_ENONFINITE.

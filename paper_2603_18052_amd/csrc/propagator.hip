@@ -1,7 +1,9 @@
 // Alg. 1: P = exp(L dt) by Pade [13/13] scaling and squaring, batched over M
 // generators, FP64 throughout.
 //   norm1_kernel     ||L dt||_1 per matrix (column sums of moduli, max)
-//   host             s = smallest s >= 0 with ||A||_1 <= theta 2^s (exact)
+//   sexp_kernel      s = smallest s >= 0 with ||A||_1 <= theta 2^s (exact), on
+//                    the device (the internal synchronous builds of the GRAPE
+//                    gradient and the mixed batch take it on the host)
 //   scale_kernel     A = (L dt) 2^-s
 //   zgemm            A2, A4, A6; V, W' with fused linear-combination epilogues; U
 //   zlincomb         V - U, V + U
@@ -298,6 +300,106 @@ static int build_chunk(int n, int M, const cd *L, const double *dt_host, double 
     return LB_OK;
 }
 
+// ------------------------------------------------- stream-ordered build
+// Step lengths reach the device as kernel arguments (captured at launch), so
+// the host array may be reused as soon as the call returns.
+constexpr int kDtPerLaunch = 256;
+struct DtArgs {
+    double v[kDtPerLaunch];
+};
+__global__ void set_dt_kernel(DtArgs a, int count, double *__restrict__ d_dt) {
+    const int i = threadIdx.x;
+    if (i < count) d_dt[i] = a.v[i];
+}
+
+// s[m] from ||A_m||_1 by exact comparison with theta 2^s; a non-finite norm
+// leaves s = 0 (the build then runs on non-finite values) and flags
+// LB_ENONFINITE, an s beyond the squaring cap flags LB_ENOTSUP.  The status
+// word keeps the smallest code (atomic min: order independent).
+__global__ void sexp_kernel(int M, double theta, const unsigned long long *__restrict__ normbits, int *__restrict__ d_s,
+                            int *__restrict__ s_out, int *__restrict__ status) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const double v = __longlong_as_double((long long)normbits[m]);
+    int sv = 0, code = LB_OK;
+    if (!isfinite(v)) {
+        code = LB_ENONFINITE;
+    } else {
+        while (v > ldexp(theta, sv)) ++sv;
+        if (sv > kMaxSquarings) code = LB_ENOTSUP;
+    }
+    d_s[m] = sv;
+    if (s_out) s_out[m] = sv;
+    if (code != LB_OK && status) atomicMin(status, code);
+}
+
+// Zero pivots (info[m] != 0) -> LB_ESINGULAR in the status word.
+__global__ void pivot_status_kernel(int M, const int *__restrict__ info, int *__restrict__ status) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < M && info[m] && status) atomicMin(status, LB_ESINGULAR);
+}
+
+size_t build_async_chunk_bytes(int n, int M) {
+    return build_async_bytes(n, M) + 3 * align256(M * sizeof(double)) + align256(M * sizeof(int));
+}
+
+static int build_chunk_stream_ordered(int n, int M, const cd *L, const double *dt_host, double theta, cd *P,
+                                      int *d_s_out, int *d_status, Workspace *ws, hipStream_t s) {
+    LB_TRY(ws_ensure(ws, build_async_chunk_bytes(n, M)));
+    const size_t mark = ws->used;
+    double *d_dt = (double *)ws_take(ws, M * sizeof(double));
+    unsigned long long *d_norm = (unsigned long long *)ws_take(ws, M * sizeof(double));
+    int *d_s = (int *)ws_take(ws, M * sizeof(int));
+    int *d_info = (int *)ws_take(ws, M * sizeof(double));
+    struct Release {
+        Workspace *w;
+        size_t m;
+        ~Release() { w->used = m; }
+    } release{ws, mark};
+    for (int m0 = 0; m0 < M; m0 += kDtPerLaunch) {
+        DtArgs a;
+        const int c = M - m0 < kDtPerLaunch ? M - m0 : kDtPerLaunch;
+        for (int i = 0; i < c; ++i) a.v[i] = dt_host[m0 + i];
+        set_dt_kernel<<<1, kDtPerLaunch, 0, s>>>(a, c, d_dt + m0);
+        LB_TRY(check_launch("set_dt"));
+    }
+    fill_u64_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_norm, M);
+    fill_i32_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_info, M);
+    {
+        dim3 grid((n + 255) / 256, M);
+        norm1_kernel<<<grid, 256, 0, s>>>(n, L, d_dt, d_norm);
+        LB_TRY(check_launch("norm1"));
+    }
+    sexp_kernel<<<(M + 255) / 256, 256, 0, s>>>(M, theta, d_norm, d_s, d_s_out, d_status);
+    LB_TRY(check_launch("sexp"));
+    // the squaring levels run up to the cap; a level skips (on the device,
+    // per workgroup) every matrix whose s it exceeds
+    LB_TRY(build_chunk_async(n, M, L, d_dt, d_s, kMaxSquarings, P, d_info, ws, s));
+    pivot_status_kernel<<<(M + 255) / 256, 256, 0, s>>>(M, d_info, d_status);
+    return check_launch("pivot_status");
+}
+
+int build_propagators_async(int n, int M, const cd *L, const double *dt_host, double theta, cd *P, int *d_s_out,
+                            int *d_status, Workspace *ws, hipStream_t s) {
+    const size_t avail = ws->fixed ? (ws->size > ws->used ? ws->size - ws->used : 0)
+                                   : (ws->used == 0 ? ws->cap : (ws->size > ws->used ? ws->size - ws->used : 0));
+    long long chunk = M;
+    while (chunk > 1 && build_async_chunk_bytes(n, (int)chunk) > avail) chunk = (chunk + 1) / 2;
+    if (chunk > 4096) chunk = 4096;
+    if (build_async_chunk_bytes(n, (int)chunk) > avail)
+        return fail(LB_ENOMEM, "lindblad_propagator: scratch of " + std::to_string(avail) +
+                                   " bytes is too small for one n x n build (" +
+                                   std::to_string(build_async_chunk_bytes(n, 1)) + " bytes at n = " +
+                                   std::to_string(n) + ")");
+    const size_t nn = (size_t)n * n;
+    for (int m0 = 0; m0 < M; m0 += (int)chunk) {
+        const int mc = (int)((M - m0) < chunk ? (M - m0) : chunk);
+        LB_TRY(build_chunk_stream_ordered(n, mc, L + nn * m0, dt_host + m0, theta, P + nn * m0,
+                                          d_s_out ? d_s_out + m0 : nullptr, d_status, ws, s));
+    }
+    return LB_OK;
+}
+
 static long long build_chunk_size(int n, int M, size_t avail) {
     long long chunk = M;
     while (chunk > 1 && chunk_bytes(n, (int)chunk) > avail) chunk = (chunk + 1) / 2;
@@ -324,19 +426,29 @@ int build_propagators(int n, int M, const cd *L, const double *dt_host, double t
     return LB_OK;
 }
 
+
+int propagator_args(const char *who, int n, int M, const void *L, const double *dt, double theta,
+                           const void *P) {
+    const std::string w(who);
+    if (n < 1 || n > 4096) return fail(LB_ESHAPE, w + ": n must be in [1, 4096]");
+    if (M < 1) return fail(LB_ESHAPE, w + ": M must be >= 1");
+    if (!L || !dt || !P) return fail(LB_EINVAL, w + ": NULL pointer");
+    if (!(theta > 0.0) || !std::isfinite(theta)) return fail(LB_EINVAL, w + ": theta must be > 0");
+    for (int m = 0; m < M; ++m)
+        if (!std::isfinite(dt[m])) return fail(LB_EINVAL, w + ": dt must be finite");
+    return LB_OK;
+}
+
 }  // namespace lb
 
 using namespace lb;
 
 extern "C" int lindblad_propagator(int n, int M, const void *L, const double *dt, double theta, void *P, int *s_used,
-                                   lb_workspace *ws, hipStream_t stream) {
-    if (n < 1 || n > 4096) return fail(LB_ESHAPE, "lindblad_propagator: n must be in [1, 4096]");
-    if (M < 1) return fail(LB_ESHAPE, "lindblad_propagator: M must be >= 1");
-    if (!L || !dt || !P) return fail(LB_EINVAL, "lindblad_propagator: NULL pointer");
-    if (!(theta > 0.0) || !std::isfinite(theta)) return fail(LB_EINVAL, "lindblad_propagator: theta must be > 0");
-    for (int m = 0; m < M; ++m)
-        if (!std::isfinite(dt[m])) return fail(LB_EINVAL, "lindblad_propagator: dt must be finite");
+                                   int *status, lb_workspace *ws, hipStream_t stream) {
+    LB_TRY(propagator_args("lindblad_propagator", n, M, L, dt, theta, P));
     Workspace *w = ws_resolve(ws);
-    ws_begin(w);
-    return build_propagators(n, M, static_cast<const cd *>(L), dt, theta, static_cast<cd *>(P), s_used, w, stream);
+    ws_begin(w, stream);
+    return build_propagators_async(n, M, static_cast<const cd *>(L), dt, theta, static_cast<cd *>(P), s_used, status,
+                                   w, stream);
 }
+

@@ -195,7 +195,7 @@ extern "C" int lindblad_propagate(int n, const void *P, lb_precision prec, int B
     LB_TRY(validate_chain("lindblad_propagate", n, P, B, rho, nsteps));
     LB_TRY(check_prec("lindblad_propagate", prec));
     Workspace *w = ws_resolve(ws);
-    ws_begin(w);
+    ws_begin(w, stream);
     return chain_run(n, static_cast<const cd *>(P), prec, B, static_cast<cd *>(rho), nsteps, w, stream);
 }
 
@@ -204,7 +204,7 @@ extern "C" int lindblad_propagate_variant(int n, const void *P, lb_precision pre
     LB_TRY(validate_chain("lindblad_propagate_variant", n, P, B, rho, nsteps));
     LB_TRY(check_prec("lindblad_propagate_variant", prec));
     Workspace *w = ws_resolve(ws);
-    ws_begin(w);
+    ws_begin(w, stream);
     return chain_run_variant(n, static_cast<const cd *>(P), prec, B, static_cast<cd *>(rho), nsteps, variant, w,
                              stream);
 }
@@ -244,7 +244,7 @@ extern "C" int lindblad_tune(int n, const void *P, lb_precision prec, int B, con
     const int nv = chain_variants(n, prec, B, ids, 32);
     if (nv < 1 || nv > 32) return fail(LB_ENOTSUP, "lindblad_tune: no variants for this shape");
     Workspace *w = ws_resolve(ws);
-    ws_begin(w);
+    ws_begin(w, stream);
     const size_t xbytes = (size_t)B * n * sizeof(cd);
     size_t need = 0;
     for (int i = 0; i < nv; ++i) need = std::max(need, chain_ws_bytes(n, prec, B, ids[i]));

@@ -31,7 +31,7 @@ SYMBOLS = {
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lindblad_propagator": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                           ctypes.c_void_p]),
+                                           ctypes.c_void_p, ctypes.c_void_p]),
     "lindblad_propagate": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p, ctypes.c_void_p]),
     "lindblad_propagate_baseline": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -200,20 +200,39 @@ def generators(L0: torch.Tensor, Lc: torch.Tensor, u: torch.Tensor, out: torch.T
     return out
 
 
-def propagator(L: torch.Tensor, dt, theta: float = 0.25, ws: Workspace | None = None, return_s: bool = False):
-    """Alg. 1: P = exp(L dt).  L is (n, n) or (M, n, n); dt a float or M floats."""
+def propagator(L: torch.Tensor, dt, theta: float = 0.25, ws: Workspace | None = None, return_s: bool = False,
+               status: torch.Tensor | None = None):
+    """Alg. 1: P = exp(L dt).  L is (n, n) or (M, n, n); dt a float or M floats.
+
+    The library call is stream-ordered (s and the status word stay on the
+    device).  Without `status` this wrapper then reads the status word back
+    (one synchronisation) and raises LindbladError on a non-finite norm, a
+    zero pivot or an s beyond the squaring cap; with a caller's int32
+    `status` tensor (set to 0 beforehand) it returns at once and the caller
+    checks the word when it wants.  return_s: also return s (ints; a device
+    tensor when `status` is given)."""
     L = _dev(L, name="L")
     single = L.dim() == 2
     Lb = L.unsqueeze(0) if single else L
     M, n = Lb.shape[0], Lb.shape[1]
     dts = (ctypes.c_double * M)(*([float(dt)] * M if isinstance(dt, (int, float)) else [float(x) for x in dt]))
-    s_used = (ctypes.c_int * M)()
+    s_dev = torch.empty(M, dtype=torch.int32, device=Lb.device) if return_s else None
+    own = status is None
+    if own:
+        status = torch.zeros(1, dtype=torch.int32, device=Lb.device)
     P = torch.empty_like(Lb)
-    _check(lib().lindblad_propagator(n, M, _ptr(Lb), dts, float(theta), _ptr(P), s_used, _ws(ws), _stream()))
+    _check(lib().lindblad_propagator(n, M, _ptr(Lb), dts, float(theta), _ptr(P),
+                                     _ptr(s_dev) if return_s else None, _ptr(status), _ws(ws), _stream()))
+    if own:
+        code = int(status.item())
+        if code != OK:
+            what = {ENONFINITE: "||L dt||_1 is not finite", ESINGULAR: "zero pivot in the Pade denominator V - U",
+                    ENOTSUP: "scaling exponent above the squaring cap"}.get(code, "device status")
+            raise LindbladError(code, f"lindblad_propagator: {what} (status {code})")
     P = P[0] if single else P
-    s = list(s_used)
     if return_s:
-        return P, (s[0] if single else s)
+        s = s_dev.tolist() if own else s_dev
+        return P, (s[0] if single and own else s)
     return P
 
 

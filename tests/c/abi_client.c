@@ -88,13 +88,20 @@ int main(int argc, char **argv) {
     hipStream_t stream;
     HIP(hipStreamCreate(&stream));
     LB(lindblad_liouvillian(d, dH, K, dLk, dL, stream));
-    int s_used = -1;
-    LB(lindblad_propagator(n, 1, dL, &dt, 0.25, dP, &s_used, ws, stream));
+    int s_used = -1, status = -100;
+    int *dS = NULL, *dStatus = NULL;
+    HIP(hipMalloc((void **)&dS, sizeof(int)));
+    HIP(hipMalloc((void **)&dStatus, sizeof(int)));
+    HIP(hipMemsetAsync(dStatus, 0, sizeof(int), stream));
+    LB(lindblad_propagator(n, 1, dL, &dt, 0.25, dP, dS, dStatus, ws, stream));
     int chosen = 0;
     LB(lindblad_chain_variant(n, LB_C128, B, &chosen));
     LB(lindblad_propagate(n, dP, LB_C128, B, dX, nsteps, ws, stream));
     LB(lindblad_propagate_variant(n, dP, LB_C128, B, dY, nsteps, variant, ws, stream));
     HIP(hipStreamSynchronize(stream));
+    HIP(hipMemcpy(&s_used, dS, sizeof(int), hipMemcpyDeviceToHost));
+    HIP(hipMemcpy(&status, dStatus, sizeof(int), hipMemcpyDeviceToHost));
+    if (status != LB_OK) return 6;
 
     void *out = malloc((size_t)n * n * cz);
     if (!out) return 1;
@@ -122,6 +129,8 @@ int main(int argc, char **argv) {
     hipFree(dP);
     hipFree(dX);
     hipFree(dY);
+    hipFree(dS);
+    hipFree(dStatus);
     free(out);
     free(H);
     free(Lk);

@@ -49,12 +49,12 @@ def test_validation_errors_without_gpu(L):
     assert L.lindblad_generators(0, 1, 1, 1, 1, 1, 1, None) == lb.ESHAPE
     assert L.lindblad_generators(9, -1, 1, 1, 1, 1, 1, None) == lb.ESHAPE
     dts = (ctypes.c_double * 1)(0.5)
-    assert L.lindblad_propagator(0, 1, 1, dts, 0.25, 1, None, None, None) == lb.ESHAPE
-    assert L.lindblad_propagator(9, 0, 1, dts, 0.25, 1, None, None, None) == lb.ESHAPE
-    assert L.lindblad_propagator(9, 1, None, dts, 0.25, 1, None, None, None) == lb.EINVAL
-    assert L.lindblad_propagator(9, 1, 1, dts, 0.0, 1, None, None, None) == lb.EINVAL
+    assert L.lindblad_propagator(0, 1, 1, dts, 0.25, 1, None, None, None, None) == lb.ESHAPE
+    assert L.lindblad_propagator(9, 0, 1, dts, 0.25, 1, None, None, None, None) == lb.ESHAPE
+    assert L.lindblad_propagator(9, 1, None, dts, 0.25, 1, None, None, None, None) == lb.EINVAL
+    assert L.lindblad_propagator(9, 1, 1, dts, 0.0, 1, None, None, None, None) == lb.EINVAL
     bad = (ctypes.c_double * 1)(float("nan"))
-    assert L.lindblad_propagator(9, 1, 1, bad, 0.25, 1, None, None, None) == lb.EINVAL
+    assert L.lindblad_propagator(9, 1, 1, bad, 0.25, 1, None, None, None, None) == lb.EINVAL
     assert L.lindblad_propagate(9, 1, 0, 0, 1, 1, None, None) == lb.ESHAPE
     assert L.lindblad_propagate(9, 1, 0, 1, 1, -1, None, None) == lb.EINVAL
     assert L.lindblad_propagate(9, 1, 9, 1, 1, 1, None, None) == lb.EINVAL

@@ -53,6 +53,6 @@ def test_c_client_matches_oracle(client, tmp_path, q, B, N, variant):
     assert s_used == sref
     assert oracle.rel_fro(P, Pref) < 1e-12
     ref = oracle.propagate(P, X, N)  # chain parity from the same P
-    assert oracle.rel_fro(out, ref) < 1e-12
-    assert oracle.rel_fro(outv, ref) < 1e-12
+    assert oracle.rel_per_state(out, ref) < 1e-12
+    assert oracle.rel_per_state(outv, ref) < 1e-12
     assert chosen > 0

@@ -46,7 +46,7 @@ def test_expmv_transmon_matches_oracle(lb, q, B, N):
     prods = lb.expmv(T(L), x, W.DT_NS, N)
     s, m = lb.expmv_params(shifted_norm(L, W.DT_NS))
     assert prods == s * m
-    err = oracle.rel_fro(x.cpu().numpy(), ref)
+    err = oracle.rel_per_state(x.cpu().numpy(), ref)
     print(f"expmv d={d} B={B} N={N}: {s} x {m} products per step, rel err {err:.2e}")
     assert err < 1e-12
 
@@ -61,7 +61,7 @@ def test_expmv_d27_full_batch_sampled(lb):
     lb.expmv(T(L), x, W.DT_NS, 2)
     idx = [0, 100, 1023]
     ref = oracle.propagate(oracle.propagator(L, W.DT_NS), X[idx], 2)
-    err = oracle.rel_fro(x.cpu().numpy()[idx], ref)
+    err = oracle.rel_per_state(x.cpu().numpy()[idx], ref)
     print(f"expmv d=27 B=1024: rel err {err:.2e}")
     assert err < 1e-12
 
@@ -76,7 +76,7 @@ def test_expmv_nonnormal_generator(lb, n, scale):
     ref = oracle.propagate(oracle.propagator(A, 1.0), X, 1)
     x = T(X.copy())
     lb.expmv(T(A), x, 1.0, 1)
-    err = oracle.rel_fro(x.cpu().numpy(), ref)
+    err = oracle.rel_per_state(x.cpu().numpy(), ref)
     print(f"expmv random n={n} ||A||={scale}: rel err {err:.2e}")
     assert err < 1e-12
 

@@ -166,3 +166,45 @@ def test_grape_chunking_does_not_change_bits(lb):
         small.close()
         assert F1 == F2
         assert np.array_equal(ref, g2)
+
+
+def _golden_grape(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    M, F, rows = None, None, []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# M "):
+                M = int(line.split()[2])
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            if line.startswith("F "):
+                F = float(line.split()[1])
+            else:
+                m, c, v = line.split()
+                rows.append((int(m), int(c), float(v)))
+    return M, F, rows
+
+
+@pytest.mark.parametrize("golden", ["grape_d27_M2.txt", "grape_d27_M200_sampled.txt"])
+@pytest.mark.parametrize("mode", ["lowrank", "dense"])
+def test_grape_d27_against_oracle_golden(lb, golden, mode):
+    """Config 4 at d = 27 (6 controls, slices of 1 ns) against the oracle's
+    block-triangular Frechet gradient, stored by tests/golden/make_grape_d27.py
+    (M = 2: every entry; M = 200: every control of slices 0 and 199).  The
+    default path (build products kept, low-rank derivative) and the dense
+    recurrences (nothing kept) both within 1e-10 of the largest entry; F to
+    1e-12."""
+    import os
+    if not os.path.exists(os.path.join(os.path.dirname(__file__), "golden", golden)):
+        pytest.skip(f"{golden} not generated")
+    M, Fo, rows = _golden_grape(golden)
+    p, L0, Lc = setup(3, M=M)
+    kw = {} if mode == "lowrank" else {"checkpoint_bytes": 1}
+    F, g = gpu_grad(lb, p, L0, Lc, **kw)
+    assert abs(F - Fo) < 1e-12
+    go = np.array([v for _, _, v in rows])
+    gg = np.array([g[m, c] for m, c, _ in rows])
+    assert np.abs(gg - go).max() <= 1e-10 * np.abs(go).max(), (np.abs(gg - go).max(), np.abs(go).max())
+    assert np.all(np.isfinite(g))

@@ -71,7 +71,7 @@ def test_past_fused_limits(lb, n, prec, tol):
         X = g.standard_normal((B, n)) + 1j * g.standard_normal((B, n))
         ref = oracle.propagate(P, X, 30)
         got = run(lb, P, X, 30, prec)
-        assert oracle.rel_fro(got, ref) < tol, (B, oracle.rel_fro(got, ref))
+        assert oracle.rel_per_state(got, ref) < tol, (B, oracle.rel_per_state(got, ref))
 
 
 def test_d27_deterministic(lb, P27):
@@ -96,7 +96,7 @@ def test_d27_config3_full_batch_sampled(lb, P27, prec, nsteps, tol, variant):
     ref = oracle.propagate(P27, X[idx], nsteps)
     g = got[idx]
     if prec == "c128":
-        assert oracle.rel_fro(g, ref) < tol
+        assert oracle.rel_per_state(g, ref) < tol
     td = oracle.trace_distance(g.reshape(-1, 27, 27), ref.reshape(-1, 27, 27))
     print(f"{prec} d=27 B=1024 N={nsteps}: trace distance max {td.max():.3e}")
     assert td.max() < (tol if prec != "c128" else 1e-12)

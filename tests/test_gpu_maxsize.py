@@ -71,7 +71,7 @@ def test_propagator_d64_properties_and_chain(lb, system):
         lb.propagate(P, x, 3, prec)
         got = x.cpu().numpy()
         if prec == "c128":
-            assert oracle.rel_fro(got, ref) < tol
+            assert oracle.rel_per_state(got, ref) < tol
         else:
             assert oracle.trace_distance(got.reshape(3, D, D), ref.reshape(3, D, D)).max() < tol
         m = got.reshape(3, D, D)

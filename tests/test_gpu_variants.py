@@ -66,7 +66,7 @@ def test_every_variant_matches_oracle(lb, d, B, N, prec):
         lb.propagate_variant(Pt, x, N, v, prec)
         got = x.cpu().numpy()
         if prec == "c128":
-            err = oracle.rel_fro(got, ref)
+            err = oracle.rel_per_state(got, ref)
         else:
             err = oracle.trace_distance(got.reshape(-1, d, d), ref.reshape(-1, d, d)).max()
         print(f"d={d} B={B} N={N} {prec} {lb.variant_name(v)}: {err:.2e}")
@@ -95,7 +95,7 @@ def test_wave_chain_config1_full_length(lb):
     x = T(X.copy())
     lb.propagate_variant(T(P), x, c["nsteps"], 200, "c128")
     got = x.cpu().numpy()
-    assert oracle.rel_fro(got, ref) < 1e-12
+    assert oracle.rel_per_state(got, ref) < 1e-12
     assert oracle.trace_distance(got.reshape(3, 3), ref.reshape(3, 3)) < 1e-12
 
 
@@ -113,7 +113,7 @@ def test_tune_records_a_listed_variant(lb, d, B, prec):
     lb.propagate(P, x, 30, prec)
     got = x.cpu().numpy()
     if prec == "c128":
-        assert oracle.rel_fro(got, ref) < 1e-12
+        assert oracle.rel_per_state(got, ref) < 1e-12
     else:
         assert oracle.trace_distance(got.reshape(-1, d, d), ref.reshape(-1, d, d)).max() < 1e-4
     lb.tune_set(n, prec, B, 0)
