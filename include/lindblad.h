@@ -132,6 +132,25 @@ int lindblad_generators(int n, int M, int C, const void *L0, const void *Lc, con
 int lindblad_propagator(int n, int M, const void *L, const double *dt, double theta, void *P,
                         int *s_used, int *status, lb_workspace *ws, hipStream_t stream);
 
+/* lindblad_propagator for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same build, arguments, results and status word, with no
+ * workspace argument.  Its scratch is a fixed device array inside the
+ * library, 80 MiB per device (lindblad_propagator_noalloc_scratch_bytes()),
+ * held until the process ends; the call itself allocates nothing
+ * (no hipMalloc / hipFree / hipMallocAsync, no library allocation).
+ *   n      : 1 <= n <= 809 (one n x n build needs 128 n^2 bytes plus a
+ *            little; larger n fail with LB_ENOMEM before anything runs)
+ *   M      : any M >= 1; batches are built in chunks that fit the scratch
+ *            (one after another on `stream`)
+ * Stream-ordered and asynchronous like lindblad_propagator.  Every call on a
+ * device shares that device's scratch and leaves its contents behind: calls
+ * that overlap on one device (several streams or threads) race and must be
+ * serialised by the caller. */
+int lindblad_propagator_noalloc(int n, int M, const void *L, const double *dt, double theta, void *P,
+                                int *s_used, int *status, hipStream_t stream);
+size_t lindblad_propagator_noalloc_scratch_bytes(void);
+
 /* The step chain, Alg. 2 applied nsteps times to each of B independent states
  * (Alg. 3 parallelism): rho_b <- P^nsteps rho_b.
  *   n      : 1 <= n <= 4096 (n = d*d)

@@ -11,6 +11,7 @@
 //   zgemm (masked)   s squarings, ping-pong between two buffers
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "lb_internal.hpp"
@@ -452,3 +453,60 @@ extern "C" int lindblad_propagator(int n, int M, const void *L, const double *dt
                                    w, stream);
 }
 
+// ------------------------------------------------- allocation-free build
+// lindblad_propagator_noalloc runs the stream-ordered build above on a fixed
+// scratch: a file-scope device array (one copy per device, held until the
+// process ends).  Its device address is looked up once per device with
+// hipGetSymbolAddress and kept; host code only ever passes that address
+// (the array's own name is a host-side stand-in).  Every call on a device
+// shares the array, so calls that overlap on one device race.
+namespace lb {
+constexpr size_t kNoAllocScratchBytes = size_t(80) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+}  // namespace lb
+
+static __device__ __align__(256) char scratch[lb::kNoAllocScratchBytes];
+
+namespace lb {
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+static int noalloc_scratch(char **out) {
+    int dev = 0;
+    LB_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices)
+        return fail(LB_ENOTSUP, "lindblad_propagator_noalloc: device index " + std::to_string(dev) +
+                                    " beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        LB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(LB_EHIP, "lindblad_propagator_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return LB_OK;
+}
+}  // namespace lb
+
+extern "C" size_t lindblad_propagator_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+extern "C" int lindblad_propagator_noalloc(int n, int M, const void *L, const double *dt, double theta, void *P,
+                                           int *s_used, int *status, hipStream_t stream) {
+    LB_TRY(propagator_args("lindblad_propagator_noalloc", n, M, L, dt, theta, P));
+    const size_t one = build_async_chunk_bytes(n, 1);
+    if (one > kNoAllocScratchBytes)
+        return fail(LB_ENOMEM, "lindblad_propagator_noalloc: one n x n build needs " + std::to_string(one) +
+                                   " bytes of scratch at n = " + std::to_string(n) + ", the fixed scratch holds " +
+                                   std::to_string(kNoAllocScratchBytes) + " bytes (n <= 809)");
+    char *base = nullptr;
+    LB_TRY(noalloc_scratch(&base));
+    Workspace w;  // a view of the device's scratch: never grown, never freed
+    w.base = base;
+    w.size = w.cap = kNoAllocScratchBytes;
+    w.fixed = true;
+    (void)hipGetDevice(&w.device);
+    ws_begin(&w, stream);
+    return build_propagators_async(n, M, static_cast<const cd *>(L), dt, theta, static_cast<cd *>(P), s_used, status,
+                                   &w, stream);
+}

@@ -32,6 +32,10 @@ SYMBOLS = {
     "lindblad_propagator": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "lindblad_propagator_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "lindblad_propagator_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "lindblad_propagate": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p, ctypes.c_void_p]),
     "lindblad_propagate_baseline": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -234,6 +238,27 @@ def propagator(L: torch.Tensor, dt, theta: float = 0.25, ws: Workspace | None = 
         s = s_dev.tolist() if own else s_dev
         return P, (s[0] if single and own else s)
     return P
+
+
+def propagator_noalloc(L: torch.Tensor, dt, P: torch.Tensor, theta: float = 0.25,
+                       s_used: torch.Tensor | None = None, status: torch.Tensor | None = None) -> None:
+    """lindblad_propagator_noalloc: the build into a caller-provided P (same
+    shape as L) on the library's fixed device scratch; allocates nothing.
+    `s_used` (int32, M) and `status` (int32, 1, set to 0 beforehand) are
+    optional device tensors; the call returns without synchronising."""
+    L = _dev(L, name="L")
+    Lb = L.unsqueeze(0) if L.dim() == 2 else L
+    M, n = Lb.shape[0], Lb.shape[1]
+    if P.shape != L.shape or P.dtype != torch.complex128 or not P.is_contiguous():
+        raise ValueError("P must be a contiguous complex128 tensor shaped like L")
+    dts = (ctypes.c_double * M)(*([float(dt)] * M if isinstance(dt, (int, float)) else [float(x) for x in dt]))
+    _check(lib().lindblad_propagator_noalloc(n, M, _ptr(Lb), dts, float(theta), _ptr(P),
+                                             _ptr(s_used) if s_used is not None else None,
+                                             _ptr(status) if status is not None else None, _stream()))
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().lindblad_propagator_noalloc_scratch_bytes())
 
 
 def propagate(P: torch.Tensor, rho: torch.Tensor, nsteps: int, precision="c128", ws: Workspace | None = None):
