@@ -36,17 +36,19 @@ PEAKS = {  # MI355X published dense peaks
     "fp64_tflops": 78.6,
     "fp32_tflops": 157.3,
     "bf16_tflops": 2500.0,
+    "int8_tops": 5000.0,
 }
 PATH_UNIT = {  # arithmetic unit and peak of each chain variant
     "c128": ("mfma", "fp64_tflops", "f64"),
     "c64": ("mfma", "fp32_tflops", "f32"),
     "bf16_hilo": ("mfma", "bf16_tflops", "bf16"),
     "bf16_sliced": ("mfma", "bf16_tflops", "bf16"),
+    "i8_sliced": ("mfma", "int8_tops", "i8"),
 }
 # Executed real MFMA products per complex multiply-add, relative to one
 # complex product (4 real): hi+lo makes 3 products of each real part pair,
 # the sliced scheme one per slice pair kept.
-TARGET_TD = {"c128": 1e-12, "c64": 1e-6, "bf16_hilo": 1e-6, "bf16_sliced": 1e-6}
+TARGET_TD = {"c128": 1e-12, "c64": 1e-6, "bf16_hilo": 1e-6, "bf16_sliced": 1e-6, "i8_sliced": 1e-6}
 
 
 def paper_step_cost(d):
@@ -134,7 +136,8 @@ def parse():
     ap.add_argument("--nsteps", type=int, default=10_000, help="chain steps per bench step")
     ap.add_argument("--precision", default="auto",
                     help="chain variant timed as `value` (auto = fastest meeting its error target)")
-    ap.add_argument("--paths", default="c128,c64,bf16_hilo,bf16_sliced,baseline", help="variants measured for the `paths` report")
+    ap.add_argument("--paths", default="c128,c64,bf16_hilo,bf16_sliced,i8_sliced,baseline",
+                    help="variants measured for the `paths` report")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extra", action="store_true",
@@ -184,10 +187,15 @@ def kernel_of(variant, prec):
         return base + ("<double>" if prec == "c128" else "<float>")
     if fam in (4, 7):
         return base + ("<HILO>" if prec == "bf16_hilo" else "<SLICED>")
+    if fam == 13:
+        return "i8_chain_kernel"
     if fam == 11:
-        return f"tgemm_step_kernel<{'double' if prec == 'c128' else 'float'}, {variant % 50}>"
+        t = "double" if prec == "c128" else "float"
+        if variant % 50 in (1, 2):
+            return f"trgemm_step_kernel<{t}>"
+        return f"tgemm_step_kernel<{t}, {variant % 50}>"
     if fam == 12:
-        return "tqplane_gemm_kernel" if variant % 50 == 1 else "tplane_gemm_kernel"
+        return "tqplane_gemm_kernel" if variant % 50 in (1, 2) else "tplane_gemm_kernel"
     return base
 
 
@@ -397,6 +405,162 @@ def expmv_section(lb, W, torch, dev, ws):
     return out
 
 
+# Executed MFMA products per complex multiply-add of the chain, relative
+# to the algorithmic one: hi+lo makes three BF16 products per complex
+# product, the sliced scheme one per digit pair kept (5 x 4 digits, levels
+# <= 4: 14 pairs).
+EXECUTED_FACTOR = {"c128": 1.0, "c64": 1.0, "bf16_hilo": 3.0, "bf16_sliced": 14.0, "i8_sliced": 14.0}
+# Bytes of the propagator one step reads in each format (n x n complex):
+# FP64 16, FP32 8, BF16 hi+lo 2 parts x 2 x 2, sliced 5 digits x 2 x 2.
+P_BYTES_PER_ENTRY = {"c128": 16, "c64": 8, "bf16_hilo": 8, "bf16_sliced": 20, "i8_sliced": 20, "baseline": 16}
+
+
+def _kernel_times():
+    """rocprofv3 kernel-trace averages stored in profiles/kernel_times.json
+    ({label: {"kernel", "avg_us", "calls", "profile"}}), or {}."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "kernel_times.json")) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _median_ms(fn, trials=5):
+    """Median over `trials` of HIP-event milliseconds around fn() on the
+    current stream (the library launches on it)."""
+    import torch
+    times = []
+    for _ in range(trials):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2], times[0], times[-1]
+
+
+def d27_section(lb, W, torch, dev, ws):
+    """Config 3 (d = 27, n = 729, B in {1, 64, 1024}, 1e3 steps of 0.5 ns):
+    every path tuned, then the median of 5 HIP-event-timed runs; per path
+    the chain kernel, the time per step, and both rooflines: algorithmic
+    flops (8 n^2 per state-step) against the dtype's MFMA peak (and the
+    executed slice products against the same peak), and the propagator
+    bytes one step must read (plus the states in and out) against HBM.
+    The reduced precisions' trace distance is measured against the FP64
+    chain on the same states (the FP64 chain is pinned to the oracle by the
+    test suite)."""
+    cfg = W.config3(B=1024, nsteps=1000)
+    n, N = 729, cfg["nsteps"]
+    H, Lk = torch.from_numpy(cfg["H"]).to(dev), torch.from_numpy(cfg["Lk"]).to(dev)
+    L = lb.liouvillian(H, Lk)
+    P = lb.propagator(L, cfg["dt"], ws=ws)
+    build_ms, _, _ = _median_ms(lambda: lb.propagator(L, cfg["dt"], ws=ws))
+    _, s_build, stages = lb.propagator_stages(L, cfg["dt"], ws=ws)
+    X0 = torch.from_numpy(cfg["rho0"].reshape(-1, n)).to(dev)
+    prof = _kernel_times()
+    flops_build = (22.0 / 3.0 + s_build[0]) * 8.0 * n ** 3
+    out = {"build": {"ms_median_of_5": build_ms, "s": s_build[0], "fp64_tflops": flops_build / build_ms / 1e9,
+                     "frac_fp64_peak": flops_build / build_ms / 1e9 / PEAKS["fp64_tflops"], "stages_ms": stages}}
+    finals = {}
+    for B in (1, 64, 1024):
+        row = {}
+        for prec in ("c128", "c64", "bf16_hilo", "bf16_sliced", "baseline"):
+            nst = N if not (prec == "baseline" and B == 1024) else 100
+            x = X0[:B].clone()
+            variant = 100
+            if prec != "baseline":
+                lb.tune(P, x, prec, probe_steps=20, repeats=2, ws=ws)
+                variant = lb.chain_variant(n, prec, B)
+
+            def run():
+                x.copy_(X0[:B])
+                if prec == "baseline":
+                    lb.propagate_baseline(P, x, nst, ws=ws)
+                else:
+                    lb.propagate(P, x, nst, prec, ws=ws)
+            run()  # warm-up
+            med, lo, hi = _median_ms(run)
+            us = med * 1e3 / nst
+            key = "c128" if prec == "baseline" else prec
+            flops = 8.0 * n * n * B  # per step
+            peak_key = PATH_UNIT[key][1]
+            tf = flops / us / 1e6
+            hbm = (P_BYTES_PER_ENTRY[prec] * n * n + 2 * B * n * 16) / us / 1e3  # GB/s
+            frac_mfma = tf / PEAKS[peak_key]
+            frac_hbm = hbm / PEAKS["hbm_gbs"]
+            r = {"variant": lb.variant_name(variant), "kernel": kernel_of(variant, key),
+                 "us_per_step": us, "state_steps_per_s": B / (us * 1e-6), "nsteps": nst,
+                 "trials_ms": {"median": med, "min": lo, "max": hi},
+                 "roofline": {"bound": "mfma" if frac_mfma >= frac_hbm else "hbm",
+                              "mfma": {"achieved_tflops": tf, "peak": PEAKS[peak_key], "frac": frac_mfma,
+                                       "executed_frac": frac_mfma * EXECUTED_FACTOR[key]},
+                              "hbm": {"achieved_gbs": hbm, "peak": PEAKS["hbm_gbs"], "frac": frac_hbm}}}
+            label = f"d27_B{B}_{prec}"
+            if label in prof:
+                r["rocprof"] = prof[label]
+            row[prec] = r
+            if nst == N:
+                finals[(B, prec)] = x[:min(B, 4)].cpu().numpy()
+        out[f"B{B}"] = row
+    for (B, prec), fin in finals.items():
+        ref = finals.get((B, "c128"))
+        if ref is not None and prec != "c128":
+            td = trace_distance(fin.reshape(-1, 27, 27), ref.reshape(-1, 27, 27))
+            out[f"B{B}"][prec]["trace_distance_vs_c128"] = float(td.max())
+    base = out["B1024"]["baseline"]["state_steps_per_s"]
+    for B in (1, 64, 1024):
+        for prec, r in out[f"B{B}"].items():
+            r["speedup_vs_fp64_matvec_B1024"] = r["state_steps_per_s"] / base
+    return out
+
+
+def grape_section(lb, W, torch, dev, ws):
+    """Config 4: the GRAPE gradient (M = 200 slices of 1 ns) at d = 9 and
+    d = 27 -- ms per gradient (median of 5 after a warm-up) -- and the batched
+    FP64 build of its M slice propagators broken down by stage the way the
+    paper's build-time table is (LU solve / Pade products / squarings /
+    other, one stage-timed build), with FP64 TF/s of the build from the
+    algorithmic count (22/3 + s) 8 n^3 per propagator and the gradient's
+    dense-equivalent rate: the build plus a Frechet derivative of the same
+    Pade and squaring steps, (22/3 + s) + (14 + 2 s) products of 8 n^3
+    per slice (the low-rank derivative does less work than that)."""
+    grape = {}
+    for q in (2, 3):
+        p = W.grape_problem(q, M=200)
+        n = (3 ** q) ** 2
+        Hc = torch.from_numpy(p["Hc"]).to(dev)
+        L0 = lb.liouvillian(torch.from_numpy(p["H0"]).to(dev), torch.from_numpy(p["Lk"]).to(dev))
+        Lc = torch.stack([lb.liouvillian(Hc[c], None) for c in range(Hc.shape[0])])
+        u = torch.from_numpy(p["u"]).to(dev)
+        x0 = torch.from_numpy(p["rho0"].reshape(-1)).to(dev)
+        w = torch.from_numpy(p["target"].reshape(-1)).to(dev)
+        Lm = lb.generators(L0, Lc, u)
+        _, svals, stages = lb.propagator_stages(Lm, p["dt"], ws=ws)
+        build_total = sum(stages.values())
+        s_mean = float(np.mean(svals))
+        flops_build = p["M"] * (22.0 / 3.0 + s_mean) * 8.0 * n ** 3
+        del Lm
+        F = [None]
+
+        def grad():
+            F[0], _ = lb.grape_gradient(L0, Lc, u, p["dt"], x0, w, ws=ws)
+        grad()  # warm
+        med, lo, hi = _median_ms(grad)
+        flops_grad = p["M"] * ((22.0 / 3.0 + s_mean) + (14.0 + 2.0 * s_mean)) * 8.0 * n ** 3
+        grape[f"d{3 ** q}"] = {
+            "ms_per_gradient": med, "trials_ms": {"median": med, "min": lo, "max": hi}, "M": p["M"],
+            "controls": int(u.shape[1]), "F": F[0], "s_per_slice": s_mean,
+            "build": {"ms": build_total,
+                      "stage_pct": {k: 100.0 * v / build_total for k, v in stages.items()},
+                      "fp64_tflops": flops_build / build_total / 1e9,
+                      "frac_fp64_peak": flops_build / build_total / 1e9 / PEAKS["fp64_tflops"]},
+            "gradient_dense_equivalent_fp64_tflops": flops_grad / med / 1e9}
+    return grape
+
+
 def extra_sections(lb, W, torch, dev, ws):
     """d = 3 single state (config 1), the timing models, the fixed-point
     chain, d = 27 chains (config 3), GRAPE gradients (config 4), mixed batch
@@ -406,66 +570,9 @@ def extra_sections(lb, W, torch, dev, ws):
            "fixed_point_q15": fixed_point_section(lb, W, torch, dev, ws),
            "expmv_report": expmv_section(lb, W, torch, dev, ws)}
     # ---- config 3: d = 27, B in {1, 64, 1024}, 1e3 steps
-    cfg = W.config3(B=1024, nsteps=1000)
-    n, N = 729, cfg["nsteps"]
-    H, Lk = torch.from_numpy(cfg["H"]).to(dev), torch.from_numpy(cfg["Lk"]).to(dev)
-    t0 = time.perf_counter()
-    L = lb.liouvillian(H, Lk)
-    P = lb.propagator(L, cfg["dt"], ws=ws)
-    torch.cuda.synchronize()
-    build_ms = (time.perf_counter() - t0) * 1e3
-    X0 = torch.from_numpy(cfg["rho0"].reshape(-1, n)).to(dev)
-    d27 = {"build_ms": build_ms}
-    samples = {}
-    for B in (1, 64, 1024):
-        row = {}
-        for prec in ("c128", "c64", "bf16_hilo", "bf16_sliced", "baseline"):
-            nst = N if not (prec == "baseline" and B == 1024) else 100
-            x = X0[:B].clone()
-            variant = None
-            if prec != "baseline":
-                lb.tune(P, x, prec, probe_steps=20, repeats=2, ws=ws)
-                variant = lb.variant_name(lb.chain_variant(n, prec, B))
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            if prec == "baseline":
-                lb.propagate_baseline(P, x, nst, ws=ws)
-            else:
-                lb.propagate(P, x, nst, prec, ws=ws)
-            torch.cuda.synchronize()
-            dtm = time.perf_counter() - t0
-            row[prec] = {"state_steps_per_s": B * nst / dtm, "ms": dtm * 1e3, "nsteps": nst}
-            if variant:
-                row[prec]["variant"] = variant
-            if nst == N:
-                samples[(B, prec)] = x[:min(B, 2)].cpu().numpy()
-        d27[f"B{B}"] = row
-    # errors of the reduced precisions against the FP64 chain on the same
-    # states (the FP64 path itself is pinned to the oracle by the test suite)
-    for (B, prec), fin in samples.items():
-        ref = samples.get((B, "c128"))
-        if ref is not None and prec != "c128":
-            td = trace_distance(fin.reshape(-1, 27, 27), ref.reshape(-1, 27, 27))
-            d27[f"B{B}"][prec]["trace_distance_vs_c128"] = float(td.max())
-    out["d27_config3"] = d27
+    out["d27_config3"] = d27_section(lb, W, torch, dev, ws)
     # ---- config 4: GRAPE gradients, M = 200 slices of 1 ns
-    grape = {}
-    for q in (2, 3):
-        p = W.grape_problem(q, M=200)
-        Hc = torch.from_numpy(p["Hc"]).to(dev)
-        L0 = lb.liouvillian(torch.from_numpy(p["H0"]).to(dev), torch.from_numpy(p["Lk"]).to(dev))
-        Lc = torch.stack([lb.liouvillian(Hc[c], None) for c in range(Hc.shape[0])])
-        u = torch.from_numpy(p["u"]).to(dev)
-        x0 = torch.from_numpy(p["rho0"].reshape(-1)).to(dev)
-        w = torch.from_numpy(p["target"].reshape(-1)).to(dev)
-        lb.grape_gradient(L0, Lc, u, p["dt"], x0, w, ws=ws)  # warm
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        F, g = lb.grape_gradient(L0, Lc, u, p["dt"], x0, w, ws=ws)
-        torch.cuda.synchronize()
-        grape[f"d{3 ** q}"] = {"ms_per_gradient": (time.perf_counter() - t0) * 1e3, "M": 200,
-                               "controls": int(u.shape[1]), "F": F}
-    out["grape_config4"] = grape
+    out["grape_config4"] = grape_section(lb, W, torch, dev, ws)
     # ---- config 5: mixed batch of 256 problems, complex64 chains
     probs = W.mixed_batch()
     gp = []
@@ -549,7 +656,7 @@ def main():
     Pn = P.cpu().numpy()
 
     # ---- choose the headline variant
-    order = ["bf16_sliced", "c64", "bf16_hilo", "c128"]
+    order = ["i8_sliced", "bf16_sliced", "c64", "bf16_hilo", "c128"]
     prec = args.precision
     # ---- errors: the reduced precisions against the FP64 chain on the same
     #      sampled states; the FP64 chain against the oracle (CPU leg below)
@@ -596,10 +703,14 @@ def main():
     kernel_name = kernel_of(variant, prec)
     flops = paper_step_cost(d)[0] * B * N  # algorithmic: 8 n^2 per state-step (paper Eq. (4))
     achieved = flops / chain_s / 1e12
-    roofline = {"bound": bound, "achieved": achieved, "peak": PEAKS[peak_key], "unit": "TFLOP/s",
+    roofline = {"bound": bound, "achieved": achieved, "peak": PEAKS[peak_key],
+                "unit": "TOP/s" if peak_key == "int8_tops" else "TFLOP/s",
                 "frac": achieved / PEAKS[peak_key], "traffic": _traffic(kernel_name),
                 "kernel": kernel_name,
-                "kernel_ms": chain_s * 1e3}
+                "kernel_ms": chain_s * 1e3,
+                # the slice products the matrix cores execute (digit pairs x the
+                # algorithmic products), against the same peak
+                "executed_frac": achieved * EXECUTED_FACTOR.get(prec, 1.0) / PEAKS[peak_key]}
     out = {
         "metric": "state-steps/s at d=9/27: batched MFMA vs plain FP64 matvec at stated error",
         "value": value, "unit": "state-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

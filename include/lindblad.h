@@ -60,12 +60,23 @@ typedef enum {
                            Phi xhi + Phi xlo + Plo xhi on BF16 MFMA with FP32 accumulation */
     LB_BF16_SLICED = 3, /* exponent-aligned BF16 integer slices of P (per row) and of each
                            state (per state): every slice product sums exactly in the FP32
-                           MFMA accumulator; slice pairs are combined in FP64 */
+                           MFMA accumulator; slice pairs are combined in FP64.  One digit
+                           set for every call (5 digits of P, 4 of the state, levels <= 4),
+                           so a run split into several calls keeps the bound of one call */
     LB_Q15 = 4          /* the paper's fixed-point step (Alg. 5): P and the state quantised to
                            Q1.15 (16-bit, 15 fractional bits; round to nearest, ties to even,
                            saturating, so 1.0 becomes 1 - 2^-15), each step's sums exact in
                            64-bit integers, then floor(acc / 2^15) saturated.  Results are
-                           integers / 2^15, bitwise reproducible and independent of the kernel */
+                           integers / 2^15, bitwise reproducible and independent of the kernel */,
+    LB_I8_SLICED = 5    /* exponent-aligned INT8 digit slices on the INT8 matrix cores: the step
+                           as its real embedding [[Re P, -Im P], [Im P, Re P]] (2n x 2n); rows of
+                           that matrix scaled by their own power of two and rounded to 38
+                           fraction bits, five balanced base-256 digits; each state scaled by
+                           its own power of two, rounded to 30 fraction bits, four digits; the
+                           14 digit pairs of levels <= 4 summed EXACTLY in int32 accumulators
+                           over the whole k range, levels combined in FP64 and the state
+                           re-sliced every step.  One digit set for every call length.  Runs
+                           for n <= 96 (one fused launch); other n return LB_ENOTSUP */
 } lb_precision;
 
 typedef struct lb_workspace lb_workspace;
@@ -131,6 +142,23 @@ int lindblad_generators(int n, int M, int C, const void *L0, const void *Lc, con
  * only. */
 int lindblad_propagator(int n, int M, const void *L, const double *dt, double theta, void *P,
                         int *s_used, int *status, lb_workspace *ws, hipStream_t stream);
+
+/* The build of lindblad_propagator timed by stage, the method of the paper's
+ * build-time breakdown (Table "Build-time breakdown per landscape point"):
+ * HIP events recorded on `stream` at the stage boundaries give
+ *   stage_ms[0] the LU solve of the Pade denominator (Alg. 1 line 6),
+ *   stage_ms[1] the Pade products (powers, V, W, U: Alg. 1 lines 2-5),
+ *   stage_ms[2] the s squarings (line 7),
+ *   stage_ms[3] everything else (norm and scaling, V -/+ U, copies and the
+ *               host's part of the scaling stage),
+ * summed over the chunks the workspace splits the batch into.  Same
+ * arguments and result P as lindblad_propagator except: s_host is a HOST
+ * array of M ints (or NULL), the call synchronises the stream (a
+ * measurement call, not for pipelines) and data-dependent failures are
+ * returned (LB_ENONFINITE, LB_ESINGULAR) instead of written to a status
+ * word.  stage_ms: HOST array of 4 doubles. */
+int lindblad_propagator_stages(int n, int M, const void *L, const double *dt, double theta, void *P,
+                               int *s_host, double *stage_ms, lb_workspace *ws, hipStream_t stream);
 
 /* lindblad_propagator for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid

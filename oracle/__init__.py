@@ -303,15 +303,23 @@ def rel_fro(X, Xref):
     return np.linalg.norm((X - Xref).ravel()) / np.linalg.norm(Xref.ravel())
 
 
-def rel_per_state(X, Xref):
+def rel_per_state(X, Xref, X0=None):
     """Largest relative 2-norm error over the states of a batch: the rows of
     (B, n) arrays ((B, d, d) batches and single (n,) states are accepted), so
     one bad state cannot hide among good ones as it can in one Frobenius
-    norm over the batch.  A zero reference state counts its absolute error."""
+    norm over the batch.  A zero reference state counts its absolute error.
+
+    With X0 (the initial states) each error is taken relative to the larger
+    of the state's initial and final norms.  A chain under a contraction
+    that is not trace preserving (random test matrices) can shrink a state
+    by many orders of magnitude; its forward error is bounded by N times the
+    per-step rounding times the initial norm, not the final one."""
     X, Xref = np.asarray(X), np.asarray(Xref)
     B = 1 if X.ndim == 1 else X.shape[0]
     D = (X - Xref).reshape(B, -1)
     den = np.linalg.norm(Xref.reshape(B, -1), axis=1)
+    if X0 is not None:
+        den = np.maximum(den, np.linalg.norm(np.asarray(X0).reshape(B, -1), axis=1))
     den = np.where(den > 0, den, 1.0)
     return float((np.linalg.norm(D, axis=1) / den).max())
 

@@ -23,6 +23,7 @@ enum ChainFamily : int {
     VF_TAIL = 10,       // fused chain, rows 0..79 on MFMA, the rest on the VALU (n = 81); param = layout 0..3
     VF_TGEMM = 11,      // one LDS-tiled MFMA GEMM launch per step (64 states x 48 outputs); param = wavefronts 4 / 8, 1 = ring, 2 = ring + split k
     VF_TPLANES = 12,    // one LDS-tiled BF16 plane-GEMM launch per step (64 states x 48 outputs); param 1: ring-pipelined, 2: ring + split k
+    VF_I8_FUSED = 13,   // whole INT8-digit chain in one launch (LB_I8_SLICED, n <= i8_fused_max_n)
 };
 inline int variant_family(int v) { return v / 100; }
 inline int variant_param(int v) { return v % 100; }
@@ -44,12 +45,13 @@ int chain_balanced(int n, const cd *P, lb_precision prec, int B, cd *rho, long l
 bool tail_ok(int n, lb_precision prec);
 int chain_tail(int n, const cd *P, lb_precision prec, int layout, int B, cd *rho, long long nsteps, hipStream_t s);
 
-// Longest chain that runs with the 4 x 4-digit slice set (10 slice pairs);
-// longer chains use 5 x 4 digits (14 pairs).  Emulated and measured trace
-// distances of the short set grow about linearly with the step count and
-// reach ~8e-7 at 1e3 steps for d = 27, so the switch sits well before that.
-constexpr long long kSlicedShortRun = 600;
+// LB_BF16_SLICED always runs 5 x 4 digits with levels <= 4 (14 slice pairs),
+// whatever the call's step count: a long run issued as many short calls
+// keeps the bound of one long call, and the tuner's short probes time the
+// kernels that the real call runs.
 int bf16_fused_max_n(lb_precision prec);
+int i8_fused_max_n();
+int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s);
 int chain_bf16_fused(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
 
 int chain_gemm(int n, const cd *P, lb_precision prec, int wn, int B, cd *rho, long long nsteps, Workspace *ws,

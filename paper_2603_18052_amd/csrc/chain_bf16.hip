@@ -379,10 +379,7 @@ int bf16_fused_max_n(lb_precision prec) {
 
 int chain_bf16_fused(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s) {
     if (prec == LB_BF16_HILO) return bfc::launch<bfc::HILO, 2, 2, 1>(n, P, B, rho, nsteps, s);
-    // Slices chosen for a trace distance below 1e-6 at the requested length:
-    // 4 x 4 digits, levels <= 3 (10 slice pairs) up to kSlicedShortRun steps;
-    // 5 x 4 digits, levels <= 4 (14 pairs) beyond.
-    if (nsteps <= kSlicedShortRun) return bfc::launch<bfc::SLICED, 4, 4, 3>(n, P, B, rho, nsteps, s);
+    // 5 x 4 digits, levels <= 4 (14 slice pairs) for every step count
     return bfc::launch<bfc::SLICED, 5, 4, 4>(n, P, B, rho, nsteps, s);
 }
 

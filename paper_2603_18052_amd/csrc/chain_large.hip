@@ -1752,8 +1752,6 @@ int chain_planes(int n, const cd *P, lb_precision prec, int B, cd *rho, long lon
     switch (prec) {
         case LB_BF16_HILO: return planes_run<HILO, 2, 2, 1>(n, P, B, rho, nsteps, ws, s, graph, tiled);
         case LB_BF16_SLICED:
-            if (nsteps <= kSlicedShortRun)
-                return planes_run<SLICED, 4, 4, 3>(n, P, B, rho, nsteps, ws, s, graph, tiled);
             return planes_run<SLICED, 5, 4, 4>(n, P, B, rho, nsteps, ws, s, graph, tiled);
         default: return fail(LB_ENOTSUP, "plane chain: BF16 precisions only");
     }

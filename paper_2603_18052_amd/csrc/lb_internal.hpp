@@ -124,17 +124,25 @@ int zlincomb(int n, int batch, int nx, const cd *const *X, const double *coef, d
              hipStream_t s);
 
 // ------------------------------------------------------- propagator
+// Stage clock of a build (measurement only): events recorded on the build's
+// stream at the stage boundaries of every chunk, their intervals summed per
+// stage after the chunk's synchronisation: ms = {LU solve, Pade products,
+// squarings, other (scaling stage, V -/+ U, odd-s copy, host gaps)}.
+struct StageClock {
+    hipEvent_t ev[7] = {};
+    double ms[4] = {0, 0, 0, 0};
+};
 // Build P[m] = exp(L[m] dt[m]) (Alg. 1) into P; s_host receives s per m.
 // Uses the workspace; synchronises the stream.
 int build_propagators(int n, int M, const cd *L, const double *dt_host, double theta, cd *P, int *s_host,
-                      Workspace *ws, hipStream_t s);
+                      Workspace *ws, hipStream_t s, StageClock *clk = nullptr);
 // Workspace bytes build_propagators needs for a batch of M (chunked inside).
 size_t build_workspace_bytes(int n, int M);
 // Alg. 1 after its scaling stage for M matrices with d_dt, d_s on the device
 // and smax = max s known on the host; enqueue only (no host synchronisation),
 // zero pivots flagged in d_info (which must start at 0).  Workspace: build_async_bytes.
 int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *d_s, int smax, cd *P, int *d_info,
-                      Workspace *ws, hipStream_t s);
+                      Workspace *ws, hipStream_t s, StageClock *clk = nullptr);
 size_t build_async_bytes(int n, int M);
 
 // Alg. 1 for M generators without any host synchronisation: dt goes to the

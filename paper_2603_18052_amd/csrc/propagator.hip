@@ -171,7 +171,8 @@ size_t build_async_bytes(int n, int M) {
 // the device (smax = max s on the host): products, LU solve, squarings.
 // Enqueue only, no host synchronisation; zero pivots are flagged in d_info.
 int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *d_s, int smax, cd *P, int *d_info,
-                      Workspace *ws, hipStream_t s) {
+                      Workspace *ws, hipStream_t s, StageClock *clk) {
+    auto stage = [&](int i) { return clk ? hipEventRecord(clk->ev[i], s) : hipSuccess; };
     const size_t nn = (size_t)n * n;
     const size_t mat = nn * sizeof(cd) * M;
     LB_TRY(ws_ensure(ws, build_async_bytes(n, M)));
@@ -197,6 +198,7 @@ int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *
     LB_TRY(scale_launch(n, M, L, d_dt, d_s, A, s));
     // zero 64 x 16 tiles of the sparse left factors A and A2 are skipped
     LB_TRY(zgemm_tile_mask(n, n, M, A, n, (long long)nn, mA, s));
+    LB_HIP(stage(1));
     double b[14];
     pade13_coefficients(b);
     ZgemmBatch g;
@@ -246,13 +248,16 @@ int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *
         LB_TRY(zgemm_batched(h, s));
         LB_TRY(mul(A, Wp, U, mA));
     }
+    LB_HIP(stage(2));
     {  // denominator V - U into A2, numerator V + U into P
         const cd *X[2] = {V, U};
         const double cm[2] = {1.0, -1.0}, cp[2] = {1.0, 1.0};
         LB_TRY(zlincomb(n, M, 2, X, cm, 0.0, A2, s));
         LB_TRY(zlincomb(n, M, 2, X, cp, 0.0, P, s));
     }
+    LB_HIP(stage(3));
     LB_TRY(lu_solve_batched(n, n, M, A2, P, d_ipiv, d_info, s));
+    LB_HIP(stage(4));
     // squarings: level k reads buffer (k even ? P : A4) and writes the other;
     // matrices with s <= k are skipped.
     for (int k = 0; k < smax; ++k) {
@@ -266,6 +271,7 @@ int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *
         h.level = k;
         LB_TRY(zgemm_batched(h, s));
     }
+    LB_HIP(stage(5));
     if (smax > 0) LB_TRY(odd_copy_launch(n, M, d_s, A4, P, s));
     return LB_OK;
 }
@@ -273,7 +279,7 @@ int build_chunk_async(int n, int M, const cd *L, const double *d_dt, const int *
 // One chunk of matrices (all buffers sized for `M` matrices): scaling stage,
 // the asynchronous build, then the pivot check (two host synchronisations).
 static int build_chunk(int n, int M, const cd *L, const double *dt_host, double theta, cd *P, int *s_host,
-                       Workspace *ws, hipStream_t s) {
+                       Workspace *ws, hipStream_t s, StageClock *clk) {
     LB_TRY(ws_ensure(ws, chunk_bytes(n, M)));
     const size_t mark = ws->used;
     double *d_dt = (double *)ws_take(ws, M * sizeof(double));
@@ -286,16 +292,26 @@ static int build_chunk(int n, int M, const cd *L, const double *dt_host, double 
         ~Release() { w->used = m; }
     } release{ws, mark};
 
+    if (clk) LB_HIP(hipEventRecord(clk->ev[0], s));
     fill_i32_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_info, M);
     std::vector<int> sv(M);
     LB_TRY(scaling_stage(n, M, L, dt_host, theta, d_dt, d_norm, d_s, sv.data(), s));
     if (s_host) std::memcpy(s_host, sv.data(), M * sizeof(int));
     int smax = 0;
     for (int m = 0; m < M; ++m) smax = sv[m] > smax ? sv[m] : smax;
-    LB_TRY(build_chunk_async(n, M, L, d_dt, d_s, smax, P, d_info, ws, s));
+    LB_TRY(build_chunk_async(n, M, L, d_dt, d_s, smax, P, d_info, ws, s, clk));
+    if (clk) LB_HIP(hipEventRecord(clk->ev[6], s));
     std::vector<int> info(M);
     LB_HIP(hipMemcpyAsync(info.data(), d_info, M * sizeof(int), hipMemcpyDeviceToHost, s));
     LB_HIP(hipStreamSynchronize(s));
+    if (clk) {
+        float t[6];
+        for (int i = 0; i < 6; ++i) LB_HIP(hipEventElapsedTime(&t[i], clk->ev[i], clk->ev[i + 1]));
+        clk->ms[0] += t[3];                // LU solve
+        clk->ms[1] += t[1];                // Pade products
+        clk->ms[2] += t[4];                // squarings
+        clk->ms[3] += t[0] + t[2] + t[5];  // scaling stage, V -/+ U, odd-s copy
+    }
     for (int m = 0; m < M; ++m)
         if (info[m]) return fail(LB_ESINGULAR, "lindblad_propagator: zero pivot in V - U of generator " + std::to_string(m));
     return LB_OK;
@@ -411,7 +427,7 @@ static long long build_chunk_size(int n, int M, size_t avail) {
 size_t build_workspace_bytes(int n, int M) { return chunk_bytes(n, M); }
 
 int build_propagators(int n, int M, const cd *L, const double *dt_host, double theta, cd *P, int *s_host,
-                      Workspace *ws, hipStream_t s) {
+                      Workspace *ws, hipStream_t s, StageClock *clk) {
     // Chunk the batch so that the eight n x n temporaries per matrix fit in
     // what the workspace can still give (its cap when nothing is taken yet).
     const size_t avail = ws->used == 0 ? ws->cap : (ws->size > ws->used ? ws->size - ws->used : 0);
@@ -422,7 +438,7 @@ int build_propagators(int n, int M, const cd *L, const double *dt_host, double t
     for (int m0 = 0; m0 < M; m0 += (int)chunk) {
         const int mc = (int)((M - m0) < chunk ? (M - m0) : chunk);
         LB_TRY(build_chunk(n, mc, L + nn * m0, dt_host + m0, theta, P + nn * m0, s_host ? s_host + m0 : nullptr, ws,
-                           s));
+                           s, clk));
     }
     return LB_OK;
 }
@@ -452,6 +468,30 @@ extern "C" int lindblad_propagator(int n, int M, const void *L, const double *dt
     return build_propagators_async(n, M, static_cast<const cd *>(L), dt, theta, static_cast<cd *>(P), s_used, status,
                                    w, stream);
 }
+
+extern "C" int lindblad_propagator_stages(int n, int M, const void *L, const double *dt, double theta, void *P,
+                                          int *s_host, double *stage_ms, lb_workspace *ws, hipStream_t stream) {
+    LB_TRY(propagator_args("lindblad_propagator_stages", n, M, L, dt, theta, P));
+    if (!stage_ms) return fail(LB_EINVAL, "lindblad_propagator_stages: stage_ms is NULL");
+    Workspace *w = ws_resolve(ws);
+    ws_begin(w, stream);
+    StageClock clk;
+    int created = 0, rc = LB_OK;
+    for (; created < 7; ++created)
+        if (hipEventCreate(&clk.ev[created]) != hipSuccess) {
+            rc = fail(LB_EHIP, "lindblad_propagator_stages: hipEventCreate failed");
+            break;
+        }
+    if (rc == LB_OK)
+        rc = build_propagators(n, M, static_cast<const cd *>(L), dt, theta, static_cast<cd *>(P), s_host, w, stream,
+                               &clk);
+    if (rc != LB_OK) (void)hipStreamSynchronize(stream);  // events may still be pending
+    for (int i = 0; i < created; ++i) (void)hipEventDestroy(clk.ev[i]);
+    if (rc == LB_OK)
+        for (int i = 0; i < 4; ++i) stage_ms[i] = clk.ms[i];
+    return rc;
+}
+
 
 // ------------------------------------------------- allocation-free build
 // lindblad_propagator_noalloc runs the stream-ordered build above on a fixed

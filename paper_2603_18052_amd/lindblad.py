@@ -16,8 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblindblad.so")
 
 OK, EINVAL, ESHAPE, ENOMEM, EHIP, ESINGULAR, ENONFINITE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
-C128, C64, BF16_HILO, BF16_SLICED, Q15 = 0, 1, 2, 3, 4
-PRECISIONS = {"c128": C128, "c64": C64, "bf16_hilo": BF16_HILO, "bf16_sliced": BF16_SLICED, "q15": Q15}
+C128, C64, BF16_HILO, BF16_SLICED, Q15, I8_SLICED = 0, 1, 2, 3, 4, 5
+PRECISIONS = {"c128": C128, "c64": C64, "bf16_hilo": BF16_HILO, "bf16_sliced": BF16_SLICED, "q15": Q15,
+              "i8_sliced": I8_SLICED}
 
 SYMBOLS = {
     # name: (restype, argtypes)
@@ -36,6 +37,9 @@ SYMBOLS = {
                                                    ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                                    ctypes.c_void_p, ctypes.c_void_p]),
     "lindblad_propagator_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "lindblad_propagator_stages": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lindblad_propagate": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p, ctypes.c_void_p]),
     "lindblad_propagate_baseline": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -66,7 +70,8 @@ SYMBOLS = {
 
 # Chain variant families (id = family * 100 + tile parameter).
 VARIANT_FAMILIES = {1: "baseline", 2: "wave", 3: "fused", 4: "bf16_fused", 5: "gemm", 6: "matvec32", 7: "planes",
-                    8: "fused_balanced", 9: "q15", 10: "fused_tail", 11: "gemm_tiled", 12: "planes_tiled"}
+                    8: "fused_balanced", 9: "q15", 10: "fused_tail", 11: "gemm_tiled", 12: "planes_tiled",
+                    13: "i8_fused"}
 
 
 GRAPH_VARIANT = 50  # added to a per-step family: steps replayed from a captured HIP graph
@@ -238,6 +243,23 @@ def propagator(L: torch.Tensor, dt, theta: float = 0.25, ws: Workspace | None = 
         s = s_dev.tolist() if own else s_dev
         return P, (s[0] if single and own else s)
     return P
+
+
+def propagator_stages(L: torch.Tensor, dt, theta: float = 0.25, ws: Workspace | None = None):
+    """lindblad_propagator_stages: the build timed by stage.  Returns
+    (P, s list, {"solve", "pade_products", "squarings", "other"} in ms);
+    synchronises."""
+    L = _dev(L, name="L")
+    Lb = L.unsqueeze(0) if L.dim() == 2 else L
+    M, n = Lb.shape[0], Lb.shape[1]
+    dts = (ctypes.c_double * M)(*([float(dt)] * M if isinstance(dt, (int, float)) else [float(x) for x in dt]))
+    s_host = (ctypes.c_int * M)()
+    ms = (ctypes.c_double * 4)()
+    P = torch.empty_like(Lb)
+    _check(lib().lindblad_propagator_stages(n, M, _ptr(Lb), dts, float(theta), _ptr(P), s_host, ms, _ws(ws),
+                                            _stream()))
+    stages = dict(zip(("solve", "pade_products", "squarings", "other"), list(ms)))
+    return (P[0] if L.dim() == 2 else P), list(s_host), stages
 
 
 def propagator_noalloc(L: torch.Tensor, dt, P: torch.Tensor, theta: float = 0.25,
