@@ -76,7 +76,10 @@ typedef enum {
                            14 digit pairs of levels <= 4 summed EXACTLY in int32 accumulators
                            over the whole k range, levels combined in FP64 and the state
                            re-sliced every step.  One digit set for every call length.  Runs
-                           for n <= 96 (one fused launch); other n return LB_ENOTSUP */
+                           for n <= 96 (one fused launch); other n return LB_ENOTSUP */,
+    LB_Q31 = 6          /* the paper's fixed-point step at 31 fraction bits (its Q1.31 drift
+                           curve): LB_Q15's rules with 32-bit codes, sums exact in 128 bits,
+                           floor(acc / 2^31) saturated.  Bitwise reproducible; n <= 96 */
 } lb_precision;
 
 typedef struct lb_workspace lb_workspace;

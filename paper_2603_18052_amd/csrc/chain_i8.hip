@@ -1,0 +1,489 @@
+// Fused INT8-digit step chain (LB_I8_SLICED) on the INT8 matrix cores
+// (v_mfma_i32_16x16x64_i8), the whole chain in one launch with P resident in
+// registers as MFMA A fragments.
+//
+// Representation.  The complex step y = P x is run as its real embedding
+//     [yR; yI] = Q [xR; xI],   Q = [[PR, -PI], [PI, PR]]   (2n x 2n),
+// so every product is one real GEMM over k < 2n.
+//   P:  row r of Q is scaled by 2^-e_r (|Q[r, k]| < 2^e_r) and rounded to the
+//       integer V = rint(Q 2^(38 - e_r)), |V| <= 2^38, written as five
+//       balanced base-256 digits p_a in [-128, 127] (a = 0 most significant).
+//   x:  each state is scaled by 2^-S (|x_k| < 2^S for its largest |Re|,
+//       |Im|), rounded to the 31-bit integer V = rint(x 2^(30 - S)) and
+//       written as four balanced digits q_b.
+// All digit pairs of one level L = a + b <= 4 (14 pairs) accumulate in ONE
+// int32 MFMA accumulator: each product is an integer and a level sum is at
+// most 5 * 2n * 128^2 < 2^31 for n <= 96 (and for any n <= 1600), so the
+// matrix cores add them exactly, over the whole k range.  The levels are
+// combined in FP64, y = 2^(e_r + S - 12) sum_L 2^-8L acc_L; y is the state
+// of the next step, re-sliced with its own exact exponent.
+//
+// Balanced digits come from the two's-complement integer in two operations:
+// U = V + 0x80..80 (128 added at every digit below the top one) holds d + 128
+// in each low byte and the top digit in the top byte, so U ^ 0x80..80 is the
+// digits packed as int8, least significant first.
+//
+// Work split: 16 states per workgroup (the MFMA N), 8 wavefronts; wavefront
+// w owns 16-row tiles w and w + 8 of Q over all of k, so its outputs end each
+// step complete (no partial sums).  Per step: MFMAs (state digits read from
+// LDS as B fragments), combine in registers, per-state exponent by an LDS
+// max, barrier, slicing of the owned rows (four consecutive k of one state
+// per lane: each digit plane one 4-byte LDS write), barrier.
+#include "chain.hpp"
+
+namespace lb {
+
+typedef int i4v __attribute__((ext_vector_type(4)));
+
+namespace i8c {
+
+constexpr int NS = 16;      // states per workgroup (MFMA N)
+constexpr int WAVES = 8;    // wavefronts per workgroup (two per SIMD)
+constexpr int TPW = 2;      // 16-row tiles per wavefront, at most
+constexpr int KCMAX = 3;    // 64-deep k chunks, at most (2n <= 192)
+constexpr int MAXN = 96;
+constexpr int NPD = 5;      // digits of Q
+constexpr int NXD = 4;      // digits of the state
+constexpr int LMAX = 4;     // highest level kept: a + b <= 4, 14 pairs
+constexpr int FRAC_P = 38;  // fraction bits of Q's row-scaled integer
+constexpr int FRAC_X = 30;  // fraction bits of the state's integer
+constexpr int EMPTY = -100000;  // exponent of an all-zero state
+// y = 2^(e_r + S - YSHIFT) sum_L 2^-8L acc_L: the digits carry weights
+// 256^(NPD-1-a) 2^(e_r - FRAC_P) and 256^(NXD-1-b) 2^(S - FRAC_X)
+constexpr int YSHIFT = FRAC_P + FRAC_X - 8 * (NPD - 1) - 8 * (NXD - 1);
+
+__device__ inline i4v mma(i4v a, i4v b, i4v c) { return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0); }
+
+struct Shape {
+    int n2, mt, kc, stride, plane;
+};
+
+__host__ __device__ inline Shape shape(int n) {
+    Shape s;
+    s.n2 = 2 * n;
+    s.mt = (s.n2 + 15) / 16;
+    s.kc = (s.n2 + 63) / 64;
+    s.stride = s.kc * 64 + 32;  // 32 bytes off a multiple of 64: conflict-free 16-byte fragment reads
+    s.plane = NS * s.stride;
+    return s;
+}
+
+inline size_t lds_bytes(int n) {
+    const Shape s = shape(n);
+    return (size_t)NXD * s.plane + 2 * NS * sizeof(int) + (size_t)s.mt * 16 * sizeof(int);
+}
+
+// exponent e with |v| < 2^e (frexp's), EMPTY for 0
+__device__ inline int exp_of(double m) {
+    if (!(m > 0.0)) return EMPTY;
+    int e;
+    (void)frexp(m, &e);
+    return e;
+}
+
+// Q[R][k] of the real embedding, from P (n x n complex, row-major)
+__device__ inline double qval(const cd *__restrict__ P, int n, int R, int k) {
+    if (R >= 2 * n || k >= 2 * n) return 0.0;
+    const bool rim = R >= n, kim = k >= n;
+    const cd v = P[(size_t)(rim ? R - n : R) * n + (kim ? k - n : k)];
+    if (!rim) return kim ? -v.im : v.re;
+    return kim ? v.re : v.im;
+}
+
+__global__ void __launch_bounds__(WAVES * 64) i8_chain_kernel(int n, const cd *__restrict__ P, int B,
+                                                              cd *__restrict__ rho, long long nsteps) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Shape sh = shape(n);
+    signed char *xdig = reinterpret_cast<signed char *>(smem);        // [NXD][NS][stride]
+    int *smax = reinterpret_cast<int *>(smem + (size_t)NXD * sh.plane);  // [2][NS]
+    int *pexp = smax + 2 * NS;                                         // [mt * 16]
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int b0 = blockIdx.x * NS;
+    const int s = lane & 15;   // this lane's state (MFMA column)
+    const int grp = lane >> 4;  // this lane's row group within a tile
+
+    // ---- row exponents of Q (rows r and r + n share one)
+    for (int R = tid; R < sh.mt * 16; R += WAVES * 64) {
+        int e = 0;
+        if (R < sh.n2) {
+            const int r = R < n ? R : R - n;
+            double m = 0.0;
+            for (int k = 0; k < n; ++k) {
+                const cd v = P[(size_t)r * n + k];
+                m = fmax(m, fmax(fabs(v.re), fabs(v.im)));
+            }
+            e = m > 0.0 ? exp_of(m) : 0;
+        }
+        pexp[R] = e;
+    }
+    for (int i = tid; i < NXD * sh.plane / 4; i += WAVES * 64) reinterpret_cast<int *>(xdig)[i] = 0;
+    if (tid < 2 * NS) smax[tid] = EMPTY;
+    __syncthreads();
+
+    // ---- this wavefront's tiles and their Q digit fragments
+    const int ntile = (wave < sh.mt ? 1 : 0) + (wave + WAVES < sh.mt ? 1 : 0);
+    i4v pf[TPW][KCMAX][NPD];
+#pragma unroll
+    for (int tl = 0; tl < TPW; ++tl)
+#pragma unroll
+        for (int c = 0; c < KCMAX; ++c)
+#pragma unroll
+            for (int a = 0; a < NPD; ++a) pf[tl][c][a] = i4v{0, 0, 0, 0};
+#pragma unroll
+    for (int tl = 0; tl < TPW; ++tl) {
+        if (tl < ntile) {
+            const int R = (wave + tl * WAVES) * 16 + (lane & 15);
+            const int e = pexp[R];
+#pragma unroll
+            for (int c = 0; c < KCMAX; ++c) {
+                if (c < sh.kc) {
+                    unsigned w[NPD][4];
+#pragma unroll
+                    for (int a = 0; a < NPD; ++a)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) w[a][i] = 0u;
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int k = c * 64 + grp * 16 + q;
+                        const long long V = (long long)rint(ldexp(qval(P, n, R, k), FRAC_P - e));
+                        const unsigned long long U = (unsigned long long)(V + 0x80808080LL);
+#pragma unroll
+                        for (int j = 0; j < NPD; ++j) {  // j = 0 least significant
+                            const unsigned byte =
+                                j < NPD - 1 ? (unsigned)((U >> (8 * j)) & 0xFFu) ^ 0x80u
+                                            : (unsigned)((unsigned long long)((long long)U >> 32) & 0xFFu);
+                            w[NPD - 1 - j][q >> 2] |= byte << (8 * (q & 3));
+                        }
+                    }
+#pragma unroll
+                    for (int a = 0; a < NPD; ++a)
+                        pf[tl][c][a] = i4v{(int)w[a][0], (int)w[a][1], (int)w[a][2], (int)w[a][3]};
+                }
+            }
+        }
+    }
+
+    // ---- output rows of this lane: tile t, register r -> row 16 t + 4 grp + r
+    double y[TPW][4];
+    int S = 0;  // slicing exponent of this lane's state
+
+    // per-state exponent of y (LDS max), then the state's digits into LDS
+    auto publish = [&](int slot) {
+        int m = EMPTY;
+#pragma unroll
+        for (int tl = 0; tl < TPW; ++tl)
+            if (tl < ntile)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) m = max(m, exp_of(fabs(y[tl][r])));
+        m = max(m, __shfl_xor(m, 16));
+        m = max(m, __shfl_xor(m, 32));
+        if (grp == 0 && ntile > 0) atomicMax(smax + slot * NS + s, m);
+        __syncthreads();
+        const int mx = smax[slot * NS + s];
+        S = mx == EMPTY ? 0 : mx;
+        if (tid < NS) smax[(slot ^ 1) * NS + tid] = EMPTY;  // the next publish's slot (last read before a barrier)
+#pragma unroll
+        for (int tl = 0; tl < TPW; ++tl) {
+            if (tl < ntile) {
+                unsigned W[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int V = (int)rint(ldexp(y[tl][r], FRAC_X - S));  // |V| <= 2^30
+                    W[r] = (unsigned)(V + 0x00808080) ^ 0x00808080u;       // digits, least significant first
+                }
+                const int k0 = (wave + tl * WAVES) * 16 + grp * 4;
+#pragma unroll
+                for (int b = 0; b < NXD; ++b) {  // b = 0 most significant
+                    const int sh8 = 8 * (NXD - 1 - b);
+                    const unsigned D = ((W[0] >> sh8) & 0xFFu) | (((W[1] >> sh8) & 0xFFu) << 8) |
+                                       (((W[2] >> sh8) & 0xFFu) << 16) | (((W[3] >> sh8) & 0xFFu) << 24);
+                    *reinterpret_cast<unsigned *>(xdig + (size_t)b * sh.plane + s * sh.stride + k0) = D;
+                }
+            }
+        }
+        __syncthreads();
+    };
+
+    // ---- initial state
+#pragma unroll
+    for (int tl = 0; tl < TPW; ++tl)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            y[tl][r] = 0.0;
+            const int k = (wave + tl * WAVES) * 16 + grp * 4 + r;
+            if (tl < ntile && k < sh.n2 && b0 + s < B) {
+                const cd v = rho[(size_t)(b0 + s) * n + (k < n ? k : k - n)];
+                y[tl][r] = k < n ? v.re : v.im;
+            }
+        }
+    if (nsteps == 0) return;
+    publish(0);
+
+    for (long long t = 0; t < nsteps; ++t) {
+        const int slot = (int)((t + 1) & 1);
+        // ---- MFMA phase
+        i4v acc[TPW][LMAX + 1];
+#pragma unroll
+        for (int tl = 0; tl < TPW; ++tl)
+#pragma unroll
+            for (int L = 0; L <= LMAX; ++L) acc[tl][L] = i4v{0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < KCMAX; ++c) {
+            if (c < sh.kc) {  // uniform
+                i4v xf[NXD];
+#pragma unroll
+                for (int b = 0; b < NXD; ++b)
+                    xf[b] = *reinterpret_cast<const i4v *>(xdig + (size_t)b * sh.plane + s * sh.stride + c * 64 +
+                                                           grp * 16);
+#pragma unroll
+                for (int a = 0; a < NPD; ++a)
+#pragma unroll
+                    for (int b = 0; b < NXD; ++b)
+                        if (a + b <= LMAX)
+#pragma unroll
+                            for (int tl = 0; tl < TPW; ++tl)
+                                if (tl < ntile) acc[tl][a + b] = mma(pf[tl][c][a], xf[b], acc[tl][a + b]);
+            }
+        }
+        // ---- combine the levels (Horner, smallest first) and scale
+#pragma unroll
+        for (int tl = 0; tl < TPW; ++tl) {
+            if (tl < ntile) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double v = (double)acc[tl][LMAX][r];
+#pragma unroll
+                    for (int L = LMAX - 1; L >= 0; --L) v = fma(v, 1.0 / 256.0, (double)acc[tl][L][r]);
+                    const int R = (wave + tl * WAVES) * 16 + grp * 4 + r;
+                    y[tl][r] = ldexp(v, pexp[R] + S - YSHIFT);
+                }
+            }
+        }
+        if (t + 1 == nsteps) break;  // uniform
+        publish(slot);
+    }
+    // ---- write the final state
+#pragma unroll
+    for (int tl = 0; tl < TPW; ++tl)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = (wave + tl * WAVES) * 16 + grp * 4 + r;
+            if (tl < ntile && k < sh.n2 && b0 + s < B) {
+                double *o = reinterpret_cast<double *>(rho + (size_t)(b0 + s) * n + (k < n ? k : k - n));
+                o[k < n ? 0 : 1] = y[tl][r];
+            }
+        }
+}
+
+// ------------------------------------------------------------------
+// Fixed-point chain (Alg. 5) on the INT8 matrix cores: P and the state in
+// Q1.F (F = 15 or 31: a value v is the integer code c = v 2^F; P and the
+// incoming states quantised by round-to-nearest (ties to even) with
+// saturation to [-2^F, 2^F - 1]).  The real embedding's codes (the -Im P
+// block negated after quantisation, so its codes reach 2^F) and the state
+// codes are written as ND balanced base-256 digits (ND = 3 for F = 15, 5 for
+// F = 31: enough that every code, negated or not, is in range), ALL ND^2
+// digit pairs are summed in 2 ND - 1 level accumulators (each exact in
+// int32), and the levels are combined exactly in 128-bit integers:
+//     acc_r = sum_k Q_rk x_k = sum_L acc_L 256^(2 ND - 2 - L),
+// then x_r = sat(floor(acc_r / 2^F)) -- the oracle's integer step bit for
+// bit, whatever the summation order.  Same tiling as the sliced chain, one
+// barrier per step (no exponent to agree on).
+template <int ND, int FRAC, int TPWF>
+__global__ void __launch_bounds__(WAVES * 64) fx_chain_kernel(int n, const cd *__restrict__ P, int B,
+                                                              cd *__restrict__ rho, long long nsteps) {
+    constexpr int NL = 2 * ND - 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Shape sh = shape(n);
+    signed char *xdig = reinterpret_cast<signed char *>(smem);  // [ND][NS][stride]
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int b0 = blockIdx.x * NS;
+    const int s = lane & 15, grp = lane >> 4;
+    const long long cmax = (1LL << FRAC) - 1, cmin = -(1LL << FRAC);
+    auto quant = [&](double v) {  // round to nearest (ties to even), saturate
+        return (long long)fmax((double)cmin, fmin((double)cmax, rint(ldexp(v, FRAC))));
+    };
+    // code of Q[R][k]: quantised parts of P, the -Im block negated afterwards
+    auto qcode = [&](int R, int k) -> long long {
+        if (R >= sh.n2 || k >= sh.n2) return 0;
+        const bool rim = R >= n, kim = k >= n;
+        const cd v = P[(size_t)(rim ? R - n : R) * n + (kim ? k - n : k)];
+        if (!rim) return kim ? -quant(v.im) : quant(v.re);
+        return kim ? quant(v.re) : quant(v.im);
+    };
+    // ND balanced digits of |c| <= 2^(8 ND - 1) - 2^(8 ND - 9): byte j of
+    // c + 0x80..80 (ND - 1 offsets) xor 0x80 for j < ND - 1, the top digit by
+    // an arithmetic shift; returned packed per digit, least significant first
+    auto digit = [&](long long c, int j) -> unsigned {
+        long long off = 0;
+#pragma unroll
+        for (int i = 0; i < ND - 1; ++i) off |= 0x80LL << (8 * i);
+        const long long U = c + off;
+        if (j < ND - 1) return (unsigned)((U >> (8 * j)) & 0xFF) ^ 0x80u;
+        return (unsigned)((U >> (8 * (ND - 1))) & 0xFF);
+    };
+
+    for (int i = tid; i < ND * sh.plane / 4; i += WAVES * 64) reinterpret_cast<int *>(xdig)[i] = 0;
+    __syncthreads();
+
+    const int ntile = (wave < sh.mt ? 1 : 0) + (TPWF > 1 && wave + WAVES < sh.mt ? 1 : 0);
+    i4v pf[TPWF][KCMAX][ND];
+#pragma unroll
+    for (int tl = 0; tl < TPWF; ++tl)
+#pragma unroll
+        for (int c = 0; c < KCMAX; ++c)
+#pragma unroll
+            for (int a = 0; a < ND; ++a) pf[tl][c][a] = i4v{0, 0, 0, 0};
+#pragma unroll
+    for (int tl = 0; tl < TPWF; ++tl) {
+        if (tl < ntile) {
+            const int R = (wave + tl * WAVES) * 16 + (lane & 15);
+#pragma unroll
+            for (int c = 0; c < KCMAX; ++c) {
+                if (c < sh.kc) {
+                    unsigned w[ND][4];
+#pragma unroll
+                    for (int a = 0; a < ND; ++a)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) w[a][i] = 0u;
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const long long code = qcode(R, c * 64 + grp * 16 + q);
+#pragma unroll
+                        for (int j = 0; j < ND; ++j) w[ND - 1 - j][q >> 2] |= digit(code, j) << (8 * (q & 3));
+                    }
+#pragma unroll
+                    for (int a = 0; a < ND; ++a)
+                        pf[tl][c][a] = i4v{(int)w[a][0], (int)w[a][1], (int)w[a][2], (int)w[a][3]};
+                }
+            }
+        }
+    }
+
+    long long x[TPWF][4];  // state codes of this lane's rows
+    auto publish = [&]() {
+#pragma unroll
+        for (int tl = 0; tl < TPWF; ++tl) {
+            if (tl < ntile) {
+                const int k0 = (wave + tl * WAVES) * 16 + grp * 4;
+#pragma unroll
+                for (int b = 0; b < ND; ++b) {  // b = 0 most significant
+                    unsigned D = 0u;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) D |= digit(x[tl][r], ND - 1 - b) << (8 * r);
+                    *reinterpret_cast<unsigned *>(xdig + (size_t)b * sh.plane + s * sh.stride + k0) = D;
+                }
+            }
+        }
+        __syncthreads();
+    };
+
+#pragma unroll
+    for (int tl = 0; tl < TPWF; ++tl)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            x[tl][r] = 0;
+            const int k = (wave + tl * WAVES) * 16 + grp * 4 + r;
+            if (tl < ntile && k < sh.n2 && b0 + s < B) {
+                const cd v = rho[(size_t)(b0 + s) * n + (k < n ? k : k - n)];
+                x[tl][r] = quant(k < n ? v.re : v.im);
+            }
+        }
+    if (nsteps == 0) return;
+    publish();
+
+    for (long long t = 0; t < nsteps; ++t) {
+        i4v acc[TPWF][NL];
+#pragma unroll
+        for (int tl = 0; tl < TPWF; ++tl)
+#pragma unroll
+            for (int L = 0; L < NL; ++L) acc[tl][L] = i4v{0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < KCMAX; ++c) {
+            if (c < sh.kc) {
+                i4v xf[ND];
+#pragma unroll
+                for (int b = 0; b < ND; ++b)
+                    xf[b] = *reinterpret_cast<const i4v *>(xdig + (size_t)b * sh.plane + s * sh.stride + c * 64 +
+                                                           grp * 16);
+#pragma unroll
+                for (int a = 0; a < ND; ++a)
+#pragma unroll
+                    for (int b = 0; b < ND; ++b)
+#pragma unroll
+                        for (int tl = 0; tl < TPWF; ++tl)
+                            if (tl < ntile) acc[tl][a + b] = mma(pf[tl][c][a], xf[b], acc[tl][a + b]);
+            }
+        }
+        __syncthreads();  // every wavefront's fragment reads are done before the digits are rewritten
+#pragma unroll
+        for (int tl = 0; tl < TPWF; ++tl) {
+            if (tl < ntile) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    __int128 Y = 0;
+#pragma unroll
+                    for (int L = 0; L < NL; ++L) Y += (__int128)acc[tl][L][r] << (8 * (NL - 1 - L));
+                    const __int128 q = Y >> FRAC;  // floor division by 2^F
+                    x[tl][r] = q < (__int128)cmin ? cmin : (q > (__int128)cmax ? cmax : (long long)q);
+                }
+            }
+        }
+        if (t + 1 == nsteps) break;  // uniform
+        publish();
+    }
+#pragma unroll
+    for (int tl = 0; tl < TPWF; ++tl)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = (wave + tl * WAVES) * 16 + grp * 4 + r;
+            if (tl < ntile && k < sh.n2 && b0 + s < B) {
+                double *o = reinterpret_cast<double *>(rho + (size_t)(b0 + s) * n + (k < n ? k : k - n));
+                o[k < n ? 0 : 1] = ldexp((double)x[tl][r], -FRAC);
+            }
+        }
+}
+
+static const size_t kLds = 160 * 1024;
+
+}  // namespace i8c
+
+int i8_fused_max_n() { return i8c::MAXN; }
+int fx_i8_max_n() { return i8c::MAXN; }
+
+// Alg. 5 on the INT8 matrix cores (LB_Q15: 3 digits, LB_Q31: 5 digits);
+// one 16-row tile per wavefront up to n = 64, two up to 96.
+int chain_fx_i8(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s) {
+    using namespace i8c;
+    if (n > MAXN) return fail(LB_ESHAPE, "fixed-point INT8 chain: n <= 96");
+    if (prec != LB_Q15 && prec != LB_Q31) return fail(LB_EINVAL, "fixed-point INT8 chain: LB_Q15 or LB_Q31");
+    if (nsteps == 0 || B == 0) return LB_OK;
+    const int nd = prec == LB_Q15 ? 3 : 5;
+    const size_t lds = (size_t)nd * shape(n).plane;
+    const dim3 grid((B + NS - 1) / NS), block(WAVES * 64);
+    const bool two = shape(n).mt > WAVES;
+    if (prec == LB_Q15) {
+        if (two)
+            fx_chain_kernel<3, 15, 2><<<grid, block, lds, s>>>(n, P, B, rho, nsteps);
+        else
+            fx_chain_kernel<3, 15, 1><<<grid, block, lds, s>>>(n, P, B, rho, nsteps);
+    } else {
+        if (two)
+            fx_chain_kernel<5, 31, 2><<<grid, block, lds, s>>>(n, P, B, rho, nsteps);
+        else
+            fx_chain_kernel<5, 31, 1><<<grid, block, lds, s>>>(n, P, B, rho, nsteps);
+    }
+    return check_launch("fx_i8_chain");
+}
+
+int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
+    if (n > i8c::MAXN) return fail(LB_ESHAPE, "i8 chain: n too large for the fused kernel");
+    if (nsteps == 0 || B == 0) return LB_OK;
+    const size_t lds = i8c::lds_bytes(n);
+    i8c::i8_chain_kernel<<<(B + i8c::NS - 1) / i8c::NS, i8c::WAVES * 64, lds, s>>>(n, P, B, rho, nsteps);
+    return check_launch("i8_chain");
+}
+
+}  // namespace lb

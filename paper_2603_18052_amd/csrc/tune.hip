@@ -86,6 +86,8 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
     } else if (prec == LB_Q15) {
         if (n <= kWaveChainMaxN) add(VF_Q15 * 100);
         add2(VF_Q15 * 100 + 1);
+    } else if (prec == LB_I8_SLICED) {
+        if (n <= i8_fused_max_n()) add(VF_I8_FUSED * 100);
     }
     return c;
 }
@@ -130,6 +132,8 @@ int chain_heuristic(int n, lb_precision prec, int B) {
         }
         case LB_Q15:
             return n <= kWaveChainMaxN ? VF_Q15 * 100 : VF_Q15 * 100 + 1;
+        case LB_I8_SLICED:
+            return n <= i8_fused_max_n() ? VF_I8_FUSED * 100 : 0;
         default:
             return 0;
     }
@@ -170,6 +174,7 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_TAIL: return chain_tail(n, P, prec, prm, B, rho, nsteps, s);
         case VF_TGEMM: return chain_tgemm(n, P, prec, prm, B, rho, nsteps, ws, s, graph);
         case VF_TPLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s, graph, prm == 0 ? 1 : prm + 1);
+        case VF_I8_FUSED: return chain_i8_fused(n, P, B, rho, nsteps, s);
         default: return fail(LB_EINVAL, "unknown chain variant");
     }
 }
@@ -178,6 +183,7 @@ int chain_run(int n, const cd *P, lb_precision prec, int B, cd *rho, long long n
     if (nsteps == 0 || B == 0) return LB_OK;
     int v = tuned_variant(n, prec, B);
     if (v == 0) v = chain_heuristic(n, prec, B);
+    if (v == 0) return fail(LB_ENOTSUP, "no chain kernel for this precision at n = " + std::to_string(n));
     return chain_run_variant(n, P, prec, B, rho, nsteps, v, ws, s);
 }
 
@@ -186,7 +192,7 @@ int chain_run(int n, const cd *P, lb_precision prec, int B, cd *rho, long long n
 using namespace lb;
 
 static int check_prec(const char *who, lb_precision prec) {
-    if ((int)prec < LB_C128 || (int)prec > LB_Q15) return fail(LB_EINVAL, std::string(who) + ": bad precision");
+    if ((int)prec < LB_C128 || (int)prec > LB_I8_SLICED) return fail(LB_EINVAL, std::string(who) + ": bad precision");
     return LB_OK;
 }
 
