@@ -312,44 +312,46 @@ def timing_models_section(lb, W, torch, dev):
 
 
 def fixed_point_section(lb, W, torch, dev, ws):
-    """Alg. 5 on the GPU (LB_Q15): the paper's d = 3 fixed-point drift model
+    """Alg. 5 on the GPU (LB_Q15, and LB_Q31 for the paper's Q1.31 curve): the paper's d = 3 fixed-point drift model
     from |0><0|, trace distance / trace loss |Re Tr rho - 1| / |delta p1|
     against the FP64 chain after 1 ... 1e4 steps (the columns of the paper's
     board-drift table; Im Tr rho reported beside them), and the fixed-point
     chain's rate."""
     out = {}
-    for name, drive in (("undriven", 0.0), ("driven", 0.05)):
-        H, Lk, dt, rho0 = W.paper_fixed_point_model(drive)
-        P = lb.propagator(lb.liouvillian(torch.from_numpy(H).to(dev), torch.from_numpy(Lk).to(dev)), dt, ws=ws)
-        rows = {}
-        for N in (1, 10, 100, 1000, 10000):
-            xq = torch.from_numpy(rho0.reshape(1, 9).copy()).to(dev)
-            xd = xq.clone()
-            lb.propagate(P, xq, N, "q15", ws=ws)
-            lb.propagate(P, xd, N, "c128", ws=ws)
-            q, r = xq.cpu().numpy().reshape(3, 3), xd.cpu().numpy().reshape(3, 3)
-            rows[f"N{N}"] = {"trace_distance": float(trace_distance(q[None], r[None])[0]),
-                             "trace_loss": float(abs(np.trace(q).real - 1.0)),
-                             "im_trace": float(np.trace(q).imag),
-                             "abs_delta_p1": float(abs(q[1, 1].real - r[1, 1].real))}
-        out[name] = rows
+    for word in ("q15", "q31"):
+        for name, drive in (("undriven", 0.0), ("driven", 0.05)):
+            H, Lk, dt, rho0 = W.paper_fixed_point_model(drive)
+            P = lb.propagator(lb.liouvillian(torch.from_numpy(H).to(dev), torch.from_numpy(Lk).to(dev)), dt, ws=ws)
+            rows = {}
+            for N in (1, 10, 100, 1000, 10000):
+                xq = torch.from_numpy(rho0.reshape(1, 9).copy()).to(dev)
+                xd = xq.clone()
+                lb.propagate(P, xq, N, word, ws=ws)
+                lb.propagate(P, xd, N, "c128", ws=ws)
+                q, r = xq.cpu().numpy().reshape(3, 3), xd.cpu().numpy().reshape(3, 3)
+                rows[f"N{N}"] = {"trace_distance": float(trace_distance(q[None], r[None])[0]),
+                                 "trace_loss": float(abs(np.trace(q).real - 1.0)),
+                                 "im_trace": float(np.trace(q).imag),
+                                 "abs_delta_p1": float(abs(q[1, 1].real - r[1, 1].real))}
+            out[name if word == "q15" else f"{name}_q31"] = rows
     # rates: one state at d = 3 (one wavefront), 4096 states at d = 9 (per-row matvec)
-    for key, q_, B, N in (("d3_B1", 1, 1, 10000), ("d9_B4096", 2, 4096, 200)):
+    for key, q_, B, N, word in (("d3_B1", 1, 1, 10000, "q15"), ("d9_B4096", 2, 4096, 2000, "q15"),
+                                ("d3_B1_q31", 1, 1, 10000, "q31"), ("d9_B4096_q31", 2, 4096, 2000, "q31")):
         d = 3 ** q_
         Hs, Lks = W.transmon_system(q_)
         P = lb.propagator(lb.liouvillian(torch.from_numpy(Hs).to(dev), torch.from_numpy(Lks).to(dev)), W.DT_NS,
                           ws=ws)
         x = torch.from_numpy(W.wishart_batch(d, B, 8).reshape(B, d * d)).to(dev)
-        lb.propagate(P, x.clone(), 10, "q15", ws=ws)
+        lb.propagate(P, x.clone(), 10, word, ws=ws)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record()
-        lb.propagate(P, x, N, "q15", ws=ws)
+        lb.propagate(P, x, N, word, ws=ws)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         out[f"rate_{key}"] = {"state_steps_per_s": B * N / (ms * 1e-3), "ns_per_step": ms * 1e6 / N,
-                              "variant": lb.variant_name(lb.chain_variant(d * d, "q15", B))}
+                              "variant": lb.variant_name(lb.chain_variant(d * d, word, B))}
     return out
 
 
@@ -567,7 +569,7 @@ def extra_sections(lb, W, torch, dev, ws):
     (config 5)."""
     out = {"d3_config1": config1_section(lb, W, torch, dev, ws),
            "timing_models": timing_models_section(lb, W, torch, dev),
-           "fixed_point_q15": fixed_point_section(lb, W, torch, dev, ws),
+           "fixed_point": fixed_point_section(lb, W, torch, dev, ws),
            "expmv_report": expmv_section(lb, W, torch, dev, ws)}
     # ---- config 3: d = 27, B in {1, 64, 1024}, 1e3 steps
     out["d27_config3"] = d27_section(lb, W, torch, dev, ws)

@@ -75,8 +75,10 @@ typedef enum {
                            its own power of two, rounded to 30 fraction bits, four digits; the
                            14 digit pairs of levels <= 4 summed EXACTLY in int32 accumulators
                            over the whole k range, levels combined in FP64 and the state
-                           re-sliced every step.  One digit set for every call length.  Runs
-                           for n <= 96 (one fused launch); other n return LB_ENOTSUP */,
+                           re-sliced every step.  One digit set for every call length.  One
+                           fused launch for n <= 96; beyond, one INT8 GEMM launch per step, the
+                           next state sliced below 2^(M + g) with M the exponent of the previous
+                           state's largest entry and 2^g the largest row sum of the embedding */,
     LB_Q31 = 6          /* the paper's fixed-point step at 31 fraction bits (its Q1.31 drift
                            curve): LB_Q15's rules with 32-bit codes, sums exact in 128 bits,
                            floor(acc / 2^31) saturated.  Bitwise reproducible; n <= 96 */

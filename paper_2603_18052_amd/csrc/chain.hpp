@@ -24,6 +24,8 @@ enum ChainFamily : int {
     VF_TGEMM = 11,      // one LDS-tiled MFMA GEMM launch per step (64 states x 48 outputs); param = wavefronts 4 / 8, 1 = ring, 2 = ring + split k
     VF_TPLANES = 12,    // one LDS-tiled BF16 plane-GEMM launch per step (64 states x 48 outputs); param 1: ring-pipelined, 2: ring + split k
     VF_I8_FUSED = 13,   // whole INT8-digit chain in one launch (LB_I8_SLICED, n <= i8_fused_max_n)
+    VF_FX_I8 = 14,      // fixed-point chain (LB_Q15, LB_Q31) on the INT8 matrix cores, one launch (n <= 96)
+    VF_I8_GEMM = 15,    // one LDS-tiled INT8-digit GEMM launch per step (LB_I8_SLICED, any n)
 };
 inline int variant_family(int v) { return v / 100; }
 inline int variant_param(int v) { return v % 100; }
@@ -52,6 +54,10 @@ int chain_tail(int n, const cd *P, lb_precision prec, int layout, int B, cd *rho
 int bf16_fused_max_n(lb_precision prec);
 int i8_fused_max_n();
 int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s);
+int fx_i8_max_n();
+size_t i8_gemm_ws_bytes(int n, int B);
+int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s, bool graph);
+int chain_fx_i8(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
 int chain_bf16_fused(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
 
 int chain_gemm(int n, const cd *P, lb_precision prec, int wn, int B, cd *rho, long long nsteps, Workspace *ws,

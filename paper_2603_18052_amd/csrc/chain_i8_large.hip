@@ -1,0 +1,378 @@
+// INT8-digit chain (LB_I8_SLICED) past the fused limit (n > 96): one
+// LDS-tiled INT8 GEMM launch per step on v_mfma_i32_16x16x64_i8.
+//
+// The representation is the fused kernel's (chain_i8.hip): the real
+// embedding Q = [[PR, -PI], [PI, PR]] (2n x 2n), each row scaled by its own
+// power of two and rounded to 38 fraction bits in five balanced base-256
+// digits; each state rounded to 30 fraction bits below its own power of two
+// in four digits; the 14 digit pairs of levels <= 4 summed exactly in int32
+// over the whole k range (a level sum is at most 5 * 2n * 2^14 < 2^31 for
+// n <= 4096), levels combined in FP64.
+//
+// One difference: a step cannot agree on the new state's exponent before
+// slicing it (that would need a grid-wide barrier), so state x_{t+1} is sliced
+// below 2^(M_t + g), where M_t is the exponent of max |x_t| (the previous
+// step's, complete when the step starts) and 2^g bounds the growth of one
+// step: 2^g >= max_r sum_k |Q_rk| >= max |x_{t+1}| / max |x_t|.  Each step
+// records M_{t+1} with atomic maxima for the step after it; four slots of
+// exponents rotate so that a step reads two, writes one and clears one.
+// The FP64 state exists only in the epilogue: the step's output is sliced
+// straight into the next step's digit planes (four consecutive k of one
+// state per lane: one 4-byte write per digit plane).
+//
+// Tile: 96 rows of Q x 64 states per workgroup (256 workgroups at n = 729,
+// B = 1024), four wavefronts in a 2 x 2 grid of 48 rows x 32 states each;
+// k in 64-deep chunks staged through two LDS buffers (47 KB each) with the
+// next chunk's loads held in registers during the current chunk's MFMAs;
+// 64-byte digit rows stored at XOR-swizzled 16-byte positions so that the
+// operand fetches run without bank conflicts.  Workgroups are ordered so that
+// those sharing a row block of Q sit on one XCD (its L2 holds the block).
+#include "chain.hpp"
+
+namespace lb {
+namespace i8g {
+
+typedef int i4v __attribute__((ext_vector_type(4)));
+
+constexpr int NPD = 5, NXD = 4, LMAX = 4;
+constexpr int FRAC_P = 38, FRAC_X = 30;
+constexpr int YSHIFT = FRAC_P + FRAC_X - 8 * (NPD - 1) - 8 * (NXD - 1);  // 12
+constexpr int EMPTY = -100000;
+constexpr int TR = 96, TS = 64, KC = 64;  // rows, states, k per chunk
+constexpr int RT = 3, ST = 2;             // 16-row / 16-state tiles per wavefront
+constexpr int APL = TR * KC, BPL = TS * KC;
+constexpr int STAGE = NPD * APL + NXD * BPL;  // 47104 bytes
+constexpr int NLD = STAGE / 16;               // 16-byte loads per chunk (2944)
+constexpr int LPT = (NLD + 255) / 256;        // per thread (12)
+constexpr int XLIM = (1 << FRAC_X) - 1;
+
+__device__ inline i4v mma(i4v a, i4v b, i4v c) { return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0); }
+__device__ inline int swz(int row, int piece) { return piece ^ ((row >> 1) & 3); }
+
+__device__ inline int exp_of(double m) {
+    if (!(m > 0.0)) return EMPTY;
+    int e;
+    (void)frexp(m, &e);
+    return e;
+}
+
+// Q[R][k] of the real embedding
+__device__ inline double qval(const cd *__restrict__ P, int n, int R, int k) {
+    if (R >= 2 * n || k >= 2 * n) return 0.0;
+    const bool rim = R >= n, kim = k >= n;
+    const cd v = P[(size_t)(rim ? R - n : R) * n + (kim ? k - n : k)];
+    if (!rim) return kim ? -v.im : v.re;
+    return kim ? v.re : v.im;
+}
+
+// digits of a row of Q (one workgroup per row): exponent, five planes, and
+// the row's absolute sum into gbits (atomic max of the non-negative bits)
+__global__ void __launch_bounds__(256) prep_q_kernel(int n, int Kp, const cd *__restrict__ P,
+                                                     signed char *__restrict__ Qd, int *__restrict__ eP,
+                                                     unsigned long long *__restrict__ gbits) {
+    const int R = blockIdx.x, tid = threadIdx.x;
+    const int r = R < n ? R : R - n;
+    double m = 0.0, sum = 0.0;
+    for (int k = tid; k < n; k += 256) {
+        const cd v = P[(size_t)r * n + k];
+        m = fmax(m, fmax(fabs(v.re), fabs(v.im)));
+        sum += fabs(v.re) + fabs(v.im);
+    }
+    __shared__ double rm[256], rs[256];
+    rm[tid] = m;
+    rs[tid] = sum;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+            rm[tid] = fmax(rm[tid], rm[tid + w]);
+            rs[tid] += rs[tid + w];
+        }
+        __syncthreads();
+    }
+    const int e = rm[0] > 0.0 ? exp_of(rm[0]) : 0;
+    if (tid == 0) {
+        eP[R] = e;
+        atomicMax(gbits, (unsigned long long)__double_as_longlong(rs[0]));
+    }
+    const size_t plane = (size_t)2 * n * Kp;
+    for (int k0 = 4 * tid; k0 < Kp; k0 += 4 * 256) {
+        unsigned w[NPD] = {0u, 0u, 0u, 0u, 0u};
+        for (int q = 0; q < 4; ++q) {
+            const long long V = (long long)rint(ldexp(qval(P, n, R, k0 + q), FRAC_P - e));
+            const unsigned long long U = (unsigned long long)(V + 0x80808080LL);
+            for (int j = 0; j < NPD; ++j) {
+                const unsigned byte = j < NPD - 1 ? (unsigned)((U >> (8 * j)) & 0xFFu) ^ 0x80u
+                                                  : (unsigned)((unsigned long long)((long long)U >> 32) & 0xFFu);
+                w[NPD - 1 - j] |= byte << (8 * q);
+            }
+        }
+        for (int a = 0; a < NPD; ++a) *reinterpret_cast<unsigned *>(Qd + a * plane + (size_t)R * Kp + k0) = w[a];
+    }
+}
+
+// growth bound g (2^g >= max row sum, 0 for contractions) from gbits
+__device__ inline int growth_bits(const unsigned long long *gbits) {
+    const double s = __longlong_as_double((long long)*gbits) * (1.0 + 0x1p-20);
+    return s > 1.0 ? exp_of(s) : 0;
+}
+
+// initial state of each state (one workgroup per state): exact exponent
+// M_0, digits of x_0 into buffer 0 (zeros past 2n), zero padding of buffer
+// 1, and the exponent slots: slot 3 = M_0 - g (so that S_0 = M_0), slot 0 =
+// M_0, slots 1 and 2 empty
+__global__ void __launch_bounds__(256) init_x_kernel(int n, int Kp, int B, const cd *__restrict__ rho,
+                                                     signed char *__restrict__ X0, signed char *__restrict__ X1,
+                                                     int *__restrict__ Mx, const unsigned long long *__restrict__ gbits) {
+    const int b = blockIdx.x, tid = threadIdx.x, n2 = 2 * n;
+    const cd *x = rho + (size_t)b * n;
+    int m = EMPTY;
+    for (int k = tid; k < n; k += 256) m = max(m, max(exp_of(fabs(x[k].re)), exp_of(fabs(x[k].im))));
+    __shared__ int red[256];
+    red[tid] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] = max(red[tid], red[tid + w]);
+        __syncthreads();
+    }
+    const int M0 = red[0];
+    const int S = M0 == EMPTY ? 0 : M0;
+    const size_t plane = (size_t)B * Kp;
+    for (int k0 = 4 * tid; k0 < Kp; k0 += 4 * 256) {
+        unsigned W[4];
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + q;
+            const double v = k < n ? x[k].re : (k < n2 ? x[k - n].im : 0.0);
+            int V = (int)rint(ldexp(v, FRAC_X - S));
+            V = V > XLIM ? XLIM : (V < -XLIM ? -XLIM : V);
+            W[q] = (unsigned)(V + 0x00808080) ^ 0x00808080u;
+        }
+        for (int bd = 0; bd < NXD; ++bd) {
+            const int sh = 8 * (NXD - 1 - bd);
+            const unsigned D = ((W[0] >> sh) & 0xFFu) | (((W[1] >> sh) & 0xFFu) << 8) | (((W[2] >> sh) & 0xFFu) << 16) |
+                               (((W[3] >> sh) & 0xFFu) << 24);
+            *reinterpret_cast<unsigned *>(X0 + bd * plane + (size_t)b * Kp + k0) = D;
+            if (k0 + 4 > n2) *reinterpret_cast<unsigned *>(X1 + bd * plane + (size_t)b * Kp + k0) = 0u;
+        }
+    }
+    if (tid == 0) {
+        const int g = growth_bits(gbits);
+        Mx[3 * B + b] = M0 == EMPTY ? EMPTY : M0 - g;
+        Mx[0 * B + b] = M0;
+        Mx[1 * B + b] = EMPTY;
+        Mx[2 * B + b] = EMPTY;
+    }
+}
+
+// one step: x_{t+1} = Q x_t for all states (t4 = t mod 4); the last step
+// writes FP64 into rho instead of digits
+__global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B, int nrb, int nsb,
+                                                           const signed char *__restrict__ Qd,
+                                                           const int *__restrict__ eP,
+                                                           const signed char *__restrict__ Xc,
+                                                           signed char *__restrict__ Xn, int *__restrict__ Mx,
+                                                           const unsigned long long *__restrict__ gbits, int t4,
+                                                           int last, cd *__restrict__ rho) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n2 = 2 * n;
+    // tile order: consecutive tiles (row-block major) on one XCD
+    const int total = nrb * nsb, per = total / 8, rem = total % 8;
+    const int xcd = blockIdx.x % 8, jx = blockIdx.x / 8;
+    const int T = xcd * per + (xcd < rem ? xcd : rem) + jx;
+    const int rb = T / nsb, sb = T - rb * nsb;
+    const int r0 = rb * TR, s0 = sb * TS;
+    const size_t qplane = (size_t)n2 * Kp, xplane = (size_t)B * Kp;
+    const int nch = Kp / KC;
+
+    // this thread's loads of a chunk: A (Q digits) then B (state digits)
+    const signed char *src[LPT];
+    int dst[LPT];
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+        int j = tid + 256 * q;
+        j = j < NLD ? j : NLD - 1;  // the tail repeats the last load
+        if (j < NPD * TR * 4) {
+            const int a = j / (TR * 4), rr = j - a * (TR * 4), row = rr >> 2, pc = rr & 3;
+            int R = r0 + row;
+            R = R < n2 ? R : n2 - 1;
+            src[q] = Qd + a * qplane + (size_t)R * Kp + pc * 16;
+            dst[q] = a * APL + row * 64 + swz(row, pc) * 16;
+        } else {
+            const int jj = j - NPD * TR * 4;
+            const int bd = jj / (TS * 4), rr = jj - bd * (TS * 4), st = rr >> 2, pc = rr & 3;
+            int b = s0 + st;
+            b = b < B ? b : B - 1;
+            src[q] = Xc + bd * xplane + (size_t)b * Kp + pc * 16;
+            dst[q] = NPD * APL + bd * BPL + st * 64 + swz(st, pc) * 16;
+        }
+    }
+    i4v pre[LPT];
+    auto fetch = [&](int c) {
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) pre[q] = *reinterpret_cast<const i4v *>(src[q] + (size_t)c * KC);
+    };
+    auto stash = [&](int stage) {
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) *reinterpret_cast<i4v *>(smem + stage * STAGE + dst[q]) = pre[q];
+    };
+
+    const int wr = (wave & 1) * (RT * 16), ws = (wave >> 1) * (ST * 16);  // this wavefront's rows / states
+    const int fr = lane & 15, fp = lane >> 4;
+    i4v acc[RT][ST][LMAX + 1];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < ST; ++j)
+#pragma unroll
+            for (int L = 0; L <= LMAX; ++L) acc[i][j][L] = i4v{0, 0, 0, 0};
+
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        if (c + 1 < nch) fetch(c + 1);
+        const unsigned char *st = smem + (c & 1) * STAGE;
+        i4v xb[ST][NXD];
+#pragma unroll
+        for (int j = 0; j < ST; ++j) {
+            const int s = ws + 16 * j + fr;
+#pragma unroll
+            for (int bd = 0; bd < NXD; ++bd)
+                xb[j][bd] = *reinterpret_cast<const i4v *>(st + NPD * APL + bd * BPL + s * 64 + swz(s, fp) * 16);
+        }
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            const int row = wr + 16 * i + fr;
+            i4v pa[NPD];
+#pragma unroll
+            for (int a = 0; a < NPD; ++a)
+                pa[a] = *reinterpret_cast<const i4v *>(st + a * APL + row * 64 + swz(row, fp) * 16);
+#pragma unroll
+            for (int a = 0; a < NPD; ++a)
+#pragma unroll
+                for (int bd = 0; bd < NXD; ++bd)
+                    if (a + bd <= LMAX)
+#pragma unroll
+                        for (int j = 0; j < ST; ++j) acc[i][j][a + bd] = mma(pa[a], xb[j][bd], acc[i][j][a + bd]);
+        }
+        if (c + 1 < nch) stash((c + 1) & 1);
+        __syncthreads();
+    }
+
+    // ---- epilogue
+    const int g = growth_bits(gbits);
+    const int *Mcur = Mx + ((t4 + 3) & 3) * B;  // x_t was sliced below 2^(Mcur + g)
+    const int *Mnow = Mx + t4 * B;              // exponent of max |x_t|
+    int *Mnext = Mx + ((t4 + 1) & 3) * B;       // exponent of max |x_{t+1}|, by atomics
+    if (!last && rb == 0 && tid < TS && s0 + tid < B) Mx[((t4 + 2) & 3) * B + s0 + tid] = EMPTY;
+#pragma unroll
+    for (int j = 0; j < ST; ++j) {
+        const int b = s0 + ws + 16 * j + fr;
+        const bool bok = b < B;
+        const int mc = bok ? Mcur[b] : 0;
+        const int Sc = mc == EMPTY ? 0 : mc + g;
+        const int mn = bok ? Mnow[b] : 0;
+        const int Sn = mn == EMPTY ? 0 : mn + g;
+        int emax = EMPTY;
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            const int R0 = r0 + wr + 16 * i + 4 * fp;  // four consecutive rows of this lane
+            double y[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double v = (double)acc[i][j][LMAX][r];
+#pragma unroll
+                for (int L = LMAX - 1; L >= 0; --L) v = fma(v, 1.0 / 256.0, (double)acc[i][j][L][r]);
+                const int R = R0 + r;
+                y[r] = (bok && R < n2) ? ldexp(v, eP[R] + Sc - YSHIFT) : 0.0;
+                emax = max(emax, exp_of(fabs(y[r])));
+            }
+            if (last) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int R = R0 + r;
+                    if (bok && R < n2) {
+                        double *o = reinterpret_cast<double *>(rho + (size_t)b * n + (R < n ? R : R - n));
+                        o[R < n ? 0 : 1] = y[r];
+                    }
+                }
+            } else if (bok && R0 < Kp) {
+                unsigned W[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    int V = (int)rint(ldexp(y[r], FRAC_X - Sn));
+                    V = V > XLIM ? XLIM : (V < -XLIM ? -XLIM : V);
+                    W[r] = (unsigned)(V + 0x00808080) ^ 0x00808080u;
+                }
+#pragma unroll
+                for (int bd = 0; bd < NXD; ++bd) {
+                    const int sh = 8 * (NXD - 1 - bd);
+                    const unsigned D = ((W[0] >> sh) & 0xFFu) | (((W[1] >> sh) & 0xFFu) << 8) |
+                                       (((W[2] >> sh) & 0xFFu) << 16) | (((W[3] >> sh) & 0xFFu) << 24);
+                    *reinterpret_cast<unsigned *>(Xn + bd * xplane + (size_t)b * Kp + R0) = D;
+                }
+            }
+        }
+        if (!last) {
+            emax = max(emax, __shfl_xor(emax, 16));
+            emax = max(emax, __shfl_xor(emax, 32));
+            if (fp == 0 && bok && emax != EMPTY) atomicMax(Mnext + b, emax);
+        }
+    }
+}
+
+static int grid1(long long work) {
+    long long g = (work + 255) / 256;
+    if (g > 65536) g = 65536;
+    return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace i8g
+
+size_t i8_gemm_ws_bytes(int n, int B) {
+    const size_t Kp = (size_t)(2 * n + 63) / 64 * 64;
+    return align256((size_t)i8g::NPD * 2 * n * Kp) + align256((size_t)2 * n * 4) +
+           2 * align256((size_t)i8g::NXD * B * Kp) + align256((size_t)4 * B * 4) + 256;
+}
+
+int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s, bool graph) {
+    using namespace i8g;
+    if (nsteps == 0 || B == 0) return LB_OK;
+    const int n2 = 2 * n, Kp = (n2 + 63) / 64 * 64;
+    LB_TRY(ws_ensure(ws, i8_gemm_ws_bytes(n, B)));
+    const size_t mark = ws->used;
+    signed char *Qd = (signed char *)ws_take(ws, (size_t)NPD * n2 * Kp);
+    int *eP = (int *)ws_take(ws, (size_t)n2 * 4);
+    signed char *X0 = (signed char *)ws_take(ws, (size_t)NXD * B * Kp);
+    signed char *X1 = (signed char *)ws_take(ws, (size_t)NXD * B * Kp);
+    int *Mx = (int *)ws_take(ws, (size_t)4 * B * 4);
+    unsigned long long *gbits = (unsigned long long *)ws_take(ws, 256);
+    struct Release {
+        Workspace *w;
+        size_t m;
+        ~Release() { w->used = m; }
+    } release{ws, mark};
+    LB_TRY(fill_i32_launch(reinterpret_cast<int *>(gbits), 2, s));
+    prep_q_kernel<<<n2, 256, 0, s>>>(n, Kp, P, Qd, eP, gbits);
+    LB_TRY(check_launch("i8 prep_q"));
+    init_x_kernel<<<B, 256, 0, s>>>(n, Kp, B, rho, X0, X1, Mx, gbits);
+    LB_TRY(check_launch("i8 init_x"));
+    static bool attr = false;
+    if (!attr) {
+        LB_HIP(hipFuncSetAttribute((const void *)i8_gemm_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   2 * STAGE));
+        attr = true;
+    }
+    const int nrb = (n2 + TR - 1) / TR, nsb = (B + TS - 1) / TS;
+    LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
+        const bool last = t + 1 == nsteps;
+        i8_gemm_step_kernel<<<nrb * nsb, 256, 2 * STAGE, st>>>(n, Kp, B, nrb, nsb, Qd, eP, (t & 1) ? X1 : X0,
+                                                              (t & 1) ? X0 : X1, Mx, gbits, (int)(t & 3),
+                                                              last ? 1 : 0, rho);
+        return LB_OK;
+    }, s));
+    return check_launch("i8 gemm step");
+}
+
+}  // namespace lb

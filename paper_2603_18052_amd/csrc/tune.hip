@@ -86,8 +86,12 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
     } else if (prec == LB_Q15) {
         if (n <= kWaveChainMaxN) add(VF_Q15 * 100);
         add2(VF_Q15 * 100 + 1);
+        if (n <= fx_i8_max_n()) add(VF_FX_I8 * 100);
+    } else if (prec == LB_Q31) {
+        if (n <= fx_i8_max_n()) add(VF_FX_I8 * 100);
     } else if (prec == LB_I8_SLICED) {
         if (n <= i8_fused_max_n()) add(VF_I8_FUSED * 100);
+        add2(VF_I8_GEMM * 100);
     }
     return c;
 }
@@ -131,9 +135,12 @@ int chain_heuristic(int n, lb_precision prec, int B) {
             return VF_TPLANES * 100 + 2;  // the ring kernel, k split over workgroups below 256 tiles
         }
         case LB_Q15:
-            return n <= kWaveChainMaxN ? VF_Q15 * 100 : VF_Q15 * 100 + 1;
+            if (n <= kWaveChainMaxN) return VF_Q15 * 100;
+            return n <= fx_i8_max_n() ? VF_FX_I8 * 100 : VF_Q15 * 100 + 1;
+        case LB_Q31:
+            return n <= fx_i8_max_n() ? VF_FX_I8 * 100 : 0;
         case LB_I8_SLICED:
-            return n <= i8_fused_max_n() ? VF_I8_FUSED * 100 : 0;
+            return n <= i8_fused_max_n() ? VF_I8_FUSED * 100 : VF_I8_GEMM * 100;
         default:
             return 0;
     }
@@ -151,6 +158,7 @@ size_t chain_ws_bytes(int n, lb_precision prec, int B, int variant) {
     const int fam = variant_family(variant);
     if (fam == VF_BASELINE) return align256((size_t)B * n * sizeof(cd));  // same for the graph twin
     if (fam == VF_Q15) return q15_ws_bytes(n, B, variant_param(variant) == 0);
+    if (fam == VF_I8_GEMM) return i8_gemm_ws_bytes(n, B);
     return large_ws_bytes(fam, n, prec, B);
 }
 
@@ -175,6 +183,8 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_TGEMM: return chain_tgemm(n, P, prec, prm, B, rho, nsteps, ws, s, graph);
         case VF_TPLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s, graph, prm == 0 ? 1 : prm + 1);
         case VF_I8_FUSED: return chain_i8_fused(n, P, B, rho, nsteps, s);
+        case VF_FX_I8: return chain_fx_i8(n, P, prec, B, rho, nsteps, s);
+        case VF_I8_GEMM: return chain_i8_gemm(n, P, B, rho, nsteps, ws, s, graph);
         default: return fail(LB_EINVAL, "unknown chain variant");
     }
 }
@@ -192,7 +202,7 @@ int chain_run(int n, const cd *P, lb_precision prec, int B, cd *rho, long long n
 using namespace lb;
 
 static int check_prec(const char *who, lb_precision prec) {
-    if ((int)prec < LB_C128 || (int)prec > LB_I8_SLICED) return fail(LB_EINVAL, std::string(who) + ": bad precision");
+    if ((int)prec < LB_C128 || (int)prec > LB_Q31) return fail(LB_EINVAL, std::string(who) + ": bad precision");
     return LB_OK;
 }
 

@@ -16,9 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblindblad.so")
 
 OK, EINVAL, ESHAPE, ENOMEM, EHIP, ESINGULAR, ENONFINITE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
-C128, C64, BF16_HILO, BF16_SLICED, Q15, I8_SLICED = 0, 1, 2, 3, 4, 5
+C128, C64, BF16_HILO, BF16_SLICED, Q15, I8_SLICED, Q31 = 0, 1, 2, 3, 4, 5, 6
 PRECISIONS = {"c128": C128, "c64": C64, "bf16_hilo": BF16_HILO, "bf16_sliced": BF16_SLICED, "q15": Q15,
-              "i8_sliced": I8_SLICED}
+              "i8_sliced": I8_SLICED, "q31": Q31}
 
 SYMBOLS = {
     # name: (restype, argtypes)
@@ -71,7 +71,7 @@ SYMBOLS = {
 # Chain variant families (id = family * 100 + tile parameter).
 VARIANT_FAMILIES = {1: "baseline", 2: "wave", 3: "fused", 4: "bf16_fused", 5: "gemm", 6: "matvec32", 7: "planes",
                     8: "fused_balanced", 9: "q15", 10: "fused_tail", 11: "gemm_tiled", 12: "planes_tiled",
-                    13: "i8_fused"}
+                    13: "i8_fused", 14: "fx_i8", 15: "i8_gemm"}
 
 
 GRAPH_VARIANT = 50  # added to a per-step family: steps replayed from a captured HIP graph

@@ -58,7 +58,7 @@ def test_validation_errors_without_gpu(L):
     assert L.lindblad_propagate(9, 1, 0, 0, 1, 1, None, None) == lb.ESHAPE
     assert L.lindblad_propagate(9, 1, 0, 1, 1, -1, None, None) == lb.EINVAL
     assert L.lindblad_propagate(9, 1, 9, 1, 1, 1, None, None) == lb.EINVAL
-    assert L.lindblad_propagate(9, 1, 5, 1, 1, 1, None, None) == lb.EINVAL  # past the last precision
+    assert L.lindblad_propagate(9, 1, 7, 1, 1, 1, None, None) == lb.EINVAL  # past the last precision
     assert L.lindblad_propagate(9, None, 0, 1, 1, 1, None, None) == lb.EINVAL
     assert L.lindblad_propagate_baseline(5000, 1, 1, 1, 1, None, None) == lb.ESHAPE
 
@@ -115,9 +115,14 @@ def test_chain_variant_lists_and_rule(L):
     assert lb.chain_variant(729, "bf16_hilo", 16) == 1202
     assert lb.chain_variant(729, "bf16_sliced", 1024) == 1202  # ring plane GEMM (256 tiles: no k split)
     # fixed point: one wavefront per state for n <= 16, else the per-row matvec (and its graph twin)
-    assert lb.chain_variants(9, "q15", 1) == [900, 901, 951]
+    assert lb.chain_variants(9, "q15", 1) == [900, 901, 951, 1400]
     assert lb.chain_variants(729, "q15", 3) == [901, 951]
-    assert lb.chain_variant(81, "q15", 16) == 901
+    assert lb.chain_variant(81, "q15", 16) == 1400  # the INT8-core kernel up to n = 96
+    assert lb.chain_variant(729, "q15", 16) == 901
+    # Q1.31 and the INT8-digit chain: one fused INT8-core kernel each, n <= 96
+    assert lb.chain_variants(9, "q31", 1) == [1400] and lb.chain_variants(97, "q31", 1) == []
+    assert lb.chain_variants(81, "i8_sliced", 4096) == [1300, 1500, 1550] and lb.chain_variant(96, "i8_sliced", 1) == 1300
+    assert lb.chain_variants(729, "i8_sliced", 64) == [1500, 1550] and lb.chain_variant(729, "i8_sliced", 1024) == 1500
     # tuning table: set, read back, reject a variant the shape lacks, clear
     lb.tune_set(81, "c128", 4096, 502)
     assert lb.chain_variant(81, "c128", 4096) == 502
