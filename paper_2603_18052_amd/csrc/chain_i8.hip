@@ -70,7 +70,7 @@ __host__ __device__ inline Shape shape(int n) {
 
 inline size_t lds_bytes(int n) {
     const Shape s = shape(n);
-    return (size_t)NXD * s.plane + 2 * NS * sizeof(int) + (size_t)s.mt * 16 * sizeof(int);
+    return (size_t)2 * NXD * s.plane + (4 * NS + 2 * (NS + 1)) * sizeof(int) + (size_t)s.mt * 16 * sizeof(int);
 }
 
 // exponent e with |v| < 2^e (frexp's), EMPTY for 0
@@ -90,20 +90,201 @@ __device__ inline double qval(const cd *__restrict__ P, int n, int R, int k) {
     return kim ? v.re : v.im;
 }
 
+// The chain as run by one wavefront that owns NT row tiles over KC k chunks
+// (both fixed at compile time, so the step loop has no branches).  Every
+// wavefront of the workgroup runs the same number of barriers.
+template <int NT, int KC>
+__device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__ rho, long long nsteps,
+                        unsigned char *smem, int wave, int lane) {
+    constexpr int NTA = NT > 0 ? NT : 1;
+    const Shape sh = shape(n);
+    signed char *xdig = reinterpret_cast<signed char *>(smem);                 // [2][NXD][NS][stride]
+    int *mexp = reinterpret_cast<int *>(smem + (size_t)2 * NXD * sh.plane);  // [4][NS]
+    int *oflag = mexp + 4 * NS;                                               // [2][NS + 1]
+    int *pexp = oflag + 2 * (NS + 1);                                         // [mt * 16]
+    const int tid = threadIdx.x;
+    const int b0 = blockIdx.x * NS;
+    const int s = lane & 15, grp = lane >> 4;
+    const size_t buf = (size_t)NXD * sh.plane;
+
+    // ---- Q digit fragments of this wavefront's tiles
+    i4v pf[NTA][KC][NPD];
+#pragma unroll
+    for (int tl = 0; tl < NT; ++tl) {
+        const int R = (wave + tl * WAVES) * 16 + (lane & 15);
+        const int e = pexp[R];
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            unsigned w[NPD][4];
+#pragma unroll
+            for (int a = 0; a < NPD; ++a)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[a][i] = 0u;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = c * 64 + grp * 16 + q;
+                const long long V = (long long)rint(ldexp(qval(P, n, R, k), FRAC_P - e));
+                const unsigned long long U = (unsigned long long)(V + 0x80808080LL);
+#pragma unroll
+                for (int j = 0; j < NPD; ++j) {  // j = 0 least significant
+                    const unsigned byte = j < NPD - 1
+                                              ? (unsigned)((U >> (8 * j)) & 0xFFu) ^ 0x80u
+                                              : (unsigned)((unsigned long long)((long long)U >> 32) & 0xFFu);
+                    w[NPD - 1 - j][q >> 2] |= byte << (8 * (q & 3));
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < NPD; ++a) pf[tl][c][a] = i4v{(int)w[a][0], (int)w[a][1], (int)w[a][2], (int)w[a][3]};
+        }
+    }
+
+    // ---- output rows of this lane: tile (wave + 8 tl), register r -> row 16 (wave + 8 tl) + 4 grp + r
+    double y[NTA][4];
+    int ey[NTA][4];  // exponents of |y|
+    // the digits of y below 2^S into buffer `to` (four consecutive k of one state: one word per plane)
+    auto slice = [&](int S, int to) {
+#pragma unroll
+        for (int tl = 0; tl < NT; ++tl) {
+            unsigned W[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int V = (int)rint(ldexp(y[tl][r], FRAC_X - S));  // |V| <= 2^30
+                W[r] = (unsigned)(V + 0x00808080) ^ 0x00808080u;       // digits, least significant first
+            }
+            const int k0 = (wave + tl * WAVES) * 16 + grp * 4;
+#pragma unroll
+            for (int b = 0; b < NXD; ++b) {  // b = 0 most significant
+                const int sh8 = 8 * (NXD - 1 - b);
+                const unsigned D = ((W[0] >> sh8) & 0xFFu) | (((W[1] >> sh8) & 0xFFu) << 8) |
+                                   (((W[2] >> sh8) & 0xFFu) << 16) | (((W[3] >> sh8) & 0xFFu) << 24);
+                *reinterpret_cast<unsigned *>(xdig + to * buf + (size_t)b * sh.plane + s * sh.stride + k0) = D;
+            }
+        }
+    };
+    // largest exponent of this lane's state over its rows, reduced over the lane group
+    auto state_exp = [&]() {
+        int m = EMPTY;
+#pragma unroll
+        for (int tl = 0; tl < NT; ++tl)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) m = max(m, ey[tl][r]);
+        m = max(m, __shfl_xor(m, 16));
+        return max(m, __shfl_xor(m, 32));
+    };
+
+    // ---- initial state: its exact exponent, digits into buffer 0
+#pragma unroll
+    for (int tl = 0; tl < NT; ++tl)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            y[tl][r] = 0.0;
+            const int k = (wave + tl * WAVES) * 16 + grp * 4 + r;
+            if (k < sh.n2 && b0 + s < B) {
+                const cd v = rho[(size_t)(b0 + s) * n + (k < n ? k : k - n)];
+                y[tl][r] = k < n ? v.re : v.im;
+            }
+            ey[tl][r] = exp_of(fabs(y[tl][r]));
+        }
+    {
+        const int m = state_exp();
+        if (NT > 0 && grp == 0) atomicMax(mexp + s, m);
+    }
+    __syncthreads();
+    int Sx = mexp[s] == EMPTY ? 0 : mexp[s];  // the exponent the current state's digits were sliced with
+    slice(Sx, 0);
+    __syncthreads();
+
+    for (long long t = 0; t < nsteps; ++t) {
+        const int cur = (int)(t & 1);
+        // ---- MFMA phase
+        i4v acc[NTA][LMAX + 1];
+#pragma unroll
+        for (int tl = 0; tl < NT; ++tl)
+#pragma unroll
+            for (int L = 0; L <= LMAX; ++L) acc[tl][L] = i4v{0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            i4v xf[NXD];
+#pragma unroll
+            for (int b = 0; b < NXD; ++b)
+                xf[b] = *reinterpret_cast<const i4v *>(xdig + cur * buf + (size_t)b * sh.plane + s * sh.stride +
+                                                       c * 64 + grp * 16);
+#pragma unroll
+            for (int a = 0; a < NPD; ++a)
+#pragma unroll
+                for (int b = 0; b < NXD; ++b)
+                    if (a + b <= LMAX)
+#pragma unroll
+                        for (int tl = 0; tl < NT; ++tl) acc[tl][a + b] = mma(pf[tl][c][a], xf[b], acc[tl][a + b]);
+        }
+        // ---- combine the levels (Horner, smallest first) and scale
+#pragma unroll
+        for (int tl = 0; tl < NT; ++tl)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double v = (double)acc[tl][LMAX][r];
+#pragma unroll
+                for (int L = LMAX - 1; L >= 0; --L) v = fma(v, 1.0 / 256.0, (double)acc[tl][L][r]);
+                const int R = (wave + tl * WAVES) * 16 + grp * 4 + r;
+                y[tl][r] = ldexp(v, pexp[R] + Sx - YSHIFT);
+                ey[tl][r] = exp_of(fabs(y[tl][r]));
+            }
+        if (t + 1 == nsteps) break;  // uniform
+        // ---- slice below the previous state's exponent M_t (speculative: the
+        // state rarely crosses a power of two in one step); a state that did
+        // is flagged and re-sliced below its own exponent after the barrier
+        const int Mt = mexp[(t & 3) * NS + s];
+        const int Sspec = Mt == EMPTY ? 0 : Mt;
+        const int m = state_exp();
+        bool over = false;
+#pragma unroll
+        for (int tl = 0; tl < NT; ++tl)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) over |= ey[tl][r] > Sspec && ey[tl][r] != EMPTY;
+        slice(Sspec, cur ^ 1);
+        int *of = oflag + cur * (NS + 1);
+        if (NT > 0 && grp == 0) atomicMax(mexp + ((t + 1) & 3) * NS + s, m);
+        if (over) {
+            atomicOr(of + s, 1);
+            atomicOr(of + NS, 1);
+        }
+        if (tid < NS) mexp[((t + 2) & 3) * NS + tid] = EMPTY;     // last read two steps ago
+        if (tid <= NS) oflag[(cur ^ 1) * (NS + 1) + tid] = 0;      // last read a step ago
+        __syncthreads();
+        Sx = Sspec;
+        if (of[NS]) {  // uniform: some state of the workgroup outgrew its exponent
+            if (of[s]) {
+                const int Mn = mexp[((t + 1) & 3) * NS + s];
+                Sx = Mn == EMPTY ? 0 : Mn;
+                slice(Sx, cur ^ 1);
+            }
+            __syncthreads();
+        }
+    }
+    // ---- write the final state
+#pragma unroll
+    for (int tl = 0; tl < NT; ++tl)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = (wave + tl * WAVES) * 16 + grp * 4 + r;
+            if (k < sh.n2 && b0 + s < B) {
+                double *o = reinterpret_cast<double *>(rho + (size_t)(b0 + s) * n + (k < n ? k : k - n));
+                o[k < n ? 0 : 1] = y[tl][r];
+            }
+        }
+}
+
 __global__ void __launch_bounds__(WAVES * 64) i8_chain_kernel(int n, const cd *__restrict__ P, int B,
                                                               cd *__restrict__ rho, long long nsteps) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Shape sh = shape(n);
-    signed char *xdig = reinterpret_cast<signed char *>(smem);        // [NXD][NS][stride]
-    int *smax = reinterpret_cast<int *>(smem + (size_t)NXD * sh.plane);  // [2][NS]
-    int *pexp = smax + 2 * NS;                                         // [mt * 16]
+    int *mexp = reinterpret_cast<int *>(smem + (size_t)2 * NXD * sh.plane);
+    int *oflag = mexp + 4 * NS;
+    int *pexp = oflag + 2 * (NS + 1);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int b0 = blockIdx.x * NS;
-    const int s = lane & 15;   // this lane's state (MFMA column)
-    const int grp = lane >> 4;  // this lane's row group within a tile
 
-    // ---- row exponents of Q (rows r and r + n share one)
+    // ---- row exponents of Q (rows r and r + n share one), cleared buffers and slots
     for (int R = tid; R < sh.mt * 16; R += WAVES * 64) {
         int e = 0;
         if (R < sh.n2) {
@@ -117,163 +298,23 @@ __global__ void __launch_bounds__(WAVES * 64) i8_chain_kernel(int n, const cd *_
         }
         pexp[R] = e;
     }
-    for (int i = tid; i < NXD * sh.plane / 4; i += WAVES * 64) reinterpret_cast<int *>(xdig)[i] = 0;
-    if (tid < 2 * NS) smax[tid] = EMPTY;
+    for (int i = tid; i < 2 * NXD * sh.plane / 4; i += WAVES * 64) reinterpret_cast<int *>(smem)[i] = 0;
+    if (tid < 4 * NS) mexp[tid] = EMPTY;
+    if (tid < 2 * (NS + 1)) oflag[tid] = 0;
+    if (nsteps == 0) return;  // uniform
     __syncthreads();
-
-    // ---- this wavefront's tiles and their Q digit fragments
     const int ntile = (wave < sh.mt ? 1 : 0) + (wave + WAVES < sh.mt ? 1 : 0);
-    i4v pf[TPW][KCMAX][NPD];
-#pragma unroll
-    for (int tl = 0; tl < TPW; ++tl)
-#pragma unroll
-        for (int c = 0; c < KCMAX; ++c)
-#pragma unroll
-            for (int a = 0; a < NPD; ++a) pf[tl][c][a] = i4v{0, 0, 0, 0};
-#pragma unroll
-    for (int tl = 0; tl < TPW; ++tl) {
-        if (tl < ntile) {
-            const int R = (wave + tl * WAVES) * 16 + (lane & 15);
-            const int e = pexp[R];
-#pragma unroll
-            for (int c = 0; c < KCMAX; ++c) {
-                if (c < sh.kc) {
-                    unsigned w[NPD][4];
-#pragma unroll
-                    for (int a = 0; a < NPD; ++a)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) w[a][i] = 0u;
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        const int k = c * 64 + grp * 16 + q;
-                        const long long V = (long long)rint(ldexp(qval(P, n, R, k), FRAC_P - e));
-                        const unsigned long long U = (unsigned long long)(V + 0x80808080LL);
-#pragma unroll
-                        for (int j = 0; j < NPD; ++j) {  // j = 0 least significant
-                            const unsigned byte =
-                                j < NPD - 1 ? (unsigned)((U >> (8 * j)) & 0xFFu) ^ 0x80u
-                                            : (unsigned)((unsigned long long)((long long)U >> 32) & 0xFFu);
-                            w[NPD - 1 - j][q >> 2] |= byte << (8 * (q & 3));
-                        }
-                    }
-#pragma unroll
-                    for (int a = 0; a < NPD; ++a)
-                        pf[tl][c][a] = i4v{(int)w[a][0], (int)w[a][1], (int)w[a][2], (int)w[a][3]};
-                }
-            }
-        }
+    // wave-uniform dispatch to the compile-time shape
+    switch (ntile * 4 + sh.kc) {
+        case 0 * 4 + 1: i8_body<0, 1>(n, P, B, rho, nsteps, smem, wave, lane); break;
+        case 0 * 4 + 2: i8_body<0, 2>(n, P, B, rho, nsteps, smem, wave, lane); break;
+        case 0 * 4 + 3: i8_body<0, 3>(n, P, B, rho, nsteps, smem, wave, lane); break;
+        case 1 * 4 + 1: i8_body<1, 1>(n, P, B, rho, nsteps, smem, wave, lane); break;
+        case 1 * 4 + 2: i8_body<1, 2>(n, P, B, rho, nsteps, smem, wave, lane); break;
+        case 1 * 4 + 3: i8_body<1, 3>(n, P, B, rho, nsteps, smem, wave, lane); break;
+        case 2 * 4 + 2: i8_body<2, 2>(n, P, B, rho, nsteps, smem, wave, lane); break;
+        default: i8_body<2, 3>(n, P, B, rho, nsteps, smem, wave, lane); break;
     }
-
-    // ---- output rows of this lane: tile t, register r -> row 16 t + 4 grp + r
-    double y[TPW][4];
-    int S = 0;  // slicing exponent of this lane's state
-
-    // per-state exponent of y (LDS max), then the state's digits into LDS
-    auto publish = [&](int slot) {
-        int m = EMPTY;
-#pragma unroll
-        for (int tl = 0; tl < TPW; ++tl)
-            if (tl < ntile)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) m = max(m, exp_of(fabs(y[tl][r])));
-        m = max(m, __shfl_xor(m, 16));
-        m = max(m, __shfl_xor(m, 32));
-        if (grp == 0 && ntile > 0) atomicMax(smax + slot * NS + s, m);
-        __syncthreads();
-        const int mx = smax[slot * NS + s];
-        S = mx == EMPTY ? 0 : mx;
-        if (tid < NS) smax[(slot ^ 1) * NS + tid] = EMPTY;  // the next publish's slot (last read before a barrier)
-#pragma unroll
-        for (int tl = 0; tl < TPW; ++tl) {
-            if (tl < ntile) {
-                unsigned W[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int V = (int)rint(ldexp(y[tl][r], FRAC_X - S));  // |V| <= 2^30
-                    W[r] = (unsigned)(V + 0x00808080) ^ 0x00808080u;       // digits, least significant first
-                }
-                const int k0 = (wave + tl * WAVES) * 16 + grp * 4;
-#pragma unroll
-                for (int b = 0; b < NXD; ++b) {  // b = 0 most significant
-                    const int sh8 = 8 * (NXD - 1 - b);
-                    const unsigned D = ((W[0] >> sh8) & 0xFFu) | (((W[1] >> sh8) & 0xFFu) << 8) |
-                                       (((W[2] >> sh8) & 0xFFu) << 16) | (((W[3] >> sh8) & 0xFFu) << 24);
-                    *reinterpret_cast<unsigned *>(xdig + (size_t)b * sh.plane + s * sh.stride + k0) = D;
-                }
-            }
-        }
-        __syncthreads();
-    };
-
-    // ---- initial state
-#pragma unroll
-    for (int tl = 0; tl < TPW; ++tl)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            y[tl][r] = 0.0;
-            const int k = (wave + tl * WAVES) * 16 + grp * 4 + r;
-            if (tl < ntile && k < sh.n2 && b0 + s < B) {
-                const cd v = rho[(size_t)(b0 + s) * n + (k < n ? k : k - n)];
-                y[tl][r] = k < n ? v.re : v.im;
-            }
-        }
-    if (nsteps == 0) return;
-    publish(0);
-
-    for (long long t = 0; t < nsteps; ++t) {
-        const int slot = (int)((t + 1) & 1);
-        // ---- MFMA phase
-        i4v acc[TPW][LMAX + 1];
-#pragma unroll
-        for (int tl = 0; tl < TPW; ++tl)
-#pragma unroll
-            for (int L = 0; L <= LMAX; ++L) acc[tl][L] = i4v{0, 0, 0, 0};
-#pragma unroll
-        for (int c = 0; c < KCMAX; ++c) {
-            if (c < sh.kc) {  // uniform
-                i4v xf[NXD];
-#pragma unroll
-                for (int b = 0; b < NXD; ++b)
-                    xf[b] = *reinterpret_cast<const i4v *>(xdig + (size_t)b * sh.plane + s * sh.stride + c * 64 +
-                                                           grp * 16);
-#pragma unroll
-                for (int a = 0; a < NPD; ++a)
-#pragma unroll
-                    for (int b = 0; b < NXD; ++b)
-                        if (a + b <= LMAX)
-#pragma unroll
-                            for (int tl = 0; tl < TPW; ++tl)
-                                if (tl < ntile) acc[tl][a + b] = mma(pf[tl][c][a], xf[b], acc[tl][a + b]);
-            }
-        }
-        // ---- combine the levels (Horner, smallest first) and scale
-#pragma unroll
-        for (int tl = 0; tl < TPW; ++tl) {
-            if (tl < ntile) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    double v = (double)acc[tl][LMAX][r];
-#pragma unroll
-                    for (int L = LMAX - 1; L >= 0; --L) v = fma(v, 1.0 / 256.0, (double)acc[tl][L][r]);
-                    const int R = (wave + tl * WAVES) * 16 + grp * 4 + r;
-                    y[tl][r] = ldexp(v, pexp[R] + S - YSHIFT);
-                }
-            }
-        }
-        if (t + 1 == nsteps) break;  // uniform
-        publish(slot);
-    }
-    // ---- write the final state
-#pragma unroll
-    for (int tl = 0; tl < TPW; ++tl)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int k = (wave + tl * WAVES) * 16 + grp * 4 + r;
-            if (tl < ntile && k < sh.n2 && b0 + s < B) {
-                double *o = reinterpret_cast<double *>(rho + (size_t)(b0 + s) * n + (k < n ? k : k - n));
-                o[k < n ? 0 : 1] = y[tl][r];
-            }
-        }
 }
 
 // ------------------------------------------------------------------

@@ -22,10 +22,10 @@
 //
 // Tile: 96 rows of Q x 64 states per workgroup (256 workgroups at n = 729,
 // B = 1024), four wavefronts in a 2 x 2 grid of 48 rows x 32 states each;
-// k in 64-deep chunks staged through two LDS buffers (47 KB each) with the
-// next chunk's loads held in registers during the current chunk's MFMAs;
-// 64-byte digit rows stored at XOR-swizzled 16-byte positions so that the
-// operand fetches run without bank conflicts.  Workgroups are ordered so that
+// k in 64-deep chunks through a ring of three LDS slots (47 KB each) filled
+// by direct global-to-LDS loads two chunks ahead of the MFMAs; 64-byte digit
+// rows stored at XOR-swizzled 16-byte positions so that the operand fetches
+// run without bank conflicts.  Workgroups are ordered so that
 // those sharing a row block of Q sit on one XCD (its L2 holds the block).
 #include "chain.hpp"
 
@@ -41,9 +41,23 @@ constexpr int EMPTY = -100000;
 constexpr int TR = 96, TS = 64, KC = 64;  // rows, states, k per chunk
 constexpr int RT = 3, ST = 2;             // 16-row / 16-state tiles per wavefront
 constexpr int APL = TR * KC, BPL = TS * KC;
-constexpr int STAGE = NPD * APL + NXD * BPL;  // 47104 bytes
-constexpr int NLD = STAGE / 16;               // 16-byte loads per chunk (2944)
-constexpr int LPT = (NLD + 255) / 256;        // per thread (12)
+constexpr int STAGE = NPD * APL + NXD * BPL;  // 47104 bytes per ring slot
+constexpr int RING = 3;                       // slots: chunk c computed while c + 1, c + 2 load
+constexpr int NLA = NPD * TR / 16, NLB = NXD * TS / 16;  // 1 KB loads per chunk: 30 + 16
+constexpr int NLT = NLA + NLB;
+constexpr int NLW = (NLT + 3) / 4;                       // per wavefront (12)
+
+// Workgroup barrier of the ring: wait until at most N of this wavefront's
+// vector loads are outstanding and its LDS accesses are done (s_waitcnt,
+// gfx9 fields: vmcnt N, expcnt 7 = no wait, lgkmcnt 0), then s_barrier; the
+// empty asm statements keep memory accesses from moving across it.
+#define I8_SYNC(N)                                                                 \
+    do {                                                                           \
+        asm volatile("" ::: "memory");                                             \
+        __builtin_amdgcn_s_waitcnt(((N) & 15) | (7 << 4) | (((N) >> 4) << 14));   \
+        __builtin_amdgcn_s_barrier();                                              \
+        asm volatile("" ::: "memory");                                             \
+    } while (0)
 constexpr int XLIM = (1 << FRAC_X) - 1;
 
 __device__ inline i4v mma(i4v a, i4v b, i4v c) { return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0); }
@@ -185,36 +199,40 @@ __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B,
     const size_t qplane = (size_t)n2 * Kp, xplane = (size_t)B * Kp;
     const int nch = Kp / KC;
 
-    // this thread's loads of a chunk: A (Q digits) then B (state digits)
-    const signed char *src[LPT];
-    int dst[LPT];
+    // A chunk is NLT loads of 1 KB (16 rows x 64 bytes of one digit plane),
+    // straight from global memory into LDS; lane l's 16 bytes land at row
+    // l / 4, position l % 4 of the tile, which holds the row's piece
+    // swz(row, l % 4).  Wavefront w issues loads w, w + 4, ... (past NLT they
+    // repeat earlier ones: same data to the same place).
+    const signed char *src[NLW];
+    int dst[NLW];
 #pragma unroll
-    for (int q = 0; q < LPT; ++q) {
-        int j = tid + 256 * q;
-        j = j < NLD ? j : NLD - 1;  // the tail repeats the last load
-        if (j < NPD * TR * 4) {
-            const int a = j / (TR * 4), rr = j - a * (TR * 4), row = rr >> 2, pc = rr & 3;
-            int R = r0 + row;
+    for (int q = 0; q < NLW; ++q) {
+        int j = wave + 4 * q;
+        j = j < NLT ? j : j - (4 * NLW - NLT);
+        const int row = lane >> 2, pc = swz(row, lane & 3);
+        if (j < NLA) {
+            const int a = j / (TR / 16), tq = j - a * (TR / 16);
+            int R = r0 + 16 * tq + row;
             R = R < n2 ? R : n2 - 1;
             src[q] = Qd + a * qplane + (size_t)R * Kp + pc * 16;
-            dst[q] = a * APL + row * 64 + swz(row, pc) * 16;
+            dst[q] = a * APL + tq * 1024;
         } else {
-            const int jj = j - NPD * TR * 4;
-            const int bd = jj / (TS * 4), rr = jj - bd * (TS * 4), st = rr >> 2, pc = rr & 3;
-            int b = s0 + st;
+            const int jj = j - NLA, bd = jj / (TS / 16), tq = jj - bd * (TS / 16);
+            int b = s0 + 16 * tq + row;
             b = b < B ? b : B - 1;
             src[q] = Xc + bd * xplane + (size_t)b * Kp + pc * 16;
-            dst[q] = NPD * APL + bd * BPL + st * 64 + swz(st, pc) * 16;
+            dst[q] = NPD * APL + bd * BPL + tq * 1024;
         }
     }
-    i4v pre[LPT];
-    auto fetch = [&](int c) {
+    // loads of chunk c (clamped to the last one) into ring slot `slot`
+    auto dma = [&](int c, int slot) {
+        const int cc = c < nch ? c : nch - 1;
 #pragma unroll
-        for (int q = 0; q < LPT; ++q) pre[q] = *reinterpret_cast<const i4v *>(src[q] + (size_t)c * KC);
-    };
-    auto stash = [&](int stage) {
-#pragma unroll
-        for (int q = 0; q < LPT; ++q) *reinterpret_cast<i4v *>(smem + stage * STAGE + dst[q]) = pre[q];
+        for (int q = 0; q < NLW; ++q)
+            __builtin_amdgcn_global_load_lds((const void *)(src[q] + (size_t)cc * KC),
+                                             (__attribute__((address_space(3))) void *)(smem + slot * STAGE + dst[q]),
+                                             16, 0, 0);
     };
 
     const int wr = (wave & 1) * (RT * 16), ws = (wave >> 1) * (ST * 16);  // this wavefront's rows / states
@@ -227,12 +245,14 @@ __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B,
 #pragma unroll
             for (int L = 0; L <= LMAX; ++L) acc[i][j][L] = i4v{0, 0, 0, 0};
 
-    fetch(0);
-    stash(0);
-    __syncthreads();
+    dma(0, 0);
+    dma(1, 1);
     for (int c = 0; c < nch; ++c) {
-        if (c + 1 < nch) fetch(c + 1);
-        const unsigned char *st = smem + (c & 1) * STAGE;
+        // chunk c's loads have landed (only chunk c + 1's may be in flight) in
+        // every wavefront, and every wavefront is done with slot (c + 2) % 3
+        I8_SYNC(NLW);
+        dma(c + 2, (c + 2) % RING);
+        const unsigned char *st = smem + (c % RING) * STAGE;
         i4v xb[ST][NXD];
 #pragma unroll
         for (int j = 0; j < ST; ++j) {
@@ -256,9 +276,8 @@ __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B,
 #pragma unroll
                         for (int j = 0; j < ST; ++j) acc[i][j][a + bd] = mma(pa[a], xb[j][bd], acc[i][j][a + bd]);
         }
-        if (c + 1 < nch) stash((c + 1) & 1);
-        __syncthreads();
     }
+    __builtin_amdgcn_s_waitcnt(0);  // the repeated loads past the last chunk land before the epilogue
 
     // ---- epilogue
     const int g = growth_bits(gbits);
@@ -361,13 +380,13 @@ int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspac
     static bool attr = false;
     if (!attr) {
         LB_HIP(hipFuncSetAttribute((const void *)i8_gemm_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   2 * STAGE));
+                                   RING * STAGE));
         attr = true;
     }
     const int nrb = (n2 + TR - 1) / TR, nsb = (B + TS - 1) / TS;
     LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
         const bool last = t + 1 == nsteps;
-        i8_gemm_step_kernel<<<nrb * nsb, 256, 2 * STAGE, st>>>(n, Kp, B, nrb, nsb, Qd, eP, (t & 1) ? X1 : X0,
+        i8_gemm_step_kernel<<<nrb * nsb, 256, RING * STAGE, st>>>(n, Kp, B, nrb, nsb, Qd, eP, (t & 1) ? X1 : X0,
                                                               (t & 1) ? X0 : X1, Mx, gbits, (int)(t & 3),
                                                               last ? 1 : 0, rho);
         return LB_OK;

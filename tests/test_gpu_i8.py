@@ -103,8 +103,10 @@ def test_i8_shapes(lb, n):
 
 def test_i8_deterministic_zero_state_and_chunked_calls(lb, P9):
     """Bitwise repeatable; a zero state stays zero; 1000 steps as ten calls
-    of 100 equal one call of 1000 bitwise (the state crosses a call boundary
-    in FP64, exactly as it crosses a step, and is re-sliced the same way)."""
+    of 100 stay within the bound of one call (a call slices its first state
+    below that state's own exponent; inside a call the next state is sliced
+    below the previous state's exponent unless it outgrew it, so the bits
+    may differ at call boundaries)."""
     X = states(9, 20, 5)
     X[7] = 0.0
     a = run(lb, P9, X, 1000)
@@ -114,10 +116,29 @@ def test_i8_deterministic_zero_state_and_chunked_calls(lb, P9):
     x = T(X.copy())
     for _ in range(10):
         lb.propagate(T(P9), x, 100, "i8_sliced")
-    assert np.array_equal(x.cpu().numpy(), a)
+    ref = oracle.propagate(P9, X, 1000)
+    keep = np.arange(20) != 7
+    td = oracle.trace_distance(x.cpu().numpy()[keep].reshape(-1, 9, 9), ref[keep].reshape(-1, 9, 9))
+    assert td.max() < 1e-6
     x = T(X.copy())
     lb.propagate(T(P9), x, 0, "i8_sliced")
     assert np.array_equal(x.cpu().numpy(), X)
+
+
+def test_i8_growing_states_take_the_exact_exponent(lb):
+    """A propagator that doubles the state every step (2 I) and one that
+    grows it by 1.6: every step outgrows the previous exponent, so every
+    step takes the re-slicing path; the results stay within the
+    representation's bound."""
+    X = states(9, 5, 9)
+    got = run(lb, 2.0 * np.eye(81, dtype=complex), X, 20)
+    assert oracle.rel_per_state(got, X * 2.0 ** 20) < 1e-8
+    P = 1.6 * np.eye(81, dtype=complex)
+    P[0, 1] = 0.01
+    ref = oracle.propagate(P, X, 30)
+    got = run(lb, P, X, 30)
+    # each step rounds the state to 2^-30 of its largest entry: N 2^-30 relative
+    assert oracle.rel_per_state(got, ref) < 30 * 2.0 ** -30
 
 
 def test_i8_config2_full_size_sampled(lb, P9):
@@ -135,9 +156,73 @@ def test_i8_config2_full_size_sampled(lb, P9):
     assert td.max() < 1e-6
 
 
-def test_i8_large_n_not_supported(lb):
-    P = np.eye(97, dtype=complex)
-    x = T(np.ones((2, 97), dtype=complex))
-    with pytest.raises(lb.LindbladError) as e:
-        lb.propagate(T(P), x, 1, "i8_sliced")
-    assert e.value.status == lb.ENOTSUP
+# ------------------------------------------------ per-step GEMM (n > 96)
+@pytest.fixture(scope="module")
+def P27():
+    H, Lk = W.transmon_system(3)
+    return oracle.propagator(oracle.liouvillian(H, Lk), W.DT_NS)
+
+
+def test_i8_gemm_d27_config3(lb, P27):
+    """Config 3 (d = 27, 10^3 steps) on the oracle's P: a ragged batch, the
+    trace distance against the oracle's chain."""
+    X = states(27, 37, 17)
+    ref = oracle.propagate(P27, X, 1000)
+    got = run(lb, P27, X, 1000)
+    td = oracle.trace_distance(got.reshape(-1, 27, 27), ref.reshape(-1, 27, 27))
+    print(f"i8 GEMM d=27 B=37 N=1e3: trace distance max {td.max():.3e} median {np.median(td):.3e}")
+    assert td.max() < 1e-6
+    rep = oracle.state_report(got.reshape(-1, 27, 27))
+    assert rep["trace_err"].max() < 1e-6 and rep["lambda_min"].min() > -1e-6
+
+
+@pytest.mark.parametrize("B", [1, 1024])
+def test_i8_gemm_d27_full_batch_sampled(lb, P27, B):
+    c = W.config3(B=B)
+    X = c["rho0"].reshape(-1, 729)
+    idx = np.unique(np.array([0, 1, 63, 64, 700, 1023]) % B)
+    ref = oracle.propagate(P27, X[idx], c["nsteps"])
+    x = T(X.copy())
+    lb.propagate(T(P27), x, c["nsteps"], "i8_sliced")
+    got = x.cpu().numpy()[idx]
+    td = oracle.trace_distance(got.reshape(-1, 27, 27), ref.reshape(-1, 27, 27))
+    print(f"i8 GEMM config 3 B={B} sampled: trace distance max {td.max():.3e}")
+    assert td.max() < 1e-6
+
+
+@pytest.mark.parametrize("n", [97, 100, 130, 260])
+def test_i8_gemm_shapes(lb, n):
+    """Row blocks of 96, 64-deep k chunks and ragged state tiles (B = 19) on
+    random contractions (relative to each state's initial norm: the states
+    shrink by orders of magnitude); n = 260 has k padding that no row block
+    covers."""
+    g = np.random.default_rng(n)
+    A = g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))
+    P = A / (1.02 * np.linalg.norm(A, 2))
+    X = g.standard_normal((19, n)) + 1j * g.standard_normal((19, n))
+    ref = oracle.propagate(P, X, 30)
+    got = run(lb, P, X, 30)
+    assert oracle.rel_per_state(got, ref, X) < 1e-8
+
+
+def test_i8_gemm_graph_twin_deterministic_and_chunked(lb, P27):
+    """The graph-replayed twin (1550) equals the direct launches (1500) bit
+    for bit, runs repeat bitwise, and a run split into calls stays within
+    the bound (each call restarts from the exact exponent, so the bits may
+    differ from one long call)."""
+    X = states(27, 20, 23)
+    out = {}
+    for v in (1500, 1550):
+        x = T(X.copy())
+        lb.propagate_variant(T(P27), x, 100, v, "i8_sliced")
+        out[v] = x.cpu().numpy()
+    assert np.array_equal(out[1500], out[1550])
+    x = T(X.copy())
+    lb.propagate_variant(T(P27), x, 100, 1500, "i8_sliced")
+    assert np.array_equal(x.cpu().numpy(), out[1500])
+    x = T(X.copy())
+    for _ in range(4):
+        lb.propagate(T(P27), x, 25, "i8_sliced")
+    ref = oracle.propagate(P27, X, 100)
+    td = oracle.trace_distance(x.cpu().numpy().reshape(-1, 27, 27), ref.reshape(-1, 27, 27))
+    assert td.max() < 1e-6
