@@ -345,6 +345,22 @@ typedef struct lb_problem {
 int lindblad_batch_run(const lb_problem *probs, int nprob, lb_precision prec, double theta,
                        lb_workspace *ws, hipStream_t stream);
 
+/* lindblad_batch_run without any host synchronisation, so that a caller can
+ * capture the whole batch into one HIP graph and replay it: every small host
+ * array (problem pointers, step counts, the window schedule) reaches the
+ * device as kernel arguments, the builds take their scaling exponents on the
+ * device, and the size groups that fit one workgroup per problem (n <= 128)
+ * run on a second, library-owned stream of the device beside the larger ones
+ * (forked from and joined back into `stream` with events).  Data-dependent
+ * failures (a non-finite ||L dt||_1, a zero pivot, a scaling exponent above
+ * 24) lower the DEVICE int `status` (the caller sets it to LB_OK first; NULL
+ * drops them).  The workspace must already hold the batch's buffers when the
+ * call is captured (a first, eager call of the same batch grows it).  Results
+ * are bitwise those of lindblad_batch_run.  Calls that overlap on one device
+ * share the side stream. */
+int lindblad_batch_enqueue(const lb_problem *probs, int nprob, lb_precision prec, double theta, int *status,
+                           lb_workspace *ws, hipStream_t stream);
+
 /* Byte budget of the propagators that lindblad_batch_run keeps running at
  * once for sizes past its one-workgroup-per-problem limit (n > 128): problems
  * run longest first in a sliding window of floor(bytes / P_bytes) (at least

@@ -24,12 +24,22 @@ FLAGS = [
 ]
 
 
+# Per-source flags.  The per-step INT8 GEMM keeps 120 int32 accumulators live
+# across its k loop; with the default accumulator-register form the compiler
+# renames them through AGPR moves every chunk (126 v_accvgpr moves per 84
+# MFMAs), with the VGPR form the MFMAs accumulate in place.
+EXTRA_FLAGS = {
+    "chain_i8_large.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
-    deps = [src] + glob.glob(os.path.join(SRC_DIR, "*.hpp")) + [os.path.join(HERE, "..", "include", "lindblad.h")]
+    deps = [src, os.path.abspath(__file__)] + glob.glob(os.path.join(SRC_DIR, "*.hpp")) + \
+        [os.path.join(HERE, "..", "include", "lindblad.h")]
     if os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps):
         return obj
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -22,7 +22,10 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "lb_internal.hpp"
@@ -284,94 +287,187 @@ static Window window_schedule(const std::vector<long long> &steps, int W) {
     return w;
 }
 
+// Small host arrays reach the device as kernel arguments (2 KB per launch),
+// so nothing the call enqueues reads host memory after it returns: the whole
+// batch can be captured into a HIP graph and replayed.
+constexpr int kArgWords = 256;
+struct WordArgs {
+    unsigned long long v[kArgWords];
+};
+__global__ void put_words_kernel(WordArgs a, int count, unsigned long long *__restrict__ dst) {
+    const int i = threadIdx.x;
+    if (i < count) dst[i] = a.v[i];
+}
+// dst must hold nbytes rounded up to 8
+static int upload(const void *src, size_t nbytes, void *dst, hipStream_t s) {
+    const unsigned char *p = static_cast<const unsigned char *>(src);
+    unsigned long long *d = static_cast<unsigned long long *>(dst);
+    for (size_t off = 0; off < nbytes; off += 8 * kArgWords) {
+        WordArgs a;
+        const size_t b = std::min(nbytes - off, (size_t)8 * kArgWords);
+        std::memset(a.v, 0, sizeof a.v);
+        std::memcpy(a.v, p + off, b);
+        const int words = (int)((b + 7) / 8);
+        put_words_kernel<<<1, kArgWords, 0, s>>>(a, words, d + off / 8);
+        LB_TRY(check_launch("batch upload"));
+    }
+    return LB_OK;
+}
+
+// Everything one size group needs, laid out in the workspace by plan_group
+// and enqueued by run_group; the group's build scratch follows its buffers,
+// so groups on different streams never share memory.
+struct Group {
+    int n = 0, M = 0, Kp = 0, nj = 0;
+    bool small = false;
+    std::vector<const cd *> srcs;
+    std::vector<cd *> rhos;
+    std::vector<long long> steps;
+    std::vector<double> dts;
+    Window win;
+    size_t prow = 0, bytes = 0;
+};
+
 template <typename T>
-static int run_group(int n, const std::vector<const lb_problem *> &probs, double theta, Workspace *ws, hipStream_t s) {
-    const int M = (int)probs.size();
+static Group plan_group(int n, const std::vector<const lb_problem *> &probs) {
+    Group g;
+    g.n = n;
+    g.M = (int)probs.size();
     const size_t nn = (size_t)n * n;
     // longest first (the window schedule takes them in this order)
-    std::vector<int> order(M);
+    std::vector<int> order(g.M);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a]->nsteps > probs[b]->nsteps; });
-    std::vector<const cd *> srcs(M);
-    std::vector<cd *> rhos(M);
-    std::vector<long long> steps(M);
-    std::vector<double> dts(M);
-    for (int i = 0; i < M; ++i) {
+    for (int i = 0; i < g.M; ++i) {
         const lb_problem *p = probs[order[i]];
-        srcs[i] = static_cast<const cd *>(p->L);
-        rhos[i] = static_cast<cd *>(p->rho);
-        steps[i] = p->nsteps;
-        dts[i] = p->dt;
+        g.srcs.push_back(static_cast<const cd *>(p->L));
+        g.rhos.push_back(static_cast<cd *>(p->rho));
+        g.steps.push_back(p->nsteps);
+        g.dts.push_back(p->dt);
     }
     const size_t lds = (nn + 2 * (size_t)n) * sizeof(Cx<T>);
-    const bool small = n <= 128 && lds <= 160 * 1024;
+    g.small = n <= 128 && lds <= 160 * 1024;
     const int VC = Vec<T>::C;
-    const int nj = window_nj(n, VC);
-    const int Kp = small ? n : (nj > 0 ? nj : (n + 64 * VC - 1) / (64 * VC)) * 64 * VC;
-    const size_t prow = (size_t)Kp * sizeof(Cx<T>);
-    Window win;
-    if (!small) {
-        long long W = (long long)(g_window_bytes.load() / ((size_t)n * prow));
-        W = std::max(1LL, std::min<long long>(W, M));
-        win = window_schedule(steps, (int)W);
+    g.nj = window_nj(n, VC);
+    g.Kp = g.small ? n : (g.nj > 0 ? g.nj : (n + 64 * VC - 1) / (64 * VC)) * 64 * VC;
+    g.prow = (size_t)g.Kp * sizeof(Cx<T>);
+    if (!g.small) {
+        long long W = (long long)(g_window_bytes.load() / ((size_t)n * g.prow));
+        W = std::max(1LL, std::min<long long>(W, g.M));
+        g.win = window_schedule(g.steps, (int)W);
     }
-    const size_t mats = align256(nn * sizeof(cd) * M);
-    const size_t need = 2 * mats + align256((size_t)n * prow * M) + 3 * align256(M * sizeof(void *)) +
-                        align256(M * sizeof(long long)) + align256(win.list.size() * sizeof(int) + 4) +
-                        2 * align256((size_t)Kp * M * sizeof(Cx<T>)) + build_workspace_bytes(n, M);
-    LB_TRY(ws_ensure(ws, need));
-    const size_t mark = ws->used;
+    const size_t M = (size_t)g.M;
+    g.bytes = 2 * align256(nn * sizeof(cd) * M) + align256((size_t)n * g.prow * M) + 3 * align256(M * sizeof(void *)) +
+              align256(M * sizeof(long long)) + align256(g.win.list.size() * sizeof(int) + 8) +
+              2 * align256((size_t)g.Kp * M * sizeof(Cx<T>)) + build_async_chunk_bytes(n, g.M);
+    return g;
+}
+
+// Enqueue one group on `s` (no host synchronisation); its buffers are taken
+// from the workspace and kept (the caller ensured plan_group's bytes).
+template <typename T>
+static int run_group(const Group &g, double theta, int *d_status, Workspace *ws, hipStream_t s) {
+    const int n = g.n, M = g.M, Kp = g.Kp;
+    const size_t nn = (size_t)n * n;
     cd *Lg = (cd *)ws_take(ws, nn * sizeof(cd) * M);
     cd *P = (cd *)ws_take(ws, nn * sizeof(cd) * M);
-    Cx<T> *PT = (Cx<T> *)ws_take(ws, (size_t)n * prow * M);
+    Cx<T> *PT = (Cx<T> *)ws_take(ws, (size_t)n * g.prow * M);
     const cd **d_srcs = (const cd **)ws_take(ws, M * sizeof(void *));
     cd **d_rhos = (cd **)ws_take(ws, M * sizeof(void *));
     long long *d_steps = (long long *)ws_take(ws, M * sizeof(long long));
     long long *d_start = (long long *)ws_take(ws, M * sizeof(long long));
-    int *d_list = (int *)ws_take(ws, win.list.size() * sizeof(int) + 4);
+    int *d_list = (int *)ws_take(ws, g.win.list.size() * sizeof(int) + 8);
     Cx<T> *X0 = (Cx<T> *)ws_take(ws, (size_t)Kp * M * sizeof(Cx<T>));
     Cx<T> *X1 = (Cx<T> *)ws_take(ws, (size_t)Kp * M * sizeof(Cx<T>));
-    LB_HIP(hipMemcpyAsync(d_srcs, srcs.data(), M * sizeof(void *), hipMemcpyHostToDevice, s));
-    LB_HIP(hipMemcpyAsync(d_rhos, rhos.data(), M * sizeof(void *), hipMemcpyHostToDevice, s));
-    LB_HIP(hipMemcpyAsync(d_steps, steps.data(), M * sizeof(long long), hipMemcpyHostToDevice, s));
+    LB_TRY(upload(g.srcs.data(), M * sizeof(void *), d_srcs, s));
+    LB_TRY(upload(g.rhos.data(), M * sizeof(void *), d_rhos, s));
+    LB_TRY(upload(g.steps.data(), M * sizeof(long long), d_steps, s));
     gather_kernel<<<grid1((long long)nn * M), 256, 0, s>>>((long long)nn, d_srcs, Lg, M);
     LB_TRY(check_launch("gather"));
-    LB_TRY(build_propagators(n, M, Lg, dts.data(), theta, P, nullptr, ws, s));
-    if (small) {
+    // the build's scratch: right here, and kept (another group may run beside it)
+    const size_t build_at = ws->used;
+    LB_TRY(build_propagators_async(n, M, Lg, g.dts.data(), theta, P, nullptr, d_status, ws, s));
+    ws->used = build_at + build_async_chunk_bytes(n, M);
+    if (g.small) {
         convert_kernel<T><<<grid1((long long)nn * M), 256, 0, s>>>((long long)nn * M, P, PT);
         LB_TRY(check_launch("convert"));
-        static bool attr = false;
-        if (!attr) {
-            LB_HIP(hipFuncSetAttribute((const void *)small_chain_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024));
-            attr = true;
-        }
         int threads = ((n * G + 63) / 64) * 64;
         if (threads > 512) threads = 512;
+        const size_t lds = (nn + 2 * (size_t)n) * sizeof(Cx<T>);
         small_chain_kernel<T><<<M, threads, lds, s>>>(n, PT, d_rhos, d_steps);
-        LB_TRY(check_launch("small_chain"));
-    } else {
-        convert_pad_kernel<T><<<grid1((long long)M * n * Kp), 256, 0, s>>>(n, Kp, M, P, PT);
-        LB_TRY(check_launch("convert_pad"));
-        LB_HIP(hipMemcpyAsync(d_start, win.start.data(), M * sizeof(long long), hipMemcpyHostToDevice, s));
-        if (!win.list.empty())
-            LB_HIP(hipMemcpyAsync(d_list, win.list.data(), win.list.size() * sizeof(int), hipMemcpyHostToDevice, s));
-        load_states_kernel<T><<<grid1((long long)Kp * M), 256, 0, s>>>(n, Kp, M, d_rhos, X0, X1);
-        LB_TRY(check_launch("load_states"));
-        const int rowblocks = (n + 15) / 16;
-        for (size_t k = 0; k + 1 < win.seg_t.size(); ++k) {
-            const int cnt = win.seg_off[k + 1] - win.seg_off[k];
-            const dim3 grid(rowblocks, cnt);
-            for (long long t = win.seg_t[k]; t < win.seg_t[k + 1]; ++t)
-                window_launch<T>(nj, grid, n, Kp, PT, d_list + win.seg_off[k], d_start, t, X0, X1, s);
-        }
-        LB_TRY(check_launch("window_step"));
-        store_states_kernel<T><<<grid1((long long)n * M), 256, 0, s>>>(n, Kp, M, X0, X1, d_steps, d_rhos);
-        LB_TRY(check_launch("store_states"));
+        return check_launch("small_chain");
     }
-    LB_HIP(hipStreamSynchronize(s));  // host arrays above go out of scope
-    ws->used = mark;
-    return LB_OK;
+    convert_pad_kernel<T><<<grid1((long long)M * n * Kp), 256, 0, s>>>(n, Kp, M, P, PT);
+    LB_TRY(check_launch("convert_pad"));
+    LB_TRY(upload(g.win.start.data(), M * sizeof(long long), d_start, s));
+    if (!g.win.list.empty()) LB_TRY(upload(g.win.list.data(), g.win.list.size() * sizeof(int), d_list, s));
+    load_states_kernel<T><<<grid1((long long)Kp * M), 256, 0, s>>>(n, Kp, M, d_rhos, X0, X1);
+    LB_TRY(check_launch("load_states"));
+    const int rowblocks = (n + 15) / 16;
+    for (size_t k = 0; k + 1 < g.win.seg_t.size(); ++k) {
+        const int cnt = g.win.seg_off[k + 1] - g.win.seg_off[k];
+        const dim3 grid(rowblocks, cnt);
+        for (long long t = g.win.seg_t[k]; t < g.win.seg_t[k + 1]; ++t)
+            window_launch<T>(g.nj, grid, n, Kp, PT, d_list + g.win.seg_off[k], d_start, t, X0, X1, s);
+    }
+    LB_TRY(check_launch("window_step"));
+    store_states_kernel<T><<<grid1((long long)n * M), 256, 0, s>>>(n, Kp, M, X0, X1, d_steps, d_rhos);
+    return check_launch("store_states");
+}
+
+// A second stream per device for the groups that run beside the largest one
+// (default priority; created on first use, kept for the process).
+static std::mutex g_side_mu;
+static std::map<int, hipStream_t> g_side;
+
+template <typename T>
+static int enqueue_all(const std::vector<std::vector<const lb_problem *>> &parts, double theta, int *d_status,
+                       Workspace *w, hipStream_t s) {
+    std::vector<Group> groups;
+    size_t total = 0;
+    for (const auto &part : parts) {
+        groups.push_back(plan_group<T>(part[0]->d * part[0]->d, part));
+        total += groups.back().bytes;
+    }
+    LB_TRY(ws_ensure(w, total));
+    // one-time kernel attribute (set outside any capture: the first call of a
+    // process is eager in every caller here)
+    static bool attr = false;
+    if (!attr) {
+        LB_HIP(hipFuncSetAttribute((const void *)small_chain_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
+        attr = true;
+    }
+    bool any_small = false, any_large = false;
+    for (const Group &g : groups) (g.small ? any_small : any_large) = true;
+    if (!(any_small && any_large)) {  // one stream
+        for (const Group &g : groups) LB_TRY(run_group<T>(g, theta, d_status, w, s));
+        return LB_OK;
+    }
+    // fork: the small-n groups on the side stream, the rest on the caller's
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    int dev = 0;
+    LB_HIP(hipGetDevice(&dev));
+    hipStream_t &side = g_side[dev];
+    if (!side) LB_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    hipEvent_t fork = nullptr, join = nullptr;
+    LB_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(fork);
+        return fail(LB_EHIP, "batch: hipEventCreate failed");
+    }
+    int rc = LB_OK;
+    if (hipEventRecord(fork, s) != hipSuccess || hipStreamWaitEvent(side, fork, 0) != hipSuccess)
+        rc = fail(LB_EHIP, "batch: fork failed");
+    for (size_t i = 0; i < groups.size() && rc == LB_OK; ++i)
+        rc = run_group<T>(groups[i], theta, d_status, w, groups[i].small ? side : s);
+    // the join is enqueued whatever happened, so the caller's stream never
+    // runs ahead of work on the side stream
+    if (hipEventRecord(join, side) != hipSuccess || hipStreamWaitEvent(s, join, 0) != hipSuccess)
+        if (rc == LB_OK) rc = fail(LB_EHIP, "batch: join failed");
+    (void)hipEventDestroy(fork);
+    (void)hipEventDestroy(join);
+    return rc;
 }
 
 }  // namespace mb
@@ -379,40 +475,76 @@ static int run_group(int n, const std::vector<const lb_problem *> &probs, double
 
 using namespace lb;
 
-extern "C" int lindblad_batch_run(const lb_problem *probs, int nprob, lb_precision prec, double theta,
-                                  lb_workspace *ws, hipStream_t stream) {
-    if (nprob < 0) return fail(LB_EINVAL, "lindblad_batch_run: nprob < 0");
-    if (nprob == 0) return LB_OK;
-    if (!probs) return fail(LB_EINVAL, "lindblad_batch_run: probs is NULL");
+static int batch_args(const char *who, const lb_problem *probs, int nprob, lb_precision prec, double theta) {
+    const std::string w(who);
+    if (nprob < 0) return fail(LB_EINVAL, w + ": nprob < 0");
+    if (nprob > 0 && !probs) return fail(LB_EINVAL, w + ": probs is NULL");
     if (prec != LB_C128 && prec != LB_C64)
-        return fail(LB_ENOTSUP, "lindblad_batch_run: single-state problems run in LB_C128 or LB_C64");
-    if (!(theta > 0.0)) return fail(LB_EINVAL, "lindblad_batch_run: theta must be > 0");
-    std::vector<int> sizes;
+        return fail(LB_ENOTSUP, w + ": single-state problems run in LB_C128 or LB_C64");
+    if (!(theta > 0.0)) return fail(LB_EINVAL, w + ": theta must be > 0");
     for (int i = 0; i < nprob; ++i) {
         const lb_problem &p = probs[i];
-        if (p.d < 1 || p.d > 64) return fail(LB_ESHAPE, "lindblad_batch_run: d must be in [1, 64]");
-        if (p.nsteps < 0) return fail(LB_EINVAL, "lindblad_batch_run: nsteps < 0");
-        if (!p.L || !p.rho) return fail(LB_EINVAL, "lindblad_batch_run: NULL pointer in a problem");
-        if (!std::isfinite(p.dt)) return fail(LB_EINVAL, "lindblad_batch_run: dt must be finite");
-        if (std::find(sizes.begin(), sizes.end(), p.d) == sizes.end()) sizes.push_back(p.d);
+        if (p.d < 1 || p.d > 64) return fail(LB_ESHAPE, w + ": d must be in [1, 64]");
+        if (p.nsteps < 0) return fail(LB_EINVAL, w + ": nsteps < 0");
+        if (!p.L || !p.rho) return fail(LB_EINVAL, w + ": NULL pointer in a problem");
+        if (!std::isfinite(p.dt)) return fail(LB_EINVAL, w + ": dt must be finite");
     }
-    Workspace *w = ws_resolve(ws);
-    ws_begin(w, stream);
+    return LB_OK;
+}
+
+// size groups (ascending d), at most 512 problems each
+static std::vector<std::vector<const lb_problem *>> batch_parts(const lb_problem *probs, int nprob) {
+    std::vector<int> sizes;
+    for (int i = 0; i < nprob; ++i)
+        if (std::find(sizes.begin(), sizes.end(), probs[i].d) == sizes.end()) sizes.push_back(probs[i].d);
     std::sort(sizes.begin(), sizes.end());
+    std::vector<std::vector<const lb_problem *>> parts;
     for (int d : sizes) {
         std::vector<const lb_problem *> group;
         for (int i = 0; i < nprob; ++i)
             if (probs[i].d == d) group.push_back(&probs[i]);
-        const int n = d * d;
-        // keep a group's workspace bounded: at most 512 problems per build
-        for (size_t g0 = 0; g0 < group.size(); g0 += 512) {
-            std::vector<const lb_problem *> part(group.begin() + g0,
-                                                 group.begin() + std::min(group.size(), g0 + 512));
-            LB_TRY(prec == LB_C64 ? mb::run_group<float>(n, part, theta, w, stream)
-                                  : mb::run_group<double>(n, part, theta, w, stream));
-        }
+        for (size_t g0 = 0; g0 < group.size(); g0 += 512)
+            parts.emplace_back(group.begin() + g0, group.begin() + std::min(group.size(), g0 + 512));
     }
-    return LB_OK;
+    return parts;
+}
+
+extern "C" int lindblad_batch_enqueue(const lb_problem *probs, int nprob, lb_precision prec, double theta,
+                                      int *status, lb_workspace *ws, hipStream_t stream) {
+    LB_TRY(batch_args("lindblad_batch_enqueue", probs, nprob, prec, theta));
+    if (nprob == 0) return LB_OK;
+    Workspace *w = ws_resolve(ws);
+    ws_begin(w, stream);
+    const auto parts = batch_parts(probs, nprob);
+    return prec == LB_C64 ? mb::enqueue_all<float>(parts, theta, status, w, stream)
+                          : mb::enqueue_all<double>(parts, theta, status, w, stream);
+}
+
+extern "C" int lindblad_batch_run(const lb_problem *probs, int nprob, lb_precision prec, double theta,
+                                  lb_workspace *ws, hipStream_t stream) {
+    LB_TRY(batch_args("lindblad_batch_run", probs, nprob, prec, theta));
+    if (nprob == 0) return LB_OK;
+    Workspace *w = ws_resolve(ws);
+    ws_begin(w, stream);
+    const auto parts = batch_parts(probs, nprob);
+    // the status word sits past the groups' buffers
+    size_t total = 256;
+    for (const auto &part : parts) {
+        const int n = part[0]->d * part[0]->d;
+        total += prec == LB_C64 ? mb::plan_group<float>(n, part).bytes : mb::plan_group<double>(n, part).bytes;
+    }
+    LB_TRY(ws_ensure(w, total));
+    int *d_status = (int *)ws_take(w, 256);
+    LB_TRY(fill_i32_launch(d_status, 1, stream));
+    LB_TRY(prec == LB_C64 ? mb::enqueue_all<float>(parts, theta, d_status, w, stream)
+                          : mb::enqueue_all<double>(parts, theta, d_status, w, stream));
+    int st = 0;
+    LB_HIP(hipMemcpyAsync(&st, d_status, sizeof(int), hipMemcpyDeviceToHost, stream));
+    LB_HIP(hipStreamSynchronize(stream));
+    if (st == LB_ENONFINITE) return fail(st, "lindblad_batch_run: ||L dt||_1 of some problem is not finite");
+    if (st == LB_ESINGULAR) return fail(st, "lindblad_batch_run: zero pivot in some problem's Pade denominator");
+    if (st == LB_ENOTSUP) return fail(st, "lindblad_batch_run: some problem's scaling exponent exceeds the cap");
+    return st == LB_OK ? LB_OK : fail(st, "lindblad_batch_run: device status " + std::to_string(st));
 }
 
 extern "C" int lindblad_batch_set_window(size_t bytes) {

@@ -61,6 +61,8 @@ SYMBOLS = {
                                      ctypes.c_void_p, ctypes.c_void_p]),
     "lindblad_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "lindblad_batch_set_window": (ctypes.c_int, [ctypes.c_size_t]),
+    "lindblad_batch_enqueue": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lindblad_expmv": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
                                       ctypes.c_longlong, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
                                       ctypes.c_void_p]),
@@ -392,8 +394,7 @@ def batch_set_window(nbytes: int = 0):
     _check(lib().lindblad_batch_set_window(int(nbytes)))
 
 
-def batch_run(problems, precision="c64", theta: float = 0.25, ws: Workspace | None = None):
-    """problems: list of dicts with d, L (n x n tensor), dt, nsteps, rho (n tensor, updated in place)."""
+def _problems(problems):
     arr = (Problem * len(problems))()
     for i, p in enumerate(problems):
         arr[i].d = int(p["d"])
@@ -401,8 +402,24 @@ def batch_run(problems, precision="c64", theta: float = 0.25, ws: Workspace | No
         arr[i].dt = float(p["dt"])
         arr[i].nsteps = int(p["nsteps"])
         arr[i].rho = _dev(p["rho"], name="rho").data_ptr()
+    return arr
+
+
+def batch_run(problems, precision="c64", theta: float = 0.25, ws: Workspace | None = None):
+    """problems: list of dicts with d, L (n x n tensor), dt, nsteps, rho (n tensor, updated in place)."""
+    arr = _problems(problems)
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     _check(lib().lindblad_batch_run(arr, len(problems), prec, float(theta), _ws(ws), _stream()))
+
+
+def batch_enqueue(problems, precision="c64", theta: float = 0.25, status: torch.Tensor | None = None,
+                  ws: Workspace | None = None):
+    """lindblad_batch_enqueue: the mixed batch without host synchronisation
+    (capturable into a graph); `status` an int32 device tensor set to 0 first."""
+    arr = _problems(problems)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().lindblad_batch_enqueue(arr, len(problems), prec, float(theta),
+                                        _ptr(status) if status is not None else None, _ws(ws), _stream()))
 
 
 class GrapeFidelity(torch.autograd.Function):

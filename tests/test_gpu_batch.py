@@ -174,3 +174,56 @@ def test_mixed_batch_full_size_sampled(lb):
         single = [dict(d=p["d"], L=g[i]["L"], dt=p["dt"], nsteps=p["nsteps"], rho=T(p["rho0"].reshape(-1).copy()))]
         lb.batch_run(single, "c64")
         assert torch.equal(single[0]["rho"], g[i]["rho"]), i
+
+
+def _reset(g, probs):
+    for p, q in zip(probs, g):
+        q["rho"].copy_(T(p["rho0"].reshape(-1)))
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_batch_enqueue_equals_run_and_replays_from_a_graph(lb, problems, prec):
+    """lindblad_batch_enqueue (no host synchronisation, the small-n groups on
+    a side stream beside the d = 27 group) equals lindblad_batch_run bit for
+    bit, and the whole batch captured into one graph replays to the same bits
+    three times, with eager work and synchronisation between the replays."""
+    g = as_gpu(problems)
+    lb.batch_run(g, prec)
+    want = [q["rho"].clone() for q in g]
+    _reset(g, problems)
+    status = torch.zeros(1, dtype=torch.int32, device=DEV)
+    lb.batch_enqueue(g, prec, status=status)
+    torch.cuda.synchronize()
+    assert status.item() == 0
+    for q, w in zip(g, want):
+        assert torch.equal(q["rho"], w)
+    # capture (the workspace and the side stream exist after the eager calls)
+    _reset(g, problems)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, capture_error_mode="thread_local"):
+        lb.batch_enqueue(g, prec, status=status)
+    for _ in range(3):
+        _reset(g, problems)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for q, w in zip(g, want):
+            assert torch.equal(q["rho"], w)
+        junk = torch.randn(1 << 20, device=DEV)  # eager work between replays
+        junk.mul_(2.0)
+        torch.cuda.synchronize()
+    assert status.item() == 0
+
+
+def test_batch_enqueue_reports_a_nonfinite_generator(lb, problems):
+    g = as_gpu(problems[:3])
+    g[1]["L"] = g[1]["L"].clone()
+    g[1]["L"][0, 0] = float("nan")
+    status = torch.zeros(1, dtype=torch.int32, device=DEV)
+    lb.batch_enqueue(g, "c64", status=status)
+    torch.cuda.synchronize()
+    assert status.item() == lb.ENONFINITE
+    with pytest.raises(lb.LindbladError) as e:
+        lb.batch_run(g, "c64")
+    assert e.value.status == lb.ENONFINITE
