@@ -189,6 +189,10 @@ def kernel_of(variant, prec):
         return base + ("<HILO>" if prec == "bf16_hilo" else "<SLICED>")
     if fam == 13:
         return "i8_chain_kernel"
+    if fam == 14:
+        return "fx_chain_kernel"
+    if fam == 15:
+        return "i8_gemm_step_kernel"
     if fam == 11:
         t = "double" if prec == "c128" else "float"
         if variant % 50 in (1, 2):
@@ -469,7 +473,7 @@ def d27_section(lb, W, torch, dev, ws):
     finals = {}
     for B in (1, 64, 1024):
         row = {}
-        for prec in ("c128", "c64", "bf16_hilo", "bf16_sliced", "baseline"):
+        for prec in ("c128", "c64", "bf16_hilo", "bf16_sliced", "i8_sliced", "baseline"):
             nst = N if not (prec == "baseline" and B == 1024) else 100
             x = X0[:B].clone()
             variant = 100
@@ -594,6 +598,29 @@ def extra_sections(lb, W, torch, dev, ws):
     lb.batch_run(gp, "c64", ws=ws)
     torch.cuda.synchronize()
     dtm = time.perf_counter() - t0
+    # the whole batch as one captured graph (lindblad_batch_enqueue: no host
+    # synchronisation; the d = 3 / 9 groups on a side stream beside d = 27)
+    graph_ms = None
+    try:
+        graph = torch.cuda.CUDAGraph()
+        for q, pr in zip(gp, probs):
+            q["rho"].copy_(torch.from_numpy(pr["rho0"].reshape(-1)))
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, capture_error_mode="thread_local"):
+            lb.batch_enqueue(gp, "c64", ws=ws)
+        reps = []
+        for _ in range(3):
+            for q, pr in zip(gp, probs):
+                q["rho"].copy_(torch.from_numpy(pr["rho0"].reshape(-1)))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            graph.replay()
+            torch.cuda.synchronize()
+            reps.append((time.perf_counter() - t0) * 1e3)
+        graph_ms = sorted(reps)[1]
+        del graph
+    except (RuntimeError, lb.LindbladError) as e:  # report, do not fail the bench
+        graph_ms = f"capture failed: {e}"
     groups = {}
     for dd in (3, 9, 27):  # each size group alone: where the makespan goes
         sub = [q for q in gp if q["d"] == dd]
@@ -606,7 +633,7 @@ def extra_sections(lb, W, torch, dev, ws):
                             "state_steps": sum(q["nsteps"] for q in sub)}
     out["mixed_config5"] = {"problems": len(probs), "state_steps": total_ss, "makespan_ms": dtm * 1e3,
                             "state_steps_per_s": total_ss / dtm, "precision": "c64 chains, FP64 builds",
-                            "groups_alone": groups}
+                            "graph_replay_ms": graph_ms, "groups_alone": groups}
     return out
 
 

@@ -27,9 +27,16 @@ FLAGS = [
 # Per-source flags.  The per-step INT8 GEMM keeps 120 int32 accumulators live
 # across its k loop; with the default accumulator-register form the compiler
 # renames them through AGPR moves every chunk (126 v_accvgpr moves per 84
-# MFMAs), with the VGPR form the MFMAs accumulate in place.
+# MFMAs), with the VGPR form the MFMAs accumulate in place (d = 27, B = 1024:
+# 47.1 -> 43.8 us per step).  The same form measured faster for the FP64
+# build products (64 d = 27 builds 53.3 -> 47.5 ms) and the FP64 / FP32
+# per-step GEMMs (ring FP64 82.8 -> 80.3 us, B = 64 16.4 -> 15.3 us); the
+# BF16 fused chain's files keep the default (hi+lo measured 2 % slower).
+VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 EXTRA_FLAGS = {
-    "chain_i8_large.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    "chain_i8_large.hip": VGPR_FORM,
+    "chain_large.hip": VGPR_FORM,
+    "zgemm.hip": VGPR_FORM,
 }
 
 
