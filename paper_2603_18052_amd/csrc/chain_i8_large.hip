@@ -81,7 +81,7 @@ __device__ inline double qval(const cd *__restrict__ P, int n, int R, int k) {
 
 // digits of a row of Q (one workgroup per row): exponent, five planes, and
 // the row's absolute sum into gbits (atomic max of the non-negative bits)
-__global__ void __launch_bounds__(256) prep_q_kernel(int n, int Kp, const cd *__restrict__ P,
+__global__ void __launch_bounds__(256) prep_q_kernel(int n, int Kp, int npad, const cd *__restrict__ P,
                                                      signed char *__restrict__ Qd, int *__restrict__ eP,
                                                      unsigned long long *__restrict__ gbits) {
     const int R = blockIdx.x, tid = threadIdx.x;
@@ -108,6 +108,11 @@ __global__ void __launch_bounds__(256) prep_q_kernel(int n, int Kp, const cd *__
         eP[R] = e;
         atomicMax(gbits, (unsigned long long)__double_as_longlong(rs[0]));
     }
+    // rows past 2n (up to whole row blocks) repeat the last row: the step
+    // kernel loads them from the last row too, so their outputs copy its
+    // output and need no masking before the exponent maximum
+    if (R == 2 * n - 1)
+        for (int q = 2 * n + tid; q < npad; q += 256) eP[q] = e;
     const size_t plane = (size_t)2 * n * Kp;
     for (int k0 = 4 * tid; k0 < Kp; k0 += 4 * 256) {
         unsigned w[NPD] = {0u, 0u, 0u, 0u, 0u};
@@ -178,15 +183,18 @@ __global__ void __launch_bounds__(256) init_x_kernel(int n, int Kp, int B, const
 }
 
 // one step: x_{t+1} = Q x_t for all states (t4 = t mod 4); the last step
-// writes FP64 into rho instead of digits
+// (LAST) writes FP64 into rho instead of digits.  Dynamic LDS: the ring, then
+// TS ints for the workgroup's exponent maxima.
+template <bool LAST>
 __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B, int nrb, int nsb,
                                                            const signed char *__restrict__ Qd,
                                                            const int *__restrict__ eP,
                                                            const signed char *__restrict__ Xc,
                                                            signed char *__restrict__ Xn, int *__restrict__ Mx,
                                                            const unsigned long long *__restrict__ gbits, int t4,
-                                                           int last, cd *__restrict__ rho) {
+                                                           cd *__restrict__ rho) {
     extern __shared__ __align__(16) unsigned char smem[];
+    int *emx = reinterpret_cast<int *>(smem + RING * STAGE);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n2 = 2 * n;
@@ -198,6 +206,26 @@ __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B,
     const int r0 = rb * TR, s0 = sb * TS;
     const size_t qplane = (size_t)n2 * Kp, xplane = (size_t)B * Kp;
     const int nch = Kp / KC;
+    const int wr = (wave & 1) * (RT * 16), ws = (wave >> 1) * (ST * 16);  // this wavefront's rows / states
+    const int fr = lane & 15, fp = lane >> 4;
+
+    // The epilogue's operands, loaded first so that they land under the k
+    // loop: the exponents of this lane's 4 x RT rows (eP is padded to whole
+    // row blocks) and the exponent slots of its ST states (clamped to the
+    // last state: the copies past B are neither stored nor reduced).
+    const int *Mcur = Mx + ((t4 + 3) & 3) * B;  // x_t was sliced below 2^(Mcur + g)
+    const int *Mnow = Mx + t4 * B;              // exponent of max |x_t|
+    i4v er[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) er[i] = *reinterpret_cast<const i4v *>(eP + r0 + wr + 16 * i + 4 * fp);
+    int mc[ST], mn[ST];
+#pragma unroll
+    for (int j = 0; j < ST; ++j) {
+        const int b = min(s0 + ws + 16 * j + fr, B - 1);
+        mc[j] = Mcur[b];
+        mn[j] = Mnow[b];
+    }
+    if (!LAST && tid < TS) emx[tid] = EMPTY;  // ordered before its use by the ring's barriers
 
     // A chunk is NLT loads of 1 KB (16 rows x 64 bytes of one digit plane),
     // straight from global memory into LDS; lane l's 16 bytes land at row
@@ -225,18 +253,15 @@ __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B,
             dst[q] = NPD * APL + bd * BPL + tq * 1024;
         }
     }
-    // loads of chunk c (clamped to the last one) into ring slot `slot`
+    // loads of chunk c into ring slot `slot`
     auto dma = [&](int c, int slot) {
-        const int cc = c < nch ? c : nch - 1;
 #pragma unroll
         for (int q = 0; q < NLW; ++q)
-            __builtin_amdgcn_global_load_lds((const void *)(src[q] + (size_t)cc * KC),
+            __builtin_amdgcn_global_load_lds((const void *)(src[q] + (size_t)c * KC),
                                              (__attribute__((address_space(3))) void *)(smem + slot * STAGE + dst[q]),
                                              16, 0, 0);
     };
 
-    const int wr = (wave & 1) * (RT * 16), ws = (wave >> 1) * (ST * 16);  // this wavefront's rows / states
-    const int fr = lane & 15, fp = lane >> 4;
     i4v acc[RT][ST][LMAX + 1];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
@@ -246,12 +271,16 @@ __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B,
             for (int L = 0; L <= LMAX; ++L) acc[i][j][L] = i4v{0, 0, 0, 0};
 
     dma(0, 0);
-    dma(1, 1);
+    if (nch > 1) dma(1, 1);
     for (int c = 0; c < nch; ++c) {
-        // chunk c's loads have landed (only chunk c + 1's may be in flight) in
-        // every wavefront, and every wavefront is done with slot (c + 2) % 3
-        I8_SYNC(NLW);
-        dma(c + 2, (c + 2) % RING);
+        // chunk c's loads have landed in every wavefront (only chunk c + 1's
+        // may still be in flight; none after the last chunk), and every
+        // wavefront is done with slot (c + 2) % 3
+        if (c + 1 < nch)
+            I8_SYNC(NLW);
+        else
+            I8_SYNC(0);
+        if (c + 2 < nch) dma(c + 2, (c + 2) % RING);
         const unsigned char *st = smem + (c % RING) * STAGE;
         i4v xb[ST][NXD];
 #pragma unroll
@@ -277,67 +306,70 @@ __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B,
                         for (int j = 0; j < ST; ++j) acc[i][j][a + bd] = mma(pa[a], xb[j][bd], acc[i][j][a + bd]);
         }
     }
-    __builtin_amdgcn_s_waitcnt(0);  // the repeated loads past the last chunk land before the epilogue
 
-    // ---- epilogue
+    // ---- epilogue: y = 2^(eP + Sc - YSHIFT) sum_L 2^(-8L) acc_L for the
+    // lane's four consecutive rows R0 .. R0 + 3 of each (i, j)
     const int g = growth_bits(gbits);
-    const int *Mcur = Mx + ((t4 + 3) & 3) * B;  // x_t was sliced below 2^(Mcur + g)
-    const int *Mnow = Mx + t4 * B;              // exponent of max |x_t|
-    int *Mnext = Mx + ((t4 + 1) & 3) * B;       // exponent of max |x_{t+1}|, by atomics
-    if (!last && rb == 0 && tid < TS && s0 + tid < B) Mx[((t4 + 2) & 3) * B + s0 + tid] = EMPTY;
+    if (!LAST && rb == 0 && tid < TS && s0 + tid < B) Mx[((t4 + 2) & 3) * B + s0 + tid] = EMPTY;
 #pragma unroll
     for (int j = 0; j < ST; ++j) {
         const int b = s0 + ws + 16 * j + fr;
         const bool bok = b < B;
-        const int mc = bok ? Mcur[b] : 0;
-        const int Sc = mc == EMPTY ? 0 : mc + g;
-        const int mn = bok ? Mnow[b] : 0;
-        const int Sn = mn == EMPTY ? 0 : mn + g;
+        const int Sc = mc[j] == EMPTY ? 0 : mc[j] + g;
+        const int Sn = mn[j] == EMPTY ? 0 : mn[j] + g;
         int emax = EMPTY;
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
-            const int R0 = r0 + wr + 16 * i + 4 * fp;  // four consecutive rows of this lane
-            double y[4];
+            const int R0 = r0 + wr + 16 * i + 4 * fp;
+            double v[4];
+            int ey[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                double v = (double)acc[i][j][LMAX][r];
+                v[r] = (double)acc[i][j][LMAX][r];
 #pragma unroll
-                for (int L = LMAX - 1; L >= 0; --L) v = fma(v, 1.0 / 256.0, (double)acc[i][j][L][r]);
-                const int R = R0 + r;
-                y[r] = (bok && R < n2) ? ldexp(v, eP[R] + Sc - YSHIFT) : 0.0;
-                emax = max(emax, exp_of(fabs(y[r])));
+                for (int L = LMAX - 1; L >= 0; --L) v[r] = fma(v[r], 1.0 / 256.0, (double)acc[i][j][L][r]);
+                ey[r] = er[i][r] + Sc - YSHIFT;  // y = v 2^ey, exactly
             }
-            if (last) {
+            if (LAST) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int R = R0 + r;
                     if (bok && R < n2) {
                         double *o = reinterpret_cast<double *>(rho + (size_t)b * n + (R < n ? R : R - n));
-                        o[R < n ? 0 : 1] = y[r];
+                        o[R < n ? 0 : 1] = __builtin_amdgcn_ldexp(v[r], ey[r]);
                     }
                 }
-            } else if (bok && R0 < Kp) {
+            } else {
                 unsigned W[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    int V = (int)rint(ldexp(y[r], FRAC_X - Sn));
+                    // frexp exponent of y (zero outputs do not count)
+                    emax = max(emax, v[r] != 0.0 ? __builtin_amdgcn_frexp_exp(v[r]) + ey[r] : EMPTY);
+                    int V = (int)rint(__builtin_amdgcn_ldexp(v[r], ey[r] + FRAC_X - Sn));
                     V = V > XLIM ? XLIM : (V < -XLIM ? -XLIM : V);
                     W[r] = (unsigned)(V + 0x00808080) ^ 0x00808080u;
                 }
+                if (bok && R0 < Kp) {
 #pragma unroll
-                for (int bd = 0; bd < NXD; ++bd) {
-                    const int sh = 8 * (NXD - 1 - bd);
-                    const unsigned D = ((W[0] >> sh) & 0xFFu) | (((W[1] >> sh) & 0xFFu) << 8) |
-                                       (((W[2] >> sh) & 0xFFu) << 16) | (((W[3] >> sh) & 0xFFu) << 24);
-                    *reinterpret_cast<unsigned *>(Xn + bd * xplane + (size_t)b * Kp + R0) = D;
+                    for (int bd = 0; bd < NXD; ++bd) {
+                        const int sh = 8 * (NXD - 1 - bd);
+                        const unsigned D = ((W[0] >> sh) & 0xFFu) | (((W[1] >> sh) & 0xFFu) << 8) |
+                                           (((W[2] >> sh) & 0xFFu) << 16) | (((W[3] >> sh) & 0xFFu) << 24);
+                        *reinterpret_cast<unsigned *>(Xn + bd * xplane + (size_t)b * Kp + R0) = D;
+                    }
                 }
             }
         }
-        if (!last) {
+        if (!LAST) {
             emax = max(emax, __shfl_xor(emax, 16));
             emax = max(emax, __shfl_xor(emax, 32));
-            if (fp == 0 && bok && emax != EMPTY) atomicMax(Mnext + b, emax);
+            if (fp == 0) atomicMax(emx + ws + 16 * j + fr, emax);
         }
+    }
+    if (!LAST) {
+        // one global maximum per state and workgroup
+        __syncthreads();
+        if (tid < TS && s0 + tid < B && emx[tid] != EMPTY) atomicMax(Mx + ((t4 + 1) & 3) * B + s0 + tid, emx[tid]);
     }
 }
 
@@ -351,7 +383,8 @@ static int grid1(long long work) {
 
 size_t i8_gemm_ws_bytes(int n, int B) {
     const size_t Kp = (size_t)(2 * n + 63) / 64 * 64;
-    return align256((size_t)i8g::NPD * 2 * n * Kp) + align256((size_t)2 * n * 4) +
+    const size_t npad = (size_t)(2 * n + i8g::TR - 1) / i8g::TR * i8g::TR;
+    return align256((size_t)i8g::NPD * 2 * n * Kp) + align256(npad * 4) +
            2 * align256((size_t)i8g::NXD * B * Kp) + align256((size_t)4 * B * 4) + 256;
 }
 
@@ -362,7 +395,8 @@ int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspac
     LB_TRY(ws_ensure(ws, i8_gemm_ws_bytes(n, B)));
     const size_t mark = ws->used;
     signed char *Qd = (signed char *)ws_take(ws, (size_t)NPD * n2 * Kp);
-    int *eP = (int *)ws_take(ws, (size_t)n2 * 4);
+    const int nrb = (n2 + TR - 1) / TR, nsb = (B + TS - 1) / TS;
+    int *eP = (int *)ws_take(ws, (size_t)nrb * TR * 4);
     signed char *X0 = (signed char *)ws_take(ws, (size_t)NXD * B * Kp);
     signed char *X1 = (signed char *)ws_take(ws, (size_t)NXD * B * Kp);
     int *Mx = (int *)ws_take(ws, (size_t)4 * B * 4);
@@ -373,22 +407,28 @@ int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspac
         ~Release() { w->used = m; }
     } release{ws, mark};
     LB_TRY(fill_i32_launch(reinterpret_cast<int *>(gbits), 2, s));
-    prep_q_kernel<<<n2, 256, 0, s>>>(n, Kp, P, Qd, eP, gbits);
+    prep_q_kernel<<<n2, 256, 0, s>>>(n, Kp, nrb * TR, P, Qd, eP, gbits);
     LB_TRY(check_launch("i8 prep_q"));
     init_x_kernel<<<B, 256, 0, s>>>(n, Kp, B, rho, X0, X1, Mx, gbits);
     LB_TRY(check_launch("i8 init_x"));
+    constexpr int lds = RING * STAGE + TS * 4;
     static bool attr = false;
     if (!attr) {
-        LB_HIP(hipFuncSetAttribute((const void *)i8_gemm_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   RING * STAGE));
+        LB_HIP(hipFuncSetAttribute((const void *)i8_gemm_step_kernel<false>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        LB_HIP(hipFuncSetAttribute((const void *)i8_gemm_step_kernel<true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
         attr = true;
     }
-    const int nrb = (n2 + TR - 1) / TR, nsb = (B + TS - 1) / TS;
     LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
-        const bool last = t + 1 == nsteps;
-        i8_gemm_step_kernel<<<nrb * nsb, 256, RING * STAGE, st>>>(n, Kp, B, nrb, nsb, Qd, eP, (t & 1) ? X1 : X0,
-                                                              (t & 1) ? X0 : X1, Mx, gbits, (int)(t & 3),
-                                                              last ? 1 : 0, rho);
+        const signed char *xc = (t & 1) ? X1 : X0;
+        signed char *xn = (t & 1) ? X0 : X1;
+        if (t + 1 == nsteps)
+            i8_gemm_step_kernel<true><<<nrb * nsb, 256, lds, st>>>(n, Kp, B, nrb, nsb, Qd, eP, xc, xn, Mx, gbits,
+                                                                   (int)(t & 3), rho);
+        else
+            i8_gemm_step_kernel<false><<<nrb * nsb, 256, lds, st>>>(n, Kp, B, nrb, nsb, Qd, eP, xc, xn, Mx, gbits,
+                                                                    (int)(t & 3), rho);
         return LB_OK;
     }, s));
     return check_launch("i8 gemm step");
