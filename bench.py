@@ -192,7 +192,7 @@ def kernel_of(variant, prec):
     if fam == 14:
         return "fx_chain_kernel"
     if fam == 15:
-        return "i8_gemm_step_kernel"
+        return "i8_gemm_step_kernel<false>"
     if fam == 11:
         t = "double" if prec == "c128" else "float"
         if variant % 50 in (1, 2):
