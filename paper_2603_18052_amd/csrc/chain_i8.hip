@@ -26,9 +26,11 @@
 // Work split: 16 states per workgroup (the MFMA N), 8 wavefronts; wavefront
 // w owns 16-row tiles w and w + 8 of Q over all of k, so its outputs end each
 // step complete (no partial sums).  Per step: MFMAs (state digits read from
-// LDS as B fragments), combine in registers, per-state exponent by an LDS
-// max, barrier, slicing of the owned rows (four consecutive k of one state
-// per lane: each digit plane one 4-byte LDS write), barrier.
+// LDS as B fragments, chunk 0's right after the previous barrier), combine
+// in registers, slicing of the owned rows below the previous state's
+// exponent (four consecutive k of one state per lane: each digit plane one
+// 4-byte LDS write), per-state exponent by LDS maxima, one barrier (and a
+// second one in a step where some state outgrew its exponent).
 #include "chain.hpp"
 
 namespace lb {
@@ -139,6 +141,11 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
     }
 
     // ---- output rows of this lane: tile (wave + 8 tl), register r -> row 16 (wave + 8 tl) + 4 grp + r
+    int pe[NTA][4];  // their row exponents
+#pragma unroll
+    for (int tl = 0; tl < NT; ++tl)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pe[tl][r] = pexp[(wave + tl * WAVES) * 16 + grp * 4 + r];
     double y[NTA][4];
     int ey[NTA][4];  // exponents of |y|
     // the digits of y below 2^S into buffer `to` (four consecutive k of one state: one word per plane)
@@ -161,15 +168,26 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
             }
         }
     };
-    // largest exponent of this lane's state over its rows, reduced over the lane group
+    // largest exponent of this lane's state over the lane's rows (the lane
+    // groups meet in the LDS maximum)
     auto state_exp = [&]() {
         int m = EMPTY;
 #pragma unroll
         for (int tl = 0; tl < NT; ++tl)
 #pragma unroll
             for (int r = 0; r < 4; ++r) m = max(m, ey[tl][r]);
-        m = max(m, __shfl_xor(m, 16));
-        return max(m, __shfl_xor(m, 32));
+        return m;
+    };
+    // chunk c's state digits (one B fragment per digit plane) from buffer
+    // `from`; the volatile form is for the reads issued early on purpose
+    // (the compiler would otherwise sink them to their first use)
+    auto fetch_x = [&](int from, int c, i4v (&xf)[NXD], bool early) {
+#pragma unroll
+        for (int b = 0; b < NXD; ++b) {
+            const i4v *q = reinterpret_cast<const i4v *>(xdig + from * buf + (size_t)b * sh.plane + s * sh.stride +
+                                                         c * 64 + grp * 16);
+            xf[b] = early ? *(const volatile __attribute__((address_space(3))) i4v *)(q) : *q;
+        }
     };
 
     // ---- initial state: its exact exponent, digits into buffer 0
@@ -185,17 +203,19 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
             }
             ey[tl][r] = exp_of(fabs(y[tl][r]));
         }
-    {
-        const int m = state_exp();
-        if (NT > 0 && grp == 0) atomicMax(mexp + s, m);
-    }
+    if (NT > 0) atomicMax(mexp + s, state_exp());
     __syncthreads();
     int Sx = mexp[s] == EMPTY ? 0 : mexp[s];  // the exponent the current state's digits were sliced with
     slice(Sx, 0);
     __syncthreads();
+    i4v x0[NXD];  // chunk 0 of the current state, fetched right after the barrier that completes it
+    fetch_x(0, 0, x0, true);
 
     for (long long t = 0; t < nsteps; ++t) {
         const int cur = (int)(t & 1);
+        // exponent of the current state's largest entry (complete since the
+        // last barrier; read now so that its latency hides under the MFMAs)
+        const int Mt = *(const volatile __attribute__((address_space(3))) int *)(mexp + (t & 3) * NS + s);
         // ---- MFMA phase
         i4v acc[NTA][LMAX + 1];
 #pragma unroll
@@ -205,10 +225,12 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
             i4v xf[NXD];
+            if (c == 0) {
 #pragma unroll
-            for (int b = 0; b < NXD; ++b)
-                xf[b] = *reinterpret_cast<const i4v *>(xdig + cur * buf + (size_t)b * sh.plane + s * sh.stride +
-                                                       c * 64 + grp * 16);
+                for (int b = 0; b < NXD; ++b) xf[b] = x0[b];
+            } else {
+                fetch_x(cur, c, xf, false);
+            }
 #pragma unroll
             for (int a = 0; a < NPD; ++a)
 #pragma unroll
@@ -225,15 +247,13 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
                 double v = (double)acc[tl][LMAX][r];
 #pragma unroll
                 for (int L = LMAX - 1; L >= 0; --L) v = fma(v, 1.0 / 256.0, (double)acc[tl][L][r]);
-                const int R = (wave + tl * WAVES) * 16 + grp * 4 + r;
-                y[tl][r] = ldexp(v, pexp[R] + Sx - YSHIFT);
+                y[tl][r] = ldexp(v, pe[tl][r] + Sx - YSHIFT);
                 ey[tl][r] = exp_of(fabs(y[tl][r]));
             }
         if (t + 1 == nsteps) break;  // uniform
         // ---- slice below the previous state's exponent M_t (speculative: the
         // state rarely crosses a power of two in one step); a state that did
         // is flagged and re-sliced below its own exponent after the barrier
-        const int Mt = mexp[(t & 3) * NS + s];
         const int Sspec = Mt == EMPTY ? 0 : Mt;
         const int m = state_exp();
         bool over = false;
@@ -243,7 +263,7 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
             for (int r = 0; r < 4; ++r) over |= ey[tl][r] > Sspec && ey[tl][r] != EMPTY;
         slice(Sspec, cur ^ 1);
         int *of = oflag + cur * (NS + 1);
-        if (NT > 0 && grp == 0) atomicMax(mexp + ((t + 1) & 3) * NS + s, m);
+        if (NT > 0) atomicMax(mexp + ((t + 1) & 3) * NS + s, m);
         if (over) {
             atomicOr(of + s, 1);
             atomicOr(of + NS, 1);
@@ -252,6 +272,7 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
         if (tid <= NS) oflag[(cur ^ 1) * (NS + 1) + tid] = 0;      // last read a step ago
         __syncthreads();
         Sx = Sspec;
+        fetch_x(cur ^ 1, 0, x0, true);  // with the flag read: one LDS round trip
         if (of[NS]) {  // uniform: some state of the workgroup outgrew its exponent
             if (of[s]) {
                 const int Mn = mexp[((t + 1) & 3) * NS + s];
@@ -259,6 +280,7 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
                 slice(Sx, cur ^ 1);
             }
             __syncthreads();
+            fetch_x(cur ^ 1, 0, x0, true);
         }
     }
     // ---- write the final state
