@@ -151,9 +151,9 @@ int lindblad_propagator(int n, int M, const void *L, const double *dt, double th
 /* The build of lindblad_propagator timed by stage, the method of the paper's
  * build-time breakdown (Table "Build-time breakdown per landscape point"):
  * HIP events recorded on `stream` at the stage boundaries give
- *   stage_ms[0] the LU solve of the Pade denominator (Alg. 1 line 6),
- *   stage_ms[1] the Pade products (powers, V, W, U: Alg. 1 lines 2-5),
- *   stage_ms[2] the s squarings (line 7),
+ *   stage_ms[0] the LU solve of the Pade denominator (Alg. 1),
+ *   stage_ms[1] the Pade products (powers, V, W, U: Alg. 1),
+ *   stage_ms[2] the s squarings,
  *   stage_ms[3] everything else (norm and scaling, V -/+ U, copies and the
  *               host's part of the scaling stage),
  * summed over the chunks the workspace splits the batch into.  Same

@@ -1,5 +1,5 @@
 // Batched solve D X = N (n x n, nrhs right-hand sides) by LU with partial
-// pivoting -- line 6 of Alg. 1, where D = V - U and N = V + U.
+// pivoting -- the denominator solve of Alg. 1, where D = V - U and N = V + U.
 //
 // Right-looking factorisation blocked on two levels: outer blocks J of
 // NBO = 64 columns (batches of 8 or more matrices; single panels below, where
@@ -8,10 +8,11 @@
 // forward substitution L^{-1} Pi N happens inside the factorisation's
 // updates.  Per outer block J:
 //   per panel, with updates confined to J's columns (all rows):
-//     1. lu_panel: one workgroup per matrix (1024 threads), each thread holds
-//        whole rows of the panel in registers; per column a block-wide argmax
-//        of |a|^2 (lowest row on ties), a row exchange through LDS, the
-//        multipliers and the rank-1 update of the rest of the panel;
+//     1. lu_panel: one workgroup per matrix (256 threads up to 768 rows,
+//        1024 beyond), each thread holds whole rows of the panel in
+//        registers; per column a block-wide argmax of |a|^2 (lowest row on
+//        ties), a row exchange through LDS, the multipliers and the rank-1
+//        update of the rest of the panel;
 //     2. the panel's row exchanges on the earlier panels' L columns of J (so
 //        that J's L ends in the final row order), and exchanges plus the
 //        unit-lower solve of the panel rows on J's later columns;
@@ -26,6 +27,7 @@
 // rows from the bottom, NB-row solves (trsm_upper) with their updates kept to
 // the outer block's rows, then one rank-NBO update N_above -= U_above,J X_J.
 #include <climits>
+#include <utility>
 
 #include "lb_internal.hpp"
 
@@ -167,9 +169,166 @@ __global__ void __launch_bounds__(PANEL_THREADS) lu_panel_kernel(cd *D, int n, l
     }
 }
 
+// The same panel factorisation for panels of at most 3 x 256 rows, by four
+// wavefronts: each thread holds R rows; per column a wavefront argmax by
+// shuffles, the four wavefront results through LDS and resolved by every
+// thread (one barrier), then the pivot row and row j through LDS (a second
+// barrier).  LDS is double-buffered by column parity, so two barriers per
+// column suffice.  The same pivot rule and the same per-element arithmetic as
+// lu_panel_kernel.  The column index is a template argument
+// (spanel_col<R, J>), so every register-array index is static and the rows
+// stay in registers for every R.
+constexpr int SPANEL_THREADS = 256;
+constexpr int SPANEL_MAX_ROWS = 3 * SPANEL_THREADS;
+constexpr int SPANEL_WAVES = SPANEL_THREADS / 64;
+
+struct SpanelLds {
+    double red_v[2][SPANEL_WAVES];
+    int red_i[2][SPANEL_WAVES];
+    cd rowbuf[2][2][NB];  // [column parity][pivot row, row j]
+};
+
+template <int R, int J>
+__device__ __forceinline__ void spanel_col(cd (&a)[R][NB], SpanelLds &sm, int tid, int nrows, int ncols, int n,
+                                           int k0, int b, int *ipiv, int *info) {
+    if (J >= ncols) return;  // uniform
+    constexpr int par = J & 1;
+    const int lane = tid & 63, wave = tid >> 6;
+    // ---- pivot search: largest |a|^2 in column J among rows >= J (lowest row on ties)
+    double bv = -1.0;
+    int bi = INT_MAX;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = tid + SPANEL_THREADS * q;
+        if (r >= J && r < nrows) {
+            const double v = a[q][J].re * a[q][J].re + a[q][J].im * a[q][J].im;
+            if (v > bv) {
+                bv = v;
+                bi = r;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    if (lane == 0) {
+        sm.red_v[par][wave] = bv;
+        sm.red_i[par][wave] = bi;
+    }
+    __syncthreads();
+    double v = sm.red_v[par][0];
+    int p = sm.red_i[par][0];
+#pragma unroll
+    for (int w = 1; w < SPANEL_WAVES; ++w)
+        if (sm.red_v[par][w] > v || (sm.red_v[par][w] == v && sm.red_i[par][w] < p)) {
+            v = sm.red_v[par][w];
+            p = sm.red_i[par][w];
+        }
+    const bool zero = !(v > 0.0);  // zero (or NaN) pivot: flag, keep going on the diagonal
+    if (zero) p = J;
+    if (tid == 0) {
+        if (zero) info[b] = 1;
+        ipiv[(size_t)b * n + k0 + J] = k0 + p;
+    }
+    // ---- row exchange J <-> p through LDS; rowbuf[par][0] holds the pivot row
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = tid + SPANEL_THREADS * q;
+        if (r == p) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) sm.rowbuf[par][0][c] = a[q][c];
+        }
+        if (r == J && p != J) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) sm.rowbuf[par][1][c] = a[q][c];
+        }
+    }
+    __syncthreads();
+    if (p != J) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = tid + SPANEL_THREADS * q;
+            if (r == J) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) a[q][c] = sm.rowbuf[par][0][c];
+            } else if (r == p) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) a[q][c] = sm.rowbuf[par][1][c];
+            }
+        }
+    }
+    // ---- multipliers and rank-1 update of the remaining panel columns (the
+    // pivot row read from LDS once, into registers)
+    cd ur[NB];
+#pragma unroll
+    for (int c = J; c < NB; ++c) ur[c] = sm.rowbuf[par][0][c];
+    const cd u = ur[J];
+    const double den = u.re * u.re + u.im * u.im;
+    const cd inv = {u.re / den, -u.im / den};
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = tid + SPANEL_THREADS * q;
+        if (r > J && r < nrows) {
+            const cd l = cmul(a[q][J], inv);
+            a[q][J] = l;
+#pragma unroll
+            for (int c = J + 1; c < NB; ++c) {
+                a[q][c].re = fma(-l.re, ur[c].re, fma(l.im, ur[c].im, a[q][c].re));
+                a[q][c].im = fma(-l.re, ur[c].im, fma(-l.im, ur[c].re, a[q][c].im));
+            }
+        }
+    }
+}
+
+template <int R, int... J>
+__device__ __forceinline__ void spanel_cols(std::integer_sequence<int, J...>, cd (&a)[R][NB], SpanelLds &sm, int tid,
+                                            int nrows, int ncols, int n, int k0, int b, int *ipiv, int *info) {
+    (spanel_col<R, J>(a, sm, tid, nrows, ncols, n, k0, b, ipiv, info), ...);
+}
+
+template <int R>
+__global__ void __launch_bounds__(SPANEL_THREADS) lu_panel_small_kernel(cd *D, int n, long long sD, int k0,
+                                                                        int *ipiv, int *info) {
+    const int b = blockIdx.x;
+    cd *A = D + (size_t)b * sD;
+    const int tid = threadIdx.x;
+    const int nrows = n - k0;
+    const int ncols = min(NB, n - k0);
+    __shared__ SpanelLds sm;
+
+    cd a[R][NB];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = tid + SPANEL_THREADS * q;
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            a[q][c] = (r < nrows && c < ncols) ? A[(size_t)(k0 + r) * n + k0 + c] : cd{0.0, 0.0};
+    }
+    spanel_cols<R>(std::make_integer_sequence<int, NB>{}, a, sm, tid, nrows, ncols, n, k0, b, ipiv, info);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = tid + SPANEL_THREADS * q;
+        if (r < nrows) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                if (c < ncols) A[(size_t)(k0 + r) * n + k0 + c] = a[q][c];
+        }
+    }
+}
+
 // Row exchanges of the panel k0 (rows k0 .. k0 + nb) and X1 = L11^{-1} X1
 // (its unit-lower block) on D columns [dc0, dc0 + dcount) and the first
 // ncount columns of N, one column per thread; either step can be skipped.
+// The panel's exchanges (row k0 + jj with row ipiv[jj], in order) are first
+// composed into one permutation of at most 2 NB rows (the panel's rows and
+// the pivot rows below it), so each column reads every moved row once and
+// writes it once: one memory round trip instead of one per exchange.
 __global__ void __launch_bounds__(256) swap_trsm_lower_kernel(cd *D, cd *N, int n, int nrhs, long long sD,
                                                               long long sN, int k0, int nb, const int *ipiv, int dc0,
                                                               int dcount, int ncount, int do_swap, int do_solve) {
@@ -177,31 +336,67 @@ __global__ void __launch_bounds__(256) swap_trsm_lower_kernel(cd *D, cd *N, int 
     cd *Dm = D + (size_t)b * sD;
     cd *Nm = N ? N + (size_t)b * sN : nullptr;
     __shared__ cd L11[NB][NB];
-    __shared__ int piv[NB];
+    // rows touched: the panel's nb rows (pos = k0 + i), then the pivot rows
+    // below it; src = the original row whose values end in that row.  Unused
+    // entries name row k0 on both sides (a read of row k0 and a write of its
+    // own value, before the panel rows are written): every column then reads
+    // and writes a fixed count of rows with no branches, so the reads issue
+    // together.
+    __shared__ int pos[2 * NB], src[2 * NB], pv[NB];
     for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
         const int i = e / NB, j = e % NB;
         L11[i][j] = (do_solve && i < nb && j < nb) ? Dm[(size_t)(k0 + i) * n + k0 + j] : cd{0.0, 0.0};
     }
-    if (threadIdx.x < NB) piv[threadIdx.x] = threadIdx.x < nb ? ipiv[(size_t)b * n + k0 + threadIdx.x] : 0;
+    if (threadIdx.x < NB) pv[threadIdx.x] = do_swap && threadIdx.x < nb ? ipiv[(size_t)b * n + k0 + threadIdx.x] : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {  // from LDS only: no global-memory round trip in this serial part
+        for (int i = 0; i < 2 * NB; ++i) pos[i] = src[i] = k0 + (i < nb ? i : 0);
+        int m = NB;  // next entry for a row below the panel
+        if (do_swap) {
+            for (int jj = 0; jj < nb; ++jj) {
+                const int p = pv[jj];
+                bool seen = p < k0 + nb;
+                for (int i = NB; i < m && !seen; ++i) seen = pos[i] == p;
+                if (!seen) pos[m] = src[m] = p, ++m;
+            }
+            for (int jj = 0; jj < nb; ++jj) {  // the exchanges in order, on the contents
+                const int p = pv[jj];
+                if (p != k0 + jj) {
+                    int ip = p - k0;  // index of row p (a panel row, or one below it)
+                    if (p >= k0 + nb)
+                        for (int i = NB; i < m; ++i)
+                            if (pos[i] == p) ip = i;
+                    const int t = src[jj];
+                    src[jj] = src[ip];
+                    src[ip] = t;
+                }
+            }
+        }
+    }
     __syncthreads();
     const int v = blockIdx.x * blockDim.x + threadIdx.x;  // one column per thread (grid covers all)
     if (v < dcount + ncount) {
         cd *col = v < dcount ? Dm + (dc0 + v) : Nm + (v - dcount);
         const size_t ld = v < dcount ? (size_t)n : (size_t)nrhs;
-        if (do_swap) {
-            for (int jj = 0; jj < nb; ++jj) {
-                const int r = k0 + jj, p = piv[jj];
-                if (p != r) {
-                    const cd t = col[(size_t)r * ld];
-                    col[(size_t)r * ld] = col[(size_t)p * ld];
-                    col[(size_t)p * ld] = t;
-                }
-            }
+        // every read before any write (the row indices first: a write through
+        // col could alias the LDS tables as far as the compiler knows)
+        int rs[2 * NB], rd[NB];
+#pragma unroll
+        for (int i = 0; i < 2 * NB; ++i) rs[i] = src[i];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) rd[i] = pos[NB + i];
+        cd x[NB], w[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) x[i] = col[(size_t)rs[i] * ld];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) w[i] = col[(size_t)rs[NB + i] * ld];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            double *q = reinterpret_cast<double *>(col + (size_t)rd[i] * ld);
+            q[0] = w[i].re;
+            q[1] = w[i].im;
         }
         if (do_solve) {
-            cd x[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) x[i] = i < nb ? col[(size_t)(k0 + i) * ld] : cd{0.0, 0.0};
 #pragma unroll
             for (int i = 1; i < NB; ++i) {
                 if (i < nb) {
@@ -215,16 +410,11 @@ __global__ void __launch_bounds__(256) swap_trsm_lower_kernel(cd *D, cd *N, int 
                     x[i] = acc;
                 }
             }
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-                if (i < nb) col[(size_t)(k0 + i) * ld] = x[i];
         }
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            if (i < nb) col[(size_t)(k0 + i) * ld] = x[i];
     }
-}
-
-__device__ inline cd cdiv(cd a, cd d) {
-    const double den = d.re * d.re + d.im * d.im;
-    return {(a.re * d.re + a.im * d.im) / den, (a.im * d.re - a.re * d.im) / den};
 }
 
 // X_block = U_block^{-1} X_block for the rows [b0, b0 + nb) of every column of N.
@@ -234,9 +424,16 @@ __global__ void __launch_bounds__(256) trsm_upper_kernel(const cd *D, cd *N, int
     const cd *Dm = D + (size_t)b * sD;
     cd *Nm = N + (size_t)b * sN;
     __shared__ cd U[NB][NB];
+    __shared__ cd Ur[NB];  // 1 / U[i][i], so that the per-column chain holds no division
     for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
         const int i = e / NB, j = e % NB;
         U[i][j] = (i < nb && j < nb) ? Dm[(size_t)(b0 + i) * n + b0 + j] : cd{1.0, 0.0};
+    }
+    __syncthreads();
+    if (threadIdx.x < NB) {
+        const cd d = U[threadIdx.x][threadIdx.x];
+        const double den = d.re * d.re + d.im * d.im;
+        Ur[threadIdx.x] = {d.re / den, -d.im / den};
     }
     __syncthreads();
     const int c = blockIdx.x * blockDim.x + threadIdx.x;  // one column per thread (grid covers all)
@@ -255,7 +452,7 @@ __global__ void __launch_bounds__(256) trsm_upper_kernel(const cd *D, cd *N, int
                         acc.re = fma(-u.re, x[j].re, fma(u.im, x[j].im, acc.re));
                         acc.im = fma(-u.re, x[j].im, fma(-u.im, x[j].re, acc.im));
                     }
-                x[i] = cdiv(acc, U[i][i]);
+                x[i] = cmul(acc, Ur[i]);
             }
         }
 #pragma unroll
@@ -328,7 +525,13 @@ int lu_solve_batched(int n, int nrhs, int batch, cd *D, cd *N, int *ipiv, int *i
         // ---- the outer block J = [K0, KE): 16-column panels, updates kept to J
         for (int k0 = K0; k0 < KE; k0 += NB) {
             const int nb = KE - k0 < NB ? KE - k0 : NB;
-            if (n - k0 <= PANEL_THREADS)
+            if (n - k0 <= SPANEL_THREADS)
+                lu_panel_small_kernel<1><<<batch, SPANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
+            else if (n - k0 <= 2 * SPANEL_THREADS)
+                lu_panel_small_kernel<2><<<batch, SPANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
+            else if (n - k0 <= SPANEL_MAX_ROWS)
+                lu_panel_small_kernel<3><<<batch, SPANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
+            else if (n - k0 <= PANEL_THREADS)
                 lu_panel_kernel<1><<<batch, PANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);
             else if (n - k0 <= 2 * PANEL_THREADS)
                 lu_panel_kernel<2><<<batch, PANEL_THREADS, 0, s>>>(D, n, sD, k0, ipiv, info);

@@ -32,30 +32,48 @@ void pade13_coefficients(double b[14]) {
 
 // Column sums of |L dt| over all rows, max over the columns of each matrix,
 // merged across workgroups with an integer atomic max on the bit pattern
-// (non-negative doubles order like their bits; NaN wins).
+// (non-negative doubles order like their bits; NaN wins).  A workgroup takes
+// 16 columns: per block of 256 rows all its threads compute the moduli
+// (coalesced 256-byte row pieces) into LDS, then 16 threads add them to their
+// column's sum in row order, so every column is summed in the order of a
+// plain loop over the rows.
+constexpr int N1_COLS = 16, N1_ROWS = 256;
 __global__ void __launch_bounds__(256) norm1_kernel(int n, const cd *__restrict__ L, const double *__restrict__ dt,
                                                     unsigned long long *__restrict__ normbits) {
     const int m = blockIdx.y;
     const cd *Lm = L + (size_t)m * n * n;
     const double h = dt[m];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    double s = 0.0;
-    if (j < n)
-        for (int i = 0; i < n; ++i) {
-            const cd v = Lm[(size_t)i * n + j];
-            s += hypot(v.re * h, v.im * h);
+    const int j0 = blockIdx.x * N1_COLS, tid = threadIdx.x;
+    __shared__ double mag[N1_ROWS][N1_COLS + 1];
+    double s = 0.0;  // the column sum of thread tid < N1_COLS
+    for (int i0 = 0; i0 < n; i0 += N1_ROWS) {
+        for (int e = tid; e < N1_ROWS * N1_COLS; e += 256) {
+            const int r = e / N1_COLS, c = e - r * N1_COLS;
+            const int i = i0 + r, j = j0 + c;
+            double v = 0.0;
+            if (i < n && j < n) {
+                const cd x = Lm[(size_t)i * n + j];
+                v = hypot(x.re * h, x.im * h);
+            }
+            mag[r][c] = v;
         }
-    __shared__ double red[256];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            const double o = red[threadIdx.x + w], c = red[threadIdx.x];
-            if (isnan(o) || (!isnan(c) && o > c)) red[threadIdx.x] = o;  // NaN wins
+        __syncthreads();
+        if (tid < N1_COLS) {
+            const int rows = min(N1_ROWS, n - i0);
+            for (int r = 0; r < rows; ++r) s += mag[r][tid];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(normbits + m, (unsigned long long)__double_as_longlong(red[0]));
+    if (tid < N1_COLS) mag[0][tid] = s;  // the last barrier ended every read of mag
+    __syncthreads();
+    if (tid == 0) {
+        double best = 0.0;
+        for (int c = 0; c < N1_COLS; ++c) {
+            const double o = mag[0][c];
+            if (isnan(o) || (!isnan(best) && o > best)) best = o;  // NaN wins
+        }
+        atomicMax(normbits + m, (unsigned long long)__double_as_longlong(best));
+    }
 }
 
 __global__ void fill_u64_kernel(unsigned long long *p, int count) {
@@ -114,7 +132,7 @@ int scaling_stage(int n, int M, const cd *L, const double *dt_host, double theta
     LB_HIP(hipMemcpyAsync(d_dt, dt_host, M * sizeof(double), hipMemcpyHostToDevice, s));
     fill_u64_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_norm, M);
     {
-        dim3 grid((n + 255) / 256, M);
+        dim3 grid((n + N1_COLS - 1) / N1_COLS, M);
         norm1_kernel<<<grid, 256, 0, s>>>(n, L, d_dt, d_norm);
         LB_TRY(check_launch("norm1"));
     }
@@ -383,7 +401,7 @@ static int build_chunk_stream_ordered(int n, int M, const cd *L, const double *d
     fill_u64_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_norm, M);
     fill_i32_kernel<<<(M + 255) / 256, 256, 0, s>>>(d_info, M);
     {
-        dim3 grid((n + 255) / 256, M);
+        dim3 grid((n + N1_COLS - 1) / N1_COLS, M);
         norm1_kernel<<<grid, 256, 0, s>>>(n, L, d_dt, d_norm);
         LB_TRY(check_launch("norm1"));
     }
