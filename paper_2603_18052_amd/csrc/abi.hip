@@ -27,6 +27,19 @@ int check_launch(const char *what) {
     return LB_OK;
 }
 
+int set_max_lds(const void *kernel, size_t bytes) {
+    int dev = 0;
+    LB_HIP(hipGetDevice(&dev));
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, size_t> done;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &have = done[{dev, kernel}];
+    if (have >= bytes) return LB_OK;
+    LB_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    have = bytes;
+    return LB_OK;
+}
+
 // ------------------------------------------------------------ workspace
 void ws_begin(Workspace *ws, hipStream_t s) {
     ws->used = 0;

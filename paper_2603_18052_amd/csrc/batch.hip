@@ -430,14 +430,9 @@ static int enqueue_all(const std::vector<std::vector<const lb_problem *>> &parts
         total += groups.back().bytes;
     }
     LB_TRY(ws_ensure(w, total));
-    // one-time kernel attribute (set outside any capture: the first call of a
-    // process is eager in every caller here)
-    static bool attr = false;
-    if (!attr) {
-        LB_HIP(hipFuncSetAttribute((const void *)small_chain_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   160 * 1024));
-        attr = true;
-    }
+    // the kernel's LDS limit (a host-side attribute, set once per device; not
+    // a stream operation, so also allowed while the caller captures a graph)
+    LB_TRY(set_max_lds((const void *)small_chain_kernel<T>, 160 * 1024));
     bool any_small = false, any_large = false;
     for (const Group &g : groups) (g.small ? any_small : any_large) = true;
     if (!(any_small && any_large)) {  // one stream

@@ -424,12 +424,7 @@ __global__ void __launch_bounds__(CW * 64) balanced_chain_kernel(int n, const cd
 template <typename T, int KS>
 static int launch_balanced_k(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
     const size_t lds = sizeof(T) * 2 * (size_t)kBalBuf;
-    static bool attr_set = false;
-    if (!attr_set) {
-        LB_HIP(hipFuncSetAttribute((const void *)balanced_chain_kernel<T, KS>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = true;
-    }
+    LB_TRY(set_max_lds((const void *)balanced_chain_kernel<T, KS>, lds));
     balanced_chain_kernel<T, KS><<<(B + NS - 1) / NS, CW * 64, lds, s>>>(n, P, B, rho, nsteps);
     return check_launch("balanced_chain");
 }
@@ -603,12 +598,7 @@ __global__ void __launch_bounds__(WPB * 64) tail_chain_kernel(int n, const cd *_
 template <typename T, int NV, int WPB>
 static int launch_tail_k(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
     const size_t lds = sizeof(Pair<T>) * 2 * (size_t)kTailBuf;
-    static bool attr_set = false;
-    if (!attr_set) {
-        LB_HIP(hipFuncSetAttribute((const void *)tail_chain_kernel<T, NV, WPB>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = true;
-    }
+    LB_TRY(set_max_lds((const void *)tail_chain_kernel<T, NV, WPB>, lds));
     tail_chain_kernel<T, NV, WPB><<<(B + NS - 1) / NS, WPB * 64, lds, s>>>(n, P, B, rho, nsteps);
     return check_launch("tail_chain");
 }
@@ -821,12 +811,7 @@ __global__ void __launch_bounds__(CW * 64) tiles_chain_kernel(int n, const cd *_
 template <typename T, bool PRESUM>
 static int launch_tiles_k(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
     const size_t lds = sizeof(Pair<T>) * 2 * (size_t)kTilesBuf;
-    static bool attr_set = false;
-    if (!attr_set) {
-        LB_HIP(hipFuncSetAttribute((const void *)tiles_chain_kernel<T, PRESUM>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = true;
-    }
+    LB_TRY(set_max_lds((const void *)tiles_chain_kernel<T, PRESUM>, lds));
     tiles_chain_kernel<T, PRESUM><<<(B + NS - 1) / NS, CW * 64, lds, s>>>(n, P, B, rho, nsteps);
     return check_launch("tiles_chain");
 }
@@ -865,12 +850,7 @@ int fused_max_n(lb_precision prec) {
 template <typename T, int KPU, int UPW>
 static int launch_fused_k(int n, int kparts, const cd *P, int B, cd *rho, long long nsteps, size_t lds,
                           hipStream_t s) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        LB_HIP(hipFuncSetAttribute((const void *)fused_chain_kernel<T, KPU, UPW>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-        attr_set = true;
-    }
+    LB_TRY(set_max_lds((const void *)fused_chain_kernel<T, KPU, UPW>, kLdsLimit));
     const int blocks = (B + NS - 1) / NS;
     fused_chain_kernel<T, KPU, UPW><<<blocks, CW * 64, lds, s>>>(n, kparts, P, B, rho, nsteps);
     return check_launch("fused_chain");

@@ -361,12 +361,7 @@ static int launch(int n, const cd *P, int B, cd *rho, long long nsteps, hipStrea
     const Shape sh = shape(n);
     if (lds > kLds || (sh.units + WAVES - 1) / WAVES > UMAX)
         return fail(LB_ESHAPE, "bf16 chain: n too large for the fused kernel");
-    static bool attr = false;
-    if (!attr) {
-        LB_HIP(hipFuncSetAttribute((const void *)bf16_chain_kernel<MODE, SP, SX, LMAX>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds));
-        attr = true;
-    }
+    LB_TRY(set_max_lds((const void *)bf16_chain_kernel<MODE, SP, SX, LMAX>, kLds));
     bf16_chain_kernel<MODE, SP, SX, LMAX><<<(B + NS - 1) / NS, WAVES * 64, lds, s>>>(n, P, B, rho, nsteps);
     return check_launch("bf16_chain");
 }

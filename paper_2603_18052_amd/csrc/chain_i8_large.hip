@@ -478,14 +478,8 @@ int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspac
     init_x_kernel<<<B, 256, 0, s>>>(n, Kp, B, rho, X0, X1, Mx, gbits);
     LB_TRY(check_launch("i8 init_x"));
     constexpr int lds = RING * STAGE + TS * 4;
-    static bool attr = false;
-    if (!attr) {
-        LB_HIP(hipFuncSetAttribute((const void *)i8_gemm_step_kernel<false>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        LB_HIP(hipFuncSetAttribute((const void *)i8_gemm_step_kernel<true>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        attr = true;
-    }
+    LB_TRY(set_max_lds((const void *)i8_gemm_step_kernel<false>, lds));
+    LB_TRY(set_max_lds((const void *)i8_gemm_step_kernel<true>, lds));
     LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
         const signed char *xc = (t & 1) ? X1 : X0;
         signed char *xn = (t & 1) ? X0 : X1;

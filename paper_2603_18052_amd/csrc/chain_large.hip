@@ -1414,12 +1414,7 @@ static int trgemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Work
     for (int q = 0; q < 2; ++q)  // zero k padding of both buffers
         to_planes_kernel<T><<<grid1((long long)B * Kp), 256, 0, s>>>(B, n, Kp, rho, X[q][0], X[q][1]);
     LB_TRY(check_launch("to_planes"));
-    static bool attr_set = false;
-    if (!attr_set) {
-        LB_HIP(hipFuncSetAttribute((const void *)trgemm_step_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   S::LDS));
-        attr_set = true;
-    }
+    LB_TRY(set_max_lds((const void *)trgemm_step_kernel<T>, S::LDS));
     LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
         const int c = (int)(t & 1);
         cd *out = t + 1 == nsteps ? rho : nullptr;
@@ -1450,12 +1445,7 @@ static int tgemm_run(int n, const cd *P, int B, cd *rho, long long nsteps, Works
         to_planes_kernel<T><<<grid1((long long)B * Kp), 256, 0, s>>>(B, n, Kp, rho, X[q][0], X[q][1]);
     LB_TRY(check_launch("to_planes"));
     const size_t lds = 2 * (size_t)S::BUF * sizeof(T);
-    static bool attr_set = false;
-    if (!attr_set) {
-        LB_HIP(hipFuncSetAttribute((const void *)tgemm_step_kernel<T, WPB>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = true;
-    }
+    LB_TRY(set_max_lds((const void *)tgemm_step_kernel<T, WPB>, lds));
     const int nbt = (B + TGB - 1) / TGB, nit = (n + TGI - 1) / TGI;
     LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
         const int c = (int)(t & 1);
@@ -1495,19 +1485,9 @@ static int planes_run(int n, const cd *P, int B, cd *rho, long long nsteps, Work
     dim3 grid((n + TO - 1) / TO, (B + TS - 1) / TS);
     const size_t lds = tiled >= 2 ? (size_t)TqShape<MODE, SP, SX>::LDS : 2 * (size_t)TpShape<MODE, SP, SX>::BUF;
     if (tiled == 1) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            LB_HIP(hipFuncSetAttribute((const void *)tplane_gemm_kernel<MODE, SP, SX, LMAX>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            attr_set = true;
-        }
+        LB_TRY(set_max_lds((const void *)tplane_gemm_kernel<MODE, SP, SX, LMAX>, lds));
     } else if (tiled >= 2) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            LB_HIP(hipFuncSetAttribute((const void *)tqplane_gemm_kernel<MODE, SP, SX, LMAX>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            attr_set = true;
-        }
+        LB_TRY(set_max_lds((const void *)tqplane_gemm_kernel<MODE, SP, SX, LMAX>, lds));
     }
     // the state ping-pongs between rho and Yt
     LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
@@ -1672,12 +1652,7 @@ int expmv_run(int n, const cd *L, double t, double mur, double mui, int s, int m
     const bool tiled = (long long)((B + TGB - 1) / TGB) * ((n + TGI - 1) / TGI) >= 240;
     const size_t lds = 2 * (size_t)S::BUF * sizeof(double);
     if (tiled) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            LB_HIP(hipFuncSetAttribute((const void *)tgemm_step_kernel<double, 8>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            attr_set = true;
-        }
+        LB_TRY(set_max_lds((const void *)tgemm_step_kernel<double, 8>, lds));
     }
     const int nbt = (B + TGB - 1) / TGB, nit = (n + TGI - 1) / TGI;
     dim3 grid((n + 15) / 16, (B + TS - 1) / TS);

@@ -32,6 +32,10 @@ int fail(int status, const std::string &msg);
 // Launch status of the last kernel launch on this thread.
 int check_launch(const char *what);
 
+// Allow `kernel` up to `bytes` of dynamic LDS on the current device: one
+// hipFuncSetAttribute per (device, kernel) and size increase, thread-safe.
+int set_max_lds(const void *kernel, size_t bytes);
+
 // --------------------------------------------------------- workspace
 // Bump allocator over one device buffer; reset at the start of every call.
 struct Workspace {
