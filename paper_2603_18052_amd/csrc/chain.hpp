@@ -56,7 +56,8 @@ int i8_fused_max_n();
 int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s);
 int fx_i8_max_n();
 size_t i8_gemm_ws_bytes(int n, int B);
-int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s, bool graph);
+int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s, bool graph,
+                  bool small);
 int chain_fx_i8(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
 int chain_bf16_fused(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
 

@@ -31,7 +31,10 @@
 // 64-byte digit rows sit at XOR-swizzled 16-byte positions so that the
 // operand fetches run without bank conflicts.  Each XCD takes a 4 x 8 block
 // of tiles, so that 4 row blocks of Q's digits and 8 state blocks pass
-// through its L2.
+// through its L2.  Small batches use a 64-row x 16-state tile (one MFMA tile
+// per wavefront) with six 24 KB slots, five chunks in flight: more
+// workgroups (92 at n = 729, B <= 64 against 16) and a deeper ring for the
+// load latency that one chunk's 14 MFMAs per wavefront cannot cover.
 #include "chain.hpp"
 
 namespace lb {
@@ -43,14 +46,31 @@ constexpr int NPD = 5, NXD = 4, LMAX = 4;
 constexpr int FRAC_P = 38, FRAC_X = 30;
 constexpr int YSHIFT = FRAC_P + FRAC_X - 8 * (NPD - 1) - 8 * (NXD - 1);  // 12
 constexpr int EMPTY = -100000;
-constexpr int TR = 96, TS = 64, KC = 64;  // rows, states, k per chunk
-constexpr int RT = 3, ST = 2;             // 16-row / 16-state tiles per wavefront
-constexpr int APL = TR * KC, BPL = TS * KC;
-constexpr int STAGE = NPD * APL + NXD * BPL;  // 47104 bytes per ring slot
-constexpr int RING = 3;                       // slots: chunk c computed while c + 1, c + 2 load
-constexpr int NLA = NPD * TR / 16, NLB = NXD * TS / 16;  // 1 KB loads per chunk: 30 + 16
-constexpr int NLT = NLA + NLB;
-constexpr int NLW = (NLT + 3) / 4;                       // per wavefront (12)
+constexpr int KC = 64;    // k per chunk (one MFMA deep)
+constexpr int TRMAX = 96;  // the tallest tile: row exponents are padded by less than this
+
+// A workgroup tile: TR rows of Q x TS states, four wavefronts in a WR x WS
+// grid of RT x ST MFMA tiles each, a ring of RING LDS slots of STAGE bytes
+// (one chunk: five Q digit planes and four state digit planes), each chunk
+// NLT loads of 1 KB (NLW per wavefront), then TS ints of exponent maxima.
+template <int TR_, int TS_, int RT_, int ST_, int RING_>
+struct GShape {
+    static constexpr int TR = TR_, TS = TS_, RT = RT_, ST = ST_, RING = RING_;
+    static constexpr int WR = TR / (16 * RT), WS = TS / (16 * ST);
+    static constexpr int APL = TR * KC, BPL = TS * KC;
+    static constexpr int STAGE = NPD * APL + NXD * BPL;
+    static constexpr int NLA = NPD * TR / 16, NLB = NXD * TS / 16, NLT = NLA + NLB;
+    static constexpr int NLW = (NLT + 3) / 4;
+    static constexpr int LDS = RING * STAGE + TS * 4;
+    static_assert(WR * WS == 4 && TR <= TRMAX && LDS <= 160 * 1024, "tile shape");
+    static_assert((RING - 1) * NLW < 64, "vmcnt range");
+};
+// 96 x 64 (256 workgroups at n = 729, B = 1024): 47 KB slots, two chunks in
+// flight behind the one being fetched
+using BigTile = GShape<96, 64, 3, 2, 3>;
+// 64 x 16 for small batches (92 workgroups at n = 729, B = 64): 24 KB slots,
+// five chunks in flight
+using SmallTile = GShape<64, 16, 1, 1, 6>;
 
 // Workgroup barrier of the ring: wait until at most N of this wavefront's
 // vector loads are outstanding and its LDS accesses are done (s_waitcnt,
@@ -206,17 +226,16 @@ __device__ inline void tile_of(int T, int nrb, int nsb, int &rb, int &sb) {
 }
 
 // one step: x_{t+1} = Q x_t for all states (t4 = t mod 4); the last step
-// (LAST) writes FP64 into rho instead of digits.  Dynamic LDS: the ring, then
-// TS ints for the workgroup's exponent maxima.
-template <bool LAST>
-__global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B, int nrb, int nsb,
-                                                           const signed char *__restrict__ Qd,
-                                                           const int *__restrict__ eP,
-                                                           const signed char *__restrict__ Xc,
-                                                           signed char *__restrict__ Xn, int *__restrict__ Mx,
-                                                           const unsigned long long *__restrict__ gbits, int t4,
-                                                           cd *__restrict__ rho) {
-    extern __shared__ __align__(16) unsigned char smem[];
+// (LAST) writes FP64 into rho instead of digits.  Dynamic LDS (smem): the
+// ring, then TS ints for the workgroup's exponent maxima.
+template <class S, bool LAST>
+__device__ __forceinline__ void i8_gemm_body(unsigned char *smem, int n, int Kp, int B, int nrb, int nsb,
+                                             const signed char *__restrict__ Qd, const int *__restrict__ eP,
+                                             const signed char *__restrict__ Xc, signed char *__restrict__ Xn,
+                                             int *__restrict__ Mx, const unsigned long long *__restrict__ gbits,
+                                             int t4, cd *__restrict__ rho) {
+    constexpr int TR = S::TR, TS = S::TS, RT = S::RT, ST = S::ST, RING = S::RING;
+    constexpr int APL = S::APL, BPL = S::BPL, STAGE = S::STAGE, NLA = S::NLA, NLT = S::NLT, NLW = S::NLW;
     int *emx = reinterpret_cast<int *>(smem + RING * STAGE);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -229,7 +248,7 @@ __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B,
     const int r0 = rb * TR, s0 = sb * TS;
     const size_t qplane = (size_t)n2 * Kp, xplane = (size_t)B * Kp;
     const int nch = Kp / KC;
-    const int wr = (wave & 1) * (RT * 16), ws = (wave >> 1) * (ST * 16);  // this wavefront's rows / states
+    const int wr = (wave % S::WR) * (RT * 16), ws = (wave / S::WR) * (ST * 16);  // this wavefront's rows / states
     const int fr = lane & 15, fp = lane >> 4;
 
     // The epilogue's operands, loaded first so that they land under the k
@@ -324,31 +343,30 @@ __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B,
                         for (int j = 0; j < ST; ++j) acc[i][j][a + bd] = mma(pa[i][a], xb[j][bd], acc[i][j][a + bd]);
     };
     // Chunk c is computed from registers while chunk c + 1's operands come
-    // from LDS into the other register set and chunks c + 2, c + 3 load into
-    // the ring: the barrier before chunk c + 1's fetch (its loads landed in
-    // every wavefront; every wavefront's fetch of chunk c is complete)
-    // frees chunk c's slot for chunk c + 3.  The last chunk fetches itself
+    // from LDS into the other register set and chunks c + 2 .. c + RING load
+    // into the ring: the barrier before chunk c + 1's fetch (its loads landed
+    // in every wavefront; every wavefront's fetch of chunk c is complete)
+    // frees chunk c's slot for chunk c + RING.  The last chunk fetches itself
     // again (its slot is no longer written) so that the fetch and the MFMAs
     // form one branch-free block.
     auto step = [&](int c, const i4v (&xc)[ST][NXD], const i4v (&pc)[RT][NPD], i4v (&xn)[ST][NXD],
                     i4v (&pn)[RT][NPD]) {
         // (one barrier on every path: the compiler's wait analysis then sees
         // every earlier fetch complete before the MFMAs)
-        if (c + 2 >= nch) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt 0: no chunk c + 2 behind c + 1
-        I8_SYNC(NLW);
-        if (c + 3 < nch) dma(c + 3, c % RING);
+        // (near the end fewer than RING - 2 chunks follow c + 1: wait for all)
+        if (c + RING - 1 >= nch) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt 0
+        I8_SYNC((RING - 2) * NLW);
+        if (c + RING < nch) dma(c + RING, c % RING);
         fetch(c + 1 < nch ? c + 1 : c, xn, pn);
         mfmas(xc, pc);
     };
 
     i4v x0[ST][NXD], p0[RT][NPD], x1[ST][NXD], p1[RT][NPD];
-    dma(0, 0);
-    if (nch > 1) dma(1, 1);
-    if (nch > 2) dma(2, 2);
-    if (nch > 2)
-        I8_SYNC(2 * NLW);
-    else if (nch > 1)
-        I8_SYNC(NLW);
+#pragma unroll
+    for (int c = 0; c < RING; ++c)
+        if (c < nch) dma(c, c);
+    if (nch >= RING)
+        I8_SYNC((RING - 1) * NLW);  // chunk 0 landed, 1 .. RING - 1 may be in flight
     else
         I8_SYNC(0);
     fetch(0, x0, p0);
@@ -439,6 +457,30 @@ __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B,
     }
 }
 
+template <bool LAST>
+__global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B, int nrb, int nsb,
+                                                           const signed char *__restrict__ Qd,
+                                                           const int *__restrict__ eP,
+                                                           const signed char *__restrict__ Xc,
+                                                           signed char *__restrict__ Xn, int *__restrict__ Mx,
+                                                           const unsigned long long *__restrict__ gbits, int t4,
+                                                           cd *__restrict__ rho) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    i8_gemm_body<BigTile, LAST>(smem, n, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
+}
+
+template <bool LAST>
+__global__ void __launch_bounds__(256) i8_gemm_small_kernel(int n, int Kp, int B, int nrb, int nsb,
+                                                            const signed char *__restrict__ Qd,
+                                                            const int *__restrict__ eP,
+                                                            const signed char *__restrict__ Xc,
+                                                            signed char *__restrict__ Xn, int *__restrict__ Mx,
+                                                            const unsigned long long *__restrict__ gbits, int t4,
+                                                            cd *__restrict__ rho) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    i8_gemm_body<SmallTile, LAST>(smem, n, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
+}
+
 static int grid1(long long work) {
     long long g = (work + 255) / 256;
     if (g > 65536) g = 65536;
@@ -449,20 +491,38 @@ static int grid1(long long work) {
 
 size_t i8_gemm_ws_bytes(int n, int B) {
     const size_t Kp = (size_t)(2 * n + 63) / 64 * 64;
-    const size_t npad = (size_t)(2 * n + i8g::TR - 1) / i8g::TR * i8g::TR;
+    const size_t npad = (size_t)2 * n + i8g::TRMAX;  // row exponents padded to whole row blocks of any tile
     return align256((size_t)i8g::NPD * 2 * n * Kp) + align256(npad * 4) +
            2 * align256((size_t)i8g::NXD * B * Kp) + align256((size_t)4 * B * 4) + 256;
 }
 
-int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s, bool graph) {
+namespace i8g {
+// the step launches of one tile shape (K<LAST> = its two kernels)
+template <class S, class Launch>
+static int run_tiles(int n, int Kp, int B, const signed char *Qd, const int *eP, signed char *X0, signed char *X1,
+                     int *Mx, const unsigned long long *gbits, cd *rho, long long nsteps, bool graph, hipStream_t s,
+                     const void *k_step, const void *k_last, Launch launch) {
+    const int nrb = (2 * n + S::TR - 1) / S::TR, nsb = (B + S::TS - 1) / S::TS;
+    LB_TRY(set_max_lds(k_step, S::LDS));
+    LB_TRY(set_max_lds(k_last, S::LDS));
+    LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
+        launch(t + 1 == nsteps, nrb * nsb, S::LDS, st, n, Kp, B, nrb, nsb, Qd, eP, (t & 1) ? X1 : X0,
+               (t & 1) ? X0 : X1, Mx, gbits, (int)(t & 3), rho);
+        return LB_OK;
+    }, s));
+    return check_launch("i8 gemm step");
+}
+}  // namespace i8g
+
+int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s, bool graph,
+                  bool small) {
     using namespace i8g;
     if (nsteps == 0 || B == 0) return LB_OK;
     const int n2 = 2 * n, Kp = (n2 + 63) / 64 * 64;
     LB_TRY(ws_ensure(ws, i8_gemm_ws_bytes(n, B)));
     const size_t mark = ws->used;
     signed char *Qd = (signed char *)ws_take(ws, (size_t)NPD * n2 * Kp);
-    const int nrb = (n2 + TR - 1) / TR, nsb = (B + TS - 1) / TS;
-    int *eP = (int *)ws_take(ws, (size_t)nrb * TR * 4);
+    int *eP = (int *)ws_take(ws, (size_t)(n2 + TRMAX) * 4);
     signed char *X0 = (signed char *)ws_take(ws, (size_t)NXD * B * Kp);
     signed char *X1 = (signed char *)ws_take(ws, (size_t)NXD * B * Kp);
     int *Mx = (int *)ws_take(ws, (size_t)4 * B * 4);
@@ -472,26 +532,29 @@ int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspac
         size_t m;
         ~Release() { w->used = m; }
     } release{ws, mark};
+    const int tr = small ? SmallTile::TR : BigTile::TR;
     LB_TRY(fill_i32_launch(reinterpret_cast<int *>(gbits), 2, s));
-    prep_q_kernel<<<n2, 256, 0, s>>>(n, Kp, nrb * TR, P, Qd, eP, gbits);
+    prep_q_kernel<<<n2, 256, 0, s>>>(n, Kp, (n2 + tr - 1) / tr * tr, P, Qd, eP, gbits);
     LB_TRY(check_launch("i8 prep_q"));
     init_x_kernel<<<B, 256, 0, s>>>(n, Kp, B, rho, X0, X1, Mx, gbits);
     LB_TRY(check_launch("i8 init_x"));
-    constexpr int lds = RING * STAGE + TS * 4;
-    LB_TRY(set_max_lds((const void *)i8_gemm_step_kernel<false>, lds));
-    LB_TRY(set_max_lds((const void *)i8_gemm_step_kernel<true>, lds));
-    LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
-        const signed char *xc = (t & 1) ? X1 : X0;
-        signed char *xn = (t & 1) ? X0 : X1;
-        if (t + 1 == nsteps)
-            i8_gemm_step_kernel<true><<<nrb * nsb, 256, lds, st>>>(n, Kp, B, nrb, nsb, Qd, eP, xc, xn, Mx, gbits,
-                                                                   (int)(t & 3), rho);
-        else
-            i8_gemm_step_kernel<false><<<nrb * nsb, 256, lds, st>>>(n, Kp, B, nrb, nsb, Qd, eP, xc, xn, Mx, gbits,
-                                                                    (int)(t & 3), rho);
-        return LB_OK;
-    }, s));
-    return check_launch("i8 gemm step");
+    if (small)
+        return run_tiles<SmallTile>(
+            n, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_small_kernel<false>,
+            (const void *)i8_gemm_small_kernel<true>, [](bool last, int grid, int lds, hipStream_t st, auto... a) {
+                if (last)
+                    i8_gemm_small_kernel<true><<<grid, 256, lds, st>>>(a...);
+                else
+                    i8_gemm_small_kernel<false><<<grid, 256, lds, st>>>(a...);
+            });
+    return run_tiles<BigTile>(
+        n, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_step_kernel<false>,
+        (const void *)i8_gemm_step_kernel<true>, [](bool last, int grid, int lds, hipStream_t st, auto... a) {
+            if (last)
+                i8_gemm_step_kernel<true><<<grid, 256, lds, st>>>(a...);
+            else
+                i8_gemm_step_kernel<false><<<grid, 256, lds, st>>>(a...);
+        });
 }
 
 }  // namespace lb

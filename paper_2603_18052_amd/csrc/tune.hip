@@ -92,6 +92,7 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
     } else if (prec == LB_I8_SLICED) {
         if (n <= i8_fused_max_n()) add(VF_I8_FUSED * 100);
         add2(VF_I8_GEMM * 100);
+        add2(VF_I8_GEMM * 100 + 1);
     }
     return c;
 }
@@ -111,6 +112,8 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
 // tile per wavefront up to 256 states (more workgroups) and two beyond, or a
 // matvec for few states.  BF16: the fused chain while P fits on chip, else
 // the BF16 plane GEMM per step, LDS-tiled once its tiles fill the chip.
+// INT8 digits: the fused chain while Q's digits fit in registers, else the
+// per-step INT8 GEMM with the tile shape that fills the chip.
 int chain_heuristic(int n, lb_precision prec, int B) {
     switch (prec) {
         case LB_C128:
@@ -139,8 +142,15 @@ int chain_heuristic(int n, lb_precision prec, int B) {
             return n <= fx_i8_max_n() ? VF_FX_I8 * 100 : VF_Q15 * 100 + 1;
         case LB_Q31:
             return n <= fx_i8_max_n() ? VF_FX_I8 * 100 : 0;
-        case LB_I8_SLICED:
-            return n <= i8_fused_max_n() ? VF_I8_FUSED * 100 : VF_I8_GEMM * 100;
+        case LB_I8_SLICED: {
+            if (n <= i8_fused_max_n()) return VF_I8_FUSED * 100;
+            // the 96 x 64 tile once it gives at least half the chip's CUs a
+            // workgroup, else the 64 x 16 tile with the deeper ring (n = 729:
+            // B = 64 12.2 vs 30.9 us per step, B = 256 26.3 vs 33.6, B = 512
+            // 39.2 vs 35.3)
+            const long long big = (long long)((2 * n + 95) / 96) * ((B + 63) / 64);
+            return VF_I8_GEMM * 100 + (big < 128 ? 1 : 0);
+        }
         default:
             return 0;
     }
@@ -184,7 +194,7 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_TPLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s, graph, prm == 0 ? 1 : prm + 1);
         case VF_I8_FUSED: return chain_i8_fused(n, P, B, rho, nsteps, s);
         case VF_FX_I8: return chain_fx_i8(n, P, prec, B, rho, nsteps, s);
-        case VF_I8_GEMM: return chain_i8_gemm(n, P, B, rho, nsteps, ws, s, graph);
+        case VF_I8_GEMM: return chain_i8_gemm(n, P, B, rho, nsteps, ws, s, graph, prm == 1);
         default: return fail(LB_EINVAL, "unknown chain variant");
     }
 }
