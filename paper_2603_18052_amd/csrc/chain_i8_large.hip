@@ -150,7 +150,9 @@ __global__ void __launch_bounds__(256) prep_q_kernel(int n, int Kp, int npad, co
                 w[NPD - 1 - j] |= byte << (8 * q);
             }
         }
-        for (int a = 0; a < NPD; ++a) *reinterpret_cast<unsigned *>(Qd + a * plane + (size_t)R * Kp + k0) = w[a];
+        for (int a = 0; a < NPD; ++a)
+            *reinterpret_cast<unsigned *>(Qd + a * plane + (size_t)(k0 / KC) * (2 * n * KC) + (size_t)R * KC + k0 % KC) =
+                w[a];
     }
 }
 
@@ -194,8 +196,9 @@ __global__ void __launch_bounds__(256) init_x_kernel(int n, int Kp, int B, const
             const int sh = 8 * (NXD - 1 - bd);
             const unsigned D = ((W[0] >> sh) & 0xFFu) | (((W[1] >> sh) & 0xFFu) << 8) | (((W[2] >> sh) & 0xFFu) << 16) |
                                (((W[3] >> sh) & 0xFFu) << 24);
-            *reinterpret_cast<unsigned *>(X0 + bd * plane + (size_t)b * Kp + k0) = D;
-            if (k0 + 4 > n2) *reinterpret_cast<unsigned *>(X1 + bd * plane + (size_t)b * Kp + k0) = 0u;
+            const size_t at = bd * plane + (size_t)(k0 / KC) * ((size_t)B * KC) + (size_t)b * KC + k0 % KC;
+            *reinterpret_cast<unsigned *>(X0 + at) = D;
+            if (k0 + 4 > n2) *reinterpret_cast<unsigned *>(X1 + at) = 0u;
         }
     }
     if (tid == 0) {
@@ -276,6 +279,7 @@ __device__ __forceinline__ void i8_gemm_body(unsigned char *smem, int n, int Kp,
     // repeat earlier ones: same data to the same place).
     const signed char *src[NLW];
     int dst[NLW];
+    size_t cstride[NLW];  // bytes from one chunk of the plane to the next (chunk-major planes)
 #pragma unroll
     for (int q = 0; q < NLW; ++q) {
         int j = wave + 4 * q;
@@ -285,13 +289,15 @@ __device__ __forceinline__ void i8_gemm_body(unsigned char *smem, int n, int Kp,
             const int a = j / (TR / 16), tq = j - a * (TR / 16);
             int R = r0 + 16 * tq + row;
             R = R < n2 ? R : n2 - 1;
-            src[q] = Qd + a * qplane + (size_t)R * Kp + pc * 16;
+            src[q] = Qd + a * qplane + (size_t)R * KC + pc * 16;
+            cstride[q] = (size_t)n2 * KC;
             dst[q] = a * APL + tq * 1024;
         } else {
             const int jj = j - NLA, bd = jj / (TS / 16), tq = jj - bd * (TS / 16);
             int b = s0 + 16 * tq + row;
             b = b < B ? b : B - 1;
-            src[q] = Xc + bd * xplane + (size_t)b * Kp + pc * 16;
+            src[q] = Xc + bd * xplane + (size_t)b * KC + pc * 16;
+            cstride[q] = (size_t)B * KC;
             dst[q] = NPD * APL + bd * BPL + tq * 1024;
         }
     }
@@ -299,7 +305,7 @@ __device__ __forceinline__ void i8_gemm_body(unsigned char *smem, int n, int Kp,
     auto dma = [&](int c, int slot) {
 #pragma unroll
         for (int q = 0; q < NLW; ++q)
-            __builtin_amdgcn_global_load_lds((const void *)(src[q] + (size_t)c * KC),
+            __builtin_amdgcn_global_load_lds((const void *)(src[q] + (size_t)c * cstride[q]),
                                              (__attribute__((address_space(3))) void *)(smem + slot * STAGE + dst[q]),
                                              16, 0, 0);
     };
@@ -439,7 +445,8 @@ __device__ __forceinline__ void i8_gemm_body(unsigned char *smem, int n, int Kp,
                         const int sh = 8 * (NXD - 1 - bd);
                         const unsigned D = ((W[0] >> sh) & 0xFFu) | (((W[1] >> sh) & 0xFFu) << 8) |
                                            (((W[2] >> sh) & 0xFFu) << 16) | (((W[3] >> sh) & 0xFFu) << 24);
-                        *reinterpret_cast<unsigned *>(Xn + bd * xplane + (size_t)b * Kp + R0) = D;
+                        *reinterpret_cast<unsigned *>(Xn + bd * xplane + (size_t)(R0 / KC) * ((size_t)B * KC) +
+                                                      (size_t)b * KC + R0 % KC) = D;
                     }
                 }
             }
