@@ -31,10 +31,12 @@
 // 64-byte digit rows sit at XOR-swizzled 16-byte positions so that the
 // operand fetches run without bank conflicts.  Each XCD takes a 4 x 8 block
 // of tiles, so that 4 row blocks of Q's digits and 8 state blocks pass
-// through its L2.  Small batches use a 64-row x 16-state tile (one MFMA tile
-// per wavefront) with six 24 KB slots, five chunks in flight: more
-// workgroups (92 at n = 729, B <= 64 against 16) and a deeper ring for the
-// load latency that one chunk's 14 MFMAs per wavefront cannot cover.
+// through its L2.  Smaller batches use smaller tiles with deeper rings: 96 x
+// 32 (four 38 KB slots) and 64 x 16 (one MFMA tile per wavefront, six 24 KB
+// slots): more workgroups (92 at n = 729, B <= 64 against 16) and more
+// chunks in flight for the load latency that fewer MFMAs per chunk cannot
+// cover.  The digit planes are chunk-major, [digit][k / 64][row][64], so one
+// chunk of a tile is contiguous: a 1 KB load reads eight whole 128-byte lines.
 #include "chain.hpp"
 
 namespace lb {
@@ -68,6 +70,9 @@ struct GShape {
 // 96 x 64 (256 workgroups at n = 729, B = 1024): 47 KB slots, two chunks in
 // flight behind the one being fetched
 using BigTile = GShape<96, 64, 3, 2, 3>;
+// 96 x 32 for middle batches (256 workgroups at n = 729, B = 512): 38 KB
+// slots, three chunks in flight
+using MidTile = GShape<96, 32, 3, 1, 4>;
 // 64 x 16 for small batches (92 workgroups at n = 729, B = 64): 24 KB slots,
 // five chunks in flight
 using SmallTile = GShape<64, 16, 1, 1, 6>;
@@ -279,7 +284,7 @@ __device__ __forceinline__ void i8_gemm_body(unsigned char *smem, int n, int Kp,
     // repeat earlier ones: same data to the same place).
     const signed char *src[NLW];
     int dst[NLW];
-    size_t cstride[NLW];  // bytes from one chunk of the plane to the next (chunk-major planes)
+    bool isq[NLW];  // a load of Q's digits (else of the states'): wave-uniform
 #pragma unroll
     for (int q = 0; q < NLW; ++q) {
         int j = wave + 4 * q;
@@ -290,22 +295,24 @@ __device__ __forceinline__ void i8_gemm_body(unsigned char *smem, int n, int Kp,
             int R = r0 + 16 * tq + row;
             R = R < n2 ? R : n2 - 1;
             src[q] = Qd + a * qplane + (size_t)R * KC + pc * 16;
-            cstride[q] = (size_t)n2 * KC;
+            isq[q] = true;
             dst[q] = a * APL + tq * 1024;
         } else {
             const int jj = j - NLA, bd = jj / (TS / 16), tq = jj - bd * (TS / 16);
             int b = s0 + 16 * tq + row;
             b = b < B ? b : B - 1;
             src[q] = Xc + bd * xplane + (size_t)b * KC + pc * 16;
-            cstride[q] = (size_t)B * KC;
+            isq[q] = false;
             dst[q] = NPD * APL + bd * BPL + tq * 1024;
         }
     }
-    // loads of chunk c into ring slot `slot`
+    // loads of chunk c into ring slot `slot` (chunk-major planes: chunk c of
+    // Q's digits starts c 2n 64 bytes in, of the states' c B 64)
     auto dma = [&](int c, int slot) {
+        const size_t qo = (size_t)c * (n2 * KC), xo = (size_t)c * (B * KC);
 #pragma unroll
         for (int q = 0; q < NLW; ++q)
-            __builtin_amdgcn_global_load_lds((const void *)(src[q] + (size_t)c * cstride[q]),
+            __builtin_amdgcn_global_load_lds((const void *)(src[q] + (isq[q] ? qo : xo)),
                                              (__attribute__((address_space(3))) void *)(smem + slot * STAGE + dst[q]),
                                              16, 0, 0);
     };
@@ -477,6 +484,18 @@ __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B,
 }
 
 template <bool LAST>
+__global__ void __launch_bounds__(256) i8_gemm_mid_kernel(int n, int Kp, int B, int nrb, int nsb,
+                                                          const signed char *__restrict__ Qd,
+                                                          const int *__restrict__ eP,
+                                                          const signed char *__restrict__ Xc,
+                                                          signed char *__restrict__ Xn, int *__restrict__ Mx,
+                                                          const unsigned long long *__restrict__ gbits, int t4,
+                                                          cd *__restrict__ rho) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    i8_gemm_body<MidTile, LAST>(smem, n, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
+}
+
+template <bool LAST>
 __global__ void __launch_bounds__(256) i8_gemm_small_kernel(int n, int Kp, int B, int nrb, int nsb,
                                                             const signed char *__restrict__ Qd,
                                                             const int *__restrict__ eP,
@@ -522,7 +541,7 @@ static int run_tiles(int n, int Kp, int B, const signed char *Qd, const int *eP,
 }  // namespace i8g
 
 int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s, bool graph,
-                  bool small) {
+                  int shape) {
     using namespace i8g;
     if (nsteps == 0 || B == 0) return LB_OK;
     const int n2 = 2 * n, Kp = (n2 + 63) / 64 * 64;
@@ -539,13 +558,22 @@ int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspac
         size_t m;
         ~Release() { w->used = m; }
     } release{ws, mark};
-    const int tr = small ? SmallTile::TR : BigTile::TR;
+    const int tr = shape == 2 ? SmallTile::TR : shape == 1 ? MidTile::TR : BigTile::TR;
     LB_TRY(fill_i32_launch(reinterpret_cast<int *>(gbits), 2, s));
     prep_q_kernel<<<n2, 256, 0, s>>>(n, Kp, (n2 + tr - 1) / tr * tr, P, Qd, eP, gbits);
     LB_TRY(check_launch("i8 prep_q"));
     init_x_kernel<<<B, 256, 0, s>>>(n, Kp, B, rho, X0, X1, Mx, gbits);
     LB_TRY(check_launch("i8 init_x"));
-    if (small)
+    if (shape == 1)
+        return run_tiles<MidTile>(
+            n, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_mid_kernel<false>,
+            (const void *)i8_gemm_mid_kernel<true>, [](bool last, int grid, int lds, hipStream_t st, auto... a) {
+                if (last)
+                    i8_gemm_mid_kernel<true><<<grid, 256, lds, st>>>(a...);
+                else
+                    i8_gemm_mid_kernel<false><<<grid, 256, lds, st>>>(a...);
+            });
+    if (shape == 2)
         return run_tiles<SmallTile>(
             n, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_small_kernel<false>,
             (const void *)i8_gemm_small_kernel<true>, [](bool last, int grid, int lds, hipStream_t st, auto... a) {

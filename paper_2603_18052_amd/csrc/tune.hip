@@ -93,6 +93,7 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
         if (n <= i8_fused_max_n()) add(VF_I8_FUSED * 100);
         add2(VF_I8_GEMM * 100);
         add2(VF_I8_GEMM * 100 + 1);
+        add2(VF_I8_GEMM * 100 + 2);
     }
     return c;
 }
@@ -144,12 +145,15 @@ int chain_heuristic(int n, lb_precision prec, int B) {
             return n <= fx_i8_max_n() ? VF_FX_I8 * 100 : 0;
         case LB_I8_SLICED: {
             if (n <= i8_fused_max_n()) return VF_I8_FUSED * 100;
-            // the 96 x 64 tile once it gives at least half the chip's CUs a
-            // workgroup, else the 64 x 16 tile with the deeper ring (n = 729:
-            // B = 64 12.2 vs 30.9 us per step, B = 256 26.3 vs 33.6, B = 512
-            // 39.2 vs 35.3)
-            const long long big = (long long)((2 * n + 95) / 96) * ((B + 63) / 64);
-            return VF_I8_GEMM * 100 + (big < 128 ? 1 : 0);
+            // the largest tile that still gives every CU a workgroup: 96 x 64
+            // (variant 1500), 96 x 32 (1501: deeper ring), else 64 x 16 (1502:
+            // deeper still).  n = 729, us per step for 1500 / 1501 / 1502:
+            // B = 1024 31.5 / 39.2 / 56.0, B = 512 30.0 / 20.9 / 29.3,
+            // B = 256 30.5 / 21.4 / 20.5, B = 64 29.4 / 20.2 / 10.9
+            const long long rb96 = (2 * n + 95) / 96;
+            if (rb96 * ((B + 63) / 64) >= 240) return VF_I8_GEMM * 100;
+            if (rb96 * ((B + 31) / 32) >= 240) return VF_I8_GEMM * 100 + 1;
+            return VF_I8_GEMM * 100 + 2;
         }
         default:
             return 0;
@@ -194,7 +198,7 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_TPLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s, graph, prm == 0 ? 1 : prm + 1);
         case VF_I8_FUSED: return chain_i8_fused(n, P, B, rho, nsteps, s);
         case VF_FX_I8: return chain_fx_i8(n, P, prec, B, rho, nsteps, s);
-        case VF_I8_GEMM: return chain_i8_gemm(n, P, B, rho, nsteps, ws, s, graph, prm == 1);
+        case VF_I8_GEMM: return chain_i8_gemm(n, P, B, rho, nsteps, ws, s, graph, prm);
         default: return fail(LB_EINVAL, "unknown chain variant");
     }
 }
