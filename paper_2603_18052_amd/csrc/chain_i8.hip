@@ -146,38 +146,46 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
     for (int tl = 0; tl < NT; ++tl)
 #pragma unroll
         for (int r = 0; r < 4; ++r) pe[tl][r] = pexp[(wave + tl * WAVES) * 16 + grp * 4 + r];
+    // y: the initial state, then each step's combined levels v (the step's
+    // output is v 2^(pe + Sx - YSHIFT), formed only after the last step)
     double y[NTA][4];
-    int ey[NTA][4];  // exponents of |y|
-    // the digits of y below 2^S into buffer `to` (four consecutive k of one state: one word per plane)
-    auto slice = [&](int S, int to) {
+    // The digits of V = rint(y 2^(off + shift)) (off = the row exponent for a
+    // step's v, 0 for the initial state) into buffer `to`, four consecutive k
+    // of one state per lane: one word per plane.  Rounding to nearest even by
+    // adding 1.5 2^52 (exact for |V| < 2^51: the sum's low 32 bits are V in
+    // two's complement; a V past the 31-bit range only occurs in a state that
+    // is re-sliced after the barrier).  Returns max |y 2^(off + sh)| over the
+    // lane's values, unrounded: its exponent is the state's exponent plus the
+    // same shift, exactly.
+    auto slice = [&](bool rows, int shift, int to) {
+        double vmax = 0.0;
 #pragma unroll
         for (int tl = 0; tl < NT; ++tl) {
             unsigned W[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int V = (int)rint(ldexp(y[tl][r], FRAC_X - S));  // |V| <= 2^30
-                W[r] = (unsigned)(V + 0x00808080) ^ 0x00808080u;       // digits, least significant first
+                const double u = ldexp(y[tl][r], (rows ? pe[tl][r] : 0) + shift);
+                vmax = fmax(vmax, fabs(u));
+                const unsigned V = (unsigned)__double_as_longlong(u + 0x1.8p52);
+                W[r] = (V + 0x00808080u) ^ 0x00808080u;  // digits, least significant first
             }
+            // byte transpose: E[j] holds digit j of the four values, value r in byte r
+            const unsigned A0 = __builtin_amdgcn_perm(W[1], W[0], 0x06020400u);  // bytes 0, 2 of W0, W1
+            const unsigned A1 = __builtin_amdgcn_perm(W[1], W[0], 0x07030501u);  // bytes 1, 3
+            const unsigned C0 = __builtin_amdgcn_perm(W[3], W[2], 0x06020400u);
+            const unsigned C1 = __builtin_amdgcn_perm(W[3], W[2], 0x07030501u);
+            const unsigned E[4] = {__builtin_amdgcn_perm(C0, A0, 0x05040100u), __builtin_amdgcn_perm(C1, A1, 0x05040100u),
+                                   __builtin_amdgcn_perm(C0, A0, 0x07060302u), __builtin_amdgcn_perm(C1, A1, 0x07060302u)};
             const int k0 = (wave + tl * WAVES) * 16 + grp * 4;
 #pragma unroll
-            for (int b = 0; b < NXD; ++b) {  // b = 0 most significant
-                const int sh8 = 8 * (NXD - 1 - b);
-                const unsigned D = ((W[0] >> sh8) & 0xFFu) | (((W[1] >> sh8) & 0xFFu) << 8) |
-                                   (((W[2] >> sh8) & 0xFFu) << 16) | (((W[3] >> sh8) & 0xFFu) << 24);
-                *reinterpret_cast<unsigned *>(xdig + to * buf + (size_t)b * sh.plane + s * sh.stride + k0) = D;
-            }
+            for (int b = 0; b < NXD; ++b)  // b = 0 most significant
+                *reinterpret_cast<unsigned *>(xdig + to * buf + (size_t)b * sh.plane + s * sh.stride + k0) = E[NXD - 1 - b];
         }
+        return vmax;
     };
-    // largest exponent of this lane's state over the lane's rows (the lane
-    // groups meet in the LDS maximum)
-    auto state_exp = [&]() {
-        int m = EMPTY;
-#pragma unroll
-        for (int tl = 0; tl < NT; ++tl)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) m = max(m, ey[tl][r]);
-        return m;
-    };
+    // frexp exponent of the largest |y| of the lane's rows from slice's
+    // maximum (EMPTY for zeros); the lane groups meet in the LDS maximum
+    auto exp_from = [&](double vmax, int shift) { return vmax > 0.0 ? __builtin_amdgcn_frexp_exp(vmax) - shift : EMPTY; };
     // chunk c's state digits (one B fragment per digit plane) from buffer
     // `from`; the volatile form is for the reads issued early on purpose
     // (the compiler would otherwise sink them to their first use)
@@ -191,6 +199,7 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
     };
 
     // ---- initial state: its exact exponent, digits into buffer 0
+    int m0 = EMPTY;
 #pragma unroll
     for (int tl = 0; tl < NT; ++tl)
 #pragma unroll
@@ -201,12 +210,12 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
                 const cd v = rho[(size_t)(b0 + s) * n + (k < n ? k : k - n)];
                 y[tl][r] = k < n ? v.re : v.im;
             }
-            ey[tl][r] = exp_of(fabs(y[tl][r]));
+            m0 = max(m0, exp_of(fabs(y[tl][r])));
         }
-    if (NT > 0) atomicMax(mexp + s, state_exp());
+    if (NT > 0) atomicMax(mexp + s, m0);
     __syncthreads();
     int Sx = mexp[s] == EMPTY ? 0 : mexp[s];  // the exponent the current state's digits were sliced with
-    slice(Sx, 0);
+    (void)slice(false, FRAC_X - Sx, 0);
     __syncthreads();
     i4v x0[NXD];  // chunk 0 of the current state, fetched right after the barrier that completes it
     fetch_x(0, 0, x0, true);
@@ -239,7 +248,7 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
 #pragma unroll
                         for (int tl = 0; tl < NT; ++tl) acc[tl][a + b] = mma(pf[tl][c][a], xf[b], acc[tl][a + b]);
         }
-        // ---- combine the levels (Horner, smallest first) and scale
+        // ---- combine the levels (Horner, smallest first)
 #pragma unroll
         for (int tl = 0; tl < NT; ++tl)
 #pragma unroll
@@ -247,21 +256,24 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
                 double v = (double)acc[tl][LMAX][r];
 #pragma unroll
                 for (int L = LMAX - 1; L >= 0; --L) v = fma(v, 1.0 / 256.0, (double)acc[tl][L][r]);
-                y[tl][r] = ldexp(v, pe[tl][r] + Sx - YSHIFT);
-                ey[tl][r] = exp_of(fabs(y[tl][r]));
+                y[tl][r] = v;
             }
-        if (t + 1 == nsteps) break;  // uniform
+        if (t + 1 == nsteps) {  // uniform: the output, y = v 2^(pe + Sx - YSHIFT)
+#pragma unroll
+            for (int tl = 0; tl < NT; ++tl)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) y[tl][r] = ldexp(y[tl][r], pe[tl][r] + Sx - YSHIFT);
+            break;
+        }
         // ---- slice below the previous state's exponent M_t (speculative: the
         // state rarely crosses a power of two in one step); a state that did
-        // is flagged and re-sliced below its own exponent after the barrier
+        // (|y| >= 2^M_t, i.e. |V| >= 2^30) is flagged and re-sliced below its
+        // own exponent after the barrier
         const int Sspec = Mt == EMPTY ? 0 : Mt;
-        const int m = state_exp();
-        bool over = false;
-#pragma unroll
-        for (int tl = 0; tl < NT; ++tl)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) over |= ey[tl][r] > Sspec && ey[tl][r] != EMPTY;
-        slice(Sspec, cur ^ 1);
+        const int shs = Sx - YSHIFT + FRAC_X - Sspec;  // V = v 2^(pe + shs)
+        const double vmax = slice(true, shs, cur ^ 1);
+        const bool over = vmax >= 0x1p30;
+        const int m = exp_from(vmax, FRAC_X - Sspec);
         int *of = oflag + cur * (NS + 1);
         if (NT > 0) atomicMax(mexp + ((t + 1) & 3) * NS + s, m);
         if (over) {
@@ -276,8 +288,9 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
         if (of[NS]) {  // uniform: some state of the workgroup outgrew its exponent
             if (of[s]) {
                 const int Mn = mexp[((t + 1) & 3) * NS + s];
-                Sx = Mn == EMPTY ? 0 : Mn;
-                slice(Sx, cur ^ 1);
+                const int Snew = Mn == EMPTY ? 0 : Mn;
+                (void)slice(true, shs + Sspec - Snew, cur ^ 1);
+                Sx = Snew;
             }
             __syncthreads();
             fetch_x(cur ^ 1, 0, x0, true);
