@@ -23,14 +23,16 @@
 // in each low byte and the top digit in the top byte, so U ^ 0x80..80 is the
 // digits packed as int8, least significant first.
 //
-// Work split: 16 states per workgroup (the MFMA N), 8 wavefronts; wavefront
-// w owns 16-row tiles w and w + 8 of Q over all of k, so its outputs end each
-// step complete (no partial sums).  Per step: MFMAs (state digits read from
-// LDS as B fragments, chunk 0's right after the previous barrier), combine
-// in registers, slicing of the owned rows below the previous state's
-// exponent (four consecutive k of one state per lane: each digit plane one
-// 4-byte LDS write), per-state exponent by LDS maxima, one barrier (and a
-// second one in a step where some state outgrew its exponent).
+// Work split: 16 states per workgroup (the MFMA N), NW = 8 wavefronts (two
+// per SIMD) or 4 (one per SIMD, up to three tiles each); wavefront w owns
+// 16-row tiles w, w + NW, ... of Q over all of k, so its outputs end each
+// step complete (no partial sums).  Per step and tile: MFMAs (state digits
+// read from LDS as B fragments, chunk 0's right after the previous barrier),
+// combine in registers, slicing of the tile's rows below the previous
+// state's exponent (four consecutive k of one state per lane: each digit
+// plane one 4-byte LDS write); then the per-state exponent by LDS maxima and
+// one barrier (and a second one in a step where some state outgrew its
+// exponent: its new exponent exceeds the previous one).
 #include "chain.hpp"
 
 namespace lb {
@@ -41,7 +43,6 @@ namespace i8c {
 
 constexpr int NS = 16;      // states per workgroup (MFMA N)
 constexpr int WAVES = 8;    // wavefronts per workgroup (two per SIMD)
-constexpr int TPW = 2;      // 16-row tiles per wavefront, at most
 constexpr int KCMAX = 3;    // 64-deep k chunks, at most (2n <= 192)
 constexpr int MAXN = 96;
 constexpr int NPD = 5;      // digits of Q
@@ -72,7 +73,7 @@ __host__ __device__ inline Shape shape(int n) {
 
 inline size_t lds_bytes(int n) {
     const Shape s = shape(n);
-    return (size_t)2 * NXD * s.plane + (4 * NS + 2 * (NS + 1)) * sizeof(int) + (size_t)s.mt * 16 * sizeof(int);
+    return (size_t)2 * NXD * s.plane + 4 * NS * sizeof(int) + (size_t)s.mt * 16 * sizeof(int);
 }
 
 // exponent e with |v| < 2^e (frexp's), EMPTY for 0
@@ -92,18 +93,20 @@ __device__ inline double qval(const cd *__restrict__ P, int n, int R, int k) {
     return kim ? v.re : v.im;
 }
 
-// The chain as run by one wavefront that owns NT row tiles over KC k chunks
-// (both fixed at compile time, so the step loop has no branches).  Every
-// wavefront of the workgroup runs the same number of barriers.
-template <int NT, int KC>
+// The chain as run by one wavefront of NW that owns NT row tiles (w, w + NW,
+// ...) over KC k chunks (all fixed at compile time, so the step loop has no
+// branches).  Every wavefront of the workgroup runs the same number of
+// barriers.  A step runs tile by tile: a tile's combine and slicing have no
+// dependence on the next tile's MFMAs, so the VALU work of one overlaps the
+// matrix-core work of the next within the wavefront.
+template <int NT, int KC, int NW>
 __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__ rho, long long nsteps,
                         unsigned char *smem, int wave, int lane) {
     constexpr int NTA = NT > 0 ? NT : 1;
     const Shape sh = shape(n);
     signed char *xdig = reinterpret_cast<signed char *>(smem);                 // [2][NXD][NS][stride]
     int *mexp = reinterpret_cast<int *>(smem + (size_t)2 * NXD * sh.plane);  // [4][NS]
-    int *oflag = mexp + 4 * NS;                                               // [2][NS + 1]
-    int *pexp = oflag + 2 * (NS + 1);                                         // [mt * 16]
+    int *pexp = mexp + 4 * NS;                                                // [mt * 16]
     const int tid = threadIdx.x;
     const int b0 = blockIdx.x * NS;
     const int s = lane & 15, grp = lane >> 4;
@@ -113,7 +116,7 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
     i4v pf[NTA][KC][NPD];
 #pragma unroll
     for (int tl = 0; tl < NT; ++tl) {
-        const int R = (wave + tl * WAVES) * 16 + (lane & 15);
+        const int R = (wave + tl * NW) * 16 + (lane & 15);
         const int e = pexp[R];
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
@@ -145,7 +148,7 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
 #pragma unroll
     for (int tl = 0; tl < NT; ++tl)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) pe[tl][r] = pexp[(wave + tl * WAVES) * 16 + grp * 4 + r];
+        for (int r = 0; r < 4; ++r) pe[tl][r] = pexp[(wave + tl * NW) * 16 + grp * 4 + r];
     // y: the initial state, then each step's combined levels v (the step's
     // output is v 2^(pe + Sx - YSHIFT), formed only after the last step)
     double y[NTA][4];
@@ -154,13 +157,12 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
     // of one state per lane: one word per plane.  Rounding to nearest even by
     // adding 1.5 2^52 (exact for |V| < 2^51: the sum's low 32 bits are V in
     // two's complement; a V past the 31-bit range only occurs in a state that
-    // is re-sliced after the barrier).  Returns max |y 2^(off + sh)| over the
+    // is re-sliced after the barrier).  Returns max |y 2^(off + shift)| over the
     // lane's values, unrounded: its exponent is the state's exponent plus the
     // same shift, exactly.
-    auto slice = [&](bool rows, int shift, int to) {
+    auto slice = [&](int tl, bool rows, int shift, int to) {
         double vmax = 0.0;
-#pragma unroll
-        for (int tl = 0; tl < NT; ++tl) {
+        {
             unsigned W[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -176,7 +178,7 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
             const unsigned C1 = __builtin_amdgcn_perm(W[3], W[2], 0x07030501u);
             const unsigned E[4] = {__builtin_amdgcn_perm(C0, A0, 0x05040100u), __builtin_amdgcn_perm(C1, A1, 0x05040100u),
                                    __builtin_amdgcn_perm(C0, A0, 0x07060302u), __builtin_amdgcn_perm(C1, A1, 0x07060302u)};
-            const int k0 = (wave + tl * WAVES) * 16 + grp * 4;
+            const int k0 = (wave + tl * NW) * 16 + grp * 4;
 #pragma unroll
             for (int b = 0; b < NXD; ++b)  // b = 0 most significant
                 *reinterpret_cast<unsigned *>(xdig + to * buf + (size_t)b * sh.plane + s * sh.stride + k0) = E[NXD - 1 - b];
@@ -205,7 +207,7 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             y[tl][r] = 0.0;
-            const int k = (wave + tl * WAVES) * 16 + grp * 4 + r;
+            const int k = (wave + tl * NW) * 16 + grp * 4 + r;
             if (k < sh.n2 && b0 + s < B) {
                 const cd v = rho[(size_t)(b0 + s) * n + (k < n ? k : k - n)];
                 y[tl][r] = k < n ? v.re : v.im;
@@ -215,93 +217,85 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
     if (NT > 0) atomicMax(mexp + s, m0);
     __syncthreads();
     int Sx = mexp[s] == EMPTY ? 0 : mexp[s];  // the exponent the current state's digits were sliced with
-    (void)slice(false, FRAC_X - Sx, 0);
+#pragma unroll
+    for (int tl = 0; tl < NT; ++tl) (void)slice(tl, false, FRAC_X - Sx, 0);
     __syncthreads();
     i4v x0[NXD];  // chunk 0 of the current state, fetched right after the barrier that completes it
     fetch_x(0, 0, x0, true);
+    // M_t: frexp exponent of the current state's largest entry (EMPTY for a
+    // zero state), read together with chunk 0 after the barrier
+    int Mt = mexp[s];
 
     for (long long t = 0; t < nsteps; ++t) {
         const int cur = (int)(t & 1);
-        // exponent of the current state's largest entry (complete since the
-        // last barrier; read now so that its latency hides under the MFMAs)
-        const int Mt = *(const volatile __attribute__((address_space(3))) int *)(mexp + (t & 3) * NS + s);
-        // ---- MFMA phase
-        i4v acc[NTA][LMAX + 1];
+        // the other chunks of the current state, for every tile
+        i4v xa[KC][NXD];
 #pragma unroll
-        for (int tl = 0; tl < NT; ++tl)
+        for (int b = 0; b < NXD; ++b) xa[0][b] = x0[b];
 #pragma unroll
-            for (int L = 0; L <= LMAX; ++L) acc[tl][L] = i4v{0, 0, 0, 0};
-#pragma unroll
-        for (int c = 0; c < KC; ++c) {
-            i4v xf[NXD];
-            if (c == 0) {
-#pragma unroll
-                for (int b = 0; b < NXD; ++b) xf[b] = x0[b];
-            } else {
-                fetch_x(cur, c, xf, false);
-            }
-#pragma unroll
-            for (int a = 0; a < NPD; ++a)
-#pragma unroll
-                for (int b = 0; b < NXD; ++b)
-                    if (a + b <= LMAX)
-#pragma unroll
-                        for (int tl = 0; tl < NT; ++tl) acc[tl][a + b] = mma(pf[tl][c][a], xf[b], acc[tl][a + b]);
-        }
-        // ---- combine the levels (Horner, smallest first)
-#pragma unroll
-        for (int tl = 0; tl < NT; ++tl)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                double v = (double)acc[tl][LMAX][r];
-#pragma unroll
-                for (int L = LMAX - 1; L >= 0; --L) v = fma(v, 1.0 / 256.0, (double)acc[tl][L][r]);
-                y[tl][r] = v;
-            }
-        if (t + 1 == nsteps) {  // uniform: the output, y = v 2^(pe + Sx - YSHIFT)
-#pragma unroll
-            for (int tl = 0; tl < NT; ++tl)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) y[tl][r] = ldexp(y[tl][r], pe[tl][r] + Sx - YSHIFT);
-            break;
-        }
-        // ---- slice below the previous state's exponent M_t (speculative: the
-        // state rarely crosses a power of two in one step); a state that did
-        // (|y| >= 2^M_t, i.e. |V| >= 2^30) is flagged and re-sliced below its
-        // own exponent after the barrier
+        for (int c = 1; c < KC; ++c) fetch_x(cur, c, xa[c], false);
+        // ---- per tile: MFMAs, combine (Horner, smallest level first), and
+        // the slicing of the tile's rows below the previous state's exponent
+        // M_t (speculative: the state rarely crosses a power of two in one
+        // step); a state that did (|y| >= 2^M_t, i.e. |V| >= 2^30, so that
+        // M_t+1 > M_t) is re-sliced below its own exponent after the barrier.
+        // The last step's slicing is not read.
         const int Sspec = Mt == EMPTY ? 0 : Mt;
         const int shs = Sx - YSHIFT + FRAC_X - Sspec;  // V = v 2^(pe + shs)
-        const double vmax = slice(true, shs, cur ^ 1);
-        const bool over = vmax >= 0x1p30;
-        const int m = exp_from(vmax, FRAC_X - Sspec);
-        int *of = oflag + cur * (NS + 1);
-        if (NT > 0) atomicMax(mexp + ((t + 1) & 3) * NS + s, m);
-        if (over) {
-            atomicOr(of + s, 1);
-            atomicOr(of + NS, 1);
+        double vmax = 0.0;
+#pragma unroll
+        for (int tl = 0; tl < NT; ++tl) {
+            i4v acc[LMAX + 1];
+#pragma unroll
+            for (int L = 0; L <= LMAX; ++L) acc[L] = i4v{0, 0, 0, 0};
+#pragma unroll
+            for (int c = 0; c < KC; ++c)
+#pragma unroll
+                for (int a = 0; a < NPD; ++a)
+#pragma unroll
+                    for (int b = 0; b < NXD; ++b)
+                        if (a + b <= LMAX) acc[a + b] = mma(pf[tl][c][a], xa[c][b], acc[a + b]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double v = (double)acc[LMAX][r];
+#pragma unroll
+                for (int L = LMAX - 1; L >= 0; --L) v = fma(v, 1.0 / 256.0, (double)acc[L][r]);
+                y[tl][r] = v;
+            }
+            vmax = fmax(vmax, slice(tl, true, shs, cur ^ 1));
         }
-        if (tid < NS) mexp[((t + 2) & 3) * NS + tid] = EMPTY;     // last read two steps ago
-        if (tid <= NS) oflag[(cur ^ 1) * (NS + 1) + tid] = 0;      // last read a step ago
+        if (t + 1 == nsteps) break;  // uniform
+        if (NT > 0) atomicMax(mexp + ((t + 1) & 3) * NS + s, exp_from(vmax, FRAC_X - Sspec));
+        if (tid < NS) mexp[((t + 2) & 3) * NS + tid] = EMPTY;  // read last in step t - 2
         __syncthreads();
+        fetch_x(cur ^ 1, 0, x0, true);  // with M_t+1: one LDS round trip
+        const int Mn = *(const volatile __attribute__((address_space(3))) int *)(mexp + ((t + 1) & 3) * NS + s);
         Sx = Sspec;
-        fetch_x(cur ^ 1, 0, x0, true);  // with the flag read: one LDS round trip
-        if (of[NS]) {  // uniform: some state of the workgroup outgrew its exponent
-            if (of[s]) {
-                const int Mn = mexp[((t + 1) & 3) * NS + s];
-                const int Snew = Mn == EMPTY ? 0 : Mn;
-                (void)slice(true, shs + Sspec - Snew, cur ^ 1);
-                Sx = Snew;
+        Mt = Mn;
+        // every wavefront holds all 16 states (lane & 15), so the vote is
+        // the same in all of them: uniform over the workgroup
+        const bool over = Mn > Sspec;  // false for a zero state (EMPTY)
+        if (__builtin_amdgcn_ballot_w64(over) != 0) {
+            if (over) {
+#pragma unroll
+                for (int tl = 0; tl < NT; ++tl) (void)slice(tl, true, shs + Sspec - Mn, cur ^ 1);
+                Sx = Mn;
             }
             __syncthreads();
             fetch_x(cur ^ 1, 0, x0, true);
         }
     }
+    // the output, y = v 2^(pe + Sx - YSHIFT)
+#pragma unroll
+    for (int tl = 0; tl < NT; ++tl)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) y[tl][r] = ldexp(y[tl][r], pe[tl][r] + Sx - YSHIFT);
     // ---- write the final state
 #pragma unroll
     for (int tl = 0; tl < NT; ++tl)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int k = (wave + tl * WAVES) * 16 + grp * 4 + r;
+            const int k = (wave + tl * NW) * 16 + grp * 4 + r;
             if (k < sh.n2 && b0 + s < B) {
                 double *o = reinterpret_cast<double *>(rho + (size_t)(b0 + s) * n + (k < n ? k : k - n));
                 o[k < n ? 0 : 1] = y[tl][r];
@@ -309,18 +303,18 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
         }
 }
 
-__global__ void __launch_bounds__(WAVES * 64) i8_chain_kernel(int n, const cd *__restrict__ P, int B,
-                                                              cd *__restrict__ rho, long long nsteps) {
+template <int NW>
+__global__ void __launch_bounds__(NW * 64) i8_chain_kernel(int n, const cd *__restrict__ P, int B,
+                                                           cd *__restrict__ rho, long long nsteps) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Shape sh = shape(n);
     int *mexp = reinterpret_cast<int *>(smem + (size_t)2 * NXD * sh.plane);
-    int *oflag = mexp + 4 * NS;
-    int *pexp = oflag + 2 * (NS + 1);
+    int *pexp = mexp + 4 * NS;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     // ---- row exponents of Q (rows r and r + n share one), cleared buffers and slots
-    for (int R = tid; R < sh.mt * 16; R += WAVES * 64) {
+    for (int R = tid; R < sh.mt * 16; R += NW * 64) {
         int e = 0;
         if (R < sh.n2) {
             const int r = R < n ? R : R - n;
@@ -333,22 +327,32 @@ __global__ void __launch_bounds__(WAVES * 64) i8_chain_kernel(int n, const cd *_
         }
         pexp[R] = e;
     }
-    for (int i = tid; i < 2 * NXD * sh.plane / 4; i += WAVES * 64) reinterpret_cast<int *>(smem)[i] = 0;
+    for (int i = tid; i < 2 * NXD * sh.plane / 4; i += NW * 64) reinterpret_cast<int *>(smem)[i] = 0;
     if (tid < 4 * NS) mexp[tid] = EMPTY;
-    if (tid < 2 * (NS + 1)) oflag[tid] = 0;
     if (nsteps == 0) return;  // uniform
     __syncthreads();
-    const int ntile = (wave < sh.mt ? 1 : 0) + (wave + WAVES < sh.mt ? 1 : 0);
-    // wave-uniform dispatch to the compile-time shape
-    switch (ntile * 4 + sh.kc) {
-        case 0 * 4 + 1: i8_body<0, 1>(n, P, B, rho, nsteps, smem, wave, lane); break;
-        case 0 * 4 + 2: i8_body<0, 2>(n, P, B, rho, nsteps, smem, wave, lane); break;
-        case 0 * 4 + 3: i8_body<0, 3>(n, P, B, rho, nsteps, smem, wave, lane); break;
-        case 1 * 4 + 1: i8_body<1, 1>(n, P, B, rho, nsteps, smem, wave, lane); break;
-        case 1 * 4 + 2: i8_body<1, 2>(n, P, B, rho, nsteps, smem, wave, lane); break;
-        case 1 * 4 + 3: i8_body<1, 3>(n, P, B, rho, nsteps, smem, wave, lane); break;
-        case 2 * 4 + 2: i8_body<2, 2>(n, P, B, rho, nsteps, smem, wave, lane); break;
-        default: i8_body<2, 3>(n, P, B, rho, nsteps, smem, wave, lane); break;
+    const int ntile = wave < sh.mt ? (sh.mt - wave + NW - 1) / NW : 0;
+    // wave-uniform dispatch to the compile-time shape (only the pairs that
+    // occur for 2n <= 192: the kernel's registers are the largest body's)
+    if constexpr (NW == 8) {
+        switch (ntile * 4 + sh.kc) {
+            case 0 * 4 + 1: i8_body<0, 1, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 1: i8_body<1, 1, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 0 * 4 + 2: i8_body<0, 2, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 2: i8_body<1, 2, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 3: i8_body<1, 3, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            default: i8_body<2, 3, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+        }
+    } else {
+        static_assert(NW == 4, "four or eight wavefronts");
+        switch (ntile * 4 + sh.kc) {
+            case 0 * 4 + 1: i8_body<0, 1, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 1: i8_body<1, 1, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 2: i8_body<1, 2, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 2 * 4 + 2: i8_body<2, 2, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 2 * 4 + 3: i8_body<2, 3, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            default: i8_body<3, 3, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+        }
     }
 }
 
@@ -554,11 +558,16 @@ int chain_fx_i8(int n, const cd *P, lb_precision prec, int B, cd *rho, long long
     return check_launch("fx_i8_chain");
 }
 
-int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s) {
+int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s, int waves) {
     if (n > i8c::MAXN) return fail(LB_ESHAPE, "i8 chain: n too large for the fused kernel");
+    if (waves != 4 && waves != 8) return fail(LB_EINVAL, "i8 chain: 4 or 8 wavefronts per workgroup");
     if (nsteps == 0 || B == 0) return LB_OK;
     const size_t lds = i8c::lds_bytes(n);
-    i8c::i8_chain_kernel<<<(B + i8c::NS - 1) / i8c::NS, i8c::WAVES * 64, lds, s>>>(n, P, B, rho, nsteps);
+    const int grid = (B + i8c::NS - 1) / i8c::NS;
+    if (waves == 8)
+        i8c::i8_chain_kernel<8><<<grid, 8 * 64, lds, s>>>(n, P, B, rho, nsteps);
+    else
+        i8c::i8_chain_kernel<4><<<grid, 4 * 64, lds, s>>>(n, P, B, rho, nsteps);
     return check_launch("i8_chain");
 }
 

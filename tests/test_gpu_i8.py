@@ -125,6 +125,26 @@ def test_i8_deterministic_zero_state_and_chunked_calls(lb, P9):
     assert np.array_equal(x.cpu().numpy(), X)
 
 
+@pytest.mark.parametrize("n", [1, 9, 40, 64, 81, 96])
+def test_i8_fused_wavefront_counts_agree_bitwise(lb, n):
+    """Eight wavefronts (1300: up to two row tiles each) and four (1301: up
+    to three) run the same arithmetic on the same digits, so they give the
+    same bits; a growing propagator makes every step re-slice."""
+    g = np.random.default_rng(100 + n)
+    A = g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))
+    P = A / (1.02 * np.linalg.norm(A, 2))
+    X = g.standard_normal((37, n)) + 1j * g.standard_normal((37, n))
+    for Pm, steps in ((P, 50), (1.3 * np.eye(n, dtype=complex) + 0.01 * A, 20)):
+        out = {}
+        for v in (1300, 1301):
+            x = T(X.copy())
+            lb.propagate_variant(T(Pm), x, steps, v, "i8_sliced")
+            out[v] = x.cpu().numpy()
+        assert np.array_equal(out[1300], out[1301])
+        ref = oracle.propagate(Pm, X, steps)
+        assert oracle.rel_per_state(out[1301], ref, X) < 1e-8
+
+
 def test_i8_growing_states_take_the_exact_exponent(lb):
     """A propagator that doubles the state every step (2 I) and one that
     grows it by 1.6: every step outgrows the previous exponent, so every
