@@ -53,8 +53,10 @@ int chain_tail(int n, const cd *P, lb_precision prec, int layout, int B, cd *rho
 // kernels that the real call runs.
 int bf16_fused_max_n(lb_precision prec);
 int i8_fused_max_n();
-// waves: 8 (two wavefronts per SIMD, variant 1300) or 4 (one, variant 1301)
-int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s, int waves);
+// waves: 8 (two wavefronts per SIMD) or 4 (one); pipe: steps synchronised
+// by per-tile progress words instead of a barrier (eight wavefronts only).
+// Variants 1300 / 1301 (8 / 4, barrier), 1302 (8, pipelined)
+int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s, int waves, bool pipe);
 int fx_i8_max_n();
 size_t i8_gemm_ws_bytes(int n, int B);
 // shape: 0 = 96 x 64 tiles, 1 = 96 x 32, 2 = 64 x 16 (rows of Q x states)

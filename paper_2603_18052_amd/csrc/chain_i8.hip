@@ -16,7 +16,9 @@
 // most 5 * 2n * 128^2 < 2^31 for n <= 96 (and for any n <= 1600), so the
 // matrix cores add them exactly, over the whole k range.  The levels are
 // combined in FP64, y = 2^(e_r + S - 12) sum_L 2^-8L acc_L; y is the state
-// of the next step, re-sliced with its own exact exponent.
+// of the next step, sliced below the previous state's exponent (the top
+// digit has a bit of headroom) and re-sliced below its own exponent only
+// when it grew out of that headroom.
 //
 // Balanced digits come from the two's-complement integer in two operations:
 // U = V + 0x80..80 (128 added at every digit below the top one) holds d + 128
@@ -33,6 +35,8 @@
 // plane one 4-byte LDS write); then the per-state exponent by LDS maxima and
 // one barrier (and a second one in a step where some state outgrew its
 // exponent: its new exponent exceeds the previous one).
+#include <algorithm>
+
 #include "chain.hpp"
 
 namespace lb {
@@ -51,6 +55,9 @@ constexpr int LMAX = 4;     // highest level kept: a + b <= 4, 14 pairs
 constexpr int FRAC_P = 38;  // fraction bits of Q's row-scaled integer
 constexpr int FRAC_X = 30;  // fraction bits of the state's integer
 constexpr int EMPTY = -100000;  // exponent of an all-zero state
+constexpr double VFIT = 2147483648.0 - 16777216.0;  // |V| below this fits four balanced digits
+constexpr int SPIN_LIMIT = 1 << 16;  // polls of a pipelined wait before it gives up (a backstop)
+constexpr long long PIPE_MAX_STEPS = 1LL << 28;  // steps per pipelined launch (the counters stay in int)
 // y = 2^(e_r + S - YSHIFT) sum_L 2^-8L acc_L: the digits carry weights
 // 256^(NPD-1-a) 2^(e_r - FRAC_P) and 256^(NXD-1-b) 2^(S - FRAC_X)
 constexpr int YSHIFT = FRAC_P + FRAC_X - 8 * (NPD - 1) - 8 * (NXD - 1);
@@ -71,9 +78,35 @@ __host__ __device__ inline Shape shape(int n) {
     return s;
 }
 
-inline size_t lds_bytes(int n) {
+// LDS: the state digit buffers ([NBUF][NXD][NS][stride]: two with a
+// barrier per step, three when the step is pipelined), the exponent slots
+// ([4][NS]), the pipelined step's progress words (per 16-row tile: the
+// number of steps whose slicing of that tile is complete; the four tiles of
+// a k chunk are one 16-byte word) and re-slice round counter, and the row
+// exponents of Q ([mt * 16]).
+struct Lds {
+    signed char *xdig;
+    int *mexp, *prog, *rcnt, *pexp;
+};
+constexpr int NCNT = 4 * KCMAX + 1;
+
+__host__ __device__ inline size_t lds_ints_offset(const Shape &s, bool pipe) {
+    return (size_t)(pipe ? 3 : 2) * NXD * s.plane;
+}
+
+__device__ inline Lds lds_layout(unsigned char *smem, const Shape &s, bool pipe) {
+    Lds L;
+    L.xdig = reinterpret_cast<signed char *>(smem);
+    L.mexp = reinterpret_cast<int *>(smem + lds_ints_offset(s, pipe));
+    L.prog = L.mexp + 4 * NS;
+    L.rcnt = L.prog + 4 * KCMAX;
+    L.pexp = L.prog + NCNT;
+    return L;
+}
+
+inline size_t lds_bytes(int n, bool pipe) {
     const Shape s = shape(n);
-    return (size_t)2 * NXD * s.plane + 4 * NS * sizeof(int) + (size_t)s.mt * 16 * sizeof(int);
+    return lds_ints_offset(s, pipe) + (4 * NS + NCNT) * sizeof(int) + (size_t)s.mt * 16 * sizeof(int);
 }
 
 // exponent e with |v| < 2^e (frexp's), EMPTY for 0
@@ -99,14 +132,15 @@ __device__ inline double qval(const cd *__restrict__ P, int n, int R, int k) {
 // barriers.  A step runs tile by tile: a tile's combine and slicing have no
 // dependence on the next tile's MFMAs, so the VALU work of one overlaps the
 // matrix-core work of the next within the wavefront.
-template <int NT, int KC, int NW>
+template <int NT, int KC, int NW, bool PIPE>
 __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__ rho, long long nsteps,
                         unsigned char *smem, int wave, int lane) {
     constexpr int NTA = NT > 0 ? NT : 1;
     const Shape sh = shape(n);
-    signed char *xdig = reinterpret_cast<signed char *>(smem);                 // [2][NXD][NS][stride]
-    int *mexp = reinterpret_cast<int *>(smem + (size_t)2 * NXD * sh.plane);  // [4][NS]
-    int *pexp = mexp + 4 * NS;                                                // [mt * 16]
+    const Lds lay = lds_layout(smem, sh, PIPE);
+    signed char *xdig = lay.xdig;
+    int *mexp = lay.mexp;
+    int *pexp = lay.pexp;
     const int tid = threadIdx.x;
     const int b0 = blockIdx.x * NS;
     const int s = lane & 15, grp = lane >> 4;
@@ -185,9 +219,18 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
         }
         return vmax;
     };
-    // frexp exponent of the largest |y| of the lane's rows from slice's
-    // maximum (EMPTY for zeros); the lane groups meet in the LDS maximum
-    auto exp_from = [&](double vmax, int shift) { return vmax > 0.0 ? __builtin_amdgcn_frexp_exp(vmax) - shift : EMPTY; };
+    // The exponent slot's entry for the lane's rows from slice's maximum
+    // |V| (taken below exponent S; EMPTY for zeros); the lane groups meet in
+    // the LDS maximum.  It is the frexp exponent of the largest |y|, except
+    // that a |V| of VFIT = 2^31 - 2^24 or more (four balanced base-256
+    // digits reach 127 (256^4 - 1) / 255, about 0.996 2^31) counts one
+    // higher.  So the digits just written are good while the slot is at most
+    // S + 1 (a state may grow to nearly twice 2^S: the top digit's
+    // headroom), and a slot of S + 2 or more calls for re-slicing below it.
+    auto exp_slot = [&](double vmax, int S) {
+        if (!(vmax > 0.0)) return EMPTY;
+        return __builtin_amdgcn_frexp_exp(vmax) - FRAC_X + S + (vmax >= VFIT && vmax < 0x1p31 ? 1 : 0);
+    };
     // chunk c's state digits (one B fragment per digit plane) from buffer
     // `from`; the volatile form is for the reads issued early on purpose
     // (the compiler would otherwise sink them to their first use)
@@ -220,69 +263,245 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
 #pragma unroll
     for (int tl = 0; tl < NT; ++tl) (void)slice(tl, false, FRAC_X - Sx, 0);
     __syncthreads();
-    i4v x0[NXD];  // chunk 0 of the current state, fetched right after the barrier that completes it
-    fetch_x(0, 0, x0, true);
-    // M_t: frexp exponent of the current state's largest entry (EMPTY for a
-    // zero state), read together with chunk 0 after the barrier
-    int Mt = mexp[s];
-
-    for (long long t = 0; t < nsteps; ++t) {
-        const int cur = (int)(t & 1);
-        // the other chunks of the current state, for every tile
+    if constexpr (PIPE) {
+        // ---- pipelined steps, no barrier: a wavefront starts the MFMAs of
+        // step t on k chunk c as soon as the tiles of step t - 1 covering
+        // chunk c are sliced (each tile's progress word, written after the
+        // tile's digit and exponent writes), so one wavefront's combine and
+        // slicing overlap the others' MFMAs across the step boundary.  Wavefronts
+        // are at most one step apart (a step waits for every tile of the
+        // previous one), so three digit buffers suffice: step t reads buffer
+        // t mod 3 and writes t + 1 mod 3, whose readers (step t - 2) have
+        // all finished.  M_t is complete once all of step t - 1's tiles are;
+        // a state that outgrew the exponent it was sliced below (slot M_t
+        // two or more above it) is re-sliced by every wavefront from the kept levels, the
+        // wavefronts meet on a round counter, and the first tile's MFMAs are
+        // redone.  Waves without tiles leave after the prologue.  Eight
+        // wavefronts only (the four-wavefront body would spill).
+        if (NT == 0) return;
+        const int na = sh.mt < NW ? sh.mt : NW;  // wavefronts with tiles
+        // Ordering: one wavefront's LDS instructions execute in issue order,
+        // so a progress word written after a tile's digit and exponent
+        // writes is seen only after them, and a read issued after a progress
+        // read sees everything that value stands for.  The words are plain
+        // LDS stores (every lane stores the same value: no branch in the
+        // instruction stream) and volatile reads, behind compiler-only
+        // fences: no hardware wait in the release, none in the acquire
+        // beyond the read's own latency.
+        auto ld = [&](const int *p) { return *(const volatile __attribute__((address_space(3))) int *)(p); };
+        auto publish = [&](int *p, int v) {
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            *(volatile __attribute__((address_space(3))) int *)(p) = v;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        };
+        // the least progress of chunk c's four tiles
+        auto chunk_prog = [&](int c) {
+            const i4v v = *(const volatile __attribute__((address_space(3))) i4v *)(lay.prog + 4 * c);
+            return min(min(v[0], v[1]), min(v[2], v[3]));
+        };
+        // bounded wait: every wait ends once the wavefronts it waits for
+        // finish their part of the previous step, which waits on nothing
+        // later; the bound (a few ms) is a backstop, after which this
+        // wavefront stops waiting altogether so that the launch still ends
+        bool stalled = false;
+        auto wait_chunk = [&](int c, int need) {
+            if (stalled) return;
+            for (int it = 0;; ++it) {
+                if (__builtin_amdgcn_readfirstlane(chunk_prog(c)) >= need) return;
+                if (it == SPIN_LIMIT) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            stalled = true;
+        };
+        auto wait_rounds = [&](int need) {
+            if (stalled) return;
+            for (int it = 0;; ++it) {
+                if (__builtin_amdgcn_readfirstlane(ld(lay.rcnt)) >= need) return;
+                if (it == SPIN_LIMIT) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            stalled = true;
+        };
+        int Sspec = mexp[s] == EMPTY ? 0 : mexp[s];  // the exponent x_t+1 is sliced below (M_t)
+        int shs = 0;
+        int nredo = 0;
+        int bc = 0;  // buffer of the current state
         i4v xa[KC][NXD];
+        i4v acc[LMAX + 1];
+        auto mfma_chunk = [&](int tl, int c) {
 #pragma unroll
-        for (int b = 0; b < NXD; ++b) xa[0][b] = x0[b];
+            for (int a = 0; a < NPD; ++a)
 #pragma unroll
-        for (int c = 1; c < KC; ++c) fetch_x(cur, c, xa[c], false);
-        // ---- per tile: MFMAs, combine (Horner, smallest level first), and
-        // the slicing of the tile's rows below the previous state's exponent
-        // M_t (speculative: the state rarely crosses a power of two in one
-        // step); a state that did (|y| >= 2^M_t, i.e. |V| >= 2^30, so that
-        // M_t+1 > M_t) is re-sliced below its own exponent after the barrier.
-        // The last step's slicing is not read.
-        const int Sspec = Mt == EMPTY ? 0 : Mt;
-        const int shs = Sx - YSHIFT + FRAC_X - Sspec;  // V = v 2^(pe + shs)
-        double vmax = 0.0;
-#pragma unroll
-        for (int tl = 0; tl < NT; ++tl) {
-            i4v acc[LMAX + 1];
+                for (int b = 0; b < NXD; ++b)
+                    if (a + b <= LMAX) acc[a + b] = mma(pf[tl][c][a], xa[c][b], acc[a + b]);
+        };
+        auto zero_acc = [&]() {
 #pragma unroll
             for (int L = 0; L <= LMAX; ++L) acc[L] = i4v{0, 0, 0, 0};
+        };
+        // One step; `last` (a constant at both call sites) drops the
+        // slicing, so the tile loop has no branch between the MFMAs.
+        auto step = [&](long long t, bool last) {
+            const int ti = (int)t;
+            const int bn = bc == 2 ? 0 : bc + 1;
+            // slot t + 2 (read last in step t - 2, written from step t + 1
+            // on, after every wavefront has passed this point): cleared
+            // by every wavefront, four lanes per state, without a branch
+            *(volatile __attribute__((address_space(3))) int *)(mexp + ((t + 2) & 3) * NS + s) = EMPTY;
+            // ---- first tile.  Every chunk's counter and digits are read in
+            // one go (the digits are good if the counter read before them
+            // was); the chunks but the last hold tiles that each wavefront
+            // slices first, so they are in; the last chunk's counter is read
+            // again under chunk 0's MFMAs, with M_t behind it.
+            int have[KC];
 #pragma unroll
-            for (int c = 0; c < KC; ++c)
-#pragma unroll
-                for (int a = 0; a < NPD; ++a)
-#pragma unroll
-                    for (int b = 0; b < NXD; ++b)
-                        if (a + b <= LMAX) acc[a + b] = mma(pf[tl][c][a], xa[c][b], acc[a + b]);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                double v = (double)acc[LMAX][r];
-#pragma unroll
-                for (int L = LMAX - 1; L >= 0; --L) v = fma(v, 1.0 / 256.0, (double)acc[L][r]);
-                y[tl][r] = v;
+            for (int c = 0; c < KC; ++c) {
+                have[c] = chunk_prog(c);
+                fetch_x(bc, c, xa[c], true);
             }
-            vmax = fmax(vmax, slice(tl, true, shs, cur ^ 1));
-        }
-        if (t + 1 == nsteps) break;  // uniform
-        if (NT > 0) atomicMax(mexp + ((t + 1) & 3) * NS + s, exp_from(vmax, FRAC_X - Sspec));
-        if (tid < NS) mexp[((t + 2) & 3) * NS + tid] = EMPTY;  // read last in step t - 2
-        __syncthreads();
-        fetch_x(cur ^ 1, 0, x0, true);  // with M_t+1: one LDS round trip
-        const int Mn = *(const volatile __attribute__((address_space(3))) int *)(mexp + ((t + 1) & 3) * NS + s);
-        Sx = Sspec;
-        Mt = Mn;
-        // every wavefront holds all 16 states (lane & 15), so the vote is
-        // the same in all of them: uniform over the workgroup
-        const bool over = Mn > Sspec;  // false for a zero state (EMPTY)
-        if (__builtin_amdgcn_ballot_w64(over) != 0) {
-            if (over) {
+            bool early_in = true;
 #pragma unroll
-                for (int tl = 0; tl < NT; ++tl) (void)slice(tl, true, shs + Sspec - Mn, cur ^ 1);
-                Sx = Mn;
+            for (int c = 0; c + 1 < KC; ++c) early_in = early_in && have[c] >= ti;
+            if (!__builtin_amdgcn_readfirstlane(early_in)) {
+#pragma unroll
+                for (int c = 0; c + 1 < KC; ++c) {
+                    wait_chunk(c, ti);
+                    fetch_x(bc, c, xa[c], true);
+                }
             }
+            zero_acc();
+            int last_have = have[KC - 1];
+            int Mt = 0;
+            if (KC > 1) {
+                mfma_chunk(0, 0);
+                last_have = chunk_prog(KC - 1);
+                fetch_x(bc, KC - 1, xa[KC - 1], true);
+                Mt = ld(mexp + (t & 3) * NS + s);
+#pragma unroll
+                for (int c = 1; c + 1 < KC; ++c) mfma_chunk(0, c);
+            } else {
+                Mt = ld(mexp + (t & 3) * NS + s);
+            }
+            if (__builtin_amdgcn_readfirstlane(last_have) < ti) {
+                wait_chunk(KC - 1, ti);
+                fetch_x(bc, KC - 1, xa[KC - 1], true);
+                Mt = ld(mexp + (t & 3) * NS + s);
+            }
+            if (KC == 1) zero_acc();
+            mfma_chunk(0, KC - 1);
+            if (t > 0) {
+                // every tile of step t - 1 is in: M_t is complete
+                const bool over = Mt > Sspec + 1;  // false for a zero state (EMPTY)
+                if (__builtin_amdgcn_ballot_w64(over) != 0) {  // the same vote in every wavefront
+                    if (over) {
+#pragma unroll
+                        for (int tl = 0; tl < NT; ++tl) (void)slice(tl, true, shs + Sspec - Mt, bc);
+                    }
+                    ++nredo;
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    if (lane == 0)
+                        __hip_atomic_fetch_add((__attribute__((address_space(3))) int *)(lay.rcnt), 1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    wait_rounds(na * nredo);
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) fetch_x(bc, c, xa[c], true);
+                    zero_acc();
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) mfma_chunk(0, c);
+                }
+                Sx = over ? Mt : Sspec;
+                Sspec = Mt == EMPTY ? 0 : Mt;
+            }
+            shs = Sx - YSHIFT + FRAC_X - Sspec;  // V = v 2^(pe + shs)
+#pragma unroll
+            for (int tl = 0; tl < NT; ++tl) {
+                if (tl > 0) {
+                    zero_acc();
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) mfma_chunk(tl, c);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double v = (double)acc[LMAX][r];
+#pragma unroll
+                    for (int L = LMAX - 1; L >= 0; --L) v = fma(v, 1.0 / 256.0, (double)acc[L][r]);
+                    y[tl][r] = v;
+                }
+                if (!last) {
+                    const double vmax = slice(tl, true, shs, bn);
+                    atomicMax(mexp + ((t + 1) & 3) * NS + s, exp_slot(vmax, Sspec));
+                    publish(lay.prog + wave + tl * NW, ti + 1);
+                }
+            }
+            bc = bn;
+        };
+        for (long long t = 0; t + 1 < nsteps; ++t) step(t, false);
+        step(nsteps - 1, true);
+    } else {
+        i4v x0[NXD];  // chunk 0 of the current state, fetched right after the barrier that completes it
+        fetch_x(0, 0, x0, true);
+        // M_t: frexp exponent of the current state's largest entry (EMPTY for a
+        // zero state), read together with chunk 0 after the barrier
+        int Mt = mexp[s];
+
+        for (long long t = 0; t < nsteps; ++t) {
+            const int cur = (int)(t & 1);
+            // the other chunks of the current state, for every tile
+            i4v xa[KC][NXD];
+#pragma unroll
+            for (int b = 0; b < NXD; ++b) xa[0][b] = x0[b];
+#pragma unroll
+            for (int c = 1; c < KC; ++c) fetch_x(cur, c, xa[c], false);
+            // ---- per tile: MFMAs, combine (Horner, smallest level first), and
+            // the slicing of the tile's rows below the previous state's exponent
+            // M_t (speculative: a state that grows past the top digit's
+            // headroom in one step, slot M_t+1 > M_t + 1, is re-sliced below
+            // the slot after the barrier).  The last step's slicing is not read.
+            const int Sspec = Mt == EMPTY ? 0 : Mt;
+            const int shs = Sx - YSHIFT + FRAC_X - Sspec;  // V = v 2^(pe + shs)
+            double vmax = 0.0;
+#pragma unroll
+            for (int tl = 0; tl < NT; ++tl) {
+                i4v acc[LMAX + 1];
+#pragma unroll
+                for (int L = 0; L <= LMAX; ++L) acc[L] = i4v{0, 0, 0, 0};
+#pragma unroll
+                for (int c = 0; c < KC; ++c)
+#pragma unroll
+                    for (int a = 0; a < NPD; ++a)
+#pragma unroll
+                        for (int b = 0; b < NXD; ++b)
+                            if (a + b <= LMAX) acc[a + b] = mma(pf[tl][c][a], xa[c][b], acc[a + b]);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double v = (double)acc[LMAX][r];
+#pragma unroll
+                    for (int L = LMAX - 1; L >= 0; --L) v = fma(v, 1.0 / 256.0, (double)acc[L][r]);
+                    y[tl][r] = v;
+                }
+                vmax = fmax(vmax, slice(tl, true, shs, cur ^ 1));
+            }
+            if (t + 1 == nsteps) break;  // uniform
+            if (NT > 0) atomicMax(mexp + ((t + 1) & 3) * NS + s, exp_slot(vmax, Sspec));
+            if (tid < NS) *(volatile __attribute__((address_space(3))) int *)(mexp + ((t + 2) & 3) * NS + tid) = EMPTY;  // read last in step t - 2
             __syncthreads();
-            fetch_x(cur ^ 1, 0, x0, true);
+            fetch_x(cur ^ 1, 0, x0, true);  // with M_t+1: one LDS round trip
+            const int Mn = *(const volatile __attribute__((address_space(3))) int *)(mexp + ((t + 1) & 3) * NS + s);
+            Sx = Sspec;
+            Mt = Mn;
+            // every wavefront holds all 16 states (lane & 15), so the vote is
+            // the same in all of them: uniform over the workgroup
+            const bool over = Mn > Sspec + 1;  // false for a zero state (EMPTY)
+            if (__builtin_amdgcn_ballot_w64(over) != 0) {
+                if (over) {
+#pragma unroll
+                    for (int tl = 0; tl < NT; ++tl) (void)slice(tl, true, shs + Sspec - Mn, cur ^ 1);
+                    Sx = Mn;
+                }
+                __syncthreads();
+                fetch_x(cur ^ 1, 0, x0, true);
+            }
         }
     }
     // the output, y = v 2^(pe + Sx - YSHIFT)
@@ -303,13 +522,14 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
         }
 }
 
-template <int NW>
+template <int NW, bool PIPE>
 __global__ void __launch_bounds__(NW * 64) i8_chain_kernel(int n, const cd *__restrict__ P, int B,
                                                            cd *__restrict__ rho, long long nsteps) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Shape sh = shape(n);
-    int *mexp = reinterpret_cast<int *>(smem + (size_t)2 * NXD * sh.plane);
-    int *pexp = mexp + 4 * NS;
+    const Lds lay = lds_layout(smem, sh, PIPE);
+    int *mexp = lay.mexp;
+    int *pexp = lay.pexp;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
@@ -327,8 +547,10 @@ __global__ void __launch_bounds__(NW * 64) i8_chain_kernel(int n, const cd *__re
         }
         pexp[R] = e;
     }
-    for (int i = tid; i < 2 * NXD * sh.plane / 4; i += NW * 64) reinterpret_cast<int *>(smem)[i] = 0;
+    for (int i = tid; i < (int)(lds_ints_offset(sh, PIPE) / 4); i += NW * 64) reinterpret_cast<int *>(smem)[i] = 0;
     if (tid < 4 * NS) mexp[tid] = EMPTY;
+    // progress: 0 for every tile that exists, never waited on past the last
+    if (tid < NCNT) lay.prog[tid] = tid < 4 * KCMAX && tid >= sh.mt ? 0x7fffffff : 0;
     if (nsteps == 0) return;  // uniform
     __syncthreads();
     const int ntile = wave < sh.mt ? (sh.mt - wave + NW - 1) / NW : 0;
@@ -336,22 +558,22 @@ __global__ void __launch_bounds__(NW * 64) i8_chain_kernel(int n, const cd *__re
     // occur for 2n <= 192: the kernel's registers are the largest body's)
     if constexpr (NW == 8) {
         switch (ntile * 4 + sh.kc) {
-            case 0 * 4 + 1: i8_body<0, 1, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 1 * 4 + 1: i8_body<1, 1, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 0 * 4 + 2: i8_body<0, 2, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 1 * 4 + 2: i8_body<1, 2, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 1 * 4 + 3: i8_body<1, 3, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            default: i8_body<2, 3, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 0 * 4 + 1: i8_body<0, 1, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 1: i8_body<1, 1, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 0 * 4 + 2: i8_body<0, 2, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 2: i8_body<1, 2, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 3: i8_body<1, 3, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            default: i8_body<2, 3, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
         }
     } else {
         static_assert(NW == 4, "four or eight wavefronts");
         switch (ntile * 4 + sh.kc) {
-            case 0 * 4 + 1: i8_body<0, 1, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 1 * 4 + 1: i8_body<1, 1, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 1 * 4 + 2: i8_body<1, 2, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 2 * 4 + 2: i8_body<2, 2, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 2 * 4 + 3: i8_body<2, 3, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            default: i8_body<3, 3, NW>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 0 * 4 + 1: i8_body<0, 1, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 1: i8_body<1, 1, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 2: i8_body<1, 2, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 2 * 4 + 2: i8_body<2, 2, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 2 * 4 + 3: i8_body<2, 3, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            default: i8_body<3, 3, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
         }
     }
 }
@@ -558,16 +780,26 @@ int chain_fx_i8(int n, const cd *P, lb_precision prec, int B, cd *rho, long long
     return check_launch("fx_i8_chain");
 }
 
-int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s, int waves) {
-    if (n > i8c::MAXN) return fail(LB_ESHAPE, "i8 chain: n too large for the fused kernel");
+int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s, int waves, bool pipe) {
+    using namespace i8c;
+    if (n > MAXN) return fail(LB_ESHAPE, "i8 chain: n too large for the fused kernel");
     if (waves != 4 && waves != 8) return fail(LB_EINVAL, "i8 chain: 4 or 8 wavefronts per workgroup");
+    if (pipe && waves != 8) return fail(LB_EINVAL, "i8 chain: the pipelined step runs eight wavefronts");
     if (nsteps == 0 || B == 0) return LB_OK;
-    const size_t lds = i8c::lds_bytes(n);
-    const int grid = (B + i8c::NS - 1) / i8c::NS;
-    if (waves == 8)
-        i8c::i8_chain_kernel<8><<<grid, 8 * 64, lds, s>>>(n, P, B, rho, nsteps);
-    else
-        i8c::i8_chain_kernel<4><<<grid, 4 * 64, lds, s>>>(n, P, B, rho, nsteps);
+    const size_t lds = lds_bytes(n, pipe);
+    const int grid = (B + NS - 1) / NS;
+    // a pipelined launch counts tiles in int: longer chains run as several
+    // launches (each starts from its state's exact exponent)
+    for (long long done = 0; done < nsteps;) {
+        const long long k = pipe ? std::min(nsteps - done, PIPE_MAX_STEPS) : nsteps - done;
+        if (pipe)
+            i8_chain_kernel<8, true><<<grid, 8 * 64, lds, s>>>(n, P, B, rho, k);
+        else if (waves == 8)
+            i8_chain_kernel<8, false><<<grid, 8 * 64, lds, s>>>(n, P, B, rho, k);
+        else
+            i8_chain_kernel<4, false><<<grid, 4 * 64, lds, s>>>(n, P, B, rho, k);
+        done += k;
+    }
     return check_launch("i8_chain");
 }
 

@@ -93,6 +93,7 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
         if (n <= i8_fused_max_n()) {
             add(VF_I8_FUSED * 100);
             add(VF_I8_FUSED * 100 + 1);
+            add(VF_I8_FUSED * 100 + 2);
         }
         add2(VF_I8_GEMM * 100);
         add2(VF_I8_GEMM * 100 + 1);
@@ -199,7 +200,7 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_TAIL: return chain_tail(n, P, prec, prm, B, rho, nsteps, s);
         case VF_TGEMM: return chain_tgemm(n, P, prec, prm, B, rho, nsteps, ws, s, graph);
         case VF_TPLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s, graph, prm == 0 ? 1 : prm + 1);
-        case VF_I8_FUSED: return chain_i8_fused(n, P, B, rho, nsteps, s, prm == 1 ? 4 : 8);
+        case VF_I8_FUSED: return chain_i8_fused(n, P, B, rho, nsteps, s, prm == 1 ? 4 : 8, prm == 2);
         case VF_FX_I8: return chain_fx_i8(n, P, prec, B, rho, nsteps, s);
         case VF_I8_GEMM: return chain_i8_gemm(n, P, B, rho, nsteps, ws, s, graph, prm);
         default: return fail(LB_EINVAL, "unknown chain variant");

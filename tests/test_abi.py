@@ -121,7 +121,7 @@ def test_chain_variant_lists_and_rule(L):
     assert lb.chain_variant(729, "q15", 16) == 901
     # Q1.31 and the INT8-digit chain: one fused INT8-core kernel each, n <= 96
     assert lb.chain_variants(9, "q31", 1) == [1400] and lb.chain_variants(97, "q31", 1) == []
-    assert lb.chain_variants(81, "i8_sliced", 4096) == [1300, 1301, 1500, 1550, 1501, 1551, 1502, 1552]
+    assert lb.chain_variants(81, "i8_sliced", 4096) == [1300, 1301, 1302, 1500, 1550, 1501, 1551, 1502, 1552]
     assert lb.chain_variant(96, "i8_sliced", 1) == 1300
     # past the fused limit: the largest GEMM tile that gives 240 or more
     # workgroups -- 96 x 64 (1500), 96 x 32 (1501), else 64 x 16 (1502)

@@ -105,8 +105,8 @@ def test_i8_deterministic_zero_state_and_chunked_calls(lb, P9):
     """Bitwise repeatable; a zero state stays zero; 1000 steps as ten calls
     of 100 stay within the bound of one call (a call slices its first state
     below that state's own exponent; inside a call the next state is sliced
-    below the previous state's exponent unless it outgrew it, so the bits
-    may differ at call boundaries)."""
+    below the previous state's exponent unless it outgrew the top digit's
+    headroom, so the bits may differ at call boundaries)."""
     X = states(9, 20, 5)
     X[7] = 0.0
     a = run(lb, P9, X, 1000)
@@ -126,31 +126,38 @@ def test_i8_deterministic_zero_state_and_chunked_calls(lb, P9):
 
 
 @pytest.mark.parametrize("n", [1, 9, 40, 64, 81, 96])
-def test_i8_fused_wavefront_counts_agree_bitwise(lb, n):
+def test_i8_fused_forms_agree_bitwise(lb, n):
     """Eight wavefronts (1300: up to two row tiles each) and four (1301: up
-    to three) run the same arithmetic on the same digits, so they give the
-    same bits; a growing propagator makes every step re-slice."""
+    to three) with a barrier per step, and eight with pipelined steps (1302:
+    per-tile progress words, three digit buffers) run the same arithmetic on
+    the same digits, so they give the same bits; a growing propagator makes
+    every step re-slice (the pipelined form redoes the step's first tile)."""
     g = np.random.default_rng(100 + n)
     A = g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))
     P = A / (1.02 * np.linalg.norm(A, 2))
     X = g.standard_normal((37, n)) + 1j * g.standard_normal((37, n))
-    for Pm, steps in ((P, 50), (1.3 * np.eye(n, dtype=complex) + 0.01 * A, 20)):
+    for Pm, steps in ((P, 50), (3.0 * np.eye(n, dtype=complex) + 0.01 * A, 20)):
         out = {}
-        for v in (1300, 1301):
+        for v in (1300, 1301, 1302):
             x = T(X.copy())
             lb.propagate_variant(T(Pm), x, steps, v, "i8_sliced")
             out[v] = x.cpu().numpy()
-        assert np.array_equal(out[1300], out[1301])
+        for v in (1301, 1302):
+            assert np.array_equal(out[1300], out[v]), v
         ref = oracle.propagate(Pm, X, steps)
-        assert oracle.rel_per_state(out[1301], ref, X) < 1e-8
+        assert oracle.rel_per_state(out[1302], ref, X) < 1e-8
 
 
 def test_i8_growing_states_take_the_exact_exponent(lb):
-    """A propagator that doubles the state every step (2 I) and one that
-    grows it by 1.6: every step outgrows the previous exponent, so every
-    step takes the re-slicing path; the results stay within the
-    representation's bound."""
+    """A propagator that quadruples the state every step (4 I): every step
+    grows past the top digit's headroom, so every step takes the re-slicing
+    path; one that doubles it (2 I) and one that grows it by 1.6 cross a
+    power of two every step or two and stay within the headroom (31-bit
+    digits until the next step's exponent catches up).  The results stay
+    within the representation's bound."""
     X = states(9, 5, 9)
+    got = run(lb, 4.0 * np.eye(81, dtype=complex), X, 12)
+    assert oracle.rel_per_state(got, X * 4.0 ** 12) < 1e-8
     got = run(lb, 2.0 * np.eye(81, dtype=complex), X, 20)
     assert oracle.rel_per_state(got, X * 2.0 ** 20) < 1e-8
     P = 1.6 * np.eye(81, dtype=complex)
