@@ -144,7 +144,9 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
     const int tid = threadIdx.x;
     const int b0 = blockIdx.x * NS;
     const int s = lane & 15, grp = lane >> 4;
-    const size_t buf = (size_t)NXD * sh.plane;
+    // the digit layout's strides as constants (the shape's, for 2n in this
+    // k chunk count): LDS offsets become instruction immediates
+    constexpr int STRIDE = KC * 64 + 32, PLANE = NS * STRIDE, BUF = NXD * PLANE;
 
     // ---- Q digit fragments of this wavefront's tiles
     i4v pf[NTA][KC][NPD];
@@ -215,7 +217,7 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
             const int k0 = (wave + tl * NW) * 16 + grp * 4;
 #pragma unroll
             for (int b = 0; b < NXD; ++b)  // b = 0 most significant
-                *reinterpret_cast<unsigned *>(xdig + to * buf + (size_t)b * sh.plane + s * sh.stride + k0) = E[NXD - 1 - b];
+                *reinterpret_cast<unsigned *>(xdig + to * BUF + b * PLANE + s * STRIDE + k0) = E[NXD - 1 - b];
         }
         return vmax;
     };
@@ -237,7 +239,7 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
     auto fetch_x = [&](int from, int c, i4v (&xf)[NXD], bool early) {
 #pragma unroll
         for (int b = 0; b < NXD; ++b) {
-            const i4v *q = reinterpret_cast<const i4v *>(xdig + from * buf + (size_t)b * sh.plane + s * sh.stride +
+            const i4v *q = reinterpret_cast<const i4v *>(xdig + from * BUF + b * PLANE + s * STRIDE +
                                                          c * 64 + grp * 16);
             xf[b] = early ? *(const volatile __attribute__((address_space(3))) i4v *)(q) : *q;
         }
