@@ -188,11 +188,13 @@ def kernel_of(variant, prec):
     if fam in (4, 7):
         return base + ("<HILO>" if prec == "bf16_hilo" else "<SLICED>")
     if fam == 13:
-        return "i8_chain_kernel"
+        return {0: "i8_chain_kernel<8, false>", 1: "i8_chain_kernel<4, false>",
+                2: "i8_chain_kernel<8, true>"}.get(variant % 100, "i8_chain_kernel")
     if fam == 14:
         return "fx_chain_kernel"
     if fam == 15:
-        return "i8_gemm_step_kernel<false>"
+        return {0: "i8_gemm_step_kernel<false>", 1: "i8_gemm_mid_kernel<false>",
+                2: "i8_gemm_small_kernel<false>"}.get(variant % 50, "i8_gemm_step_kernel<false>")
     if fam == 11:
         t = "double" if prec == "c128" else "float"
         if variant % 50 in (1, 2):

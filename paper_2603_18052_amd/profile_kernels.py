@@ -23,13 +23,16 @@ def main():
     ap.add_argument("--precision", default="c128")
     ap.add_argument("--d", type=int, default=9, choices=(9, 27))
     ap.add_argument("--nsteps", type=int, default=None, help="default 10^4 (d = 9), 40 (d = 27)")
-    ap.add_argument("--batch", type=int, default=None, help="default 4096 (d = 9), 1024 (d = 27)")
+    ap.add_argument("--batch", default=None,
+                    help="default 4096 (d = 9), 1024 (d = 27); a comma list runs each batch in turn")
+    ap.add_argument("--variant", default=None,
+                    help="chain variant(s) to launch (comma list, each in turn); default: the library's choice")
     ap.add_argument("--grape", action="store_true", help="one GRAPE gradient (M = 200) instead of a chain")
     a = ap.parse_args()
     if a.nsteps is None:
         a.nsteps = 10_000 if a.d == 9 else 40
-    if a.batch is None:
-        a.batch = 4096 if a.d == 9 else 1024
+    batches = [4096 if a.d == 9 else 1024] if a.batch is None else [int(b) for b in str(a.batch).split(",")]
+    variants = [None] if a.variant is None else [int(v) for v in a.variant.split(",")]
     import torch
     from paper_2603_18052_amd import lindblad as lb
     from paper_2603_18052_amd import workloads as W
@@ -50,17 +53,22 @@ def main():
         torch.cuda.synchronize()
         print("profile_kernels: done grape", a.d, F, flush=True)
         return
-    cfg = (W.config2 if a.d == 9 else W.config3)(B=a.batch, nsteps=a.nsteps)
+    cfg = (W.config2 if a.d == 9 else W.config3)(B=max(batches), nsteps=a.nsteps)
     H, Lk = torch.from_numpy(cfg["H"]).to(dev), torch.from_numpy(cfg["Lk"]).to(dev)
     P = lb.propagator(lb.liouvillian(H, Lk), cfg["dt"])
-    X = torch.from_numpy(cfg["rho0"].reshape(a.batch, -1)).to(dev)
-    torch.cuda.synchronize()
-    if a.precision == "baseline":
-        lb.propagate_baseline(P, X, a.nsteps)
-    else:
-        lb.propagate(P, X, a.nsteps, a.precision)
-    torch.cuda.synchronize()
-    print("profile_kernels: done", a.precision, flush=True)
+    X0 = torch.from_numpy(cfg["rho0"].reshape(max(batches), -1)).to(dev)
+    for B in batches:
+        for v in variants:
+            X = X0[:B].clone()
+            torch.cuda.synchronize()
+            if a.precision == "baseline":
+                lb.propagate_baseline(P, X, a.nsteps)
+            elif v is None:
+                lb.propagate(P, X, a.nsteps, a.precision)
+            else:
+                lb.propagate_variant(P, X, a.nsteps, v, a.precision)
+            torch.cuda.synchronize()
+            print("profile_kernels: done", a.precision, "B", B, "variant", v, flush=True)
 
 
 if __name__ == "__main__":
