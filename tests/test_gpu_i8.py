@@ -168,6 +168,21 @@ def test_i8_growing_states_take_the_exact_exponent(lb):
     assert oracle.rel_per_state(got, ref) < 30 * 2.0 ** -30
 
 
+def test_i8_config2_fused_forms_full_size_bitwise(lb, P9):
+    """The bench's configuration (4096 Wishart states, 1e4 steps) in each
+    fused form the tuner may pick: the barrier forms (1300, 1301) and the
+    pipelined one (1302) give the same bits at full size."""
+    c = W.config2()
+    X = c["rho0"].reshape(-1, 81)
+    out = {}
+    for v in (1300, 1301, 1302):
+        x = T(X.copy())
+        lb.propagate_variant(T(P9), x, c["nsteps"], v, "i8_sliced")
+        out[v] = x.cpu().numpy()
+    assert np.array_equal(out[1300], out[1301])
+    assert np.array_equal(out[1300], out[1302])
+
+
 def test_i8_config2_full_size_sampled(lb, P9):
     """The configuration the bench times: 4096 Wishart states, 1e4 steps, on
     the oracle's P; sampled states against the oracle's chain."""
@@ -203,7 +218,7 @@ def test_i8_gemm_d27_config3(lb, P27):
     assert rep["trace_err"].max() < 1e-6 and rep["lambda_min"].min() > -1e-6
 
 
-@pytest.mark.parametrize("B", [1, 1024])
+@pytest.mark.parametrize("B", [1, 512, 1024])
 def test_i8_gemm_d27_full_batch_sampled(lb, P27, B):
     c = W.config3(B=B)
     X = c["rho0"].reshape(-1, 729)
