@@ -268,13 +268,28 @@ int lindblad_expmv_params(double a, int *s, int *m);
  *             per workgroup, w = 4 or 8 wavefronts (LB_C128 / LB_C64)
  *   1101      the same tile with k chunks loaded straight into an LDS ring a few
  *             chunks ahead (four wavefronts)
+ *   1102      1101 with the k range split over workgroups (FP64 partial sums
+ *             added in a fixed order)
  *   1200      one LDS-tiled BF16 plane-GEMM launch per step, 64 states x 48
  *             outputs per workgroup, direct global-to-LDS loads (BF16 precisions)
  *   1201      the same tile with each wavefront's state planes staged per 64-k
  *             pair and a ring of propagator chunks loaded 2-3 chunks ahead
  *   1202      1201 with the k range split over workgroups when the batch has
  *             fewer than 256 tiles (partial sums added in a fixed order)
- * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901, 1100 + w, 1101, 1200 .. 1202) replays its steps
+ *   1300      LB_I8_SLICED, whole chain in one launch (n <= 96), eight
+ *             wavefronts of up to two 16-row tiles, a barrier per step
+ *   1301      the same with four wavefronts of up to three tiles
+ *   1302      eight wavefronts, steps synchronised by per-tile progress words
+ *             in LDS instead of a barrier (three state digit buffers)
+ *   1400      LB_Q15 / LB_Q31, whole chain in one launch on the INT8 matrix
+ *             cores (n <= 96)
+ *   1500      LB_I8_SLICED, one INT8-digit GEMM launch per step, 96 rows x 64
+ *             states per workgroup, three LDS ring slots
+ *   1501      96 rows x 32 states, four ring slots
+ *   1502      64 rows x 16 states, six ring slots
+ * 1300 .. 1302 give the same bits, and so do 1500 .. 1502.
+ * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901, 1100 + w,
+ * 1101, 1102, 1200 .. 1202, 1500 .. 1502) replays its steps
  * from a HIP graph captured once per call (32 steps, replayed over all but
  * the last step).  Variants of one shape differ only in summation order. */
 
