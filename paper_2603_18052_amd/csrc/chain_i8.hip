@@ -8,9 +8,10 @@
 //   P:  row r of Q is scaled by 2^-e_r (|Q[r, k]| < 2^e_r) and rounded to the
 //       integer V = rint(Q 2^(38 - e_r)), |V| <= 2^38, written as five
 //       balanced base-256 digits p_a in [-128, 127] (a = 0 most significant).
-//   x:  each state is scaled by 2^-S (|x_k| < 2^S for its largest |Re|,
-//       |Im|), rounded to the 31-bit integer V = rint(x 2^(30 - S)) and
-//       written as four balanced digits q_b.
+//   x:  each state is scaled by 2^-S, S the exponent of its largest |Re|,
+//       |Im| (exact for the initial state, the previous state's after
+//       that), rounded to the integer V = rint(x 2^(30 - S)) and written as
+//       four balanced digits q_b.
 // All digit pairs of one level L = a + b <= 4 (14 pairs) accumulate in ONE
 // int32 MFMA accumulator: each product is an integer and a level sum is at
 // most 5 * 2n * 128^2 < 2^31 for n <= 96 (and for any n <= 1600), so the
@@ -33,8 +34,9 @@
 // combine in registers, slicing of the tile's rows below the previous
 // state's exponent (four consecutive k of one state per lane: each digit
 // plane one 4-byte LDS write); then the per-state exponent by LDS maxima and
-// one barrier (and a second one in a step where some state outgrew its
-// exponent: its new exponent exceeds the previous one).
+// one barrier (and a second one in a step where some state outgrew the top
+// digit's headroom).  The pipelined form replaces the barrier by per-tile
+// progress words in LDS (see the body).
 #include <algorithm>
 
 #include "chain.hpp"
