@@ -194,7 +194,8 @@ def kernel_of(variant, prec):
         return "fx_chain_kernel"
     if fam == 15:
         return {0: "i8_gemm_step_kernel<false>", 1: "i8_gemm_mid_kernel<false>",
-                2: "i8_gemm_small_kernel<false>"}.get(variant % 50, "i8_gemm_step_kernel<false>")
+                2: "i8_gemm_small_kernel<false>", 3: "i8_gemm_pair_kernel<false>"}.get(variant % 50,
+                                                                                    "i8_gemm_step_kernel<false>")
     if fam == 11:
         t = "double" if prec == "c128" else "float"
         if variant % 50 in (1, 2):

@@ -287,9 +287,10 @@ int lindblad_expmv_params(double a, int *s, int *m);
  *             states per workgroup, three LDS ring slots
  *   1501      96 rows x 32 states, four ring slots
  *   1502      64 rows x 16 states, six ring slots
- * 1300 .. 1302 give the same bits, and so do 1500 .. 1502.
+ *   1503      96 rows x 32 states, two ring slots, two workgroups per CU
+ * 1300 .. 1302 give the same bits, and so do 1500 .. 1503.
  * Adding 50 to a per-step family (100, 500 + w, 600, 700, 901, 1100 + w,
- * 1101, 1102, 1200 .. 1202, 1500 .. 1502) replays its steps
+ * 1101, 1102, 1200 .. 1202, 1500 .. 1503) replays its steps
  * from a HIP graph captured once per call (32 steps, replayed over all but
  * the last step).  Variants of one shape differ only in summation order. */
 

@@ -59,7 +59,8 @@ int i8_fused_max_n();
 int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s, int waves, bool pipe);
 int fx_i8_max_n();
 size_t i8_gemm_ws_bytes(int n, int B);
-// shape: 0 = 96 x 64 tiles, 1 = 96 x 32, 2 = 64 x 16 (rows of Q x states)
+// shape: 0 = 96 x 64 tiles, 1 = 96 x 32, 2 = 64 x 16 (rows of Q x states), 3 = 96 x 32
+// with two LDS slots, two workgroups per CU
 int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s, bool graph,
                   int shape);
 int chain_fx_i8(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);

@@ -76,6 +76,9 @@ using MidTile = GShape<96, 32, 3, 1, 4>;
 // 64 x 16 for small batches (92 workgroups at n = 729, B = 64): 24 KB slots,
 // five chunks in flight
 using SmallTile = GShape<64, 16, 1, 1, 6>;
+// 96 x 32 with two slots (76 KB): two workgroups share a CU, so one
+// workgroup's MFMAs cover the other's loads
+using PairTile = GShape<96, 32, 3, 1, 2>;
 
 // Workgroup barrier of the ring: wait until at most N of this wavefront's
 // vector loads are outstanding and its LDS accesses are done (s_waitcnt,
@@ -507,6 +510,18 @@ __global__ void __launch_bounds__(256) i8_gemm_small_kernel(int n, int Kp, int B
     i8_gemm_body<SmallTile, LAST>(smem, n, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
 }
 
+template <bool LAST>
+__global__ void __launch_bounds__(256, 2) i8_gemm_pair_kernel(int n, int Kp, int B, int nrb, int nsb,
+                                                              const signed char *__restrict__ Qd,
+                                                              const int *__restrict__ eP,
+                                                              const signed char *__restrict__ Xc,
+                                                              signed char *__restrict__ Xn, int *__restrict__ Mx,
+                                                              const unsigned long long *__restrict__ gbits, int t4,
+                                                              cd *__restrict__ rho) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    i8_gemm_body<PairTile, LAST>(smem, n, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
+}
+
 static int grid1(long long work) {
     long long g = (work + 255) / 256;
     if (g > 65536) g = 65536;
@@ -558,7 +573,7 @@ int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspac
         size_t m;
         ~Release() { w->used = m; }
     } release{ws, mark};
-    const int tr = shape == 2 ? SmallTile::TR : shape == 1 ? MidTile::TR : BigTile::TR;
+    const int tr = shape == 2 ? SmallTile::TR : shape == 1 ? MidTile::TR : shape == 3 ? PairTile::TR : BigTile::TR;
     LB_TRY(fill_i32_launch(reinterpret_cast<int *>(gbits), 2, s));
     prep_q_kernel<<<n2, 256, 0, s>>>(n, Kp, (n2 + tr - 1) / tr * tr, P, Qd, eP, gbits);
     LB_TRY(check_launch("i8 prep_q"));
@@ -572,6 +587,15 @@ int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspac
                     i8_gemm_mid_kernel<true><<<grid, 256, lds, st>>>(a...);
                 else
                     i8_gemm_mid_kernel<false><<<grid, 256, lds, st>>>(a...);
+            });
+    if (shape == 3)
+        return run_tiles<PairTile>(
+            n, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_pair_kernel<false>,
+            (const void *)i8_gemm_pair_kernel<true>, [](bool last, int grid, int lds, hipStream_t st, auto... a) {
+                if (last)
+                    i8_gemm_pair_kernel<true><<<grid, 256, lds, st>>>(a...);
+                else
+                    i8_gemm_pair_kernel<false><<<grid, 256, lds, st>>>(a...);
             });
     if (shape == 2)
         return run_tiles<SmallTile>(

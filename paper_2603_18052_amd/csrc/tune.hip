@@ -98,6 +98,7 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
         add2(VF_I8_GEMM * 100);
         add2(VF_I8_GEMM * 100 + 1);
         add2(VF_I8_GEMM * 100 + 2);
+        add2(VF_I8_GEMM * 100 + 3);
     }
     return c;
 }
@@ -149,14 +150,15 @@ int chain_heuristic(int n, lb_precision prec, int B) {
             return n <= fx_i8_max_n() ? VF_FX_I8 * 100 : 0;
         case LB_I8_SLICED: {
             if (n <= i8_fused_max_n()) return VF_I8_FUSED * 100;
-            // the largest tile that still gives every CU a workgroup: 96 x 64
-            // (variant 1500), 96 x 32 (1501: deeper ring), else 64 x 16 (1502:
-            // deeper still).  n = 729, us per step for 1500 / 1501 / 1502:
-            // B = 1024 31.5 / 39.2 / 56.0, B = 512 30.0 / 20.9 / 29.3,
-            // B = 256 30.5 / 21.4 / 20.5, B = 64 29.4 / 20.2 / 10.9
+            // 96 x 32 tiles with two LDS slots and two workgroups per CU
+            // (variant 1503) while they give 240 or more workgroups, else
+            // 64 x 16 with six slots (1502).  n = 729, us per step for 1500
+            // (96 x 64) / 1501 (96 x 32, four slots) / 1502 / 1503, one box:
+            // B = 1024 33.2 / 39.2 / 54.5 / 31.4, B = 768 30.4 / 38.7 / 45.7
+            // / 29.1, B = 512 29.9 / 21.2 / 28.5 / 20.3, B = 256 30.4 / 21.1
+            // / 19.9 / 20.6, B = 128 29.8 / 20.4 / 11.4 / 19.8
             const long long rb96 = (2 * n + 95) / 96;
-            if (rb96 * ((B + 63) / 64) >= 240) return VF_I8_GEMM * 100;
-            if (rb96 * ((B + 31) / 32) >= 240) return VF_I8_GEMM * 100 + 1;
+            if (rb96 * ((B + 31) / 32) >= 240) return VF_I8_GEMM * 100 + 3;
             return VF_I8_GEMM * 100 + 2;
         }
         default:

@@ -121,13 +121,12 @@ def test_chain_variant_lists_and_rule(L):
     assert lb.chain_variant(729, "q15", 16) == 901
     # Q1.31 and the INT8-digit chain: one fused INT8-core kernel each, n <= 96
     assert lb.chain_variants(9, "q31", 1) == [1400] and lb.chain_variants(97, "q31", 1) == []
-    assert lb.chain_variants(81, "i8_sliced", 4096) == [1300, 1301, 1302, 1500, 1550, 1501, 1551, 1502, 1552]
+    assert lb.chain_variants(81, "i8_sliced", 4096) == [1300, 1301, 1302, 1500, 1550, 1501, 1551, 1502, 1552, 1503, 1553]
     assert lb.chain_variant(96, "i8_sliced", 1) == 1300
-    # past the fused limit: the largest GEMM tile that gives 240 or more
-    # workgroups -- 96 x 64 (1500), 96 x 32 (1501), else 64 x 16 (1502)
-    assert lb.chain_variants(729, "i8_sliced", 64) == [1500, 1550, 1501, 1551, 1502, 1552]
-    assert lb.chain_variant(729, "i8_sliced", 1024) == 1500 and lb.chain_variant(729, "i8_sliced", 960) == 1500
-    assert lb.chain_variant(729, "i8_sliced", 512) == 1501 and lb.chain_variant(729, "i8_sliced", 480) == 1501
+    # past the fused limit: 96 x 32 tiles two to a CU (1503) while they give
+    # 240 or more workgroups, else 64 x 16 (1502)
+    assert lb.chain_variants(729, "i8_sliced", 64) == [1500, 1550, 1501, 1551, 1502, 1552, 1503, 1553]
+    assert lb.chain_variant(729, "i8_sliced", 1024) == 1503 and lb.chain_variant(729, "i8_sliced", 480) == 1503
     assert lb.chain_variant(729, "i8_sliced", 448) == 1502 and lb.chain_variant(729, "i8_sliced", 1) == 1502
     # tuning table: set, read back, reject a variant the shape lacks, clear
     lb.tune_set(81, "c128", 4096, 502)

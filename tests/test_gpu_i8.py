@@ -232,12 +232,12 @@ def test_i8_gemm_d27_full_batch_sampled(lb, P27, B):
     assert td.max() < 1e-6
 
 
-@pytest.mark.parametrize("variant", [1500, 1501, 1502])
+@pytest.mark.parametrize("variant", [1500, 1501, 1502, 1503])
 @pytest.mark.parametrize("n", [97, 100, 130, 260])
 def test_i8_gemm_shapes(lb, n, variant):
-    """The three tile shapes (1500: 96 rows x 64 states, 1501: 96 x 32 with
-    four ring slots, 1502: 64 x 16 with six), 64-deep k chunks and ragged
-    state tiles (B = 19) on
+    """The four tile shapes (1500: 96 rows x 64 states, 1501: 96 x 32 with
+    four ring slots, 1502: 64 x 16 with six, 1503: 96 x 32 with two, two
+    workgroups per CU), 64-deep k chunks and ragged state tiles (B = 19) on
     random contractions (relative to each state's initial norm: the states
     shrink by orders of magnitude); n = 260 has k padding that no row block
     covers."""
@@ -254,16 +254,16 @@ def test_i8_gemm_shapes(lb, n, variant):
 @pytest.mark.parametrize("B", [1, 19, 64, 129])
 def test_i8_gemm_tile_shapes_agree_bitwise(lb, P27, B):
     """The digit sums are exact integers and the epilogue's arithmetic does
-    not depend on the tiling, so the three tile shapes (and the small
+    not depend on the tiling, so the four tile shapes (and the small
     shape's graph-replayed twin, 1552) give the same bits; the result meets
     the 1e-6 bound against the oracle."""
     X = states(27, B, 31 + B)
     out = {}
-    for v in (1500, 1501, 1502, 1552):
+    for v in (1500, 1501, 1502, 1503, 1552):
         x = T(X.copy())
         lb.propagate_variant(T(P27), x, 60, v, "i8_sliced")
         out[v] = x.cpu().numpy()
-    for v in (1501, 1502, 1552):
+    for v in (1501, 1502, 1503, 1552):
         assert np.array_equal(out[1500], out[v]), v
     idx = np.unique(np.array([0, B // 2, B - 1]))
     ref = oracle.propagate(P27, X[idx], 60)
