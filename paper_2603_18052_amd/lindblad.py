@@ -82,8 +82,8 @@ GRAPH_VARIANT = 50  # added to a per-step family: steps replayed from a captured
 def variant_name(v: int) -> str:
     fam, prm = divmod(int(v), 100)
     name = VARIANT_FAMILIES.get(fam, f"family{fam}")
-    graph = fam in (1, 5, 6, 7, 9, 11, 12) and prm >= GRAPH_VARIANT
-    prm = prm % GRAPH_VARIANT if fam in (1, 5, 6, 7, 9, 11, 12) else prm
+    graph = fam in (1, 5, 6, 7, 9, 11, 12, 15) and prm >= GRAPH_VARIANT
+    prm = prm % GRAPH_VARIANT if fam in (1, 5, 6, 7, 9, 11, 12, 15) else prm
     if fam == 3:
         name = f"{name}(k{prm})"
     elif fam == 5:
@@ -96,6 +96,10 @@ def variant_name(v: int) -> str:
         name = f"{name}({'ring' if prm == 1 else 'ring+splitk'})"
     elif fam == 10 and prm in (1, 2, 3):
         name = f"{name}({('w16', 'tiles', 'tiles+presum')[prm - 1]})"
+    elif fam == 13 and prm in (0, 1, 2):
+        name = f"{name}({('w8', 'w4', 'w8+progress')[prm]})"
+    elif fam == 15 and prm in (0, 1, 2, 3):
+        name = f"{name}({('96x64', '96x32', '64x16', '96x32 pair')[prm]})"
     return name + "+graph" if graph else name
 
 

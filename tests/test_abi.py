@@ -112,6 +112,8 @@ def test_chain_variant_lists_and_rule(L):
         "fused_tail(tiles)", "fused_tail(tiles+presum)", "gemm_tiled(w4)", "gemm_tiled(w8)+graph"]
     assert [lb.variant_name(x) for x in (1200, 1201, 1251)] == [
         "planes_tiled", "planes_tiled(ring)", "planes_tiled(ring)+graph"]
+    assert [lb.variant_name(x) for x in (1300, 1301, 1302, 1500, 1553)] == [
+        "i8_fused(w8)", "i8_fused(w4)", "i8_fused(w8+progress)", "i8_gemm(96x64)", "i8_gemm(96x32 pair)+graph"]
     assert lb.chain_variant(729, "bf16_hilo", 16) == 1202
     assert lb.chain_variant(729, "bf16_sliced", 1024) == 1202  # ring plane GEMM (256 tiles: no k split)
     # fixed point: one wavefront per state for n <= 16, else the per-row matvec (and its graph twin)
