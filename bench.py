@@ -44,11 +44,12 @@ PATH_UNIT = {  # arithmetic unit and peak of each chain variant
     "bf16_hilo": ("mfma", "bf16_tflops", "bf16"),
     "bf16_sliced": ("mfma", "bf16_tflops", "bf16"),
     "i8_sliced": ("mfma", "int8_tops", "i8"),
+    "i8_herm": ("mfma", "int8_tops", "i8"),
 }
 # Executed real MFMA products per complex multiply-add, relative to one
 # complex product (4 real): hi+lo makes 3 products of each real part pair,
 # the sliced scheme one per slice pair kept.
-TARGET_TD = {"c128": 1e-12, "c64": 1e-6, "bf16_hilo": 1e-6, "bf16_sliced": 1e-6, "i8_sliced": 1e-6}
+TARGET_TD = {"c128": 1e-12, "c64": 1e-6, "bf16_hilo": 1e-6, "bf16_sliced": 1e-6, "i8_sliced": 1e-6, "i8_herm": 1e-6}
 
 
 def paper_step_cost(d):
@@ -136,7 +137,7 @@ def parse():
     ap.add_argument("--nsteps", type=int, default=10_000, help="chain steps per bench step")
     ap.add_argument("--precision", default="auto",
                     help="chain variant timed as `value` (auto = fastest meeting its error target)")
-    ap.add_argument("--paths", default="c128,c64,bf16_hilo,bf16_sliced,i8_sliced,baseline",
+    ap.add_argument("--paths", default="c128,c64,bf16_hilo,bf16_sliced,i8_sliced,i8_herm,baseline",
                     help="variants measured for the `paths` report")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -188,8 +189,9 @@ def kernel_of(variant, prec):
     if fam in (4, 7):
         return base + ("<HILO>" if prec == "bf16_hilo" else "<SLICED>")
     if fam == 13:
-        return {0: "i8_chain_kernel<8, false>", 1: "i8_chain_kernel<4, false>",
-                2: "i8_chain_kernel<8, true>"}.get(variant % 100, "i8_chain_kernel")
+        h = "true" if prec == "i8_herm" else "false"
+        return {0: f"i8_chain_kernel<8, false, {h}>", 1: f"i8_chain_kernel<4, false, {h}>",
+                2: f"i8_chain_kernel<8, true, {h}>"}.get(variant % 100, "i8_chain_kernel")
     if fam == 14:
         return "fx_chain_kernel"
     if fam == 15:
@@ -417,11 +419,15 @@ def expmv_section(lb, W, torch, dev, ws):
 # Executed MFMA products per complex multiply-add of the chain, relative
 # to the algorithmic one: hi+lo makes three BF16 products per complex
 # product, the sliced scheme one per digit pair kept (5 x 4 digits, levels
-# <= 4: 14 pairs).
-EXECUTED_FACTOR = {"c128": 1.0, "c64": 1.0, "bf16_hilo": 3.0, "bf16_sliced": 14.0, "i8_sliced": 14.0}
+# <= 4: 14 pairs).  The Hermitian-coordinate form runs its 14 pairs on the
+# n x n real step: n^2 real products per state-step, a quarter of the 4 n^2
+# of a complex product, so 14 / 4.
+EXECUTED_FACTOR = {"c128": 1.0, "c64": 1.0, "bf16_hilo": 3.0, "bf16_sliced": 14.0, "i8_sliced": 14.0,
+                   "i8_herm": 3.5}
 # Bytes of the propagator one step reads in each format (n x n complex):
 # FP64 16, FP32 8, BF16 hi+lo 2 parts x 2 x 2, sliced 5 digits x 2 x 2.
-P_BYTES_PER_ENTRY = {"c128": 16, "c64": 8, "bf16_hilo": 8, "bf16_sliced": 20, "i8_sliced": 20, "baseline": 16}
+P_BYTES_PER_ENTRY = {"c128": 16, "c64": 8, "bf16_hilo": 8, "bf16_sliced": 20, "i8_sliced": 20, "i8_herm": 5,
+                     "baseline": 16}
 
 
 def _kernel_times():
@@ -702,7 +708,7 @@ def main():
     Pn = P.cpu().numpy()
 
     # ---- choose the headline variant
-    order = ["i8_sliced", "bf16_sliced", "c64", "bf16_hilo", "c128"]
+    order = ["i8_herm", "i8_sliced", "bf16_sliced", "c64", "bf16_hilo", "c128"]
     prec = args.precision
     # ---- errors: the reduced precisions against the FP64 chain on the same
     #      sampled states; the FP64 chain against the oracle (CPU leg below)

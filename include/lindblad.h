@@ -79,9 +79,18 @@ typedef enum {
                            fused launch for n <= 96; beyond, one INT8 GEMM launch per step, the
                            next state sliced below 2^(M + g) with M the exponent of the previous
                            state's largest entry and 2^g the largest row sum of the embedding */,
-    LB_Q31 = 6          /* the paper's fixed-point step at 31 fraction bits (its Q1.31 drift
+    LB_Q31 = 6,         /* the paper's fixed-point step at 31 fraction bits (its Q1.31 drift
                            curve): LB_Q15's rules with 32-bit codes, sums exact in 128 bits,
                            floor(acc / 2^31) saturated.  Bitwise reproducible; n <= 96 */
+    LB_I8_HERM = 7      /* LB_I8_SLICED's digits and rules on the real coordinates of a
+                           HERMITIAN state (a density matrix; n = d^2, n <= 192).  The Lindblad
+                           generator (Eq. 1), exp(L dt) and its Pade approximant map rho^dagger
+                           to (P rho)^dagger, so the step is one real n x n matrix R on the
+                           coordinates h_(i,j) = Re rho_ij (i <= j), Im rho_ij (i > j):
+                           half the rows and half the k of the 2n x 2n embedding.  The call
+                           reads only those entries of each state (the Hermitian matrix they
+                           define) and writes a Hermitian result.  No kernel (LB_ENOTSUP)
+                           unless n is a perfect square within the limit */
 } lb_precision;
 
 typedef struct lb_workspace lb_workspace;
@@ -277,7 +286,8 @@ int lindblad_expmv_params(double a, int *s, int *m);
  *   1202      1201 with the k range split over workgroups when the batch has
  *             fewer than 256 tiles (partial sums added in a fixed order)
  *   1300      LB_I8_SLICED, whole chain in one launch (n <= 96), eight
- *             wavefronts of up to two 16-row tiles, a barrier per step
+ *             wavefronts of up to two 16-row tiles, a barrier per step;
+ *             1300 .. 1302 are also LB_I8_HERM's variants (n = d^2 <= 192)
  *   1301      the same with four wavefronts of up to three tiles
  *   1302      eight wavefronts, steps synchronised by per-tile progress words
  *             in LDS instead of a barrier (three state digit buffers)

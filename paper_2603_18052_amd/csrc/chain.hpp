@@ -23,7 +23,7 @@ enum ChainFamily : int {
     VF_TAIL = 10,       // fused chain, rows 0..79 on MFMA, the rest on the VALU (n = 81); param = layout 0..3
     VF_TGEMM = 11,      // one LDS-tiled MFMA GEMM launch per step (64 states x 48 outputs); param = wavefronts 4 / 8, 1 = ring, 2 = ring + split k
     VF_TPLANES = 12,    // one LDS-tiled BF16 plane-GEMM launch per step (64 states x 48 outputs); param 1: ring-pipelined, 2: ring + split k
-    VF_I8_FUSED = 13,   // whole INT8-digit chain in one launch (LB_I8_SLICED, n <= i8_fused_max_n)
+    VF_I8_FUSED = 13,   // whole INT8-digit chain in one launch (LB_I8_SLICED, n <= i8_fused_max_n; LB_I8_HERM)
     VF_FX_I8 = 14,      // fixed-point chain (LB_Q15, LB_Q31) on the INT8 matrix cores, one launch (n <= 96)
     VF_I8_GEMM = 15,    // one LDS-tiled INT8-digit GEMM launch per step (LB_I8_SLICED, any n)
 };
@@ -55,8 +55,13 @@ int bf16_fused_max_n(lb_precision prec);
 int i8_fused_max_n();
 // waves: 8 (two wavefronts per SIMD) or 4 (one); pipe: steps synchronised
 // by per-tile progress words instead of a barrier (eight wavefronts only).
-// Variants 1300 / 1301 (8 / 4, barrier), 1302 (8, pipelined)
-int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s, int waves, bool pipe);
+// Variants 1300 / 1301 (8 / 4, barrier), 1302 (8, pipelined).  herm: the
+// Hermitian-coordinate form (LB_I8_HERM: n = d^2, the n x n real step on
+// the d^2 real coordinates of a Hermitian state), n <= i8_herm_fused_max_n
+int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s, int waves, bool pipe,
+                   bool herm);
+int i8_herm_fused_max_n();
+bool i8_herm_shape_ok(int n);  // n = d^2
 int fx_i8_max_n();
 size_t i8_gemm_ws_bytes(int n, int B);
 // shape: 0 = 96 x 64 tiles, 1 = 96 x 32, 2 = 64 x 16 (rows of Q x states), 3 = 96 x 32

@@ -37,6 +37,19 @@
 // one barrier (and a second one in a step where some state outgrew the top
 // digit's headroom).  The pipelined form replaces the barrier by per-tile
 // progress words in LDS (see the body).
+//
+// Hermitian states.  The generator of Eq. (1) maps rho^dagger to
+// (L rho)^dagger, and so do P = exp(L dt) and its Pade-13 approximant (real
+// coefficients), so a density matrix stays Hermitian and is fixed by n = d^2
+// real coordinates, h_p = Re rho_p for p = (i, j) with i <= j and
+// h_p = Im rho_p for i > j.  On them the step is one real n x n matrix
+// (the HERM form, half the rows and half the k of the real embedding):
+//     with z = P[r, q]                     for q = (a, a),
+//          z = P[r, q] + P[r, q']          for q = (a, b), a < b,
+//          z = i (P[r, q] - P[r, q'])      for q = (a, b), a > b,
+// (q' = (b, a)), R[r, q] = Re z if row r = (i, j) has i <= j, else Im z.
+// The final state is written back as the Hermitian matrix of its
+// coordinates: rho_ij = h_(i,j) - i h_(j,i) for i < j, conjugate below.
 #include <algorithm>
 
 #include "chain.hpp"
@@ -66,13 +79,15 @@ constexpr int YSHIFT = FRAC_P + FRAC_X - 8 * (NPD - 1) - 8 * (NXD - 1);
 
 __device__ inline i4v mma(i4v a, i4v b, i4v c) { return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0); }
 
+// n2: the real dimension of the step (2n for the embedding, n for the
+// Hermitian coordinates)
 struct Shape {
     int n2, mt, kc, stride, plane;
 };
 
-__host__ __device__ inline Shape shape(int n) {
+__host__ __device__ inline Shape shape(int n, bool herm = false) {
     Shape s;
-    s.n2 = 2 * n;
+    s.n2 = herm ? n : 2 * n;
     s.mt = (s.n2 + 15) / 16;
     s.kc = (s.n2 + 63) / 64;
     s.stride = s.kc * 64 + 32;  // 32 bytes off a multiple of 64: conflict-free 16-byte fragment reads
@@ -106,8 +121,8 @@ __device__ inline Lds lds_layout(unsigned char *smem, const Shape &s, bool pipe)
     return L;
 }
 
-inline size_t lds_bytes(int n, bool pipe) {
-    const Shape s = shape(n);
+inline size_t lds_bytes(int n, bool pipe, bool herm) {
+    const Shape s = shape(n, herm);
     return lds_ints_offset(s, pipe) + (4 * NS + NCNT) * sizeof(int) + (size_t)s.mt * 16 * sizeof(int);
 }
 
@@ -128,17 +143,44 @@ __device__ inline double qval(const cd *__restrict__ P, int n, int R, int k) {
     return kim ? v.re : v.im;
 }
 
+// R[r][q] of the Hermitian-coordinate step (n = d^2), from P.  Row r =
+// (i, j) takes the real parts of z for i <= j and the imaginary parts
+// otherwise, so one component of u = P[r, q] and v = P[r, q'] serves:
+// z = u (a = b), u + v (a < b), i (u - v) (a > b); the imaginary parts
+// for an upper row with a > b or a lower row with a <= b, else the real.
+// Index pairs by multiplying with dm = ceil(2^16 / d): (x dm) >> 16 is
+// x / d for every x < 2^16 / d (here x < 192, d <= 13).
+__device__ inline double hval(const cd *__restrict__ P, int n, int d, int dm, int r, int q) {
+    // branch-free: indices clamped into the matrix, padding selected to 0
+    const int rc = min(r, n - 1), qc = min(q, n - 1);
+    const int a = (qc * dm) >> 16, b = qc - a * d, i = (rc * dm) >> 16, j = rc - i * d;
+    const bool upper = i <= j, below = a > b;
+    const double *Pr = reinterpret_cast<const double *>(P + (size_t)rc * n);
+    const int c = upper == below ? 1 : 0;
+    const double x = Pr[2 * qc + c], y = Pr[2 * (b * d + a) + c];  // y = x on the diagonal
+    const double z = a == b ? x : !below ? x + y : upper ? y - x : x - y;
+    return r < n && q < n ? z : 0.0;
+}
+
+// isqrt of a perfect square n = d^2 (d <= 13 here)
+__device__ inline int dim_of(int n) {
+    int d = 1;
+    while ((d + 1) * (d + 1) <= n) ++d;
+    return d;
+}
+
 // The chain as run by one wavefront of NW that owns NT row tiles (w, w + NW,
 // ...) over KC k chunks (all fixed at compile time, so the step loop has no
 // branches).  Every wavefront of the workgroup runs the same number of
 // barriers.  A step runs tile by tile: a tile's combine and slicing have no
 // dependence on the next tile's MFMAs, so the VALU work of one overlaps the
 // matrix-core work of the next within the wavefront.
-template <int NT, int KC, int NW, bool PIPE>
-__device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__ rho, long long nsteps,
+template <int NT, int KC, int NW, bool PIPE, bool HERM>
+__device__ __forceinline__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__ rho, long long nsteps,
                         unsigned char *smem, int wave, int lane) {
     constexpr int NTA = NT > 0 ? NT : 1;
-    const Shape sh = shape(n);
+    const Shape sh = shape(n, HERM);
+    const int dd = HERM ? dim_of(n) : 1, dm = (65536 + dd - 1) / dd;
     const Lds lay = lds_layout(smem, sh, PIPE);
     signed char *xdig = lay.xdig;
     int *mexp = lay.mexp;
@@ -163,17 +205,42 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
             for (int a = 0; a < NPD; ++a)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) w[a][i] = 0u;
+            if constexpr (HERM) {
+                // the Hermitian form gathers two entries per value: one value
+                // at a time (a rolled loop), else the hoisted gathers of all
+                // sixteen outgrow the registers the step loop leaves
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int k = c * 64 + grp * 16 + q;
-                const long long V = (long long)rint(ldexp(qval(P, n, R, k), FRAC_P - e));
-                const unsigned long long U = (unsigned long long)(V + 0x80808080LL);
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    unsigned wq[NPD] = {0u, 0u, 0u, 0u, 0u};
+#pragma unroll 1
+                    for (int q = 0; q < 4; ++q) {
+                        const int k = c * 64 + grp * 16 + 4 * q4 + q;
+                        const long long V = (long long)rint(ldexp(hval(P, n, dd, dm, R, k), FRAC_P - e));
+                        const unsigned long long U = (unsigned long long)(V + 0x80808080LL);
 #pragma unroll
-                for (int j = 0; j < NPD; ++j) {  // j = 0 least significant
-                    const unsigned byte = j < NPD - 1
-                                              ? (unsigned)((U >> (8 * j)) & 0xFFu) ^ 0x80u
-                                              : (unsigned)((unsigned long long)((long long)U >> 32) & 0xFFu);
-                    w[NPD - 1 - j][q >> 2] |= byte << (8 * (q & 3));
+                        for (int j = 0; j < NPD; ++j) {  // j = 0 least significant
+                            const unsigned byte = j < NPD - 1
+                                                      ? (unsigned)((U >> (8 * j)) & 0xFFu) ^ 0x80u
+                                                      : (unsigned)((unsigned long long)((long long)U >> 32) & 0xFFu);
+                            wq[NPD - 1 - j] |= byte << (8 * q);
+                        }
+                    }
+#pragma unroll
+                    for (int a = 0; a < NPD; ++a) w[a][q4] = wq[a];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int k = c * 64 + grp * 16 + q;
+                    const long long V = (long long)rint(ldexp(qval(P, n, R, k), FRAC_P - e));
+                    const unsigned long long U = (unsigned long long)(V + 0x80808080LL);
+#pragma unroll
+                    for (int j = 0; j < NPD; ++j) {  // j = 0 least significant
+                        const unsigned byte = j < NPD - 1
+                                                  ? (unsigned)((U >> (8 * j)) & 0xFFu) ^ 0x80u
+                                                  : (unsigned)((unsigned long long)((long long)U >> 32) & 0xFFu);
+                        w[NPD - 1 - j][q >> 2] |= byte << (8 * (q & 3));
+                    }
                 }
             }
 #pragma unroll
@@ -256,8 +323,14 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
             y[tl][r] = 0.0;
             const int k = (wave + tl * NW) * 16 + grp * 4 + r;
             if (k < sh.n2 && b0 + s < B) {
-                const cd v = rho[(size_t)(b0 + s) * n + (k < n ? k : k - n)];
-                y[tl][r] = k < n ? v.re : v.im;
+                if constexpr (HERM) {
+                    const cd v = rho[(size_t)(b0 + s) * n + k];
+                    const int i = (k * dm) >> 16, j = k - i * dd;
+                    y[tl][r] = i <= j ? v.re : v.im;
+                } else {
+                    const cd v = rho[(size_t)(b0 + s) * n + (k < n ? k : k - n)];
+                    y[tl][r] = k < n ? v.re : v.im;
+                }
             }
             m0 = max(m0, exp_of(fabs(y[tl][r])));
         }
@@ -520,32 +593,52 @@ __device__ void i8_body(int n, const cd *__restrict__ P, int B, cd *__restrict__
         for (int r = 0; r < 4; ++r) {
             const int k = (wave + tl * NW) * 16 + grp * 4 + r;
             if (k < sh.n2 && b0 + s < B) {
-                double *o = reinterpret_cast<double *>(rho + (size_t)(b0 + s) * n + (k < n ? k : k - n));
-                o[k < n ? 0 : 1] = y[tl][r];
+                if constexpr (HERM) {
+                    // h_(i,j) is Re rho_ij = Re rho_ji (i <= j), or Im rho_ij = -Im rho_ji (i > j)
+                    const int i = (k * dm) >> 16, j = k - i * dd;
+                    double *o = reinterpret_cast<double *>(rho + (size_t)(b0 + s) * n);
+                    if (i == j) {
+                        o[2 * k] = y[tl][r];
+                        o[2 * k + 1] = 0.0;
+                    } else {
+                        const int kt = j * dd + i, c = i < j ? 0 : 1;
+                        o[2 * k + c] = y[tl][r];
+                        o[2 * kt + c] = c ? -y[tl][r] : y[tl][r];
+                    }
+                } else {
+                    double *o = reinterpret_cast<double *>(rho + (size_t)(b0 + s) * n + (k < n ? k : k - n));
+                    o[k < n ? 0 : 1] = y[tl][r];
+                }
             }
         }
 }
 
-template <int NW, bool PIPE>
+template <int NW, bool PIPE, bool HERM>
 __global__ void __launch_bounds__(NW * 64) i8_chain_kernel(int n, const cd *__restrict__ P, int B,
                                                            cd *__restrict__ rho, long long nsteps) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const Shape sh = shape(n);
+    const Shape sh = shape(n, HERM);
     const Lds lay = lds_layout(smem, sh, PIPE);
     int *mexp = lay.mexp;
     int *pexp = lay.pexp;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-    // ---- row exponents of Q (rows r and r + n share one), cleared buffers and slots
+    // ---- row exponents of Q (rows r and r + n share one; the Hermitian
+    // form's rows each their own), cleared buffers and slots
+    const int dd = HERM ? dim_of(n) : 1, dm = (65536 + dd - 1) / dd;
     for (int R = tid; R < sh.mt * 16; R += NW * 64) {
         int e = 0;
         if (R < sh.n2) {
-            const int r = R < n ? R : R - n;
             double m = 0.0;
-            for (int k = 0; k < n; ++k) {
-                const cd v = P[(size_t)r * n + k];
-                m = fmax(m, fmax(fabs(v.re), fabs(v.im)));
+            if constexpr (HERM) {
+                for (int k = 0; k < n; ++k) m = fmax(m, fabs(hval(P, n, dd, dm, R, k)));
+            } else {
+                const int r = R < n ? R : R - n;
+                for (int k = 0; k < n; ++k) {
+                    const cd v = P[(size_t)r * n + k];
+                    m = fmax(m, fmax(fabs(v.re), fabs(v.im)));
+                }
             }
             e = m > 0.0 ? exp_of(m) : 0;
         }
@@ -562,22 +655,22 @@ __global__ void __launch_bounds__(NW * 64) i8_chain_kernel(int n, const cd *__re
     // occur for 2n <= 192: the kernel's registers are the largest body's)
     if constexpr (NW == 8) {
         switch (ntile * 4 + sh.kc) {
-            case 0 * 4 + 1: i8_body<0, 1, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 1 * 4 + 1: i8_body<1, 1, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 0 * 4 + 2: i8_body<0, 2, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 1 * 4 + 2: i8_body<1, 2, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 1 * 4 + 3: i8_body<1, 3, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            default: i8_body<2, 3, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 0 * 4 + 1: i8_body<0, 1, NW, PIPE, HERM>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 1: i8_body<1, 1, NW, PIPE, HERM>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 0 * 4 + 2: i8_body<0, 2, NW, PIPE, HERM>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 2: i8_body<1, 2, NW, PIPE, HERM>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 3: i8_body<1, 3, NW, PIPE, HERM>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            default: i8_body<2, 3, NW, PIPE, HERM>(n, P, B, rho, nsteps, smem, wave, lane); break;
         }
     } else {
         static_assert(NW == 4, "four or eight wavefronts");
         switch (ntile * 4 + sh.kc) {
-            case 0 * 4 + 1: i8_body<0, 1, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 1 * 4 + 1: i8_body<1, 1, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 1 * 4 + 2: i8_body<1, 2, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 2 * 4 + 2: i8_body<2, 2, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            case 2 * 4 + 3: i8_body<2, 3, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
-            default: i8_body<3, 3, NW, PIPE>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 0 * 4 + 1: i8_body<0, 1, NW, PIPE, HERM>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 1: i8_body<1, 1, NW, PIPE, HERM>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 1 * 4 + 2: i8_body<1, 2, NW, PIPE, HERM>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 2 * 4 + 2: i8_body<2, 2, NW, PIPE, HERM>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            case 2 * 4 + 3: i8_body<2, 3, NW, PIPE, HERM>(n, P, B, rho, nsteps, smem, wave, lane); break;
+            default: i8_body<3, 3, NW, PIPE, HERM>(n, P, B, rho, nsteps, smem, wave, lane); break;
         }
     }
 }
@@ -784,24 +877,41 @@ int chain_fx_i8(int n, const cd *P, lb_precision prec, int B, cd *rho, long long
     return check_launch("fx_i8_chain");
 }
 
-int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s, int waves, bool pipe) {
+int i8_herm_fused_max_n() { return 2 * i8c::MAXN; }
+
+bool i8_herm_shape_ok(int n) {
+    int d = 1;
+    while ((d + 1) * (d + 1) <= n) ++d;
+    return n >= 1 && d * d == n;
+}
+
+int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStream_t s, int waves, bool pipe,
+                   bool herm) {
     using namespace i8c;
-    if (n > MAXN) return fail(LB_ESHAPE, "i8 chain: n too large for the fused kernel");
+    if (herm && !i8_herm_shape_ok(n)) return fail(LB_ESHAPE, "i8 Hermitian chain: n must be d^2");
+    if (n > (herm ? 2 * MAXN : MAXN)) return fail(LB_ESHAPE, "i8 chain: n too large for the fused kernel");
     if (waves != 4 && waves != 8) return fail(LB_EINVAL, "i8 chain: 4 or 8 wavefronts per workgroup");
     if (pipe && waves != 8) return fail(LB_EINVAL, "i8 chain: the pipelined step runs eight wavefronts");
     if (nsteps == 0 || B == 0) return LB_OK;
-    const size_t lds = lds_bytes(n, pipe);
+    const size_t lds = lds_bytes(n, pipe, herm);
     const int grid = (B + NS - 1) / NS;
     // a pipelined launch counts tiles in int: longer chains run as several
     // launches (each starts from its state's exact exponent)
     for (long long done = 0; done < nsteps;) {
         const long long k = pipe ? std::min(nsteps - done, PIPE_MAX_STEPS) : nsteps - done;
-        if (pipe)
-            i8_chain_kernel<8, true><<<grid, 8 * 64, lds, s>>>(n, P, B, rho, k);
+        if (herm) {
+            if (pipe)
+                i8_chain_kernel<8, true, true><<<grid, 8 * 64, lds, s>>>(n, P, B, rho, k);
+            else if (waves == 8)
+                i8_chain_kernel<8, false, true><<<grid, 8 * 64, lds, s>>>(n, P, B, rho, k);
+            else
+                i8_chain_kernel<4, false, true><<<grid, 4 * 64, lds, s>>>(n, P, B, rho, k);
+        } else if (pipe)
+            i8_chain_kernel<8, true, false><<<grid, 8 * 64, lds, s>>>(n, P, B, rho, k);
         else if (waves == 8)
-            i8_chain_kernel<8, false><<<grid, 8 * 64, lds, s>>>(n, P, B, rho, k);
+            i8_chain_kernel<8, false, false><<<grid, 8 * 64, lds, s>>>(n, P, B, rho, k);
         else
-            i8_chain_kernel<4, false><<<grid, 4 * 64, lds, s>>>(n, P, B, rho, k);
+            i8_chain_kernel<4, false, false><<<grid, 4 * 64, lds, s>>>(n, P, B, rho, k);
         done += k;
     }
     return check_launch("i8_chain");

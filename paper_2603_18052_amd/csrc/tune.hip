@@ -99,6 +99,12 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
         add2(VF_I8_GEMM * 100 + 1);
         add2(VF_I8_GEMM * 100 + 2);
         add2(VF_I8_GEMM * 100 + 3);
+    } else if (prec == LB_I8_HERM) {
+        if (i8_herm_shape_ok(n) && n <= i8_herm_fused_max_n()) {
+            add(VF_I8_FUSED * 100);
+            add(VF_I8_FUSED * 100 + 1);
+            add(VF_I8_FUSED * 100 + 2);
+        }
     }
     return c;
 }
@@ -161,6 +167,8 @@ int chain_heuristic(int n, lb_precision prec, int B) {
             if (rb96 * ((B + 31) / 32) >= 240) return VF_I8_GEMM * 100 + 3;
             return VF_I8_GEMM * 100 + 2;
         }
+        case LB_I8_HERM:
+            return i8_herm_shape_ok(n) && n <= i8_herm_fused_max_n() ? VF_I8_FUSED * 100 : 0;
         default:
             return 0;
     }
@@ -202,7 +210,8 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_TAIL: return chain_tail(n, P, prec, prm, B, rho, nsteps, s);
         case VF_TGEMM: return chain_tgemm(n, P, prec, prm, B, rho, nsteps, ws, s, graph);
         case VF_TPLANES: return chain_planes(n, P, prec, B, rho, nsteps, ws, s, graph, prm == 0 ? 1 : prm + 1);
-        case VF_I8_FUSED: return chain_i8_fused(n, P, B, rho, nsteps, s, prm == 1 ? 4 : 8, prm == 2);
+        case VF_I8_FUSED:
+            return chain_i8_fused(n, P, B, rho, nsteps, s, prm == 1 ? 4 : 8, prm == 2, prec == LB_I8_HERM);
         case VF_FX_I8: return chain_fx_i8(n, P, prec, B, rho, nsteps, s);
         case VF_I8_GEMM: return chain_i8_gemm(n, P, B, rho, nsteps, ws, s, graph, prm);
         default: return fail(LB_EINVAL, "unknown chain variant");
@@ -222,7 +231,7 @@ int chain_run(int n, const cd *P, lb_precision prec, int B, cd *rho, long long n
 using namespace lb;
 
 static int check_prec(const char *who, lb_precision prec) {
-    if ((int)prec < LB_C128 || (int)prec > LB_Q31) return fail(LB_EINVAL, std::string(who) + ": bad precision");
+    if ((int)prec < LB_C128 || (int)prec > LB_I8_HERM) return fail(LB_EINVAL, std::string(who) + ": bad precision");
     return LB_OK;
 }
 

@@ -16,9 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblindblad.so")
 
 OK, EINVAL, ESHAPE, ENOMEM, EHIP, ESINGULAR, ENONFINITE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
-C128, C64, BF16_HILO, BF16_SLICED, Q15, I8_SLICED, Q31 = 0, 1, 2, 3, 4, 5, 6
+C128, C64, BF16_HILO, BF16_SLICED, Q15, I8_SLICED, Q31, I8_HERM = 0, 1, 2, 3, 4, 5, 6, 7
 PRECISIONS = {"c128": C128, "c64": C64, "bf16_hilo": BF16_HILO, "bf16_sliced": BF16_SLICED, "q15": Q15,
-              "i8_sliced": I8_SLICED, "q31": Q31}
+              "i8_sliced": I8_SLICED, "q31": Q31, "i8_herm": I8_HERM}
 
 SYMBOLS = {
     # name: (restype, argtypes)

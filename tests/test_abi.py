@@ -58,7 +58,7 @@ def test_validation_errors_without_gpu(L):
     assert L.lindblad_propagate(9, 1, 0, 0, 1, 1, None, None) == lb.ESHAPE
     assert L.lindblad_propagate(9, 1, 0, 1, 1, -1, None, None) == lb.EINVAL
     assert L.lindblad_propagate(9, 1, 9, 1, 1, 1, None, None) == lb.EINVAL
-    assert L.lindblad_propagate(9, 1, 7, 1, 1, 1, None, None) == lb.EINVAL  # past the last precision
+    assert L.lindblad_propagate(9, 1, 8, 1, 1, 1, None, None) == lb.EINVAL  # past the last precision
     assert L.lindblad_propagate(9, None, 0, 1, 1, 1, None, None) == lb.EINVAL
     assert L.lindblad_propagate_baseline(5000, 1, 1, 1, 1, None, None) == lb.ESHAPE
 
@@ -130,6 +130,11 @@ def test_chain_variant_lists_and_rule(L):
     assert lb.chain_variants(729, "i8_sliced", 64) == [1500, 1550, 1501, 1551, 1502, 1552, 1503, 1553]
     assert lb.chain_variant(729, "i8_sliced", 1024) == 1503 and lb.chain_variant(729, "i8_sliced", 480) == 1503
     assert lb.chain_variant(729, "i8_sliced", 448) == 1502 and lb.chain_variant(729, "i8_sliced", 1) == 1502
+    # the Hermitian-coordinate form: the fused kernels for n = d^2 <= 192 only
+    assert lb.chain_variants(81, "i8_herm", 4096) == [1300, 1301, 1302] and lb.chain_variant(81, "i8_herm", 1) == 1300
+    assert lb.chain_variants(169, "i8_herm", 16) == [1300, 1301, 1302] and lb.chain_variants(1, "i8_herm", 1) == [1300, 1301, 1302]
+    assert lb.chain_variants(82, "i8_herm", 16) == [] and lb.chain_variant(82, "i8_herm", 16) == 0
+    assert lb.chain_variants(196, "i8_herm", 16) == [] and lb.chain_variant(729, "i8_herm", 16) == 0
     # tuning table: set, read back, reject a variant the shape lacks, clear
     lb.tune_set(81, "c128", 4096, 502)
     assert lb.chain_variant(81, "c128", 4096) == 502
@@ -139,7 +144,7 @@ def test_chain_variant_lists_and_rule(L):
     assert lb.chain_variant(81, "c128", 4096) == 1002
     cnt = ctypes.c_int()
     assert L.lindblad_chain_variants(0, 0, 1, None, 0, ctypes.byref(cnt)) == lb.ESHAPE
-    assert L.lindblad_chain_variants(9, 7, 1, None, 0, ctypes.byref(cnt)) == lb.EINVAL
+    assert L.lindblad_chain_variants(9, 8, 1, None, 0, ctypes.byref(cnt)) == lb.EINVAL
     assert L.lindblad_chain_variants(9, 0, 1, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 18
     assert L.lindblad_propagate_variant(9, 1, 0, 1, 1, 5, 999, None, None) == lb.EINVAL
     assert L.lindblad_tune(9, 1, 0, 1, 1, 0, 1, None, None, None, None) == lb.EINVAL
