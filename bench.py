@@ -482,7 +482,7 @@ def d27_section(lb, W, torch, dev, ws):
     finals = {}
     for B in (1, 64, 1024):
         row = {}
-        for prec in ("c128", "c64", "bf16_hilo", "bf16_sliced", "i8_sliced", "baseline"):
+        for prec in ("c128", "c64", "bf16_hilo", "bf16_sliced", "i8_sliced", "i8_herm", "baseline"):
             nst = N if not (prec == "baseline" and B == 1024) else 100
             x = X0[:B].clone()
             variant = 100

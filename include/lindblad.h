@@ -83,14 +83,15 @@ typedef enum {
                            curve): LB_Q15's rules with 32-bit codes, sums exact in 128 bits,
                            floor(acc / 2^31) saturated.  Bitwise reproducible; n <= 96 */
     LB_I8_HERM = 7      /* LB_I8_SLICED's digits and rules on the real coordinates of a
-                           HERMITIAN state (a density matrix; n = d^2, n <= 192).  The Lindblad
+                           HERMITIAN state (a density matrix; n = d^2).  The Lindblad
                            generator (Eq. 1), exp(L dt) and its Pade approximant map rho^dagger
                            to (P rho)^dagger, so the step is one real n x n matrix R on the
                            coordinates h_(i,j) = Re rho_ij (i <= j), Im rho_ij (i > j):
                            half the rows and half the k of the 2n x 2n embedding.  The call
                            reads only those entries of each state (the Hermitian matrix they
-                           define) and writes a Hermitian result.  No kernel (LB_ENOTSUP)
-                           unless n is a perfect square within the limit */
+                           define) and writes a Hermitian result.  One fused launch for
+                           n <= 192, beyond one INT8 GEMM launch per step as LB_I8_SLICED.
+                           No kernel (LB_ENOTSUP) unless n is a perfect square */
 } lb_precision;
 
 typedef struct lb_workspace lb_workspace;
@@ -287,7 +288,8 @@ int lindblad_expmv_params(double a, int *s, int *m);
  *             fewer than 256 tiles (partial sums added in a fixed order)
  *   1300      LB_I8_SLICED, whole chain in one launch (n <= 96), eight
  *             wavefronts of up to two 16-row tiles, a barrier per step;
- *             1300 .. 1302 are also LB_I8_HERM's variants (n = d^2 <= 192)
+ *             1300 .. 1302 are also LB_I8_HERM's variants (n = d^2 <= 192), and
+ *             so are 1500 .. 1503 (any n = d^2)
  *   1301      the same with four wavefronts of up to three tiles
  *   1302      eight wavefronts, steps synchronised by per-tile progress words
  *             in LDS instead of a barrier (three state digit buffers)

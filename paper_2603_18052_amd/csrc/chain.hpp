@@ -63,11 +63,12 @@ int chain_i8_fused(int n, const cd *P, int B, cd *rho, long long nsteps, hipStre
 int i8_herm_fused_max_n();
 bool i8_herm_shape_ok(int n);  // n = d^2
 int fx_i8_max_n();
-size_t i8_gemm_ws_bytes(int n, int B);
+size_t i8_gemm_ws_bytes(int n, int B, bool herm);
 // shape: 0 = 96 x 64 tiles, 1 = 96 x 32, 2 = 64 x 16 (rows of Q x states), 3 = 96 x 32
-// with two LDS slots, two workgroups per CU
+// with two LDS slots, two workgroups per CU; herm: the Hermitian-coordinate
+// form (LB_I8_HERM, n = d^2: the n x n real step)
 int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s, bool graph,
-                  int shape);
+                  int shape, bool herm);
 int chain_fx_i8(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
 int chain_bf16_fused(int n, const cd *P, lb_precision prec, int B, cd *rho, long long nsteps, hipStream_t s);
 

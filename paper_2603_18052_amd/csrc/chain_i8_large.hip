@@ -112,18 +112,52 @@ __device__ inline double qval(const cd *__restrict__ P, int n, int R, int k) {
     return kim ? v.re : v.im;
 }
 
-// digits of a row of Q (one workgroup per row): exponent, five planes, and
-// the row's absolute sum into gbits (atomic max of the non-negative bits)
+// Hermitian coordinates (n = d^2): the real step R on h_(i,j) = Re rho_ij
+// (i <= j), Im rho_ij (i > j).  With u = P[r, (a, b)], v = P[r, (b, a)]:
+// z = u (a = b), u + v (a < b), i (u - v) (a > b); R[r, q] = Re z for a
+// row r = (i, j) with i <= j, else Im z.
+__device__ inline double hval(const cd *__restrict__ P, int n, int d, int r, int q) {
+    if (r >= n || q >= n) return 0.0;
+    const int a = q / d, b = q - a * d, i = r / d, j = r - i * d;
+    const cd u = P[(size_t)r * n + q], v = P[(size_t)r * n + b * d + a];
+    double re = u.re, im = u.im;
+    if (a < b) {
+        re += v.re;
+        im += v.im;
+    } else if (a > b) {
+        re = v.im - u.im;
+        im = u.re - v.re;
+    }
+    return i <= j ? re : im;
+}
+
+__device__ inline int dim_of(int n) {
+    int d = 1;
+    while ((d + 1) * (d + 1) <= n) ++d;
+    return d;
+}
+
+// digits of a row of the step matrix (Q, or R of the Hermitian form; one
+// workgroup per row): exponent, five planes, and the row's absolute sum
+// into gbits (atomic max of the non-negative bits)
+template <bool HERM>
 __global__ void __launch_bounds__(256) prep_q_kernel(int n, int Kp, int npad, const cd *__restrict__ P,
                                                      signed char *__restrict__ Qd, int *__restrict__ eP,
                                                      unsigned long long *__restrict__ gbits) {
     const int R = blockIdx.x, tid = threadIdx.x;
     const int r = R < n ? R : R - n;
+    const int m2 = HERM ? n : 2 * n, dd = HERM ? dim_of(n) : 1;
     double m = 0.0, sum = 0.0;
     for (int k = tid; k < n; k += 256) {
-        const cd v = P[(size_t)r * n + k];
-        m = fmax(m, fmax(fabs(v.re), fabs(v.im)));
-        sum += fabs(v.re) + fabs(v.im);
+        if (HERM) {
+            const double h = fabs(hval(P, n, dd, R, k));
+            m = fmax(m, h);
+            sum += h;
+        } else {
+            const cd v = P[(size_t)r * n + k];
+            m = fmax(m, fmax(fabs(v.re), fabs(v.im)));
+            sum += fabs(v.re) + fabs(v.im);
+        }
     }
     __shared__ double rm[256], rs[256];
     rm[tid] = m;
@@ -144,13 +178,14 @@ __global__ void __launch_bounds__(256) prep_q_kernel(int n, int Kp, int npad, co
     // rows past 2n (up to whole row blocks) repeat the last row: the step
     // kernel loads them from the last row too, so their outputs copy its
     // output and need no masking before the exponent maximum
-    if (R == 2 * n - 1)
-        for (int q = 2 * n + tid; q < npad; q += 256) eP[q] = e;
-    const size_t plane = (size_t)2 * n * Kp;
+    if (R == m2 - 1)
+        for (int q = m2 + tid; q < npad; q += 256) eP[q] = e;
+    const size_t plane = (size_t)m2 * Kp;
     for (int k0 = 4 * tid; k0 < Kp; k0 += 4 * 256) {
         unsigned w[NPD] = {0u, 0u, 0u, 0u, 0u};
         for (int q = 0; q < 4; ++q) {
-            const long long V = (long long)rint(ldexp(qval(P, n, R, k0 + q), FRAC_P - e));
+            const double qv = HERM ? hval(P, n, dd, R, k0 + q) : qval(P, n, R, k0 + q);
+            const long long V = (long long)rint(ldexp(qv, FRAC_P - e));
             const unsigned long long U = (unsigned long long)(V + 0x80808080LL);
             for (int j = 0; j < NPD; ++j) {
                 const unsigned byte = j < NPD - 1 ? (unsigned)((U >> (8 * j)) & 0xFFu) ^ 0x80u
@@ -159,7 +194,7 @@ __global__ void __launch_bounds__(256) prep_q_kernel(int n, int Kp, int npad, co
             }
         }
         for (int a = 0; a < NPD; ++a)
-            *reinterpret_cast<unsigned *>(Qd + a * plane + (size_t)(k0 / KC) * (2 * n * KC) + (size_t)R * KC + k0 % KC) =
+            *reinterpret_cast<unsigned *>(Qd + a * plane + (size_t)(k0 / KC) * (m2 * KC) + (size_t)R * KC + k0 % KC) =
                 w[a];
     }
 }
@@ -174,13 +209,19 @@ __device__ inline int growth_bits(const unsigned long long *gbits) {
 // M_0, digits of x_0 into buffer 0 (zeros past 2n), zero padding of buffer
 // 1, and the exponent slots: slot 3 = M_0 - g (so that S_0 = M_0), slot 0 =
 // M_0, slots 1 and 2 empty
+template <bool HERM>
 __global__ void __launch_bounds__(256) init_x_kernel(int n, int Kp, int B, const cd *__restrict__ rho,
                                                      signed char *__restrict__ X0, signed char *__restrict__ X1,
                                                      int *__restrict__ Mx, const unsigned long long *__restrict__ gbits) {
-    const int b = blockIdx.x, tid = threadIdx.x, n2 = 2 * n;
+    const int b = blockIdx.x, tid = threadIdx.x, n2 = HERM ? n : 2 * n, dd = HERM ? dim_of(n) : 1;
     const cd *x = rho + (size_t)b * n;
+    // coordinate k of the state: Re / Im of the embedding, or h_k
+    auto coord = [&](int k) {
+        if (HERM) return k < n ? ((k / dd <= k % dd) ? x[k].re : x[k].im) : 0.0;
+        return k < n ? x[k].re : (k < n2 ? x[k - n].im : 0.0);
+    };
     int m = EMPTY;
-    for (int k = tid; k < n; k += 256) m = max(m, max(exp_of(fabs(x[k].re)), exp_of(fabs(x[k].im))));
+    for (int k = tid; k < n2; k += 256) m = max(m, exp_of(fabs(coord(k))));
     __shared__ int red[256];
     red[tid] = m;
     __syncthreads();
@@ -195,7 +236,7 @@ __global__ void __launch_bounds__(256) init_x_kernel(int n, int Kp, int B, const
         unsigned W[4];
         for (int q = 0; q < 4; ++q) {
             const int k = k0 + q;
-            const double v = k < n ? x[k].re : (k < n2 ? x[k - n].im : 0.0);
+            const double v = coord(k);
             int V = (int)rint(ldexp(v, FRAC_X - S));
             V = V > XLIM ? XLIM : (V < -XLIM ? -XLIM : V);
             W[q] = (unsigned)(V + 0x00808080) ^ 0x00808080u;
@@ -240,7 +281,7 @@ __device__ inline void tile_of(int T, int nrb, int nsb, int &rb, int &sb) {
 // (LAST) writes FP64 into rho instead of digits.  Dynamic LDS (smem): the
 // ring, then TS ints for the workgroup's exponent maxima.
 template <class S, bool LAST>
-__device__ __forceinline__ void i8_gemm_body(unsigned char *smem, int n, int Kp, int B, int nrb, int nsb,
+__device__ __forceinline__ void i8_gemm_body(unsigned char *smem, int n, int m2, int Kp, int B, int nrb, int nsb,
                                              const signed char *__restrict__ Qd, const int *__restrict__ eP,
                                              const signed char *__restrict__ Xc, signed char *__restrict__ Xn,
                                              int *__restrict__ Mx, const unsigned long long *__restrict__ gbits,
@@ -250,7 +291,7 @@ __device__ __forceinline__ void i8_gemm_body(unsigned char *smem, int n, int Kp,
     int *emx = reinterpret_cast<int *>(smem + RING * STAGE);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int n2 = 2 * n;
+    const int n2 = m2;  // rows and k of the step: 2n, or n for the Hermitian coordinates
     // tile order: each XCD takes consecutive tiles
     const int total = nrb * nsb, per = total / 8, rem = total % 8;
     const int xcd = blockIdx.x % 8, jx = blockIdx.x / 8;
@@ -435,8 +476,20 @@ __device__ __forceinline__ void i8_gemm_body(unsigned char *smem, int n, int Kp,
                 for (int r = 0; r < 4; ++r) {
                     const int R = R0 + r;
                     if (bok && R < n2) {
-                        double *o = reinterpret_cast<double *>(rho + (size_t)b * n + (R < n ? R : R - n));
-                        o[R < n ? 0 : 1] = __builtin_amdgcn_ldexp(v[r], ey[r]);
+                        const double y = __builtin_amdgcn_ldexp(v[r], ey[r]);
+                        if (n2 == 2 * n) {
+                            double *o = reinterpret_cast<double *>(rho + (size_t)b * n + (R < n ? R : R - n));
+                            o[R < n ? 0 : 1] = y;
+                        } else {
+                            // h_(i,j): Re rho_ij = Re rho_ji (i <= j), or Im rho_ij = -Im rho_ji (i > j)
+                            const int d = dim_of(n), i = R / d, jj = R - i * d, c = i <= jj ? 0 : 1;
+                            double *o = reinterpret_cast<double *>(rho + (size_t)b * n);
+                            o[2 * R + c] = y;
+                            if (i == jj)
+                                o[2 * R + 1] = 0.0;
+                            else
+                                o[2 * (jj * d + i) + c] = c ? -y : y;
+                        }
                     }
                 }
             } else {
@@ -475,7 +528,7 @@ __device__ __forceinline__ void i8_gemm_body(unsigned char *smem, int n, int Kp,
 }
 
 template <bool LAST>
-__global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B, int nrb, int nsb,
+__global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int m2, int Kp, int B, int nrb, int nsb,
                                                            const signed char *__restrict__ Qd,
                                                            const int *__restrict__ eP,
                                                            const signed char *__restrict__ Xc,
@@ -483,11 +536,11 @@ __global__ void __launch_bounds__(256) i8_gemm_step_kernel(int n, int Kp, int B,
                                                            const unsigned long long *__restrict__ gbits, int t4,
                                                            cd *__restrict__ rho) {
     extern __shared__ __align__(16) unsigned char smem[];
-    i8_gemm_body<BigTile, LAST>(smem, n, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
+    i8_gemm_body<BigTile, LAST>(smem, n, m2, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
 }
 
 template <bool LAST>
-__global__ void __launch_bounds__(256) i8_gemm_mid_kernel(int n, int Kp, int B, int nrb, int nsb,
+__global__ void __launch_bounds__(256) i8_gemm_mid_kernel(int n, int m2, int Kp, int B, int nrb, int nsb,
                                                           const signed char *__restrict__ Qd,
                                                           const int *__restrict__ eP,
                                                           const signed char *__restrict__ Xc,
@@ -495,11 +548,11 @@ __global__ void __launch_bounds__(256) i8_gemm_mid_kernel(int n, int Kp, int B, 
                                                           const unsigned long long *__restrict__ gbits, int t4,
                                                           cd *__restrict__ rho) {
     extern __shared__ __align__(16) unsigned char smem[];
-    i8_gemm_body<MidTile, LAST>(smem, n, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
+    i8_gemm_body<MidTile, LAST>(smem, n, m2, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
 }
 
 template <bool LAST>
-__global__ void __launch_bounds__(256) i8_gemm_small_kernel(int n, int Kp, int B, int nrb, int nsb,
+__global__ void __launch_bounds__(256) i8_gemm_small_kernel(int n, int m2, int Kp, int B, int nrb, int nsb,
                                                             const signed char *__restrict__ Qd,
                                                             const int *__restrict__ eP,
                                                             const signed char *__restrict__ Xc,
@@ -507,11 +560,11 @@ __global__ void __launch_bounds__(256) i8_gemm_small_kernel(int n, int Kp, int B
                                                             const unsigned long long *__restrict__ gbits, int t4,
                                                             cd *__restrict__ rho) {
     extern __shared__ __align__(16) unsigned char smem[];
-    i8_gemm_body<SmallTile, LAST>(smem, n, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
+    i8_gemm_body<SmallTile, LAST>(smem, n, m2, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
 }
 
 template <bool LAST>
-__global__ void __launch_bounds__(256, 2) i8_gemm_pair_kernel(int n, int Kp, int B, int nrb, int nsb,
+__global__ void __launch_bounds__(256, 2) i8_gemm_pair_kernel(int n, int m2, int Kp, int B, int nrb, int nsb,
                                                               const signed char *__restrict__ Qd,
                                                               const int *__restrict__ eP,
                                                               const signed char *__restrict__ Xc,
@@ -519,7 +572,7 @@ __global__ void __launch_bounds__(256, 2) i8_gemm_pair_kernel(int n, int Kp, int
                                                               const unsigned long long *__restrict__ gbits, int t4,
                                                               cd *__restrict__ rho) {
     extern __shared__ __align__(16) unsigned char smem[];
-    i8_gemm_body<PairTile, LAST>(smem, n, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
+    i8_gemm_body<PairTile, LAST>(smem, n, m2, Kp, B, nrb, nsb, Qd, eP, Xc, Xn, Mx, gbits, t4, rho);
 }
 
 static int grid1(long long work) {
@@ -530,24 +583,25 @@ static int grid1(long long work) {
 
 }  // namespace i8g
 
-size_t i8_gemm_ws_bytes(int n, int B) {
-    const size_t Kp = (size_t)(2 * n + 63) / 64 * 64;
-    const size_t npad = (size_t)2 * n + i8g::TRMAX;  // row exponents padded to whole row blocks of any tile
-    return align256((size_t)i8g::NPD * 2 * n * Kp) + align256(npad * 4) +
+size_t i8_gemm_ws_bytes(int n, int B, bool herm) {
+    const size_t m2 = herm ? n : 2 * (size_t)n;
+    const size_t Kp = (m2 + 63) / 64 * 64;
+    const size_t npad = m2 + i8g::TRMAX;  // row exponents padded to whole row blocks of any tile
+    return align256((size_t)i8g::NPD * m2 * Kp) + align256(npad * 4) +
            2 * align256((size_t)i8g::NXD * B * Kp) + align256((size_t)4 * B * 4) + 256;
 }
 
 namespace i8g {
 // the step launches of one tile shape (K<LAST> = its two kernels)
 template <class S, class Launch>
-static int run_tiles(int n, int Kp, int B, const signed char *Qd, const int *eP, signed char *X0, signed char *X1,
+static int run_tiles(int n, int m2, int Kp, int B, const signed char *Qd, const int *eP, signed char *X0, signed char *X1,
                      int *Mx, const unsigned long long *gbits, cd *rho, long long nsteps, bool graph, hipStream_t s,
                      const void *k_step, const void *k_last, Launch launch) {
-    const int nrb = (2 * n + S::TR - 1) / S::TR, nsb = (B + S::TS - 1) / S::TS;
+    const int nrb = (m2 + S::TR - 1) / S::TR, nsb = (B + S::TS - 1) / S::TS;
     LB_TRY(set_max_lds(k_step, S::LDS));
     LB_TRY(set_max_lds(k_last, S::LDS));
     LB_TRY(run_steps(nsteps, graph, [&](long long t, hipStream_t st) {
-        launch(t + 1 == nsteps, nrb * nsb, S::LDS, st, n, Kp, B, nrb, nsb, Qd, eP, (t & 1) ? X1 : X0,
+        launch(t + 1 == nsteps, nrb * nsb, S::LDS, st, n, m2, Kp, B, nrb, nsb, Qd, eP, (t & 1) ? X1 : X0,
                (t & 1) ? X0 : X1, Mx, gbits, (int)(t & 3), rho);
         return LB_OK;
     }, s));
@@ -556,11 +610,12 @@ static int run_tiles(int n, int Kp, int B, const signed char *Qd, const int *eP,
 }  // namespace i8g
 
 int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspace *ws, hipStream_t s, bool graph,
-                  int shape) {
+                  int shape, bool herm) {
     using namespace i8g;
+    if (herm && !i8_herm_shape_ok(n)) return fail(LB_ESHAPE, "i8 Hermitian chain: n must be d^2");
     if (nsteps == 0 || B == 0) return LB_OK;
-    const int n2 = 2 * n, Kp = (n2 + 63) / 64 * 64;
-    LB_TRY(ws_ensure(ws, i8_gemm_ws_bytes(n, B)));
+    const int n2 = herm ? n : 2 * n, Kp = (n2 + 63) / 64 * 64;
+    LB_TRY(ws_ensure(ws, i8_gemm_ws_bytes(n, B, herm)));
     const size_t mark = ws->used;
     signed char *Qd = (signed char *)ws_take(ws, (size_t)NPD * n2 * Kp);
     int *eP = (int *)ws_take(ws, (size_t)(n2 + TRMAX) * 4);
@@ -575,13 +630,19 @@ int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspac
     } release{ws, mark};
     const int tr = shape == 2 ? SmallTile::TR : shape == 1 ? MidTile::TR : shape == 3 ? PairTile::TR : BigTile::TR;
     LB_TRY(fill_i32_launch(reinterpret_cast<int *>(gbits), 2, s));
-    prep_q_kernel<<<n2, 256, 0, s>>>(n, Kp, (n2 + tr - 1) / tr * tr, P, Qd, eP, gbits);
-    LB_TRY(check_launch("i8 prep_q"));
-    init_x_kernel<<<B, 256, 0, s>>>(n, Kp, B, rho, X0, X1, Mx, gbits);
+    if (herm) {
+        prep_q_kernel<true><<<n2, 256, 0, s>>>(n, Kp, (n2 + tr - 1) / tr * tr, P, Qd, eP, gbits);
+        LB_TRY(check_launch("i8 prep_q"));
+        init_x_kernel<true><<<B, 256, 0, s>>>(n, Kp, B, rho, X0, X1, Mx, gbits);
+    } else {
+        prep_q_kernel<false><<<n2, 256, 0, s>>>(n, Kp, (n2 + tr - 1) / tr * tr, P, Qd, eP, gbits);
+        LB_TRY(check_launch("i8 prep_q"));
+        init_x_kernel<false><<<B, 256, 0, s>>>(n, Kp, B, rho, X0, X1, Mx, gbits);
+    }
     LB_TRY(check_launch("i8 init_x"));
     if (shape == 1)
         return run_tiles<MidTile>(
-            n, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_mid_kernel<false>,
+            n, n2, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_mid_kernel<false>,
             (const void *)i8_gemm_mid_kernel<true>, [](bool last, int grid, int lds, hipStream_t st, auto... a) {
                 if (last)
                     i8_gemm_mid_kernel<true><<<grid, 256, lds, st>>>(a...);
@@ -590,7 +651,7 @@ int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspac
             });
     if (shape == 3)
         return run_tiles<PairTile>(
-            n, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_pair_kernel<false>,
+            n, n2, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_pair_kernel<false>,
             (const void *)i8_gemm_pair_kernel<true>, [](bool last, int grid, int lds, hipStream_t st, auto... a) {
                 if (last)
                     i8_gemm_pair_kernel<true><<<grid, 256, lds, st>>>(a...);
@@ -599,7 +660,7 @@ int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspac
             });
     if (shape == 2)
         return run_tiles<SmallTile>(
-            n, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_small_kernel<false>,
+            n, n2, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_small_kernel<false>,
             (const void *)i8_gemm_small_kernel<true>, [](bool last, int grid, int lds, hipStream_t st, auto... a) {
                 if (last)
                     i8_gemm_small_kernel<true><<<grid, 256, lds, st>>>(a...);
@@ -607,7 +668,7 @@ int chain_i8_gemm(int n, const cd *P, int B, cd *rho, long long nsteps, Workspac
                     i8_gemm_small_kernel<false><<<grid, 256, lds, st>>>(a...);
             });
     return run_tiles<BigTile>(
-        n, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_step_kernel<false>,
+        n, n2, Kp, B, Qd, eP, X0, X1, Mx, gbits, rho, nsteps, graph, s, (const void *)i8_gemm_step_kernel<false>,
         (const void *)i8_gemm_step_kernel<true>, [](bool last, int grid, int lds, hipStream_t st, auto... a) {
             if (last)
                 i8_gemm_step_kernel<true><<<grid, 256, lds, st>>>(a...);

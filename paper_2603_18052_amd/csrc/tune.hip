@@ -99,12 +99,16 @@ int chain_variants(int n, lb_precision prec, int B, int *ids, int max) {
         add2(VF_I8_GEMM * 100 + 1);
         add2(VF_I8_GEMM * 100 + 2);
         add2(VF_I8_GEMM * 100 + 3);
-    } else if (prec == LB_I8_HERM) {
-        if (i8_herm_shape_ok(n) && n <= i8_herm_fused_max_n()) {
+    } else if (prec == LB_I8_HERM && i8_herm_shape_ok(n)) {
+        if (n <= i8_herm_fused_max_n()) {
             add(VF_I8_FUSED * 100);
             add(VF_I8_FUSED * 100 + 1);
             add(VF_I8_FUSED * 100 + 2);
         }
+        add2(VF_I8_GEMM * 100);
+        add2(VF_I8_GEMM * 100 + 1);
+        add2(VF_I8_GEMM * 100 + 2);
+        add2(VF_I8_GEMM * 100 + 3);
     }
     return c;
 }
@@ -167,8 +171,14 @@ int chain_heuristic(int n, lb_precision prec, int B) {
             if (rb96 * ((B + 31) / 32) >= 240) return VF_I8_GEMM * 100 + 3;
             return VF_I8_GEMM * 100 + 2;
         }
-        case LB_I8_HERM:
-            return i8_herm_shape_ok(n) && n <= i8_herm_fused_max_n() ? VF_I8_FUSED * 100 : 0;
+        case LB_I8_HERM: {
+            if (!i8_herm_shape_ok(n)) return 0;
+            if (n <= i8_herm_fused_max_n()) return VF_I8_FUSED * 100;
+            // the embedding's rule on the n rows of the Hermitian step
+            const long long rb96 = (n + 95) / 96;
+            if (rb96 * ((B + 31) / 32) >= 240) return VF_I8_GEMM * 100 + 3;
+            return VF_I8_GEMM * 100 + 2;
+        }
         default:
             return 0;
     }
@@ -186,7 +196,7 @@ size_t chain_ws_bytes(int n, lb_precision prec, int B, int variant) {
     const int fam = variant_family(variant);
     if (fam == VF_BASELINE) return align256((size_t)B * n * sizeof(cd));  // same for the graph twin
     if (fam == VF_Q15) return q15_ws_bytes(n, B, variant_param(variant) == 0);
-    if (fam == VF_I8_GEMM) return i8_gemm_ws_bytes(n, B);
+    if (fam == VF_I8_GEMM) return i8_gemm_ws_bytes(n, B, prec == LB_I8_HERM);
     return large_ws_bytes(fam, n, prec, B);
 }
 
@@ -213,7 +223,7 @@ int chain_run_variant(int n, const cd *P, lb_precision prec, int B, cd *rho, lon
         case VF_I8_FUSED:
             return chain_i8_fused(n, P, B, rho, nsteps, s, prm == 1 ? 4 : 8, prm == 2, prec == LB_I8_HERM);
         case VF_FX_I8: return chain_fx_i8(n, P, prec, B, rho, nsteps, s);
-        case VF_I8_GEMM: return chain_i8_gemm(n, P, B, rho, nsteps, ws, s, graph, prm);
+        case VF_I8_GEMM: return chain_i8_gemm(n, P, B, rho, nsteps, ws, s, graph, prm, prec == LB_I8_HERM);
         default: return fail(LB_EINVAL, "unknown chain variant");
     }
 }

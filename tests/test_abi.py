@@ -131,10 +131,13 @@ def test_chain_variant_lists_and_rule(L):
     assert lb.chain_variant(729, "i8_sliced", 1024) == 1503 and lb.chain_variant(729, "i8_sliced", 480) == 1503
     assert lb.chain_variant(729, "i8_sliced", 448) == 1502 and lb.chain_variant(729, "i8_sliced", 1) == 1502
     # the Hermitian-coordinate form: the fused kernels for n = d^2 <= 192 only
-    assert lb.chain_variants(81, "i8_herm", 4096) == [1300, 1301, 1302] and lb.chain_variant(81, "i8_herm", 1) == 1300
-    assert lb.chain_variants(169, "i8_herm", 16) == [1300, 1301, 1302] and lb.chain_variants(1, "i8_herm", 1) == [1300, 1301, 1302]
+    i8v = [1300, 1301, 1302, 1500, 1550, 1501, 1551, 1502, 1552, 1503, 1553]
+    assert lb.chain_variants(81, "i8_herm", 4096) == i8v and lb.chain_variant(81, "i8_herm", 1) == 1300
+    assert lb.chain_variants(169, "i8_herm", 16) == i8v and lb.chain_variants(1, "i8_herm", 1) == i8v
     assert lb.chain_variants(82, "i8_herm", 16) == [] and lb.chain_variant(82, "i8_herm", 16) == 0
-    assert lb.chain_variants(196, "i8_herm", 16) == [] and lb.chain_variant(729, "i8_herm", 16) == 0
+    # past n = 192 the per-step GEMM on the n x n step, the embedding's tile rule on n rows
+    assert lb.chain_variants(196, "i8_herm", 16) == [1500, 1550, 1501, 1551, 1502, 1552, 1503, 1553]
+    assert lb.chain_variant(729, "i8_herm", 1024) == 1503 and lb.chain_variant(729, "i8_herm", 64) == 1502
     # tuning table: set, read back, reject a variant the shape lacks, clear
     lb.tune_set(81, "c128", 4096, 502)
     assert lb.chain_variant(81, "c128", 4096) == 502

@@ -167,13 +167,13 @@ def test_herm_reads_upper_real_and_lower_imaginary(lb):
 
 
 def test_herm_shape_errors(lb, P9):
-    """n must be a perfect square, at most 192 (d <= 13)."""
+    """n must be a perfect square."""
     x = T(np.zeros((2, 82), complex))
     with pytest.raises(lb.LindbladError):
         lb.propagate(T(np.eye(82, dtype=complex)), x, 1, "i8_herm")
-    x = T(np.zeros((2, 196), complex))
+    x = T(np.zeros((2, 200), complex))
     with pytest.raises(lb.LindbladError):
-        lb.propagate(T(np.eye(196, dtype=complex)), x, 1, "i8_herm")
+        lb.propagate(T(np.eye(200, dtype=complex)), x, 1, "i8_herm")
 
 
 def test_herm_config2_full_size(lb, P9):
@@ -190,3 +190,50 @@ def test_herm_config2_full_size(lb, P9):
     print(f"i8 herm config 2 (B=4096, N=1e4) sampled: trace distance max {td.max():.3e}")
     assert td.max() < 1e-6
     assert_hermitian(out[1300], 9)
+
+
+@pytest.mark.parametrize("d", [14, 15, 20])
+def test_herm_gemm_shapes_agree_bitwise(lb, d):
+    """Past the fused limit (n = d^2 > 192) the per-step INT8 GEMM runs the
+    n x n Hermitian step: every tile shape (1500 .. 1503) gives the same
+    bits, within the representation's bound of the oracle's chain, and a
+    Hermitian result."""
+    g = np.random.default_rng(400 + d)
+    P = kraus_map(d, g)
+    X = hermitian_states(d, 19, g)
+    out = {v: run(lb, P, X, 20, v) for v in (1500, 1501, 1502, 1503)}
+    for v in (1501, 1502, 1503):
+        assert np.array_equal(out[1500], out[v]), v
+    ref = oracle.propagate(P, X, 20)
+    assert oracle.rel_per_state(out[1500], ref, X) < 1e-8
+    assert_hermitian(out[1500], d)
+
+
+@pytest.fixture(scope="module")
+def P27():
+    H, Lk = W.transmon_system(3)
+    return oracle.propagator(oracle.liouvillian(H, Lk), W.DT_NS)
+
+
+def test_herm_gemm_d27_config3(lb, P27):
+    """Config 3 (d = 27, 10^3 steps) on the oracle's P, a ragged batch: the
+    trace distance against the oracle's chain."""
+    X = states(27, 37, 17)
+    ref = oracle.propagate(P27, X, 1000)
+    got = run(lb, P27, X, 1000)
+    td = oracle.trace_distance(got.reshape(-1, 27, 27), ref.reshape(-1, 27, 27))
+    print(f"i8 herm GEMM d=27 B=37 N=1e3: trace distance max {td.max():.3e} median {np.median(td):.3e}")
+    assert td.max() < 1e-6
+    assert_hermitian(got, 27)
+
+
+@pytest.mark.parametrize("B", [1, 64, 1024])
+def test_herm_gemm_d27_full_batch_sampled(lb, P27, B):
+    c = W.config3(B=B)
+    X = c["rho0"].reshape(-1, 729)
+    idx = np.unique(np.array([0, 1, 63, 64, 700, 1023]) % B)
+    ref = oracle.propagate(P27, X[idx], c["nsteps"])
+    got = run(lb, P27, X, c["nsteps"])[idx]
+    td = oracle.trace_distance(got.reshape(-1, 27, 27), ref.reshape(-1, 27, 27))
+    print(f"i8 herm GEMM config 3 B={B} sampled: trace distance max {td.max():.3e}")
+    assert td.max() < 1e-6
